@@ -1,0 +1,226 @@
+/*
+ * cq.h -- C ABI of the MI355X (gfx950) community-quality library.
+ *
+ * Computes the community-quality metrics of Chen, Liu and Szymanski, "Parallel
+ * Toolkit for Measuring the Quality of Network Community Structure":
+ *   - scoring one partition of an unweighted undirected graph (Section II-B):
+ *     modularity Q (Eq. 8), modularity density Qds (Eq. 9), and the six measures
+ *     of Section II-B3 (intra-edges, intra-density, contraction, inter-edges,
+ *     expansion, conductance);
+ *   - comparing a ground-truth partition C with a detected partition C'
+ *     (Section II-A): VI (Eq. 1), NMI (Eq. 2), F-measure (Eq. 3), NVD (Eq. 4),
+ *     RI (Eq. 5), ARI (Eq. 6), JI (Eq. 7) and the pair counts of Section II-A3.
+ *
+ * Conventions shared by every entry point
+ *   Memory     All arrays marked DEVICE are device pointers owned by the caller
+ *              (for example the storage of torch tensors).  The library never
+ *              frees caller memory and never allocates device memory inside a
+ *              scoring or comparison call; scratch space is the caller-provided
+ *              workspace, sized by the *_workspace_size queries.  Structs marked
+ *              HOST are host memory.
+ *   Streams    Work is enqueued on the context's HIP stream (hipStream_t passed
+ *              as void*).  Synchronous calls return after the result struct has
+ *              reached host memory.
+ *   Errors     Every call returns a cq_status.  Argument errors detectable on the
+ *              host return before anything is enqueued.  Errors found by the
+ *              kernels (a label outside [0, num_labels)) are reported through a
+ *              device flag word and mapped to CQ_E_LABEL_RANGE; the numeric
+ *              outputs of that call are then unspecified.  cq_context_last_error()
+ *              gives a one-line description of the last failure on a context.
+ *   Threads    A context and everything enqueued through it belong to one host
+ *              thread at a time.
+ *   Sizes      Graphs use int32 CSR (row offsets and column indices), so the
+ *              number of stored entries 2|E| must be below 2^31.  All counts the
+ *              library returns are exact integers; floating-point outputs are
+ *              binary64.
+ */
+#ifndef CQ_H
+#define CQ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t cq_status;
+#define CQ_OK 0
+#define CQ_E_INVALID_ARG (-1)   /* null pointer, bad size, bad flag */
+#define CQ_E_LABEL_RANGE (-2)   /* a label outside [0, num_labels) */
+#define CQ_E_GRAPH_FORMAT (-3)  /* CSR not well formed, or (when validated) not symmetric / has loops / duplicates */
+#define CQ_E_OVERFLOW (-4)      /* a size exceeds the int32 CSR limits */
+#define CQ_E_WORKSPACE (-5)     /* workspace missing or smaller than the size query returned */
+#define CQ_E_NO_EDGES (-6)      /* graph has no edges: Q and Qds divide by |E| */
+#define CQ_E_DEVICE (-7)        /* a HIP runtime call failed */
+#define CQ_E_BUSY (-8)          /* server: request not admitted */
+#define CQ_E_CANCELLED (-9)     /* server: request cancelled */
+#define CQ_E_CAPACITY (-10)     /* an optional export table was too small; all other outputs are valid */
+
+/* Human-readable name of a status code (static storage). */
+const char* cq_status_string(cq_status s);
+
+typedef struct cq_context cq_context;
+typedef struct cq_graph cq_graph;
+
+/* Create a context bound to HIP device `device`, enqueueing on `hip_stream`
+ * (a hipStream_t; NULL means the default stream).  *out receives the handle. */
+cq_status cq_context_create(int device, void* hip_stream, cq_context** out);
+/* Change the stream later calls enqueue on. */
+cq_status cq_context_set_stream(cq_context* ctx, void* hip_stream);
+void cq_context_destroy(cq_context* ctx);
+/* One-line description of the last failing call on ctx ("" if none). */
+const char* cq_context_last_error(const cq_context* ctx);
+
+/* ---- graphs ---------------------------------------------------------------- */
+
+/* Flags for cq_graph_load. */
+#define CQ_VALIDATE_GRAPH 1u  /* also check symmetry (rows must be sorted), no self-loops, no repeated entries */
+
+typedef struct {
+  int64_t n;           /* |V| */
+  int64_t nnz;         /* stored CSR entries = 2|E| */
+  int64_t m;           /* |E| */
+  int64_t max_degree;
+  uint32_t validated;  /* CQ_VALIDATE_GRAPH if the full check ran and passed */
+} cq_graph_stats;
+
+/*
+ * Register a graph: the symmetric CSR of a simple unweighted undirected graph
+ * G = (V, E) (Section II-B1), with every undirected edge stored in both rows.
+ *   n          number of nodes, >= 1
+ *   nnz        number of stored entries, row_ptr[n]; even, < 2^31
+ *   d_row_ptr  DEVICE int32[n+1], row_ptr[0] = 0, non-decreasing, row_ptr[n] = nnz
+ *   d_col_idx  DEVICE int32[nnz], entries in [0, n)
+ * The pointers are BORROWED: the arrays must stay alive and unchanged until
+ * cq_graph_release.  The structural checks above always run (one pass over the
+ * arrays, synchronous); CQ_VALIDATE_GRAPH adds the symmetry / loop / repeat checks.
+ * Returns CQ_E_GRAPH_FORMAT if a check fails.
+ */
+cq_status cq_graph_load(cq_context* ctx, int32_t n, int64_t nnz, const int32_t* d_row_ptr,
+                        const int32_t* d_col_idx, uint32_t flags, cq_graph** out);
+cq_status cq_graph_get_stats(const cq_graph* g, cq_graph_stats* out);
+void cq_graph_release(cq_graph* g);
+
+/* ---- scoring one partition (Section II-B) ---------------------------------- */
+
+/* HOST result of cq_score_partition.  "Communities" are the label ids carried by
+ * at least one node; K counts them; means are unweighted over those K. */
+typedef struct {
+  int64_t n, m;              /* |V|, |E| */
+  int64_t K;                 /* non-empty communities */
+  int64_t num_pairs;         /* unordered community pairs joined by at least one edge */
+  int64_t sum_ein;           /* sum_c |E_c^in|  (intra-edges, Section II-B3) */
+  int64_t sum_eout;          /* sum_c |E_c^out| (inter-edges, Section II-B3) */
+  uint64_t sum_degsum_sq;    /* sum_c (2|E_c^in| + |E_c^out|)^2, exact */
+  double Q;                  /* Eq. 8 */
+  double Qds;                /* Eq. 9 */
+  double split_penalty;      /* sum_i sum_{j != i} |E_ij| / (2|E|) * d_ij, the subtracted part of Eq. 9 */
+  double mean_intra_edges, mean_intra_density, mean_contraction;
+  double mean_inter_edges, mean_expansion, mean_conductance;
+  uint32_t device_flags;     /* raw device error bits (0 on success) */
+  uint32_t reserved;
+} cq_score_result;
+
+/* Optional per-label outputs: DEVICE arrays of length num_labels, each may be NULL.
+ * Entries for label ids that no node carries are zero. */
+typedef struct {
+  int64_t* size;           /* |c| */
+  int64_t* degsum;         /* 2|E_c^in| + |E_c^out| */
+  int64_t* ein;            /* |E_c^in|  (intra-edges) */
+  int64_t* eout;           /* |E_c^out| (inter-edges) */
+  double* intra_density;   /* d_c = 2|E_c^in| / (|c|(|c|-1)); 0 when |c| < 2 */
+  double* contraction;     /* 2|E_c^in| / |c| */
+  double* expansion;       /* |E_c^out| / |c| */
+  double* conductance;     /* |E_c^out| / (2|E_c^in| + |E_c^out|); 0 when that is 0 */
+  double* q_term;          /* bracket of Eq. 8 for c */
+  double* qds_term;        /* bracket of Eq. 9 for c (including its split-penalty sum) */
+} cq_per_community;
+
+/* Optional export of the inter-community edge counts |E_{ci,cj}| (Eq. 9): DEVICE
+ * arrays of `capacity` entries; one entry per unordered pair ci < cj with a
+ * non-zero count, in unspecified order.  If capacity is too small the call
+ * returns CQ_E_CAPACITY (all other outputs valid; result.num_pairs is exact). */
+typedef struct {
+  int32_t* ci;
+  int32_t* cj;
+  int64_t* count;
+  int64_t capacity;
+} cq_pair_table;
+
+/* Bytes of workspace cq_score_partition needs for graph g and num_labels ids. */
+size_t cq_score_workspace_size(const cq_graph* g, int32_t num_labels);
+
+/*
+ * Score the partition given by d_labels (DEVICE int32[n], values in
+ * [0, num_labels); ids no node carries are allowed and ignored).
+ *   d_ws/ws_bytes  DEVICE workspace of at least cq_score_workspace_size bytes;
+ *                  contents on entry are ignored, on exit unspecified.
+ *   h_out          HOST result.
+ *   per_comm       optional per-label DEVICE outputs (NULL to skip).
+ *   pairs          optional pair-table export (NULL to skip).
+ * Synchronous.  Errors: CQ_E_INVALID_ARG, CQ_E_WORKSPACE, CQ_E_NO_EDGES,
+ * CQ_E_LABEL_RANGE, CQ_E_CAPACITY, CQ_E_DEVICE.
+ */
+cq_status cq_score_partition(cq_context* ctx, const cq_graph* g, const int32_t* d_labels,
+                             int32_t num_labels, void* d_ws, size_t ws_bytes, cq_score_result* h_out,
+                             const cq_per_community* per_comm, const cq_pair_table* pairs);
+
+/* Asynchronous form: enqueue the same work and write the result struct to DEVICE
+ * memory d_out (a cq_score_result, 8-byte aligned) without synchronising.  Host
+ * argument errors are returned immediately; device-detected errors appear in
+ * d_out->device_flags (bit 0: label out of range; bit 2: pair export overflow). */
+cq_status cq_score_partition_async(cq_context* ctx, const cq_graph* g, const int32_t* d_labels,
+                                   int32_t num_labels, void* d_ws, size_t ws_bytes,
+                                   cq_score_result* d_out, const cq_per_community* per_comm,
+                                   const cq_pair_table* pairs);
+
+/* ---- comparing two partitions (Section II-A) -------------------------------- */
+
+/* HOST result of cq_compare_partitions.  C is the ground truth (labels a), C' the
+ * detected partition (labels b).  Pair counts are over unordered node pairs. */
+typedef struct {
+  int64_t n;                 /* |V| */
+  int64_t Ka, Kb;            /* non-empty communities of C and C' */
+  int64_t nnz;               /* non-zero cells |c ∩ c'| of the contingency table */
+  int64_t a11, a10, a01, a00, A;
+  double VI;                 /* Eq. 1, natural logarithm */
+  double NMI;                /* Eq. 2; 1 when both partitions are a single community */
+  double F;                  /* Eq. 3 (asymmetric: C is the reference) */
+  double NVD;                /* Eq. 4 */
+  double RI, ARI, JI;        /* Eqs. 5-7; ARI, JI are 1 when their denominators vanish */
+  uint32_t device_flags;
+  uint32_t reserved;
+} cq_compare_result;
+
+/* Optional export of the contingency table: DEVICE arrays of `capacity` entries,
+ * one per non-zero cell (i, j, |c_i ∩ c'_j|), unspecified order. */
+typedef struct {
+  int32_t* ci;
+  int32_t* cj;
+  int64_t* count;
+  int64_t capacity;
+} cq_cell_table;
+
+size_t cq_compare_workspace_size(int32_t n, int32_t num_labels_a, int32_t num_labels_b);
+
+/*
+ * Compare ground truth C (d_labels_a, DEVICE int32[n], values in [0, num_labels_a))
+ * with detected C' (d_labels_b, DEVICE int32[n], values in [0, num_labels_b)).
+ * n >= 2 (the pair count A = n(n-1)/2 must be positive).  Synchronous.
+ */
+cq_status cq_compare_partitions(cq_context* ctx, int32_t n, const int32_t* d_labels_a,
+                                int32_t num_labels_a, const int32_t* d_labels_b, int32_t num_labels_b,
+                                void* d_ws, size_t ws_bytes, cq_compare_result* h_out,
+                                const cq_cell_table* cells);
+
+/* Asynchronous form; result written to DEVICE memory d_out. */
+cq_status cq_compare_partitions_async(cq_context* ctx, int32_t n, const int32_t* d_labels_a,
+                                      int32_t num_labels_a, const int32_t* d_labels_b,
+                                      int32_t num_labels_b, void* d_ws, size_t ws_bytes,
+                                      cq_compare_result* d_out, const cq_cell_table* cells);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CQ_H */

@@ -1,0 +1,348 @@
+"""ctypes binding of the C ABI in ``include/cq.h`` (argument marshalling only).
+
+Every function named ``cq_*`` here calls the library function of the same name.
+The helpers at the bottom (:class:`Context`, :class:`Graph`, :func:`score_partition`,
+:func:`compare_partitions`) take torch tensors for device memory and the current
+torch stream, size the workspace and convert results to dicts.  All computation
+happens in ``libcq.so``; if it is missing, importing this module fails.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcq.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "cq.h")
+
+CQ_OK = 0
+CQ_E_INVALID_ARG = -1
+CQ_E_LABEL_RANGE = -2
+CQ_E_GRAPH_FORMAT = -3
+CQ_E_OVERFLOW = -4
+CQ_E_WORKSPACE = -5
+CQ_E_NO_EDGES = -6
+CQ_E_DEVICE = -7
+CQ_E_BUSY = -8
+CQ_E_CANCELLED = -9
+CQ_E_CAPACITY = -10
+CQ_VALIDATE_GRAPH = 1
+
+_P = ctypes.c_void_p
+_I32 = ctypes.c_int32
+_I64 = ctypes.c_int64
+_SZ = ctypes.c_size_t
+
+
+class CQError(RuntimeError):
+    def __init__(self, status: int, message: str = ""):
+        self.status = status
+        super().__init__(f"{_name(status)}: {message}" if message else _name(status))
+
+
+class ScoreResult(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_int64) for k in ("n", "m", "K", "num_pairs", "sum_ein", "sum_eout")] + [
+        ("sum_degsum_sq", ctypes.c_uint64)
+    ] + [(k, ctypes.c_double) for k in (
+        "Q", "Qds", "split_penalty", "mean_intra_edges", "mean_intra_density", "mean_contraction",
+        "mean_inter_edges", "mean_expansion", "mean_conductance",
+    )] + [("device_flags", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+class CompareResult(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_int64) for k in ("n", "Ka", "Kb", "nnz", "a11", "a10", "a01", "a00", "A")] + [
+        (k, ctypes.c_double) for k in ("VI", "NMI", "F", "NVD", "RI", "ARI", "JI")
+    ] + [("device_flags", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+PER_COMMUNITY_FIELDS = ("size", "degsum", "ein", "eout", "intra_density", "contraction", "expansion",
+                        "conductance", "q_term", "qds_term")
+
+
+class PerCommunity(ctypes.Structure):
+    _fields_ = [(k, _P) for k in PER_COMMUNITY_FIELDS]
+
+
+class PairTable(ctypes.Structure):
+    _fields_ = [("ci", _P), ("cj", _P), ("count", _P), ("capacity", _I64)]
+
+
+CellTable = PairTable
+
+
+class GraphStats(ctypes.Structure):
+    _fields_ = [("n", _I64), ("nnz", _I64), ("m", _I64), ("max_degree", _I64), ("validated", ctypes.c_uint32)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: run `python -m paper_1507_05492_amd.build` (needs hipcc)")
+    L = ctypes.CDLL(LIB_PATH)
+    sig = {
+        "cq_status_string": (ctypes.c_char_p, [_I32]),
+        "cq_context_create": (_I32, [ctypes.c_int, _P, ctypes.POINTER(_P)]),
+        "cq_context_set_stream": (_I32, [_P, _P]),
+        "cq_context_destroy": (None, [_P]),
+        "cq_context_last_error": (ctypes.c_char_p, [_P]),
+        "cq_graph_load": (_I32, [_P, _I32, _I64, _P, _P, ctypes.c_uint32, ctypes.POINTER(_P)]),
+        "cq_graph_get_stats": (_I32, [_P, ctypes.POINTER(GraphStats)]),
+        "cq_graph_release": (None, [_P]),
+        "cq_score_workspace_size": (_SZ, [_P, _I32]),
+        "cq_score_partition": (_I32, [_P, _P, _P, _I32, _P, _SZ, ctypes.POINTER(ScoreResult), _P, _P]),
+        "cq_score_partition_async": (_I32, [_P, _P, _P, _I32, _P, _SZ, _P, _P, _P]),
+        "cq_compare_workspace_size": (_SZ, [_I32, _I32, _I32]),
+        "cq_compare_partitions": (_I32, [_P, _I32, _P, _I32, _P, _I32, _P, _SZ, ctypes.POINTER(CompareResult), _P]),
+        "cq_compare_partitions_async": (_I32, [_P, _I32, _P, _I32, _P, _I32, _P, _SZ, _P, _P]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    return L
+
+
+_lib = _load()
+
+
+def header_functions() -> list[str]:
+    """Names of the functions declared in include/cq.h."""
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\**\s+\**\s*(cq_[a-z_]+)\s*\(", txt, re.M)))
+
+
+def _name(status: int) -> str:
+    return _lib.cq_status_string(status).decode()
+
+
+# ---- raw C ABI (same names) -------------------------------------------------
+def cq_status_string(status: int) -> str:
+    return _name(status)
+
+
+def cq_context_create(device: int = 0, stream: int | None = None) -> int:
+    out = _P()
+    st = _lib.cq_context_create(device, stream, ctypes.byref(out))
+    if st != CQ_OK:
+        raise CQError(st, "cq_context_create")
+    return out.value
+
+
+def cq_context_set_stream(ctx: int, stream: int | None) -> None:
+    st = _lib.cq_context_set_stream(ctx, stream)
+    if st != CQ_OK:
+        raise CQError(st)
+
+
+def cq_context_destroy(ctx: int) -> None:
+    _lib.cq_context_destroy(ctx)
+
+
+def cq_context_last_error(ctx: int) -> str:
+    return _lib.cq_context_last_error(ctx).decode()
+
+
+def _check(ctx: int, st: int, allow=(CQ_OK,)) -> int:
+    if st not in allow:
+        raise CQError(st, cq_context_last_error(ctx))
+    return st
+
+
+def cq_graph_load(ctx: int, n: int, nnz: int, d_row_ptr: int, d_col_idx: int, flags: int = 0) -> int:
+    out = _P()
+    _check(ctx, _lib.cq_graph_load(ctx, n, nnz, d_row_ptr, d_col_idx, flags, ctypes.byref(out)))
+    return out.value
+
+
+def cq_graph_get_stats(g: int) -> dict:
+    s = GraphStats()
+    st = _lib.cq_graph_get_stats(g, ctypes.byref(s))
+    if st != CQ_OK:
+        raise CQError(st)
+    return {k: getattr(s, k) for k, _ in GraphStats._fields_}
+
+
+def cq_graph_release(g: int) -> None:
+    _lib.cq_graph_release(g)
+
+
+def cq_score_workspace_size(g: int, num_labels: int) -> int:
+    return _lib.cq_score_workspace_size(g, num_labels)
+
+
+def cq_compare_workspace_size(n: int, num_labels_a: int, num_labels_b: int) -> int:
+    return _lib.cq_compare_workspace_size(n, num_labels_a, num_labels_b)
+
+
+def cq_score_partition(ctx, g, d_labels, num_labels, d_ws, ws_bytes, per_comm: PerCommunity | None = None,
+                       pairs: PairTable | None = None, allow=(CQ_OK,)) -> tuple[int, ScoreResult]:
+    res = ScoreResult()
+    st = _lib.cq_score_partition(ctx, g, d_labels, num_labels, d_ws, ws_bytes, ctypes.byref(res),
+                                 ctypes.byref(per_comm) if per_comm is not None else None,
+                                 ctypes.byref(pairs) if pairs is not None else None)
+    return _check(ctx, st, allow), res
+
+
+def cq_score_partition_async(ctx, g, d_labels, num_labels, d_ws, ws_bytes, d_out, per_comm=None, pairs=None) -> None:
+    _check(ctx, _lib.cq_score_partition_async(ctx, g, d_labels, num_labels, d_ws, ws_bytes, d_out,
+                                              ctypes.byref(per_comm) if per_comm is not None else None,
+                                              ctypes.byref(pairs) if pairs is not None else None))
+
+
+def cq_compare_partitions(ctx, n, d_a, La, d_b, Lb, d_ws, ws_bytes, cells: CellTable | None = None,
+                          allow=(CQ_OK,)) -> tuple[int, CompareResult]:
+    res = CompareResult()
+    st = _lib.cq_compare_partitions(ctx, n, d_a, La, d_b, Lb, d_ws, ws_bytes, ctypes.byref(res),
+                                    ctypes.byref(cells) if cells is not None else None)
+    return _check(ctx, st, allow), res
+
+
+def cq_compare_partitions_async(ctx, n, d_a, La, d_b, Lb, d_ws, ws_bytes, d_out, cells=None) -> None:
+    _check(ctx, _lib.cq_compare_partitions_async(ctx, n, d_a, La, d_b, Lb, d_ws, ws_bytes, d_out,
+                                                 ctypes.byref(cells) if cells is not None else None))
+
+
+# ---- torch conveniences -------------------------------------------------------
+def _torch():
+    import torch
+
+    return torch
+
+
+def _dev_i32(t, name):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda" or t.dtype != torch.int32 or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous int32 CUDA tensor")
+    return t
+
+
+def as_dict(res) -> dict:
+    return {k: getattr(res, k) for k, _ in res._fields_ if k != "reserved"}
+
+
+class Context:
+    """A library context on a torch device, enqueueing on the current torch stream."""
+
+    def __init__(self, device: int = 0):
+        torch = _torch()
+        self.device = device
+        self.stream = torch.cuda.current_stream(device)
+        self.handle = cq_context_create(device, self.stream.cuda_stream)
+        self._ws = None
+
+    def use_current_stream(self):
+        torch = _torch()
+        self.stream = torch.cuda.current_stream(self.device)
+        cq_context_set_stream(self.handle, self.stream.cuda_stream)
+
+    def workspace(self, nbytes: int):
+        torch = _torch()
+        if self._ws is None or self._ws.numel() < nbytes:
+            self._ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=f"cuda:{self.device}")
+        return self._ws
+
+    def close(self):
+        if self.handle:
+            cq_context_destroy(self.handle)
+            self.handle = 0
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Graph:
+    """A registered graph; keeps its CSR tensors alive while registered."""
+
+    def __init__(self, ctx: Context, row_ptr, col_idx, validate: bool = False):
+        self.ctx = ctx
+        self.row_ptr = _dev_i32(row_ptr, "row_ptr")
+        self.col_idx = _dev_i32(col_idx, "col_idx")
+        self.n = self.row_ptr.numel() - 1
+        self.nnz = self.col_idx.numel()
+        self.handle = cq_graph_load(ctx.handle, self.n, self.nnz, self.row_ptr.data_ptr(),
+                                    self.col_idx.data_ptr() if self.nnz else None,
+                                    CQ_VALIDATE_GRAPH if validate else 0)
+        self.stats = cq_graph_get_stats(self.handle)
+
+    def workspace_size(self, num_labels: int) -> int:
+        return cq_score_workspace_size(self.handle, num_labels)
+
+    def close(self):
+        if self.handle:
+            cq_graph_release(self.handle)
+            self.handle = 0
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def score_partition(graph: Graph, labels, num_labels: int, *, per_community: bool = False,
+                    pairs_capacity: int = 0, workspace=None, allow=(CQ_OK,)):
+    """Score a partition; returns (result dict, per-community dict | None, pairs tensor | None)."""
+    torch = _torch()
+    labels = _dev_i32(labels, "labels")
+    if labels.numel() != graph.n:
+        raise ValueError("labels must have one entry per node")
+    ctx = graph.ctx
+    need = graph.workspace_size(num_labels)
+    ws = workspace if workspace is not None else ctx.workspace(need)
+    dev = labels.device
+    pc = None
+    pc_t = None
+    if per_community:
+        pc_t = {}
+        for k in PER_COMMUNITY_FIELDS:
+            dt = torch.int64 if k in ("size", "degsum", "ein", "eout") else torch.float64
+            pc_t[k] = torch.empty(num_labels, dtype=dt, device=dev)
+        pc = PerCommunity(*[pc_t[k].data_ptr() for k in PER_COMMUNITY_FIELDS])
+    pt = None
+    pairs = None
+    if pairs_capacity > 0:
+        pairs = (torch.empty(pairs_capacity, dtype=torch.int32, device=dev),
+                 torch.empty(pairs_capacity, dtype=torch.int32, device=dev),
+                 torch.empty(pairs_capacity, dtype=torch.int64, device=dev))
+        pt = PairTable(pairs[0].data_ptr(), pairs[1].data_ptr(), pairs[2].data_ptr(), pairs_capacity)
+    st, res = cq_score_partition(ctx.handle, graph.handle, labels.data_ptr(), num_labels, ws.data_ptr(),
+                                 ws.numel(), pc, pt, allow=allow)
+    r = as_dict(res)
+    r["status"] = st
+    pair_tensor = None
+    if pairs is not None:
+        k = min(r["num_pairs"], pairs_capacity)
+        pair_tensor = torch.stack([pairs[0][:k].to(torch.int64), pairs[1][:k].to(torch.int64), pairs[2][:k]], dim=1)
+    return r, pc_t, pair_tensor
+
+
+def compare_partitions(ctx: Context, labels_a, num_labels_a: int, labels_b, num_labels_b: int, *,
+                       cells_capacity: int = 0, workspace=None, allow=(CQ_OK,)):
+    """Compare ground truth (labels_a) with a detected partition (labels_b); returns (dict, cells | None)."""
+    torch = _torch()
+    la = _dev_i32(labels_a, "labels_a")
+    lb = _dev_i32(labels_b, "labels_b")
+    n = la.numel()
+    if lb.numel() != n:
+        raise ValueError("label arrays differ in length")
+    need = cq_compare_workspace_size(n, num_labels_a, num_labels_b)
+    ws = workspace if workspace is not None else ctx.workspace(need)
+    ct = None
+    cells = None
+    if cells_capacity > 0:
+        cells = (torch.empty(cells_capacity, dtype=torch.int32, device=la.device),
+                 torch.empty(cells_capacity, dtype=torch.int32, device=la.device),
+                 torch.empty(cells_capacity, dtype=torch.int64, device=la.device))
+        ct = CellTable(cells[0].data_ptr(), cells[1].data_ptr(), cells[2].data_ptr(), cells_capacity)
+    st, res = cq_compare_partitions(ctx.handle, n, la.data_ptr(), num_labels_a, lb.data_ptr(), num_labels_b,
+                                    ws.data_ptr(), ws.numel(), ct, allow=allow)
+    r = as_dict(res)
+    r["status"] = st
+    cell_tensor = None
+    if cells is not None:
+        k = min(r["nnz"], cells_capacity)
+        cell_tensor = torch.stack([cells[0][:k].to(torch.int64), cells[1][:k].to(torch.int64), cells[2][:k]], dim=1)
+    return r, cell_tensor

@@ -1,0 +1,109 @@
+// cq_device.hpp -- device-side building blocks shared by the gfx950 kernels:
+// integer types, exact fixed-point accumulation, wave/block reductions and the
+// per-workgroup LDS count tables (direct-indexed and open-addressing).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace cq {
+
+typedef unsigned __int128 u128;
+typedef uint64_t u64;
+typedef uint32_t u32;
+
+constexpr u32 SENT = 0xFFFFFFFFu;  // "no label" marker in staged label arrays
+constexpr u32 EMPTY = 0xFFFFFFFFu; // empty hash slot
+
+// device flag bits (cq_score_result.device_flags / cq_compare_result.device_flags)
+constexpr u32 F_LABEL = 1u;   // a label outside [0, num_labels)
+constexpr u32 F_GRAPH = 2u;   // malformed CSR (graph load only)
+constexpr u32 F_EXPORT = 4u;  // export table too small
+constexpr u32 F_STACK = 8u;   // internal: class stack exhausted (never expected)
+
+// Control block at the start of every workspace.
+struct Ctl {
+  u32 flags;
+  u32 K;          // non-empty communities (filled by the scan kernel)
+  u32 ticket;     // work-queue cursor of the per-community kernels
+  u32 pad0;
+  unsigned long long export_count;
+  unsigned long long cells;   // non-zero contingency cells (comparison)
+  unsigned long long pad1[4];
+};
+
+// ---- exact fixed-point accumulation --------------------------------------
+// A binary64 value t is turned into the integer round_toward_zero(t * 2^96) held in
+// a 128-bit two's-complement word.  Integer addition is associative, so sums of
+// such words are independent of the order in which terms arrive.  |t| < 2^31 is
+// required; every term accumulated this way is bounded far below that.
+__device__ __forceinline__ u128 fix96(double t) {
+  double a = fabs(t);
+  double f = ldexp(a, 96);
+  u64 hi = __double2ull_rz(ldexp(f, -64));
+  double rem = f - ldexp((double)hi, 64);  // exact: f and hi*2^64 share the leading bits
+  u64 lo = __double2ull_rz(rem);
+  u128 v = ((u128)hi << 64) | (u128)lo;
+  return t < 0 ? (u128)(-(__int128)v) : v;
+}
+__device__ __forceinline__ double unfix96(u128 v) {
+  bool neg = ((__int128)v) < 0;
+  u128 a = neg ? (u128)(-(__int128)v) : v;
+  double d = ldexp((double)(u64)(a >> 64), -32) + ldexp((double)(u64)a, -96);
+  return neg ? -d : d;
+}
+
+// ---- wave / block reductions (wave64) ---------------------------------------
+__device__ __forceinline__ u64 wave_sum_u64(u64 x) {
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+  return x;
+}
+__device__ __forceinline__ u32 wave_max_u32(u32 x) {
+  for (int o = 32; o > 0; o >>= 1) { u32 y = __shfl_xor(x, o, 64); x = y > x ? y : x; }
+  return x;
+}
+__device__ __forceinline__ double wave_max_f64(double x) {
+  for (int o = 32; o > 0; o >>= 1) { double y = __shfl_xor(x, o, 64); x = y > x ? y : x; }
+  return x;
+}
+__device__ __forceinline__ u128 wave_sum_u128(u128 x) {
+  u64 lo = (u64)x, hi = (u64)(x >> 64);
+  for (int o = 32; o > 0; o >>= 1) {
+    u64 lo2 = __shfl_xor(lo, o, 64), hi2 = __shfl_xor(hi, o, 64);
+    u64 s = lo + lo2;
+    hi = hi + hi2 + (s < lo ? 1ull : 0ull);
+    lo = s;
+  }
+  return ((u128)hi << 64) | lo;
+}
+// Deterministic double sum over a block: a fixed butterfly inside each wave, then
+// wave totals combined in wave order by thread 0.  The result depends only on which
+// thread held which value, never on timing.
+template <int NW>
+__device__ __forceinline__ double block_sum_f64(double x, double* sh) {
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+  int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) sh[w] = x;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0) {
+    for (int i = 0; i < NW; ++i) r += sh[i];
+  }
+  __syncthreads();
+  return r;  // valid in thread 0
+}
+
+// inclusive scan of u32 inside a wave
+__device__ __forceinline__ u32 wave_incl_scan(u32 x) {
+  int lane = threadIdx.x & 63;
+  for (int o = 1; o < 64; o <<= 1) {
+    u32 y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  return x;
+}
+
+__device__ __forceinline__ u32 hash_slot(u32 key, u32 log2cap) {
+  return (key * 0x9E3779B1u) >> (32 - log2cap);
+}
+
+}  // namespace cq

@@ -1,0 +1,871 @@
+// cq_kernels.hpp -- gfx950 kernels of the community-quality library.
+//
+// Scoring one partition (Section II-B of the paper) runs as:
+//   node pass   -> per-label size |c| and degree sum D_c = 2|E_c^in| + |E_c^out|, and for
+//                  every node its slot inside its community's segment (counting sort)
+//   scan/order  -> segment starts; non-empty communities ordered by decreasing D_c
+//   edge pass   -> for every CSR entry (u, v) the label of v is written into the segment
+//                  of u's community (streamed col_idx, gathered labels)
+//   group pass  -> one workgroup per community counts its segment in LDS: the count of
+//                  its own label is 2|E_c^in|, the others are |E_{c,c'}| (Eq. 9)
+//   final       -> Q (Eq. 8), Qds (Eq. 9), the six measures (Section II-B3)
+// Comparing two partitions (Section II-A) reuses the node pass (weight 1), scan and
+// group pass on the contingency table rows: the segment of ground-truth community c_i
+// holds the detected labels of its members, so the LDS counts are |c_i ∩ c'_j|.
+#pragma once
+#include "cq_device.hpp"
+
+namespace cq {
+
+// ---------------------------------------------------------------------------
+// utility
+__global__ void k_fill_u32(u32* __restrict__ p, size_t count, u32 v) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x) p[i] = v;
+}
+
+// ---------------------------------------------------------------------------
+// Graph checks (load time).  Structural: offsets monotone and within [0, nnz],
+// indices within [0, n).  Full: no self-loops, rows strictly increasing (sorted, no
+// repeated entry), and every (u, v) has its mirror (v, u).
+__global__ void k_check_csr(int n, long long nnz, const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
+                            u32* __restrict__ flags, u32* __restrict__ maxdeg) {
+  u32 bad = 0, md = 0;
+  size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t u = (size_t)blockIdx.x * blockDim.x + threadIdx.x; u < (size_t)n; u += stride) {
+    long long a = rp[u], b = rp[u + 1];
+    if (a < 0 || b < a || b > nnz) bad = 1;
+    else md = max(md, (u32)(b - a));
+  }
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < (size_t)nnz; e += stride) {
+    int v = col[e];
+    if (v < 0 || v >= n) bad = 1;
+  }
+  md = wave_max_u32(md);
+  if ((threadIdx.x & 63) == 0 && md) atomicMax(maxdeg, md);
+  if (bad) atomicOr(flags, F_GRAPH);
+}
+
+__global__ void k_check_symmetric(int n, const int32_t* __restrict__ rp, const int32_t* __restrict__ col, u32* __restrict__ flags) {
+  // one wave per row; lanes stride over the row's entries
+  int lane = threadIdx.x & 63;
+  size_t wave = ((size_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  size_t nwaves = ((size_t)gridDim.x * blockDim.x) >> 6;
+  u32 bad = 0;
+  for (size_t u = wave; u < (size_t)n; u += nwaves) {
+    int a = rp[u], b = rp[u + 1];
+    for (int e = a + lane; e < b; e += 64) {
+      int v = col[e];
+      if (v == (int)u) bad = 1;
+      if (e > a && col[e - 1] >= v) bad = 1;
+      int lo = rp[v], hi = rp[v + 1];
+      while (lo < hi) {  // lower_bound of u in the (sorted) row of v
+        int mid = (lo + hi) >> 1;
+        if (col[mid] < (int)u) lo = mid + 1; else hi = mid;
+      }
+      if (lo >= rp[v + 1] || col[lo] != (int)u) bad = 1;
+    }
+  }
+  if (bad) atomicOr(flags, F_GRAPH);
+}
+
+// ---------------------------------------------------------------------------
+// Node pass, LDS-private histograms (num_labels small enough for LDS).
+// Workgroup w owns nodes [w*chunk, (w+1)*chunk).  It counts, per label, the nodes
+// (HN) and the weights (HD: degree when WEIGHTED, else 1) of its nodes, and gives
+// each node the running weight offset of its label inside the workgroup (loc).
+// Rows w of HN/HD are later prefix-summed over w, which turns loc into a position
+// inside the label's segment.
+template <bool WEIGHTED>
+__global__ __launch_bounds__(1024) void k_node_priv(int n, const int32_t* __restrict__ labels, const int32_t* __restrict__ rp,
+                                                    int L, int chunk, u32* __restrict__ HN, u32* __restrict__ HD,
+                                                    u32* __restrict__ loc, Ctl* __restrict__ ctl) {
+  extern __shared__ u32 sh[];
+  u32* hn = sh;
+  u32* hd = WEIGHTED ? sh + L : sh;
+  __shared__ u32 s_bad;
+  const int words = WEIGHTED ? 2 * L : L;
+  for (int i = threadIdx.x; i < words; i += blockDim.x) sh[i] = 0;
+  if (threadIdx.x == 0) s_bad = 0;
+  __syncthreads();
+  long long u0 = (long long)blockIdx.x * chunk;
+  long long u1 = min((long long)n, u0 + chunk);
+  u32 bad = 0;
+  for (long long u = u0 + threadIdx.x; u < u1; u += blockDim.x) {
+    int c = labels[u];
+    if ((u32)c >= (u32)L) { bad = 1; loc[u] = SENT; continue; }
+    u32 old;
+    if (WEIGHTED) {
+      u32 w = (u32)(rp[u + 1] - rp[u]);
+      atomicAdd(&hn[c], 1u);
+      old = atomicAdd(&hd[c], w);
+    } else {
+      old = atomicAdd(&hn[c], 1u);
+    }
+    loc[u] = old;
+  }
+  if (bad) s_bad = 1;
+  __syncthreads();
+  size_t row = (size_t)blockIdx.x * (size_t)L;
+  for (int c = threadIdx.x; c < L; c += blockDim.x) {
+    HN[row + c] = hn[c];
+    if (WEIGHTED) HD[row + c] = hd[c];
+  }
+  if (threadIdx.x == 0 && s_bad) atomicOr(&ctl->flags, F_LABEL);
+}
+
+// Node pass with global atomics (too many labels for LDS).  SZ[c] packs
+// (count << 32) | weight sum; the returned old value gives the node's offset.
+template <bool WEIGHTED>
+__global__ __launch_bounds__(256) void k_node_global(int n, const int32_t* __restrict__ labels, const int32_t* __restrict__ rp,
+                                                     int L, unsigned long long* __restrict__ SZ, u32* __restrict__ loc,
+                                                     Ctl* __restrict__ ctl) {
+  u32 bad = 0;
+  for (size_t u = (size_t)blockIdx.x * blockDim.x + threadIdx.x; u < (size_t)n; u += (size_t)gridDim.x * blockDim.x) {
+    int c = labels[u];
+    if ((u32)c >= (u32)L) { bad = 1; loc[u] = SENT; continue; }
+    u32 w = WEIGHTED ? (u32)(rp[u + 1] - rp[u]) : 1u;
+    unsigned long long old = atomicAdd(&SZ[c], (1ull << 32) | (unsigned long long)w);
+    loc[u] = (u32)old;
+  }
+  if (bad) atomicOr(&ctl->flags, F_LABEL);
+}
+
+// Plain label histogram (no slots): detected-partition sizes |c'| for the comparison.
+__global__ __launch_bounds__(1024) void k_hist_priv(int n, const int32_t* __restrict__ labels, int L, u32* __restrict__ HN,
+                                                    Ctl* __restrict__ ctl) {
+  extern __shared__ u32 sh[];
+  __shared__ u32 s_bad;
+  for (int i = threadIdx.x; i < L; i += blockDim.x) sh[i] = 0;
+  if (threadIdx.x == 0) s_bad = 0;
+  __syncthreads();
+  u32 bad = 0;
+  for (size_t u = (size_t)blockIdx.x * blockDim.x + threadIdx.x; u < (size_t)n; u += (size_t)gridDim.x * blockDim.x) {
+    int c = labels[u];
+    if ((u32)c >= (u32)L) { bad = 1; continue; }
+    atomicAdd(&sh[c], 1u);
+  }
+  if (bad) s_bad = 1;
+  __syncthreads();
+  size_t row = (size_t)blockIdx.x * (size_t)L;
+  for (int c = threadIdx.x; c < L; c += blockDim.x) HN[row + c] = sh[c];
+  if (threadIdx.x == 0 && s_bad) atomicOr(&ctl->flags, F_LABEL);
+}
+
+__global__ __launch_bounds__(256) void k_hist_global(int n, const int32_t* __restrict__ labels, int L, u32* __restrict__ cnt,
+                                                     Ctl* __restrict__ ctl) {
+  u32 bad = 0;
+  for (size_t u = (size_t)blockIdx.x * blockDim.x + threadIdx.x; u < (size_t)n; u += (size_t)gridDim.x * blockDim.x) {
+    int c = labels[u];
+    if ((u32)c >= (u32)L) { bad = 1; continue; }
+    atomicAdd(&cnt[c], 1u);
+  }
+  if (bad) atomicOr(&ctl->flags, F_LABEL);
+}
+
+// Column pass over the per-workgroup histograms: totals per label, and (SCAN) the
+// exclusive prefix over workgroups written back into the prefix matrix PM.
+template <bool WEIGHTED, bool SCAN>
+__global__ __launch_bounds__(256) void k_colscan(int W, int L, u32* __restrict__ HN, u32* __restrict__ HD, u32* __restrict__ N,
+                                                 u32* __restrict__ D) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= L) return;
+  u32* PM = WEIGHTED ? HD : HN;
+  u32 sn = 0, sd = 0;
+  int w = 0;
+  for (; w + 8 <= W; w += 8) {
+    u32 xn[8], xd[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      xn[k] = HN[(size_t)(w + k) * L + c];
+      xd[k] = WEIGHTED ? HD[(size_t)(w + k) * L + c] : xn[k];
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      if (SCAN) PM[(size_t)(w + k) * L + c] = sd;
+      sn += xn[k];
+      sd += xd[k];
+    }
+  }
+  for (; w < W; ++w) {
+    u32 xn = HN[(size_t)w * L + c];
+    u32 xd = WEIGHTED ? HD[(size_t)w * L + c] : xn;
+    if (SCAN) PM[(size_t)w * L + c] = sd;
+    sn += xn;
+    sd += xd;
+  }
+  N[c] = sn;
+  if (D) D[c] = sd;
+}
+
+__global__ void k_unpack(int L, const unsigned long long* __restrict__ SZ, u32* __restrict__ N, u32* __restrict__ D) {
+  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < L; c += gridDim.x * blockDim.x) {
+    unsigned long long v = SZ[c];
+    N[c] = (u32)(v >> 32);
+    if (D) D[c] = (u32)v;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Segment starts (exclusive scan of the weights D) and the work order of the
+// non-empty groups: by decreasing floor(log2 D), so the largest groups start first.
+__device__ __forceinline__ int size_bucket(u32 x) { return x ? 32 - __clz(x) : 0; }
+
+__global__ __launch_bounds__(1024) void k_scan_order(int L, const u32* __restrict__ N, const u32* __restrict__ D,
+                                                     u32* __restrict__ start, u32* __restrict__ order, Ctl* __restrict__ ctl) {
+  __shared__ u32 s_wtot[16];
+  __shared__ u32 s_carry;
+  __shared__ u32 s_bcnt[33];
+  __shared__ u32 s_boff[33];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  if (tid < 33) s_bcnt[tid] = 0;
+  if (tid == 0) s_carry = 0;
+  __syncthreads();
+  for (int base = 0; base < L; base += 1024) {
+    int c = base + tid;
+    u32 x = 0;
+    if (c < L) {
+      x = D[c];
+      if (N[c] > 0) atomicAdd(&s_bcnt[size_bucket(x)], 1u);
+    }
+    u32 incl = wave_incl_scan(x);
+    if (lane == 63) s_wtot[wv] = incl;
+    __syncthreads();
+    u32 before = s_carry;
+    for (int i = 0; i < wv; ++i) before += s_wtot[i];
+    if (c < L) start[c] = before + incl - x;
+    __syncthreads();
+    if (tid == 0) {
+      u32 t = s_carry;
+      for (int i = 0; i < 16; ++i) t += s_wtot[i];
+      s_carry = t;
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    u32 off = 0;
+    for (int b = 32; b >= 0; --b) { s_boff[b] = off; off += s_bcnt[b]; }
+    ctl->K = off;
+  }
+  __syncthreads();
+  for (int c = tid; c < L; c += 1024) {
+    if (N[c] > 0) {
+      u32 pos = atomicAdd(&s_boff[size_bucket(D[c])], 1u);
+      order[pos] = (u32)c;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Edge pass: for every stored entry (u, v) write label[v] into the segment of
+// community label[u] at start[c_u] + (offset of u) + (position of v in u's row).
+// A workgroup takes 256 consecutive rows; their entries are contiguous in col_idx and
+// are walked by all threads in order (coalesced); the owning row of an entry is found
+// by binary search over the 256 row starts staged in LDS.
+constexpr int GROWS = 256;
+template <bool PRIV>
+__global__ __launch_bounds__(GROWS) void k_gather(int n, const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
+                                                  const int32_t* __restrict__ labels, int L, int chunk,
+                                                  const u32* __restrict__ PM, const u32* __restrict__ start,
+                                                  const u32* __restrict__ loc, u32* __restrict__ CB) {
+  __shared__ int s_rs[GROWS + 1];
+  __shared__ u32 s_base[GROWS];
+  const int tid = threadIdx.x;
+  const long long r0 = (long long)blockIdx.x * GROWS;
+  const int rows = (int)min((long long)GROWS, (long long)n - r0);
+  if (tid < rows) {
+    long long u = r0 + tid;
+    s_rs[tid] = rp[u];
+    int c = labels[u];
+    u32 lu = loc[u];
+    u32 base = SENT;
+    if ((u32)c < (u32)L && lu != SENT) {
+      base = start[c] + lu;
+      if (PRIV) base += PM[(size_t)(u / chunk) * L + c];
+    }
+    s_base[tid] = base;
+  }
+  if (tid == 0) s_rs[rows] = rp[r0 + rows];
+  __syncthreads();
+  const int e0 = s_rs[0], e1 = s_rs[rows];
+  for (int e = e0 + tid; e < e1; e += GROWS) {
+    int lo = 0, hi = rows - 1;  // last row r with s_rs[r] <= e
+    while (lo < hi) {
+      int mid = (lo + hi + 1) >> 1;
+      if (s_rs[mid] <= e) lo = mid; else hi = mid - 1;
+    }
+    u32 base = s_base[lo];
+    if (base == SENT) continue;
+    int v = col[e];
+    int j = labels[v];
+    CB[base + (u32)(e - s_rs[lo])] = ((u32)j < (u32)L) ? (u32)j : SENT;
+  }
+}
+
+// Comparison: the segment of ground-truth community a_u receives b_u.
+template <bool PRIV>
+__global__ __launch_bounds__(256) void k_cmp_scatter(int n, const int32_t* __restrict__ la, const int32_t* __restrict__ lb,
+                                                     int La, int Lb, int chunk, const u32* __restrict__ PM,
+                                                     const u32* __restrict__ start, const u32* __restrict__ loc,
+                                                     u32* __restrict__ CB) {
+  for (size_t u = (size_t)blockIdx.x * blockDim.x + threadIdx.x; u < (size_t)n; u += (size_t)gridDim.x * blockDim.x) {
+    int a = la[u];
+    u32 lu = loc[u];
+    if ((u32)a >= (u32)La || lu == SENT) continue;
+    u32 pos = start[a] + lu;
+    if (PRIV) pos += PM[(u / chunk) * (size_t)La + a];
+    int b = lb[u];
+    CB[pos] = ((u32)b < (u32)Lb) ? (u32)b : SENT;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Group pass.  Persistent workgroups take groups (communities) from a ticket
+// counter in the order produced by k_scan_order.  Each group's segment
+// CB[start, start+len) holds label values in [0, Lv) (or SENT); the workgroup counts
+// them in LDS and hands every (label, count) with count > 0 to the visitor.
+//   direct table : Lv counters, when Lv fits the LDS budget and the group is not tiny
+//   hash table   : open addressing (keys, counts), capacity a power of two >= 2*min(len, Lv);
+//                  when the capacity would exceed the LDS budget the labels are split
+//                  into residue classes mod 2^k and counted one class at a time; a class
+//                  that overflows is split again.  Every label is counted in exactly one
+//                  class, so visitors see each (label, count) once.
+constexpr int GBLOCK = 512;
+constexpr int STACK = 96;
+
+__device__ __forceinline__ u32 pow2ceil_u32(u32 x) { return x <= 1 ? 1u : 1u << (32 - __clz(x - 1)); }
+__device__ __forceinline__ u32 log2_u32(u32 x) { return 31 - __clz(x); }
+
+template <class V>
+__global__ __launch_bounds__(GBLOCK) void k_groups(const u32* __restrict__ CB, const u32* __restrict__ seg_start,
+                                                   const u32* __restrict__ seg_len, const u32* __restrict__ order,
+                                                   Ctl* __restrict__ ctl, u32 Lv, u32 lds_words, V vis) {
+  extern __shared__ u32 tab[];
+  __shared__ u32 s_item;
+  __shared__ u32 s_over;
+  __shared__ int s_sp;
+  __shared__ u32 s_sr[STACK], s_sm[STACK];
+  const int tid = threadIdx.x;
+  const u32 K = ctl->K;
+  for (;;) {
+    if (tid == 0) s_item = atomicAdd(&ctl->ticket, 1u);
+    __syncthreads();
+    const u32 item = s_item;
+    __syncthreads();
+    if (item >= K) break;
+    const u32 g = order[item];
+    const u32 base = seg_start[g], len = seg_len[g];
+    typename V::State st;
+    vis.begin(st, g);
+    const u32 M = min(len, Lv);
+    u32 hcap = pow2ceil_u32(max(64u, 2u * M));
+    const bool direct = (Lv <= lds_words) && (2u * hcap > Lv);
+    if (direct) {
+      for (u32 j = tid; j < Lv; j += GBLOCK) tab[j] = 0;
+      __syncthreads();
+      for (u32 e = base + tid; e < base + len; e += GBLOCK) {
+        u32 j = CB[e];
+        if (j < Lv) atomicAdd(&tab[j], 1u);
+      }
+      __syncthreads();
+      for (u32 j = tid; j < Lv; j += GBLOCK) {
+        u32 x = tab[j];
+        if (x) vis.visit(st, j, x);
+      }
+    } else {
+      const u32 capmax = 1u << log2_u32(lds_words / 2u);
+      u32 classes = 1;
+      if (hcap > capmax) {
+        classes = pow2ceil_u32((2u * M + capmax - 1u) / capmax);
+        if (classes > 32u) classes = 32u;
+        hcap = capmax;
+      }
+      const u32 lg = log2_u32(hcap);
+      u32* keys = tab;
+      u32* cnt = tab + hcap;
+      if (tid == 0) {
+        s_sp = 0;
+        for (int r = (int)classes - 1; r >= 0; --r) { s_sr[s_sp] = (u32)r; s_sm[s_sp] = classes; ++s_sp; }
+      }
+      __syncthreads();
+      for (;;) {
+        const int sp = s_sp;
+        if (sp == 0) break;
+        const u32 r = s_sr[sp - 1], mod = s_sm[sp - 1];
+        __syncthreads();
+        if (tid == 0) { s_sp = sp - 1; s_over = 0; }
+        for (u32 s = tid; s < hcap; s += GBLOCK) { keys[s] = EMPTY; cnt[s] = 0; }
+        __syncthreads();
+        for (u32 e = base + tid; e < base + len; e += GBLOCK) {
+          u32 j = CB[e];
+          if (j >= Lv || (j & (mod - 1u)) != r) continue;
+          u32 h = hash_slot(j, lg);
+          bool done = false;
+          for (u32 p = 0; p < hcap; ++p) {
+            u32 k = keys[h];
+            if (k == EMPTY) {
+              u32 old = atomicCAS(&keys[h], EMPTY, j);
+              if (old == EMPTY || old == j) { atomicAdd(&cnt[h], 1u); done = true; break; }
+            } else if (k == j) {
+              atomicAdd(&cnt[h], 1u);
+              done = true;
+              break;
+            }
+            h = (h + 1u) & (hcap - 1u);
+          }
+          if (!done) s_over = 1;
+        }
+        __syncthreads();
+        if (s_over) {
+          if (tid == 0) {
+            if (s_sp + 2 <= STACK && mod < 0x80000000u) {
+              s_sr[s_sp] = r + mod; s_sm[s_sp] = 2u * mod; ++s_sp;
+              s_sr[s_sp] = r; s_sm[s_sp] = 2u * mod; ++s_sp;
+            } else {
+              atomicOr(&ctl->flags, F_STACK);
+            }
+          }
+          __syncthreads();
+          continue;
+        }
+        for (u32 s = tid; s < hcap; s += GBLOCK) {
+          u32 k = keys[s];
+          if (k != EMPTY) vis.visit(st, k, cnt[s]);
+        }
+        __syncthreads();
+      }
+    }
+    vis.finish(st, g);
+    __syncthreads();
+  }
+}
+
+// block reduction helpers for the visitors (GBLOCK threads = 8 waves)
+__device__ __forceinline__ u128 block_sum_u128(u128 x, u64* sh_lo, u64* sh_hi) {
+  x = wave_sum_u128(x);
+  int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) { sh_lo[w] = (u64)x; sh_hi[w] = (u64)(x >> 64); }
+  __syncthreads();
+  u128 r = 0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) r += ((u128)sh_hi[i] << 64) | sh_lo[i];
+  __syncthreads();
+  return r;
+}
+__device__ __forceinline__ u64 block_sum_u64(u64 x, u64* sh) {
+  x = wave_sum_u64(x);
+  int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) sh[w] = x;
+  __syncthreads();
+  u64 r = 0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) r += sh[i];
+  __syncthreads();
+  return r;
+}
+__device__ __forceinline__ u32 block_max_u32(u32 x, u64* sh) {
+  x = wave_max_u32(x);
+  int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) sh[w] = x;
+  __syncthreads();
+  u32 r = 0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) r = max(r, (u32)sh[i]);
+  __syncthreads();
+  return r;
+}
+__device__ __forceinline__ double block_max_f64(double x, double* sh) {
+  x = wave_max_f64(x);
+  int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) sh[w] = x;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) r = sh[i] > r ? sh[i] : r;
+  __syncthreads();
+  return r;
+}
+
+// Score visitor: for community g, label j with count x in g's segment:
+//   j == g  ->  x = 2|E_g^in|
+//   j != g  ->  x = |E_{g,j}|; contributes |E_gj|/(2|E|) * |E_gj|/(|g||j|) to g's
+//               split-penalty sum (Eq. 9); pairs with j > g are counted (and exported).
+struct ScoreVis {
+  const u32* N;
+  double twom;
+  u32* I;
+  u32* NP;
+  u64* PEN;
+  int32_t* eci;
+  int32_t* ecj;
+  int64_t* ecnt;
+  long long ecap;
+  Ctl* ctl;
+  struct State {
+    u128 pen;
+    u32 np;
+    u32 g;
+    double denom;
+  };
+  __device__ void begin(State& st, u32 g) {
+    st.pen = 0;
+    st.np = 0;
+    st.g = g;
+    st.denom = twom * (double)N[g];
+    if (threadIdx.x == 0) I[g] = 0;  // overwritten by the thread that meets label g
+  }
+  __device__ void visit(State& st, u32 j, u32 x) {
+    if (j == st.g) {
+      I[j] = x;
+      return;
+    }
+    double xd = (double)x;
+    double t = xd * xd / (st.denom * (double)N[j]);
+    st.pen += fix96(t);
+    if (j > st.g) {
+      st.np += 1;
+      if (ecap > 0) {
+        unsigned long long idx = atomicAdd(&ctl->export_count, 1ull);
+        if ((long long)idx < ecap) { eci[idx] = (int32_t)st.g; ecj[idx] = (int32_t)j; ecnt[idx] = (int64_t)x; }
+      }
+    }
+  }
+  __device__ void finish(State& st, u32 g) {
+    __shared__ u64 r_lo[GBLOCK / 64], r_hi[GBLOCK / 64];
+    u128 pen = block_sum_u128(st.pen, r_lo, r_hi);
+    u64 np = block_sum_u64(st.np, r_lo);
+    if (threadIdx.x == 0) {
+      PEN[2 * (size_t)g] = (u64)pen;
+      PEN[2 * (size_t)g + 1] = (u64)(pen >> 64);
+      NP[g] = (u32)np;
+    }
+  }
+};
+
+// Comparison visitor: row i of the contingency table, column j, cell x = |c_i ∩ c'_j|.
+struct CmpVis {
+  const u32* A;   // |c_i|
+  const u32* B;   // |c'_j|
+  double Nd;
+  unsigned long long Nu;
+  u32* COLMAX;
+  u64* RA11;
+  u32* RMAX;
+  double* RF;
+  u64* RMI;
+  u64* RVI;
+  int32_t* eci;
+  int32_t* ecj;
+  int64_t* ecnt;
+  long long ecap;
+  Ctl* ctl;
+  struct State {
+    u64 a11;
+    u32 rmax;
+    double fmax;
+    u128 mi, vi;
+    u32 g;
+    u32 ai;
+    u32 nz;
+  };
+  __device__ void begin(State& st, u32 g) {
+    st.a11 = 0;
+    st.rmax = 0;
+    st.fmax = 0.0;
+    st.mi = 0;
+    st.vi = 0;
+    st.g = g;
+    st.ai = A[g];
+    st.nz = 0;
+  }
+  __device__ void visit(State& st, u32 j, u32 x) {
+    const u32 bj = B[j];
+    st.a11 += (u64)x * (u64)(x - 1u) / 2u;
+    st.rmax = max(st.rmax, x);
+    double f = 2.0 * (double)x / (double)((u64)st.ai + (u64)bj);   // Eq. 3 ratio
+    st.fmax = f > st.fmax ? f : st.fmax;
+    double ab = (double)((u64)st.ai * (u64)bj);
+    double w = (double)x / Nd;
+    st.mi += fix96(w * log((double)((u64)x * Nu) / ab));           // Eq. 2 numerator term
+    st.vi += fix96(w * log((double)((u64)x * (u64)x) / ab));       // Eq. 1 term
+    atomicMax(&COLMAX[j], x);
+    st.nz += 1;
+    if (ecap > 0) {
+      unsigned long long idx = atomicAdd(&ctl->export_count, 1ull);
+      if ((long long)idx < ecap) { eci[idx] = (int32_t)st.g; ecj[idx] = (int32_t)j; ecnt[idx] = (int64_t)x; }
+    }
+  }
+  __device__ void finish(State& st, u32 g) {
+    __shared__ u64 r_lo[GBLOCK / 64], r_hi[GBLOCK / 64];
+    __shared__ double r_d[GBLOCK / 64];
+    u128 mi = block_sum_u128(st.mi, r_lo, r_hi);
+    u128 vi = block_sum_u128(st.vi, r_lo, r_hi);
+    u64 a11 = block_sum_u64(st.a11, r_lo);
+    u32 rmax = block_max_u32(st.rmax, r_lo);
+    double fmax = block_max_f64(st.fmax, r_d);
+    u64 nz = block_sum_u64(st.nz, r_lo);
+    if (threadIdx.x == 0) {
+      atomicAdd(&ctl->cells, (unsigned long long)nz);
+      RA11[g] = a11;
+      RMAX[g] = rmax;
+      RF[g] = fmax;
+      RMI[2 * (size_t)g] = (u64)mi;
+      RMI[2 * (size_t)g + 1] = (u64)(mi >> 64);
+      RVI[2 * (size_t)g] = (u64)vi;
+      RVI[2 * (size_t)g + 1] = (u64)(vi >> 64);
+    }
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Final reductions.  Stage 1: block b reduces a fixed contiguous range of labels
+// (thread t takes every blockDim-th label of it), then combines its threads in a
+// fixed order.  Stage 2: one block combines the stage-1 partials in block order.
+// Integer and fixed-point sums are exact; double sums have a fixed order, so the
+// result is bitwise reproducible.
+constexpr int FBLOCK = 256;
+
+struct ScorePart {
+  u64 K, sein, seout, sD2, np, pen_lo, pen_hi, pad;
+  double qds_a, s_dens, s_contr, s_exp, s_cond, pad2[3];
+};
+
+struct PerComm {
+  int64_t* size;
+  int64_t* degsum;
+  int64_t* ein;
+  int64_t* eout;
+  double* intra_density;
+  double* contraction;
+  double* expansion;
+  double* conductance;
+  double* q_term;
+  double* qds_term;
+};
+
+__global__ __launch_bounds__(FBLOCK) void k_score_final1(int L, const u32* __restrict__ N, const u32* __restrict__ D,
+                                                         const u32* __restrict__ I, const u32* __restrict__ NP,
+                                                         const u64* __restrict__ PEN, double twom, PerComm pc,
+                                                         ScorePart* __restrict__ parts) {
+  __shared__ u64 sh_lo[FBLOCK / 64], sh_hi[FBLOCK / 64];
+  __shared__ double sh_d[FBLOCK / 64];
+  const int R = (L + gridDim.x - 1) / gridDim.x;
+  const int c0 = blockIdx.x * R, c1 = min(L, c0 + R);
+  const double m = 0.5 * twom;
+  u64 K = 0, sein = 0, seout = 0, sD2 = 0, np = 0;
+  u128 pen = 0;
+  double qds_a = 0, s_dens = 0, s_contr = 0, s_exp = 0, s_cond = 0;
+  for (int c = c0 + threadIdx.x; c < c1; c += FBLOCK) {
+    const u32 nc = N[c];
+    int64_t o_size = 0, o_deg = 0, o_ein = 0, o_eout = 0;
+    double o_d = 0, o_contr = 0, o_exp = 0, o_cond = 0, o_q = 0, o_qds = 0;
+    if (nc > 0) {
+      const u32 Dc = D[c], Ic = I[c];
+      const u32 ein = Ic / 2u, eout = Dc - Ic;
+      const u128 pc128 = ((u128)PEN[2 * (size_t)c + 1] << 64) | PEN[2 * (size_t)c];
+      const double d = nc >= 2 ? (2.0 * (double)ein) / (double)((u64)nc * (u64)(nc - 1u)) : 0.0;
+      const double tot = (double)Dc / twom;
+      const double tdc = tot * d;
+      const double qa = (double)ein / m * d - tdc * tdc;
+      const double penc = unfix96(pc128);
+      o_size = nc; o_deg = Dc; o_ein = ein; o_eout = eout;
+      o_d = d;
+      o_contr = 2.0 * (double)ein / (double)nc;
+      o_exp = (double)eout / (double)nc;
+      o_cond = Dc > 0 ? (double)eout / (double)Dc : 0.0;
+      o_q = (double)ein / m - tot * tot;
+      o_qds = qa - penc;
+      K += 1; sein += ein; seout += eout; sD2 += (u64)Dc * (u64)Dc; np += NP[c]; pen += pc128;
+      qds_a += qa; s_dens += o_d; s_contr += o_contr; s_exp += o_exp; s_cond += o_cond;
+    }
+    if (pc.size) pc.size[c] = o_size;
+    if (pc.degsum) pc.degsum[c] = o_deg;
+    if (pc.ein) pc.ein[c] = o_ein;
+    if (pc.eout) pc.eout[c] = o_eout;
+    if (pc.intra_density) pc.intra_density[c] = o_d;
+    if (pc.contraction) pc.contraction[c] = o_contr;
+    if (pc.expansion) pc.expansion[c] = o_exp;
+    if (pc.conductance) pc.conductance[c] = o_cond;
+    if (pc.q_term) pc.q_term[c] = o_q;
+    if (pc.qds_term) pc.qds_term[c] = o_qds;
+  }
+  ScorePart p;
+  p.K = block_sum_u64(K, sh_lo);
+  p.sein = block_sum_u64(sein, sh_lo);
+  p.seout = block_sum_u64(seout, sh_lo);
+  p.sD2 = block_sum_u64(sD2, sh_lo);
+  p.np = block_sum_u64(np, sh_lo);
+  u128 pt = block_sum_u128(pen, sh_lo, sh_hi);
+  p.pen_lo = (u64)pt;
+  p.pen_hi = (u64)(pt >> 64);
+  p.pad = 0;
+  p.qds_a = block_sum_f64<FBLOCK / 64>(qds_a, sh_d);
+  p.s_dens = block_sum_f64<FBLOCK / 64>(s_dens, sh_d);
+  p.s_contr = block_sum_f64<FBLOCK / 64>(s_contr, sh_d);
+  p.s_exp = block_sum_f64<FBLOCK / 64>(s_exp, sh_d);
+  p.s_cond = block_sum_f64<FBLOCK / 64>(s_cond, sh_d);
+  p.pad2[0] = p.pad2[1] = p.pad2[2] = 0;
+  if (threadIdx.x == 0) parts[blockIdx.x] = p;
+}
+
+// device mirror of the public cq_score_result (same layout)
+struct ScoreResultDev {
+  int64_t n, m, K, num_pairs, sum_ein, sum_eout;
+  uint64_t sum_degsum_sq;
+  double Q, Qds, split_penalty;
+  double mean_intra_edges, mean_intra_density, mean_contraction;
+  double mean_inter_edges, mean_expansion, mean_conductance;
+  uint32_t device_flags, reserved;
+};
+
+__global__ void k_score_final2(int G, const ScorePart* __restrict__ parts, long long n, long long twom, long long ecap,
+                               Ctl* __restrict__ ctl, ScoreResultDev* __restrict__ out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  u64 K = 0, sein = 0, seout = 0, sD2 = 0, np = 0;
+  u128 pen = 0;
+  double qds_a = 0, s_dens = 0, s_contr = 0, s_exp = 0, s_cond = 0;
+  for (int b = 0; b < G; ++b) {
+    const ScorePart p = parts[b];
+    K += p.K; sein += p.sein; seout += p.seout; sD2 += p.sD2; np += p.np;
+    pen += ((u128)p.pen_hi << 64) | p.pen_lo;
+    qds_a += p.qds_a; s_dens += p.s_dens; s_contr += p.s_contr; s_exp += p.s_exp; s_cond += p.s_cond;
+  }
+  const long long m = twom / 2;
+  ScoreResultDev r;
+  r.n = n; r.m = m; r.K = (int64_t)K; r.num_pairs = (int64_t)np;
+  r.sum_ein = (int64_t)sein; r.sum_eout = (int64_t)seout; r.sum_degsum_sq = sD2;
+  // Eq. 8 summed over communities: sum_c E_c/m - (D_c/2m)^2 = (4 m sum_c E_c - sum_c D_c^2) / (4 m^2),
+  // evaluated from exact integers with a single rounding of numerator and denominator.
+  const long long qnum = 4ll * m * (long long)sein - (long long)sD2;
+  r.Q = (double)qnum / (double)(4ull * (u64)m * (u64)m);
+  const double p = unfix96(pen);
+  r.split_penalty = p;
+  r.Qds = qds_a - p;
+  const double Kd = (double)K;
+  r.mean_intra_edges = (double)sein / Kd;
+  r.mean_intra_density = s_dens / Kd;
+  r.mean_contraction = s_contr / Kd;
+  r.mean_inter_edges = (double)seout / Kd;
+  r.mean_expansion = s_exp / Kd;
+  r.mean_conductance = s_cond / Kd;
+  r.device_flags = ctl->flags | ((ecap > 0 && (long long)ctl->export_count > ecap) ? F_EXPORT : 0u);
+  r.reserved = 0;
+  *out = r;
+}
+
+// comparison final reduction ------------------------------------------------
+struct CmpPart {
+  u64 Ka, Kb, a11, X, Y, smax, mi_lo, mi_hi, vi_lo, vi_hi;
+  double fsum, ha, hb, pad;
+};
+
+__global__ __launch_bounds__(FBLOCK) void k_cmp_final1(int La, int Lb, int Ga, const u32* __restrict__ A, const u32* __restrict__ B,
+                                                       const u32* __restrict__ COLMAX, const u64* __restrict__ RA11,
+                                                       const u32* __restrict__ RMAX, const double* __restrict__ RF,
+                                                       const u64* __restrict__ RMI, const u64* __restrict__ RVI, double Nd,
+                                                       CmpPart* __restrict__ parts) {
+  __shared__ u64 sh_lo[FBLOCK / 64], sh_hi[FBLOCK / 64];
+  __shared__ double sh_d[FBLOCK / 64];
+  u64 Ka = 0, Kb = 0, a11 = 0, X = 0, Y = 0, smax = 0;
+  u128 mi = 0, vi = 0;
+  double fsum = 0, ha = 0, hb = 0;
+  if ((int)blockIdx.x < Ga) {  // rows: ground-truth communities
+    const int R = (La + Ga - 1) / Ga;
+    const int c0 = blockIdx.x * R, c1 = min(La, c0 + R);
+    for (int i = c0 + threadIdx.x; i < c1; i += FBLOCK) {
+      const u32 ai = A[i];
+      if (ai == 0) continue;
+      Ka += 1;
+      a11 += RA11[i];
+      smax += RMAX[i];
+      X += (u64)ai * (u64)(ai - 1u) / 2u;
+      mi += ((u128)RMI[2 * (size_t)i + 1] << 64) | RMI[2 * (size_t)i];
+      vi += ((u128)RVI[2 * (size_t)i + 1] << 64) | RVI[2 * (size_t)i];
+      fsum += (double)ai * RF[i];
+      ha += (double)ai / Nd * log((double)ai / Nd);
+    }
+  } else {  // columns: detected communities
+    const int Gb = gridDim.x - Ga;
+    const int R = (Lb + Gb - 1) / Gb;
+    const int c0 = (blockIdx.x - Ga) * R, c1 = min(Lb, c0 + R);
+    for (int j = c0 + threadIdx.x; j < c1; j += FBLOCK) {
+      const u32 bj = B[j];
+      if (bj == 0) continue;
+      Kb += 1;
+      smax += COLMAX[j];
+      Y += (u64)bj * (u64)(bj - 1u) / 2u;
+      hb += (double)bj / Nd * log((double)bj / Nd);
+    }
+  }
+  CmpPart p;
+  p.Ka = block_sum_u64(Ka, sh_lo);
+  p.Kb = block_sum_u64(Kb, sh_lo);
+  p.a11 = block_sum_u64(a11, sh_lo);
+  p.X = block_sum_u64(X, sh_lo);
+  p.Y = block_sum_u64(Y, sh_lo);
+  p.smax = block_sum_u64(smax, sh_lo);
+  u128 t = block_sum_u128(mi, sh_lo, sh_hi);
+  p.mi_lo = (u64)t; p.mi_hi = (u64)(t >> 64);
+  t = block_sum_u128(vi, sh_lo, sh_hi);
+  p.vi_lo = (u64)t; p.vi_hi = (u64)(t >> 64);
+  p.fsum = block_sum_f64<FBLOCK / 64>(fsum, sh_d);
+  p.ha = block_sum_f64<FBLOCK / 64>(ha, sh_d);
+  p.hb = block_sum_f64<FBLOCK / 64>(hb, sh_d);
+  p.pad = 0;
+  if (threadIdx.x == 0) parts[blockIdx.x] = p;
+}
+
+struct CmpResultDev {
+  int64_t n, Ka, Kb, nnz, a11, a10, a01, a00, A;
+  double VI, NMI, F, NVD, RI, ARI, JI;
+  uint32_t device_flags, reserved;
+};
+
+__device__ __forceinline__ double i128_to_f64(__int128 v) {
+  bool neg = v < 0;
+  u128 a = neg ? (u128)(-v) : (u128)v;
+  double d = ldexp((double)(u64)(a >> 64), 64) + (double)(u64)a;
+  return neg ? -d : d;
+}
+
+__global__ void k_cmp_final2(int G, const CmpPart* __restrict__ parts, long long n, long long ecap, Ctl* __restrict__ ctl,
+                             CmpResultDev* __restrict__ out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  u64 Ka = 0, Kb = 0, a11 = 0, X = 0, Y = 0, smax = 0;
+  u128 mi = 0, vi = 0;
+  double fsum = 0, ha = 0, hb = 0;
+  for (int b = 0; b < G; ++b) {
+    const CmpPart p = parts[b];
+    Ka += p.Ka; Kb += p.Kb; a11 += p.a11; X += p.X; Y += p.Y; smax += p.smax;
+    mi += ((u128)p.mi_hi << 64) | p.mi_lo;
+    vi += ((u128)p.vi_hi << 64) | p.vi_lo;
+    fsum += p.fsum; ha += p.ha; hb += p.hb;
+  }
+  const double Nd = (double)n;
+  const u64 A = (u64)n * (u64)(n - 1) / 2u;
+  CmpResultDev r;
+  r.n = n; r.Ka = (int64_t)Ka; r.Kb = (int64_t)Kb; r.nnz = (int64_t)ctl->cells;
+  r.a11 = (int64_t)a11;
+  r.a10 = (int64_t)(X - a11);
+  r.a01 = (int64_t)(Y - a11);
+  r.a00 = (int64_t)(A - X - Y + a11);
+  r.A = (int64_t)A;
+  r.VI = -unfix96(vi);
+  const double den = ha + hb;
+  r.NMI = den != 0.0 ? -2.0 * unfix96(mi) / den : 1.0;
+  r.F = fsum / Nd;
+  r.NVD = 1.0 - (double)smax / (2.0 * Nd);
+  r.RI = (double)(a11 + (A - X - Y + a11)) / (double)A;
+  // Eq. 6 with M = (a11+a10)(a11+a01)/A, numerator and denominator scaled by 2A:
+  // ARI = (2 A a11 - 2 X Y) / (A (X + Y) - 2 X Y), exact in 128-bit integers.
+  const __int128 XY = (__int128)X * (__int128)Y;
+  const __int128 anum = 2 * (__int128)A * (__int128)a11 - 2 * XY;
+  const __int128 aden = (__int128)A * (__int128)(X + Y) - 2 * XY;
+  r.ARI = aden != 0 ? i128_to_f64(anum) / i128_to_f64(aden) : 1.0;
+  const u64 jden = a11 + (X - a11) + (Y - a11);
+  r.JI = jden != 0 ? (double)a11 / (double)jden : 1.0;
+  r.device_flags = ctl->flags | ((ecap > 0 && (long long)ctl->export_count > ecap) ? F_EXPORT : 0u);
+  r.reserved = 0;
+  *out = r;
+}
+
+}  // namespace cq

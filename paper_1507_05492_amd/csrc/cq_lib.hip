@@ -1,0 +1,510 @@
+// cq_lib.hip -- host runtime and C ABI (include/cq.h) of the gfx950 community-quality
+// library: argument checks, workspace layout, launch sequencing on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "cq.h"
+#include "cq_kernels.hpp"
+
+using namespace cq;
+
+struct cq_context {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int num_cus = 256;
+  void* pinned = nullptr;  // host staging for result structs (hipHostMalloc)
+  u32* dscratch = nullptr; // 2 words used by graph checks
+  char err[512] = {0};
+};
+
+struct cq_graph {
+  cq_context* ctx = nullptr;
+  int32_t n = 0;
+  int64_t nnz = 0;
+  const int32_t* rp = nullptr;
+  const int32_t* col = nullptr;
+  int64_t max_degree = 0;
+  uint32_t validated = 0;
+};
+
+static_assert(sizeof(ScoreResultDev) == sizeof(cq_score_result), "score result layout");
+static_assert(sizeof(CmpResultDev) == sizeof(cq_compare_result), "compare result layout");
+static_assert(sizeof(PerComm) == sizeof(cq_per_community), "per-community layout");
+
+namespace {
+
+constexpr int64_t PRIV_MAX = 16384;    // labels handled by LDS-private node histograms
+constexpr int64_t DIRECT_MAX = 16384;  // labels handled by direct-indexed group tables
+constexpr u32 HASH_WORDS = 16384;      // LDS words of the group hash table (8192 slots)
+constexpr size_t ALIGN = 256;
+
+cq_status fail(cq_context* ctx, cq_status s, const char* fmt, ...) {
+  if (ctx) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(ctx->err, sizeof(ctx->err), fmt, ap);
+    va_end(ap);
+  }
+  return s;
+}
+
+struct Carve {
+  size_t off = 0;
+  size_t take(size_t bytes) {
+    size_t o = off;
+    off += (std::max<size_t>(bytes, 1) + ALIGN - 1) & ~(ALIGN - 1);
+    return o;
+  }
+};
+
+int pick_chunk(int64_t n) {
+  int64_t c = 1024;
+  while (c < 65536 && c * 256 < n) c <<= 1;
+  return (int)c;
+}
+
+unsigned grid_for(int64_t items, int per_block, unsigned cap) {
+  int64_t g = (items + per_block - 1) / per_block;
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>(g, cap));
+}
+
+struct ScoreLayout {
+  bool priv;
+  int chunk, W, G;
+  size_t ctl, N, D, start, order, I, NP, PEN, SZ, loc, HN, HD, CB, parts, res, total;
+};
+
+ScoreLayout score_layout(int64_t n, int64_t nnz, int64_t L) {
+  ScoreLayout s{};
+  Carve c;
+  s.priv = L <= PRIV_MAX;
+  s.chunk = pick_chunk(n);
+  s.W = (int)((n + s.chunk - 1) / s.chunk);
+  s.G = (int)std::min<int64_t>(128, std::max<int64_t>(1, (L + 1023) / 1024));
+  s.ctl = c.take(sizeof(Ctl));
+  s.N = c.take(4 * L);
+  s.D = c.take(4 * L);
+  s.start = c.take(4 * L);
+  s.order = c.take(4 * L);
+  s.I = c.take(4 * L);
+  s.NP = c.take(4 * L);
+  s.PEN = c.take(16 * L);
+  s.SZ = s.priv ? 0 : c.take(8 * L);
+  s.loc = c.take(4 * n);
+  s.HN = s.priv ? c.take(4 * (size_t)s.W * L) : 0;
+  s.HD = s.priv ? c.take(4 * (size_t)s.W * L) : 0;
+  s.CB = c.take(4 * nnz);
+  s.parts = c.take(sizeof(ScorePart) * s.G);
+  s.res = c.take(sizeof(ScoreResultDev));
+  s.total = c.off;
+  return s;
+}
+
+struct CmpLayout {
+  bool privA, privB;
+  int chunk, W, Wb, Ga, Gb;
+  size_t ctl, A, B, start, order, COLMAX, RA11, RMAX, RF, RMI, RVI, SZ, loc, HN, HB, CB, parts, res, total;
+};
+
+CmpLayout cmp_layout(int64_t n, int64_t La, int64_t Lb) {
+  CmpLayout s{};
+  Carve c;
+  s.privA = La <= PRIV_MAX;
+  s.privB = Lb <= PRIV_MAX;
+  s.chunk = pick_chunk(n);
+  s.W = (int)((n + s.chunk - 1) / s.chunk);
+  s.Wb = (int)std::min<int64_t>(256, std::max<int64_t>(1, (n + 8191) / 8192));
+  s.Ga = (int)std::min<int64_t>(64, std::max<int64_t>(1, (La + 1023) / 1024));
+  s.Gb = (int)std::min<int64_t>(64, std::max<int64_t>(1, (Lb + 1023) / 1024));
+  s.ctl = c.take(sizeof(Ctl));
+  s.A = c.take(4 * La);
+  s.B = c.take(4 * Lb);
+  s.start = c.take(4 * La);
+  s.order = c.take(4 * La);
+  s.COLMAX = c.take(4 * Lb);
+  s.RA11 = c.take(8 * La);
+  s.RMAX = c.take(4 * La);
+  s.RF = c.take(8 * La);
+  s.RMI = c.take(16 * La);
+  s.RVI = c.take(16 * La);
+  s.SZ = s.privA ? 0 : c.take(8 * La);
+  s.loc = c.take(4 * n);
+  s.HN = s.privA ? c.take(4 * (size_t)s.W * La) : 0;
+  s.HB = s.privB ? c.take(4 * (size_t)s.Wb * Lb) : 0;
+  s.CB = c.take(4 * n);
+  s.parts = c.take(sizeof(CmpPart) * (s.Ga + s.Gb));
+  s.res = c.take(sizeof(CmpResultDev));
+  s.total = c.off;
+  return s;
+}
+
+template <class T>
+T* at(void* ws, size_t off) {
+  return reinterpret_cast<T*>(static_cast<char*>(ws) + off);
+}
+
+cq_status launch_status(cq_context* ctx, const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(ctx, CQ_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+  return CQ_OK;
+}
+
+void fill(u32* p, size_t words, u32 v, hipStream_t s) {
+  k_fill_u32<<<grid_for((int64_t)words, 256, 1024), 256, 0, s>>>(p, words, v);
+}
+
+template <class V>
+unsigned group_grid(cq_context* ctx, size_t lds_bytes) {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_groups<V>, GBLOCK, lds_bytes) != hipSuccess || nb < 1) nb = 1;
+  return (unsigned)(ctx->num_cus * nb);
+}
+
+cq_status map_flags(cq_context* ctx, u32 flags) {
+  if (flags & F_LABEL) return fail(ctx, CQ_E_LABEL_RANGE, "a label is outside [0, num_labels)");
+  if (flags & F_STACK) return fail(ctx, CQ_E_DEVICE, "internal: group table split limit reached");
+  if (flags & F_EXPORT) return fail(ctx, CQ_E_CAPACITY, "export table capacity too small");
+  return CQ_OK;
+}
+
+cq_status score_enqueue(cq_context* ctx, const cq_graph* g, const int32_t* labels, int32_t L, void* ws, size_t ws_bytes,
+                        ScoreResultDev* d_out, const cq_per_community* per_comm, const cq_pair_table* pairs) {
+  if (!ctx) return CQ_E_INVALID_ARG;
+  ctx->err[0] = 0;
+  if (!g || !labels || !d_out) return fail(ctx, CQ_E_INVALID_ARG, "null graph, labels or output");
+  if (L < 1) return fail(ctx, CQ_E_INVALID_ARG, "num_labels must be >= 1");
+  if (g->nnz == 0) return fail(ctx, CQ_E_NO_EDGES, "graph has no edges");
+  if (pairs && pairs->capacity > 0 && (!pairs->ci || !pairs->cj || !pairs->count))
+    return fail(ctx, CQ_E_INVALID_ARG, "pair table with null arrays");
+  const int64_t n = g->n, nnz = g->nnz;
+  const ScoreLayout lay = score_layout(n, nnz, L);
+  if (!ws || ws_bytes < lay.total)
+    return fail(ctx, CQ_E_WORKSPACE, "workspace %zu bytes, need %zu", ws_bytes, lay.total);
+  hipStream_t s = ctx->stream;
+  Ctl* ctl = at<Ctl>(ws, lay.ctl);
+  u32* N = at<u32>(ws, lay.N);
+  u32* D = at<u32>(ws, lay.D);
+  u32* start = at<u32>(ws, lay.start);
+  u32* order = at<u32>(ws, lay.order);
+  u32* I = at<u32>(ws, lay.I);
+  u32* NP = at<u32>(ws, lay.NP);
+  u64* PEN = at<u64>(ws, lay.PEN);
+  u32* loc = at<u32>(ws, lay.loc);
+  u32* CB = at<u32>(ws, lay.CB);
+  ScorePart* parts = at<ScorePart>(ws, lay.parts);
+
+  fill(reinterpret_cast<u32*>(ctl), sizeof(Ctl) / 4, 0, s);
+  const u32* PM = nullptr;
+  if (lay.priv) {
+    u32* HN = at<u32>(ws, lay.HN);
+    u32* HD = at<u32>(ws, lay.HD);
+    k_node_priv<true><<<lay.W, 1024, 2 * (size_t)L * 4, s>>>((int)n, labels, g->rp, L, lay.chunk, HN, HD, loc, ctl);
+    k_colscan<true, true><<<grid_for(L, 256, 1u << 30), 256, 0, s>>>(lay.W, L, HN, HD, N, D);
+    PM = HD;
+  } else {
+    unsigned long long* SZ = at<unsigned long long>(ws, lay.SZ);
+    fill(reinterpret_cast<u32*>(SZ), 2 * (size_t)L, 0, s);
+    k_node_global<true><<<grid_for(n, 256, 8192), 256, 0, s>>>((int)n, labels, g->rp, L, SZ, loc, ctl);
+    k_unpack<<<grid_for(L, 256, 4096), 256, 0, s>>>(L, SZ, N, D);
+  }
+  k_scan_order<<<1, 1024, 0, s>>>(L, N, D, start, order, ctl);
+  if (lay.priv)
+    k_gather<true><<<grid_for(n, GROWS, 1u << 30), GROWS, 0, s>>>((int)n, g->rp, g->col, labels, L, lay.chunk, PM, start, loc, CB);
+  else
+    k_gather<false><<<grid_for(n, GROWS, 1u << 30), GROWS, 0, s>>>((int)n, g->rp, g->col, labels, L, lay.chunk, PM, start, loc, CB);
+
+  ScoreVis vis;
+  vis.N = N;
+  vis.twom = (double)nnz;
+  vis.I = I;
+  vis.NP = NP;
+  vis.PEN = PEN;
+  vis.eci = pairs ? pairs->ci : nullptr;
+  vis.ecj = pairs ? pairs->cj : nullptr;
+  vis.ecnt = pairs ? pairs->count : nullptr;
+  vis.ecap = pairs ? pairs->capacity : 0;
+  vis.ctl = ctl;
+  const u32 lds_words = L <= DIRECT_MAX ? std::max<u32>((u32)L, 128u) : HASH_WORDS;
+  const size_t lds = (size_t)lds_words * 4;
+  k_groups<ScoreVis><<<group_grid<ScoreVis>(ctx, lds), GBLOCK, lds, s>>>(CB, start, D, order, ctl, (u32)L, lds_words, vis);
+
+  PerComm pc;
+  std::memset(&pc, 0, sizeof(pc));
+  if (per_comm) std::memcpy(&pc, per_comm, sizeof(pc));
+  k_score_final1<<<lay.G, FBLOCK, 0, s>>>(L, N, D, I, NP, PEN, (double)nnz, pc, parts);
+  k_score_final2<<<1, 64, 0, s>>>(lay.G, parts, n, nnz, vis.ecap, ctl, d_out);
+  return launch_status(ctx, "score launch");
+}
+
+cq_status compare_enqueue(cq_context* ctx, int32_t n, const int32_t* la, int32_t La, const int32_t* lb, int32_t Lb, void* ws,
+                          size_t ws_bytes, CmpResultDev* d_out, const cq_cell_table* cells) {
+  if (!ctx) return CQ_E_INVALID_ARG;
+  ctx->err[0] = 0;
+  if (!la || !lb || !d_out) return fail(ctx, CQ_E_INVALID_ARG, "null labels or output");
+  if (n < 2) return fail(ctx, CQ_E_INVALID_ARG, "n must be >= 2");
+  if (La < 1 || Lb < 1) return fail(ctx, CQ_E_INVALID_ARG, "num_labels must be >= 1");
+  if (cells && cells->capacity > 0 && (!cells->ci || !cells->cj || !cells->count))
+    return fail(ctx, CQ_E_INVALID_ARG, "cell table with null arrays");
+  const CmpLayout lay = cmp_layout(n, La, Lb);
+  if (!ws || ws_bytes < lay.total)
+    return fail(ctx, CQ_E_WORKSPACE, "workspace %zu bytes, need %zu", ws_bytes, lay.total);
+  hipStream_t s = ctx->stream;
+  Ctl* ctl = at<Ctl>(ws, lay.ctl);
+  u32* A = at<u32>(ws, lay.A);
+  u32* B = at<u32>(ws, lay.B);
+  u32* start = at<u32>(ws, lay.start);
+  u32* order = at<u32>(ws, lay.order);
+  u32* COLMAX = at<u32>(ws, lay.COLMAX);
+  u32* loc = at<u32>(ws, lay.loc);
+  u32* CB = at<u32>(ws, lay.CB);
+  fill(reinterpret_cast<u32*>(ctl), sizeof(Ctl) / 4, 0, s);
+  fill(COLMAX, (size_t)Lb, 0, s);
+  const u32* PM = nullptr;
+  if (lay.privA) {
+    u32* HN = at<u32>(ws, lay.HN);
+    k_node_priv<false><<<lay.W, 1024, (size_t)La * 4, s>>>(n, la, nullptr, La, lay.chunk, HN, nullptr, loc, ctl);
+    k_colscan<false, true><<<grid_for(La, 256, 1u << 30), 256, 0, s>>>(lay.W, La, HN, HN, A, nullptr);
+    PM = HN;
+  } else {
+    unsigned long long* SZ = at<unsigned long long>(ws, lay.SZ);
+    fill(reinterpret_cast<u32*>(SZ), 2 * (size_t)La, 0, s);
+    k_node_global<false><<<grid_for(n, 256, 8192), 256, 0, s>>>(n, la, nullptr, La, SZ, loc, ctl);
+    k_unpack<<<grid_for(La, 256, 4096), 256, 0, s>>>(La, SZ, A, nullptr);
+  }
+  if (lay.privB) {
+    u32* HB = at<u32>(ws, lay.HB);
+    k_hist_priv<<<lay.Wb, 1024, (size_t)Lb * 4, s>>>(n, lb, Lb, HB, ctl);
+    k_colscan<false, false><<<grid_for(Lb, 256, 1u << 30), 256, 0, s>>>(lay.Wb, Lb, HB, HB, B, nullptr);
+  } else {
+    fill(B, (size_t)Lb, 0, s);
+    k_hist_global<<<grid_for(n, 256, 8192), 256, 0, s>>>(n, lb, Lb, B, ctl);
+  }
+  k_scan_order<<<1, 1024, 0, s>>>(La, A, A, start, order, ctl);
+  if (lay.privA)
+    k_cmp_scatter<true><<<grid_for(n, 256, 8192), 256, 0, s>>>(n, la, lb, La, Lb, lay.chunk, PM, start, loc, CB);
+  else
+    k_cmp_scatter<false><<<grid_for(n, 256, 8192), 256, 0, s>>>(n, la, lb, La, Lb, lay.chunk, PM, start, loc, CB);
+
+  CmpVis vis;
+  vis.A = A;
+  vis.B = B;
+  vis.Nd = (double)n;
+  vis.Nu = (unsigned long long)n;
+  vis.COLMAX = COLMAX;
+  vis.RA11 = at<u64>(ws, lay.RA11);
+  vis.RMAX = at<u32>(ws, lay.RMAX);
+  vis.RF = at<double>(ws, lay.RF);
+  vis.RMI = at<u64>(ws, lay.RMI);
+  vis.RVI = at<u64>(ws, lay.RVI);
+  vis.eci = cells ? cells->ci : nullptr;
+  vis.ecj = cells ? cells->cj : nullptr;
+  vis.ecnt = cells ? cells->count : nullptr;
+  vis.ecap = cells ? cells->capacity : 0;
+  vis.ctl = ctl;
+  const u32 lds_words = Lb <= DIRECT_MAX ? std::max<u32>((u32)Lb, 128u) : HASH_WORDS;
+  const size_t lds = (size_t)lds_words * 4;
+  k_groups<CmpVis><<<group_grid<CmpVis>(ctx, lds), GBLOCK, lds, s>>>(CB, start, A, order, ctl, (u32)Lb, lds_words, vis);
+  CmpPart* parts = at<CmpPart>(ws, lay.parts);
+  k_cmp_final1<<<lay.Ga + lay.Gb, FBLOCK, 0, s>>>(La, Lb, lay.Ga, A, B, COLMAX, vis.RA11, vis.RMAX, vis.RF, vis.RMI, vis.RVI,
+                                                 (double)n, parts);
+  k_cmp_final2<<<1, 64, 0, s>>>(lay.Ga + lay.Gb, parts, n, vis.ecap, ctl, d_out);
+  return launch_status(ctx, "compare launch");
+}
+
+template <class R>
+cq_status fetch(cq_context* ctx, const void* d_res, R* h_out) {
+  hipError_t e = hipMemcpyAsync(ctx->pinned, d_res, sizeof(R), hipMemcpyDeviceToHost, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) return fail(ctx, CQ_E_DEVICE, "result copy: %s", hipGetErrorString(e));
+  std::memcpy(h_out, ctx->pinned, sizeof(R));
+  return CQ_OK;
+}
+
+void set_big_lds(const void* fn, size_t bytes) {
+  (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* cq_status_string(cq_status s) {
+  switch (s) {
+    case CQ_OK: return "CQ_OK";
+    case CQ_E_INVALID_ARG: return "CQ_E_INVALID_ARG";
+    case CQ_E_LABEL_RANGE: return "CQ_E_LABEL_RANGE";
+    case CQ_E_GRAPH_FORMAT: return "CQ_E_GRAPH_FORMAT";
+    case CQ_E_OVERFLOW: return "CQ_E_OVERFLOW";
+    case CQ_E_WORKSPACE: return "CQ_E_WORKSPACE";
+    case CQ_E_NO_EDGES: return "CQ_E_NO_EDGES";
+    case CQ_E_DEVICE: return "CQ_E_DEVICE";
+    case CQ_E_BUSY: return "CQ_E_BUSY";
+    case CQ_E_CANCELLED: return "CQ_E_CANCELLED";
+    case CQ_E_CAPACITY: return "CQ_E_CAPACITY";
+    default: return "CQ_E_UNKNOWN";
+  }
+}
+
+cq_status cq_context_create(int device, void* hip_stream, cq_context** out) {
+  if (!out) return CQ_E_INVALID_ARG;
+  *out = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) return CQ_E_DEVICE;
+  if (hipSetDevice(device) != hipSuccess) return CQ_E_DEVICE;
+  cq_context* ctx = new (std::nothrow) cq_context();
+  if (!ctx) return CQ_E_DEVICE;
+  ctx->device = device;
+  ctx->stream = static_cast<hipStream_t>(hip_stream);
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) == hipSuccess) ctx->num_cus = prop.multiProcessorCount;
+  if (hipHostMalloc(&ctx->pinned, 4096, hipHostMallocDefault) != hipSuccess ||
+      hipMalloc(&ctx->dscratch, 256) != hipSuccess) {
+    if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+    delete ctx;
+    return CQ_E_DEVICE;
+  }
+  set_big_lds(reinterpret_cast<const void*>(k_node_priv<true>), 2 * PRIV_MAX * 4);
+  set_big_lds(reinterpret_cast<const void*>(k_node_priv<false>), PRIV_MAX * 4);
+  set_big_lds(reinterpret_cast<const void*>(k_hist_priv), PRIV_MAX * 4);
+  set_big_lds(reinterpret_cast<const void*>(k_groups<ScoreVis>), std::max<size_t>(DIRECT_MAX, HASH_WORDS) * 4);
+  set_big_lds(reinterpret_cast<const void*>(k_groups<CmpVis>), std::max<size_t>(DIRECT_MAX, HASH_WORDS) * 4);
+  *out = ctx;
+  return CQ_OK;
+}
+
+cq_status cq_context_set_stream(cq_context* ctx, void* hip_stream) {
+  if (!ctx) return CQ_E_INVALID_ARG;
+  ctx->stream = static_cast<hipStream_t>(hip_stream);
+  return CQ_OK;
+}
+
+void cq_context_destroy(cq_context* ctx) {
+  if (!ctx) return;
+  if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+  if (ctx->dscratch) (void)hipFree(ctx->dscratch);
+  delete ctx;
+}
+
+const char* cq_context_last_error(const cq_context* ctx) { return ctx ? ctx->err : "null context"; }
+
+cq_status cq_graph_load(cq_context* ctx, int32_t n, int64_t nnz, const int32_t* d_row_ptr, const int32_t* d_col_idx,
+                        uint32_t flags, cq_graph** out) {
+  if (!ctx) return CQ_E_INVALID_ARG;
+  ctx->err[0] = 0;
+  if (!out || !d_row_ptr || (nnz > 0 && !d_col_idx)) return fail(ctx, CQ_E_INVALID_ARG, "null pointer");
+  *out = nullptr;
+  if (n < 1) return fail(ctx, CQ_E_INVALID_ARG, "n must be >= 1");
+  if (flags & ~CQ_VALIDATE_GRAPH) return fail(ctx, CQ_E_INVALID_ARG, "unknown flag bits");
+  if (nnz < 0 || nnz >= (int64_t)1 << 31) return fail(ctx, CQ_E_OVERFLOW, "nnz must be in [0, 2^31)");
+  if (nnz % 2) return fail(ctx, CQ_E_GRAPH_FORMAT, "an undirected CSR stores an even number of entries");
+  hipStream_t s = ctx->stream;
+  int32_t ends[2] = {0, 0};
+  hipError_t e = hipMemcpyAsync(&ends[0], d_row_ptr, 4, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(&ends[1], d_row_ptr + n, 4, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return fail(ctx, CQ_E_DEVICE, "reading row_ptr: %s", hipGetErrorString(e));
+  if (ends[0] != 0 || (int64_t)ends[1] != nnz) return fail(ctx, CQ_E_GRAPH_FORMAT, "row_ptr[0] != 0 or row_ptr[n] != nnz");
+  fill(ctx->dscratch, 2, 0, s);
+  k_check_csr<<<grid_for(std::max<int64_t>(n, nnz), 256, 4096), 256, 0, s>>>(n, nnz, d_row_ptr, d_col_idx, ctx->dscratch,
+                                                                            ctx->dscratch + 1);
+  u32 res[2] = {0, 0};
+  e = hipMemcpyAsync(res, ctx->dscratch, 8, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return fail(ctx, CQ_E_DEVICE, "graph check: %s", hipGetErrorString(e));
+  if (res[0]) return fail(ctx, CQ_E_GRAPH_FORMAT, "row_ptr not monotone or col_idx out of range");
+  uint32_t validated = 0;
+  if (flags & CQ_VALIDATE_GRAPH) {
+    fill(ctx->dscratch, 1, 0, s);
+    k_check_symmetric<<<grid_for(n, 4, 8192), 256, 0, s>>>(n, d_row_ptr, d_col_idx, ctx->dscratch);
+    u32 f = 0;
+    e = hipMemcpyAsync(&f, ctx->dscratch, 4, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return fail(ctx, CQ_E_DEVICE, "symmetry check: %s", hipGetErrorString(e));
+    if (f) return fail(ctx, CQ_E_GRAPH_FORMAT, "graph is not a simple symmetric CSR with sorted rows");
+    validated = CQ_VALIDATE_GRAPH;
+  }
+  cq_graph* g = new (std::nothrow) cq_graph();
+  if (!g) return fail(ctx, CQ_E_DEVICE, "out of host memory");
+  g->ctx = ctx;
+  g->n = n;
+  g->nnz = nnz;
+  g->rp = d_row_ptr;
+  g->col = d_col_idx;
+  g->max_degree = res[1];
+  g->validated = validated;
+  *out = g;
+  return CQ_OK;
+}
+
+cq_status cq_graph_get_stats(const cq_graph* g, cq_graph_stats* out) {
+  if (!g || !out) return CQ_E_INVALID_ARG;
+  out->n = g->n;
+  out->nnz = g->nnz;
+  out->m = g->nnz / 2;
+  out->max_degree = g->max_degree;
+  out->validated = g->validated;
+  return CQ_OK;
+}
+
+void cq_graph_release(cq_graph* g) { delete g; }
+
+size_t cq_score_workspace_size(const cq_graph* g, int32_t num_labels) {
+  if (!g || num_labels < 1) return 0;
+  return score_layout(g->n, g->nnz, num_labels).total;
+}
+
+size_t cq_compare_workspace_size(int32_t n, int32_t num_labels_a, int32_t num_labels_b) {
+  if (n < 2 || num_labels_a < 1 || num_labels_b < 1) return 0;
+  return cmp_layout(n, num_labels_a, num_labels_b).total;
+}
+
+cq_status cq_score_partition_async(cq_context* ctx, const cq_graph* g, const int32_t* d_labels, int32_t num_labels, void* d_ws,
+                                   size_t ws_bytes, cq_score_result* d_out, const cq_per_community* per_comm,
+                                   const cq_pair_table* pairs) {
+  return score_enqueue(ctx, g, d_labels, num_labels, d_ws, ws_bytes, reinterpret_cast<ScoreResultDev*>(d_out), per_comm, pairs);
+}
+
+cq_status cq_score_partition(cq_context* ctx, const cq_graph* g, const int32_t* d_labels, int32_t num_labels, void* d_ws,
+                             size_t ws_bytes, cq_score_result* h_out, const cq_per_community* per_comm,
+                             const cq_pair_table* pairs) {
+  if (!ctx) return CQ_E_INVALID_ARG;
+  if (!h_out) return fail(ctx, CQ_E_INVALID_ARG, "null result pointer");
+  if (!g) return fail(ctx, CQ_E_INVALID_ARG, "null graph");
+  const ScoreLayout lay = score_layout(g->n, g->nnz, std::max(num_labels, 1));
+  ScoreResultDev* d_res = (d_ws && ws_bytes >= lay.total) ? at<ScoreResultDev>(d_ws, lay.res) : nullptr;
+  cq_status st = score_enqueue(ctx, g, d_labels, num_labels, d_ws, ws_bytes, d_res ? d_res : reinterpret_cast<ScoreResultDev*>(1),
+                               per_comm, pairs);
+  if (st != CQ_OK) return st;
+  st = fetch(ctx, d_res, h_out);
+  if (st != CQ_OK) return st;
+  return map_flags(ctx, h_out->device_flags);
+}
+
+cq_status cq_compare_partitions_async(cq_context* ctx, int32_t n, const int32_t* d_labels_a, int32_t num_labels_a,
+                                      const int32_t* d_labels_b, int32_t num_labels_b, void* d_ws, size_t ws_bytes,
+                                      cq_compare_result* d_out, const cq_cell_table* cells) {
+  return compare_enqueue(ctx, n, d_labels_a, num_labels_a, d_labels_b, num_labels_b, d_ws, ws_bytes,
+                         reinterpret_cast<CmpResultDev*>(d_out), cells);
+}
+
+cq_status cq_compare_partitions(cq_context* ctx, int32_t n, const int32_t* d_labels_a, int32_t num_labels_a,
+                                const int32_t* d_labels_b, int32_t num_labels_b, void* d_ws, size_t ws_bytes,
+                                cq_compare_result* h_out, const cq_cell_table* cells) {
+  if (!ctx) return CQ_E_INVALID_ARG;
+  if (!h_out) return fail(ctx, CQ_E_INVALID_ARG, "null result pointer");
+  const CmpLayout lay = cmp_layout(std::max(n, 2), std::max(num_labels_a, 1), std::max(num_labels_b, 1));
+  CmpResultDev* d_res = (d_ws && ws_bytes >= lay.total) ? at<CmpResultDev>(d_ws, lay.res) : nullptr;
+  cq_status st = compare_enqueue(ctx, n, d_labels_a, num_labels_a, d_labels_b, num_labels_b, d_ws, ws_bytes,
+                                 d_res ? d_res : reinterpret_cast<CmpResultDev*>(1), cells);
+  if (st != CQ_OK) return st;
+  st = fetch(ctx, d_res, h_out);
+  if (st != CQ_OK) return st;
+  return map_flags(ctx, h_out->device_flags);
+}
+
+}  // extern "C"

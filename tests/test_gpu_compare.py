@@ -1,0 +1,102 @@
+"""GPU parity: cq_compare_partitions against the oracle (Section II-A, Eqs. 1-7).
+
+Pair counts and the contingency table must match bit for bit; binary64 metrics within
+the tolerance in tests/gpu_util.py."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from cqgen import CONFIGS, lfr_graph, perturb_labels, random_labels
+from tests.gpu_util import check_compare, note, sort_rows
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def cq():
+    from paper_1507_05492_amd import cq as mod
+
+    return mod
+
+
+@pytest.fixture(scope="module")
+def ctx(cq):
+    c = cq.Context(0)
+    yield c
+    c.close()
+
+
+def run_cmp(cq, ctx, a, La, b, Lb, what, cells=True):
+    note(what)
+    a = np.asarray(a, np.int32)
+    b = np.asarray(b, np.int32)
+    o = oracle.compare(a, La, b, Lb, want_cells=cells)
+    cap = int(o.result["nnz"]) if cells else 0
+    r, ct = cq.compare_partitions(ctx, torch.as_tensor(a).cuda(), La, torch.as_tensor(b).cuda(), Lb, cells_capacity=cap)
+    check_compare(r, o.result, what)
+    if cells:
+        assert np.array_equal(sort_rows(ct), o.cells), f"{what}: contingency table differs"
+    return r, o
+
+
+def test_tiny_lfr(cq, ctx):
+    g = lfr_graph(CONFIGS["tiny_1k"], 1)
+    lab = g.labels
+    pert = perturb_labels(lab, g.num_labels, 0.10, 101)
+    run_cmp(cq, ctx, lab.numpy(), g.num_labels, pert.numpy(), g.num_labels, "tiny_1k GT vs 10%")
+
+
+@pytest.mark.parametrize("name", ["m100k_mu0.1", "m100k_mu0.3", "m100k_mu0.5"])
+def test_m100k_sweep(cq, ctx, name):
+    g = lfr_graph(CONFIGS[name], 11)
+    for pct in (5, 10, 15, 20, 25, 30):
+        pert = perturb_labels(g.labels, g.num_labels, pct / 100, 1000 + pct)
+        run_cmp(cq, ctx, g.labels.numpy(), g.num_labels, pert.numpy(), g.num_labels, f"{name} GT vs {pct}%",
+                cells=(pct in (5, 30)))
+
+
+def test_identical_symmetric_relabelled(cq, ctx):
+    a = random_labels(20000, 300, 1).numpy()
+    r, _ = run_cmp(cq, ctx, a, 300, a, 300, "identical")
+    assert r["ARI"] == 1.0 and r["NVD"] == 0.0 and abs(r["NMI"] - 1.0) < 1e-15 and r["VI"] == 0.0
+    b = random_labels(20000, 150, 2).numpy()
+    r1, _ = run_cmp(cq, ctx, a, 300, b, 150, "random vs random")
+    r2, _ = run_cmp(cq, ctx, b, 150, a, 300, "random vs random, swapped")
+    for k in ("NMI", "NVD", "RI", "ARI", "JI", "VI"):
+        assert abs(r1[k] - r2[k]) <= 1e-13 * max(1.0, abs(r1[k])), k
+    perm = np.random.default_rng(0).permutation(500)[:300].astype(np.int32)
+    r3, _ = run_cmp(cq, ctx, perm[a], 500, a, 300, "relabelled copy")
+    assert r3["ARI"] == 1.0 and r3["NVD"] == 0.0
+
+
+def test_degenerate(cq, ctx):
+    n = 5000
+    one = np.zeros(n, np.int32)
+    sing = np.arange(n, dtype=np.int32)
+    run_cmp(cq, ctx, one, 1, one, 1, "one vs one")
+    run_cmp(cq, ctx, sing, n, sing, n, "singletons vs singletons")
+    run_cmp(cq, ctx, one, 1, sing, n, "one vs singletons")
+    run_cmp(cq, ctx, np.array([0, 1], np.int32), 2, np.array([0, 0], np.int32), 1, "n=2")
+
+
+def test_many_labels(cq, ctx):
+    # label spaces beyond LDS: global node pass, hash group tables, class splitting
+    n = 200000
+    a = random_labels(n, 30000, 3).numpy()
+    b = ((a.astype(np.int64) * 37 + random_labels(n, 3, 4).numpy()) % 90001).astype(np.int32)
+    run_cmp(cq, ctx, a, 30000, b, 90001, "30000 x 90001 labels")
+    big = np.zeros(n, np.int32)
+    run_cmp(cq, ctx, big, 1, (np.arange(n) * 8).astype(np.int32), 8 * n, "one row, 2e5 cells, labels = 8i")
+
+
+def test_errors(cq, ctx):
+    a = torch.zeros(10, dtype=torch.int32, device="cuda")
+    b = torch.zeros(10, dtype=torch.int32, device="cuda")
+    b[3] = 9
+    note("compare label out of range")
+    r, _ = cq.compare_partitions(ctx, a, 1, b, 2, allow=(cq.CQ_E_LABEL_RANGE,))
+    assert r["status"] == cq.CQ_E_LABEL_RANGE
+    with pytest.raises(cq.CQError) as e:
+        cq.compare_partitions(ctx, a[:1], 1, b[:1], 2)
+    assert e.value.status == cq.CQ_E_INVALID_ARG
