@@ -1,0 +1,183 @@
+#!/usr/bin/env python3
+"""Throughput of scoring a partition with the full no-ground-truth metric set
+(Q, Qds with its split penalty, and the six measures of Section II-B3) on an
+LFR-style graph of 10,000,000 nodes (degree exponent 2, average degree 20, maximum
+1,000; community-size exponent 1, sizes 50-5,000; mixing 0.3), on one MI355X.
+
+One step = one synchronous cq_score_partition call over the resident graph and label
+array: every kernel of the scoring path plus the copy of the result to the host.
+Value = stored CSR entries (2|E|) per second, in GEdges/s.
+
+Prints one JSON line.  ``roofline`` reports the dominant kernel (per-stage durations
+are HIP events on the library's stream, recorded inside the timed steps);
+``cpu_baseline`` times the CPU oracle on the same graph on this host.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+METRIC = "GEdges/s scoring full metric set at 10M/100M nodes; served p50/p99 latency"
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_l10m.json")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1507_05492_amd", "csrc", f) for f in ("cq_kernels.hpp", "cq_device.hpp")]
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        h.update(open(p, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def algorithmic_bytes(n: int, nnz: int) -> int:
+    # what the scoring path must move: every stored CSR entry once (4 B) and, per node,
+    # its row offset and its label once (8 B)
+    return 4 * nnz + 8 * n
+
+
+def traffic_for(kernel: str):
+    """Measured HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated),
+    valid only if the kernels are unchanged since the counters were taken."""
+    try:
+        t = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_source_sha") != kernel_source_hash():
+        return None
+    k = t.get("kernels", {}).get(kernel)
+    return None if k is None else k.get("bytes_per_launch")
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="l10m", choices=["l10m", "s100m", "m100k_mu0.3"])
+    ap.add_argument("--seed", type=int, default=21)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU; multi-GPU scoring is not part of this build",
+                          "n_gpus": args.gpus}))
+        return 2
+
+    import numpy as np
+    import torch
+
+    sys.path.insert(0, ROOT)
+    from cqgen import CONFIGS, lfr_graph
+    from paper_1507_05492_amd import cq
+
+    def log(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+    params = CONFIGS[args.workload]
+    t = time.perf_counter()
+    g = lfr_graph(params, args.seed, device="cuda")
+    torch.cuda.synchronize()
+    gen_s = time.perf_counter() - t
+    n, nnz, L = g.n, g.nnz, g.num_labels
+    log(f"graph {args.workload}: n={n} nnz={nnz} K={L} generated in {gen_s:.1f}s")
+
+    ctx = cq.Context(0)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    graph = cq.Graph(ctx, g.row_ptr, g.col_idx)
+    load_ms = (time.perf_counter() - t) * 1e3
+    ws = ctx.workspace(graph.workspace_size(L))
+    labels = g.labels
+
+    for _ in range(args.warmup):
+        r, _, _ = cq.score_partition(graph, labels, L, workspace=ws)
+    cq.cq_context_enable_timing(ctx.handle, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        r, _, _ = cq.score_partition(graph, labels, L, workspace=ws)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    stages = cq.cq_context_stage_times(ctx.handle)
+    cq.cq_context_enable_timing(ctx.handle, False)
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    gedges = nnz / (ms_per_step * 1e-3) / 1e9
+    log(f"{ms_per_step:.3f} ms/step, {gedges:.1f} GEdges/s; stages " +
+        ", ".join(f"{k}={v[0] / v[1]:.3f}ms" for k, v in stages.items()))
+
+    stage_avg = {k: v[0] / v[1] for k, v in stages.items()}
+    dom = max(stage_avg, key=stage_avg.get)
+    kernel_of = {"edge_gather": "k_gather", "group_count": "k_groups", "node_pass": "k_node_priv",
+                 "final_reduce": "k_score_final1", "column_scan": "k_colscan", "scan_order": "k_scan_order"}
+    abytes = algorithmic_bytes(n, nnz)
+    achieved = abytes / (stage_avg[dom] * 1e-3) / 1e9
+    roofline = {
+        "bound": "hbm", "kernel": kernel_of.get(dom, dom), "stage": dom,
+        "avg_ms": round(stage_avg[dom], 4),
+        "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 4),
+        "algorithmic_bytes": abytes,
+        "traffic": traffic_for(kernel_of.get(dom, dom)),
+        "stage_ms": {k: round(v, 4) for k, v in stage_avg.items()},
+    }
+
+    # comparison path on the same node set (ground truth vs 10% reassigned), for context
+    from cqgen import perturb_labels
+    pert = perturb_labels(labels, L, 0.10, 1010)
+    cws = ctx.workspace(max(cq.cq_compare_workspace_size(n, L, L), ws.numel()))
+    for _ in range(2):
+        cr, _ = cq.compare_partitions(ctx, labels, L, pert, L, workspace=cws)
+    torch.cuda.synchronize()
+    tc = time.perf_counter()
+    csteps = max(3, args.steps // 4)
+    for _ in range(csteps):
+        cr, _ = cq.compare_partitions(ctx, labels, L, pert, L, workspace=cws)
+    torch.cuda.synchronize()
+    cmp_ms = (time.perf_counter() - tc) * 1e3 / csteps
+
+    cpu = None
+    check = None
+    if not args.no_cpu_baseline:
+        import oracle
+
+        rp, ci, lab = g.row_ptr.cpu().numpy(), g.col_idx.cpu().numpy(), labels.cpu().numpy()
+        oracle.lib()
+        log("oracle on the host (full graph, one thread)")
+        t = time.perf_counter()
+        o = oracle.score(rp, ci, lab, L, want_pairs=False)
+        cpu_s = time.perf_counter() - t
+        cpu = {"value": round(nnz / cpu_s / 1e9, 5), "unit": "GEdges/s", "cores": 1, "kind": "oracle",
+               "sample": f"whole {args.workload} graph (n={n}, 2|E|={nnz}), one partition, single-threaded C oracle",
+               "seconds": round(cpu_s, 2)}
+        ok = all(int(r[k]) == int(o.result[k]) for k in ("m", "K", "num_pairs", "sum_ein", "sum_eout"))
+        ok = ok and all(abs(r[k] - o.result[k]) <= max(1e-12 * abs(o.result[k]), 1e-13) for k in ("Q", "Qds"))
+        check = "match" if ok else "MISMATCH"
+
+    out = {
+        "metric": METRIC, "value": round(gedges, 2), "unit": "GEdges/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": f"lfr_{args.workload}", "n": n, "nnz": nnz, "m": nnz // 2, "communities": L,
+                   "seed": args.seed, "partition": "ground truth", "avg_degree": round(nnz / n, 2),
+                   "max_degree": g.stats["max_degree"], "mu": params.mu, "epilogue": "f64"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "aux": {"graph_load_ms": round(load_ms, 2), "generate_s": round(gen_s, 2),
+                "compare_ms": round(cmp_ms, 4), "compare_Gnodes_per_s": round(n / (cmp_ms * 1e-3) / 1e9, 3),
+                "oracle_check": check,
+                "Q": r["Q"], "Qds": r["Qds"]},
+    }
+    print(json.dumps(out), flush=True)
+    graph.close()
+    ctx.close()
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

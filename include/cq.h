@@ -72,6 +72,22 @@ void cq_context_destroy(cq_context* ctx);
 /* One-line description of the last failing call on ctx ("" if none). */
 const char* cq_context_last_error(const cq_context* ctx);
 
+/* ---- stage timing (tracing) ------------------------------------------------ */
+
+/* When timing is enabled on a context, every stage of a synchronous call
+ * (cq_score_partition, cq_compare_partitions) is bracketed by HIP events recorded on
+ * the context's stream; after the call synchronises, each stage's elapsed time is
+ * added to a per-stage total.  Stage ids are small integers named by cq_stage_name.
+ * Asynchronous calls are not timed. */
+#define CQ_MAX_STAGES 12
+/* enable != 0 turns timing on, 0 off; both reset the totals. */
+cq_status cq_context_enable_timing(cq_context* ctx, int enable);
+/* Copy up to max_stages per-stage totals (milliseconds) and counts (timed calls
+ * that ran the stage) into the HOST arrays total_ms[] and counts[]. */
+cq_status cq_context_stage_times(const cq_context* ctx, double* total_ms, int64_t* counts, int32_t max_stages);
+/* Name of stage id s (static storage), or "" if s is not a stage id. */
+const char* cq_stage_name(int32_t s);
+
 /* ---- graphs ---------------------------------------------------------------- */
 
 /* Flags for cq_graph_load. */

@@ -94,6 +94,9 @@ def _load():
         "cq_compare_workspace_size": (_SZ, [_I32, _I32, _I32]),
         "cq_compare_partitions": (_I32, [_P, _I32, _P, _I32, _P, _I32, _P, _SZ, ctypes.POINTER(CompareResult), _P]),
         "cq_compare_partitions_async": (_I32, [_P, _I32, _P, _I32, _P, _I32, _P, _SZ, _P, _P]),
+        "cq_context_enable_timing": (_I32, [_P, ctypes.c_int]),
+        "cq_context_stage_times": (_I32, [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_I64), _I32]),
+        "cq_stage_name": (ctypes.c_char_p, [_I32]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -140,6 +143,29 @@ def cq_context_destroy(ctx: int) -> None:
 
 def cq_context_last_error(ctx: int) -> str:
     return _lib.cq_context_last_error(ctx).decode()
+
+
+CQ_MAX_STAGES = 12
+
+
+def cq_context_enable_timing(ctx: int, enable: bool) -> None:
+    st = _lib.cq_context_enable_timing(ctx, 1 if enable else 0)
+    if st != CQ_OK:
+        raise CQError(st)
+
+
+def cq_stage_name(s: int) -> str:
+    return _lib.cq_stage_name(s).decode()
+
+
+def cq_context_stage_times(ctx: int) -> dict:
+    """{stage name: (total ms, count)} for stages that ran while timing was on."""
+    tot = (ctypes.c_double * CQ_MAX_STAGES)()
+    cnt = (_I64 * CQ_MAX_STAGES)()
+    st = _lib.cq_context_stage_times(ctx, tot, cnt, CQ_MAX_STAGES)
+    if st != CQ_OK:
+        raise CQError(st)
+    return {cq_stage_name(i): (tot[i], cnt[i]) for i in range(CQ_MAX_STAGES) if cnt[i] > 0}
 
 
 def _check(ctx: int, st: int, allow=(CQ_OK,)) -> int:

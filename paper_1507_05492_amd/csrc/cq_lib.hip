@@ -20,6 +20,12 @@ struct cq_context {
   void* pinned = nullptr;  // host staging for result structs (hipHostMalloc)
   u32* dscratch = nullptr; // 2 words used by graph checks
   char err[512] = {0};
+  // stage timing
+  bool timing = false;
+  hipEvent_t ev[2 * CQ_MAX_STAGES] = {};
+  bool recorded[CQ_MAX_STAGES] = {};
+  double total_ms[CQ_MAX_STAGES] = {};
+  int64_t counts[CQ_MAX_STAGES] = {};
 };
 
 struct cq_graph {
@@ -42,6 +48,39 @@ constexpr int64_t PRIV_MAX = 16384;    // labels handled by LDS-private node his
 constexpr int64_t DIRECT_MAX = 16384;  // labels handled by direct-indexed group tables
 constexpr u32 HASH_WORDS = 16384;      // LDS words of the group hash table (8192 slots)
 constexpr size_t ALIGN = 256;
+
+enum Stage { ST_SETUP = 0, ST_NODE, ST_COLSCAN, ST_ORDER, ST_GATHER, ST_GROUPS, ST_FINAL, ST_HIST_B, ST_SCATTER, ST_COUNT };
+const char* const kStageNames[ST_COUNT] = {"setup", "node_pass", "column_scan", "scan_order", "edge_gather",
+                                           "group_count", "final_reduce", "label_hist_b", "node_scatter"};
+static_assert(ST_COUNT <= CQ_MAX_STAGES, "stage ids");
+
+// Brackets one stage with events when timing is on (synchronous calls only).
+struct StageMark {
+  cq_context* ctx;
+  int st;
+  bool on;
+  StageMark(cq_context* c, int s, bool timed) : ctx(c), st(s), on(timed && c->timing) {
+    if (on) (void)hipEventRecord(ctx->ev[2 * st], ctx->stream);
+  }
+  ~StageMark() {
+    if (on) {
+      (void)hipEventRecord(ctx->ev[2 * st + 1], ctx->stream);
+      ctx->recorded[st] = true;
+    }
+  }
+};
+
+void collect_stage_times(cq_context* ctx) {
+  for (int i = 0; i < ST_COUNT; ++i) {
+    if (!ctx->recorded[i]) continue;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, ctx->ev[2 * i], ctx->ev[2 * i + 1]) == hipSuccess) {
+      ctx->total_ms[i] += ms;
+      ctx->counts[i] += 1;
+    }
+    ctx->recorded[i] = false;
+  }
+}
 
 cq_status fail(cq_context* ctx, cq_status s, const char* fmt, ...) {
   if (ctx) {
@@ -173,7 +212,7 @@ cq_status map_flags(cq_context* ctx, u32 flags) {
 }
 
 cq_status score_enqueue(cq_context* ctx, const cq_graph* g, const int32_t* labels, int32_t L, void* ws, size_t ws_bytes,
-                        ScoreResultDev* d_out, const cq_per_community* per_comm, const cq_pair_table* pairs) {
+                        ScoreResultDev* d_out, const cq_per_community* per_comm, const cq_pair_table* pairs, bool timed) {
   if (!ctx) return CQ_E_INVALID_ARG;
   ctx->err[0] = 0;
   if (!g || !labels || !d_out) return fail(ctx, CQ_E_INVALID_ARG, "null graph, labels or output");
@@ -198,25 +237,46 @@ cq_status score_enqueue(cq_context* ctx, const cq_graph* g, const int32_t* label
   u32* CB = at<u32>(ws, lay.CB);
   ScorePart* parts = at<ScorePart>(ws, lay.parts);
 
-  fill(reinterpret_cast<u32*>(ctl), sizeof(Ctl) / 4, 0, s);
   const u32* PM = nullptr;
+  {
+    StageMark mk(ctx, ST_SETUP, timed);
+    fill(reinterpret_cast<u32*>(ctl), sizeof(Ctl) / 4, 0, s);
+    if (!lay.priv) fill(at<u32>(ws, lay.SZ), 2 * (size_t)L, 0, s);
+  }
   if (lay.priv) {
     u32* HN = at<u32>(ws, lay.HN);
     u32* HD = at<u32>(ws, lay.HD);
-    k_node_priv<true><<<lay.W, 1024, 2 * (size_t)L * 4, s>>>((int)n, labels, g->rp, L, lay.chunk, HN, HD, loc, ctl);
-    k_colscan<true, true><<<grid_for(L, 256, 1u << 30), 256, 0, s>>>(lay.W, L, HN, HD, N, D);
+    {
+      StageMark mk(ctx, ST_NODE, timed);
+      k_node_priv<true><<<lay.W, 1024, 2 * (size_t)L * 4, s>>>((int)n, labels, g->rp, L, lay.chunk, HN, HD, loc, ctl);
+    }
+    {
+      StageMark mk(ctx, ST_COLSCAN, timed);
+      k_colscan<true, true><<<grid_for(L, 256, 1u << 30), 256, 0, s>>>(lay.W, L, HN, HD, N, D);
+    }
     PM = HD;
   } else {
     unsigned long long* SZ = at<unsigned long long>(ws, lay.SZ);
-    fill(reinterpret_cast<u32*>(SZ), 2 * (size_t)L, 0, s);
-    k_node_global<true><<<grid_for(n, 256, 8192), 256, 0, s>>>((int)n, labels, g->rp, L, SZ, loc, ctl);
-    k_unpack<<<grid_for(L, 256, 4096), 256, 0, s>>>(L, SZ, N, D);
+    {
+      StageMark mk(ctx, ST_NODE, timed);
+      k_node_global<true><<<grid_for(n, 256, 8192), 256, 0, s>>>((int)n, labels, g->rp, L, SZ, loc, ctl);
+    }
+    {
+      StageMark mk(ctx, ST_COLSCAN, timed);
+      k_unpack<<<grid_for(L, 256, 4096), 256, 0, s>>>(L, SZ, N, D);
+    }
   }
-  k_scan_order<<<1, 1024, 0, s>>>(L, N, D, start, order, ctl);
-  if (lay.priv)
-    k_gather<true><<<grid_for(n, GROWS, 1u << 30), GROWS, 0, s>>>((int)n, g->rp, g->col, labels, L, lay.chunk, PM, start, loc, CB);
-  else
-    k_gather<false><<<grid_for(n, GROWS, 1u << 30), GROWS, 0, s>>>((int)n, g->rp, g->col, labels, L, lay.chunk, PM, start, loc, CB);
+  {
+    StageMark mk(ctx, ST_ORDER, timed);
+    k_scan_order<<<1, 1024, 0, s>>>(L, N, D, start, order, ctl);
+  }
+  {
+    StageMark mk(ctx, ST_GATHER, timed);
+    if (lay.priv)
+      k_gather<true><<<grid_for(n, GROWS, 1u << 30), GROWS, 0, s>>>((int)n, g->rp, g->col, labels, L, lay.chunk, PM, start, loc, CB);
+    else
+      k_gather<false><<<grid_for(n, GROWS, 1u << 30), GROWS, 0, s>>>((int)n, g->rp, g->col, labels, L, lay.chunk, PM, start, loc, CB);
+  }
 
   ScoreVis vis;
   vis.N = N;
@@ -231,18 +291,23 @@ cq_status score_enqueue(cq_context* ctx, const cq_graph* g, const int32_t* label
   vis.ctl = ctl;
   const u32 lds_words = L <= DIRECT_MAX ? std::max<u32>((u32)L, 128u) : HASH_WORDS;
   const size_t lds = (size_t)lds_words * 4;
-  k_groups<ScoreVis><<<group_grid<ScoreVis>(ctx, lds), GBLOCK, lds, s>>>(CB, start, D, order, ctl, (u32)L, lds_words, vis);
-
+  {
+    StageMark mk(ctx, ST_GROUPS, timed);
+    k_groups<ScoreVis><<<group_grid<ScoreVis>(ctx, lds), GBLOCK, lds, s>>>(CB, start, D, order, ctl, (u32)L, lds_words, vis);
+  }
   PerComm pc;
   std::memset(&pc, 0, sizeof(pc));
   if (per_comm) std::memcpy(&pc, per_comm, sizeof(pc));
-  k_score_final1<<<lay.G, FBLOCK, 0, s>>>(L, N, D, I, NP, PEN, (double)nnz, pc, parts);
-  k_score_final2<<<1, 64, 0, s>>>(lay.G, parts, n, nnz, vis.ecap, ctl, d_out);
+  {
+    StageMark mk(ctx, ST_FINAL, timed);
+    k_score_final1<<<lay.G, FBLOCK, 0, s>>>(L, N, D, I, NP, PEN, (double)nnz, pc, parts);
+    k_score_final2<<<1, 64, 0, s>>>(lay.G, parts, n, nnz, vis.ecap, ctl, d_out);
+  }
   return launch_status(ctx, "score launch");
 }
 
 cq_status compare_enqueue(cq_context* ctx, int32_t n, const int32_t* la, int32_t La, const int32_t* lb, int32_t Lb, void* ws,
-                          size_t ws_bytes, CmpResultDev* d_out, const cq_cell_table* cells) {
+                          size_t ws_bytes, CmpResultDev* d_out, const cq_cell_table* cells, bool timed) {
   if (!ctx) return CQ_E_INVALID_ARG;
   ctx->err[0] = 0;
   if (!la || !lb || !d_out) return fail(ctx, CQ_E_INVALID_ARG, "null labels or output");
@@ -262,33 +327,57 @@ cq_status compare_enqueue(cq_context* ctx, int32_t n, const int32_t* la, int32_t
   u32* COLMAX = at<u32>(ws, lay.COLMAX);
   u32* loc = at<u32>(ws, lay.loc);
   u32* CB = at<u32>(ws, lay.CB);
-  fill(reinterpret_cast<u32*>(ctl), sizeof(Ctl) / 4, 0, s);
-  fill(COLMAX, (size_t)Lb, 0, s);
   const u32* PM = nullptr;
+  {
+    StageMark mk(ctx, ST_SETUP, timed);
+    fill(reinterpret_cast<u32*>(ctl), sizeof(Ctl) / 4, 0, s);
+    fill(COLMAX, (size_t)Lb, 0, s);
+    if (!lay.privA) fill(at<u32>(ws, lay.SZ), 2 * (size_t)La, 0, s);
+    if (!lay.privB) fill(B, (size_t)Lb, 0, s);
+  }
   if (lay.privA) {
     u32* HN = at<u32>(ws, lay.HN);
-    k_node_priv<false><<<lay.W, 1024, (size_t)La * 4, s>>>(n, la, nullptr, La, lay.chunk, HN, nullptr, loc, ctl);
-    k_colscan<false, true><<<grid_for(La, 256, 1u << 30), 256, 0, s>>>(lay.W, La, HN, HN, A, nullptr);
+    {
+      StageMark mk(ctx, ST_NODE, timed);
+      k_node_priv<false><<<lay.W, 1024, (size_t)La * 4, s>>>(n, la, nullptr, La, lay.chunk, HN, nullptr, loc, ctl);
+    }
+    {
+      StageMark mk(ctx, ST_COLSCAN, timed);
+      k_colscan<false, true><<<grid_for(La, 256, 1u << 30), 256, 0, s>>>(lay.W, La, HN, HN, A, nullptr);
+    }
     PM = HN;
   } else {
     unsigned long long* SZ = at<unsigned long long>(ws, lay.SZ);
-    fill(reinterpret_cast<u32*>(SZ), 2 * (size_t)La, 0, s);
-    k_node_global<false><<<grid_for(n, 256, 8192), 256, 0, s>>>(n, la, nullptr, La, SZ, loc, ctl);
-    k_unpack<<<grid_for(La, 256, 4096), 256, 0, s>>>(La, SZ, A, nullptr);
+    {
+      StageMark mk(ctx, ST_NODE, timed);
+      k_node_global<false><<<grid_for(n, 256, 8192), 256, 0, s>>>(n, la, nullptr, La, SZ, loc, ctl);
+    }
+    {
+      StageMark mk(ctx, ST_COLSCAN, timed);
+      k_unpack<<<grid_for(La, 256, 4096), 256, 0, s>>>(La, SZ, A, nullptr);
+    }
   }
-  if (lay.privB) {
-    u32* HB = at<u32>(ws, lay.HB);
-    k_hist_priv<<<lay.Wb, 1024, (size_t)Lb * 4, s>>>(n, lb, Lb, HB, ctl);
-    k_colscan<false, false><<<grid_for(Lb, 256, 1u << 30), 256, 0, s>>>(lay.Wb, Lb, HB, HB, B, nullptr);
-  } else {
-    fill(B, (size_t)Lb, 0, s);
-    k_hist_global<<<grid_for(n, 256, 8192), 256, 0, s>>>(n, lb, Lb, B, ctl);
+  {
+    StageMark mk(ctx, ST_HIST_B, timed);
+    if (lay.privB) {
+      u32* HB = at<u32>(ws, lay.HB);
+      k_hist_priv<<<lay.Wb, 1024, (size_t)Lb * 4, s>>>(n, lb, Lb, HB, ctl);
+      k_colscan<false, false><<<grid_for(Lb, 256, 1u << 30), 256, 0, s>>>(lay.Wb, Lb, HB, HB, B, nullptr);
+    } else {
+      k_hist_global<<<grid_for(n, 256, 8192), 256, 0, s>>>(n, lb, Lb, B, ctl);
+    }
   }
-  k_scan_order<<<1, 1024, 0, s>>>(La, A, A, start, order, ctl);
-  if (lay.privA)
-    k_cmp_scatter<true><<<grid_for(n, 256, 8192), 256, 0, s>>>(n, la, lb, La, Lb, lay.chunk, PM, start, loc, CB);
-  else
-    k_cmp_scatter<false><<<grid_for(n, 256, 8192), 256, 0, s>>>(n, la, lb, La, Lb, lay.chunk, PM, start, loc, CB);
+  {
+    StageMark mk(ctx, ST_ORDER, timed);
+    k_scan_order<<<1, 1024, 0, s>>>(La, A, A, start, order, ctl);
+  }
+  {
+    StageMark mk(ctx, ST_SCATTER, timed);
+    if (lay.privA)
+      k_cmp_scatter<true><<<grid_for(n, 256, 8192), 256, 0, s>>>(n, la, lb, La, Lb, lay.chunk, PM, start, loc, CB);
+    else
+      k_cmp_scatter<false><<<grid_for(n, 256, 8192), 256, 0, s>>>(n, la, lb, La, Lb, lay.chunk, PM, start, loc, CB);
+  }
 
   CmpVis vis;
   vis.A = A;
@@ -308,11 +397,17 @@ cq_status compare_enqueue(cq_context* ctx, int32_t n, const int32_t* la, int32_t
   vis.ctl = ctl;
   const u32 lds_words = Lb <= DIRECT_MAX ? std::max<u32>((u32)Lb, 128u) : HASH_WORDS;
   const size_t lds = (size_t)lds_words * 4;
-  k_groups<CmpVis><<<group_grid<CmpVis>(ctx, lds), GBLOCK, lds, s>>>(CB, start, A, order, ctl, (u32)Lb, lds_words, vis);
+  {
+    StageMark mk(ctx, ST_GROUPS, timed);
+    k_groups<CmpVis><<<group_grid<CmpVis>(ctx, lds), GBLOCK, lds, s>>>(CB, start, A, order, ctl, (u32)Lb, lds_words, vis);
+  }
   CmpPart* parts = at<CmpPart>(ws, lay.parts);
-  k_cmp_final1<<<lay.Ga + lay.Gb, FBLOCK, 0, s>>>(La, Lb, lay.Ga, A, B, COLMAX, vis.RA11, vis.RMAX, vis.RF, vis.RMI, vis.RVI,
-                                                 (double)n, parts);
-  k_cmp_final2<<<1, 64, 0, s>>>(lay.Ga + lay.Gb, parts, n, vis.ecap, ctl, d_out);
+  {
+    StageMark mk(ctx, ST_FINAL, timed);
+    k_cmp_final1<<<lay.Ga + lay.Gb, FBLOCK, 0, s>>>(La, Lb, lay.Ga, A, B, COLMAX, vis.RA11, vis.RMAX, vis.RF, vis.RMI,
+                                                   vis.RVI, (double)n, parts);
+    k_cmp_final2<<<1, 64, 0, s>>>(lay.Ga + lay.Gb, parts, n, vis.ecap, ctl, d_out);
+  }
   return launch_status(ctx, "compare launch");
 }
 
@@ -322,6 +417,7 @@ cq_status fetch(cq_context* ctx, const void* d_res, R* h_out) {
   if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
   if (e != hipSuccess) return fail(ctx, CQ_E_DEVICE, "result copy: %s", hipGetErrorString(e));
   std::memcpy(h_out, ctx->pinned, sizeof(R));
+  if (ctx->timing) collect_stage_times(ctx);
   return CQ_OK;
 }
 
@@ -368,6 +464,12 @@ cq_status cq_context_create(int device, void* hip_stream, cq_context** out) {
     delete ctx;
     return CQ_E_DEVICE;
   }
+  for (int i = 0; i < 2 * CQ_MAX_STAGES; ++i) {
+    if (hipEventCreate(&ctx->ev[i]) != hipSuccess) {
+      cq_context_destroy(ctx);
+      return CQ_E_DEVICE;
+    }
+  }
   set_big_lds(reinterpret_cast<const void*>(k_node_priv<true>), 2 * PRIV_MAX * 4);
   set_big_lds(reinterpret_cast<const void*>(k_node_priv<false>), PRIV_MAX * 4);
   set_big_lds(reinterpret_cast<const void*>(k_hist_priv), PRIV_MAX * 4);
@@ -387,8 +489,32 @@ void cq_context_destroy(cq_context* ctx) {
   if (!ctx) return;
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
   if (ctx->dscratch) (void)hipFree(ctx->dscratch);
+  for (int i = 0; i < 2 * CQ_MAX_STAGES; ++i)
+    if (ctx->ev[i]) (void)hipEventDestroy(ctx->ev[i]);
   delete ctx;
 }
+
+cq_status cq_context_enable_timing(cq_context* ctx, int enable) {
+  if (!ctx) return CQ_E_INVALID_ARG;
+  ctx->timing = enable != 0;
+  for (int i = 0; i < CQ_MAX_STAGES; ++i) {
+    ctx->total_ms[i] = 0.0;
+    ctx->counts[i] = 0;
+    ctx->recorded[i] = false;
+  }
+  return CQ_OK;
+}
+
+cq_status cq_context_stage_times(const cq_context* ctx, double* total_ms, int64_t* counts, int32_t max_stages) {
+  if (!ctx || !total_ms || !counts || max_stages < 0) return CQ_E_INVALID_ARG;
+  for (int i = 0; i < max_stages && i < CQ_MAX_STAGES; ++i) {
+    total_ms[i] = ctx->total_ms[i];
+    counts[i] = ctx->counts[i];
+  }
+  return CQ_OK;
+}
+
+const char* cq_stage_name(int32_t s) { return (s >= 0 && s < ST_COUNT) ? kStageNames[s] : ""; }
 
 const char* cq_context_last_error(const cq_context* ctx) { return ctx ? ctx->err : "null context"; }
 
@@ -466,7 +592,8 @@ size_t cq_compare_workspace_size(int32_t n, int32_t num_labels_a, int32_t num_la
 cq_status cq_score_partition_async(cq_context* ctx, const cq_graph* g, const int32_t* d_labels, int32_t num_labels, void* d_ws,
                                    size_t ws_bytes, cq_score_result* d_out, const cq_per_community* per_comm,
                                    const cq_pair_table* pairs) {
-  return score_enqueue(ctx, g, d_labels, num_labels, d_ws, ws_bytes, reinterpret_cast<ScoreResultDev*>(d_out), per_comm, pairs);
+  return score_enqueue(ctx, g, d_labels, num_labels, d_ws, ws_bytes, reinterpret_cast<ScoreResultDev*>(d_out), per_comm, pairs,
+                       false);
 }
 
 cq_status cq_score_partition(cq_context* ctx, const cq_graph* g, const int32_t* d_labels, int32_t num_labels, void* d_ws,
@@ -478,7 +605,7 @@ cq_status cq_score_partition(cq_context* ctx, const cq_graph* g, const int32_t* 
   const ScoreLayout lay = score_layout(g->n, g->nnz, std::max(num_labels, 1));
   ScoreResultDev* d_res = (d_ws && ws_bytes >= lay.total) ? at<ScoreResultDev>(d_ws, lay.res) : nullptr;
   cq_status st = score_enqueue(ctx, g, d_labels, num_labels, d_ws, ws_bytes, d_res ? d_res : reinterpret_cast<ScoreResultDev*>(1),
-                               per_comm, pairs);
+                               per_comm, pairs, true);
   if (st != CQ_OK) return st;
   st = fetch(ctx, d_res, h_out);
   if (st != CQ_OK) return st;
@@ -489,7 +616,7 @@ cq_status cq_compare_partitions_async(cq_context* ctx, int32_t n, const int32_t*
                                       const int32_t* d_labels_b, int32_t num_labels_b, void* d_ws, size_t ws_bytes,
                                       cq_compare_result* d_out, const cq_cell_table* cells) {
   return compare_enqueue(ctx, n, d_labels_a, num_labels_a, d_labels_b, num_labels_b, d_ws, ws_bytes,
-                         reinterpret_cast<CmpResultDev*>(d_out), cells);
+                         reinterpret_cast<CmpResultDev*>(d_out), cells, false);
 }
 
 cq_status cq_compare_partitions(cq_context* ctx, int32_t n, const int32_t* d_labels_a, int32_t num_labels_a,
@@ -500,7 +627,7 @@ cq_status cq_compare_partitions(cq_context* ctx, int32_t n, const int32_t* d_lab
   const CmpLayout lay = cmp_layout(std::max(n, 2), std::max(num_labels_a, 1), std::max(num_labels_b, 1));
   CmpResultDev* d_res = (d_ws && ws_bytes >= lay.total) ? at<CmpResultDev>(d_ws, lay.res) : nullptr;
   cq_status st = compare_enqueue(ctx, n, d_labels_a, num_labels_a, d_labels_b, num_labels_b, d_ws, ws_bytes,
-                                 d_res ? d_res : reinterpret_cast<CmpResultDev*>(1), cells);
+                                 d_res ? d_res : reinterpret_cast<CmpResultDev*>(1), cells, true);
   if (st != CQ_OK) return st;
   st = fetch(ctx, d_res, h_out);
   if (st != CQ_OK) return st;
