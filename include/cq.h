@@ -92,6 +92,7 @@ const char* cq_stage_name(int32_t s);
 
 /* Flags for cq_graph_load. */
 #define CQ_VALIDATE_GRAPH 1u  /* also check symmetry (rows must be sorted), no self-loops, no repeated entries */
+#define CQ_GRAPH_REORDER 2u   /* store the graph in a locality order (see cq_graph_load) */
 
 typedef struct {
   int64_t n;           /* |V| */
@@ -99,6 +100,8 @@ typedef struct {
   int64_t m;           /* |E| */
   int64_t max_degree;
   uint32_t validated;  /* CQ_VALIDATE_GRAPH if the full check ran and passed */
+  uint32_t reordered;  /* CQ_GRAPH_REORDER if the graph is stored in a locality order */
+  int64_t owned_bytes; /* device memory the graph handle allocated (0 without CQ_GRAPH_REORDER) */
 } cq_graph_stats;
 
 /*
@@ -112,6 +115,12 @@ typedef struct {
  * cq_graph_release.  The structural checks above always run (one pass over the
  * arrays, synchronous); CQ_VALIDATE_GRAPH adds the symmetry / loop / repeat checks.
  * Returns CQ_E_GRAPH_FORMAT if a check fails.
+ * CQ_GRAPH_REORDER: the handle builds and owns a renumbered copy of the graph
+ * (4(n+1) + 4 nnz + 4n bytes of device memory, allocated here and freed by
+ * cq_graph_release) in which nodes are grouped by a few sweeps of label propagation,
+ * so that the neighbours of a row mostly have nearby ids.  Labels passed to scoring
+ * calls keep the caller's node numbering; every result is identical with and without
+ * the flag.  The borrowed arrays are not read after the load returns.
  */
 cq_status cq_graph_load(cq_context* ctx, int32_t n, int64_t nnz, const int32_t* d_row_ptr,
                         const int32_t* d_col_idx, uint32_t flags, cq_graph** out);

@@ -57,6 +57,10 @@ __device__ __forceinline__ u64 wave_sum_u64(u64 x) {
   for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
   return x;
 }
+__device__ __forceinline__ u64 wave_max_u64(u64 x) {
+  for (int o = 32; o > 0; o >>= 1) { u64 y = __shfl_xor(x, o, 64); x = y > x ? y : x; }
+  return x;
+}
 __device__ __forceinline__ u32 wave_max_u32(u32 x) {
   for (int o = 32; o > 0; o >>= 1) { u32 y = __shfl_xor(x, o, 64); x = y > x ? y : x; }
   return x;

@@ -69,16 +69,190 @@ __global__ void k_check_symmetric(int n, const int32_t* __restrict__ rp, const i
 }
 
 // ---------------------------------------------------------------------------
+// Exclusive scan of a u32 array of any length (three launches): tiles of
+// SCAN_TILE items are scanned in place, the tile totals are scanned by one block,
+// and the tile offsets are added back.  out[n] receives the total.
+constexpr int SCAN_THREADS = 1024;
+constexpr int SCAN_ITEMS = 4;
+constexpr int SCAN_TILE = SCAN_THREADS * SCAN_ITEMS;
+
+__device__ u32 block_excl_scan_1024(u32 x, u32* s_w, u32* total) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  u32 incl = wave_incl_scan(x);
+  if (lane == 63) s_w[wv] = incl;
+  __syncthreads();
+  u32 before = 0, tot = 0;
+  for (int i = 0; i < SCAN_THREADS / 64; ++i) {
+    u32 t = s_w[i];
+    if (i < wv) before += t;
+    tot += t;
+  }
+  __syncthreads();
+  *total = tot;
+  return before + incl - x;
+}
+
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan_tiles(long long n, const u32* __restrict__ in, u32* __restrict__ out,
+                                                             u32* __restrict__ tile_sums) {
+  __shared__ u32 s_w[SCAN_THREADS / 64];
+  const long long base = (long long)blockIdx.x * SCAN_TILE + (long long)threadIdx.x * SCAN_ITEMS;
+  u32 v[SCAN_ITEMS], sum = 0;
+#pragma unroll
+  for (int k = 0; k < SCAN_ITEMS; ++k) {
+    v[k] = (base + k < n) ? in[base + k] : 0u;
+    sum += v[k];
+  }
+  u32 total;
+  u32 run = block_excl_scan_1024(sum, s_w, &total);
+#pragma unroll
+  for (int k = 0; k < SCAN_ITEMS; ++k) {
+    if (base + k < n) out[base + k] = run;
+    run += v[k];
+  }
+  if (threadIdx.x == 0) tile_sums[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan_tops(int T, u32* __restrict__ tile_sums, long long n, u32* __restrict__ out) {
+  __shared__ u32 s_w[SCAN_THREADS / 64];
+  __shared__ u32 s_carry;
+  if (threadIdx.x == 0) s_carry = 0;
+  __syncthreads();
+  for (int b = 0; b < T; b += SCAN_THREADS) {
+    int i = b + threadIdx.x;
+    u32 x = i < T ? tile_sums[i] : 0u;
+    u32 total;
+    u32 ex = block_excl_scan_1024(x, s_w, &total);
+    u32 carry = s_carry;
+    if (i < T) tile_sums[i] = carry + ex;
+    __syncthreads();
+    if (threadIdx.x == 0) s_carry = carry + total;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[n] = s_carry;
+}
+
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan_add(long long n, u32* __restrict__ out, const u32* __restrict__ tile_sums) {
+  const long long base = (long long)blockIdx.x * SCAN_TILE + (long long)threadIdx.x * SCAN_ITEMS;
+  const u32 off = tile_sums[blockIdx.x];
+#pragma unroll
+  for (int k = 0; k < SCAN_ITEMS; ++k)
+    if (base + k < n) out[base + k] += off;
+}
+
+// ---------------------------------------------------------------------------
+// Locality order for a graph (load time, graph only).  A few sweeps of label
+// propagation group nodes into clusters; nodes are then renumbered cluster by
+// cluster, so that most neighbours of a row have nearby ids.  The order only moves
+// data: every count the library reports is the same in any node order.
+constexpr u32 HMUL = 0x9E3779B1u;  // odd, so x -> x*HMUL is a bijection on 32-bit words
+constexpr u32 HINV = 0x0E8B2F51u;  // HMUL * HINV == 1 (mod 2^32)
+constexpr int LP_CAP = 256;         // neighbours looked at per row
+
+__global__ void k_iota(int n, int32_t* __restrict__ a) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < (size_t)n; i += (size_t)gridDim.x * blockDim.x) a[i] = (int32_t)i;
+}
+
+// One sweep: every node takes the label that occurs most often among (up to LP_CAP of)
+// its neighbours; ties go to the label with the smallest hash.  One wave per row.
+__global__ __launch_bounds__(256) void k_lp(int n, const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
+                                            const int32_t* __restrict__ lin, int32_t* __restrict__ lout) {
+  const int lane = threadIdx.x & 63;
+  const size_t wave = ((size_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const size_t nwaves = ((size_t)gridDim.x * blockDim.x) >> 6;
+  for (size_t u = wave; u < (size_t)n; u += nwaves) {
+    const int a = rp[u];
+    const int deg = min(rp[u + 1] - a, LP_CAP);
+    if (deg == 0) {
+      if (lane == 0) lout[u] = lin[u];
+      continue;
+    }
+    int x[LP_CAP / 64];
+    u32 cnt[LP_CAP / 64];
+#pragma unroll
+    for (int q = 0; q < LP_CAP / 64; ++q) {
+      const int k = lane + 64 * q;
+      x[q] = k < deg ? lin[col[a + k]] : -1;
+      cnt[q] = 0;
+    }
+    const int chunks = (deg + 63) >> 6;
+    for (int q2 = 0; q2 < chunks; ++q2) {
+      const int lim = min(64, deg - 64 * q2);
+      int xv = x[0];
+#pragma unroll
+      for (int q = 1; q < LP_CAP / 64; ++q) if (q == q2) xv = x[q];
+      for (int s2 = 0; s2 < lim; ++s2) {
+        const int y = __shfl(xv, s2, 64);
+#pragma unroll
+        for (int q = 0; q < LP_CAP / 64; ++q) cnt[q] += (x[q] == y) ? 1u : 0u;
+      }
+    }
+    u64 best = 0;
+#pragma unroll
+    for (int q = 0; q < LP_CAP / 64; ++q) {
+      if (x[q] >= 0) {
+        const u64 key = ((u64)cnt[q] << 32) | (u64)(~((u32)x[q] * HMUL));
+        best = key > best ? key : best;
+      }
+    }
+    best = wave_max_u64(best);
+    if (lane == 0) lout[u] = (int32_t)((~(u32)best) * HINV);
+  }
+}
+
+__global__ void k_count_labels(int n, const int32_t* __restrict__ lab, u32* __restrict__ cnt) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < (size_t)n; i += (size_t)gridDim.x * blockDim.x)
+    atomicAdd(&cnt[lab[i]], 1u);
+}
+
+// new id of node u = start[cluster] + arrival order inside the cluster
+__global__ void k_place(int n, const int32_t* __restrict__ lab, const u32* __restrict__ start, u32* __restrict__ cursor,
+                        int32_t* __restrict__ newid, int32_t* __restrict__ old) {
+  for (size_t u = (size_t)blockIdx.x * blockDim.x + threadIdx.x; u < (size_t)n; u += (size_t)gridDim.x * blockDim.x) {
+    const int c = lab[u];
+    const u32 p = start[c] + atomicAdd(&cursor[c], 1u);
+    newid[u] = (int32_t)p;
+    old[p] = (int32_t)u;
+  }
+}
+
+__global__ void k_new_degree(int n, const int32_t* __restrict__ rp, const int32_t* __restrict__ old, u32* __restrict__ deg) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < (size_t)n; i += (size_t)gridDim.x * blockDim.x) {
+    const int u = old[i];
+    deg[i] = (u32)(rp[u + 1] - rp[u]);
+  }
+}
+
+// row i of the renumbered graph = row old[i] of the input, with neighbour ids renumbered
+__global__ __launch_bounds__(256) void k_relabel_rows(int n, const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
+                                                      const int32_t* __restrict__ old, const int32_t* __restrict__ newid,
+                                                      const int32_t* __restrict__ rp2, int32_t* __restrict__ col2) {
+  const int lane = threadIdx.x & 63;
+  const size_t wave = ((size_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const size_t nwaves = ((size_t)gridDim.x * blockDim.x) >> 6;
+  for (size_t i = wave; i < (size_t)n; i += nwaves) {
+    const int u = old[i];
+    const int a = rp[u], deg = rp[u + 1] - a, b = rp2[i];
+    for (int k = lane; k < deg; k += 64) col2[b + k] = newid[col[a + k]];
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Node pass, LDS-private histograms (num_labels small enough for LDS).
 // Workgroup w owns nodes [w*chunk, (w+1)*chunk).  It counts, per label, the nodes
 // (HN) and the weights (HD: degree when WEIGHTED, else 1) of its nodes, and gives
 // each node the running weight offset of its label inside the workgroup (loc).
 // Rows w of HN/HD are later prefix-summed over w, which turns loc into a position
 // inside the label's segment.
-template <bool WEIGHTED>
-__global__ __launch_bounds__(1024) void k_node_priv(int n, const int32_t* __restrict__ labels, const int32_t* __restrict__ rp,
-                                                    int L, int chunk, u32* __restrict__ HN, u32* __restrict__ HD,
-                                                    u32* __restrict__ loc, Ctl* __restrict__ ctl) {
+template <class LT>
+struct LabelT {
+  static constexpr LT SENTINEL = (LT)~(LT)0;  // "no label" marker in staged label arrays
+};
+
+template <bool WEIGHTED, class LT>
+__global__ __launch_bounds__(1024) void k_node_priv(int n, const int32_t* __restrict__ labels, const int32_t* __restrict__ perm,
+                                                    const int32_t* __restrict__ rp, int L, int chunk, u32* __restrict__ HN,
+                                                    u32* __restrict__ HD, u32* __restrict__ loc, LT* __restrict__ labx,
+                                                    Ctl* __restrict__ ctl) {
   extern __shared__ u32 sh[];
   u32* hn = sh;
   u32* hd = WEIGHTED ? sh + L : sh;
@@ -91,8 +265,13 @@ __global__ __launch_bounds__(1024) void k_node_priv(int n, const int32_t* __rest
   long long u1 = min((long long)n, u0 + chunk);
   u32 bad = 0;
   for (long long u = u0 + threadIdx.x; u < u1; u += blockDim.x) {
-    int c = labels[u];
-    if ((u32)c >= (u32)L) { bad = 1; loc[u] = SENT; continue; }
+    int c = labels[perm ? perm[u] : u];
+    if ((u32)c >= (u32)L) {
+      bad = 1;
+      loc[u] = SENT;
+      if (labx) labx[u] = LabelT<LT>::SENTINEL;
+      continue;
+    }
     u32 old;
     if (WEIGHTED) {
       u32 w = (u32)(rp[u + 1] - rp[u]);
@@ -102,6 +281,7 @@ __global__ __launch_bounds__(1024) void k_node_priv(int n, const int32_t* __rest
       old = atomicAdd(&hn[c], 1u);
     }
     loc[u] = old;
+    if (labx) labx[u] = (LT)c;
   }
   if (bad) s_bad = 1;
   __syncthreads();
@@ -115,17 +295,23 @@ __global__ __launch_bounds__(1024) void k_node_priv(int n, const int32_t* __rest
 
 // Node pass with global atomics (too many labels for LDS).  SZ[c] packs
 // (count << 32) | weight sum; the returned old value gives the node's offset.
-template <bool WEIGHTED>
-__global__ __launch_bounds__(256) void k_node_global(int n, const int32_t* __restrict__ labels, const int32_t* __restrict__ rp,
-                                                     int L, unsigned long long* __restrict__ SZ, u32* __restrict__ loc,
-                                                     Ctl* __restrict__ ctl) {
+template <bool WEIGHTED, class LT>
+__global__ __launch_bounds__(256) void k_node_global(int n, const int32_t* __restrict__ labels, const int32_t* __restrict__ perm,
+                                                     const int32_t* __restrict__ rp, int L, unsigned long long* __restrict__ SZ,
+                                                     u32* __restrict__ loc, LT* __restrict__ labx, Ctl* __restrict__ ctl) {
   u32 bad = 0;
   for (size_t u = (size_t)blockIdx.x * blockDim.x + threadIdx.x; u < (size_t)n; u += (size_t)gridDim.x * blockDim.x) {
-    int c = labels[u];
-    if ((u32)c >= (u32)L) { bad = 1; loc[u] = SENT; continue; }
+    int c = labels[perm ? perm[u] : u];
+    if ((u32)c >= (u32)L) {
+      bad = 1;
+      loc[u] = SENT;
+      if (labx) labx[u] = LabelT<LT>::SENTINEL;
+      continue;
+    }
     u32 w = WEIGHTED ? (u32)(rp[u + 1] - rp[u]) : 1u;
     unsigned long long old = atomicAdd(&SZ[c], (1ull << 32) | (unsigned long long)w);
     loc[u] = (u32)old;
+    if (labx) labx[u] = (LT)c;
   }
   if (bad) atomicOr(&ctl->flags, F_LABEL);
 }
@@ -262,11 +448,11 @@ __global__ __launch_bounds__(1024) void k_scan_order(int L, const u32* __restric
 // are walked by all threads in order (coalesced); the owning row of an entry is found
 // by binary search over the 256 row starts staged in LDS.
 constexpr int GROWS = 256;
-template <bool PRIV>
+template <bool PRIV, class LT>
 __global__ __launch_bounds__(GROWS) void k_gather(int n, const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
-                                                  const int32_t* __restrict__ labels, int L, int chunk,
-                                                  const u32* __restrict__ PM, const u32* __restrict__ start,
-                                                  const u32* __restrict__ loc, u32* __restrict__ CB) {
+                                                  const LT* __restrict__ labx, int L, int chunk, const u32* __restrict__ PM,
+                                                  const u32* __restrict__ start, const u32* __restrict__ loc,
+                                                  LT* __restrict__ CB) {
   __shared__ int s_rs[GROWS + 1];
   __shared__ u32 s_base[GROWS];
   const int tid = threadIdx.x;
@@ -275,10 +461,10 @@ __global__ __launch_bounds__(GROWS) void k_gather(int n, const int32_t* __restri
   if (tid < rows) {
     long long u = r0 + tid;
     s_rs[tid] = rp[u];
-    int c = labels[u];
-    u32 lu = loc[u];
+    const LT c = labx[u];
+    const u32 lu = loc[u];
     u32 base = SENT;
-    if ((u32)c < (u32)L && lu != SENT) {
+    if (c != LabelT<LT>::SENTINEL && lu != SENT) {
       base = start[c] + lu;
       if (PRIV) base += PM[(size_t)(u / chunk) * L + c];
     }
@@ -293,20 +479,18 @@ __global__ __launch_bounds__(GROWS) void k_gather(int n, const int32_t* __restri
       int mid = (lo + hi + 1) >> 1;
       if (s_rs[mid] <= e) lo = mid; else hi = mid - 1;
     }
-    u32 base = s_base[lo];
+    const u32 base = s_base[lo];
     if (base == SENT) continue;
-    int v = col[e];
-    int j = labels[v];
-    CB[base + (u32)(e - s_rs[lo])] = ((u32)j < (u32)L) ? (u32)j : SENT;
+    CB[base + (u32)(e - s_rs[lo])] = labx[col[e]];
   }
 }
 
 // Comparison: the segment of ground-truth community a_u receives b_u.
-template <bool PRIV>
+template <bool PRIV, class LT>
 __global__ __launch_bounds__(256) void k_cmp_scatter(int n, const int32_t* __restrict__ la, const int32_t* __restrict__ lb,
                                                      int La, int Lb, int chunk, const u32* __restrict__ PM,
                                                      const u32* __restrict__ start, const u32* __restrict__ loc,
-                                                     u32* __restrict__ CB) {
+                                                     LT* __restrict__ CB) {
   for (size_t u = (size_t)blockIdx.x * blockDim.x + threadIdx.x; u < (size_t)n; u += (size_t)gridDim.x * blockDim.x) {
     int a = la[u];
     u32 lu = loc[u];
@@ -314,7 +498,7 @@ __global__ __launch_bounds__(256) void k_cmp_scatter(int n, const int32_t* __res
     u32 pos = start[a] + lu;
     if (PRIV) pos += PM[(u / chunk) * (size_t)La + a];
     int b = lb[u];
-    CB[pos] = ((u32)b < (u32)Lb) ? (u32)b : SENT;
+    CB[pos] = ((u32)b < (u32)Lb) ? (LT)b : LabelT<LT>::SENTINEL;
   }
 }
 
@@ -335,8 +519,8 @@ constexpr int STACK = 96;
 __device__ __forceinline__ u32 pow2ceil_u32(u32 x) { return x <= 1 ? 1u : 1u << (32 - __clz(x - 1)); }
 __device__ __forceinline__ u32 log2_u32(u32 x) { return 31 - __clz(x); }
 
-template <class V>
-__global__ __launch_bounds__(GBLOCK) void k_groups(const u32* __restrict__ CB, const u32* __restrict__ seg_start,
+template <class V, class LT>
+__global__ __launch_bounds__(GBLOCK) void k_groups(const LT* __restrict__ CB, const u32* __restrict__ seg_start,
                                                    const u32* __restrict__ seg_len, const u32* __restrict__ order,
                                                    Ctl* __restrict__ ctl, u32 Lv, u32 lds_words, V vis) {
   extern __shared__ u32 tab[];
@@ -363,7 +547,7 @@ __global__ __launch_bounds__(GBLOCK) void k_groups(const u32* __restrict__ CB, c
       for (u32 j = tid; j < Lv; j += GBLOCK) tab[j] = 0;
       __syncthreads();
       for (u32 e = base + tid; e < base + len; e += GBLOCK) {
-        u32 j = CB[e];
+        u32 j = (u32)CB[e];
         if (j < Lv) atomicAdd(&tab[j], 1u);
       }
       __syncthreads();
@@ -396,7 +580,7 @@ __global__ __launch_bounds__(GBLOCK) void k_groups(const u32* __restrict__ CB, c
         for (u32 s = tid; s < hcap; s += GBLOCK) { keys[s] = EMPTY; cnt[s] = 0; }
         __syncthreads();
         for (u32 e = base + tid; e < base + len; e += GBLOCK) {
-          u32 j = CB[e];
+          u32 j = (u32)CB[e];
           if (j >= Lv || (j & (mod - 1u)) != r) continue;
           u32 h = hash_slot(j, lg);
           bool done = false;

@@ -32,10 +32,21 @@ struct cq_graph {
   cq_context* ctx = nullptr;
   int32_t n = 0;
   int64_t nnz = 0;
-  const int32_t* rp = nullptr;
+  const int32_t* rp = nullptr;    // CSR the kernels read (borrowed, or owned_rp)
   const int32_t* col = nullptr;
+  const int32_t* perm = nullptr;  // graph row -> caller node id (null: identity)
   int64_t max_degree = 0;
   uint32_t validated = 0;
+  uint32_t reordered = 0;
+  int32_t* owned_rp = nullptr;    // device memory owned by the handle (CQ_GRAPH_REORDER)
+  int32_t* owned_col = nullptr;
+  int32_t* owned_perm = nullptr;
+  int64_t owned_bytes = 0;
+  ~cq_graph() {
+    if (owned_rp) (void)hipFree(owned_rp);
+    if (owned_col) (void)hipFree(owned_col);
+    if (owned_perm) (void)hipFree(owned_perm);
+  }
 };
 
 static_assert(sizeof(ScoreResultDev) == sizeof(cq_score_result), "score result layout");
@@ -113,15 +124,17 @@ unsigned grid_for(int64_t items, int per_block, unsigned cap) {
 }
 
 struct ScoreLayout {
-  bool priv;
+  bool priv, small;  // small: labels fit 16 bits (num_labels <= 65535)
   int chunk, W, G;
-  size_t ctl, N, D, start, order, I, NP, PEN, SZ, loc, HN, HD, CB, parts, res, total;
+  size_t ctl, N, D, start, order, I, NP, PEN, SZ, loc, HN, HD, labx, CB, parts, res, total;
 };
 
 ScoreLayout score_layout(int64_t n, int64_t nnz, int64_t L) {
   ScoreLayout s{};
   Carve c;
   s.priv = L <= PRIV_MAX;
+  s.small = L <= 65535;
+  const size_t lt = s.small ? 2 : 4;
   s.chunk = pick_chunk(n);
   s.W = (int)((n + s.chunk - 1) / s.chunk);
   s.G = (int)std::min<int64_t>(128, std::max<int64_t>(1, (L + 1023) / 1024));
@@ -137,7 +150,8 @@ ScoreLayout score_layout(int64_t n, int64_t nnz, int64_t L) {
   s.loc = c.take(4 * n);
   s.HN = s.priv ? c.take(4 * (size_t)s.W * L) : 0;
   s.HD = s.priv ? c.take(4 * (size_t)s.W * L) : 0;
-  s.CB = c.take(4 * nnz);
+  s.labx = c.take(lt * n);
+  s.CB = c.take(lt * nnz);
   s.parts = c.take(sizeof(ScorePart) * s.G);
   s.res = c.take(sizeof(ScoreResultDev));
   s.total = c.off;
@@ -145,7 +159,7 @@ ScoreLayout score_layout(int64_t n, int64_t nnz, int64_t L) {
 }
 
 struct CmpLayout {
-  bool privA, privB;
+  bool privA, privB, small;  // small: detected labels fit 16 bits
   int chunk, W, Wb, Ga, Gb;
   size_t ctl, A, B, start, order, COLMAX, RA11, RMAX, RF, RMI, RVI, SZ, loc, HN, HB, CB, parts, res, total;
 };
@@ -155,6 +169,7 @@ CmpLayout cmp_layout(int64_t n, int64_t La, int64_t Lb) {
   Carve c;
   s.privA = La <= PRIV_MAX;
   s.privB = Lb <= PRIV_MAX;
+  s.small = Lb <= 65535;
   s.chunk = pick_chunk(n);
   s.W = (int)((n + s.chunk - 1) / s.chunk);
   s.Wb = (int)std::min<int64_t>(256, std::max<int64_t>(1, (n + 8191) / 8192));
@@ -175,7 +190,7 @@ CmpLayout cmp_layout(int64_t n, int64_t La, int64_t Lb) {
   s.loc = c.take(4 * n);
   s.HN = s.privA ? c.take(4 * (size_t)s.W * La) : 0;
   s.HB = s.privB ? c.take(4 * (size_t)s.Wb * Lb) : 0;
-  s.CB = c.take(4 * n);
+  s.CB = c.take((s.small ? 2 : 4) * n);
   s.parts = c.take(sizeof(CmpPart) * (s.Ga + s.Gb));
   s.res = c.take(sizeof(CmpResultDev));
   s.total = c.off;
@@ -197,10 +212,10 @@ void fill(u32* p, size_t words, u32 v, hipStream_t s) {
   k_fill_u32<<<grid_for((int64_t)words, 256, 1024), 256, 0, s>>>(p, words, v);
 }
 
-template <class V>
+template <class V, class LT>
 unsigned group_grid(cq_context* ctx, size_t lds_bytes) {
   int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_groups<V>, GBLOCK, lds_bytes) != hipSuccess || nb < 1) nb = 1;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_groups<V, LT>, GBLOCK, lds_bytes) != hipSuccess || nb < 1) nb = 1;
   return (unsigned)(ctx->num_cus * nb);
 }
 
@@ -211,19 +226,11 @@ cq_status map_flags(cq_context* ctx, u32 flags) {
   return CQ_OK;
 }
 
-cq_status score_enqueue(cq_context* ctx, const cq_graph* g, const int32_t* labels, int32_t L, void* ws, size_t ws_bytes,
-                        ScoreResultDev* d_out, const cq_per_community* per_comm, const cq_pair_table* pairs, bool timed) {
-  if (!ctx) return CQ_E_INVALID_ARG;
-  ctx->err[0] = 0;
-  if (!g || !labels || !d_out) return fail(ctx, CQ_E_INVALID_ARG, "null graph, labels or output");
-  if (L < 1) return fail(ctx, CQ_E_INVALID_ARG, "num_labels must be >= 1");
-  if (g->nnz == 0) return fail(ctx, CQ_E_NO_EDGES, "graph has no edges");
-  if (pairs && pairs->capacity > 0 && (!pairs->ci || !pairs->cj || !pairs->count))
-    return fail(ctx, CQ_E_INVALID_ARG, "pair table with null arrays");
+// The scoring path with staged labels of type LT (u16 when num_labels <= 65535).
+template <class LT>
+void score_launch(cq_context* ctx, const cq_graph* g, const int32_t* labels, int32_t L, void* ws, const ScoreLayout& lay,
+                  ScoreResultDev* d_out, const cq_per_community* per_comm, const cq_pair_table* pairs, bool timed) {
   const int64_t n = g->n, nnz = g->nnz;
-  const ScoreLayout lay = score_layout(n, nnz, L);
-  if (!ws || ws_bytes < lay.total)
-    return fail(ctx, CQ_E_WORKSPACE, "workspace %zu bytes, need %zu", ws_bytes, lay.total);
   hipStream_t s = ctx->stream;
   Ctl* ctl = at<Ctl>(ws, lay.ctl);
   u32* N = at<u32>(ws, lay.N);
@@ -234,9 +241,9 @@ cq_status score_enqueue(cq_context* ctx, const cq_graph* g, const int32_t* label
   u32* NP = at<u32>(ws, lay.NP);
   u64* PEN = at<u64>(ws, lay.PEN);
   u32* loc = at<u32>(ws, lay.loc);
-  u32* CB = at<u32>(ws, lay.CB);
+  LT* labx = at<LT>(ws, lay.labx);
+  LT* CB = at<LT>(ws, lay.CB);
   ScorePart* parts = at<ScorePart>(ws, lay.parts);
-
   const u32* PM = nullptr;
   {
     StageMark mk(ctx, ST_SETUP, timed);
@@ -248,7 +255,8 @@ cq_status score_enqueue(cq_context* ctx, const cq_graph* g, const int32_t* label
     u32* HD = at<u32>(ws, lay.HD);
     {
       StageMark mk(ctx, ST_NODE, timed);
-      k_node_priv<true><<<lay.W, 1024, 2 * (size_t)L * 4, s>>>((int)n, labels, g->rp, L, lay.chunk, HN, HD, loc, ctl);
+      k_node_priv<true, LT><<<lay.W, 1024, 2 * (size_t)L * 4, s>>>((int)n, labels, g->perm, g->rp, L, lay.chunk, HN, HD, loc,
+                                                                   labx, ctl);
     }
     {
       StageMark mk(ctx, ST_COLSCAN, timed);
@@ -259,7 +267,7 @@ cq_status score_enqueue(cq_context* ctx, const cq_graph* g, const int32_t* label
     unsigned long long* SZ = at<unsigned long long>(ws, lay.SZ);
     {
       StageMark mk(ctx, ST_NODE, timed);
-      k_node_global<true><<<grid_for(n, 256, 8192), 256, 0, s>>>((int)n, labels, g->rp, L, SZ, loc, ctl);
+      k_node_global<true, LT><<<grid_for(n, 256, 8192), 256, 0, s>>>((int)n, labels, g->perm, g->rp, L, SZ, loc, labx, ctl);
     }
     {
       StageMark mk(ctx, ST_COLSCAN, timed);
@@ -273,11 +281,10 @@ cq_status score_enqueue(cq_context* ctx, const cq_graph* g, const int32_t* label
   {
     StageMark mk(ctx, ST_GATHER, timed);
     if (lay.priv)
-      k_gather<true><<<grid_for(n, GROWS, 1u << 30), GROWS, 0, s>>>((int)n, g->rp, g->col, labels, L, lay.chunk, PM, start, loc, CB);
+      k_gather<true, LT><<<grid_for(n, GROWS, 1u << 30), GROWS, 0, s>>>((int)n, g->rp, g->col, labx, L, lay.chunk, PM, start, loc, CB);
     else
-      k_gather<false><<<grid_for(n, GROWS, 1u << 30), GROWS, 0, s>>>((int)n, g->rp, g->col, labels, L, lay.chunk, PM, start, loc, CB);
+      k_gather<false, LT><<<grid_for(n, GROWS, 1u << 30), GROWS, 0, s>>>((int)n, g->rp, g->col, labx, L, lay.chunk, PM, start, loc, CB);
   }
-
   ScoreVis vis;
   vis.N = N;
   vis.twom = (double)nnz;
@@ -293,7 +300,7 @@ cq_status score_enqueue(cq_context* ctx, const cq_graph* g, const int32_t* label
   const size_t lds = (size_t)lds_words * 4;
   {
     StageMark mk(ctx, ST_GROUPS, timed);
-    k_groups<ScoreVis><<<group_grid<ScoreVis>(ctx, lds), GBLOCK, lds, s>>>(CB, start, D, order, ctl, (u32)L, lds_words, vis);
+    k_groups<ScoreVis, LT><<<group_grid<ScoreVis, LT>(ctx, lds), GBLOCK, lds, s>>>(CB, start, D, order, ctl, (u32)L, lds_words, vis);
   }
   PerComm pc;
   std::memset(&pc, 0, sizeof(pc));
@@ -303,21 +310,30 @@ cq_status score_enqueue(cq_context* ctx, const cq_graph* g, const int32_t* label
     k_score_final1<<<lay.G, FBLOCK, 0, s>>>(L, N, D, I, NP, PEN, (double)nnz, pc, parts);
     k_score_final2<<<1, 64, 0, s>>>(lay.G, parts, n, nnz, vis.ecap, ctl, d_out);
   }
+}
+
+cq_status score_enqueue(cq_context* ctx, const cq_graph* g, const int32_t* labels, int32_t L, void* ws, size_t ws_bytes,
+                        ScoreResultDev* d_out, const cq_per_community* per_comm, const cq_pair_table* pairs, bool timed) {
+  if (!ctx) return CQ_E_INVALID_ARG;
+  ctx->err[0] = 0;
+  if (!g || !labels || !d_out) return fail(ctx, CQ_E_INVALID_ARG, "null graph, labels or output");
+  if (L < 1) return fail(ctx, CQ_E_INVALID_ARG, "num_labels must be >= 1");
+  if (g->nnz == 0) return fail(ctx, CQ_E_NO_EDGES, "graph has no edges");
+  if (pairs && pairs->capacity > 0 && (!pairs->ci || !pairs->cj || !pairs->count))
+    return fail(ctx, CQ_E_INVALID_ARG, "pair table with null arrays");
+  const ScoreLayout lay = score_layout(g->n, g->nnz, L);
+  if (!ws || ws_bytes < lay.total)
+    return fail(ctx, CQ_E_WORKSPACE, "workspace %zu bytes, need %zu", ws_bytes, lay.total);
+  if (lay.small)
+    score_launch<uint16_t>(ctx, g, labels, L, ws, lay, d_out, per_comm, pairs, timed);
+  else
+    score_launch<uint32_t>(ctx, g, labels, L, ws, lay, d_out, per_comm, pairs, timed);
   return launch_status(ctx, "score launch");
 }
 
-cq_status compare_enqueue(cq_context* ctx, int32_t n, const int32_t* la, int32_t La, const int32_t* lb, int32_t Lb, void* ws,
-                          size_t ws_bytes, CmpResultDev* d_out, const cq_cell_table* cells, bool timed) {
-  if (!ctx) return CQ_E_INVALID_ARG;
-  ctx->err[0] = 0;
-  if (!la || !lb || !d_out) return fail(ctx, CQ_E_INVALID_ARG, "null labels or output");
-  if (n < 2) return fail(ctx, CQ_E_INVALID_ARG, "n must be >= 2");
-  if (La < 1 || Lb < 1) return fail(ctx, CQ_E_INVALID_ARG, "num_labels must be >= 1");
-  if (cells && cells->capacity > 0 && (!cells->ci || !cells->cj || !cells->count))
-    return fail(ctx, CQ_E_INVALID_ARG, "cell table with null arrays");
-  const CmpLayout lay = cmp_layout(n, La, Lb);
-  if (!ws || ws_bytes < lay.total)
-    return fail(ctx, CQ_E_WORKSPACE, "workspace %zu bytes, need %zu", ws_bytes, lay.total);
+template <class LT>
+void compare_launch(cq_context* ctx, int32_t n, const int32_t* la, int32_t La, const int32_t* lb, int32_t Lb, void* ws,
+                    const CmpLayout& lay, CmpResultDev* d_out, const cq_cell_table* cells, bool timed) {
   hipStream_t s = ctx->stream;
   Ctl* ctl = at<Ctl>(ws, lay.ctl);
   u32* A = at<u32>(ws, lay.A);
@@ -326,7 +342,7 @@ cq_status compare_enqueue(cq_context* ctx, int32_t n, const int32_t* la, int32_t
   u32* order = at<u32>(ws, lay.order);
   u32* COLMAX = at<u32>(ws, lay.COLMAX);
   u32* loc = at<u32>(ws, lay.loc);
-  u32* CB = at<u32>(ws, lay.CB);
+  LT* CB = at<LT>(ws, lay.CB);
   const u32* PM = nullptr;
   {
     StageMark mk(ctx, ST_SETUP, timed);
@@ -339,7 +355,8 @@ cq_status compare_enqueue(cq_context* ctx, int32_t n, const int32_t* la, int32_t
     u32* HN = at<u32>(ws, lay.HN);
     {
       StageMark mk(ctx, ST_NODE, timed);
-      k_node_priv<false><<<lay.W, 1024, (size_t)La * 4, s>>>(n, la, nullptr, La, lay.chunk, HN, nullptr, loc, ctl);
+      k_node_priv<false, uint32_t><<<lay.W, 1024, (size_t)La * 4, s>>>(n, la, nullptr, nullptr, La, lay.chunk, HN, nullptr, loc,
+                                                                       nullptr, ctl);
     }
     {
       StageMark mk(ctx, ST_COLSCAN, timed);
@@ -350,7 +367,7 @@ cq_status compare_enqueue(cq_context* ctx, int32_t n, const int32_t* la, int32_t
     unsigned long long* SZ = at<unsigned long long>(ws, lay.SZ);
     {
       StageMark mk(ctx, ST_NODE, timed);
-      k_node_global<false><<<grid_for(n, 256, 8192), 256, 0, s>>>(n, la, nullptr, La, SZ, loc, ctl);
+      k_node_global<false, uint32_t><<<grid_for(n, 256, 8192), 256, 0, s>>>(n, la, nullptr, nullptr, La, SZ, loc, nullptr, ctl);
     }
     {
       StageMark mk(ctx, ST_COLSCAN, timed);
@@ -374,11 +391,10 @@ cq_status compare_enqueue(cq_context* ctx, int32_t n, const int32_t* la, int32_t
   {
     StageMark mk(ctx, ST_SCATTER, timed);
     if (lay.privA)
-      k_cmp_scatter<true><<<grid_for(n, 256, 8192), 256, 0, s>>>(n, la, lb, La, Lb, lay.chunk, PM, start, loc, CB);
+      k_cmp_scatter<true, LT><<<grid_for(n, 256, 8192), 256, 0, s>>>(n, la, lb, La, Lb, lay.chunk, PM, start, loc, CB);
     else
-      k_cmp_scatter<false><<<grid_for(n, 256, 8192), 256, 0, s>>>(n, la, lb, La, Lb, lay.chunk, PM, start, loc, CB);
+      k_cmp_scatter<false, LT><<<grid_for(n, 256, 8192), 256, 0, s>>>(n, la, lb, La, Lb, lay.chunk, PM, start, loc, CB);
   }
-
   CmpVis vis;
   vis.A = A;
   vis.B = B;
@@ -399,7 +415,7 @@ cq_status compare_enqueue(cq_context* ctx, int32_t n, const int32_t* la, int32_t
   const size_t lds = (size_t)lds_words * 4;
   {
     StageMark mk(ctx, ST_GROUPS, timed);
-    k_groups<CmpVis><<<group_grid<CmpVis>(ctx, lds), GBLOCK, lds, s>>>(CB, start, A, order, ctl, (u32)Lb, lds_words, vis);
+    k_groups<CmpVis, LT><<<group_grid<CmpVis, LT>(ctx, lds), GBLOCK, lds, s>>>(CB, start, A, order, ctl, (u32)Lb, lds_words, vis);
   }
   CmpPart* parts = at<CmpPart>(ws, lay.parts);
   {
@@ -408,6 +424,24 @@ cq_status compare_enqueue(cq_context* ctx, int32_t n, const int32_t* la, int32_t
                                                    vis.RVI, (double)n, parts);
     k_cmp_final2<<<1, 64, 0, s>>>(lay.Ga + lay.Gb, parts, n, vis.ecap, ctl, d_out);
   }
+}
+
+cq_status compare_enqueue(cq_context* ctx, int32_t n, const int32_t* la, int32_t La, const int32_t* lb, int32_t Lb, void* ws,
+                          size_t ws_bytes, CmpResultDev* d_out, const cq_cell_table* cells, bool timed) {
+  if (!ctx) return CQ_E_INVALID_ARG;
+  ctx->err[0] = 0;
+  if (!la || !lb || !d_out) return fail(ctx, CQ_E_INVALID_ARG, "null labels or output");
+  if (n < 2) return fail(ctx, CQ_E_INVALID_ARG, "n must be >= 2");
+  if (La < 1 || Lb < 1) return fail(ctx, CQ_E_INVALID_ARG, "num_labels must be >= 1");
+  if (cells && cells->capacity > 0 && (!cells->ci || !cells->cj || !cells->count))
+    return fail(ctx, CQ_E_INVALID_ARG, "cell table with null arrays");
+  const CmpLayout lay = cmp_layout(n, La, Lb);
+  if (!ws || ws_bytes < lay.total)
+    return fail(ctx, CQ_E_WORKSPACE, "workspace %zu bytes, need %zu", ws_bytes, lay.total);
+  if (lay.small)
+    compare_launch<uint16_t>(ctx, n, la, La, lb, Lb, ws, lay, d_out, cells, timed);
+  else
+    compare_launch<uint32_t>(ctx, n, la, La, lb, Lb, ws, lay, d_out, cells, timed);
   return launch_status(ctx, "compare launch");
 }
 
@@ -423,6 +457,72 @@ cq_status fetch(cq_context* ctx, const void* d_res, R* h_out) {
 
 void set_big_lds(const void* fn, size_t bytes) {
   (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+// Exclusive scan of in[0, n) into out[0, n] (out[n] = total) using tmp tiles.
+void scan_u32(const u32* in, u32* out, long long n, u32* tiles, hipStream_t s) {
+  const int T = (int)((n + SCAN_TILE - 1) / SCAN_TILE);
+  k_scan_tiles<<<std::max(T, 1), SCAN_THREADS, 0, s>>>(n, in, out, tiles);
+  k_scan_tops<<<1, SCAN_THREADS, 0, s>>>(T, tiles, n, out);
+  if (T > 0) k_scan_add<<<T, SCAN_THREADS, 0, s>>>(n, out, tiles);
+}
+
+constexpr int LP_SWEEPS = 4;
+
+// Builds the renumbered copy of a graph (see CQ_GRAPH_REORDER in cq.h).
+cq_status build_locality_order(cq_context* ctx, cq_graph* g, const int32_t* rp, const int32_t* col) {
+  const int n = g->n;
+  const int64_t nnz = g->nnz;
+  hipStream_t s = ctx->stream;
+  const size_t tiles_n = (size_t)((n + 1 + SCAN_TILE - 1) / SCAN_TILE) + 1;
+  int32_t *lpA = nullptr, *lpB = nullptr, *newid = nullptr;
+  u32 *cnt = nullptr, *start = nullptr, *tiles = nullptr;
+  hipError_t e = hipSuccess;
+  auto alloc = [&](void** p, size_t bytes) {
+    if (e == hipSuccess) e = hipMalloc(p, std::max<size_t>(bytes, 4));
+  };
+  alloc((void**)&g->owned_rp, 4 * ((size_t)n + 1));
+  alloc((void**)&g->owned_col, 4 * (size_t)std::max<int64_t>(nnz, 1));
+  alloc((void**)&g->owned_perm, 4 * (size_t)n);
+  alloc((void**)&lpA, 4 * (size_t)n);
+  alloc((void**)&lpB, 4 * (size_t)n);
+  alloc((void**)&newid, 4 * (size_t)n);
+  alloc((void**)&cnt, 4 * ((size_t)n + 1));
+  alloc((void**)&start, 4 * ((size_t)n + 1));
+  alloc((void**)&tiles, 4 * tiles_n);
+  cq_status st = CQ_OK;
+  if (e != hipSuccess) {
+    st = fail(ctx, CQ_E_DEVICE, "allocating the renumbered graph: %s", hipGetErrorString(e));
+  } else {
+    const unsigned gw = grid_for((int64_t)n * 64, 256, 65535);  // one wave per row
+    const unsigned gn = grid_for(n, 256, 8192);
+    k_iota<<<gn, 256, 0, s>>>(n, lpA);
+    for (int it = 0; it < LP_SWEEPS; ++it) {
+      k_lp<<<gw, 256, 0, s>>>(n, rp, col, lpA, lpB);
+      std::swap(lpA, lpB);
+    }
+    fill(cnt, (size_t)n + 1, 0, s);
+    k_count_labels<<<gn, 256, 0, s>>>(n, lpA, cnt);
+    scan_u32(cnt, start, n, tiles, s);
+    fill(cnt, (size_t)n + 1, 0, s);
+    k_place<<<gn, 256, 0, s>>>(n, lpA, start, cnt, newid, g->owned_perm);
+    k_new_degree<<<gn, 256, 0, s>>>(n, rp, g->owned_perm, cnt);
+    scan_u32(cnt, reinterpret_cast<u32*>(g->owned_rp), n, tiles, s);
+    k_relabel_rows<<<gw, 256, 0, s>>>(n, rp, col, g->owned_perm, newid, g->owned_rp, g->owned_col);
+    e = hipGetLastError();
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) st = fail(ctx, CQ_E_DEVICE, "renumbering the graph: %s", hipGetErrorString(e));
+  }
+  for (void* p : {(void*)lpA, (void*)lpB, (void*)newid, (void*)cnt, (void*)start, (void*)tiles})
+    if (p) (void)hipFree(p);
+  if (st == CQ_OK) {
+    g->rp = g->owned_rp;
+    g->col = g->owned_col;
+    g->perm = g->owned_perm;
+    g->reordered = CQ_GRAPH_REORDER;
+    g->owned_bytes = (int64_t)(4 * ((size_t)n + 1) + 4 * (size_t)nnz + 4 * (size_t)n);
+  }
+  return st;
 }
 
 }  // namespace
@@ -470,11 +570,15 @@ cq_status cq_context_create(int device, void* hip_stream, cq_context** out) {
       return CQ_E_DEVICE;
     }
   }
-  set_big_lds(reinterpret_cast<const void*>(k_node_priv<true>), 2 * PRIV_MAX * 4);
-  set_big_lds(reinterpret_cast<const void*>(k_node_priv<false>), PRIV_MAX * 4);
+  const size_t gl = std::max<size_t>(DIRECT_MAX, HASH_WORDS) * 4;
+  set_big_lds(reinterpret_cast<const void*>(k_node_priv<true, uint16_t>), 2 * PRIV_MAX * 4);
+  set_big_lds(reinterpret_cast<const void*>(k_node_priv<true, uint32_t>), 2 * PRIV_MAX * 4);
+  set_big_lds(reinterpret_cast<const void*>(k_node_priv<false, uint32_t>), PRIV_MAX * 4);
   set_big_lds(reinterpret_cast<const void*>(k_hist_priv), PRIV_MAX * 4);
-  set_big_lds(reinterpret_cast<const void*>(k_groups<ScoreVis>), std::max<size_t>(DIRECT_MAX, HASH_WORDS) * 4);
-  set_big_lds(reinterpret_cast<const void*>(k_groups<CmpVis>), std::max<size_t>(DIRECT_MAX, HASH_WORDS) * 4);
+  set_big_lds(reinterpret_cast<const void*>(k_groups<ScoreVis, uint16_t>), gl);
+  set_big_lds(reinterpret_cast<const void*>(k_groups<ScoreVis, uint32_t>), gl);
+  set_big_lds(reinterpret_cast<const void*>(k_groups<CmpVis, uint16_t>), gl);
+  set_big_lds(reinterpret_cast<const void*>(k_groups<CmpVis, uint32_t>), gl);
   *out = ctx;
   return CQ_OK;
 }
@@ -525,7 +629,7 @@ cq_status cq_graph_load(cq_context* ctx, int32_t n, int64_t nnz, const int32_t* 
   if (!out || !d_row_ptr || (nnz > 0 && !d_col_idx)) return fail(ctx, CQ_E_INVALID_ARG, "null pointer");
   *out = nullptr;
   if (n < 1) return fail(ctx, CQ_E_INVALID_ARG, "n must be >= 1");
-  if (flags & ~CQ_VALIDATE_GRAPH) return fail(ctx, CQ_E_INVALID_ARG, "unknown flag bits");
+  if (flags & ~(CQ_VALIDATE_GRAPH | CQ_GRAPH_REORDER)) return fail(ctx, CQ_E_INVALID_ARG, "unknown flag bits");
   if (nnz < 0 || nnz >= (int64_t)1 << 31) return fail(ctx, CQ_E_OVERFLOW, "nnz must be in [0, 2^31)");
   if (nnz % 2) return fail(ctx, CQ_E_GRAPH_FORMAT, "an undirected CSR stores an even number of entries");
   hipStream_t s = ctx->stream;
@@ -563,6 +667,13 @@ cq_status cq_graph_load(cq_context* ctx, int32_t n, int64_t nnz, const int32_t* 
   g->col = d_col_idx;
   g->max_degree = res[1];
   g->validated = validated;
+  if ((flags & CQ_GRAPH_REORDER) && nnz > 0) {
+    cq_status st = build_locality_order(ctx, g, d_row_ptr, d_col_idx);
+    if (st != CQ_OK) {
+      delete g;
+      return st;
+    }
+  }
   *out = g;
   return CQ_OK;
 }
@@ -574,6 +685,8 @@ cq_status cq_graph_get_stats(const cq_graph* g, cq_graph_stats* out) {
   out->m = g->nnz / 2;
   out->max_degree = g->max_degree;
   out->validated = g->validated;
+  out->reordered = g->reordered;
+  out->owned_bytes = g->owned_bytes;
   return CQ_OK;
 }
 

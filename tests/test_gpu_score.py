@@ -27,12 +27,14 @@ def ctx(cq):
     c.close()
 
 
-def run_case(cq, ctx, rp, ci, lab, L, what, *, validate=True, pairs=True, per_comm=True):
+def run_case(cq, ctx, rp, ci, lab, L, what, *, validate=True, pairs=True, per_comm=True, reorder=False):
+    what = f"{what}{' [reordered graph]' if reorder else ''}"
     note(what)
     rp_t = torch.as_tensor(np.asarray(rp, np.int32)).cuda()
     ci_t = torch.as_tensor(np.asarray(ci, np.int32)).cuda()
     lab_t = torch.as_tensor(np.asarray(lab, np.int32)).cuda()
-    g = cq.Graph(ctx, rp_t, ci_t, validate=validate)
+    g = cq.Graph(ctx, rp_t, ci_t, validate=validate, reorder=reorder)
+    assert g.stats["reordered"] == (cq.CQ_GRAPH_REORDER if reorder else 0)
     o = oracle.score(np.asarray(rp), np.asarray(ci), np.asarray(lab), L, want_pairs=pairs)
     cap = max(1, int(o.result["num_pairs"])) if pairs else 0
     r, pc, pt = cq.score_partition(g, lab_t, L, per_community=per_comm, pairs_capacity=cap)
@@ -51,20 +53,22 @@ def lfr_case(name, seed):
     return g.row_ptr.numpy(), g.col_idx.numpy(), g.labels.numpy(), g.num_labels
 
 
-def test_tiny_lfr_ground_truth_and_perturbed(cq, ctx):
+@pytest.mark.parametrize("reorder", [False, True])
+def test_tiny_lfr_ground_truth_and_perturbed(cq, ctx, reorder):
     rp, ci, lab, L = lfr_case("tiny_1k", 1)
-    run_case(cq, ctx, rp, ci, lab, L, "tiny_1k seed1 ground truth")
+    run_case(cq, ctx, rp, ci, lab, L, "tiny_1k seed1 ground truth", reorder=reorder)
     pert = perturb_labels(torch.as_tensor(lab), L, 0.10, 101).numpy()
-    run_case(cq, ctx, rp, ci, pert, L, "tiny_1k seed1 perturbed 10%")
+    run_case(cq, ctx, rp, ci, pert, L, "tiny_1k seed1 perturbed 10%", reorder=reorder)
 
 
+@pytest.mark.parametrize("reorder", [False, True])
 @pytest.mark.parametrize("name", ["m100k_mu0.1", "m100k_mu0.3", "m100k_mu0.5"])
-def test_m100k(cq, ctx, name):
+def test_m100k(cq, ctx, name, reorder):
     rp, ci, lab, L = lfr_case(name, 11)
-    run_case(cq, ctx, rp, ci, lab, L, f"{name} ground truth")
+    run_case(cq, ctx, rp, ci, lab, L, f"{name} ground truth", reorder=reorder)
     for pct in (5, 30):
         pert = perturb_labels(torch.as_tensor(lab), L, pct / 100, 1000 + pct).numpy()
-        run_case(cq, ctx, rp, ci, pert, L, f"{name} perturbed {pct}%", per_comm=False)
+        run_case(cq, ctx, rp, ci, pert, L, f"{name} perturbed {pct}%", per_comm=False, reorder=reorder)
 
 
 def test_special_partitions(cq, ctx):
@@ -85,6 +89,9 @@ def test_many_labels_global_paths(cq, ctx):
     run_case(cq, ctx, rp, ci, np.arange(n, dtype=np.int32), n, "all singletons n=1e5", pairs=True)
     lab2 = (lab.astype(np.int64) * 7919 % 40009).astype(np.int32)  # injective relabel into 40009 ids
     run_case(cq, ctx, rp, ci, lab2, 40009, "relabelled into 40009 ids")
+    run_case(cq, ctx, rp, ci, lab2, 40009, "relabelled into 40009 ids", reorder=True)
+    lab3 = (lab.astype(np.int64) * 7919 % 70001).astype(np.int32)  # ids beyond 16 bits: 32-bit staging
+    run_case(cq, ctx, rp, ci, lab3, 70001, "relabelled into 70001 ids", reorder=True)
 
 
 def test_hub_split_classes(cq, ctx):
@@ -96,11 +103,13 @@ def test_hub_split_classes(cq, ctx):
     run_case(cq, ctx, rp, ci, np.arange(n, dtype=np.int32), n, "star 20000 singletons")
     lab = (np.arange(n, dtype=np.int64) * 8).astype(np.int32)
     run_case(cq, ctx, rp, ci, lab, 8 * n, "star 20000 singletons, labels = 8i")
+    run_case(cq, ctx, rp, ci, lab, 8 * n, "star 20000 singletons, labels = 8i", reorder=True)
 
 
-def test_errors(cq, ctx):
+@pytest.mark.parametrize("reorder", [False, True])
+def test_errors(cq, ctx, reorder):
     rp, ci = erdos_renyi(50, 0.2, 1)
-    g = cq.Graph(ctx, torch.as_tensor(rp).cuda(), torch.as_tensor(ci).cuda(), validate=True)
+    g = cq.Graph(ctx, torch.as_tensor(rp).cuda(), torch.as_tensor(ci).cuda(), validate=True, reorder=reorder)
     lab = torch.zeros(50, dtype=torch.int32, device="cuda")
     lab[7] = 5
     note("label out of range")
@@ -141,14 +150,19 @@ def test_errors(cq, ctx):
 
 def test_deterministic_and_workspace_reuse(cq, ctx):
     rp, ci, lab, L = lfr_case("m100k_mu0.5", 13)
-    note("m100k_mu0.5 repeated runs")
+    note("m100k_mu0.5 repeated runs, plain and reordered graph")
     g = cq.Graph(ctx, torch.as_tensor(rp).cuda(), torch.as_tensor(ci).cuda())
+    g2 = cq.Graph(ctx, torch.as_tensor(rp).cuda(), torch.as_tensor(ci).cuda(), reorder=True)
+    assert g2.stats["owned_bytes"] > 0
     lab_t = torch.as_tensor(lab).cuda()
     first, _, _ = cq.score_partition(g, lab_t, L)
     for _ in range(3):
         again, _, _ = cq.score_partition(g, lab_t, L)
         assert again == first  # bitwise: every float compared with ==
+        other, _, _ = cq.score_partition(g2, lab_t, L)
+        assert other == first  # the node order of the stored graph changes no bit of the result
     g.close()
+    g2.close()
 
 
 def test_full_size_l10m(cq, ctx):
@@ -160,11 +174,12 @@ def test_full_size_l10m(cq, ctx):
     rp, ci, lab = gr.row_ptr.cpu().numpy(), gr.col_idx.cpu().numpy(), gr.labels.cpu().numpy()
     note(f"l10m: n={gr.n} nnz={gr.nnz} K={gr.num_labels}; oracle")
     o = oracle.score(rp, ci, lab, gr.num_labels)
-    note("l10m: GPU")
-    g = cq.Graph(ctx, gr.row_ptr, gr.col_idx)
-    r, pc, pt = cq.score_partition(g, gr.labels, gr.num_labels, per_community=True,
-                                   pairs_capacity=int(o.result["num_pairs"]))
-    check_score(r, o.result, "l10m")
-    check_per_community(pc, o)
-    assert np.array_equal(sort_rows(pt), o.pairs)
-    g.close()
+    for reorder in (False, True):
+        note(f"l10m: GPU, reorder={reorder}")
+        g = cq.Graph(ctx, gr.row_ptr, gr.col_idx, reorder=reorder)
+        r, pc, pt = cq.score_partition(g, gr.labels, gr.num_labels, per_community=True,
+                                       pairs_capacity=int(o.result["num_pairs"]))
+        check_score(r, o.result, f"l10m reorder={reorder}")
+        check_per_community(pc, o)
+        assert np.array_equal(sort_rows(pt), o.pairs)
+        g.close()
