@@ -261,27 +261,56 @@ __global__ __launch_bounds__(1024) void k_node_priv(int n, const int32_t* __rest
   for (int i = threadIdx.x; i < words; i += blockDim.x) sh[i] = 0;
   if (threadIdx.x == 0) s_bad = 0;
   __syncthreads();
-  long long u0 = (long long)blockIdx.x * chunk;
-  long long u1 = min((long long)n, u0 + chunk);
+  const long long u0 = (long long)blockIdx.x * chunk;
+  const long long u1 = min((long long)n, u0 + chunk);
+  const int lane = threadIdx.x & 63;
   u32 bad = 0;
-  for (long long u = u0 + threadIdx.x; u < u1; u += blockDim.x) {
-    int c = labels[perm ? perm[u] : u];
-    if ((u32)c >= (u32)L) {
+  for (long long ub = u0; ub < u1; ub += blockDim.x) {  // uniform trip count per wave
+    const long long u = ub + threadIdx.x;
+    const bool in = u < u1;
+    int c = in ? labels[perm ? perm[u] : u] : 0;
+    const bool valid = in && (u32)c < (u32)L;
+    if (in && !valid) {
       bad = 1;
       loc[u] = SENT;
       if (labx) labx[u] = LabelT<LT>::SENTINEL;
-      continue;
     }
-    u32 old;
-    if (WEIGHTED) {
-      u32 w = (u32)(rp[u + 1] - rp[u]);
-      atomicAdd(&hn[c], 1u);
+    const u32 w = valid ? (WEIGHTED ? (u32)(rp[u + 1] - rp[u]) : 1u) : 0u;
+    // Lanes with equal labels (common when the graph is stored in a locality order)
+    // add to the LDS histogram through one leader lane; each lane's offset is the
+    // leader's old value plus the weights of the group's lower lanes.
+    bool pending = valid;
+    u32 old = 0;
+    for (int round = 0; round < 4; ++round) {
+      const u64 act = __ballot(pending);
+      if (act == 0) break;
+      const int leader = __ffsll((long long)act) - 1;
+      const int lc = __shfl(c, leader, 64);
+      const bool mine = pending && c == lc;
+      const u64 grp = __ballot(mine);
+      if (__popcll(grp) < 4) break;  // mixed labels: plain atomics below
+      const u32 pw = mine ? w : 0u;
+      const u32 incl = wave_incl_scan(pw);
+      const u32 tot = __shfl(incl, 63, 64);
+      u32 b = 0;
+      if (lane == leader) {
+        if (WEIGHTED) atomicAdd(&hn[lc], (u32)__popcll(grp));
+        b = atomicAdd(&hd[lc], tot);
+      }
+      b = __shfl(b, leader, 64);
+      if (mine) {
+        old = b + incl - pw;
+        pending = false;
+      }
+    }
+    if (pending) {
+      if (WEIGHTED) atomicAdd(&hn[c], 1u);
       old = atomicAdd(&hd[c], w);
-    } else {
-      old = atomicAdd(&hn[c], 1u);
     }
-    loc[u] = old;
-    if (labx) labx[u] = (LT)c;
+    if (valid) {
+      loc[u] = old;
+      if (labx) labx[u] = (LT)c;
+    }
   }
   if (bad) s_bad = 1;
   __syncthreads();
@@ -526,6 +555,7 @@ __global__ __launch_bounds__(GBLOCK) void k_groups(const LT* __restrict__ CB, co
   extern __shared__ u32 tab[];
   __shared__ u32 s_item;
   __shared__ u32 s_over;
+  __shared__ u32 s_hot;
   __shared__ int s_sp;
   __shared__ u32 s_sr[STACK], s_sm[STACK];
   const int tid = threadIdx.x;
@@ -544,16 +574,50 @@ __global__ __launch_bounds__(GBLOCK) void k_groups(const LT* __restrict__ CB, co
     u32 hcap = pow2ceil_u32(max(64u, 2u * M));
     const bool direct = (Lv <= lds_words) && (2u * hcap > Lv);
     if (direct) {
-      for (u32 j = tid; j < Lv; j += GBLOCK) tab[j] = 0;
+      // One label usually dominates a segment (the community's own label when scoring,
+      // the best-matching detected community when comparing).  Its entries are counted
+      // in registers: LDS atomics on a single address would serialise.
+      const u32 hot = V::kHotIsGroup ? g : (len ? (u32)CB[base] : 0xFFFFFFFFu);
+      const u32 nq = (Lv + 3u) >> 2;  // the table is padded to whole 16-byte words
+      uint4* tab4 = reinterpret_cast<uint4*>(tab);
+      for (u32 q = tid; q < nq; q += GBLOCK) tab4[q] = make_uint4(0u, 0u, 0u, 0u);
+      if (tid == 0) s_hot = 0;
       __syncthreads();
-      for (u32 e = base + tid; e < base + len; e += GBLOCK) {
-        u32 j = (u32)CB[e];
-        if (j < Lv) atomicAdd(&tab[j], 1u);
+      u32 mine = 0;
+      const LT* seg = CB + base;
+      constexpr u32 PER = 16u / sizeof(LT);
+      u32 head = (u32)(((16u - ((uintptr_t)seg & 15u)) & 15u) / sizeof(LT));
+      if (head > len) head = len;
+      const u32 nvec = (len - head) / PER;
+      auto count1 = [&](u32 j) {
+        if (j == hot) ++mine;
+        else if (j < Lv) atomicAdd(&tab[j], 1u);
+      };
+      for (u32 e = tid; e < head; e += GBLOCK) count1((u32)seg[e]);
+      const uint4* vec = reinterpret_cast<const uint4*>(seg + head);
+      for (u32 i = tid; i < nvec; i += GBLOCK) {
+        const uint4 q = vec[i];
+        const u32 w4[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          if (sizeof(LT) == 2) {
+            count1(w4[k] & 0xFFFFu);
+            count1(w4[k] >> 16);
+          } else {
+            count1(w4[k]);
+          }
+        }
       }
+      for (u32 e = head + nvec * PER + tid; e < len; e += GBLOCK) count1((u32)seg[e]);
+      if (mine) atomicAdd(&s_hot, mine);
       __syncthreads();
-      for (u32 j = tid; j < Lv; j += GBLOCK) {
-        u32 x = tab[j];
-        if (x) vis.visit(st, j, x);
+      if (tid == 0 && s_hot && hot < Lv) vis.visit(st, hot, s_hot);
+      for (u32 q = tid; q < nq; q += GBLOCK) {
+        const uint4 x = tab4[q];
+        if (x.x) vis.visit(st, 4u * q, x.x);
+        if (x.y) vis.visit(st, 4u * q + 1u, x.y);
+        if (x.z) vis.visit(st, 4u * q + 2u, x.z);
+        if (x.w) vis.visit(st, 4u * q + 3u, x.w);
       }
     } else {
       const u32 capmax = 1u << log2_u32(lds_words / 2u);
@@ -674,6 +738,7 @@ __device__ __forceinline__ double block_max_f64(double x, double* sh) {
 //   j != g  ->  x = |E_{g,j}|; contributes |E_gj|/(2|E|) * |E_gj|/(|g||j|) to g's
 //               split-penalty sum (Eq. 9); pairs with j > g are counted (and exported).
 struct ScoreVis {
+  static constexpr bool kHotIsGroup = true;
   const u32* N;
   double twom;
   u32* I;
@@ -727,6 +792,7 @@ struct ScoreVis {
 
 // Comparison visitor: row i of the contingency table, column j, cell x = |c_i ∩ c'_j|.
 struct CmpVis {
+  static constexpr bool kHotIsGroup = false;
   const u32* A;   // |c_i|
   const u32* B;   // |c'_j|
   double Nd;

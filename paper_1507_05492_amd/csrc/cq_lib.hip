@@ -296,7 +296,7 @@ void score_launch(cq_context* ctx, const cq_graph* g, const int32_t* labels, int
   vis.ecnt = pairs ? pairs->count : nullptr;
   vis.ecap = pairs ? pairs->capacity : 0;
   vis.ctl = ctl;
-  const u32 lds_words = L <= DIRECT_MAX ? std::max<u32>((u32)L, 128u) : HASH_WORDS;
+  const u32 lds_words = L <= DIRECT_MAX ? std::max<u32>(((u32)L + 3u) & ~3u, 128u) : HASH_WORDS;
   const size_t lds = (size_t)lds_words * 4;
   {
     StageMark mk(ctx, ST_GROUPS, timed);
@@ -411,7 +411,7 @@ void compare_launch(cq_context* ctx, int32_t n, const int32_t* la, int32_t La, c
   vis.ecnt = cells ? cells->count : nullptr;
   vis.ecap = cells ? cells->capacity : 0;
   vis.ctl = ctl;
-  const u32 lds_words = Lb <= DIRECT_MAX ? std::max<u32>((u32)Lb, 128u) : HASH_WORDS;
+  const u32 lds_words = Lb <= DIRECT_MAX ? std::max<u32>(((u32)Lb + 3u) & ~3u, 128u) : HASH_WORDS;
   const size_t lds = (size_t)lds_words * 4;
   {
     StageMark mk(ctx, ST_GROUPS, timed);
