@@ -200,6 +200,54 @@ cq_status cq_score_partition_async(cq_context* ctx, const cq_graph* g, const int
                                    cq_score_result* d_out, const cq_per_community* per_comm,
                                    const cq_pair_table* pairs);
 
+/* ---- batched scoring (many graphs x many partitions) ------------------------ */
+
+/* A batch scores many (graph, partition) tasks with one launch per stage of the
+ * scoring path instead of one call per task: every stage works on all tasks at once,
+ * partitions of the same graph share one read of its col_idx (up to 4 per group), and
+ * the per-community pass is one persistent launch over the communities of all tasks.
+ * The stage sequence is captured once in a HIP graph and replayed by cq_batch_run.
+ * Results are those of cq_score_partition for each task (bit for bit).
+ * Envelope: 1 <= num_labels <= 16384 per task, graphs with at least one edge; larger
+ * label spaces go through cq_score_partition. */
+typedef struct {
+  const cq_graph* graph;    /* registered graph (may be shared by several tasks) */
+  const int32_t* d_labels;  /* DEVICE int32[n], read at every run (contents may change between runs) */
+  int32_t num_labels;
+} cq_batch_task;
+
+typedef struct cq_batch_plan cq_batch_plan;
+
+#define CQ_BATCH_AUTOTUNE 1u  /* time candidate tilings on this batch at bind and keep the fastest */
+#define CQ_BATCH_NO_GRAPH 2u  /* launch the stage kernels directly instead of replaying a HIP graph */
+
+/* Validate tasks and lay out the batch (host only; copies the task array). */
+cq_status cq_batch_plan_create(cq_context* ctx, const cq_batch_task* tasks, int32_t num_tasks, uint32_t flags,
+                               cq_batch_plan** out);
+/* Workspace bytes the plan needs (0 for a null plan). */
+size_t cq_batch_workspace_size(const cq_batch_plan* plan);
+/* Bind DEVICE workspace and a DEVICE result array (cq_score_result[num_tasks]) to the
+ * plan: builds the device task tables (plan-owned device memory), autotunes when asked
+ * (this runs the batch), and captures the HIP graph.  Rebinding replaces all of this. */
+cq_status cq_batch_bind(cq_batch_plan* plan, void* d_ws, size_t ws_bytes, cq_score_result* d_results);
+/* Enqueue one run of the bound batch, ordered after earlier work on the context's stream. */
+cq_status cq_batch_run(cq_batch_plan* plan);
+/* Run, copy all results to HOST h_results[num_tasks] and synchronise.  Returns
+ * CQ_E_LABEL_RANGE if any task had a label outside its range (its results are then
+ * unspecified; the others are valid). */
+cq_status cq_batch_run_sync(cq_batch_plan* plan, cq_score_result* h_results);
+
+typedef struct {
+  int32_t gather_rows;          /* rows per workgroup of the batched edge pass */
+  int32_t group_blocks_per_cu;  /* resident workgroups per CU of the persistent group pass */
+  double tuned_ms;              /* fastest candidate's time (0 if not autotuned) */
+  int32_t from_cache;           /* 1 if the choice came from the tuning cache */
+  int32_t graph_nodes;          /* nodes of the captured HIP graph (0 with CQ_BATCH_NO_GRAPH) */
+  int32_t num_groups;           /* graph groups (partitions sharing one graph read) */
+} cq_batch_tuning;
+cq_status cq_batch_get_tuning(const cq_batch_plan* plan, cq_batch_tuning* out);
+void cq_batch_plan_destroy(cq_batch_plan* plan);
+
 /* ---- comparing two partitions (Section II-A) -------------------------------- */
 
 /* HOST result of cq_compare_partitions.  C is the ground truth (labels a), C' the

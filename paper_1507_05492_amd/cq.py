@@ -72,6 +72,19 @@ class PairTable(ctypes.Structure):
 CellTable = PairTable
 
 
+class BatchTask(ctypes.Structure):
+    _fields_ = [("graph", _P), ("d_labels", _P), ("num_labels", _I32)]
+
+
+class BatchTuning(ctypes.Structure):
+    _fields_ = [("gather_rows", _I32), ("group_blocks_per_cu", _I32), ("tuned_ms", ctypes.c_double),
+                ("from_cache", _I32), ("graph_nodes", _I32), ("num_groups", _I32)]
+
+
+CQ_BATCH_AUTOTUNE = 1
+CQ_BATCH_NO_GRAPH = 2
+
+
 class GraphStats(ctypes.Structure):
     _fields_ = [("n", _I64), ("nnz", _I64), ("m", _I64), ("max_degree", _I64), ("validated", ctypes.c_uint32),
                 ("reordered", ctypes.c_uint32), ("owned_bytes", _I64)]
@@ -99,6 +112,13 @@ def _load():
         "cq_context_enable_timing": (_I32, [_P, ctypes.c_int]),
         "cq_context_stage_times": (_I32, [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_I64), _I32]),
         "cq_stage_name": (ctypes.c_char_p, [_I32]),
+        "cq_batch_plan_create": (_I32, [_P, ctypes.POINTER(BatchTask), _I32, ctypes.c_uint32, ctypes.POINTER(_P)]),
+        "cq_batch_workspace_size": (_SZ, [_P]),
+        "cq_batch_bind": (_I32, [_P, _P, _SZ, _P]),
+        "cq_batch_run": (_I32, [_P]),
+        "cq_batch_run_sync": (_I32, [_P, ctypes.POINTER(ScoreResult)]),
+        "cq_batch_get_tuning": (_I32, [_P, ctypes.POINTER(BatchTuning)]),
+        "cq_batch_plan_destroy": (None, [_P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -228,6 +248,44 @@ def cq_compare_partitions(ctx, n, d_a, La, d_b, Lb, d_ws, ws_bytes, cells: CellT
 def cq_compare_partitions_async(ctx, n, d_a, La, d_b, Lb, d_ws, ws_bytes, d_out, cells=None) -> None:
     _check(ctx, _lib.cq_compare_partitions_async(ctx, n, d_a, La, d_b, Lb, d_ws, ws_bytes, d_out,
                                                  ctypes.byref(cells) if cells is not None else None))
+
+
+def cq_batch_plan_create(ctx: int, tasks: list[tuple[int, int, int]], flags: int = 0) -> int:
+    """tasks: (graph handle, device label pointer, num_labels)."""
+    arr = (BatchTask * len(tasks))(*[BatchTask(g, lab, L) for g, lab, L in tasks])
+    out = _P()
+    _check(ctx, _lib.cq_batch_plan_create(ctx, arr, len(tasks), flags, ctypes.byref(out)))
+    return out.value
+
+
+def cq_batch_workspace_size(plan: int) -> int:
+    return _lib.cq_batch_workspace_size(plan)
+
+
+def cq_batch_bind(ctx: int, plan: int, d_ws: int, ws_bytes: int, d_results: int) -> None:
+    _check(ctx, _lib.cq_batch_bind(plan, d_ws, ws_bytes, d_results))
+
+
+def cq_batch_run(ctx: int, plan: int) -> None:
+    _check(ctx, _lib.cq_batch_run(plan))
+
+
+def cq_batch_run_sync(ctx: int, plan: int, num_tasks: int, allow=(CQ_OK,)) -> tuple[int, list[ScoreResult]]:
+    res = (ScoreResult * num_tasks)()
+    st = _lib.cq_batch_run_sync(plan, res)
+    return _check(ctx, st, allow), list(res)
+
+
+def cq_batch_get_tuning(plan: int) -> dict:
+    t = BatchTuning()
+    st = _lib.cq_batch_get_tuning(plan, ctypes.byref(t))
+    if st != CQ_OK:
+        raise CQError(st)
+    return {k: getattr(t, k) for k, _ in BatchTuning._fields_}
+
+
+def cq_batch_plan_destroy(plan: int) -> None:
+    _lib.cq_batch_plan_destroy(plan)
 
 
 # ---- torch conveniences -------------------------------------------------------
@@ -374,3 +432,44 @@ def compare_partitions(ctx: Context, labels_a, num_labels_a: int, labels_b, num_
         k = min(r["nnz"], cells_capacity)
         cell_tensor = torch.stack([cells[0][:k].to(torch.int64), cells[1][:k].to(torch.int64), cells[2][:k]], dim=1)
     return r, cell_tensor
+
+
+class Batch:
+    """Many (graph, labels, num_labels) scoring tasks run as one batch (one HIP graph replay)."""
+
+    def __init__(self, ctx: Context, tasks, *, autotune: bool = True, use_graph: bool = True):
+        torch = _torch()
+        self.ctx = ctx
+        self.tasks = [(g, _dev_i32(lab, "labels"), int(L)) for g, lab, L in tasks]
+        for g, lab, _ in self.tasks:
+            if lab.numel() != g.n:
+                raise ValueError("labels must have one entry per node of their graph")
+        flags = (CQ_BATCH_AUTOTUNE if autotune else 0) | (0 if use_graph else CQ_BATCH_NO_GRAPH)
+        self.handle = cq_batch_plan_create(ctx.handle, [(g.handle, lab.data_ptr(), L) for g, lab, L in self.tasks], flags)
+        nbytes = cq_batch_workspace_size(self.handle)
+        self.ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=f"cuda:{ctx.device}")
+        self.results = torch.empty(len(self.tasks) * ctypes.sizeof(ScoreResult), dtype=torch.uint8,
+                                   device=f"cuda:{ctx.device}")
+        cq_batch_bind(ctx.handle, self.handle, self.ws.data_ptr(), self.ws.numel(), self.results.data_ptr())
+        self.tuning = cq_batch_get_tuning(self.handle)
+
+    def run(self) -> None:
+        cq_batch_run(self.ctx.handle, self.handle)
+
+    def run_sync(self, allow=(CQ_OK,)) -> list[dict]:
+        st, res = cq_batch_run_sync(self.ctx.handle, self.handle, len(self.tasks), allow=allow)
+        out = [as_dict(r) for r in res]
+        for r in out:
+            r["status"] = st
+        return out
+
+    def close(self):
+        if self.handle:
+            cq_batch_plan_destroy(self.handle)
+            self.handle = 0
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

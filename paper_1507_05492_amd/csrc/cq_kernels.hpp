@@ -249,10 +249,10 @@ struct LabelT {
 };
 
 template <bool WEIGHTED, class LT>
-__global__ __launch_bounds__(1024) void k_node_priv(int n, const int32_t* __restrict__ labels, const int32_t* __restrict__ perm,
-                                                    const int32_t* __restrict__ rp, int L, int chunk, u32* __restrict__ HN,
-                                                    u32* __restrict__ HD, u32* __restrict__ loc, LT* __restrict__ labx,
-                                                    Ctl* __restrict__ ctl) {
+__device__ __forceinline__ void node_priv_body(int n, const int32_t* __restrict__ labels, const int32_t* __restrict__ perm,
+                                               const int32_t* __restrict__ rp, int L, int chunk, u32* __restrict__ HN,
+                                               u32* __restrict__ HD, u32* __restrict__ loc, LT* __restrict__ labx,
+                                               Ctl* __restrict__ ctl, int blk) {
   extern __shared__ u32 sh[];
   u32* hn = sh;
   u32* hd = WEIGHTED ? sh + L : sh;
@@ -261,7 +261,7 @@ __global__ __launch_bounds__(1024) void k_node_priv(int n, const int32_t* __rest
   for (int i = threadIdx.x; i < words; i += blockDim.x) sh[i] = 0;
   if (threadIdx.x == 0) s_bad = 0;
   __syncthreads();
-  const long long u0 = (long long)blockIdx.x * chunk;
+  const long long u0 = (long long)blk * chunk;
   const long long u1 = min((long long)n, u0 + chunk);
   const int lane = threadIdx.x & 63;
   u32 bad = 0;
@@ -314,12 +314,20 @@ __global__ __launch_bounds__(1024) void k_node_priv(int n, const int32_t* __rest
   }
   if (bad) s_bad = 1;
   __syncthreads();
-  size_t row = (size_t)blockIdx.x * (size_t)L;
+  size_t row = (size_t)blk * (size_t)L;
   for (int c = threadIdx.x; c < L; c += blockDim.x) {
     HN[row + c] = hn[c];
     if (WEIGHTED) HD[row + c] = hd[c];
   }
   if (threadIdx.x == 0 && s_bad) atomicOr(&ctl->flags, F_LABEL);
+}
+
+template <bool WEIGHTED, class LT>
+__global__ __launch_bounds__(1024) void k_node_priv(int n, const int32_t* __restrict__ labels, const int32_t* __restrict__ perm,
+                                                    const int32_t* __restrict__ rp, int L, int chunk, u32* __restrict__ HN,
+                                                    u32* __restrict__ HD, u32* __restrict__ loc, LT* __restrict__ labx,
+                                                    Ctl* __restrict__ ctl) {
+  node_priv_body<WEIGHTED, LT>(n, labels, perm, rp, L, chunk, HN, HD, loc, labx, ctl, blockIdx.x);
 }
 
 // Node pass with global atomics (too many labels for LDS).  SZ[c] packs
@@ -380,10 +388,8 @@ __global__ __launch_bounds__(256) void k_hist_global(int n, const int32_t* __res
 // Column pass over the per-workgroup histograms: totals per label, and (SCAN) the
 // exclusive prefix over workgroups written back into the prefix matrix PM.
 template <bool WEIGHTED, bool SCAN>
-__global__ __launch_bounds__(256) void k_colscan(int W, int L, u32* __restrict__ HN, u32* __restrict__ HD, u32* __restrict__ N,
-                                                 u32* __restrict__ D) {
-  int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= L) return;
+__device__ __forceinline__ void colscan_body(int W, int L, u32* __restrict__ HN, u32* __restrict__ HD, u32* __restrict__ N,
+                                             u32* __restrict__ D, int c) {
   u32* PM = WEIGHTED ? HD : HN;
   u32 sn = 0, sd = 0;
   int w = 0;
@@ -412,6 +418,13 @@ __global__ __launch_bounds__(256) void k_colscan(int W, int L, u32* __restrict__
   if (D) D[c] = sd;
 }
 
+template <bool WEIGHTED, bool SCAN>
+__global__ __launch_bounds__(256) void k_colscan(int W, int L, u32* __restrict__ HN, u32* __restrict__ HD, u32* __restrict__ N,
+                                                 u32* __restrict__ D) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < L) colscan_body<WEIGHTED, SCAN>(W, L, HN, HD, N, D, c);
+}
+
 __global__ void k_unpack(int L, const unsigned long long* __restrict__ SZ, u32* __restrict__ N, u32* __restrict__ D) {
   for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < L; c += gridDim.x * blockDim.x) {
     unsigned long long v = SZ[c];
@@ -425,8 +438,8 @@ __global__ void k_unpack(int L, const unsigned long long* __restrict__ SZ, u32* 
 // non-empty groups: by decreasing floor(log2 D), so the largest groups start first.
 __device__ __forceinline__ int size_bucket(u32 x) { return x ? 32 - __clz(x) : 0; }
 
-__global__ __launch_bounds__(1024) void k_scan_order(int L, const u32* __restrict__ N, const u32* __restrict__ D,
-                                                     u32* __restrict__ start, u32* __restrict__ order, Ctl* __restrict__ ctl) {
+__device__ void scan_order_body(int L, const u32* __restrict__ N, const u32* __restrict__ D, u32* __restrict__ start,
+                                u32* __restrict__ order, Ctl* __restrict__ ctl) {
   __shared__ u32 s_wtot[16];
   __shared__ u32 s_carry;
   __shared__ u32 s_bcnt[33];
@@ -468,6 +481,11 @@ __global__ __launch_bounds__(1024) void k_scan_order(int L, const u32* __restric
       order[pos] = (u32)c;
     }
   }
+}
+
+__global__ __launch_bounds__(1024) void k_scan_order(int L, const u32* __restrict__ N, const u32* __restrict__ D,
+                                                     u32* __restrict__ start, u32* __restrict__ order, Ctl* __restrict__ ctl) {
+  scan_order_body(L, N, D, start, order, ctl);
 }
 
 // ---------------------------------------------------------------------------
@@ -548,142 +566,149 @@ constexpr int STACK = 96;
 __device__ __forceinline__ u32 pow2ceil_u32(u32 x) { return x <= 1 ? 1u : 1u << (32 - __clz(x - 1)); }
 __device__ __forceinline__ u32 log2_u32(u32 x) { return 31 - __clz(x); }
 
+// Counts one group's segment CB[base, base+len) (values in [0, Lv) or the sentinel)
+// in LDS and hands every (label, count) with count > 0 to the visitor.
 template <class V, class LT>
-__global__ __launch_bounds__(GBLOCK) void k_groups(const LT* __restrict__ CB, const u32* __restrict__ seg_start,
-                                                   const u32* __restrict__ seg_len, const u32* __restrict__ order,
-                                                   Ctl* __restrict__ ctl, u32 Lv, u32 lds_words, V vis) {
+__device__ void group_one(const LT* __restrict__ CB, const u32 base, const u32 len, const u32 g, const u32 Lv,
+                          const u32 lds_words, V& vis, Ctl* __restrict__ ctl) {
   extern __shared__ u32 tab[];
-  __shared__ u32 s_item;
   __shared__ u32 s_over;
   __shared__ u32 s_hot;
   __shared__ int s_sp;
   __shared__ u32 s_sr[STACK], s_sm[STACK];
   const int tid = threadIdx.x;
+  typename V::State st;
+  vis.begin(st, g);
+  const u32 M = min(len, Lv);
+  u32 hcap = pow2ceil_u32(max(64u, 2u * M));
+  const bool direct = (Lv <= lds_words) && (2u * hcap > Lv);
+  if (direct) {
+    // One label usually dominates a segment (the community's own label when scoring,
+    // the best-matching detected community when comparing).  Its entries are counted
+    // in registers: LDS atomics on a single address would serialise.
+    const u32 hot = V::kHotIsGroup ? g : (len ? (u32)CB[base] : 0xFFFFFFFFu);
+    const u32 nq = (Lv + 3u) >> 2;  // the table is padded to whole 16-byte words
+    uint4* tab4 = reinterpret_cast<uint4*>(tab);
+    for (u32 q = tid; q < nq; q += GBLOCK) tab4[q] = make_uint4(0u, 0u, 0u, 0u);
+    if (tid == 0) s_hot = 0;
+    __syncthreads();
+    u32 mine = 0;
+    const LT* seg = CB + base;
+    constexpr u32 PER = 16u / sizeof(LT);
+    u32 head = (u32)(((16u - ((uintptr_t)seg & 15u)) & 15u) / sizeof(LT));
+    if (head > len) head = len;
+    const u32 nvec = (len - head) / PER;
+    auto count1 = [&](u32 j) {
+      if (j == hot) ++mine;
+      else if (j < Lv) atomicAdd(&tab[j], 1u);
+    };
+    for (u32 e = tid; e < head; e += GBLOCK) count1((u32)seg[e]);
+    const uint4* vec = reinterpret_cast<const uint4*>(seg + head);
+    for (u32 i = tid; i < nvec; i += GBLOCK) {
+      const uint4 q = vec[i];
+      const u32 w4[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        if (sizeof(LT) == 2) {
+          count1(w4[k] & 0xFFFFu);
+          count1(w4[k] >> 16);
+        } else {
+          count1(w4[k]);
+        }
+      }
+    }
+    for (u32 e = head + nvec * PER + tid; e < len; e += GBLOCK) count1((u32)seg[e]);
+    if (mine) atomicAdd(&s_hot, mine);
+    __syncthreads();
+    if (tid == 0 && s_hot && hot < Lv) vis.visit(st, hot, s_hot);
+    for (u32 q = tid; q < nq; q += GBLOCK) {
+      const uint4 x = tab4[q];
+      if (x.x) vis.visit(st, 4u * q, x.x);
+      if (x.y) vis.visit(st, 4u * q + 1u, x.y);
+      if (x.z) vis.visit(st, 4u * q + 2u, x.z);
+      if (x.w) vis.visit(st, 4u * q + 3u, x.w);
+    }
+  } else {
+    const u32 capmax = 1u << log2_u32(lds_words / 2u);
+    u32 classes = 1;
+    if (hcap > capmax) {
+      classes = pow2ceil_u32((2u * M + capmax - 1u) / capmax);
+      if (classes > 32u) classes = 32u;
+      hcap = capmax;
+    }
+    const u32 lg = log2_u32(hcap);
+    u32* keys = tab;
+    u32* cnt = tab + hcap;
+    if (tid == 0) {
+      s_sp = 0;
+      for (int r = (int)classes - 1; r >= 0; --r) { s_sr[s_sp] = (u32)r; s_sm[s_sp] = classes; ++s_sp; }
+    }
+    __syncthreads();
+    for (;;) {
+      const int sp = s_sp;
+      if (sp == 0) break;
+      const u32 r = s_sr[sp - 1], mod = s_sm[sp - 1];
+      __syncthreads();
+      if (tid == 0) { s_sp = sp - 1; s_over = 0; }
+      for (u32 s = tid; s < hcap; s += GBLOCK) { keys[s] = EMPTY; cnt[s] = 0; }
+      __syncthreads();
+      for (u32 e = base + tid; e < base + len; e += GBLOCK) {
+        u32 j = (u32)CB[e];
+        if (j >= Lv || (j & (mod - 1u)) != r) continue;
+        u32 h = hash_slot(j, lg);
+        bool done = false;
+        for (u32 p = 0; p < hcap; ++p) {
+          u32 k = keys[h];
+          if (k == EMPTY) {
+            u32 old = atomicCAS(&keys[h], EMPTY, j);
+            if (old == EMPTY || old == j) { atomicAdd(&cnt[h], 1u); done = true; break; }
+          } else if (k == j) {
+            atomicAdd(&cnt[h], 1u);
+            done = true;
+            break;
+          }
+          h = (h + 1u) & (hcap - 1u);
+        }
+        if (!done) s_over = 1;
+      }
+      __syncthreads();
+      if (s_over) {
+        if (tid == 0) {
+          if (s_sp + 2 <= STACK && mod < 0x80000000u) {
+            s_sr[s_sp] = r + mod; s_sm[s_sp] = 2u * mod; ++s_sp;
+            s_sr[s_sp] = r; s_sm[s_sp] = 2u * mod; ++s_sp;
+          } else {
+            atomicOr(&ctl->flags, F_STACK);
+          }
+        }
+        __syncthreads();
+        continue;
+      }
+      for (u32 s = tid; s < hcap; s += GBLOCK) {
+        u32 k = keys[s];
+        if (k != EMPTY) vis.visit(st, k, cnt[s]);
+      }
+      __syncthreads();
+    }
+  }
+  vis.finish(st, g);
+  __syncthreads();
+}
+
+template <class V, class LT>
+__global__ __launch_bounds__(GBLOCK) void k_groups(const LT* __restrict__ CB, const u32* __restrict__ seg_start,
+                                                   const u32* __restrict__ seg_len, const u32* __restrict__ order,
+                                                   Ctl* __restrict__ ctl, u32 Lv, u32 lds_words, V vis) {
+  __shared__ u32 s_item;
   const u32 K = ctl->K;
   for (;;) {
-    if (tid == 0) s_item = atomicAdd(&ctl->ticket, 1u);
+    if (threadIdx.x == 0) s_item = atomicAdd(&ctl->ticket, 1u);
     __syncthreads();
     const u32 item = s_item;
     __syncthreads();
     if (item >= K) break;
     const u32 g = order[item];
-    const u32 base = seg_start[g], len = seg_len[g];
-    typename V::State st;
-    vis.begin(st, g);
-    const u32 M = min(len, Lv);
-    u32 hcap = pow2ceil_u32(max(64u, 2u * M));
-    const bool direct = (Lv <= lds_words) && (2u * hcap > Lv);
-    if (direct) {
-      // One label usually dominates a segment (the community's own label when scoring,
-      // the best-matching detected community when comparing).  Its entries are counted
-      // in registers: LDS atomics on a single address would serialise.
-      const u32 hot = V::kHotIsGroup ? g : (len ? (u32)CB[base] : 0xFFFFFFFFu);
-      const u32 nq = (Lv + 3u) >> 2;  // the table is padded to whole 16-byte words
-      uint4* tab4 = reinterpret_cast<uint4*>(tab);
-      for (u32 q = tid; q < nq; q += GBLOCK) tab4[q] = make_uint4(0u, 0u, 0u, 0u);
-      if (tid == 0) s_hot = 0;
-      __syncthreads();
-      u32 mine = 0;
-      const LT* seg = CB + base;
-      constexpr u32 PER = 16u / sizeof(LT);
-      u32 head = (u32)(((16u - ((uintptr_t)seg & 15u)) & 15u) / sizeof(LT));
-      if (head > len) head = len;
-      const u32 nvec = (len - head) / PER;
-      auto count1 = [&](u32 j) {
-        if (j == hot) ++mine;
-        else if (j < Lv) atomicAdd(&tab[j], 1u);
-      };
-      for (u32 e = tid; e < head; e += GBLOCK) count1((u32)seg[e]);
-      const uint4* vec = reinterpret_cast<const uint4*>(seg + head);
-      for (u32 i = tid; i < nvec; i += GBLOCK) {
-        const uint4 q = vec[i];
-        const u32 w4[4] = {q.x, q.y, q.z, q.w};
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          if (sizeof(LT) == 2) {
-            count1(w4[k] & 0xFFFFu);
-            count1(w4[k] >> 16);
-          } else {
-            count1(w4[k]);
-          }
-        }
-      }
-      for (u32 e = head + nvec * PER + tid; e < len; e += GBLOCK) count1((u32)seg[e]);
-      if (mine) atomicAdd(&s_hot, mine);
-      __syncthreads();
-      if (tid == 0 && s_hot && hot < Lv) vis.visit(st, hot, s_hot);
-      for (u32 q = tid; q < nq; q += GBLOCK) {
-        const uint4 x = tab4[q];
-        if (x.x) vis.visit(st, 4u * q, x.x);
-        if (x.y) vis.visit(st, 4u * q + 1u, x.y);
-        if (x.z) vis.visit(st, 4u * q + 2u, x.z);
-        if (x.w) vis.visit(st, 4u * q + 3u, x.w);
-      }
-    } else {
-      const u32 capmax = 1u << log2_u32(lds_words / 2u);
-      u32 classes = 1;
-      if (hcap > capmax) {
-        classes = pow2ceil_u32((2u * M + capmax - 1u) / capmax);
-        if (classes > 32u) classes = 32u;
-        hcap = capmax;
-      }
-      const u32 lg = log2_u32(hcap);
-      u32* keys = tab;
-      u32* cnt = tab + hcap;
-      if (tid == 0) {
-        s_sp = 0;
-        for (int r = (int)classes - 1; r >= 0; --r) { s_sr[s_sp] = (u32)r; s_sm[s_sp] = classes; ++s_sp; }
-      }
-      __syncthreads();
-      for (;;) {
-        const int sp = s_sp;
-        if (sp == 0) break;
-        const u32 r = s_sr[sp - 1], mod = s_sm[sp - 1];
-        __syncthreads();
-        if (tid == 0) { s_sp = sp - 1; s_over = 0; }
-        for (u32 s = tid; s < hcap; s += GBLOCK) { keys[s] = EMPTY; cnt[s] = 0; }
-        __syncthreads();
-        for (u32 e = base + tid; e < base + len; e += GBLOCK) {
-          u32 j = (u32)CB[e];
-          if (j >= Lv || (j & (mod - 1u)) != r) continue;
-          u32 h = hash_slot(j, lg);
-          bool done = false;
-          for (u32 p = 0; p < hcap; ++p) {
-            u32 k = keys[h];
-            if (k == EMPTY) {
-              u32 old = atomicCAS(&keys[h], EMPTY, j);
-              if (old == EMPTY || old == j) { atomicAdd(&cnt[h], 1u); done = true; break; }
-            } else if (k == j) {
-              atomicAdd(&cnt[h], 1u);
-              done = true;
-              break;
-            }
-            h = (h + 1u) & (hcap - 1u);
-          }
-          if (!done) s_over = 1;
-        }
-        __syncthreads();
-        if (s_over) {
-          if (tid == 0) {
-            if (s_sp + 2 <= STACK && mod < 0x80000000u) {
-              s_sr[s_sp] = r + mod; s_sm[s_sp] = 2u * mod; ++s_sp;
-              s_sr[s_sp] = r; s_sm[s_sp] = 2u * mod; ++s_sp;
-            } else {
-              atomicOr(&ctl->flags, F_STACK);
-            }
-          }
-          __syncthreads();
-          continue;
-        }
-        for (u32 s = tid; s < hcap; s += GBLOCK) {
-          u32 k = keys[s];
-          if (k != EMPTY) vis.visit(st, k, cnt[s]);
-        }
-        __syncthreads();
-      }
-    }
-    vis.finish(st, g);
-    __syncthreads();
+    group_one<V, LT>(CB, seg_start[g], seg_len[g], g, Lv, lds_words, vis, ctl);
   }
 }
 
@@ -892,14 +917,13 @@ struct PerComm {
   double* qds_term;
 };
 
-__global__ __launch_bounds__(FBLOCK) void k_score_final1(int L, const u32* __restrict__ N, const u32* __restrict__ D,
-                                                         const u32* __restrict__ I, const u32* __restrict__ NP,
-                                                         const u64* __restrict__ PEN, double twom, PerComm pc,
-                                                         ScorePart* __restrict__ parts) {
+__device__ void score_final1_body(int L, const u32* __restrict__ N, const u32* __restrict__ D, const u32* __restrict__ I,
+                                  const u32* __restrict__ NP, const u64* __restrict__ PEN, double twom, const PerComm& pc,
+                                  ScorePart* __restrict__ parts, int blk, int G) {
   __shared__ u64 sh_lo[FBLOCK / 64], sh_hi[FBLOCK / 64];
   __shared__ double sh_d[FBLOCK / 64];
-  const int R = (L + gridDim.x - 1) / gridDim.x;
-  const int c0 = blockIdx.x * R, c1 = min(L, c0 + R);
+  const int R = (L + G - 1) / G;
+  const int c0 = blk * R, c1 = min(L, c0 + R);
   const double m = 0.5 * twom;
   u64 K = 0, sein = 0, seout = 0, sD2 = 0, np = 0;
   u128 pen = 0;
@@ -954,7 +978,14 @@ __global__ __launch_bounds__(FBLOCK) void k_score_final1(int L, const u32* __res
   p.s_exp = block_sum_f64<FBLOCK / 64>(s_exp, sh_d);
   p.s_cond = block_sum_f64<FBLOCK / 64>(s_cond, sh_d);
   p.pad2[0] = p.pad2[1] = p.pad2[2] = 0;
-  if (threadIdx.x == 0) parts[blockIdx.x] = p;
+  if (threadIdx.x == 0) parts[blk] = p;
+}
+
+__global__ __launch_bounds__(FBLOCK) void k_score_final1(int L, const u32* __restrict__ N, const u32* __restrict__ D,
+                                                         const u32* __restrict__ I, const u32* __restrict__ NP,
+                                                         const u64* __restrict__ PEN, double twom, PerComm pc,
+                                                         ScorePart* __restrict__ parts) {
+  score_final1_body(L, N, D, I, NP, PEN, twom, pc, parts, blockIdx.x, gridDim.x);
 }
 
 // device mirror of the public cq_score_result (same layout)
@@ -967,9 +998,8 @@ struct ScoreResultDev {
   uint32_t device_flags, reserved;
 };
 
-__global__ void k_score_final2(int G, const ScorePart* __restrict__ parts, long long n, long long twom, long long ecap,
-                               Ctl* __restrict__ ctl, ScoreResultDev* __restrict__ out) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+__device__ void score_final2_body(int G, const ScorePart* __restrict__ parts, long long n, long long twom, long long ecap,
+                                  Ctl* __restrict__ ctl, ScoreResultDev* __restrict__ out) {
   u64 K = 0, sein = 0, seout = 0, sD2 = 0, np = 0;
   u128 pen = 0;
   double qds_a = 0, s_dens = 0, s_contr = 0, s_exp = 0, s_cond = 0;
@@ -1000,6 +1030,11 @@ __global__ void k_score_final2(int G, const ScorePart* __restrict__ parts, long 
   r.device_flags = ctl->flags | ((ecap > 0 && (long long)ctl->export_count > ecap) ? F_EXPORT : 0u);
   r.reserved = 0;
   *out = r;
+}
+
+__global__ void k_score_final2(int G, const ScorePart* __restrict__ parts, long long n, long long twom, long long ecap,
+                               Ctl* __restrict__ ctl, ScoreResultDev* __restrict__ out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) score_final2_body(G, parts, n, twom, ecap, ctl, out);
 }
 
 // comparison final reduction ------------------------------------------------
@@ -1116,6 +1151,197 @@ __global__ void k_cmp_final2(int G, const CmpPart* __restrict__ parts, long long
   r.device_flags = ctl->flags | ((ecap > 0 && (long long)ctl->export_count > ecap) ? F_EXPORT : 0u);
   r.reserved = 0;
   *out = r;
+}
+
+// ---------------------------------------------------------------------------
+// Batched scoring: many (graph, partition) tasks per launch.  Every stage of the
+// scoring path runs as one launch over the work of all tasks; blocks find their task
+// through prefix tables built by the host plan.  Tasks that share a graph are grouped
+// (up to BATCH_FUSE partitions), and the edge pass reads that graph's col_idx once for
+// the whole group.  Batched tasks use LDS-private histograms and 16-bit labels
+// (num_labels <= 16384).
+constexpr int BATCH_FUSE = 4;
+
+struct TaskDev {
+  const int32_t* labels;
+  const int32_t* perm;
+  const int32_t* rp;
+  const int32_t* col;
+  long long nnz;
+  int n, L, chunk, W, G, pad;
+  Ctl* ctl;
+  u32 *N, *D, *start, *order, *I, *NP;
+  u64* PEN;
+  u32* loc;
+  u32 *HN, *HD;
+  uint16_t* labx;
+  uint16_t* CB;
+  ScorePart* parts;
+  ScoreResultDev* out;
+};
+
+struct GroupDev {
+  const int32_t* rp;
+  const int32_t* col;
+  int n, np;
+  int task[BATCH_FUSE];
+};
+
+// largest i in [0, cnt) with pre[i] <= x (pre non-decreasing, pre[0] == 0)
+__device__ __forceinline__ int find_seg(const u32* __restrict__ pre, int cnt, u32 x) {
+  int lo = 0, hi = cnt - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (pre[mid] <= x) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+__global__ void k_b_setup(int T, const TaskDev* __restrict__ td, u32* __restrict__ ticket) {
+  const int t = blockIdx.x;
+  if (t < T) {
+    u32* c = reinterpret_cast<u32*>(td[t].ctl);
+    for (int i = threadIdx.x; i < (int)(sizeof(Ctl) / 4); i += blockDim.x) c[i] = 0;
+  }
+  if (t == 0 && threadIdx.x == 0) *ticket = 0;
+}
+
+__global__ __launch_bounds__(1024) void k_b_node(const TaskDev* __restrict__ td, const u32* __restrict__ Wpre, int T) {
+  const int t = find_seg(Wpre, T, blockIdx.x);
+  const TaskDev& d = td[t];
+  node_priv_body<true, uint16_t>(d.n, d.labels, d.perm, d.rp, d.L, d.chunk, d.HN, d.HD, d.loc, d.labx, d.ctl,
+                                 (int)(blockIdx.x - Wpre[t]));
+}
+
+__global__ __launch_bounds__(256) void k_b_colscan(const TaskDev* __restrict__ td, const u32* __restrict__ Lpre, int T) {
+  const u32 gid = blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= Lpre[T]) return;
+  const int t = find_seg(Lpre, T, gid);
+  const TaskDev& d = td[t];
+  colscan_body<true, true>(d.W, d.L, d.HN, d.HD, d.N, d.D, (int)(gid - Lpre[t]));
+}
+
+__global__ __launch_bounds__(1024) void k_b_scan_order(const TaskDev* __restrict__ td) {
+  const TaskDev& d = td[blockIdx.x];
+  scan_order_body(d.L, d.N, d.D, d.start, d.order, d.ctl);
+}
+
+// Kpre[t] = number of non-empty communities of tasks before t; Kpre[T] = total
+__global__ __launch_bounds__(1024) void k_b_kprefix(const TaskDev* __restrict__ td, int T, u32* __restrict__ Kpre) {
+  __shared__ u32 s_w[SCAN_THREADS / 64];
+  __shared__ u32 s_carry;
+  if (threadIdx.x == 0) s_carry = 0;
+  __syncthreads();
+  for (int b = 0; b < T; b += SCAN_THREADS) {
+    const int i = b + threadIdx.x;
+    const u32 x = i < T ? td[i].ctl->K : 0u;
+    u32 total;
+    const u32 ex = block_excl_scan_1024(x, s_w, &total);
+    const u32 carry = s_carry;
+    if (i < T) Kpre[i] = carry + ex;
+    __syncthreads();
+    if (threadIdx.x == 0) s_carry = carry + total;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) Kpre[T] = s_carry;
+}
+
+// Edge pass for a group of partitions of one graph: every col_idx entry is read once
+// and the neighbour's label of each partition goes to that partition's segment.
+template <int R>
+__global__ __launch_bounds__(R) void k_b_gather(const GroupDev* __restrict__ gd, const u32* __restrict__ RBpre, int ngroups,
+                                                const TaskDev* __restrict__ td) {
+  __shared__ int s_rs[R + 1];
+  __shared__ u32 s_base[BATCH_FUSE][R];
+  const int k = find_seg(RBpre, ngroups, blockIdx.x);
+  const GroupDev grp = gd[k];
+  const int tid = threadIdx.x;
+  const long long r0 = (long long)(blockIdx.x - RBpre[k]) * R;
+  const int rows = (int)min((long long)R, (long long)grp.n - r0);
+  if (tid < rows) {
+    const long long u = r0 + tid;
+    s_rs[tid] = grp.rp[u];
+#pragma unroll
+    for (int p = 0; p < BATCH_FUSE; ++p) {
+      if (p < grp.np) {
+        const TaskDev& d = td[grp.task[p]];
+        const uint16_t c = d.labx[u];
+        const u32 lu = d.loc[u];
+        u32 base = SENT;
+        if (c != LabelT<uint16_t>::SENTINEL && lu != SENT) base = d.start[c] + d.HD[(size_t)(u / d.chunk) * d.L + c] + lu;
+        s_base[p][tid] = base;
+      }
+    }
+  }
+  if (tid == 0) s_rs[rows] = grp.rp[r0 + rows];
+  __syncthreads();
+  const uint16_t* lx[BATCH_FUSE];
+  uint16_t* cb[BATCH_FUSE];
+#pragma unroll
+  for (int p = 0; p < BATCH_FUSE; ++p) {
+    lx[p] = p < grp.np ? td[grp.task[p]].labx : nullptr;
+    cb[p] = p < grp.np ? td[grp.task[p]].CB : nullptr;
+  }
+  const int e0 = s_rs[0], e1 = s_rs[rows];
+  for (int e = e0 + tid; e < e1; e += R) {
+    int lo = 0, hi = rows - 1;
+    while (lo < hi) {
+      int mid = (lo + hi + 1) >> 1;
+      if (s_rs[mid] <= e) lo = mid; else hi = mid - 1;
+    }
+    const int v = grp.col[e];
+    const u32 off = (u32)(e - s_rs[lo]);
+#pragma unroll
+    for (int p = 0; p < BATCH_FUSE; ++p) {
+      if (p < grp.np) {
+        const u32 b = s_base[p][lo];
+        if (b != SENT) cb[p][b + off] = lx[p][v];
+      }
+    }
+  }
+}
+
+// Persistent group pass over the communities of every task (one ticket counter).
+__global__ __launch_bounds__(GBLOCK) void k_b_groups(const TaskDev* __restrict__ td, const u32* __restrict__ Kpre, int T,
+                                                     u32* __restrict__ ticket, u32 lds_words) {
+  __shared__ u32 s_item;
+  const u32 total = Kpre[T];
+  for (;;) {
+    if (threadIdx.x == 0) s_item = atomicAdd(ticket, 1u);
+    __syncthreads();
+    const u32 item = s_item;
+    __syncthreads();
+    if (item >= total) break;
+    const int t = find_seg(Kpre, T, item);
+    const TaskDev& d = td[t];
+    const u32 g = d.order[item - Kpre[t]];
+    ScoreVis vis;
+    vis.N = d.N;
+    vis.twom = (double)d.nnz;
+    vis.I = d.I;
+    vis.NP = d.NP;
+    vis.PEN = d.PEN;
+    vis.eci = nullptr;
+    vis.ecj = nullptr;
+    vis.ecnt = nullptr;
+    vis.ecap = 0;
+    vis.ctl = d.ctl;
+    group_one<ScoreVis, uint16_t>(d.CB, d.start[g], d.D[g], g, (u32)d.L, lds_words, vis, d.ctl);
+  }
+}
+
+__global__ __launch_bounds__(FBLOCK) void k_b_final1(const TaskDev* __restrict__ td, const u32* __restrict__ Gpre, int T) {
+  const int t = find_seg(Gpre, T, blockIdx.x);
+  const TaskDev& d = td[t];
+  PerComm pc = {};
+  score_final1_body(d.L, d.N, d.D, d.I, d.NP, d.PEN, (double)d.nnz, pc, d.parts, (int)(blockIdx.x - Gpre[t]), d.G);
+}
+
+__global__ void k_b_final2(const TaskDev* __restrict__ td, int T) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= T) return;
+  const TaskDev& d = td[t];
+  score_final2_body(d.G, d.parts, d.n, d.nnz, 0, d.ctl, d.out);
 }
 
 }  // namespace cq

@@ -3,10 +3,16 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
+#include <string>
+#include <vector>
 
 #include "cq.h"
 #include "cq_kernels.hpp"
@@ -46,6 +52,48 @@ struct cq_graph {
     if (owned_rp) (void)hipFree(owned_rp);
     if (owned_col) (void)hipFree(owned_col);
     if (owned_perm) (void)hipFree(owned_perm);
+  }
+};
+
+struct cq_batch_plan {
+  cq_context* ctx = nullptr;
+  uint32_t flags = 0;
+  std::vector<cq_batch_task> tasks;
+  std::vector<size_t> ws_off;  // per-task workspace offset
+  size_t ws_total = 0;
+  std::vector<std::array<int, 4>> groups;
+  std::vector<int> group_np;
+  int maxL = 1;
+  // device tables (owned)
+  void* d_tab = nullptr;
+  size_t tab_bytes = 0;
+  void* td = nullptr;  // cq::TaskDev[T]
+  void* gd = nullptr;  // cq::GroupDev[ngroups]
+  uint32_t *Wpre = nullptr, *Lpre = nullptr, *Gpre = nullptr, *Kpre = nullptr, *ticket = nullptr;
+  uint32_t* RBpre[3] = {nullptr, nullptr, nullptr};
+  uint32_t Wsum = 0, Lsum = 0, Gsum = 0, RBsum[3] = {0, 0, 0};
+  // binding
+  void* ws = nullptr;
+  cq_score_result* d_results = nullptr;
+  bool bound = false;
+  // tuning and replay
+  int rsel = 1, occ = 1;
+  double tuned_ms = 0.0;
+  int from_cache = 0;
+  int graph_nodes = 0;
+  hipStream_t stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  void* pinned = nullptr;
+  ~cq_batch_plan() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (d_tab) (void)hipFree(d_tab);
+    if (ev_in) (void)hipEventDestroy(ev_in);
+    if (ev_out) (void)hipEventDestroy(ev_out);
+    if (stream) (void)hipStreamDestroy(stream);
+    if (pinned) (void)hipHostFree(pinned);
   }
 };
 
@@ -525,6 +573,95 @@ cq_status build_locality_order(cq_context* ctx, cq_graph* g, const int32_t* rp, 
   return st;
 }
 
+
+// ---- batched scoring -------------------------------------------------------
+constexpr int kGatherRows[3] = {128, 256, 512};
+constexpr int64_t BATCH_MAX_L = PRIV_MAX;
+
+void batch_launch(cq_batch_plan* p, hipStream_t s, int rsel, int occ) {
+  const int T = (int)p->tasks.size();
+  const TaskDev* td = static_cast<const TaskDev*>(p->td);
+  const GroupDev* gd = static_cast<const GroupDev*>(p->gd);
+  const int ng = (int)p->groups.size();
+  k_b_setup<<<T, 64, 0, s>>>(T, td, p->ticket);
+  k_b_node<<<p->Wsum, 1024, 2 * (size_t)p->maxL * 4, s>>>(td, p->Wpre, T);
+  k_b_colscan<<<grid_for(p->Lsum, 256, 1u << 30), 256, 0, s>>>(td, p->Lpre, T);
+  k_b_scan_order<<<T, 1024, 0, s>>>(td);
+  k_b_kprefix<<<1, 1024, 0, s>>>(td, T, p->Kpre);
+  switch (rsel) {
+    case 0: k_b_gather<128><<<p->RBsum[0], 128, 0, s>>>(gd, p->RBpre[0], ng, td); break;
+    case 1: k_b_gather<256><<<p->RBsum[1], 256, 0, s>>>(gd, p->RBpre[1], ng, td); break;
+    default: k_b_gather<512><<<p->RBsum[2], 512, 0, s>>>(gd, p->RBpre[2], ng, td); break;
+  }
+  const u32 lds_words = std::max<u32>(((u32)p->maxL + 3u) & ~3u, 128u);
+  k_b_groups<<<(unsigned)(p->ctx->num_cus * occ), GBLOCK, (size_t)lds_words * 4, s>>>(td, p->Kpre, T, p->ticket, lds_words);
+  k_b_final1<<<p->Gsum, FBLOCK, 0, s>>>(td, p->Gpre, T);
+  k_b_final2<<<grid_for(T, 64, 1u << 20), 64, 0, s>>>(td, T);
+}
+
+int batch_max_occ(cq_batch_plan* p) {
+  const u32 lds_words = std::max<u32>(((u32)p->maxL + 3u) & ~3u, 128u);
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_b_groups, GBLOCK, (size_t)lds_words * 4) != hipSuccess || nb < 1)
+    nb = 1;
+  return nb;
+}
+
+std::string batch_key(const cq_batch_plan* p) {
+  long long sn = 0, snnz = 0;
+  for (const auto& t : p->tasks) {
+    sn += t.graph->n;
+    snnz += t.graph->nnz;
+  }
+  char buf[160];
+  snprintf(buf, sizeof(buf), "gfx950:cus%d:T%zu:G%zu:n%lld:nnz%lld:L%d", p->ctx->num_cus, p->tasks.size(), p->groups.size(),
+           sn, snnz, p->maxL);
+  return buf;
+}
+
+std::mutex g_tune_mu;
+std::map<std::string, std::array<double, 3>> g_tune;  // key -> (rsel, occ, ms)
+
+// Tuning cache: kept for the process; when CQ_TUNE_CACHE names a file, it is also read
+// from and appended to as JSON lines {"key": ..., "gather_rows": ..., "occ": ..., "ms": ...}.
+bool tune_lookup(const std::string& key, int* rsel, int* occ, double* ms) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  const char* path = std::getenv("CQ_TUNE_CACHE");
+  if (path && *path) {
+    if (FILE* f = fopen(path, "r")) {
+      char line[512];
+      while (fgets(line, sizeof(line), f)) {
+        char k[256];
+        int rows = 0, o = 0;
+        double t = 0;
+        if (sscanf(line, "{\"key\": \"%255[^\"]\", \"gather_rows\": %d, \"occ\": %d, \"ms\": %lf}", k, &rows, &o, &t) == 4) {
+          int r = rows == 128 ? 0 : rows == 256 ? 1 : 2;
+          g_tune[k] = {(double)r, (double)o, t};
+        }
+      }
+      fclose(f);
+    }
+  }
+  auto it = g_tune.find(key);
+  if (it == g_tune.end()) return false;
+  *rsel = (int)it->second[0];
+  *occ = (int)it->second[1];
+  *ms = it->second[2];
+  return true;
+}
+
+void tune_store(const std::string& key, int rsel, int occ, double ms) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune[key] = {(double)rsel, (double)occ, ms};
+  const char* path = std::getenv("CQ_TUNE_CACHE");
+  if (path && *path) {
+    if (FILE* f = fopen(path, "a")) {
+      fprintf(f, "{\"key\": \"%s\", \"gather_rows\": %d, \"occ\": %d, \"ms\": %.6f}\n", key.c_str(), kGatherRows[rsel], occ, ms);
+      fclose(f);
+    }
+  }
+}
+
 }  // namespace
 
 extern "C" {
@@ -579,6 +716,8 @@ cq_status cq_context_create(int device, void* hip_stream, cq_context** out) {
   set_big_lds(reinterpret_cast<const void*>(k_groups<ScoreVis, uint32_t>), gl);
   set_big_lds(reinterpret_cast<const void*>(k_groups<CmpVis, uint16_t>), gl);
   set_big_lds(reinterpret_cast<const void*>(k_groups<CmpVis, uint32_t>), gl);
+  set_big_lds(reinterpret_cast<const void*>(k_b_node), 2 * PRIV_MAX * 4);
+  set_big_lds(reinterpret_cast<const void*>(k_b_groups), gl);
   *out = ctx;
   return CQ_OK;
 }
@@ -746,5 +885,277 @@ cq_status cq_compare_partitions(cq_context* ctx, int32_t n, const int32_t* d_lab
   if (st != CQ_OK) return st;
   return map_flags(ctx, h_out->device_flags);
 }
+
+// ---- batched scoring ---------------------------------------------------------
+
+cq_status cq_batch_plan_create(cq_context* ctx, const cq_batch_task* tasks, int32_t num_tasks, uint32_t flags,
+                               cq_batch_plan** out) {
+  if (!ctx) return CQ_E_INVALID_ARG;
+  ctx->err[0] = 0;
+  if (!out || !tasks || num_tasks < 1) return fail(ctx, CQ_E_INVALID_ARG, "null tasks or num_tasks < 1");
+  *out = nullptr;
+  if (flags & ~(CQ_BATCH_AUTOTUNE | CQ_BATCH_NO_GRAPH)) return fail(ctx, CQ_E_INVALID_ARG, "unknown flag bits");
+  for (int i = 0; i < num_tasks; ++i) {
+    const cq_batch_task& t = tasks[i];
+    if (!t.graph || !t.d_labels) return fail(ctx, CQ_E_INVALID_ARG, "task %d: null graph or labels", i);
+    if (t.num_labels < 1 || t.num_labels > BATCH_MAX_L)
+      return fail(ctx, CQ_E_INVALID_ARG, "task %d: num_labels must be in [1, %lld] for batching", i, (long long)BATCH_MAX_L);
+    if (t.graph->nnz == 0) return fail(ctx, CQ_E_NO_EDGES, "task %d: graph has no edges", i);
+  }
+  cq_batch_plan* p = new (std::nothrow) cq_batch_plan();
+  if (!p) return fail(ctx, CQ_E_DEVICE, "out of host memory");
+  p->ctx = ctx;
+  p->flags = flags;
+  p->tasks.assign(tasks, tasks + num_tasks);
+  // workspace: one score layout per task, back to back
+  Carve c;
+  for (const auto& t : p->tasks) {
+    const ScoreLayout lay = score_layout(t.graph->n, t.graph->nnz, t.num_labels);
+    p->ws_off.push_back(c.take(lay.total));
+    p->maxL = std::max(p->maxL, (int)t.num_labels);
+  }
+  p->ws_total = c.off;
+  // groups: partitions of one graph, up to BATCH_FUSE per group, in task order
+  std::map<const cq_graph*, int> open;
+  for (int i = 0; i < num_tasks; ++i) {
+    auto it = open.find(p->tasks[i].graph);
+    if (it == open.end() || p->group_np[it->second] == BATCH_FUSE) {
+      p->groups.push_back({-1, -1, -1, -1});
+      p->group_np.push_back(0);
+      open[p->tasks[i].graph] = (int)p->groups.size() - 1;
+      it = open.find(p->tasks[i].graph);
+    }
+    p->groups[it->second][p->group_np[it->second]++] = i;
+  }
+  if (hipStreamCreateWithFlags(&p->stream, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&p->ev_in, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&p->ev_out, hipEventDisableTiming) != hipSuccess ||
+      hipHostMalloc(&p->pinned, sizeof(cq_score_result) * (size_t)num_tasks, hipHostMallocDefault) != hipSuccess) {
+    delete p;
+    return fail(ctx, CQ_E_DEVICE, "creating batch stream/events");
+  }
+  *out = p;
+  return CQ_OK;
+}
+
+size_t cq_batch_workspace_size(const cq_batch_plan* p) { return p ? p->ws_total : 0; }
+
+cq_status cq_batch_bind(cq_batch_plan* p, void* d_ws, size_t ws_bytes, cq_score_result* d_results) {
+  if (!p) return CQ_E_INVALID_ARG;
+  cq_context* ctx = p->ctx;
+  ctx->err[0] = 0;
+  if (!d_ws || ws_bytes < p->ws_total)
+    return fail(ctx, CQ_E_WORKSPACE, "workspace %zu bytes, need %zu", ws_bytes, p->ws_total);
+  if (!d_results) return fail(ctx, CQ_E_INVALID_ARG, "null result array");
+  if (p->exec) { (void)hipGraphExecDestroy(p->exec); p->exec = nullptr; }
+  if (p->graph) { (void)hipGraphDestroy(p->graph); p->graph = nullptr; }
+  if (p->d_tab) { (void)hipFree(p->d_tab); p->d_tab = nullptr; }
+  p->bound = false;
+  const int T = (int)p->tasks.size();
+  const int ng = (int)p->groups.size();
+  // host tables
+  std::vector<TaskDev> td(T);
+  std::vector<u32> Wpre(T + 1, 0), Lpre(T + 1, 0), Gpre(T + 1, 0);
+  for (int t = 0; t < T; ++t) {
+    const cq_batch_task& bt = p->tasks[t];
+    const cq_graph* g = bt.graph;
+    const ScoreLayout lay = score_layout(g->n, g->nnz, bt.num_labels);
+    char* base = static_cast<char*>(d_ws) + p->ws_off[t];
+    TaskDev& d = td[t];
+    d.labels = bt.d_labels;
+    d.perm = g->perm;
+    d.rp = g->rp;
+    d.col = g->col;
+    d.nnz = g->nnz;
+    d.n = g->n;
+    d.L = bt.num_labels;
+    d.chunk = lay.chunk;
+    d.W = lay.W;
+    d.G = lay.G;
+    d.pad = 0;
+    d.ctl = reinterpret_cast<Ctl*>(base + lay.ctl);
+    d.N = reinterpret_cast<u32*>(base + lay.N);
+    d.D = reinterpret_cast<u32*>(base + lay.D);
+    d.start = reinterpret_cast<u32*>(base + lay.start);
+    d.order = reinterpret_cast<u32*>(base + lay.order);
+    d.I = reinterpret_cast<u32*>(base + lay.I);
+    d.NP = reinterpret_cast<u32*>(base + lay.NP);
+    d.PEN = reinterpret_cast<u64*>(base + lay.PEN);
+    d.loc = reinterpret_cast<u32*>(base + lay.loc);
+    d.HN = reinterpret_cast<u32*>(base + lay.HN);
+    d.HD = reinterpret_cast<u32*>(base + lay.HD);
+    d.labx = reinterpret_cast<uint16_t*>(base + lay.labx);
+    d.CB = reinterpret_cast<uint16_t*>(base + lay.CB);
+    d.parts = reinterpret_cast<ScorePart*>(base + lay.parts);
+    d.out = reinterpret_cast<ScoreResultDev*>(d_results + t);
+    Wpre[t + 1] = Wpre[t] + (u32)lay.W;
+    Lpre[t + 1] = Lpre[t] + (u32)bt.num_labels;
+    Gpre[t + 1] = Gpre[t] + (u32)lay.G;
+  }
+  std::vector<GroupDev> gd(ng);
+  std::vector<u32> RB[3];
+  for (int r = 0; r < 3; ++r) RB[r].assign(ng + 1, 0);
+  for (int k = 0; k < ng; ++k) {
+    const cq_graph* g = p->tasks[p->groups[k][0]].graph;
+    gd[k].rp = g->rp;
+    gd[k].col = g->col;
+    gd[k].n = g->n;
+    gd[k].np = p->group_np[k];
+    for (int i = 0; i < BATCH_FUSE; ++i) gd[k].task[i] = p->groups[k][i];
+    for (int r = 0; r < 3; ++r) RB[r][k + 1] = RB[r][k] + (u32)((g->n + kGatherRows[r] - 1) / kGatherRows[r]);
+  }
+  // one device allocation for all tables
+  Carve c;
+  const size_t o_td = c.take(sizeof(TaskDev) * T), o_gd = c.take(sizeof(GroupDev) * ng);
+  const size_t o_W = c.take(4 * (T + 1)), o_L = c.take(4 * (T + 1)), o_G = c.take(4 * (T + 1)), o_K = c.take(4 * (T + 1));
+  const size_t o_tk = c.take(4);
+  size_t o_RB[3];
+  for (int r = 0; r < 3; ++r) o_RB[r] = c.take(4 * (ng + 1));
+  if (hipMalloc(&p->d_tab, c.off) != hipSuccess) return fail(ctx, CQ_E_DEVICE, "allocating batch tables");
+  p->tab_bytes = c.off;
+  char* b = static_cast<char*>(p->d_tab);
+  p->td = b + o_td;
+  p->gd = b + o_gd;
+  p->Wpre = reinterpret_cast<u32*>(b + o_W);
+  p->Lpre = reinterpret_cast<u32*>(b + o_L);
+  p->Gpre = reinterpret_cast<u32*>(b + o_G);
+  p->Kpre = reinterpret_cast<u32*>(b + o_K);
+  p->ticket = reinterpret_cast<u32*>(b + o_tk);
+  for (int r = 0; r < 3; ++r) {
+    p->RBpre[r] = reinterpret_cast<u32*>(b + o_RB[r]);
+    p->RBsum[r] = RB[r][ng];
+  }
+  p->Wsum = Wpre[T];
+  p->Lsum = Lpre[T];
+  p->Gsum = Gpre[T];
+  hipStream_t s = p->stream;
+  hipError_t e = hipMemcpyAsync(p->td, td.data(), sizeof(TaskDev) * T, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(p->gd, gd.data(), sizeof(GroupDev) * ng, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(p->Wpre, Wpre.data(), 4 * (T + 1), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(p->Lpre, Lpre.data(), 4 * (T + 1), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(p->Gpre, Gpre.data(), 4 * (T + 1), hipMemcpyHostToDevice, s);
+  for (int r = 0; r < 3 && e == hipSuccess; ++r)
+    e = hipMemcpyAsync(p->RBpre[r], RB[r].data(), 4 * (ng + 1), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return fail(ctx, CQ_E_DEVICE, "uploading batch tables: %s", hipGetErrorString(e));
+  p->ws = d_ws;
+  p->d_results = d_results;
+
+  // choose the tiling: cached choice, or time every candidate on this batch
+  const int maxocc = batch_max_occ(p);
+  p->rsel = 1;
+  p->occ = maxocc;
+  p->tuned_ms = 0.0;
+  p->from_cache = 0;
+  if (p->flags & CQ_BATCH_AUTOTUNE) {
+    const std::string key = batch_key(p);
+    int rs = 1, oc = maxocc;
+    double ms = 0.0;
+    if (tune_lookup(key, &rs, &oc, &ms) && oc <= maxocc) {
+      p->rsel = rs;
+      p->occ = oc;
+      p->tuned_ms = ms;
+      p->from_cache = 1;
+    } else {
+      hipEvent_t a, z;
+      (void)hipEventCreate(&a);
+      (void)hipEventCreate(&z);
+      double best = 1e30;
+      std::vector<int> occs = {1, 2, maxocc};
+      for (int r = 0; r < 3; ++r) {
+        for (int oc2 : occs) {
+          if (oc2 > maxocc) continue;
+          batch_launch(p, s, r, oc2);  // warm
+          (void)hipEventRecord(a, s);
+          batch_launch(p, s, r, oc2);
+          (void)hipEventRecord(z, s);
+          (void)hipEventSynchronize(z);
+          float t = 0.f;
+          (void)hipEventElapsedTime(&t, a, z);
+          if (t < best) {
+            best = t;
+            p->rsel = r;
+            p->occ = oc2;
+          }
+        }
+      }
+      (void)hipEventDestroy(a);
+      (void)hipEventDestroy(z);
+      p->tuned_ms = best;
+      tune_store(key, p->rsel, p->occ, best);
+    }
+  }
+  e = hipGetLastError();
+  if (e != hipSuccess) return fail(ctx, CQ_E_DEVICE, "batch tuning: %s", hipGetErrorString(e));
+  p->graph_nodes = 0;
+  if (!(p->flags & CQ_BATCH_NO_GRAPH)) {
+    e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+      batch_launch(p, s, p->rsel, p->occ);
+      e = hipStreamEndCapture(s, &p->graph);
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) return fail(ctx, CQ_E_DEVICE, "capturing the batch graph: %s", hipGetErrorString(e));
+    size_t nn = 0;
+    if (hipGraphGetNodes(p->graph, nullptr, &nn) == hipSuccess) p->graph_nodes = (int)nn;
+  }
+  p->bound = true;
+  return CQ_OK;
+}
+
+cq_status cq_batch_run(cq_batch_plan* p) {
+  if (!p) return CQ_E_INVALID_ARG;
+  cq_context* ctx = p->ctx;
+  if (!p->bound) return fail(ctx, CQ_E_INVALID_ARG, "batch plan is not bound");
+  hipError_t e = hipEventRecord(p->ev_in, ctx->stream);
+  if (e == hipSuccess) e = hipStreamWaitEvent(p->stream, p->ev_in, 0);
+  if (e == hipSuccess) {
+    if (p->exec) e = hipGraphLaunch(p->exec, p->stream);
+    else {
+      batch_launch(p, p->stream, p->rsel, p->occ);
+      e = hipGetLastError();
+    }
+  }
+  if (e == hipSuccess) e = hipEventRecord(p->ev_out, p->stream);
+  if (e == hipSuccess) e = hipStreamWaitEvent(ctx->stream, p->ev_out, 0);
+  if (e != hipSuccess) return fail(ctx, CQ_E_DEVICE, "batch run: %s", hipGetErrorString(e));
+  return CQ_OK;
+}
+
+cq_status cq_batch_run_sync(cq_batch_plan* p, cq_score_result* h_results) {
+  if (!p) return CQ_E_INVALID_ARG;
+  cq_context* ctx = p->ctx;
+  if (!h_results) return fail(ctx, CQ_E_INVALID_ARG, "null host result array");
+  cq_status st = cq_batch_run(p);
+  if (st != CQ_OK) return st;
+  const size_t bytes = sizeof(cq_score_result) * p->tasks.size();
+  hipError_t e = hipMemcpyAsync(p->pinned, p->d_results, bytes, hipMemcpyDeviceToHost, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) return fail(ctx, CQ_E_DEVICE, "batch results: %s", hipGetErrorString(e));
+  std::memcpy(h_results, p->pinned, bytes);
+  for (size_t t = 0; t < p->tasks.size(); ++t) {
+    if (h_results[t].device_flags) {
+      cq_status fs = map_flags(ctx, h_results[t].device_flags);
+      char msg[64];
+      snprintf(msg, sizeof(msg), " (task %zu)", t);
+      strncat(ctx->err, msg, sizeof(ctx->err) - strlen(ctx->err) - 1);
+      return fs;
+    }
+  }
+  return CQ_OK;
+}
+
+cq_status cq_batch_get_tuning(const cq_batch_plan* p, cq_batch_tuning* out) {
+  if (!p || !out) return CQ_E_INVALID_ARG;
+  out->gather_rows = kGatherRows[p->rsel];
+  out->group_blocks_per_cu = p->occ;
+  out->tuned_ms = p->tuned_ms;
+  out->from_cache = p->from_cache;
+  out->graph_nodes = p->graph_nodes;
+  out->num_groups = (int32_t)p->groups.size();
+  return CQ_OK;
+}
+
+void cq_batch_plan_destroy(cq_batch_plan* p) { delete p; }
 
 }  // extern "C"
