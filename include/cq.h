@@ -293,6 +293,62 @@ cq_status cq_compare_partitions_async(cq_context* ctx, int32_t n, const int32_t*
                                       int32_t num_labels_b, void* d_ws, size_t ws_bytes,
                                       cq_compare_result* d_out, const cq_cell_table* cells);
 
+/* ---- serving (continuous batching) ----------------------------------------- */
+
+/* A server keeps graphs resident (registered cq_graph handles), takes scoring and
+ * comparison requests whose labels are in HOST memory, and runs them on the GPU as
+ * soon as a slot and device memory are free, while other requests are still running:
+ *   - each slot is one HIP stream, so launches of different slots overlap on the GPU;
+ *   - a request is admitted when its footprint (labels + workspace + result) fits in
+ *     the server's device arena (memory_budget bytes, allocated at creation);
+ *   - small scoring requests (graph with <= small_nnz stored entries, num_labels <=
+ *     16384) that are waiting together are grouped, up to max_batch, into one batched
+ *     launch (the cq_batch kernels);
+ *   - requests are otherwise served in arrival order.
+ * Latency is measured from submit to the result being in host memory.  A request's
+ * result is the same as that of the synchronous call on the same inputs. */
+typedef struct cq_server cq_server;
+
+typedef struct {
+  int32_t num_slots;      /* launches in flight at once, >= 1 */
+  int32_t max_batch;      /* most small scoring requests in one launch, >= 1 */
+  int64_t memory_budget;  /* device bytes for request labels, workspaces and results */
+  int64_t small_nnz;      /* graphs with at most this many stored entries are "small" */
+} cq_server_config;
+
+typedef struct {
+  int64_t submitted, completed, failed, rejected;
+  int64_t launches;          /* device launches (a grouped launch counts once) */
+  int64_t grouped_requests;  /* requests that ran inside grouped launches */
+  double p50_ms, p99_ms, mean_ms, max_ms;  /* submit -> result in host memory */
+  double busy_s;             /* wall time with at least one launch in flight */
+  int64_t peak_bytes;        /* most arena bytes admitted at once */
+} cq_server_stats;
+
+/* Create a server on ctx's device (it uses its own streams).  Allocates the arena,
+ * pinned result buffers and starts one worker thread. */
+cq_status cq_server_create(cq_context* ctx, const cq_server_config* cfg, cq_server** out);
+/* Submit a scoring request.  h_labels: HOST int32[n] of graph g; it must stay valid
+ * and unchanged until the request has been waited for (pinned memory transfers
+ * fastest).  *ticket identifies the request.  CQ_E_BUSY: the request can never fit in
+ * the arena. */
+cq_status cq_server_submit_score(cq_server* srv, const cq_graph* g, const int32_t* h_labels, int32_t num_labels,
+                                 uint64_t* ticket);
+/* Submit a comparison request (HOST label arrays of length n, same lifetime rule). */
+cq_status cq_server_submit_compare(cq_server* srv, int32_t n, const int32_t* h_labels_a, int32_t num_labels_a,
+                                   const int32_t* h_labels_b, int32_t num_labels_b, uint64_t* ticket);
+/* Wait up to timeout_ms (< 0: no limit) for a request, then release its ticket and
+ * return its status and result (score_out or compare_out by kind; either may be NULL)
+ * and its latency.  Returns CQ_E_BUSY if the request is not finished in time (the
+ * ticket stays valid), CQ_E_INVALID_ARG for an unknown ticket. */
+cq_status cq_server_wait(cq_server* srv, uint64_t ticket, double timeout_ms, cq_status* request_status,
+                         cq_score_result* score_out, cq_compare_result* compare_out, double* latency_ms);
+cq_status cq_server_get_stats(cq_server* srv, cq_server_stats* out);
+cq_status cq_server_reset_stats(cq_server* srv);
+/* Stop: waiting requests are cancelled (their status becomes CQ_E_CANCELLED), launches
+ * in flight finish, then everything is freed.  Tickets not yet waited for are lost. */
+void cq_server_destroy(cq_server* srv);
+
 #ifdef __cplusplus
 }
 #endif

@@ -81,6 +81,15 @@ class BatchTuning(ctypes.Structure):
                 ("from_cache", _I32), ("graph_nodes", _I32), ("num_groups", _I32)]
 
 
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("num_slots", _I32), ("max_batch", _I32), ("memory_budget", _I64), ("small_nnz", _I64)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [(k, _I64) for k in ("submitted", "completed", "failed", "rejected", "launches", "grouped_requests")] + [
+        (k, ctypes.c_double) for k in ("p50_ms", "p99_ms", "mean_ms", "max_ms", "busy_s")] + [("peak_bytes", _I64)]
+
+
 CQ_BATCH_AUTOTUNE = 1
 CQ_BATCH_NO_GRAPH = 2
 
@@ -119,6 +128,14 @@ def _load():
         "cq_batch_run_sync": (_I32, [_P, ctypes.POINTER(ScoreResult)]),
         "cq_batch_get_tuning": (_I32, [_P, ctypes.POINTER(BatchTuning)]),
         "cq_batch_plan_destroy": (None, [_P]),
+        "cq_server_create": (_I32, [_P, ctypes.POINTER(ServerConfig), ctypes.POINTER(_P)]),
+        "cq_server_submit_score": (_I32, [_P, _P, _P, _I32, ctypes.POINTER(ctypes.c_uint64)]),
+        "cq_server_submit_compare": (_I32, [_P, _I32, _P, _I32, _P, _I32, ctypes.POINTER(ctypes.c_uint64)]),
+        "cq_server_wait": (_I32, [_P, ctypes.c_uint64, ctypes.c_double, ctypes.POINTER(_I32), ctypes.POINTER(ScoreResult),
+                                  ctypes.POINTER(CompareResult), ctypes.POINTER(ctypes.c_double)]),
+        "cq_server_get_stats": (_I32, [_P, ctypes.POINTER(ServerStats)]),
+        "cq_server_reset_stats": (_I32, [_P]),
+        "cq_server_destroy": (None, [_P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -286,6 +303,53 @@ def cq_batch_get_tuning(plan: int) -> dict:
 
 def cq_batch_plan_destroy(plan: int) -> None:
     _lib.cq_batch_plan_destroy(plan)
+
+
+def cq_server_create(ctx: int, num_slots: int, max_batch: int, memory_budget: int, small_nnz: int) -> int:
+    cfg = ServerConfig(num_slots, max_batch, memory_budget, small_nnz)
+    out = _P()
+    _check(ctx, _lib.cq_server_create(ctx, ctypes.byref(cfg), ctypes.byref(out)))
+    return out.value
+
+
+def cq_server_submit_score(ctx: int, srv: int, g: int, h_labels: int, num_labels: int) -> int:
+    t = ctypes.c_uint64()
+    _check(ctx, _lib.cq_server_submit_score(srv, g, h_labels, num_labels, ctypes.byref(t)))
+    return t.value
+
+
+def cq_server_submit_compare(ctx: int, srv: int, n: int, h_a: int, La: int, h_b: int, Lb: int) -> int:
+    t = ctypes.c_uint64()
+    _check(ctx, _lib.cq_server_submit_compare(srv, n, h_a, La, h_b, Lb, ctypes.byref(t)))
+    return t.value
+
+
+def cq_server_wait(ctx: int, srv: int, ticket: int, timeout_ms: float = -1.0):
+    """Returns (call status, request status, score dict | None, compare dict | None, latency ms)."""
+    rs = _I32()
+    sr = ScoreResult()
+    cr = CompareResult()
+    lat = ctypes.c_double()
+    st = _lib.cq_server_wait(srv, ticket, timeout_ms, ctypes.byref(rs), ctypes.byref(sr), ctypes.byref(cr), ctypes.byref(lat))
+    if st not in (CQ_OK, CQ_E_BUSY):
+        raise CQError(st, cq_context_last_error(ctx))
+    return st, rs.value, as_dict(sr), as_dict(cr), lat.value
+
+
+def cq_server_get_stats(srv: int) -> dict:
+    s = ServerStats()
+    st = _lib.cq_server_get_stats(srv, ctypes.byref(s))
+    if st != CQ_OK:
+        raise CQError(st)
+    return {k: getattr(s, k) for k, _ in ServerStats._fields_}
+
+
+def cq_server_reset_stats(srv: int) -> None:
+    _lib.cq_server_reset_stats(srv)
+
+
+def cq_server_destroy(srv: int) -> None:
+    _lib.cq_server_destroy(srv)
 
 
 # ---- torch conveniences -------------------------------------------------------
@@ -467,6 +531,57 @@ class Batch:
         if self.handle:
             cq_batch_plan_destroy(self.handle)
             self.handle = 0
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Continuous-batching request server over resident graphs (labels in host memory)."""
+
+    def __init__(self, ctx: Context, *, num_slots: int = 4, max_batch: int = 16, memory_budget: int = 8 << 30,
+                 small_nnz: int = 4_000_000):
+        self.ctx = ctx
+        self.handle = cq_server_create(ctx.handle, num_slots, max_batch, memory_budget, small_nnz)
+        self._keep = {}
+
+    def submit_score(self, graph: Graph, h_labels, num_labels: int) -> int:
+        """h_labels: host int32 tensor (pinned is fastest); kept alive until waited for."""
+        torch = _torch()
+        if not isinstance(h_labels, torch.Tensor) or h_labels.device.type != "cpu" or h_labels.dtype != torch.int32 \
+                or not h_labels.is_contiguous() or h_labels.numel() != graph.n:
+            raise TypeError("h_labels must be a contiguous int32 CPU tensor with one entry per node")
+        t = cq_server_submit_score(self.ctx.handle, self.handle, graph.handle, h_labels.data_ptr(), num_labels)
+        self._keep[t] = (h_labels,)
+        return t
+
+    def submit_compare(self, h_a, num_labels_a: int, h_b, num_labels_b: int) -> int:
+        t = cq_server_submit_compare(self.ctx.handle, self.handle, h_a.numel(), h_a.data_ptr(), num_labels_a,
+                                     h_b.data_ptr(), num_labels_b)
+        self._keep[t] = (h_a, h_b)
+        return t
+
+    def wait(self, ticket: int, timeout_ms: float = -1.0):
+        st, rs, sres, cres, lat = cq_server_wait(self.ctx.handle, self.handle, ticket, timeout_ms)
+        if st == CQ_E_BUSY:
+            return None
+        self._keep.pop(ticket, None)
+        return {"status": rs, "score": sres, "compare": cres, "latency_ms": lat}
+
+    def stats(self) -> dict:
+        return cq_server_get_stats(self.handle)
+
+    def reset_stats(self) -> None:
+        cq_server_reset_stats(self.handle)
+
+    def close(self):
+        if self.handle:
+            cq_server_destroy(self.handle)
+            self.handle = 0
+            self._keep.clear()
 
     def __del__(self):
         try:

@@ -4,14 +4,18 @@
 
 #include <algorithm>
 #include <array>
+#include <chrono>
+#include <condition_variable>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <deque>
 #include <map>
 #include <mutex>
 #include <new>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "cq.h"
@@ -599,6 +603,141 @@ void batch_launch(cq_batch_plan* p, hipStream_t s, int rsel, int occ) {
   k_b_final2<<<grid_for(T, 64, 1u << 20), 64, 0, s>>>(td, T);
 }
 
+
+struct BatchTabLayout {
+  size_t td, gd, W, L, G, K, tk, RB[3], total;
+};
+
+BatchTabLayout batch_tab_layout(int T, int ng) {
+  BatchTabLayout l{};
+  Carve c;
+  l.td = c.take(sizeof(TaskDev) * T);
+  l.gd = c.take(sizeof(GroupDev) * ng);
+  l.W = c.take(4 * (T + 1));
+  l.L = c.take(4 * (T + 1));
+  l.G = c.take(4 * (T + 1));
+  l.K = c.take(4 * (T + 1));
+  l.tk = c.take(4);
+  for (int r = 0; r < 3; ++r) l.RB[r] = c.take(4 * (ng + 1));
+  l.total = c.off;
+  return l;
+}
+
+// Writes the device tables of plan p (task descriptors, group descriptors, block
+// prefix tables) into the host blob hb, laid out as they will sit at d_tab, and points
+// the plan at d_tab.  The caller copies hb to d_tab before the plan runs.
+void batch_fill_tables(cq_batch_plan* p, void* d_ws, cq_score_result* d_results, char* hb, void* d_tab) {
+  const int T = (int)p->tasks.size();
+  const int ng = (int)p->groups.size();
+  const BatchTabLayout tl = batch_tab_layout(T, ng);
+  TaskDev* td = reinterpret_cast<TaskDev*>(hb + tl.td);
+  GroupDev* gd = reinterpret_cast<GroupDev*>(hb + tl.gd);
+  u32* Wpre = reinterpret_cast<u32*>(hb + tl.W);
+  u32* Lpre = reinterpret_cast<u32*>(hb + tl.L);
+  u32* Gpre = reinterpret_cast<u32*>(hb + tl.G);
+  u32* Kpre = reinterpret_cast<u32*>(hb + tl.K);
+  Wpre[0] = Lpre[0] = Gpre[0] = 0;
+  for (int t = 0; t <= T; ++t) Kpre[t] = 0;
+  *reinterpret_cast<u32*>(hb + tl.tk) = 0;
+  for (int t = 0; t < T; ++t) {
+    const cq_batch_task& bt = p->tasks[t];
+    const cq_graph* g = bt.graph;
+    const ScoreLayout lay = score_layout(g->n, g->nnz, bt.num_labels);
+    char* base = static_cast<char*>(d_ws) + p->ws_off[t];
+    TaskDev d;
+    std::memset(&d, 0, sizeof(d));
+    d.labels = bt.d_labels;
+    d.perm = g->perm;
+    d.rp = g->rp;
+    d.col = g->col;
+    d.nnz = g->nnz;
+    d.n = g->n;
+    d.L = bt.num_labels;
+    d.chunk = lay.chunk;
+    d.W = lay.W;
+    d.G = lay.G;
+    d.ctl = reinterpret_cast<Ctl*>(base + lay.ctl);
+    d.N = reinterpret_cast<u32*>(base + lay.N);
+    d.D = reinterpret_cast<u32*>(base + lay.D);
+    d.start = reinterpret_cast<u32*>(base + lay.start);
+    d.order = reinterpret_cast<u32*>(base + lay.order);
+    d.I = reinterpret_cast<u32*>(base + lay.I);
+    d.NP = reinterpret_cast<u32*>(base + lay.NP);
+    d.PEN = reinterpret_cast<u64*>(base + lay.PEN);
+    d.loc = reinterpret_cast<u32*>(base + lay.loc);
+    d.HN = reinterpret_cast<u32*>(base + lay.HN);
+    d.HD = reinterpret_cast<u32*>(base + lay.HD);
+    d.labx = reinterpret_cast<uint16_t*>(base + lay.labx);
+    d.CB = reinterpret_cast<uint16_t*>(base + lay.CB);
+    d.parts = reinterpret_cast<ScorePart*>(base + lay.parts);
+    d.out = reinterpret_cast<ScoreResultDev*>(d_results + t);
+    std::memcpy(&td[t], &d, sizeof(d));
+    Wpre[t + 1] = Wpre[t] + (u32)lay.W;
+    Lpre[t + 1] = Lpre[t] + (u32)bt.num_labels;
+    Gpre[t + 1] = Gpre[t] + (u32)lay.G;
+  }
+  u32* RB[3];
+  for (int r = 0; r < 3; ++r) {
+    RB[r] = reinterpret_cast<u32*>(hb + tl.RB[r]);
+    RB[r][0] = 0;
+  }
+  for (int k = 0; k < ng; ++k) {
+    const cq_graph* g = p->tasks[p->groups[k][0]].graph;
+    GroupDev gdv;
+    std::memset(&gdv, 0, sizeof(gdv));
+    gdv.rp = g->rp;
+    gdv.col = g->col;
+    gdv.n = g->n;
+    gdv.np = p->group_np[k];
+    for (int i = 0; i < BATCH_FUSE; ++i) gdv.task[i] = p->groups[k][i];
+    std::memcpy(&gd[k], &gdv, sizeof(gdv));
+    for (int r = 0; r < 3; ++r) RB[r][k + 1] = RB[r][k] + (u32)((g->n + kGatherRows[r] - 1) / kGatherRows[r]);
+  }
+  char* b = static_cast<char*>(d_tab);
+  p->td = b + tl.td;
+  p->gd = b + tl.gd;
+  p->Wpre = reinterpret_cast<u32*>(b + tl.W);
+  p->Lpre = reinterpret_cast<u32*>(b + tl.L);
+  p->Gpre = reinterpret_cast<u32*>(b + tl.G);
+  p->Kpre = reinterpret_cast<u32*>(b + tl.K);
+  p->ticket = reinterpret_cast<u32*>(b + tl.tk);
+  for (int r = 0; r < 3; ++r) {
+    p->RBpre[r] = reinterpret_cast<u32*>(b + tl.RB[r]);
+    p->RBsum[r] = RB[r][ng];
+  }
+  p->Wsum = Wpre[T];
+  p->Lsum = Lpre[T];
+  p->Gsum = Gpre[T];
+  p->ws = d_ws;
+  p->d_results = d_results;
+}
+
+// Lays out a plan's per-task workspace and its groups (tasks already in p->tasks).
+void batch_layout(cq_batch_plan* p) {
+  p->ws_off.clear();
+  p->groups.clear();
+  p->group_np.clear();
+  p->maxL = 1;
+  Carve c;
+  for (const auto& t : p->tasks) {
+    const ScoreLayout lay = score_layout(t.graph->n, t.graph->nnz, t.num_labels);
+    p->ws_off.push_back(c.take(lay.total));
+    p->maxL = std::max(p->maxL, (int)t.num_labels);
+  }
+  p->ws_total = c.off;
+  std::map<const cq_graph*, int> open;
+  for (int i = 0; i < (int)p->tasks.size(); ++i) {
+    auto it = open.find(p->tasks[i].graph);
+    if (it == open.end() || p->group_np[it->second] == BATCH_FUSE) {
+      p->groups.push_back({-1, -1, -1, -1});
+      p->group_np.push_back(0);
+      open[p->tasks[i].graph] = (int)p->groups.size() - 1;
+      it = open.find(p->tasks[i].graph);
+    }
+    p->groups[it->second][p->group_np[it->second]++] = i;
+  }
+}
+
 int batch_max_occ(cq_batch_plan* p) {
   const u32 lds_words = std::max<u32>(((u32)p->maxL + 3u) & ~3u, 128u);
   int nb = 0;
@@ -660,6 +799,283 @@ void tune_store(const std::string& key, int rsel, int occ, double ms) {
       fclose(f);
     }
   }
+}
+
+
+// ---- serving -------------------------------------------------------------------
+
+using SrvClock = std::chrono::steady_clock;
+
+struct SrvReq {
+  uint64_t id = 0;
+  int kind = 0;  // 0 score, 1 compare
+  const cq_graph* g = nullptr;
+  int32_t n = 0, L = 0, La = 0, Lb = 0;
+  const int32_t* ha = nullptr;
+  const int32_t* hb = nullptr;
+  size_t ws_bytes = 0, foot = 0;
+  bool small = false;
+  SrvClock::time_point t_submit, t_done;
+  cq_status status = CQ_OK;
+  cq_score_result sres{};
+  cq_compare_result cres{};
+  bool done = false;
+};
+
+struct SrvSlot {
+  cq_context* ctx = nullptr;  // context bound to this slot's stream
+  hipStream_t stream = nullptr;
+  hipEvent_t ev = nullptr;
+  char* pinned = nullptr;     // results, then the batch table blob
+  size_t res_bytes = 0;
+  void* d_tab = nullptr;
+  cq_batch_plan plan;         // reused host plan for grouped launches (no HIP graph)
+  bool busy = false;
+  bool grouped = false;
+  std::vector<SrvReq*> reqs;
+  size_t off = 0, len = 0;
+};
+
+constexpr size_t kAlign = 256;
+size_t aup(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
+
+cq_status status_of_flags(u32 f) {
+  if (f & F_LABEL) return CQ_E_LABEL_RANGE;
+  if (f & F_STACK) return CQ_E_DEVICE;
+  if (f & F_EXPORT) return CQ_E_CAPACITY;
+  return CQ_OK;
+}
+
+}  // namespace
+
+struct cq_server {
+  cq_context* ctx = nullptr;
+  cq_server_config cfg{};
+  char* arena = nullptr;
+  std::map<size_t, size_t> free_blocks;  // offset -> length
+  size_t in_use = 0, peak = 0;
+  std::vector<SrvSlot*> slots;
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::deque<SrvReq*> pending;
+  std::map<uint64_t, SrvReq*> reqs;
+  uint64_t next_id = 1;
+  bool stop = false;
+  std::thread worker;
+  std::vector<double> lat_ms;
+  int64_t submitted = 0, completed = 0, failed = 0, launches = 0, grouped = 0, rejected = 0;
+  int inflight = 0;
+  double busy_s = 0;
+  SrvClock::time_point busy_since;
+};
+
+namespace {
+
+bool arena_alloc(cq_server* s, size_t len, size_t* off) {
+  len = aup(len);
+  for (auto it = s->free_blocks.begin(); it != s->free_blocks.end(); ++it) {
+    if (it->second >= len) {
+      *off = it->first;
+      const size_t rest = it->second - len, noff = it->first + len;
+      s->free_blocks.erase(it);
+      if (rest) s->free_blocks[noff] = rest;
+      s->in_use += len;
+      s->peak = std::max(s->peak, s->in_use);
+      return true;
+    }
+  }
+  return false;
+}
+
+void arena_free(cq_server* s, size_t off, size_t len) {
+  len = aup(len);
+  s->in_use -= len;
+  auto it = s->free_blocks.emplace(off, len).first;
+  auto nx = std::next(it);
+  if (nx != s->free_blocks.end() && it->first + it->second == nx->first) {
+    it->second += nx->second;
+    s->free_blocks.erase(nx);
+  }
+  if (it != s->free_blocks.begin()) {
+    auto pv = std::prev(it);
+    if (pv->first + pv->second == it->first) {
+      pv->second += it->second;
+      s->free_blocks.erase(it);
+    }
+  }
+}
+
+size_t req_footprint(const SrvReq* r) {
+  if (r->kind == 0) return aup(4 * (size_t)r->n) + aup(r->ws_bytes) + aup(sizeof(cq_score_result));
+  return 2 * aup(4 * (size_t)r->n) + aup(r->ws_bytes) + aup(sizeof(cq_compare_result));
+}
+
+// Enqueue one admitted request (or a group of small scoring requests) on a slot.
+void srv_dispatch(cq_server* s, SrvSlot* sl) {
+  hipStream_t st = sl->stream;
+  char* region = s->arena + sl->off;
+  if (!sl->grouped) {
+    SrvReq* r = sl->reqs[0];
+    if (r->kind == 0) {
+      int32_t* d_lab = reinterpret_cast<int32_t*>(region);
+      char* d_ws = region + aup(4 * (size_t)r->n);
+      ScoreResultDev* d_res = reinterpret_cast<ScoreResultDev*>(d_ws + aup(r->ws_bytes));
+      (void)hipMemcpyAsync(d_lab, r->ha, 4 * (size_t)r->n, hipMemcpyHostToDevice, st);
+      r->status = score_enqueue(sl->ctx, r->g, d_lab, r->L, d_ws, r->ws_bytes, d_res, nullptr, nullptr, false);
+      (void)hipMemcpyAsync(sl->pinned, d_res, sizeof(cq_score_result), hipMemcpyDeviceToHost, st);
+    } else {
+      int32_t* d_a = reinterpret_cast<int32_t*>(region);
+      int32_t* d_b = reinterpret_cast<int32_t*>(region + aup(4 * (size_t)r->n));
+      char* d_ws = region + 2 * aup(4 * (size_t)r->n);
+      CmpResultDev* d_res = reinterpret_cast<CmpResultDev*>(d_ws + aup(r->ws_bytes));
+      (void)hipMemcpyAsync(d_a, r->ha, 4 * (size_t)r->n, hipMemcpyHostToDevice, st);
+      (void)hipMemcpyAsync(d_b, r->hb, 4 * (size_t)r->n, hipMemcpyHostToDevice, st);
+      r->status = compare_enqueue(sl->ctx, r->n, d_a, r->La, d_b, r->Lb, d_ws, r->ws_bytes, d_res, nullptr, false);
+      (void)hipMemcpyAsync(sl->pinned, d_res, sizeof(cq_compare_result), hipMemcpyDeviceToHost, st);
+    }
+  } else {
+    // labels of every request, then the batch workspace, then the results
+    cq_batch_plan* p = &sl->plan;
+    p->tasks.clear();
+    size_t o = 0;
+    for (SrvReq* r : sl->reqs) {
+      int32_t* d_lab = reinterpret_cast<int32_t*>(region + o);
+      (void)hipMemcpyAsync(d_lab, r->ha, 4 * (size_t)r->n, hipMemcpyHostToDevice, st);
+      p->tasks.push_back({r->g, d_lab, r->L});
+      o += aup(4 * (size_t)r->n);
+    }
+    batch_layout(p);
+    char* d_ws = region + o;
+    cq_score_result* d_res = reinterpret_cast<cq_score_result*>(d_ws + aup(p->ws_total));
+    const BatchTabLayout tl = batch_tab_layout((int)p->tasks.size(), (int)p->groups.size());
+    char* blob = sl->pinned + sl->res_bytes;
+    batch_fill_tables(p, d_ws, d_res, blob, sl->d_tab);
+    (void)hipMemcpyAsync(sl->d_tab, blob, tl.total, hipMemcpyHostToDevice, st);
+    batch_launch(p, st, 1, batch_max_occ(p));
+    (void)hipMemcpyAsync(sl->pinned, d_res, sizeof(cq_score_result) * p->tasks.size(), hipMemcpyDeviceToHost, st);
+  }
+  (void)hipEventRecord(sl->ev, st);
+}
+
+// Footprint of a group of small scoring requests run as one batched launch.
+size_t group_footprint(const std::vector<SrvReq*>& g) {
+  size_t lab = 0, ws = 0;
+  for (const SrvReq* r : g) {
+    lab += aup(4 * (size_t)r->n);
+    ws += aup(score_layout(r->g->n, r->g->nnz, r->L).total);
+  }
+  return lab + aup(ws) + aup(sizeof(cq_score_result) * g.size());
+}
+
+void srv_loop(cq_server* s) {
+  (void)hipSetDevice(s->ctx->device);
+  for (;;) {
+    bool progress = false;
+    // completions
+    for (SrvSlot* sl : s->slots) {
+      if (!sl->busy || hipEventQuery(sl->ev) != hipSuccess) continue;
+      const auto now = SrvClock::now();
+      std::lock_guard<std::mutex> lk(s->mu);
+      for (size_t i = 0; i < sl->reqs.size(); ++i) {
+        SrvReq* r = sl->reqs[i];
+        if (r->status == CQ_OK) {
+          if (r->kind == 0) {
+            std::memcpy(&r->sres, sl->pinned + i * sizeof(cq_score_result), sizeof(cq_score_result));
+            r->status = status_of_flags(r->sres.device_flags);
+          } else {
+            std::memcpy(&r->cres, sl->pinned, sizeof(cq_compare_result));
+            r->status = status_of_flags(r->cres.device_flags);
+          }
+        }
+        r->t_done = now;
+        r->done = true;
+        s->lat_ms.push_back(std::chrono::duration<double, std::milli>(now - r->t_submit).count());
+        if (r->status == CQ_OK) ++s->completed; else ++s->failed;
+      }
+      arena_free(s, sl->off, sl->len);
+      sl->busy = false;
+      sl->reqs.clear();
+      if (--s->inflight == 0) s->busy_s += std::chrono::duration<double>(now - s->busy_since).count();
+      progress = true;
+      s->cv_done.notify_all();
+    }
+    // admissions: fill free slots in arrival order
+    std::unique_lock<std::mutex> lk(s->mu);
+    for (;;) {
+      if (s->pending.empty()) break;
+      SrvSlot* sl = nullptr;
+      for (SrvSlot* c : s->slots)
+        if (!c->busy) { sl = c; break; }
+      if (!sl) break;
+      SrvReq* head = s->pending.front();
+      std::vector<SrvReq*> take = {head};
+      size_t off = 0, len = 0;
+      bool grouped = false;
+      if (head->small && s->cfg.max_batch > 1) {
+        for (size_t i = 1; i < s->pending.size() && (int)take.size() < s->cfg.max_batch; ++i)
+          if (s->pending[i]->small) take.push_back(s->pending[i]);
+        while (take.size() > 1) {
+          len = group_footprint(take);
+          if (arena_alloc(s, len, &off)) break;
+          take.pop_back();
+        }
+        grouped = take.size() > 1;
+      }
+      if (!grouped) {
+        len = req_footprint(head);
+        if (!arena_alloc(s, len, &off)) break;  // wait for memory (arrival order is kept)
+      }
+      for (SrvReq* r : take) s->pending.erase(std::find(s->pending.begin(), s->pending.end(), r));
+      sl->reqs = take;
+      sl->grouped = grouped;
+      sl->off = off;
+      sl->len = len;
+      sl->busy = true;
+      if (s->inflight++ == 0) s->busy_since = SrvClock::now();
+      ++s->launches;
+      if (grouped) s->grouped += (int64_t)take.size();
+      lk.unlock();
+      srv_dispatch(s, sl);
+      lk.lock();
+      progress = true;
+    }
+    if (s->stop && s->pending.empty() && s->inflight == 0) break;
+    if (!progress) {
+      if (s->inflight > 0) {
+        lk.unlock();
+        std::this_thread::yield();
+      } else {
+        s->cv_work.wait_for(lk, std::chrono::microseconds(200));
+      }
+    }
+  }
+}
+
+cq_status srv_submit(cq_server* s, SrvReq* r, uint64_t* ticket) {
+  r->foot = req_footprint(r);
+  if (r->foot > (size_t)s->cfg.memory_budget) {
+    const size_t need = r->foot;
+    delete r;
+    std::lock_guard<std::mutex> lk(s->mu);
+    ++s->rejected;
+    return fail(s->ctx, CQ_E_BUSY, "request needs %zu bytes, the server arena has %lld", need,
+                (long long)s->cfg.memory_budget);
+  }
+  r->t_submit = SrvClock::now();
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->stop) {
+      delete r;
+      return CQ_E_CANCELLED;
+    }
+    r->id = s->next_id++;
+    s->reqs[r->id] = r;
+    s->pending.push_back(r);
+    ++s->submitted;
+    *ticket = r->id;
+  }
+  s->cv_work.notify_one();
+  return CQ_OK;
 }
 
 }  // namespace
@@ -907,26 +1323,7 @@ cq_status cq_batch_plan_create(cq_context* ctx, const cq_batch_task* tasks, int3
   p->ctx = ctx;
   p->flags = flags;
   p->tasks.assign(tasks, tasks + num_tasks);
-  // workspace: one score layout per task, back to back
-  Carve c;
-  for (const auto& t : p->tasks) {
-    const ScoreLayout lay = score_layout(t.graph->n, t.graph->nnz, t.num_labels);
-    p->ws_off.push_back(c.take(lay.total));
-    p->maxL = std::max(p->maxL, (int)t.num_labels);
-  }
-  p->ws_total = c.off;
-  // groups: partitions of one graph, up to BATCH_FUSE per group, in task order
-  std::map<const cq_graph*, int> open;
-  for (int i = 0; i < num_tasks; ++i) {
-    auto it = open.find(p->tasks[i].graph);
-    if (it == open.end() || p->group_np[it->second] == BATCH_FUSE) {
-      p->groups.push_back({-1, -1, -1, -1});
-      p->group_np.push_back(0);
-      open[p->tasks[i].graph] = (int)p->groups.size() - 1;
-      it = open.find(p->tasks[i].graph);
-    }
-    p->groups[it->second][p->group_np[it->second]++] = i;
-  }
+  batch_layout(p);
   if (hipStreamCreateWithFlags(&p->stream, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&p->ev_in, hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&p->ev_out, hipEventDisableTiming) != hipSuccess ||
@@ -951,95 +1348,15 @@ cq_status cq_batch_bind(cq_batch_plan* p, void* d_ws, size_t ws_bytes, cq_score_
   if (p->graph) { (void)hipGraphDestroy(p->graph); p->graph = nullptr; }
   if (p->d_tab) { (void)hipFree(p->d_tab); p->d_tab = nullptr; }
   p->bound = false;
-  const int T = (int)p->tasks.size();
-  const int ng = (int)p->groups.size();
-  // host tables
-  std::vector<TaskDev> td(T);
-  std::vector<u32> Wpre(T + 1, 0), Lpre(T + 1, 0), Gpre(T + 1, 0);
-  for (int t = 0; t < T; ++t) {
-    const cq_batch_task& bt = p->tasks[t];
-    const cq_graph* g = bt.graph;
-    const ScoreLayout lay = score_layout(g->n, g->nnz, bt.num_labels);
-    char* base = static_cast<char*>(d_ws) + p->ws_off[t];
-    TaskDev& d = td[t];
-    d.labels = bt.d_labels;
-    d.perm = g->perm;
-    d.rp = g->rp;
-    d.col = g->col;
-    d.nnz = g->nnz;
-    d.n = g->n;
-    d.L = bt.num_labels;
-    d.chunk = lay.chunk;
-    d.W = lay.W;
-    d.G = lay.G;
-    d.pad = 0;
-    d.ctl = reinterpret_cast<Ctl*>(base + lay.ctl);
-    d.N = reinterpret_cast<u32*>(base + lay.N);
-    d.D = reinterpret_cast<u32*>(base + lay.D);
-    d.start = reinterpret_cast<u32*>(base + lay.start);
-    d.order = reinterpret_cast<u32*>(base + lay.order);
-    d.I = reinterpret_cast<u32*>(base + lay.I);
-    d.NP = reinterpret_cast<u32*>(base + lay.NP);
-    d.PEN = reinterpret_cast<u64*>(base + lay.PEN);
-    d.loc = reinterpret_cast<u32*>(base + lay.loc);
-    d.HN = reinterpret_cast<u32*>(base + lay.HN);
-    d.HD = reinterpret_cast<u32*>(base + lay.HD);
-    d.labx = reinterpret_cast<uint16_t*>(base + lay.labx);
-    d.CB = reinterpret_cast<uint16_t*>(base + lay.CB);
-    d.parts = reinterpret_cast<ScorePart*>(base + lay.parts);
-    d.out = reinterpret_cast<ScoreResultDev*>(d_results + t);
-    Wpre[t + 1] = Wpre[t] + (u32)lay.W;
-    Lpre[t + 1] = Lpre[t] + (u32)bt.num_labels;
-    Gpre[t + 1] = Gpre[t] + (u32)lay.G;
-  }
-  std::vector<GroupDev> gd(ng);
-  std::vector<u32> RB[3];
-  for (int r = 0; r < 3; ++r) RB[r].assign(ng + 1, 0);
-  for (int k = 0; k < ng; ++k) {
-    const cq_graph* g = p->tasks[p->groups[k][0]].graph;
-    gd[k].rp = g->rp;
-    gd[k].col = g->col;
-    gd[k].n = g->n;
-    gd[k].np = p->group_np[k];
-    for (int i = 0; i < BATCH_FUSE; ++i) gd[k].task[i] = p->groups[k][i];
-    for (int r = 0; r < 3; ++r) RB[r][k + 1] = RB[r][k] + (u32)((g->n + kGatherRows[r] - 1) / kGatherRows[r]);
-  }
-  // one device allocation for all tables
-  Carve c;
-  const size_t o_td = c.take(sizeof(TaskDev) * T), o_gd = c.take(sizeof(GroupDev) * ng);
-  const size_t o_W = c.take(4 * (T + 1)), o_L = c.take(4 * (T + 1)), o_G = c.take(4 * (T + 1)), o_K = c.take(4 * (T + 1));
-  const size_t o_tk = c.take(4);
-  size_t o_RB[3];
-  for (int r = 0; r < 3; ++r) o_RB[r] = c.take(4 * (ng + 1));
-  if (hipMalloc(&p->d_tab, c.off) != hipSuccess) return fail(ctx, CQ_E_DEVICE, "allocating batch tables");
-  p->tab_bytes = c.off;
-  char* b = static_cast<char*>(p->d_tab);
-  p->td = b + o_td;
-  p->gd = b + o_gd;
-  p->Wpre = reinterpret_cast<u32*>(b + o_W);
-  p->Lpre = reinterpret_cast<u32*>(b + o_L);
-  p->Gpre = reinterpret_cast<u32*>(b + o_G);
-  p->Kpre = reinterpret_cast<u32*>(b + o_K);
-  p->ticket = reinterpret_cast<u32*>(b + o_tk);
-  for (int r = 0; r < 3; ++r) {
-    p->RBpre[r] = reinterpret_cast<u32*>(b + o_RB[r]);
-    p->RBsum[r] = RB[r][ng];
-  }
-  p->Wsum = Wpre[T];
-  p->Lsum = Lpre[T];
-  p->Gsum = Gpre[T];
+  const BatchTabLayout tl = batch_tab_layout((int)p->tasks.size(), (int)p->groups.size());
+  if (hipMalloc(&p->d_tab, tl.total) != hipSuccess) return fail(ctx, CQ_E_DEVICE, "allocating batch tables");
+  p->tab_bytes = tl.total;
+  std::vector<char> blob(tl.total);
+  batch_fill_tables(p, d_ws, d_results, blob.data(), p->d_tab);
   hipStream_t s = p->stream;
-  hipError_t e = hipMemcpyAsync(p->td, td.data(), sizeof(TaskDev) * T, hipMemcpyHostToDevice, s);
-  if (e == hipSuccess) e = hipMemcpyAsync(p->gd, gd.data(), sizeof(GroupDev) * ng, hipMemcpyHostToDevice, s);
-  if (e == hipSuccess) e = hipMemcpyAsync(p->Wpre, Wpre.data(), 4 * (T + 1), hipMemcpyHostToDevice, s);
-  if (e == hipSuccess) e = hipMemcpyAsync(p->Lpre, Lpre.data(), 4 * (T + 1), hipMemcpyHostToDevice, s);
-  if (e == hipSuccess) e = hipMemcpyAsync(p->Gpre, Gpre.data(), 4 * (T + 1), hipMemcpyHostToDevice, s);
-  for (int r = 0; r < 3 && e == hipSuccess; ++r)
-    e = hipMemcpyAsync(p->RBpre[r], RB[r].data(), 4 * (ng + 1), hipMemcpyHostToDevice, s);
+  hipError_t e = hipMemcpyAsync(p->d_tab, blob.data(), tl.total, hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return fail(ctx, CQ_E_DEVICE, "uploading batch tables: %s", hipGetErrorString(e));
-  p->ws = d_ws;
-  p->d_results = d_results;
 
   // choose the tiling: cached choice, or time every candidate on this batch
   const int maxocc = batch_max_occ(p);
@@ -1157,5 +1474,165 @@ cq_status cq_batch_get_tuning(const cq_batch_plan* p, cq_batch_tuning* out) {
 }
 
 void cq_batch_plan_destroy(cq_batch_plan* p) { delete p; }
+
+// ---- serving -------------------------------------------------------------------
+
+cq_status cq_server_create(cq_context* ctx, const cq_server_config* cfg, cq_server** out) {
+  if (!ctx) return CQ_E_INVALID_ARG;
+  ctx->err[0] = 0;
+  if (!cfg || !out) return fail(ctx, CQ_E_INVALID_ARG, "null config or output");
+  *out = nullptr;
+  if (cfg->num_slots < 1 || cfg->num_slots > 64 || cfg->max_batch < 1 || cfg->max_batch > 4096 || cfg->memory_budget < 4096)
+    return fail(ctx, CQ_E_INVALID_ARG, "num_slots in [1, 64], max_batch in [1, 4096], memory_budget >= 4096");
+  cq_server* s = new (std::nothrow) cq_server();
+  if (!s) return fail(ctx, CQ_E_DEVICE, "out of host memory");
+  s->ctx = ctx;
+  s->cfg = *cfg;
+  hipError_t e = hipMalloc((void**)&s->arena, (size_t)cfg->memory_budget);
+  if (e != hipSuccess) {
+    delete s;
+    return fail(ctx, CQ_E_DEVICE, "allocating the server arena: %s", hipGetErrorString(e));
+  }
+  s->free_blocks[0] = (size_t)cfg->memory_budget & ~(kAlign - 1);
+  const BatchTabLayout tl = batch_tab_layout(cfg->max_batch, cfg->max_batch);
+  const size_t res_bytes = aup(std::max(sizeof(cq_compare_result), sizeof(cq_score_result) * (size_t)cfg->max_batch));
+  for (int i = 0; i < cfg->num_slots && e == hipSuccess; ++i) {
+    SrvSlot* sl = new SrvSlot();
+    s->slots.push_back(sl);
+    e = hipStreamCreateWithFlags(&sl->stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&sl->ev, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&sl->pinned, res_bytes + tl.total, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipMalloc(&sl->d_tab, tl.total);
+    if (e == hipSuccess && cq_context_create(ctx->device, sl->stream, &sl->ctx) != CQ_OK) e = hipErrorUnknown;
+    sl->res_bytes = res_bytes;
+    sl->plan.ctx = sl->ctx;
+  }
+  if (e != hipSuccess) {
+    cq_server_destroy(s);
+    return fail(ctx, CQ_E_DEVICE, "creating server slots: %s", hipGetErrorString(e));
+  }
+  s->worker = std::thread(srv_loop, s);
+  *out = s;
+  return CQ_OK;
+}
+
+cq_status cq_server_submit_score(cq_server* srv, const cq_graph* g, const int32_t* h_labels, int32_t num_labels,
+                                 uint64_t* ticket) {
+  if (!srv) return CQ_E_INVALID_ARG;
+  if (!g || !h_labels || !ticket || num_labels < 1) return fail(srv->ctx, CQ_E_INVALID_ARG, "bad scoring request");
+  if (g->nnz == 0) return fail(srv->ctx, CQ_E_NO_EDGES, "graph has no edges");
+  SrvReq* r = new (std::nothrow) SrvReq();
+  if (!r) return CQ_E_DEVICE;
+  r->kind = 0;
+  r->g = g;
+  r->n = g->n;
+  r->L = num_labels;
+  r->ha = h_labels;
+  r->ws_bytes = score_layout(g->n, g->nnz, num_labels).total;
+  r->small = num_labels <= BATCH_MAX_L && g->nnz <= srv->cfg.small_nnz;
+  return srv_submit(srv, r, ticket);
+}
+
+cq_status cq_server_submit_compare(cq_server* srv, int32_t n, const int32_t* h_labels_a, int32_t num_labels_a,
+                                   const int32_t* h_labels_b, int32_t num_labels_b, uint64_t* ticket) {
+  if (!srv) return CQ_E_INVALID_ARG;
+  if (n < 2 || !h_labels_a || !h_labels_b || !ticket || num_labels_a < 1 || num_labels_b < 1)
+    return fail(srv->ctx, CQ_E_INVALID_ARG, "bad comparison request");
+  SrvReq* r = new (std::nothrow) SrvReq();
+  if (!r) return CQ_E_DEVICE;
+  r->kind = 1;
+  r->n = n;
+  r->La = num_labels_a;
+  r->Lb = num_labels_b;
+  r->ha = h_labels_a;
+  r->hb = h_labels_b;
+  r->ws_bytes = cmp_layout(n, num_labels_a, num_labels_b).total;
+  return srv_submit(srv, r, ticket);
+}
+
+cq_status cq_server_wait(cq_server* srv, uint64_t ticket, double timeout_ms, cq_status* request_status,
+                         cq_score_result* score_out, cq_compare_result* compare_out, double* latency_ms) {
+  if (!srv) return CQ_E_INVALID_ARG;
+  std::unique_lock<std::mutex> lk(srv->mu);
+  auto it = srv->reqs.find(ticket);
+  if (it == srv->reqs.end()) return fail(srv->ctx, CQ_E_INVALID_ARG, "unknown ticket");
+  SrvReq* r = it->second;
+  auto ready = [&] { return r->done; };
+  if (timeout_ms < 0) srv->cv_done.wait(lk, ready);
+  else if (!srv->cv_done.wait_for(lk, std::chrono::duration<double, std::milli>(timeout_ms), ready)) return CQ_E_BUSY;
+  if (request_status) *request_status = r->status;
+  if (score_out && r->kind == 0) *score_out = r->sres;
+  if (compare_out && r->kind == 1) *compare_out = r->cres;
+  if (latency_ms) *latency_ms = std::chrono::duration<double, std::milli>(r->t_done - r->t_submit).count();
+  srv->reqs.erase(it);
+  delete r;
+  return CQ_OK;
+}
+
+cq_status cq_server_get_stats(cq_server* srv, cq_server_stats* out) {
+  if (!srv || !out) return CQ_E_INVALID_ARG;
+  std::lock_guard<std::mutex> lk(srv->mu);
+  std::memset(out, 0, sizeof(*out));
+  out->submitted = srv->submitted;
+  out->completed = srv->completed;
+  out->failed = srv->failed;
+  out->rejected = srv->rejected;
+  out->launches = srv->launches;
+  out->grouped_requests = srv->grouped;
+  out->busy_s = srv->busy_s;
+  out->peak_bytes = (int64_t)srv->peak;
+  std::vector<double> v = srv->lat_ms;
+  if (!v.empty()) {
+    std::sort(v.begin(), v.end());
+    auto q = [&](double f) { return v[std::min(v.size() - 1, (size_t)(f * (double)(v.size() - 1) + 0.5))]; };
+    out->p50_ms = q(0.50);
+    out->p99_ms = q(0.99);
+    out->max_ms = v.back();
+    double sum = 0;
+    for (double x : v) sum += x;
+    out->mean_ms = sum / (double)v.size();
+  }
+  return CQ_OK;
+}
+
+cq_status cq_server_reset_stats(cq_server* srv) {
+  if (!srv) return CQ_E_INVALID_ARG;
+  std::lock_guard<std::mutex> lk(srv->mu);
+  srv->lat_ms.clear();
+  srv->submitted = srv->completed = srv->failed = srv->launches = srv->grouped = srv->rejected = 0;
+  srv->busy_s = 0;
+  srv->peak = srv->in_use;
+  if (srv->inflight > 0) srv->busy_since = SrvClock::now();
+  return CQ_OK;
+}
+
+void cq_server_destroy(cq_server* srv) {
+  if (!srv) return;
+  {
+    std::lock_guard<std::mutex> lk(srv->mu);
+    srv->stop = true;
+    for (SrvReq* r : srv->pending) {
+      r->status = CQ_E_CANCELLED;
+      r->done = true;
+    }
+    srv->pending.clear();
+  }
+  srv->cv_work.notify_all();
+  if (srv->worker.joinable()) srv->worker.join();
+  srv->cv_done.notify_all();
+  for (SrvSlot* sl : srv->slots) {
+    if (sl->stream) (void)hipStreamSynchronize(sl->stream);
+    if (sl->ctx) cq_context_destroy(sl->ctx);
+    if (sl->ev) (void)hipEventDestroy(sl->ev);
+    if (sl->stream) (void)hipStreamDestroy(sl->stream);
+    if (sl->pinned) (void)hipHostFree(sl->pinned);
+    if (sl->d_tab) (void)hipFree(sl->d_tab);
+    sl->plan.stream = nullptr;  // the plan object owns nothing here
+    delete sl;
+  }
+  for (auto& kv : srv->reqs) delete kv.second;
+  if (srv->arena) (void)hipFree(srv->arena);
+  delete srv;
+}
 
 }  // extern "C"

@@ -1,0 +1,143 @@
+"""GPU: the continuous-batching server.  Every request's result in a concurrent mix is
+the same as the same request run alone (bit for bit), admission never exceeds the
+memory budget, a bad request fails alone, and destroy cancels waiting work."""
+import numpy as np
+import pytest
+import torch
+
+from cqgen import CONFIGS, LFRParams, lfr_graph, perturb_labels
+from tests.gpu_util import note
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def cq():
+    from paper_1507_05492_amd import cq as mod
+
+    return mod
+
+
+@pytest.fixture(scope="module")
+def ctx(cq):
+    c = cq.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def world(cq, ctx):
+    """4 resident graphs (one of 100k nodes), host label sets, and a request list."""
+    rng = np.random.default_rng(77)
+    graphs = []
+    for i, n in enumerate((4000, 12000, 30000)):
+        p = LFRParams(n, 15.0, 60, 2.0, 1.0, 20, max(40, min(1000, n // 5)), 0.3)
+        g = lfr_graph(p, 700 + i, device="cuda")
+        graphs.append((g, cq.Graph(ctx, g.row_ptr, g.col_idx, reorder=(i % 2 == 0))))
+    g = lfr_graph(CONFIGS["m100k_mu0.3"], 711, device="cuda")
+    graphs.append((g, cq.Graph(ctx, g.row_ptr, g.col_idx, reorder=True)))
+    labels = []
+    for g, _ in graphs:
+        sets = [g.labels] + [perturb_labels(g.labels, g.num_labels, f, 7000 + int(100 * f)) for f in (0.05, 0.15, 0.30)]
+        labels.append([s.cpu().pin_memory() for s in sets])
+    reqs = []
+    for k in range(48):
+        gi = int(rng.integers(0, len(graphs)))
+        if rng.random() < 0.7:
+            reqs.append(("score", gi, int(rng.integers(0, 4))))
+        else:
+            reqs.append(("compare", gi, int(rng.integers(1, 4))))
+    return graphs, labels, reqs
+
+
+def alone(cq, ctx, graphs, labels, req):
+    kind, gi, li = req
+    g, G = graphs[gi]
+    if kind == "score":
+        r, _, _ = cq.score_partition(G, labels[gi][li].cuda(), g.num_labels)
+    else:
+        r, _ = cq.compare_partitions(ctx, labels[gi][0].cuda(), g.num_labels, labels[gi][li].cuda(), g.num_labels)
+    r = dict(r)
+    r.pop("status")
+    return r
+
+
+def submit(srv, graphs, labels, req):
+    kind, gi, li = req
+    g, G = graphs[gi]
+    if kind == "score":
+        return srv.submit_score(G, labels[gi][li], g.num_labels)
+    return srv.submit_compare(labels[gi][0], g.num_labels, labels[gi][li], g.num_labels)
+
+
+def test_same_alone_and_in_mix(cq, ctx, world):
+    graphs, labels, reqs = world
+    note("server: requests alone")
+    expect = [alone(cq, ctx, graphs, labels, r) for r in reqs]
+    for slots, batch in ((4, 8), (1, 1), (8, 32)):
+        note(f"server: mix, slots={slots} max_batch={batch}")
+        srv = cq.Server(ctx, num_slots=slots, max_batch=batch, memory_budget=2 << 30, small_nnz=1_000_000)
+        tickets = [submit(srv, graphs, labels, r) for r in reqs]
+        for i, t in enumerate(tickets):
+            out = srv.wait(t)
+            assert out["status"] == cq.CQ_OK, (i, out["status"])
+            got = out["score"] if reqs[i][0] == "score" else out["compare"]
+            assert got == expect[i], (slots, batch, i, reqs[i])
+            assert out["latency_ms"] > 0
+        st = srv.stats()
+        assert st["completed"] == len(reqs) and st["failed"] == 0
+        assert st["peak_bytes"] <= 2 << 30
+        if batch > 1:
+            assert st["grouped_requests"] > 0 and st["launches"] < len(reqs)
+        else:
+            assert st["grouped_requests"] == 0 and st["launches"] == len(reqs)
+        assert st["p99_ms"] >= st["p50_ms"] > 0
+        srv.close()
+
+
+def test_admission_within_budget(cq, ctx, world):
+    graphs, labels, reqs = world
+    g, G = graphs[3]
+    need = G.workspace_size(g.num_labels) + 4 * g.n + 4096
+    budget = int(2.2 * need)  # room for two big requests at a time
+    note(f"server: budget {budget}")
+    srv = cq.Server(ctx, num_slots=6, max_batch=4, memory_budget=budget, small_nnz=1_000_000)
+    tickets = [srv.submit_score(G, labels[3][i % 4], g.num_labels) for i in range(12)]
+    res = [srv.wait(t) for t in tickets]
+    assert all(r["status"] == cq.CQ_OK for r in res)
+    st = srv.stats()
+    assert st["peak_bytes"] <= budget and st["completed"] == 12
+    small_srv = cq.Server(ctx, num_slots=1, max_batch=1, memory_budget=1 << 20, small_nnz=0)
+    with pytest.raises(cq.CQError) as e:
+        small_srv.submit_score(G, labels[3][0], g.num_labels)
+    assert e.value.status == cq.CQ_E_BUSY
+    assert small_srv.stats()["rejected"] == 1
+    small_srv.close()
+    srv.close()
+
+
+def test_bad_request_fails_alone(cq, ctx, world):
+    graphs, labels, reqs = world
+    g, G = graphs[0]
+    bad = labels[0][0].clone().pin_memory()
+    bad[17] = g.num_labels + 5
+    srv = cq.Server(ctx, num_slots=2, max_batch=8, memory_budget=1 << 30, small_nnz=1_000_000)
+    ok1 = srv.submit_score(G, labels[0][1], g.num_labels)
+    badt = srv.submit_score(G, bad, g.num_labels)
+    ok2 = srv.submit_score(G, labels[0][2], g.num_labels)
+    r1, rb, r2 = srv.wait(ok1), srv.wait(badt), srv.wait(ok2)
+    assert r1["status"] == cq.CQ_OK and r2["status"] == cq.CQ_OK
+    assert rb["status"] == cq.CQ_E_LABEL_RANGE
+    assert r1["score"] == alone(cq, ctx, graphs, labels, ("score", 0, 1))
+    assert srv.stats()["failed"] == 1
+    with pytest.raises(cq.CQError):
+        srv.wait(123456789)
+    srv.close()
+
+
+def test_destroy_with_waiting_requests(cq, ctx, world):
+    graphs, labels, reqs = world
+    srv = cq.Server(ctx, num_slots=1, max_batch=1, memory_budget=1 << 30, small_nnz=0)
+    for r in reqs[:20]:
+        submit(srv, graphs, labels, r)
+    srv.close()  # cancels what has not started, lets launches in flight finish
