@@ -59,8 +59,10 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="l10m", choices=["l10m", "s100m", "m100k_mu0.3", "batch256"],
-                    help="batch256: 256 LFR-style graphs x 4 partitions scored as one batch (separate JSON line)")
+    ap.add_argument("--workload", default="l10m", choices=["l10m", "s100m", "m100k_mu0.3", "batch256", "serve"],
+                    help="batch256: 256 LFR-style graphs x 4 partitions as one batch; serve: Poisson request "
+                         "load on a resident 100M-node graph plus 64 graphs (each prints its own JSON line)")
+    ap.add_argument("--serve-requests", type=int, default=800, help="requests per load point (serve)")
     ap.add_argument("--seed", type=int, default=21)
     ap.add_argument("--order", default="locality", choices=["locality", "input"],
                     help="graph storage order: 'locality' loads with CQ_GRAPH_REORDER (default), 'input' keeps node ids")
@@ -85,6 +87,8 @@ def main() -> int:
 
     if args.workload == "batch256":
         return bench_batch(args, log)
+    if args.workload == "serve":
+        return bench_serve(args, log)
 
     if args.calibrate_copy:
         src = torch.ones(1 << 28, dtype=torch.int32, device="cuda")
@@ -300,6 +304,146 @@ def bench_batch(args, log) -> int:
     }
     print(json.dumps(out), flush=True)
     b.close()
+    return 0
+
+
+def bench_serve(args, log) -> int:
+    """Serving: a resident LFR-style graph of 100M nodes (average degree 10, maximum 1,000,
+    community sizes 50-10,000, mixing 0.3) plus 64 graphs with n log-uniform in
+    [1e4, 1e6]; requests are 70 % scoring / 30 % comparison, 10 % of them on the big
+    graph, with label sets = ground truth or 5/15/30 % reassigned (pinned host memory).
+    Saturated throughput is measured with all requests submitted at once; then Poisson
+    arrivals at 25/50/75/90 % of it.  The same request streams go to a one-at-a-time
+    FIFO server (one slot, no grouping) for comparison."""
+    import threading
+
+    import numpy as np
+    import torch
+
+    from cqgen import CONFIGS, LFRParams, lfr_graph, perturb_labels
+    from paper_1507_05492_amd import cq
+
+    rng = np.random.default_rng(41)
+    ctx = cq.Context(0)
+    t = time.perf_counter()
+    graphs = []  # (n, nnz, num_labels, Graph, [pinned label sets])
+
+    def add(g, reorder=True):
+        G = cq.Graph(ctx, g.row_ptr, g.col_idx, reorder=reorder)
+        sets = [g.labels] + [perturb_labels(g.labels, g.num_labels, f, 4100 + int(100 * f)) for f in (0.05, 0.15, 0.30)]
+        pins = [s_.cpu().pin_memory() for s_ in sets]
+        graphs.append((g.n, g.nnz, g.num_labels, G, pins))
+
+    big = lfr_graph(CONFIGS["s100m"], 41, device="cuda")
+    add(big)
+    big_nnz = big.nnz
+    del big
+    for i in range(64):
+        n = int(np.exp(rng.uniform(np.log(1e4), np.log(1e6))))
+        avg = float(rng.uniform(10, 30))
+        p = LFRParams(n, avg, int(5 * avg), 2.0, 1.0, 20, max(40, min(1000, n // 5)), 0.3)
+        add(lfr_graph(p, 4200 + i, device="cuda"))
+    torch.cuda.synchronize()
+    log(f"serve: 1 + 64 resident graphs built in {time.perf_counter() - t:.1f}s (big graph 2|E| = {big_nnz})")
+
+    def make_stream(m, seed):
+        r = np.random.default_rng(seed)
+        out = []
+        for _ in range(m):
+            gi = 0 if r.random() < 0.10 else int(r.integers(1, len(graphs)))
+            kind = "score" if r.random() < 0.70 else "compare"
+            li = int(r.integers(0, 4)) if kind == "score" else int(r.integers(1, 4))
+            out.append((kind, gi, li))
+        return out
+
+    def entries(req):
+        kind, gi, _ = req
+        n, nnz = graphs[gi][0], graphs[gi][1]
+        return nnz if kind == "score" else n
+
+    def run(server, stream, rate):
+        """rate None: submit everything at once.  Returns (wall s, per-request results)."""
+        tickets = [None] * len(stream)
+        arrivals = None
+        if rate:
+            gaps = np.random.default_rng(7).exponential(1.0 / rate, len(stream))
+            arrivals = np.cumsum(gaps)
+        server.reset_stats()
+        t0 = time.perf_counter()
+
+        def submitter():
+            for i, (kind, gi, li) in enumerate(stream):
+                if arrivals is not None:
+                    while time.perf_counter() - t0 < arrivals[i]:
+                        pass
+                n, nnz, L, G, pins = graphs[gi]
+                if kind == "score":
+                    tickets[i] = server.submit_score(G, pins[li], L)
+                else:
+                    tickets[i] = server.submit_compare(pins[0], L, pins[li], L)
+
+        th = threading.Thread(target=submitter)
+        th.start()
+        th.join()
+        outs = [server.wait(tk) for tk in tickets]
+        wall = time.perf_counter() - t0
+        return wall, outs, server.stats()
+
+    points = {}
+    for name, slots, batch in (("continuous", 4, 32), ("fifo_one_at_a_time", 1, 1)):
+        srv = cq.Server(ctx, num_slots=slots, max_batch=batch, memory_budget=24 << 30, small_nnz=8_000_000)
+        warm = make_stream(64, 1)
+        run(srv, warm, None)
+        sat_stream = make_stream(args.serve_requests, 2)
+        wall, outs, st = run(srv, sat_stream, None)
+        assert all(o["status"] == cq.CQ_OK for o in outs)
+        sat_rate = len(sat_stream) / wall
+        res = {"saturated_req_per_s": round(sat_rate, 1),
+               "saturated_GEdges_per_s": round(sum(entries(q) for q in sat_stream) / wall / 1e9, 2),
+               "saturated_p50_ms": round(st["p50_ms"], 3), "saturated_p99_ms": round(st["p99_ms"], 3),
+               "launches": st["launches"], "grouped_requests": st["grouped_requests"], "loads": []}
+        base_rate = points.get("continuous", {}).get("saturated_req_per_s", sat_rate)
+        for frac in (0.25, 0.50, 0.75, 0.90):
+            rate = frac * base_rate  # same absolute arrival rates for both servers
+            stream = make_stream(args.serve_requests, 3)
+            wall, outs, st = run(srv, stream, rate)
+            assert all(o["status"] == cq.CQ_OK for o in outs)
+            res["loads"].append({"offered_req_per_s": round(rate, 1), "fraction_of_continuous_saturation": frac,
+                                 "p50_ms": round(st["p50_ms"], 3), "p99_ms": round(st["p99_ms"], 3),
+                                 "achieved_req_per_s": round(len(stream) / wall, 1),
+                                 "GEdges_per_s": round(sum(entries(q) for q in stream) / wall / 1e9, 2)})
+            log(f"serve[{name}] load {frac:.2f}: p50 {st['p50_ms']:.2f} ms p99 {st['p99_ms']:.2f} ms")
+        points[name] = res
+        srv.close()
+
+    # results in the mix equal results alone (a sample of the saturated stream)
+    check = make_stream(40, 2)
+    srv = cq.Server(ctx, num_slots=4, max_batch=32, memory_budget=24 << 30, small_nnz=8_000_000)
+    _, outs, _ = run(srv, check, None)
+    same = True
+    for (kind, gi, li), o in zip(check, outs):
+        n, nnz, L, G, pins = graphs[gi]
+        if kind == "score":
+            a, _, _ = cq.score_partition(G, pins[li].cuda(), L)
+            got = o["score"]
+        else:
+            a, _ = cq.compare_partitions(ctx, pins[0].cuda(), L, pins[li].cuda(), L)
+            got = o["compare"]
+        a.pop("status")
+        same = same and got == a
+    srv.close()
+    c = points["continuous"]
+    out = {
+        "metric": "served p50/p99 latency (ms) at 75% of saturation, continuous batching",
+        "value": c["loads"][2]["p99_ms"], "unit": "ms (p99)", "n_gpus": 1, "higher_is_better": False,
+        "data": "synthetic", "dtype": "u32",
+        "config": {"workload": "lfr_serve_100m_plus_64", "big_graph_nnz": big_nnz, "graphs": len(graphs),
+                   "requests_per_point": args.serve_requests, "mix": "70% score / 30% compare, 10% on the 100M graph"},
+        "continuous": points["continuous"], "fifo_one_at_a_time": points["fifo_one_at_a_time"],
+        "results_same_alone_and_in_mix": bool(same),
+    }
+    print(json.dumps(out), flush=True)
+    ctx.close()
     return 0
 
 

@@ -629,10 +629,15 @@ __device__ void group_one(const LT* __restrict__ CB, const u32 base, const u32 l
       if (x.w) vis.visit(st, 4u * q + 3u, x.w);
     }
   } else {
+    // The segment's dominant label is counted in registers during the first pass and
+    // never enters the table.  When the table must be split, the first split gives each
+    // residue class about capmax of the M entries (repeated and dominant labels keep the
+    // distinct keys well below that); a class that still overflows is split again.
+    const u32 hot = V::kHotIsGroup ? g : (len ? (u32)CB[base] : 0xFFFFFFFFu);
     const u32 capmax = 1u << log2_u32(lds_words / 2u);
     u32 classes = 1;
     if (hcap > capmax) {
-      classes = pow2ceil_u32((2u * M + capmax - 1u) / capmax);
+      classes = pow2ceil_u32((M + capmax - 1u) / capmax);
       if (classes > 32u) classes = 32u;
       hcap = capmax;
     }
@@ -641,9 +646,12 @@ __device__ void group_one(const LT* __restrict__ CB, const u32 base, const u32 l
     u32* cnt = tab + hcap;
     if (tid == 0) {
       s_sp = 0;
+      s_hot = 0;
       for (int r = (int)classes - 1; r >= 0; --r) { s_sr[s_sp] = (u32)r; s_sm[s_sp] = classes; ++s_sp; }
     }
     __syncthreads();
+    u32 mine = 0;
+    bool first = true;
     for (;;) {
       const int sp = s_sp;
       if (sp == 0) break;
@@ -654,6 +662,10 @@ __device__ void group_one(const LT* __restrict__ CB, const u32 base, const u32 l
       __syncthreads();
       for (u32 e = base + tid; e < base + len; e += GBLOCK) {
         u32 j = (u32)CB[e];
+        if (j == hot) {
+          if (first) ++mine;
+          continue;
+        }
         if (j >= Lv || (j & (mod - 1u)) != r) continue;
         u32 h = hash_slot(j, lg);
         bool done = false;
@@ -671,6 +683,7 @@ __device__ void group_one(const LT* __restrict__ CB, const u32 base, const u32 l
         }
         if (!done) s_over = 1;
       }
+      first = false;
       __syncthreads();
       if (s_over) {
         if (tid == 0) {
@@ -690,6 +703,9 @@ __device__ void group_one(const LT* __restrict__ CB, const u32 base, const u32 l
       }
       __syncthreads();
     }
+    if (mine) atomicAdd(&s_hot, mine);
+    __syncthreads();
+    if (tid == 0 && s_hot && hot < Lv) vis.visit(st, hot, s_hot);
   }
   vis.finish(st, g);
   __syncthreads();
