@@ -336,19 +336,47 @@ template <bool WEIGHTED, class LT>
 __global__ __launch_bounds__(256) void k_node_global(int n, const int32_t* __restrict__ labels, const int32_t* __restrict__ perm,
                                                      const int32_t* __restrict__ rp, int L, unsigned long long* __restrict__ SZ,
                                                      u32* __restrict__ loc, LT* __restrict__ labx, Ctl* __restrict__ ctl) {
+  const int lane = threadIdx.x & 63;
   u32 bad = 0;
-  for (size_t u = (size_t)blockIdx.x * blockDim.x + threadIdx.x; u < (size_t)n; u += (size_t)gridDim.x * blockDim.x) {
-    int c = labels[perm ? perm[u] : u];
-    if ((u32)c >= (u32)L) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t ub = (size_t)blockIdx.x * blockDim.x; ub < (size_t)n; ub += stride) {  // uniform per wave
+    const size_t u = ub + threadIdx.x;
+    const bool in = u < (size_t)n;
+    const int c = in ? labels[perm ? perm[u] : u] : 0;
+    const bool valid = in && (u32)c < (u32)L;
+    if (in && !valid) {
       bad = 1;
       loc[u] = SENT;
       if (labx) labx[u] = LabelT<LT>::SENTINEL;
-      continue;
     }
-    u32 w = WEIGHTED ? (u32)(rp[u + 1] - rp[u]) : 1u;
-    unsigned long long old = atomicAdd(&SZ[c], (1ull << 32) | (unsigned long long)w);
-    loc[u] = (u32)old;
-    if (labx) labx[u] = (LT)c;
+    const u32 w = valid ? (WEIGHTED ? (u32)(rp[u + 1] - rp[u]) : 1u) : 0u;
+    // lanes with equal labels add through one leader (see k_node_priv)
+    bool pending = valid;
+    u32 old = 0;
+    for (int round = 0; round < 4; ++round) {
+      const u64 act = __ballot(pending);
+      if (act == 0) break;
+      const int leader = __ffsll((long long)act) - 1;
+      const int lc = __shfl(c, leader, 64);
+      const bool mine = pending && c == lc;
+      const u64 grp = __ballot(mine);
+      if (__popcll(grp) < 4) break;
+      const u32 pw = mine ? w : 0u;
+      const u32 incl = wave_incl_scan(pw);
+      const u32 tot = __shfl(incl, 63, 64);
+      u32 b = 0;
+      if (lane == leader) b = (u32)atomicAdd(&SZ[lc], ((unsigned long long)__popcll(grp) << 32) | (unsigned long long)tot);
+      b = __shfl(b, leader, 64);
+      if (mine) {
+        old = b + incl - pw;
+        pending = false;
+      }
+    }
+    if (pending) old = (u32)atomicAdd(&SZ[c], (1ull << 32) | (unsigned long long)w);
+    if (valid) {
+      loc[u] = old;
+      if (labx) labx[u] = (LT)c;
+    }
   }
   if (bad) atomicOr(&ctl->flags, F_LABEL);
 }
@@ -562,9 +590,43 @@ __global__ __launch_bounds__(256) void k_cmp_scatter(int n, const int32_t* __res
 //                  class, so visitors see each (label, count) once.
 constexpr int GBLOCK = 512;
 constexpr int STACK = 96;
+constexpr u32 WIDE_FIX = 256;  // wrap corrections a 16-bit table can log per group
 
 __device__ __forceinline__ u32 pow2ceil_u32(u32 x) { return x <= 1 ? 1u : 1u << (32 - __clz(x - 1)); }
 __device__ __forceinline__ u32 log2_u32(u32 x) { return 31 - __clz(x); }
+
+// Calls f(label) for every entry of a segment: 16-byte vector loads (8 labels of 16
+// bits or 4 of 32 bits), two loads in flight per thread, scalar head and tail.
+template <class LT, class F>
+__device__ __forceinline__ void for_each_in_segment(const LT* __restrict__ seg, const u32 len, F&& f) {
+  constexpr u32 PER = 16u / sizeof(LT);
+  u32 head = (u32)(((16u - ((uintptr_t)seg & 15u)) & 15u) / sizeof(LT));
+  if (head > len) head = len;
+  const u32 nvec = (len - head) / PER;
+  for (u32 e = threadIdx.x; e < head; e += GBLOCK) f((u32)seg[e]);
+  const uint4* vec = reinterpret_cast<const uint4*>(seg + head);
+  auto unpack = [&](const uint4 q) {
+    const u32 w4[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      if (sizeof(LT) == 2) {
+        f(w4[k] & 0xFFFFu);
+        f(w4[k] >> 16);
+      } else {
+        f(w4[k]);
+      }
+    }
+  };
+  u32 i = threadIdx.x;
+  for (; i + GBLOCK < nvec; i += 2 * GBLOCK) {
+    const uint4 q0 = vec[i];
+    const uint4 q1 = vec[i + GBLOCK];
+    unpack(q0);
+    unpack(q1);
+  }
+  for (; i < nvec; i += GBLOCK) unpack(vec[i]);
+  for (u32 e = head + nvec * PER + threadIdx.x; e < len; e += GBLOCK) f((u32)seg[e]);
+}
 
 // Counts one group's segment CB[base, base+len) (values in [0, Lv) or the sentinel)
 // in LDS and hands every (label, count) with count > 0 to the visitor.
@@ -574,6 +636,9 @@ __device__ void group_one(const LT* __restrict__ CB, const u32 base, const u32 l
   extern __shared__ u32 tab[];
   __shared__ u32 s_over;
   __shared__ u32 s_hot;
+  __shared__ u32 s_nfix;
+  __shared__ u32 s_fix_lab[WIDE_FIX];
+  __shared__ int s_fix_del[WIDE_FIX];
   __shared__ int s_sp;
   __shared__ u32 s_sr[STACK], s_sm[STACK];
   const int tid = threadIdx.x;
@@ -582,6 +647,77 @@ __device__ void group_one(const LT* __restrict__ CB, const u32 base, const u32 l
   const u32 M = min(len, Lv);
   u32 hcap = pow2ceil_u32(max(64u, 2u * M));
   const bool direct = (Lv <= lds_words) && (2u * hcap > Lv);
+  // 16-bit counters, two per LDS word, for label spaces up to twice the LDS budget
+  const bool wide = !direct && Lv > lds_words && ((Lv + 7u) >> 3) * 4u <= lds_words && (4u * hcap > Lv);
+  bool use_hash = !direct && !wide;
+  if (wide) {
+    // Every change of a counter word is one atomic add whose returned value shows
+    // whether a 16-bit half wrapped: low half (even label) at 0xFFFF + 1, which also
+    // carries 1 into the high half; high half (odd label) at 0xFFFF + 1 from either
+    // its own increment or that carry.  Each wrap is logged as a correction (+65536
+    // to the wrapped label, -1 to the high label for a carry), so the counts are exact.
+    const u32 hot = V::kHotIsGroup ? g : (len ? (u32)CB[base] : 0xFFFFFFFFu);
+    const u32 nq = (Lv + 7u) >> 3;  // 16-byte words of the 16-bit table
+    uint4* tab4 = reinterpret_cast<uint4*>(tab);
+    for (u32 q = tid; q < nq; q += GBLOCK) tab4[q] = make_uint4(0u, 0u, 0u, 0u);
+    if (tid == 0) {
+      s_hot = 0;
+      s_nfix = 0;
+    }
+    __syncthreads();
+    u32 mine = 0;
+    auto fix = [&](u32 j, int delta) {
+      const u32 i = atomicAdd(&s_nfix, 1u);
+      if (i < WIDE_FIX) {
+        s_fix_lab[i] = j;
+        s_fix_del[i] = delta;
+      }
+    };
+    for_each_in_segment<LT>(CB + base, len, [&](u32 j) {
+      if (j == hot) {
+        ++mine;
+        return;
+      }
+      if (j >= Lv) return;
+      if (j & 1u) {
+        const u32 old = atomicAdd(&tab[j >> 1], 0x10000u);
+        if ((old >> 16) == 0xFFFFu) fix(j, 1);
+      } else {
+        const u32 old = atomicAdd(&tab[j >> 1], 1u);
+        if ((old & 0xFFFFu) == 0xFFFFu) {
+          fix(j, 1);
+          fix(j + 1u, 0);  // carry into the high half
+          if ((old >> 16) == 0xFFFFu) fix(j + 1u, 1);
+        }
+      }
+    });
+    if (mine) atomicAdd(&s_hot, mine);
+    __syncthreads();
+    const u32 nfix = s_nfix;
+    if (nfix > WIDE_FIX) {
+      use_hash = true;  // correction log full (more than WIDE_FIX wraps): count again with hashing
+    } else {
+      if (tid == 0 && s_hot && hot < Lv) vis.visit(st, hot, s_hot);
+      auto total = [&](u32 j, u32 half) -> u32 {
+        u32 t = half;
+        for (u32 i = 0; i < nfix; ++i)
+          if (s_fix_lab[i] == j) t += s_fix_del[i] ? 65536u : (u32)-1;
+        return t;
+      };
+      for (u32 q = tid; q < nq; q += GBLOCK) {
+        const uint4 x = tab4[q];
+        const u32 w4[4] = {x.x, x.y, x.z, x.w};
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          const u32 j = 8u * q + (u32)k;
+          const u32 half = (w4[k >> 1] >> (16 * (k & 1))) & 0xFFFFu;
+          const u32 c = nfix ? total(j, half) : half;
+          if (c && j < Lv && j != hot) vis.visit(st, j, c);
+        }
+      }
+    }
+    __syncthreads();
+  }
   if (direct) {
     // One label usually dominates a segment (the community's own label when scoring,
     // the best-matching detected community when comparing).  Its entries are counted
@@ -593,31 +729,10 @@ __device__ void group_one(const LT* __restrict__ CB, const u32 base, const u32 l
     if (tid == 0) s_hot = 0;
     __syncthreads();
     u32 mine = 0;
-    const LT* seg = CB + base;
-    constexpr u32 PER = 16u / sizeof(LT);
-    u32 head = (u32)(((16u - ((uintptr_t)seg & 15u)) & 15u) / sizeof(LT));
-    if (head > len) head = len;
-    const u32 nvec = (len - head) / PER;
-    auto count1 = [&](u32 j) {
+    for_each_in_segment<LT>(CB + base, len, [&](u32 j) {
       if (j == hot) ++mine;
       else if (j < Lv) atomicAdd(&tab[j], 1u);
-    };
-    for (u32 e = tid; e < head; e += GBLOCK) count1((u32)seg[e]);
-    const uint4* vec = reinterpret_cast<const uint4*>(seg + head);
-    for (u32 i = tid; i < nvec; i += GBLOCK) {
-      const uint4 q = vec[i];
-      const u32 w4[4] = {q.x, q.y, q.z, q.w};
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        if (sizeof(LT) == 2) {
-          count1(w4[k] & 0xFFFFu);
-          count1(w4[k] >> 16);
-        } else {
-          count1(w4[k]);
-        }
-      }
-    }
-    for (u32 e = head + nvec * PER + tid; e < len; e += GBLOCK) count1((u32)seg[e]);
+    });
     if (mine) atomicAdd(&s_hot, mine);
     __syncthreads();
     if (tid == 0 && s_hot && hot < Lv) vis.visit(st, hot, s_hot);
@@ -628,16 +743,18 @@ __device__ void group_one(const LT* __restrict__ CB, const u32 base, const u32 l
       if (x.z) vis.visit(st, 4u * q + 2u, x.z);
       if (x.w) vis.visit(st, 4u * q + 3u, x.w);
     }
-  } else {
+  }
+  if (use_hash) {
     // The segment's dominant label is counted in registers during the first pass and
     // never enters the table.  When the table must be split, the first split gives each
-    // residue class about capmax of the M entries (repeated and dominant labels keep the
-    // distinct keys well below that); a class that still overflows is split again.
+    // residue class about 2*capmax of the M entries, assuming at most M/2 distinct keys
+    // (repeated and dominant labels keep them below that); a class that still
+    // overflows is split again.
     const u32 hot = V::kHotIsGroup ? g : (len ? (u32)CB[base] : 0xFFFFFFFFu);
     const u32 capmax = 1u << log2_u32(lds_words / 2u);
     u32 classes = 1;
     if (hcap > capmax) {
-      classes = pow2ceil_u32((M + capmax - 1u) / capmax);
+      classes = pow2ceil_u32((M + 2u * capmax - 1u) / (2u * capmax));
       if (classes > 32u) classes = 32u;
       hcap = capmax;
     }
@@ -660,29 +777,31 @@ __device__ void group_one(const LT* __restrict__ CB, const u32 base, const u32 l
       if (tid == 0) { s_sp = sp - 1; s_over = 0; }
       for (u32 s = tid; s < hcap; s += GBLOCK) { keys[s] = EMPTY; cnt[s] = 0; }
       __syncthreads();
-      for (u32 e = base + tid; e < base + len; e += GBLOCK) {
-        u32 j = (u32)CB[e];
+      bool over = false;
+      for_each_in_segment<LT>(CB + base, len, [&](u32 j) {
         if (j == hot) {
           if (first) ++mine;
-          continue;
+          return;
         }
-        if (j >= Lv || (j & (mod - 1u)) != r) continue;
+        if (j >= Lv || (j & (mod - 1u)) != r) return;
         u32 h = hash_slot(j, lg);
-        bool done = false;
         for (u32 p = 0; p < hcap; ++p) {
-          u32 k = keys[h];
+          const u32 k = keys[h];
           if (k == EMPTY) {
-            u32 old = atomicCAS(&keys[h], EMPTY, j);
-            if (old == EMPTY || old == j) { atomicAdd(&cnt[h], 1u); done = true; break; }
+            const u32 old = atomicCAS(&keys[h], EMPTY, j);
+            if (old == EMPTY || old == j) {
+              atomicAdd(&cnt[h], 1u);
+              return;
+            }
           } else if (k == j) {
             atomicAdd(&cnt[h], 1u);
-            done = true;
-            break;
+            return;
           }
           h = (h + 1u) & (hcap - 1u);
         }
-        if (!done) s_over = 1;
-      }
+        over = true;
+      });
+      if (over) s_over = 1;
       first = false;
       __syncthreads();
       if (s_over) {

@@ -109,7 +109,7 @@ namespace {
 
 constexpr int64_t PRIV_MAX = 16384;    // labels handled by LDS-private node histograms
 constexpr int64_t DIRECT_MAX = 16384;  // labels handled by direct-indexed group tables
-constexpr u32 HASH_WORDS = 16384;      // LDS words of the group hash table (8192 slots)
+constexpr u32 HASH_WORDS = 32768;      // LDS words of the group hash table (16384 slots)
 constexpr size_t ALIGN = 256;
 
 enum Stage { ST_SETUP = 0, ST_NODE, ST_COLSCAN, ST_ORDER, ST_GATHER, ST_GROUPS, ST_FINAL, ST_HIST_B, ST_SCATTER, ST_COUNT };
@@ -519,7 +519,7 @@ void scan_u32(const u32* in, u32* out, long long n, u32* tiles, hipStream_t s) {
   if (T > 0) k_scan_add<<<T, SCAN_THREADS, 0, s>>>(n, out, tiles);
 }
 
-constexpr int LP_SWEEPS = 4;
+constexpr int LP_SWEEPS = 10;
 
 // Builds the renumbered copy of a graph (see CQ_GRAPH_REORDER in cq.h).
 cq_status build_locality_order(cq_context* ctx, cq_graph* g, const int32_t* rp, const int32_t* col) {

@@ -90,6 +90,27 @@ def test_many_labels(cq, ctx):
     run_cmp(cq, ctx, big, 1, (np.arange(n) * 8).astype(np.int32), 8 * n, "one row, 2e5 cells, labels = 8i")
 
 
+def test_wide_counter_wraps(cq, ctx):
+    # 32768 < Lb <= 65535 selects 16-bit LDS counters; cells above 65535 wrap them and
+    # must come back exact through the correction log, or through the hash path once
+    # the log is full.  The first node's label is the register-counted one.
+    n = 200000
+    a = np.zeros(n, np.int32)
+    b = np.where(np.arange(n) % 2 == 0, 40000, 40001).astype(np.int32)
+    b[0] = 5
+    run_cmp(cq, ctx, a, 1, b, 40003, "one row, two cells of 1e5 (even+odd label wraps)")
+    b2 = np.full(n, 40000, np.int32)
+    b2[0] = 5
+    b2[1:70000] = 40001
+    run_cmp(cq, ctx, a, 1, b2, 40003, "even label 130000 entries, odd 69999")
+    n3 = 8_700_000  # 40000 holds ~132 * 65536 entries: more wraps than the log holds
+    a3 = np.zeros(n3, np.int32)
+    b3 = np.full(n3, 40000, np.int32)
+    b3[0] = 7
+    b3[1::97] = 40001
+    run_cmp(cq, ctx, a3, 1, b3, 40003, "log overflow: 8.7e6 entries in two cells")
+
+
 def test_errors(cq, ctx):
     a = torch.zeros(10, dtype=torch.int32, device="cuda")
     b = torch.zeros(10, dtype=torch.int32, device="cuda")

@@ -94,6 +94,22 @@ def test_many_labels_global_paths(cq, ctx):
     run_case(cq, ctx, rp, ci, lab3, 70001, "relabelled into 70001 ids", reorder=True)
 
 
+def test_wide_counter_wraps(cq, ctx):
+    # 40003 label ids select 16-bit LDS counters for large segments.  Community 0 is
+    # joined completely to communities 40000 and 40001 (300 x 300 edges each), so both
+    # of its counters pass 65535 (even label: low-half wrap with a carry; odd: high half).
+    k = 300
+    A = np.arange(k)
+    B = np.arange(k, 2 * k)
+    C = np.arange(2 * k, 3 * k)
+    edges = [(int(u), int(v)) for u in A for v in np.concatenate([B, C])]
+    edges += [(int(B[i]), int(B[i + 1])) for i in range(k - 1)] + [(int(C[i]), int(C[i + 1])) for i in range(k - 1)]
+    rp, ci = csr_from_edges(3 * k, edges)
+    lab = np.concatenate([np.zeros(k), np.full(k, 40000), np.full(k, 40001)]).astype(np.int32)
+    run_case(cq, ctx, rp, ci, lab, 40003, "complete bipartite 300x600, labels 0/40000/40001")
+    run_case(cq, ctx, rp, ci, lab, 40003, "complete bipartite 300x600, labels 0/40000/40001", reorder=True)
+
+
 def test_hub_split_classes(cq, ctx):
     # a hub adjacent to 20000 singleton communities: its table needs residue classes;
     # labels that are all multiples of 8 force classes to overflow and split again.
