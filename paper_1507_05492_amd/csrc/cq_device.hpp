@@ -19,6 +19,7 @@ constexpr u32 F_LABEL = 1u;   // a label outside [0, num_labels)
 constexpr u32 F_GRAPH = 2u;   // malformed CSR (graph load only)
 constexpr u32 F_EXPORT = 4u;  // export table too small
 constexpr u32 F_STACK = 8u;   // internal: class stack exhausted (never expected)
+constexpr u32 F_SEGMENT = 16u;  // internal: a community's entries exceed its segment (never expected)
 
 // Control block at the start of every workspace.
 struct Ctl {

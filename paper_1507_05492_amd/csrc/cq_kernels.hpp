@@ -236,6 +236,59 @@ __global__ __launch_bounds__(256) void k_relabel_rows(int n, const int32_t* __re
   }
 }
 
+// Column blocks of the renumbered graph.  The id range is cut into COL_BLOCKS spans of
+// `span` ids; block y holds, row by row, the entries whose neighbour lies in span y, as
+// its own CSR whose row pointers RPB[y*(n+1) + u] index one array colb shared by all
+// blocks (block y's entries follow block y-1's).  One wave per row.
+constexpr int COL_BLOCKS = 8;
+
+__global__ __launch_bounds__(256) void k_blk_count(int n, const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
+                                                   int span, u32* __restrict__ cnt) {
+  const int lane = threadIdx.x & 63;
+  const size_t wave = ((size_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const size_t nwaves = ((size_t)gridDim.x * blockDim.x) >> 6;
+  for (size_t u = wave; u < (size_t)n; u += nwaves) {
+    const int a = rp[u], deg = rp[u + 1] - a;
+    u32 mine = 0;  // lane y < COL_BLOCKS counts block y
+    for (int k0 = 0; k0 < deg; k0 += 64) {
+      const int y = k0 + lane < deg ? col[a + k0 + lane] / span : -1;
+#pragma unroll
+      for (int b = 0; b < COL_BLOCKS; ++b) {
+        const u32 c = (u32)__popcll(__ballot(y == b));
+        if (lane == b) mine += c;
+      }
+    }
+    if (lane < COL_BLOCKS) cnt[(size_t)lane * ((size_t)n + 1) + u] = mine;
+    if (u == 0 && lane < COL_BLOCKS) cnt[(size_t)lane * ((size_t)n + 1) + n] = 0;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_blk_place(int n, const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
+                                                   int span, const u32* __restrict__ RPB, int32_t* __restrict__ colb) {
+  const int lane = threadIdx.x & 63;
+  const u64 below = lane ? (~0ull >> (64 - lane)) : 0ull;
+  const size_t wave = ((size_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const size_t nwaves = ((size_t)gridDim.x * blockDim.x) >> 6;
+  for (size_t u = wave; u < (size_t)n; u += nwaves) {
+    const int a = rp[u], deg = rp[u + 1] - a;
+    u32 fill_b = lane < COL_BLOCKS ? RPB[(size_t)lane * ((size_t)n + 1) + u] : 0u;  // lane y: next slot of block y
+    for (int k0 = 0; k0 < deg; k0 += 64) {
+      const bool in = k0 + lane < deg;
+      const int v = in ? col[a + k0 + lane] : 0;
+      const int y = in ? v / span : -1;
+      u32 slot = 0;
+#pragma unroll
+      for (int b = 0; b < COL_BLOCKS; ++b) {
+        const u64 m = __ballot(y == b);
+        const u32 base = __shfl(fill_b, b, 64);
+        if (y == b) slot = base + (u32)__popcll(m & below);
+        if (lane == b) fill_b += (u32)__popcll(m);
+      }
+      if (in) colb[slot] = v;
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Node pass, LDS-private histograms (num_labels small enough for LDS).
 // Workgroup w owns nodes [w*chunk, (w+1)*chunk).  It counts, per label, the nodes
@@ -557,6 +610,94 @@ __global__ __launch_bounds__(GROWS) void k_gather(int n, const int32_t* __restri
     const u32 base = s_base[lo];
     if (base == SENT) continue;
     CB[base + (u32)(e - s_rs[lo])] = labx[col[e]];
+  }
+}
+
+// Edge pass over a column-blocked graph.  Workgroup i runs on XCD i % 8 (workgroups
+// are handed to the XCDs in turn), and XCD x walks column blocks x, x+8, ... so every
+// neighbour label it reads lies in the span of ids its own L2 holds.  A workgroup takes
+// BT_ROWS consecutive rows of one block; rows with equal labels that follow each other
+// form a run, whose entries are given consecutive places in the community's segment
+// by one atomic add on that community's cursor.  Entries of a run are then written in
+// entry order (place = run start + index inside the run), so only the run, not the
+// row, of an entry has to be looked up.
+constexpr int BT_THREADS = 256;
+constexpr int BT_ROWS = 1024;  // rows per workgroup (4 per thread)
+template <class LT>
+__global__ __launch_bounds__(BT_THREADS) void k_gather_blk(int n, int tiles, const u32* __restrict__ RPB,
+                                                           const int32_t* __restrict__ colb, const LT* __restrict__ labx,
+                                                           const u32* __restrict__ start, const u32* __restrict__ D,
+                                                           u32* __restrict__ cursor, Ctl* __restrict__ ctl,
+                                                           LT* __restrict__ CB) {
+  __shared__ u32 s_re[BT_ROWS + 1];  // first entry of run q (tile-relative); s_re[nruns] = entry count
+  __shared__ u32 s_rl[BT_ROWS];      // label of run q, then the segment place of its first entry (or SENT)
+  __shared__ u32 s_w[BT_THREADS / 64];
+  const u32 bi = blockIdx.x, xcd = bi % 8u, k = bi / 8u;
+  const u32 y = xcd + 8u * (k / (u32)tiles);
+  const long long r0 = (long long)(k % (u32)tiles) * BT_ROWS;
+  if (y >= (u32)COL_BLOCKS || r0 >= n) return;
+  const u32* rpb = RPB + (size_t)y * ((size_t)n + 1);
+  const int rows = (int)min((long long)BT_ROWS, (long long)n - r0);
+  const u32 e0 = rpb[r0], e1 = rpb[r0 + rows];
+  if (e0 == e1) return;
+  const int tid = threadIdx.x;
+  // rows 4*tid .. 4*tid+3 of the tile: run heads where the label changes
+  u32 lab[4], beg[4];
+  u32 heads = 0;
+  const int rb = 4 * tid;
+  u32 prev = rb > 0 && rb - 1 < rows ? (u32)labx[r0 + rb - 1] : 0xFFFFFFFFu;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int r = rb + j;
+    lab[j] = r < rows ? (u32)labx[r0 + r] : 0u;
+    beg[j] = r < rows ? rpb[r0 + r] - e0 : 0u;
+    if (r < rows && (r == 0 || lab[j] != prev)) heads |= 1u << j;
+    prev = lab[j];
+  }
+  // exclusive scan of head counts over the workgroup gives each head its run index
+  const u32 nh = (u32)__popc(heads);
+  const u32 incl = wave_incl_scan(nh);
+  const int w = tid >> 6;
+  if ((tid & 63) == 63) s_w[w] = incl;
+  __syncthreads();
+  u32 q = incl - nh;
+  u32 nruns = 0;
+  for (int i = 0; i < BT_THREADS / 64; ++i) {
+    if (i < w) q += s_w[i];
+    nruns += s_w[i];
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    if (heads & (1u << j)) {
+      s_re[q] = beg[j];
+      s_rl[q] = lab[j];
+      ++q;
+    }
+  }
+  if (tid == 0) s_re[nruns] = e1 - e0;
+  __syncthreads();
+  for (u32 r = tid; r < nruns; r += BT_THREADS) {
+    const u32 c = s_rl[r];
+    const u32 tot = s_re[r + 1] - s_re[r];
+    u32 base = SENT;
+    if (c != (u32)LabelT<LT>::SENTINEL && tot > 0) {
+      const u32 old = atomicAdd(&cursor[c], tot);
+      if (old + tot <= D[c]) base = start[c] + old;  // < 2^31, so never the SENT marker
+      else atomicOr(&ctl->flags, F_SEGMENT);  // never expected: the block counts disagree with the degrees
+    }
+    s_rl[r] = base;
+  }
+  __syncthreads();
+  const int32_t* cb = colb + e0;
+  for (u32 e = tid; e < e1 - e0; e += BT_THREADS) {
+    u32 lo = 0, hi = nruns - 1;  // last run r with s_re[r] <= e
+    while (lo < hi) {
+      const u32 mid = (lo + hi + 1) >> 1;
+      if (s_re[mid] <= e) lo = mid; else hi = mid - 1;
+    }
+    const u32 base = s_rl[lo];
+    if (base == SENT) continue;
+    CB[base + (e - s_re[lo])] = labx[cb[e]];
   }
 }
 

@@ -51,11 +51,15 @@ struct cq_graph {
   int32_t* owned_rp = nullptr;    // device memory owned by the handle (CQ_GRAPH_REORDER)
   int32_t* owned_col = nullptr;
   int32_t* owned_perm = nullptr;
+  u32* rpb = nullptr;              // column blocks (owned; null when the graph is not blocked)
+  int32_t* colb = nullptr;
   int64_t owned_bytes = 0;
   ~cq_graph() {
     if (owned_rp) (void)hipFree(owned_rp);
     if (owned_col) (void)hipFree(owned_col);
     if (owned_perm) (void)hipFree(owned_perm);
+    if (rpb) (void)hipFree(rpb);
+    if (colb) (void)hipFree(colb);
   }
 };
 
@@ -178,7 +182,7 @@ unsigned grid_for(int64_t items, int per_block, unsigned cap) {
 struct ScoreLayout {
   bool priv, small;  // small: labels fit 16 bits (num_labels <= 65535)
   int chunk, W, G;
-  size_t ctl, N, D, start, order, I, NP, PEN, SZ, loc, HN, HD, labx, CB, parts, res, total;
+  size_t ctl, N, D, start, order, I, NP, PEN, SZ, cursor, loc, HN, HD, labx, CB, parts, res, total;
 };
 
 ScoreLayout score_layout(int64_t n, int64_t nnz, int64_t L) {
@@ -199,6 +203,7 @@ ScoreLayout score_layout(int64_t n, int64_t nnz, int64_t L) {
   s.NP = c.take(4 * L);
   s.PEN = c.take(16 * L);
   s.SZ = s.priv ? 0 : c.take(8 * L);
+  s.cursor = c.take(4 * L);
   s.loc = c.take(4 * n);
   s.HN = s.priv ? c.take(4 * (size_t)s.W * L) : 0;
   s.HD = s.priv ? c.take(4 * (size_t)s.W * L) : 0;
@@ -274,6 +279,7 @@ unsigned group_grid(cq_context* ctx, size_t lds_bytes) {
 cq_status map_flags(cq_context* ctx, u32 flags) {
   if (flags & F_LABEL) return fail(ctx, CQ_E_LABEL_RANGE, "a label is outside [0, num_labels)");
   if (flags & F_STACK) return fail(ctx, CQ_E_DEVICE, "internal: group table split limit reached");
+  if (flags & F_SEGMENT) return fail(ctx, CQ_E_DEVICE, "internal: segment overflow in the edge pass");
   if (flags & F_EXPORT) return fail(ctx, CQ_E_CAPACITY, "export table capacity too small");
   return CQ_OK;
 }
@@ -301,6 +307,7 @@ void score_launch(cq_context* ctx, const cq_graph* g, const int32_t* labels, int
     StageMark mk(ctx, ST_SETUP, timed);
     fill(reinterpret_cast<u32*>(ctl), sizeof(Ctl) / 4, 0, s);
     if (!lay.priv) fill(at<u32>(ws, lay.SZ), 2 * (size_t)L, 0, s);
+    if (g->rpb) fill(at<u32>(ws, lay.cursor), (size_t)L, 0, s);
   }
   if (lay.priv) {
     u32* HN = at<u32>(ws, lay.HN);
@@ -332,7 +339,11 @@ void score_launch(cq_context* ctx, const cq_graph* g, const int32_t* labels, int
   }
   {
     StageMark mk(ctx, ST_GATHER, timed);
-    if (lay.priv)
+    if (g->rpb) {
+      const int tiles = (int)((n + BT_ROWS - 1) / BT_ROWS);
+      k_gather_blk<LT><<<(unsigned)(COL_BLOCKS * tiles), BT_THREADS, 0, s>>>((int)n, tiles, g->rpb, g->colb, labx, start, D,
+                                                                           at<u32>(ws, lay.cursor), ctl, CB);
+    } else if (lay.priv)
       k_gather<true, LT><<<grid_for(n, GROWS, 1u << 30), GROWS, 0, s>>>((int)n, g->rp, g->col, labx, L, lay.chunk, PM, start, loc, CB);
     else
       k_gather<false, LT><<<grid_for(n, GROWS, 1u << 30), GROWS, 0, s>>>((int)n, g->rp, g->col, labx, L, lay.chunk, PM, start, loc, CB);
@@ -520,6 +531,47 @@ void scan_u32(const u32* in, u32* out, long long n, u32* tiles, hipStream_t s) {
 }
 
 constexpr int LP_SWEEPS = 10;
+// Column blocks pay off while one block's labels (2 bytes per node) fit an XCD's L2.
+constexpr int64_t BLOCK_MAX_N = 16 << 20;
+
+// Splits the renumbered graph (g->owned_rp / owned_col) into COL_BLOCKS column blocks.
+cq_status build_column_blocks(cq_context* ctx, cq_graph* g) {
+  const int n = g->n;
+  const int64_t nnz = g->nnz;
+  hipStream_t s = ctx->stream;
+  const long long len = (long long)COL_BLOCKS * ((long long)n + 1);
+  u32 *cnt = nullptr, *tiles = nullptr;
+  hipError_t e = hipSuccess;
+  auto alloc = [&](void** p, size_t bytes) {
+    if (e == hipSuccess) e = hipMalloc(p, std::max<size_t>(bytes, 4));
+  };
+  alloc((void**)&g->rpb, 4 * ((size_t)len + 1));
+  alloc((void**)&g->colb, 4 * (size_t)nnz);
+  alloc((void**)&cnt, 4 * (size_t)len);
+  alloc((void**)&tiles, 4 * ((size_t)((len + SCAN_TILE - 1) / SCAN_TILE) + 1));
+  cq_status st = CQ_OK;
+  if (e != hipSuccess) {
+    st = fail(ctx, CQ_E_DEVICE, "allocating column blocks: %s", hipGetErrorString(e));
+  } else {
+    const int span = (int)(((int64_t)n + COL_BLOCKS - 1) / COL_BLOCKS);
+    const unsigned gw = grid_for((int64_t)n * 64, 256, 65535);
+    k_blk_count<<<gw, 256, 0, s>>>(n, g->owned_rp, g->owned_col, span, cnt);
+    scan_u32(cnt, g->rpb, len, tiles, s);
+    k_blk_place<<<gw, 256, 0, s>>>(n, g->owned_rp, g->owned_col, span, g->rpb, g->colb);
+    e = hipGetLastError();
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) st = fail(ctx, CQ_E_DEVICE, "building column blocks: %s", hipGetErrorString(e));
+  }
+  if (cnt) (void)hipFree(cnt);
+  if (tiles) (void)hipFree(tiles);
+  if (st != CQ_OK) {
+    if (g->rpb) (void)hipFree(g->rpb);
+    if (g->colb) (void)hipFree(g->colb);
+    g->rpb = nullptr;
+    g->colb = nullptr;
+  }
+  return st;
+}
 
 // Builds the renumbered copy of a graph (see CQ_GRAPH_REORDER in cq.h).
 cq_status build_locality_order(cq_context* ctx, cq_graph* g, const int32_t* rp, const int32_t* col) {
@@ -561,9 +613,10 @@ cq_status build_locality_order(cq_context* ctx, cq_graph* g, const int32_t* rp, 
     k_new_degree<<<gn, 256, 0, s>>>(n, rp, g->owned_perm, cnt);
     scan_u32(cnt, reinterpret_cast<u32*>(g->owned_rp), n, tiles, s);
     k_relabel_rows<<<gw, 256, 0, s>>>(n, rp, col, g->owned_perm, newid, g->owned_rp, g->owned_col);
+    if (n <= BLOCK_MAX_N) st = build_column_blocks(ctx, g);
     e = hipGetLastError();
     if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (e != hipSuccess) st = fail(ctx, CQ_E_DEVICE, "renumbering the graph: %s", hipGetErrorString(e));
+    if (st == CQ_OK && e != hipSuccess) st = fail(ctx, CQ_E_DEVICE, "renumbering the graph: %s", hipGetErrorString(e));
   }
   for (void* p : {(void*)lpA, (void*)lpB, (void*)newid, (void*)cnt, (void*)start, (void*)tiles})
     if (p) (void)hipFree(p);
@@ -573,6 +626,7 @@ cq_status build_locality_order(cq_context* ctx, cq_graph* g, const int32_t* rp, 
     g->perm = g->owned_perm;
     g->reordered = CQ_GRAPH_REORDER;
     g->owned_bytes = (int64_t)(4 * ((size_t)n + 1) + 4 * (size_t)nnz + 4 * (size_t)n);
+    if (g->rpb) g->owned_bytes += (int64_t)(4 * ((size_t)COL_BLOCKS * ((size_t)n + 1) + 1) + 4 * (size_t)nnz);
   }
   return st;
 }
@@ -841,7 +895,7 @@ size_t aup(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 
 cq_status status_of_flags(u32 f) {
   if (f & F_LABEL) return CQ_E_LABEL_RANGE;
-  if (f & F_STACK) return CQ_E_DEVICE;
+  if (f & (F_STACK | F_SEGMENT)) return CQ_E_DEVICE;
   if (f & F_EXPORT) return CQ_E_CAPACITY;
   return CQ_OK;
 }

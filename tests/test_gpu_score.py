@@ -164,18 +164,28 @@ def test_errors(cq, ctx, reorder):
     assert e.value.status == cq.CQ_E_NO_EDGES
 
 
-def test_deterministic_and_workspace_reuse(cq, ctx):
+@pytest.mark.parametrize("pct", [0, 30])
+def test_deterministic_and_workspace_reuse(cq, ctx, pct):
     rp, ci, lab, L = lfr_case("m100k_mu0.5", 13)
-    note("m100k_mu0.5 repeated runs, plain and reordered graph")
+    if pct:
+        lab = perturb_labels(torch.as_tensor(lab), L, pct / 100, 77).numpy()
+    note(f"m100k_mu0.5 perturbed {pct}%: repeated runs, plain and reordered graph")
     g = cq.Graph(ctx, torch.as_tensor(rp).cuda(), torch.as_tensor(ci).cuda())
     g2 = cq.Graph(ctx, torch.as_tensor(rp).cuda(), torch.as_tensor(ci).cuda(), reorder=True)
     assert g2.stats["owned_bytes"] > 0
     lab_t = torch.as_tensor(lab).cuda()
+    ws = ctx.workspace(max(g.workspace_size(L), g2.workspace_size(L)))
     first, _, _ = cq.score_partition(g, lab_t, L)
-    for _ in range(3):
-        again, _, _ = cq.score_partition(g, lab_t, L)
+    o = oracle.score(rp, ci, lab, L).result
+    check_score(first, o, f"m100k_mu0.5 perturbed {pct}%")
+    for _ in range(4):
+        # a workspace full of 0xFF: a staged slot the kernels fail to write reads as an
+        # out-of-range label and changes the counts
+        ws.fill_(255)
+        again, _, _ = cq.score_partition(g, lab_t, L, workspace=ws)
         assert again == first  # bitwise: every float compared with ==
-        other, _, _ = cq.score_partition(g2, lab_t, L)
+        ws.fill_(255)
+        other, _, _ = cq.score_partition(g2, lab_t, L, workspace=ws)
         assert other == first  # the node order of the stored graph changes no bit of the result
     g.close()
     g2.close()
