@@ -239,7 +239,8 @@ __global__ __launch_bounds__(256) void k_relabel_rows(int n, const int32_t* __re
 // Column blocks of the renumbered graph.  The id range is cut into COL_BLOCKS spans of
 // `span` ids; block y holds, row by row, the entries whose neighbour lies in span y, as
 // its own CSR whose row pointers RPB[y*(n+1) + u] index one array colb shared by all
-// blocks (block y's entries follow block y-1's).  One wave per row.
+// blocks (block y's entries follow block y-1's); rowb holds the row of every entry.
+// One wave per row.
 constexpr int COL_BLOCKS = 8;
 
 __global__ __launch_bounds__(256) void k_blk_count(int n, const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
@@ -264,7 +265,8 @@ __global__ __launch_bounds__(256) void k_blk_count(int n, const int32_t* __restr
 }
 
 __global__ __launch_bounds__(256) void k_blk_place(int n, const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
-                                                   int span, const u32* __restrict__ RPB, int32_t* __restrict__ colb) {
+                                                   int span, const u32* __restrict__ RPB, int32_t* __restrict__ colb,
+                                                   int32_t* __restrict__ rowb) {
   const int lane = threadIdx.x & 63;
   const u64 below = lane ? (~0ull >> (64 - lane)) : 0ull;
   const size_t wave = ((size_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
@@ -284,7 +286,10 @@ __global__ __launch_bounds__(256) void k_blk_place(int n, const int32_t* __restr
         if (y == b) slot = base + (u32)__popcll(m & below);
         if (lane == b) fill_b += (u32)__popcll(m);
       }
-      if (in) colb[slot] = v;
+      if (in) {
+        colb[slot] = v;
+        rowb[slot] = (int32_t)u;
+      }
     }
   }
 }
@@ -614,60 +619,146 @@ __global__ __launch_bounds__(GROWS) void k_gather(int n, const int32_t* __restri
 }
 
 // Edge pass over a column-blocked graph.  Workgroup i runs on XCD i % 8 (workgroups
-// are handed to the XCDs in turn), and XCD x walks column blocks x, x+8, ... so every
-// neighbour label it reads lies in the span of ids its own L2 holds.  A workgroup takes
-// BT_ROWS consecutive rows of one block; rows with equal labels that follow each other
-// form a run, whose entries are given consecutive places in the community's segment
-// by one atomic add on that community's cursor.  Entries of a run are then written in
-// entry order (place = run start + index inside the run), so only the run, not the
-// row, of an entry has to be looked up.
+// are handed to the XCDs in turn) and takes entries of column block y = i % 8, so every
+// neighbour label an XCD reads lies in the span of ids its own L2 holds.  Two kinds of
+// tile share the work of block y: own-span tiles take rows of span y itself (most
+// entries: a row's community mostly lies in its own span; the labels of ids near the
+// tile are staged in LDS), far tiles take the block's entries in the rows of the other
+// spans as a list of (row, neighbour) pairs (under one entry per row, so per-row
+// headers would cost more than the entries).  In a tile, rows with equal labels that
+// follow each other form a run; one atomic add on the community's cursor gives the run
+// consecutive places in the community's segment, and each entry goes to run start +
+// its index in the run.
 constexpr int BT_THREADS = 256;
-constexpr int BT_ROWS = 1024;  // rows per workgroup (4 per thread)
+constexpr int BT_UNROLL = 8;     // entries in flight per thread
+constexpr int BT_HALO = 4096;    // OWN tiles keep labels of ids within this distance of their rows in LDS
+constexpr int BT_RPT = 4;                        // rows per thread in own-span tiles
+constexpr int BT_ROWS = BT_THREADS * BT_RPT;     // rows per own-span tile
+constexpr int FT_EPT = 8;                        // far entries per thread
+constexpr int FT_ENT = BT_THREADS * FT_EPT;      // far entries per tile
+
+// Far entries of column block y: colb/rowb ranges [b[y][0], b[y][1]) (rows before span y)
+// and [b[y][2], b[y][3]) (rows after it), row-major.
+struct FarTable {
+  u32 b[COL_BLOCKS][4];
+};
+
 template <class LT>
-__global__ __launch_bounds__(BT_THREADS) void k_gather_blk(int n, int tiles, const u32* __restrict__ RPB,
-                                                           const int32_t* __restrict__ colb, const LT* __restrict__ labx,
-                                                           const u32* __restrict__ start, const u32* __restrict__ D,
-                                                           u32* __restrict__ cursor, Ctl* __restrict__ ctl,
-                                                           LT* __restrict__ CB) {
-  __shared__ u32 s_re[BT_ROWS + 1];  // first entry of run q (tile-relative); s_re[nruns] = entry count
-  __shared__ u32 s_rl[BT_ROWS];      // label of run q, then the segment place of its first entry (or SENT)
-  __shared__ u32 s_w[BT_THREADS / 64];
-  const u32 bi = blockIdx.x, xcd = bi % 8u, k = bi / 8u;
-  const u32 y = xcd + 8u * (k / (u32)tiles);
-  const long long r0 = (long long)(k % (u32)tiles) * BT_ROWS;
-  if (y >= (u32)COL_BLOCKS || r0 >= n) return;
+struct GatherLds {
+  static constexpr int PER = 16 / (int)sizeof(LT);             // labels per 16-byte word
+  static constexpr int WINV = (BT_ROWS + 2 * BT_HALO) / PER + 1;  // 16-byte words of the label window
+  static constexpr int RUN_WORDS = (2 * BT_ROWS + 1 + 3) & ~3;    // s_re + s_rl, padded to 16 bytes
+  static constexpr int OWN = RUN_WORDS + 4 * WINV;
+  static constexpr int FAR = 2 * FT_ENT + 1;
+  static constexpr int WORDS = OWN > FAR ? OWN : FAR;
+};
+
+// Block-wide run numbering: `heads` marks (bit j) the thread's items that start a run.
+// Returns the number of heads before this thread's items; *nruns gets the total.
+__device__ __forceinline__ u32 runs_before(u32 heads, u32* s_w, u32* nruns) {
+  const u32 nh = (u32)__popc(heads);
+  const u32 incl = wave_incl_scan(nh);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 63) s_w[w] = incl;
+  __syncthreads();
+  u32 q = incl - nh, tot = 0;
+  for (int i = 0; i < BT_THREADS / 64; ++i) {
+    if (i < w) q += s_w[i];
+    tot += s_w[i];
+  }
+  *nruns = tot;
+  return q;
+}
+
+// Gives every run (label c = s_lab[r], entries s_first[r] .. s_first[r+1]) consecutive
+// places in segment c: s_lab[r] becomes the place of its first entry, or SENT.
+template <class LT>
+__device__ __forceinline__ void claim_runs(u32 nruns, const u32* s_first, u32* s_lab, const u32* __restrict__ start,
+                                           const u32* __restrict__ D, u32* __restrict__ cursor, Ctl* __restrict__ ctl) {
+  for (u32 r = threadIdx.x; r < nruns; r += BT_THREADS) {
+    const u32 c = s_lab[r];
+    const u32 tot = s_first[r + 1] - s_first[r];
+    u32 base = SENT;
+    if (c != (u32)LabelT<LT>::SENTINEL && tot > 0) {
+      const u32 old = atomicAdd(&cursor[c], tot);
+      if (old + tot <= D[c]) base = start[c] + old;  // < 2^31, so never the SENT marker
+      else atomicOr(&ctl->flags, F_SEGMENT);  // never expected: the block counts disagree with the degrees
+    }
+    s_lab[r] = base;
+  }
+}
+
+// Own-span tile t of block y: rows [s0 + t*BT_ROWS, ...) of span y, their block-y entries.
+template <class LT>
+__device__ void gather_own_tile(u32 y, u32 t, int n, int span, const u32* __restrict__ RPB,
+                                const int32_t* __restrict__ colb, const LT* __restrict__ labx,
+                                const u32* __restrict__ start, const u32* __restrict__ D, u32* __restrict__ cursor,
+                                Ctl* __restrict__ ctl, LT* __restrict__ CB, u32* lds, u32* s_w) {
+  using LL = GatherLds<LT>;
+  constexpr int PER = LL::PER;
+  constexpr int WIT = (LL::WINV + BT_THREADS - 1) / BT_THREADS;
+  u32* s_re = lds;                   // staged row starts, then first entry of run q (tile-relative)
+  u32* s_rl = lds + BT_ROWS + 1;     // staged row labels, then label of run q, then its segment place
+  uint4* s_win = reinterpret_cast<uint4*>(lds + LL::RUN_WORDS);  // labels of ids [w0, w1)
+  const long long s0 = min((long long)n, (long long)y * span), s1 = min((long long)n, s0 + span);
+  const long long r0 = s0 + (long long)t * BT_ROWS, r1 = min(s1, r0 + BT_ROWS);
+  if (r0 >= r1) return;
   const u32* rpb = RPB + (size_t)y * ((size_t)n + 1);
-  const int rows = (int)min((long long)BT_ROWS, (long long)n - r0);
-  const u32 e0 = rpb[r0], e1 = rpb[r0 + rows];
+  const int rows = (int)(r1 - r0);
+  const u32 e0 = rpb[r0], e1 = rpb[r1];
   if (e0 == e1) return;
   const int tid = threadIdx.x;
-  // rows 4*tid .. 4*tid+3 of the tile: run heads where the label changes
-  u32 lab[4], beg[4];
-  u32 heads = 0;
-  const int rb = 4 * tid;
-  u32 prev = rb > 0 && rb - 1 < rows ? (u32)labx[r0 + rb - 1] : 0xFFFFFFFFu;
+  // Stage the tile's row starts and labels and the label window (coalesced; every load
+  // is issued before the first one is used), then each thread takes BT_RPT rows.
+  const long long w0 = (max(0ll, r0 - BT_HALO) / PER) * PER;
+  const long long w1 = max(w0, (min((long long)n, r1 + BT_HALO) / PER) * PER);
+  {
+    u32 ra[BT_RPT], rl[BT_RPT];
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < BT_RPT; ++j) {
+      const int r = min(tid + j * BT_THREADS, rows - 1);
+      ra[j] = rpb[r0 + r];
+      rl[j] = (u32)labx[r0 + r];
+    }
+    const uint4* src = reinterpret_cast<const uint4*>(labx + w0);
+    const int nv = (int)((w1 - w0) / PER);
+    uint4 wv[WIT];
+#pragma unroll
+    for (int j = 0; j < WIT; ++j) {
+      const int i = tid + j * BT_THREADS;
+      if (i < nv) wv[j] = src[i];
+    }
+#pragma unroll
+    for (int j = 0; j < BT_RPT; ++j) {
+      const int r = tid + j * BT_THREADS;
+      if (r < rows) {
+        s_re[r] = ra[j] - e0;
+        s_rl[r] = rl[j];
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < WIT; ++j) {
+      const int i = tid + j * BT_THREADS;
+      if (i < nv) s_win[i] = wv[j];
+    }
+  }
+  __syncthreads();
+  u32 lab[BT_RPT], beg[BT_RPT];
+  u32 heads = 0;
+  const int rb = BT_RPT * tid;
+  u32 prev = rb > 0 && rb - 1 < rows ? s_rl[rb - 1] : 0xFFFFFFFFu;
+#pragma unroll
+  for (int j = 0; j < BT_RPT; ++j) {
     const int r = rb + j;
-    lab[j] = r < rows ? (u32)labx[r0 + r] : 0u;
-    beg[j] = r < rows ? rpb[r0 + r] - e0 : 0u;
+    lab[j] = r < rows ? s_rl[r] : 0u;
+    beg[j] = r < rows ? s_re[r] : 0u;
     if (r < rows && (r == 0 || lab[j] != prev)) heads |= 1u << j;
     prev = lab[j];
   }
-  // exclusive scan of head counts over the workgroup gives each head its run index
-  const u32 nh = (u32)__popc(heads);
-  const u32 incl = wave_incl_scan(nh);
-  const int w = tid >> 6;
-  if ((tid & 63) == 63) s_w[w] = incl;
-  __syncthreads();
-  u32 q = incl - nh;
-  u32 nruns = 0;
-  for (int i = 0; i < BT_THREADS / 64; ++i) {
-    if (i < w) q += s_w[i];
-    nruns += s_w[i];
-  }
+  u32 nruns;
+  u32 q = runs_before(heads, s_w, &nruns);  // its barrier also ends the reads of staged rows
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
+  for (int j = 0; j < BT_RPT; ++j) {
     if (heads & (1u << j)) {
       s_re[q] = beg[j];
       s_rl[q] = lab[j];
@@ -676,29 +767,128 @@ __global__ __launch_bounds__(BT_THREADS) void k_gather_blk(int n, int tiles, con
   }
   if (tid == 0) s_re[nruns] = e1 - e0;
   __syncthreads();
-  for (u32 r = tid; r < nruns; r += BT_THREADS) {
-    const u32 c = s_rl[r];
-    const u32 tot = s_re[r + 1] - s_re[r];
-    u32 base = SENT;
-    if (c != (u32)LabelT<LT>::SENTINEL && tot > 0) {
-      const u32 old = atomicAdd(&cursor[c], tot);
-      if (old + tot <= D[c]) base = start[c] + old;  // < 2^31, so never the SENT marker
-      else atomicOr(&ctl->flags, F_SEGMENT);  // never expected: the block counts disagree with the degrees
-    }
-    s_rl[r] = base;
-  }
+  claim_runs<LT>(nruns, s_re, s_rl, start, D, cursor, ctl);
   __syncthreads();
   const int32_t* cb = colb + e0;
-  for (u32 e = tid; e < e1 - e0; e += BT_THREADS) {
-    u32 lo = 0, hi = nruns - 1;  // last run r with s_re[r] <= e
-    while (lo < hi) {
-      const u32 mid = (lo + hi + 1) >> 1;
-      if (s_re[mid] <= e) lo = mid; else hi = mid - 1;
+  const u32 ne = e1 - e0;
+  for (u32 eb = tid; eb < ne; eb += BT_THREADS * BT_UNROLL) {
+    int v[BT_UNROLL];
+    u32 pos[BT_UNROLL];
+#pragma unroll
+    for (int u = 0; u < BT_UNROLL; ++u) v[u] = cb[min(eb + (u32)(u * BT_THREADS), ne - 1u)];  // in bounds; masked below
+#pragma unroll
+    for (int u = 0; u < BT_UNROLL; ++u) {
+      const u32 e = eb + (u32)(u * BT_THREADS);
+      u32 lo = 0, hi = nruns - 1;  // last run r with s_re[r] <= e
+      while (lo < hi) {
+        const u32 mid = (lo + hi + 1) >> 1;
+        if (s_re[mid] <= e) lo = mid; else hi = mid - 1;
+      }
+      const u32 base = s_rl[lo];
+      pos[u] = (e < ne && base != SENT) ? base + (e - s_re[lo]) : SENT;
     }
-    const u32 base = s_rl[lo];
-    if (base == SENT) continue;
-    CB[base + (e - s_re[lo])] = labx[cb[e]];
+    LT x[BT_UNROLL];
+#pragma unroll
+    for (int u = 0; u < BT_UNROLL; ++u) {
+      const u32 off = (u32)((long long)v[u] - w0);
+      x[u] = off < (u32)(w1 - w0) ? reinterpret_cast<const LT*>(s_win)[off] : labx[v[u]];
+    }
+#pragma unroll
+    for (int u = 0; u < BT_UNROLL; ++u)
+      if (pos[u] != SENT) CB[pos[u]] = x[u];
   }
+}
+
+// Far tile t of block y: FT_ENT consecutive entries of the block's far ranges.
+template <class LT>
+__device__ void gather_far_tile(u32 y, u32 t, const FarTable& ft, const int32_t* __restrict__ colb,
+                                const int32_t* __restrict__ rowb, const LT* __restrict__ labx,
+                                const u32* __restrict__ start, const u32* __restrict__ D, u32* __restrict__ cursor,
+                                Ctl* __restrict__ ctl, LT* __restrict__ CB, u32* lds, u32* s_w) {
+  u32* s_rf = lds;               // first entry of run q (tile-relative); s_rf[nruns] = entry count
+  u32* s_rb = lds + FT_ENT + 1;  // staged row labels, then label of run q, then its segment place
+  const u32 b0 = ft.b[y][0], b1 = ft.b[y][1], b2 = ft.b[y][2], b3 = ft.b[y][3];
+  const u32 t1 = (b1 - b0 + FT_ENT - 1) / FT_ENT;
+  u32 e0, e1;
+  if (t < t1) {
+    e0 = b0 + t * FT_ENT;
+    e1 = min(b1, e0 + FT_ENT);
+  } else {
+    e0 = b2 + (t - t1) * FT_ENT;
+    if (e0 >= b3) return;
+    e1 = min(b3, e0 + FT_ENT);
+  }
+  const u32 ne = e1 - e0;
+  const int tid = threadIdx.x;
+  const u32 i0 = (u32)tid * FT_EPT;  // this thread's entries i0 .. i0+FT_EPT-1 (tile-relative)
+  LT x[FT_EPT];
+  u32 lab[FT_EPT];
+#pragma unroll
+  for (int j = 0; j < FT_EPT; ++j) {
+    const u32 e = e0 + min(i0 + (u32)j, ne - 1u);  // in bounds; entries past ne are masked below
+    x[j] = labx[colb[e]];  // the neighbour labels are loaded now and used after the runs are placed
+    lab[j] = (u32)labx[rowb[e]];
+  }
+#pragma unroll
+  for (int j = 0; j < FT_EPT; ++j)
+    if (i0 + (u32)j < ne) s_rb[i0 + j] = lab[j];
+  __syncthreads();
+  u32 prev = (i0 > 0 && i0 - 1 < ne) ? s_rb[i0 - 1] : 0xFFFFFFFFu;
+  u32 heads = 0;
+#pragma unroll
+  for (int j = 0; j < FT_EPT; ++j) {
+    const u32 i = i0 + (u32)j;
+    if (i < ne && (i == 0 || lab[j] != prev)) heads |= 1u << j;
+    prev = lab[j];
+  }
+  u32 nruns;
+  const u32 q0 = runs_before(heads, s_w, &nruns);  // its barrier also ends the reads of staged labels
+  {
+    u32 q = q0;
+#pragma unroll
+    for (int j = 0; j < FT_EPT; ++j) {
+      if (heads & (1u << j)) {
+        s_rf[q] = i0 + (u32)j;
+        s_rb[q] = lab[j];
+        ++q;
+      }
+    }
+  }
+  if (tid == 0) s_rf[nruns] = ne;
+  __syncthreads();
+  claim_runs<LT>(nruns, s_rf, s_rb, start, D, cursor, ctl);
+  __syncthreads();
+  u32 q = q0;  // runs started up to entry i0 + j
+#pragma unroll
+  for (int j = 0; j < FT_EPT; ++j) {
+    const u32 i = i0 + (u32)j;
+    if (heads & (1u << j)) ++q;
+    if (i >= ne) continue;
+    const u32 run = q - 1u;  // entry i lies in the last run that starts at or before it
+    const u32 base = s_rb[run];
+    if (base != SENT) CB[base + (i - s_rf[run])] = x[j];
+  }
+}
+
+// One launch for both kinds of tile.  Groups of 8 consecutive workgroups (one per XCD,
+// so workgroup i serves block i % 8): the own-span groups first (they carry most
+// entries), then the far groups.
+template <class LT>
+__global__ __launch_bounds__(BT_THREADS) void k_gather_blocked(int n, int span, const u32* __restrict__ RPB,
+                                                               const int32_t* __restrict__ colb,
+                                                               const int32_t* __restrict__ rowb, FarTable ft,
+                                                               u32 own_groups, u32 far_groups,
+                                                               const LT* __restrict__ labx, const u32* __restrict__ start,
+                                                               const u32* __restrict__ D, u32* __restrict__ cursor,
+                                                               Ctl* __restrict__ ctl, LT* __restrict__ CB) {
+  __shared__ __align__(16) u32 lds[GatherLds<LT>::WORDS];
+  __shared__ u32 s_w[BT_THREADS / 64];
+  const u32 y = blockIdx.x % 8u, gi = blockIdx.x / 8u;
+  if (y >= (u32)COL_BLOCKS || gi >= own_groups + far_groups) return;
+  if (gi < own_groups)
+    gather_own_tile<LT>(y, gi, n, span, RPB, colb, labx, start, D, cursor, ctl, CB, lds, s_w);
+  else
+    gather_far_tile<LT>(y, gi - own_groups, ft, colb, rowb, labx, start, D, cursor, ctl, CB, lds, s_w);
 }
 
 // Comparison: the segment of ground-truth community a_u receives b_u.

@@ -53,6 +53,9 @@ struct cq_graph {
   int32_t* owned_perm = nullptr;
   u32* rpb = nullptr;              // column blocks (owned; null when the graph is not blocked)
   int32_t* colb = nullptr;
+  int32_t* rowb = nullptr;
+  FarTable far{};                  // per block: entry ranges of the rows outside its span
+  unsigned far_tiles = 0;          // most far-entry tiles of any block
   int64_t owned_bytes = 0;
   ~cq_graph() {
     if (owned_rp) (void)hipFree(owned_rp);
@@ -60,6 +63,7 @@ struct cq_graph {
     if (owned_perm) (void)hipFree(owned_perm);
     if (rpb) (void)hipFree(rpb);
     if (colb) (void)hipFree(colb);
+    if (rowb) (void)hipFree(rowb);
   }
 };
 
@@ -340,9 +344,11 @@ void score_launch(cq_context* ctx, const cq_graph* g, const int32_t* labels, int
   {
     StageMark mk(ctx, ST_GATHER, timed);
     if (g->rpb) {
-      const int tiles = (int)((n + BT_ROWS - 1) / BT_ROWS);
-      k_gather_blk<LT><<<(unsigned)(COL_BLOCKS * tiles), BT_THREADS, 0, s>>>((int)n, tiles, g->rpb, g->colb, labx, start, D,
-                                                                           at<u32>(ws, lay.cursor), ctl, CB);
+      const int64_t span = (n + COL_BLOCKS - 1) / COL_BLOCKS;
+      const unsigned own_groups = (unsigned)((span + BT_ROWS - 1) / BT_ROWS);
+      k_gather_blocked<LT><<<COL_BLOCKS * (own_groups + g->far_tiles), BT_THREADS, 0, s>>>(
+          (int)n, (int)span, g->rpb, g->colb, g->rowb, g->far, own_groups, g->far_tiles, labx, start, D,
+          at<u32>(ws, lay.cursor), ctl, CB);
     } else if (lay.priv)
       k_gather<true, LT><<<grid_for(n, GROWS, 1u << 30), GROWS, 0, s>>>((int)n, g->rp, g->col, labx, L, lay.chunk, PM, start, loc, CB);
     else
@@ -547,6 +553,7 @@ cq_status build_column_blocks(cq_context* ctx, cq_graph* g) {
   };
   alloc((void**)&g->rpb, 4 * ((size_t)len + 1));
   alloc((void**)&g->colb, 4 * (size_t)nnz);
+  alloc((void**)&g->rowb, 4 * (size_t)nnz);
   alloc((void**)&cnt, 4 * (size_t)len);
   alloc((void**)&tiles, 4 * ((size_t)((len + SCAN_TILE - 1) / SCAN_TILE) + 1));
   cq_status st = CQ_OK;
@@ -557,9 +564,19 @@ cq_status build_column_blocks(cq_context* ctx, cq_graph* g) {
     const unsigned gw = grid_for((int64_t)n * 64, 256, 65535);
     k_blk_count<<<gw, 256, 0, s>>>(n, g->owned_rp, g->owned_col, span, cnt);
     scan_u32(cnt, g->rpb, len, tiles, s);
-    k_blk_place<<<gw, 256, 0, s>>>(n, g->owned_rp, g->owned_col, span, g->rpb, g->colb);
+    k_blk_place<<<gw, 256, 0, s>>>(n, g->owned_rp, g->owned_col, span, g->rpb, g->colb, g->rowb);
     e = hipGetLastError();
     if (e == hipSuccess) e = hipStreamSynchronize(s);
+    // far-entry ranges of every block: rows [0, s0) and [s1, n), s0..s1 being its span
+    g->far_tiles = 0;
+    for (int y = 0; y < COL_BLOCKS && e == hipSuccess; ++y) {
+      const int64_t s0 = std::min<int64_t>(n, (int64_t)y * span), s1 = std::min<int64_t>(n, s0 + span);
+      const int64_t at_row[4] = {0, s0, s1, n};
+      for (int j = 0; j < 4 && e == hipSuccess; ++j)
+        e = hipMemcpy(&g->far.b[y][j], g->rpb + (size_t)y * ((size_t)n + 1) + at_row[j], 4, hipMemcpyDeviceToHost);
+      const u32 t = (g->far.b[y][1] - g->far.b[y][0] + FT_ENT - 1) / FT_ENT + (g->far.b[y][3] - g->far.b[y][2] + FT_ENT - 1) / FT_ENT;
+      g->far_tiles = std::max(g->far_tiles, (unsigned)t);
+    }
     if (e != hipSuccess) st = fail(ctx, CQ_E_DEVICE, "building column blocks: %s", hipGetErrorString(e));
   }
   if (cnt) (void)hipFree(cnt);
@@ -567,8 +584,10 @@ cq_status build_column_blocks(cq_context* ctx, cq_graph* g) {
   if (st != CQ_OK) {
     if (g->rpb) (void)hipFree(g->rpb);
     if (g->colb) (void)hipFree(g->colb);
+    if (g->rowb) (void)hipFree(g->rowb);
     g->rpb = nullptr;
     g->colb = nullptr;
+    g->rowb = nullptr;
   }
   return st;
 }
@@ -626,7 +645,7 @@ cq_status build_locality_order(cq_context* ctx, cq_graph* g, const int32_t* rp, 
     g->perm = g->owned_perm;
     g->reordered = CQ_GRAPH_REORDER;
     g->owned_bytes = (int64_t)(4 * ((size_t)n + 1) + 4 * (size_t)nnz + 4 * (size_t)n);
-    if (g->rpb) g->owned_bytes += (int64_t)(4 * ((size_t)COL_BLOCKS * ((size_t)n + 1) + 1) + 4 * (size_t)nnz);
+    if (g->rpb) g->owned_bytes += (int64_t)(4 * ((size_t)COL_BLOCKS * ((size_t)n + 1) + 1) + 8 * (size_t)nnz);
   }
   return st;
 }
