@@ -93,6 +93,7 @@ const char* cq_stage_name(int32_t s);
 /* Flags for cq_graph_load. */
 #define CQ_VALIDATE_GRAPH 1u  /* also check symmetry (rows must be sorted), no self-loops, no repeated entries */
 #define CQ_GRAPH_REORDER 2u   /* store the graph in a locality order (see cq_graph_load) */
+#define CQ_GRAPH_NO_BLOCKS 4u /* with CQ_GRAPH_REORDER: skip the column blocks (see cq_graph_load) */
 
 typedef struct {
   int64_t n;           /* |V| */
@@ -100,7 +101,8 @@ typedef struct {
   int64_t m;           /* |E| */
   int64_t max_degree;
   uint32_t validated;  /* CQ_VALIDATE_GRAPH if the full check ran and passed */
-  uint32_t reordered;  /* CQ_GRAPH_REORDER if the graph is stored in a locality order */
+  uint32_t reordered;  /* CQ_GRAPH_REORDER if the graph is stored in a locality order, plus
+                          CQ_GRAPH_NO_BLOCKS if it is stored without column blocks */
   int64_t owned_bytes; /* device memory the graph handle allocated (0 without CQ_GRAPH_REORDER) */
 } cq_graph_stats;
 
@@ -121,6 +123,11 @@ typedef struct {
  * so that the neighbours of a row mostly have nearby ids.  Labels passed to scoring
  * calls keep the caller's node numbering; every result is identical with and without
  * the flag.  The borrowed arrays are not read after the load returns.
+ * When n <= 2^24 the copy is also kept as 8 column blocks, one per XCD of the device
+ * (the edge pass then reads each neighbour label from one XCD's L2), with a plan that
+ * moves labels from the caller's order to the stored one: a further
+ * 4(8(n+1)+1) + 8 nnz + 12n + 4(n/32768 + 2) bytes.  CQ_GRAPH_NO_BLOCKS skips them.
+ * owned_bytes in cq_graph_stats reports the total.
  */
 cq_status cq_graph_load(cq_context* ctx, int32_t n, int64_t nnz, const int32_t* d_row_ptr,
                         const int32_t* d_col_idx, uint32_t flags, cq_graph** out);

@@ -29,6 +29,7 @@ CQ_E_CANCELLED = -9
 CQ_E_CAPACITY = -10
 CQ_VALIDATE_GRAPH = 1
 CQ_GRAPH_REORDER = 2
+CQ_GRAPH_NO_BLOCKS = 4
 
 _P = ctypes.c_void_p
 _I32 = ctypes.c_int32
@@ -406,7 +407,8 @@ class Context:
 class Graph:
     """A registered graph; keeps its CSR tensors alive while registered."""
 
-    def __init__(self, ctx: Context, row_ptr, col_idx, validate: bool = False, reorder: bool = False):
+    def __init__(self, ctx: Context, row_ptr, col_idx, validate: bool = False, reorder: bool = False,
+                 blocks: bool = True):
         self.ctx = ctx
         self.row_ptr = _dev_i32(row_ptr, "row_ptr")
         self.col_idx = _dev_i32(col_idx, "col_idx")
@@ -414,7 +416,8 @@ class Graph:
         self.nnz = self.col_idx.numel()
         self.handle = cq_graph_load(ctx.handle, self.n, self.nnz, self.row_ptr.data_ptr(),
                                     self.col_idx.data_ptr() if self.nnz else None,
-                                    (CQ_VALIDATE_GRAPH if validate else 0) | (CQ_GRAPH_REORDER if reorder else 0))
+                                    (CQ_VALIDATE_GRAPH if validate else 0) | (CQ_GRAPH_REORDER if reorder else 0)
+                                    | (CQ_GRAPH_NO_BLOCKS if reorder and not blocks else 0))
         self.stats = cq_graph_get_stats(self.handle)
 
     def workspace_size(self, num_labels: int) -> int:

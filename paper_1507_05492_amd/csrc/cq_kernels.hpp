@@ -306,6 +306,138 @@ struct LabelT {
   static constexpr LT SENTINEL = (LT)~(LT)0;  // "no label" marker in staged label arrays
 };
 
+// Label permutation plan (load time).  Scoring calls receive labels in the caller's
+// node order, the kernels want them in the stored order.  A random gather costs a
+// whole cache line per label, so the move is done in two streaming passes instead:
+// node u (caller order) first writes its label to tmp[pos1[u]], where tmp is grouped
+// into buckets of 2^PERM_SHIFT stored ids (bucket b = newid >> PERM_SHIFT); then one
+// workgroup per bucket copies every slot j of the bucket to labx[tgt[j]] through LDS
+// (the bucket's labels fit there) and writes the bucket's labels out in order.  The
+// order inside a bucket is whatever the atomics gave.
+constexpr int PERM_SHIFT = 15;  // 32768 stored ids per bucket: 64 KB of 16-bit labels
+
+// Each workgroup counts its nodes per bucket in LDS, reserves a range of every bucket
+// with one global atomic, and places its nodes inside those ranges.
+constexpr int PERM_NODES = 8192;  // nodes per workgroup of the plan kernels
+constexpr int PERM_MAX_BUCKETS = 1024;  // n up to 2^25
+
+__global__ __launch_bounds__(256) void k_perm_count(int n, const int32_t* __restrict__ newid, int nb, u32* __restrict__ bcnt) {
+  __shared__ u32 h[PERM_MAX_BUCKETS];
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) h[i] = 0;
+  __syncthreads();
+  const long long u0 = (long long)blockIdx.x * PERM_NODES, u1 = min((long long)n, u0 + PERM_NODES);
+  for (long long u = u0 + threadIdx.x; u < u1; u += blockDim.x) atomicAdd(&h[(u32)newid[u] >> PERM_SHIFT], 1u);
+  __syncthreads();
+  for (int i = threadIdx.x; i < nb; i += blockDim.x)
+    if (h[i]) atomicAdd(&bcnt[i], h[i]);
+}
+
+__global__ __launch_bounds__(256) void k_perm_plan(int n, const int32_t* __restrict__ newid, int nb,
+                                                   const u32* __restrict__ bstart, u32* __restrict__ bcur,
+                                                   u32* __restrict__ pos1, u32* __restrict__ tgt) {
+  __shared__ u32 h[PERM_MAX_BUCKETS];
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) h[i] = 0;
+  __syncthreads();
+  const long long u0 = (long long)blockIdx.x * PERM_NODES, u1 = min((long long)n, u0 + PERM_NODES);
+  for (long long u = u0 + threadIdx.x; u < u1; u += blockDim.x) atomicAdd(&h[(u32)newid[u] >> PERM_SHIFT], 1u);
+  __syncthreads();
+  for (int i = threadIdx.x; i < nb; i += blockDim.x)
+    if (h[i]) h[i] = bstart[i] + atomicAdd(&bcur[i], h[i]);  // this workgroup's range in bucket i
+  __syncthreads();
+  for (long long u = u0 + threadIdx.x; u < u1; u += blockDim.x) {
+    const u32 v = (u32)newid[u];
+    const u32 p = atomicAdd(&h[v >> PERM_SHIFT], 1u);
+    pos1[u] = p;
+    tgt[p] = v;
+  }
+}
+
+__global__ void k_degree(int n, const int32_t* __restrict__ rp, u32* __restrict__ deg) {
+  for (size_t u = (size_t)blockIdx.x * blockDim.x + threadIdx.x; u < (size_t)n; u += (size_t)gridDim.x * blockDim.x)
+    deg[u] = (u32)(rp[u + 1] - rp[u]);
+}
+
+// Node pass in the caller's order for a renumbered graph (labels fit LDS): workgroup w
+// counts nodes and degrees per label over nodes [w*chunk, (w+1)*chunk) into its rows of
+// HN/HD, and writes each label (or the sentinel) to tmp[pos1[u]].
+template <class LT>
+__global__ __launch_bounds__(1024) void k_node_perm(int n, const int32_t* __restrict__ labels, const u32* __restrict__ deg,
+                                                    const u32* __restrict__ pos1, int L, int chunk, u32* __restrict__ HN,
+                                                    u32* __restrict__ HD, LT* __restrict__ tmp, Ctl* __restrict__ ctl) {
+  extern __shared__ u32 sh[];
+  u32* hn = sh;
+  u32* hd = sh + L;
+  __shared__ u32 s_bad;
+  for (int i = threadIdx.x; i < 2 * L; i += blockDim.x) sh[i] = 0;
+  if (threadIdx.x == 0) s_bad = 0;
+  __syncthreads();
+  const long long u0 = (long long)blockIdx.x * chunk, u1 = min((long long)n, u0 + chunk);
+  constexpr int U = 8;  // nodes per thread in flight
+  u32 bad = 0;
+  for (long long ub = u0 + threadIdx.x; ub < u1; ub += (long long)U * blockDim.x) {
+    int c[U];
+    u32 d[U], p[U];
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+      const long long u = min(ub + (long long)k * blockDim.x, u1 - 1);  // in bounds; masked below
+      c[k] = labels[u];
+      d[k] = deg[u];
+      p[k] = pos1[u];
+    }
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+      if (ub + (long long)k * blockDim.x >= u1) break;
+      if ((u32)c[k] < (u32)L) {
+        atomicAdd(&hn[c[k]], 1u);
+        atomicAdd(&hd[c[k]], d[k]);
+        tmp[p[k]] = (LT)c[k];
+      } else {
+        bad = 1;
+        tmp[p[k]] = LabelT<LT>::SENTINEL;
+      }
+    }
+  }
+  if (bad) s_bad = 1;
+  __syncthreads();
+  const size_t row = (size_t)blockIdx.x * (size_t)L;
+  for (int c = threadIdx.x; c < L; c += blockDim.x) {
+    HN[row + c] = hn[c];
+    HD[row + c] = hd[c];
+  }
+  if (threadIdx.x == 0 && s_bad) atomicOr(&ctl->flags, F_LABEL);
+}
+
+template <class LT>
+__global__ __launch_bounds__(1024) void k_perm_apply(int n, const u32* __restrict__ bstart, const u32* __restrict__ tgt,
+                                                     const LT* __restrict__ tmp, LT* __restrict__ labx) {
+  extern __shared__ uint4 sl4[];
+  LT* sl = reinterpret_cast<LT*>(sl4);
+  const u32 b = blockIdx.x, id0 = b << PERM_SHIFT;
+  const u32 j0 = bstart[b], j1 = bstart[b + 1];
+  constexpr int U = 8;
+  for (u32 jb = j0 + threadIdx.x; jb < j1; jb += U * blockDim.x) {
+    u32 t[U];
+    LT x[U];
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+      const u32 j = min(jb + (u32)k * blockDim.x, j1 - 1u);  // in bounds; masked below
+      t[k] = tgt[j];
+      x[k] = tmp[j];
+    }
+#pragma unroll
+    for (int k = 0; k < U; ++k)
+      if (jb + (u32)k * blockDim.x < j1) sl[t[k] - id0] = x[k];
+  }
+  __syncthreads();
+  // the bucket's ids [id0, id0 + cnt) are all present exactly once: write them in order
+  const u32 cnt = j1 - j0;
+  constexpr u32 PER = 16u / sizeof(LT);
+  uint4* dst = reinterpret_cast<uint4*>(labx + id0);  // id0 is a multiple of 2^PERM_SHIFT: 16-byte aligned
+  for (u32 i = threadIdx.x; i < cnt / PER; i += blockDim.x) dst[i] = sl4[i];
+  for (u32 i = (cnt / PER) * PER + threadIdx.x; i < cnt; i += blockDim.x) labx[id0 + i] = sl[i];
+}
+
+
 template <bool WEIGHTED, class LT>
 __device__ __forceinline__ void node_priv_body(int n, const int32_t* __restrict__ labels, const int32_t* __restrict__ perm,
                                                const int32_t* __restrict__ rp, int L, int chunk, u32* __restrict__ HN,

@@ -54,6 +54,11 @@ struct cq_graph {
   u32* rpb = nullptr;              // column blocks (owned; null when the graph is not blocked)
   int32_t* colb = nullptr;
   int32_t* rowb = nullptr;
+  u32* deg_in = nullptr;           // label permutation plan (caller order -> stored order): degrees,
+  u32* pos1 = nullptr;             // bucket slots and their stored ids; null when not built
+  u32* tgt = nullptr;
+  u32* pbstart = nullptr;          // first slot of every bucket (nb + 1)
+  int perm_buckets = 0;
   FarTable far{};                  // per block: entry ranges of the rows outside its span
   unsigned far_tiles = 0;          // most far-entry tiles of any block
   int64_t owned_bytes = 0;
@@ -64,6 +69,8 @@ struct cq_graph {
     if (rpb) (void)hipFree(rpb);
     if (colb) (void)hipFree(colb);
     if (rowb) (void)hipFree(rowb);
+    for (u32* p : {deg_in, pos1, tgt, pbstart})
+      if (p) (void)hipFree(p);
   }
 };
 
@@ -313,7 +320,25 @@ void score_launch(cq_context* ctx, const cq_graph* g, const int32_t* labels, int
     if (!lay.priv) fill(at<u32>(ws, lay.SZ), 2 * (size_t)L, 0, s);
     if (g->rpb) fill(at<u32>(ws, lay.cursor), (size_t)L, 0, s);
   }
-  if (lay.priv) {
+  if (lay.priv && g->rpb && g->pos1) {
+    // column-blocked graph: count in the caller's order, move labels with the bucket plan
+    // (the blocked edge pass needs no per-node offsets)
+    u32* HN = at<u32>(ws, lay.HN);
+    u32* HD = at<u32>(ws, lay.HD);
+    LT* tmp = reinterpret_cast<LT*>(loc);  // per-node offsets are not used on this path
+    {
+      StageMark mk(ctx, ST_NODE, timed);
+      k_node_perm<LT><<<lay.W, 1024, 2 * (size_t)L * 4, s>>>((int)n, labels, g->deg_in, g->pos1, L, lay.chunk, HN, HD, tmp,
+                                                             ctl);
+      k_perm_apply<LT><<<g->perm_buckets, 1024, ((size_t)1 << PERM_SHIFT) * sizeof(LT), s>>>((int)n, g->pbstart, g->tgt, tmp,
+                                                                                          labx);
+    }
+    {
+      StageMark mk(ctx, ST_COLSCAN, timed);
+      k_colscan<true, false><<<grid_for(L, 256, 1u << 30), 256, 0, s>>>(lay.W, L, HN, HD, N, D);
+    }
+    PM = HD;
+  } else if (lay.priv) {
     u32* HN = at<u32>(ws, lay.HN);
     u32* HD = at<u32>(ws, lay.HD);
     {
@@ -592,8 +617,56 @@ cq_status build_column_blocks(cq_context* ctx, cq_graph* g) {
   return st;
 }
 
+// Builds the label permutation plan of a renumbered graph from newid (caller id ->
+// stored id) and the caller's row_ptr.
+cq_status build_perm_plan(cq_context* ctx, cq_graph* g, const int32_t* newid, const int32_t* rp_in) {
+  const int n = g->n;
+  hipStream_t s = ctx->stream;
+  const int nb = (int)(((int64_t)n + (1 << PERM_SHIFT) - 1) >> PERM_SHIFT);
+  if (nb > PERM_MAX_BUCKETS) return CQ_OK;  // no plan: scoring gathers labels through perm instead
+  u32 *bcnt = nullptr, *tiles = nullptr;
+  hipError_t e = hipSuccess;
+  auto alloc = [&](void** p, size_t bytes) {
+    if (e == hipSuccess) e = hipMalloc(p, std::max<size_t>(bytes, 4));
+  };
+  alloc((void**)&g->deg_in, 4 * (size_t)n);
+  alloc((void**)&g->pos1, 4 * (size_t)n);
+  alloc((void**)&g->tgt, 4 * (size_t)n);
+  alloc((void**)&g->pbstart, 4 * ((size_t)nb + 1));
+  alloc((void**)&bcnt, 4 * ((size_t)nb + 1));
+  u32* bstart = g->pbstart;
+  alloc((void**)&tiles, 4 * ((size_t)((nb + SCAN_TILE - 1) / SCAN_TILE) + 1));
+  cq_status st = CQ_OK;
+  if (e != hipSuccess) {
+    st = fail(ctx, CQ_E_DEVICE, "allocating the label permutation plan: %s", hipGetErrorString(e));
+  } else {
+    const unsigned gn = grid_for(n, 256, 8192);
+    const unsigned gp = (unsigned)(((int64_t)n + PERM_NODES - 1) / PERM_NODES);
+    k_degree<<<gn, 256, 0, s>>>(n, rp_in, g->deg_in);
+    fill(bcnt, (size_t)nb + 1, 0, s);
+    k_perm_count<<<gp, 256, 0, s>>>(n, newid, nb, bcnt);
+    scan_u32(bcnt, bstart, nb, tiles, s);
+    fill(bcnt, (size_t)nb + 1, 0, s);
+    k_perm_plan<<<gp, 256, 0, s>>>(n, newid, nb, bstart, bcnt, g->pos1, g->tgt);
+    e = hipGetLastError();
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) st = fail(ctx, CQ_E_DEVICE, "building the label permutation plan: %s", hipGetErrorString(e));
+  }
+  for (void* p : {(void*)bcnt, (void*)tiles})
+    if (p) (void)hipFree(p);
+  if (st != CQ_OK) {
+    for (u32** p : {&g->deg_in, &g->pos1, &g->tgt, &g->pbstart}) {
+      if (*p) (void)hipFree(*p);
+      *p = nullptr;
+    }
+  } else {
+    g->perm_buckets = nb;
+  }
+  return st;
+}
+
 // Builds the renumbered copy of a graph (see CQ_GRAPH_REORDER in cq.h).
-cq_status build_locality_order(cq_context* ctx, cq_graph* g, const int32_t* rp, const int32_t* col) {
+cq_status build_locality_order(cq_context* ctx, cq_graph* g, const int32_t* rp, const int32_t* col, bool blocks) {
   const int n = g->n;
   const int64_t nnz = g->nnz;
   hipStream_t s = ctx->stream;
@@ -632,7 +705,8 @@ cq_status build_locality_order(cq_context* ctx, cq_graph* g, const int32_t* rp, 
     k_new_degree<<<gn, 256, 0, s>>>(n, rp, g->owned_perm, cnt);
     scan_u32(cnt, reinterpret_cast<u32*>(g->owned_rp), n, tiles, s);
     k_relabel_rows<<<gw, 256, 0, s>>>(n, rp, col, g->owned_perm, newid, g->owned_rp, g->owned_col);
-    if (n <= BLOCK_MAX_N) st = build_column_blocks(ctx, g);
+    if (blocks && n <= BLOCK_MAX_N) st = build_column_blocks(ctx, g);
+    if (st == CQ_OK && g->rpb) st = build_perm_plan(ctx, g, newid, rp);
     e = hipGetLastError();
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (st == CQ_OK && e != hipSuccess) st = fail(ctx, CQ_E_DEVICE, "renumbering the graph: %s", hipGetErrorString(e));
@@ -643,9 +717,10 @@ cq_status build_locality_order(cq_context* ctx, cq_graph* g, const int32_t* rp, 
     g->rp = g->owned_rp;
     g->col = g->owned_col;
     g->perm = g->owned_perm;
-    g->reordered = CQ_GRAPH_REORDER;
+    g->reordered = CQ_GRAPH_REORDER | (g->rpb ? 0u : CQ_GRAPH_NO_BLOCKS);
     g->owned_bytes = (int64_t)(4 * ((size_t)n + 1) + 4 * (size_t)nnz + 4 * (size_t)n);
     if (g->rpb) g->owned_bytes += (int64_t)(4 * ((size_t)COL_BLOCKS * ((size_t)n + 1) + 1) + 8 * (size_t)nnz);
+    if (g->pos1) g->owned_bytes += (int64_t)(12 * (size_t)n + 4 * ((size_t)g->perm_buckets + 1));
   }
   return st;
 }
@@ -1198,6 +1273,10 @@ cq_status cq_context_create(int device, void* hip_stream, cq_context** out) {
   }
   const size_t gl = std::max<size_t>(DIRECT_MAX, HASH_WORDS) * 4;
   set_big_lds(reinterpret_cast<const void*>(k_node_priv<true, uint16_t>), 2 * PRIV_MAX * 4);
+  set_big_lds(reinterpret_cast<const void*>(k_node_perm<uint16_t>), 2 * PRIV_MAX * 4);
+  set_big_lds(reinterpret_cast<const void*>(k_node_perm<uint32_t>), 2 * PRIV_MAX * 4);
+  set_big_lds(reinterpret_cast<const void*>(k_perm_apply<uint16_t>), ((size_t)1 << PERM_SHIFT) * 2);
+  set_big_lds(reinterpret_cast<const void*>(k_perm_apply<uint32_t>), ((size_t)1 << PERM_SHIFT) * 4);
   set_big_lds(reinterpret_cast<const void*>(k_node_priv<true, uint32_t>), 2 * PRIV_MAX * 4);
   set_big_lds(reinterpret_cast<const void*>(k_node_priv<false, uint32_t>), PRIV_MAX * 4);
   set_big_lds(reinterpret_cast<const void*>(k_hist_priv), PRIV_MAX * 4);
@@ -1257,7 +1336,10 @@ cq_status cq_graph_load(cq_context* ctx, int32_t n, int64_t nnz, const int32_t* 
   if (!out || !d_row_ptr || (nnz > 0 && !d_col_idx)) return fail(ctx, CQ_E_INVALID_ARG, "null pointer");
   *out = nullptr;
   if (n < 1) return fail(ctx, CQ_E_INVALID_ARG, "n must be >= 1");
-  if (flags & ~(CQ_VALIDATE_GRAPH | CQ_GRAPH_REORDER)) return fail(ctx, CQ_E_INVALID_ARG, "unknown flag bits");
+  if (flags & ~(CQ_VALIDATE_GRAPH | CQ_GRAPH_REORDER | CQ_GRAPH_NO_BLOCKS))
+    return fail(ctx, CQ_E_INVALID_ARG, "unknown flag bits");
+  if ((flags & CQ_GRAPH_NO_BLOCKS) && !(flags & CQ_GRAPH_REORDER))
+    return fail(ctx, CQ_E_INVALID_ARG, "CQ_GRAPH_NO_BLOCKS needs CQ_GRAPH_REORDER");
   if (nnz < 0 || nnz >= (int64_t)1 << 31) return fail(ctx, CQ_E_OVERFLOW, "nnz must be in [0, 2^31)");
   if (nnz % 2) return fail(ctx, CQ_E_GRAPH_FORMAT, "an undirected CSR stores an even number of entries");
   hipStream_t s = ctx->stream;
@@ -1296,7 +1378,7 @@ cq_status cq_graph_load(cq_context* ctx, int32_t n, int64_t nnz, const int32_t* 
   g->max_degree = res[1];
   g->validated = validated;
   if ((flags & CQ_GRAPH_REORDER) && nnz > 0) {
-    cq_status st = build_locality_order(ctx, g, d_row_ptr, d_col_idx);
+    cq_status st = build_locality_order(ctx, g, d_row_ptr, d_col_idx, !(flags & CQ_GRAPH_NO_BLOCKS));
     if (st != CQ_OK) {
       delete g;
       return st;

@@ -27,14 +27,24 @@ def ctx(cq):
     c.close()
 
 
-def run_case(cq, ctx, rp, ci, lab, L, what, *, validate=True, pairs=True, per_comm=True, reorder=False):
-    what = f"{what}{' [reordered graph]' if reorder else ''}"
+# graph storage: the caller's order, renumbered with column blocks, renumbered without
+ORDERS = ["input", "blocked", "unblocked"]
+
+
+def open_graph(cq, ctx, rp_t, ci_t, order, validate=False):
+    g = cq.Graph(ctx, rp_t, ci_t, validate=validate, reorder=(order != "input"), blocks=(order == "blocked"))
+    want = {"input": 0, "blocked": cq.CQ_GRAPH_REORDER, "unblocked": cq.CQ_GRAPH_REORDER | cq.CQ_GRAPH_NO_BLOCKS}[order]
+    assert g.stats["reordered"] == want
+    return g
+
+
+def run_case(cq, ctx, rp, ci, lab, L, what, *, validate=True, pairs=True, per_comm=True, reorder="input"):
+    what = f"{what} [{reorder} graph]"
     note(what)
     rp_t = torch.as_tensor(np.asarray(rp, np.int32)).cuda()
     ci_t = torch.as_tensor(np.asarray(ci, np.int32)).cuda()
     lab_t = torch.as_tensor(np.asarray(lab, np.int32)).cuda()
-    g = cq.Graph(ctx, rp_t, ci_t, validate=validate, reorder=reorder)
-    assert g.stats["reordered"] == (cq.CQ_GRAPH_REORDER if reorder else 0)
+    g = open_graph(cq, ctx, rp_t, ci_t, reorder, validate=validate)
     o = oracle.score(np.asarray(rp), np.asarray(ci), np.asarray(lab), L, want_pairs=pairs)
     cap = max(1, int(o.result["num_pairs"])) if pairs else 0
     r, pc, pt = cq.score_partition(g, lab_t, L, per_community=per_comm, pairs_capacity=cap)
@@ -53,7 +63,7 @@ def lfr_case(name, seed):
     return g.row_ptr.numpy(), g.col_idx.numpy(), g.labels.numpy(), g.num_labels
 
 
-@pytest.mark.parametrize("reorder", [False, True])
+@pytest.mark.parametrize("reorder", ORDERS)
 def test_tiny_lfr_ground_truth_and_perturbed(cq, ctx, reorder):
     rp, ci, lab, L = lfr_case("tiny_1k", 1)
     run_case(cq, ctx, rp, ci, lab, L, "tiny_1k seed1 ground truth", reorder=reorder)
@@ -61,7 +71,7 @@ def test_tiny_lfr_ground_truth_and_perturbed(cq, ctx, reorder):
     run_case(cq, ctx, rp, ci, pert, L, "tiny_1k seed1 perturbed 10%", reorder=reorder)
 
 
-@pytest.mark.parametrize("reorder", [False, True])
+@pytest.mark.parametrize("reorder", ORDERS)
 @pytest.mark.parametrize("name", ["m100k_mu0.1", "m100k_mu0.3", "m100k_mu0.5"])
 def test_m100k(cq, ctx, name, reorder):
     rp, ci, lab, L = lfr_case(name, 11)
@@ -89,9 +99,11 @@ def test_many_labels_global_paths(cq, ctx):
     run_case(cq, ctx, rp, ci, np.arange(n, dtype=np.int32), n, "all singletons n=1e5", pairs=True)
     lab2 = (lab.astype(np.int64) * 7919 % 40009).astype(np.int32)  # injective relabel into 40009 ids
     run_case(cq, ctx, rp, ci, lab2, 40009, "relabelled into 40009 ids")
-    run_case(cq, ctx, rp, ci, lab2, 40009, "relabelled into 40009 ids", reorder=True)
+    run_case(cq, ctx, rp, ci, lab2, 40009, "relabelled into 40009 ids", reorder="blocked")
+    run_case(cq, ctx, rp, ci, lab2, 40009, "relabelled into 40009 ids", reorder="unblocked")
     lab3 = (lab.astype(np.int64) * 7919 % 70001).astype(np.int32)  # ids beyond 16 bits: 32-bit staging
-    run_case(cq, ctx, rp, ci, lab3, 70001, "relabelled into 70001 ids", reorder=True)
+    run_case(cq, ctx, rp, ci, lab3, 70001, "relabelled into 70001 ids", reorder="blocked")
+    run_case(cq, ctx, rp, ci, lab3, 70001, "relabelled into 70001 ids", reorder="unblocked")
 
 
 def test_wide_counter_wraps(cq, ctx):
@@ -106,8 +118,8 @@ def test_wide_counter_wraps(cq, ctx):
     edges += [(int(B[i]), int(B[i + 1])) for i in range(k - 1)] + [(int(C[i]), int(C[i + 1])) for i in range(k - 1)]
     rp, ci = csr_from_edges(3 * k, edges)
     lab = np.concatenate([np.zeros(k), np.full(k, 40000), np.full(k, 40001)]).astype(np.int32)
-    run_case(cq, ctx, rp, ci, lab, 40003, "complete bipartite 300x600, labels 0/40000/40001")
-    run_case(cq, ctx, rp, ci, lab, 40003, "complete bipartite 300x600, labels 0/40000/40001", reorder=True)
+    for order in ORDERS:
+        run_case(cq, ctx, rp, ci, lab, 40003, "complete bipartite 300x600, labels 0/40000/40001", reorder=order)
 
 
 def test_hub_split_classes(cq, ctx):
@@ -118,14 +130,14 @@ def test_hub_split_classes(cq, ctx):
     n = leaves + 1
     run_case(cq, ctx, rp, ci, np.arange(n, dtype=np.int32), n, "star 20000 singletons")
     lab = (np.arange(n, dtype=np.int64) * 8).astype(np.int32)
-    run_case(cq, ctx, rp, ci, lab, 8 * n, "star 20000 singletons, labels = 8i")
-    run_case(cq, ctx, rp, ci, lab, 8 * n, "star 20000 singletons, labels = 8i", reorder=True)
+    for order in ORDERS:
+        run_case(cq, ctx, rp, ci, lab, 8 * n, "star 20000 singletons, labels = 8i", reorder=order)
 
 
-@pytest.mark.parametrize("reorder", [False, True])
+@pytest.mark.parametrize("reorder", ORDERS)
 def test_errors(cq, ctx, reorder):
     rp, ci = erdos_renyi(50, 0.2, 1)
-    g = cq.Graph(ctx, torch.as_tensor(rp).cuda(), torch.as_tensor(ci).cuda(), validate=True, reorder=reorder)
+    g = open_graph(cq, ctx, torch.as_tensor(rp).cuda(), torch.as_tensor(ci).cuda(), reorder, validate=True)
     lab = torch.zeros(50, dtype=torch.int32, device="cuda")
     lab[7] = 5
     note("label out of range")
@@ -170,25 +182,23 @@ def test_deterministic_and_workspace_reuse(cq, ctx, pct):
     if pct:
         lab = perturb_labels(torch.as_tensor(lab), L, pct / 100, 77).numpy()
     note(f"m100k_mu0.5 perturbed {pct}%: repeated runs, plain and reordered graph")
-    g = cq.Graph(ctx, torch.as_tensor(rp).cuda(), torch.as_tensor(ci).cuda())
-    g2 = cq.Graph(ctx, torch.as_tensor(rp).cuda(), torch.as_tensor(ci).cuda(), reorder=True)
-    assert g2.stats["owned_bytes"] > 0
+    rp_t, ci_t = torch.as_tensor(rp).cuda(), torch.as_tensor(ci).cuda()
+    graphs = [open_graph(cq, ctx, rp_t, ci_t, order) for order in ORDERS]
+    assert graphs[1].stats["owned_bytes"] > graphs[2].stats["owned_bytes"] > 0
     lab_t = torch.as_tensor(lab).cuda()
-    ws = ctx.workspace(max(g.workspace_size(L), g2.workspace_size(L)))
-    first, _, _ = cq.score_partition(g, lab_t, L)
+    ws = ctx.workspace(max(g.workspace_size(L) for g in graphs))
+    first, _, _ = cq.score_partition(graphs[0], lab_t, L)
     o = oracle.score(rp, ci, lab, L).result
     check_score(first, o, f"m100k_mu0.5 perturbed {pct}%")
     for _ in range(4):
-        # a workspace full of 0xFF: a staged slot the kernels fail to write reads as an
-        # out-of-range label and changes the counts
-        ws.fill_(255)
-        again, _, _ = cq.score_partition(g, lab_t, L, workspace=ws)
-        assert again == first  # bitwise: every float compared with ==
-        ws.fill_(255)
-        other, _, _ = cq.score_partition(g2, lab_t, L, workspace=ws)
-        assert other == first  # the node order of the stored graph changes no bit of the result
-    g.close()
-    g2.close()
+        for g in graphs:
+            # a workspace full of 0xFF: a staged slot the kernels fail to write reads as
+            # an out-of-range label and changes the counts
+            ws.fill_(255)
+            again, _, _ = cq.score_partition(g, lab_t, L, workspace=ws)
+            assert again == first  # bitwise: the stored node order changes no bit of the result
+    for g in graphs:
+        g.close()
 
 
 def test_full_size_l10m(cq, ctx):
@@ -200,9 +210,9 @@ def test_full_size_l10m(cq, ctx):
     rp, ci, lab = gr.row_ptr.cpu().numpy(), gr.col_idx.cpu().numpy(), gr.labels.cpu().numpy()
     note(f"l10m: n={gr.n} nnz={gr.nnz} K={gr.num_labels}; oracle")
     o = oracle.score(rp, ci, lab, gr.num_labels)
-    for reorder in (False, True):
-        note(f"l10m: GPU, reorder={reorder}")
-        g = cq.Graph(ctx, gr.row_ptr, gr.col_idx, reorder=reorder)
+    for reorder in ORDERS:
+        note(f"l10m: GPU, {reorder} graph")
+        g = open_graph(cq, ctx, gr.row_ptr, gr.col_idx, reorder)
         r, pc, pt = cq.score_partition(g, gr.labels, gr.num_labels, per_community=True,
                                        pairs_capacity=int(o.result["num_pairs"]))
         check_score(r, o.result, f"l10m reorder={reorder}")
