@@ -144,7 +144,9 @@ def main() -> int:
 
     stage_avg = {k: v[0] / v[1] for k, v in stages.items()}
     dom = max(stage_avg, key=stage_avg.get)
-    kernel_of = {"edge_gather": "k_gather", "group_count": "k_groups", "node_pass": "k_node_priv",
+    blocked = graph.stats["reordered"] == cq.CQ_GRAPH_REORDER  # renumbered and stored in column blocks
+    kernel_of = {"edge_gather": "k_gather_blocked" if blocked else "k_gather", "group_count": "k_groups<ScoreVis>",
+                 "node_pass": "k_node_perm" if blocked else "k_node_priv",
                  "final_reduce": "k_score_final1", "column_scan": "k_colscan", "scan_order": "k_scan_order"}
     abytes = algorithmic_bytes(n, nnz)
     achieved = abytes / (stage_avg[dom] * 1e-3) / 1e9
