@@ -93,7 +93,8 @@ const char* cq_stage_name(int32_t s);
 /* Flags for cq_graph_load. */
 #define CQ_VALIDATE_GRAPH 1u  /* also check symmetry (rows must be sorted), no self-loops, no repeated entries */
 #define CQ_GRAPH_REORDER 2u   /* store the graph in a locality order (see cq_graph_load) */
-#define CQ_GRAPH_NO_BLOCKS 4u /* with CQ_GRAPH_REORDER: skip the column blocks (see cq_graph_load) */
+#define CQ_GRAPH_NO_BLOCKS 4u /* with CQ_GRAPH_REORDER: never build column blocks (see cq_graph_load) */
+#define CQ_GRAPH_BLOCKS 8u    /* with CQ_GRAPH_REORDER: build column blocks for any n <= 2^24 */
 
 typedef struct {
   int64_t n;           /* |V| */
@@ -123,11 +124,13 @@ typedef struct {
  * so that the neighbours of a row mostly have nearby ids.  Labels passed to scoring
  * calls keep the caller's node numbering; every result is identical with and without
  * the flag.  The borrowed arrays are not read after the load returns.
- * When n <= 2^24 the copy is also kept as 8 column blocks, one per XCD of the device
- * (the edge pass then reads each neighbour label from one XCD's L2), with a plan that
- * moves labels from the caller's order to the stored one: a further
- * 4(8(n+1)+1) + 8 nnz + 12n + 4(n/32768 + 2) bytes.  CQ_GRAPH_NO_BLOCKS skips them.
- * owned_bytes in cq_graph_stats reports the total.
+ * When 2^20 <= n <= 2^24 the copy is also kept as 8 column blocks, one per XCD of the
+ * device (the edge pass then reads each neighbour label from one XCD's L2; below 2^20
+ * nodes one L2 holds all labels anyway), with a plan that moves labels from the
+ * caller's order to the stored one: a further 4(8(n+1)+1) + 8 nnz + 12n + 4(n/32768 + 2)
+ * bytes.  CQ_GRAPH_NO_BLOCKS never builds them, CQ_GRAPH_BLOCKS builds them for any
+ * n <= 2^24 (both flags at once: CQ_E_INVALID_ARG).  owned_bytes in cq_graph_stats
+ * reports the total.
  */
 cq_status cq_graph_load(cq_context* ctx, int32_t n, int64_t nnz, const int32_t* d_row_ptr,
                         const int32_t* d_col_idx, uint32_t flags, cq_graph** out);

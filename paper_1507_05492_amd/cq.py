@@ -30,6 +30,7 @@ CQ_E_CAPACITY = -10
 CQ_VALIDATE_GRAPH = 1
 CQ_GRAPH_REORDER = 2
 CQ_GRAPH_NO_BLOCKS = 4
+CQ_GRAPH_BLOCKS = 8
 
 _P = ctypes.c_void_p
 _I32 = ctypes.c_int32
@@ -408,7 +409,9 @@ class Graph:
     """A registered graph; keeps its CSR tensors alive while registered."""
 
     def __init__(self, ctx: Context, row_ptr, col_idx, validate: bool = False, reorder: bool = False,
-                 blocks: bool = True):
+                 blocks: bool | None = None):
+        """reorder: store in a locality order; blocks (with reorder): None = column blocks
+        when the library's size rule says so, True = always (n <= 2^24), False = never."""
         self.ctx = ctx
         self.row_ptr = _dev_i32(row_ptr, "row_ptr")
         self.col_idx = _dev_i32(col_idx, "col_idx")
@@ -417,7 +420,8 @@ class Graph:
         self.handle = cq_graph_load(ctx.handle, self.n, self.nnz, self.row_ptr.data_ptr(),
                                     self.col_idx.data_ptr() if self.nnz else None,
                                     (CQ_VALIDATE_GRAPH if validate else 0) | (CQ_GRAPH_REORDER if reorder else 0)
-                                    | (CQ_GRAPH_NO_BLOCKS if reorder and not blocks else 0))
+                                    | (CQ_GRAPH_BLOCKS if reorder and blocks is True else 0)
+                                    | (CQ_GRAPH_NO_BLOCKS if reorder and blocks is False else 0))
         self.stats = cq_graph_get_stats(self.handle)
 
     def workspace_size(self, num_labels: int) -> int:

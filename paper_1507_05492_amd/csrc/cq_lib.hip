@@ -562,8 +562,10 @@ void scan_u32(const u32* in, u32* out, long long n, u32* tiles, hipStream_t s) {
 }
 
 constexpr int LP_SWEEPS = 10;
-// Column blocks pay off while one block's labels (2 bytes per node) fit an XCD's L2.
+// Column blocks pay off while one block's labels (2 bytes per node) fit an XCD's L2, and
+// once all labels do not (below that the plain edge pass has more workgroups in flight).
 constexpr int64_t BLOCK_MAX_N = 16 << 20;
+constexpr int64_t BLOCK_MIN_N = 1 << 20;
 
 // Splits the renumbered graph (g->owned_rp / owned_col) into COL_BLOCKS column blocks.
 cq_status build_column_blocks(cq_context* ctx, cq_graph* g) {
@@ -705,7 +707,7 @@ cq_status build_locality_order(cq_context* ctx, cq_graph* g, const int32_t* rp, 
     k_new_degree<<<gn, 256, 0, s>>>(n, rp, g->owned_perm, cnt);
     scan_u32(cnt, reinterpret_cast<u32*>(g->owned_rp), n, tiles, s);
     k_relabel_rows<<<gw, 256, 0, s>>>(n, rp, col, g->owned_perm, newid, g->owned_rp, g->owned_col);
-    if (blocks && n <= BLOCK_MAX_N) st = build_column_blocks(ctx, g);
+    if (blocks) st = build_column_blocks(ctx, g);
     if (st == CQ_OK && g->rpb) st = build_perm_plan(ctx, g, newid, rp);
     e = hipGetLastError();
     if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -1336,10 +1338,12 @@ cq_status cq_graph_load(cq_context* ctx, int32_t n, int64_t nnz, const int32_t* 
   if (!out || !d_row_ptr || (nnz > 0 && !d_col_idx)) return fail(ctx, CQ_E_INVALID_ARG, "null pointer");
   *out = nullptr;
   if (n < 1) return fail(ctx, CQ_E_INVALID_ARG, "n must be >= 1");
-  if (flags & ~(CQ_VALIDATE_GRAPH | CQ_GRAPH_REORDER | CQ_GRAPH_NO_BLOCKS))
+  if (flags & ~(CQ_VALIDATE_GRAPH | CQ_GRAPH_REORDER | CQ_GRAPH_NO_BLOCKS | CQ_GRAPH_BLOCKS))
     return fail(ctx, CQ_E_INVALID_ARG, "unknown flag bits");
-  if ((flags & CQ_GRAPH_NO_BLOCKS) && !(flags & CQ_GRAPH_REORDER))
-    return fail(ctx, CQ_E_INVALID_ARG, "CQ_GRAPH_NO_BLOCKS needs CQ_GRAPH_REORDER");
+  if ((flags & (CQ_GRAPH_NO_BLOCKS | CQ_GRAPH_BLOCKS)) && !(flags & CQ_GRAPH_REORDER))
+    return fail(ctx, CQ_E_INVALID_ARG, "CQ_GRAPH_NO_BLOCKS and CQ_GRAPH_BLOCKS need CQ_GRAPH_REORDER");
+  if ((flags & CQ_GRAPH_NO_BLOCKS) && (flags & CQ_GRAPH_BLOCKS))
+    return fail(ctx, CQ_E_INVALID_ARG, "CQ_GRAPH_NO_BLOCKS and CQ_GRAPH_BLOCKS exclude each other");
   if (nnz < 0 || nnz >= (int64_t)1 << 31) return fail(ctx, CQ_E_OVERFLOW, "nnz must be in [0, 2^31)");
   if (nnz % 2) return fail(ctx, CQ_E_GRAPH_FORMAT, "an undirected CSR stores an even number of entries");
   hipStream_t s = ctx->stream;
@@ -1378,7 +1382,9 @@ cq_status cq_graph_load(cq_context* ctx, int32_t n, int64_t nnz, const int32_t* 
   g->max_degree = res[1];
   g->validated = validated;
   if ((flags & CQ_GRAPH_REORDER) && nnz > 0) {
-    cq_status st = build_locality_order(ctx, g, d_row_ptr, d_col_idx, !(flags & CQ_GRAPH_NO_BLOCKS));
+    const bool blocks = (flags & CQ_GRAPH_BLOCKS) ? n <= BLOCK_MAX_N
+                        : !(flags & CQ_GRAPH_NO_BLOCKS) && n >= BLOCK_MIN_N && n <= BLOCK_MAX_N;
+    cq_status st = build_locality_order(ctx, g, d_row_ptr, d_col_idx, blocks);
     if (st != CQ_OK) {
       delete g;
       return st;
