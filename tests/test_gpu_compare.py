@@ -111,6 +111,21 @@ def test_wide_counter_wraps(cq, ctx):
     run_cmp(cq, ctx, a3, 1, b3, 40003, "log overflow: 8.7e6 entries in two cells")
 
 
+def test_full_size_l10m(cq, ctx):
+    """The comparison the benchmark times: ground truth of the 10M-node graph against 10 %
+    of its nodes reassigned.  Every pair count and the whole contingency table exact."""
+    note("l10m compare: generating on the GPU")
+    g = lfr_graph(CONFIGS["l10m"], 21, device="cuda")
+    pert = perturb_labels(g.labels, g.num_labels, 0.10, 1010)
+    a, b = g.labels.cpu().numpy(), pert.cpu().numpy()
+    note(f"l10m compare: n={g.n} K={g.num_labels}; oracle")
+    o = oracle.compare(a, g.num_labels, b, g.num_labels, want_cells=True)
+    note("l10m compare: GPU")
+    r, ct = cq.compare_partitions(ctx, g.labels, g.num_labels, pert, g.num_labels, cells_capacity=int(o.result["nnz"]))
+    check_compare(r, o.result, "l10m GT vs 10%")
+    assert np.array_equal(sort_rows(ct), o.cells), "l10m: contingency table differs"
+
+
 def test_errors(cq, ctx):
     a = torch.zeros(10, dtype=torch.int32, device="cuda")
     b = torch.zeros(10, dtype=torch.int32, device="cuda")
