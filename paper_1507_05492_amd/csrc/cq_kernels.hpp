@@ -319,7 +319,7 @@ constexpr int PERM_SHIFT = 15;  // 32768 stored ids per bucket: 64 KB of 16-bit 
 // Each workgroup counts its nodes per bucket in LDS, reserves a range of every bucket
 // with one global atomic, and places its nodes inside those ranges.
 constexpr int PERM_NODES = 8192;  // nodes per workgroup of the plan kernels
-constexpr int PERM_MAX_BUCKETS = 1024;  // n up to 2^25
+constexpr int PERM_MAX_BUCKETS = 16384;  // n up to 2^29
 
 __global__ __launch_bounds__(256) void k_perm_count(int n, const int32_t* __restrict__ newid, int nb, u32* __restrict__ bcnt) {
   __shared__ u32 h[PERM_MAX_BUCKETS];
@@ -407,6 +407,34 @@ __global__ __launch_bounds__(1024) void k_node_perm(int n, const int32_t* __rest
   if (threadIdx.x == 0 && s_bad) atomicOr(&ctl->flags, F_LABEL);
 }
 
+// Caller-order pass without counting (labels beyond LDS, or a graph without column
+// blocks): tmp[pos1[u]] = label of u, or the sentinel (flagged) when out of range.
+template <class LT>
+__global__ __launch_bounds__(256) void k_perm_scatter(int n, const int32_t* __restrict__ labels, const u32* __restrict__ pos1,
+                                                      int L, LT* __restrict__ tmp, Ctl* __restrict__ ctl) {
+  constexpr int U = 8;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  u32 bad = 0;
+  for (size_t ub = (size_t)blockIdx.x * blockDim.x + threadIdx.x; ub < (size_t)n; ub += U * stride) {
+    int c[U];
+    u32 p[U];
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+      const size_t u = min(ub + k * stride, (size_t)n - 1);  // in bounds; masked below
+      c[k] = labels[u];
+      p[k] = pos1[u];
+    }
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+      if (ub + k * stride >= (size_t)n) break;
+      const bool ok = (u32)c[k] < (u32)L;
+      bad |= ok ? 0u : 1u;
+      tmp[p[k]] = ok ? (LT)c[k] : LabelT<LT>::SENTINEL;
+    }
+  }
+  if (bad) atomicOr(&ctl->flags, F_LABEL);
+}
+
 template <class LT>
 __global__ __launch_bounds__(1024) void k_perm_apply(int n, const u32* __restrict__ bstart, const u32* __restrict__ tgt,
                                                      const LT* __restrict__ tmp, LT* __restrict__ labx) {
@@ -438,7 +466,9 @@ __global__ __launch_bounds__(1024) void k_perm_apply(int n, const u32* __restric
 }
 
 
-template <bool WEIGHTED, class LT>
+// STAGED: the labels were already moved to the stored order into labx (sentinel = out of
+// range); otherwise they are read from labels[perm[u]] (or labels[u]) and written to labx.
+template <bool WEIGHTED, class LT, bool STAGED = false>
 __device__ __forceinline__ void node_priv_body(int n, const int32_t* __restrict__ labels, const int32_t* __restrict__ perm,
                                                const int32_t* __restrict__ rp, int L, int chunk, u32* __restrict__ HN,
                                                u32* __restrict__ HD, u32* __restrict__ loc, LT* __restrict__ labx,
@@ -458,12 +488,18 @@ __device__ __forceinline__ void node_priv_body(int n, const int32_t* __restrict_
   for (long long ub = u0; ub < u1; ub += blockDim.x) {  // uniform trip count per wave
     const long long u = ub + threadIdx.x;
     const bool in = u < u1;
-    int c = in ? labels[perm ? perm[u] : u] : 0;
+    int c;
+    if (STAGED) {
+      const u32 x = in ? (u32)labx[u] : 0u;
+      c = x == (u32)LabelT<LT>::SENTINEL ? -1 : (int)x;
+    } else {
+      c = in ? labels[perm ? perm[u] : u] : 0;
+    }
     const bool valid = in && (u32)c < (u32)L;
     if (in && !valid) {
       bad = 1;
       loc[u] = SENT;
-      if (labx) labx[u] = LabelT<LT>::SENTINEL;
+      if (labx && !STAGED) labx[u] = LabelT<LT>::SENTINEL;
     }
     const u32 w = valid ? (WEIGHTED ? (u32)(rp[u + 1] - rp[u]) : 1u) : 0u;
     // Lanes with equal labels (common when the graph is stored in a locality order)
@@ -499,7 +535,7 @@ __device__ __forceinline__ void node_priv_body(int n, const int32_t* __restrict_
     }
     if (valid) {
       loc[u] = old;
-      if (labx) labx[u] = (LT)c;
+      if (labx && !STAGED) labx[u] = (LT)c;
     }
   }
   if (bad) s_bad = 1;
@@ -512,17 +548,17 @@ __device__ __forceinline__ void node_priv_body(int n, const int32_t* __restrict_
   if (threadIdx.x == 0 && s_bad) atomicOr(&ctl->flags, F_LABEL);
 }
 
-template <bool WEIGHTED, class LT>
+template <bool WEIGHTED, class LT, bool STAGED = false>
 __global__ __launch_bounds__(1024) void k_node_priv(int n, const int32_t* __restrict__ labels, const int32_t* __restrict__ perm,
                                                     const int32_t* __restrict__ rp, int L, int chunk, u32* __restrict__ HN,
                                                     u32* __restrict__ HD, u32* __restrict__ loc, LT* __restrict__ labx,
                                                     Ctl* __restrict__ ctl) {
-  node_priv_body<WEIGHTED, LT>(n, labels, perm, rp, L, chunk, HN, HD, loc, labx, ctl, blockIdx.x);
+  node_priv_body<WEIGHTED, LT, STAGED>(n, labels, perm, rp, L, chunk, HN, HD, loc, labx, ctl, blockIdx.x);
 }
 
 // Node pass with global atomics (too many labels for LDS).  SZ[c] packs
 // (count << 32) | weight sum; the returned old value gives the node's offset.
-template <bool WEIGHTED, class LT>
+template <bool WEIGHTED, class LT, bool STAGED = false>
 __global__ __launch_bounds__(256) void k_node_global(int n, const int32_t* __restrict__ labels, const int32_t* __restrict__ perm,
                                                      const int32_t* __restrict__ rp, int L, unsigned long long* __restrict__ SZ,
                                                      u32* __restrict__ loc, LT* __restrict__ labx, Ctl* __restrict__ ctl) {
@@ -532,12 +568,18 @@ __global__ __launch_bounds__(256) void k_node_global(int n, const int32_t* __res
   for (size_t ub = (size_t)blockIdx.x * blockDim.x; ub < (size_t)n; ub += stride) {  // uniform per wave
     const size_t u = ub + threadIdx.x;
     const bool in = u < (size_t)n;
-    const int c = in ? labels[perm ? perm[u] : u] : 0;
+    int c;
+    if (STAGED) {
+      const u32 x = in ? (u32)labx[u] : 0u;
+      c = x == (u32)LabelT<LT>::SENTINEL ? -1 : (int)x;
+    } else {
+      c = in ? labels[perm ? perm[u] : u] : 0;
+    }
     const bool valid = in && (u32)c < (u32)L;
     if (in && !valid) {
       bad = 1;
       loc[u] = SENT;
-      if (labx) labx[u] = LabelT<LT>::SENTINEL;
+      if (labx && !STAGED) labx[u] = LabelT<LT>::SENTINEL;
     }
     const u32 w = valid ? (WEIGHTED ? (u32)(rp[u + 1] - rp[u]) : 1u) : 0u;
     // lanes with equal labels add through one leader (see k_node_priv)
@@ -565,7 +607,7 @@ __global__ __launch_bounds__(256) void k_node_global(int n, const int32_t* __res
     if (pending) old = (u32)atomicAdd(&SZ[c], (1ull << 32) | (unsigned long long)w);
     if (valid) {
       loc[u] = old;
-      if (labx) labx[u] = (LT)c;
+      if (labx && !STAGED) labx[u] = (LT)c;
     }
   }
   if (bad) atomicOr(&ctl->flags, F_LABEL);

@@ -295,6 +295,15 @@ cq_status map_flags(cq_context* ctx, u32 flags) {
   return CQ_OK;
 }
 
+// Moves the caller's labels to the stored node order with the graph's bucket plan:
+// labx[stored id] = label, or the sentinel (flagged) when out of range.  tmp holds n
+// labels and may alias the per-node offsets, which are written only afterwards.
+template <class LT>
+void stage_labels(const cq_graph* g, const int32_t* labels, int32_t L, LT* tmp, LT* labx, Ctl* ctl, hipStream_t s) {
+  k_perm_scatter<LT><<<grid_for(g->n, 256 * 8, 8192), 256, 0, s>>>(g->n, labels, g->pos1, L, tmp, ctl);
+  k_perm_apply<LT><<<g->perm_buckets, 1024, ((size_t)1 << PERM_SHIFT) * sizeof(LT), s>>>(g->n, g->pbstart, g->tgt, tmp, labx);
+}
+
 // The scoring path with staged labels of type LT (u16 when num_labels <= 65535).
 template <class LT>
 void score_launch(cq_context* ctx, const cq_graph* g, const int32_t* labels, int32_t L, void* ws, const ScoreLayout& lay,
@@ -343,8 +352,15 @@ void score_launch(cq_context* ctx, const cq_graph* g, const int32_t* labels, int
     u32* HD = at<u32>(ws, lay.HD);
     {
       StageMark mk(ctx, ST_NODE, timed);
-      k_node_priv<true, LT><<<lay.W, 1024, 2 * (size_t)L * 4, s>>>((int)n, labels, g->perm, g->rp, L, lay.chunk, HN, HD, loc,
-                                                                   labx, ctl);
+      if (g->pos1) {
+        // move the labels to the stored order first (streaming), then count in that order
+        stage_labels<LT>(g, labels, L, reinterpret_cast<LT*>(loc), labx, ctl, s);
+        k_node_priv<true, LT, true><<<lay.W, 1024, 2 * (size_t)L * 4, s>>>((int)n, labels, g->perm, g->rp, L, lay.chunk, HN, HD,
+                                                                         loc, labx, ctl);
+      } else {
+        k_node_priv<true, LT><<<lay.W, 1024, 2 * (size_t)L * 4, s>>>((int)n, labels, g->perm, g->rp, L, lay.chunk, HN, HD, loc,
+                                                                     labx, ctl);
+      }
     }
     {
       StageMark mk(ctx, ST_COLSCAN, timed);
@@ -355,7 +371,13 @@ void score_launch(cq_context* ctx, const cq_graph* g, const int32_t* labels, int
     unsigned long long* SZ = at<unsigned long long>(ws, lay.SZ);
     {
       StageMark mk(ctx, ST_NODE, timed);
-      k_node_global<true, LT><<<grid_for(n, 256, 8192), 256, 0, s>>>((int)n, labels, g->perm, g->rp, L, SZ, loc, labx, ctl);
+      if (g->pos1) {
+        stage_labels<LT>(g, labels, L, reinterpret_cast<LT*>(loc), labx, ctl, s);
+        k_node_global<true, LT, true><<<grid_for(n, 256, 8192), 256, 0, s>>>((int)n, labels, g->perm, g->rp, L, SZ, loc, labx,
+                                                                            ctl);
+      } else {
+        k_node_global<true, LT><<<grid_for(n, 256, 8192), 256, 0, s>>>((int)n, labels, g->perm, g->rp, L, SZ, loc, labx, ctl);
+      }
     }
     {
       StageMark mk(ctx, ST_COLSCAN, timed);
@@ -708,7 +730,7 @@ cq_status build_locality_order(cq_context* ctx, cq_graph* g, const int32_t* rp, 
     scan_u32(cnt, reinterpret_cast<u32*>(g->owned_rp), n, tiles, s);
     k_relabel_rows<<<gw, 256, 0, s>>>(n, rp, col, g->owned_perm, newid, g->owned_rp, g->owned_col);
     if (blocks) st = build_column_blocks(ctx, g);
-    if (st == CQ_OK && g->rpb) st = build_perm_plan(ctx, g, newid, rp);
+    if (st == CQ_OK && (g->rpb || n >= BLOCK_MIN_N)) st = build_perm_plan(ctx, g, newid, rp);
     e = hipGetLastError();
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (st == CQ_OK && e != hipSuccess) st = fail(ctx, CQ_E_DEVICE, "renumbering the graph: %s", hipGetErrorString(e));
@@ -1280,6 +1302,8 @@ cq_status cq_context_create(int device, void* hip_stream, cq_context** out) {
   set_big_lds(reinterpret_cast<const void*>(k_perm_apply<uint16_t>), ((size_t)1 << PERM_SHIFT) * 2);
   set_big_lds(reinterpret_cast<const void*>(k_perm_apply<uint32_t>), ((size_t)1 << PERM_SHIFT) * 4);
   set_big_lds(reinterpret_cast<const void*>(k_node_priv<true, uint32_t>), 2 * PRIV_MAX * 4);
+  set_big_lds(reinterpret_cast<const void*>(k_node_priv<true, uint16_t, true>), 2 * PRIV_MAX * 4);
+  set_big_lds(reinterpret_cast<const void*>(k_node_priv<true, uint32_t, true>), 2 * PRIV_MAX * 4);
   set_big_lds(reinterpret_cast<const void*>(k_node_priv<false, uint32_t>), PRIV_MAX * 4);
   set_big_lds(reinterpret_cast<const void*>(k_hist_priv), PRIV_MAX * 4);
   set_big_lds(reinterpret_cast<const void*>(k_groups<ScoreVis, uint16_t>), gl);

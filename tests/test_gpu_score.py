@@ -210,12 +210,22 @@ def test_full_size_l10m(cq, ctx):
     rp, ci, lab = gr.row_ptr.cpu().numpy(), gr.col_idx.cpu().numpy(), gr.labels.cpu().numpy()
     note(f"l10m: n={gr.n} nnz={gr.nnz} K={gr.num_labels}; oracle")
     o = oracle.score(rp, ci, lab, gr.num_labels)
+    graphs = {}
     for reorder in ORDERS:
         note(f"l10m: GPU, {reorder} graph")
-        g = open_graph(cq, ctx, gr.row_ptr, gr.col_idx, reorder)
+        g = graphs[reorder] = open_graph(cq, ctx, gr.row_ptr, gr.col_idx, reorder)
         r, pc, pt = cq.score_partition(g, gr.labels, gr.num_labels, per_community=True,
                                        pairs_capacity=int(o.result["num_pairs"]))
         check_score(r, o.result, f"l10m reorder={reorder}")
         check_per_community(pc, o)
         assert np.array_equal(sort_rows(pt), o.pairs)
+    # label ids beyond the LDS histograms: global-atomic node pass after the staged move
+    lab2 = (lab.astype(np.int64) * 7919 % 40009).astype(np.int32)
+    note("l10m relabelled into 40009 ids: oracle")
+    o2 = oracle.score(rp, ci, lab2, 40009)
+    lab2_t = torch.as_tensor(lab2).cuda()
+    for reorder, g in graphs.items():
+        note(f"l10m relabelled into 40009 ids: GPU, {reorder} graph")
+        r, _, _ = cq.score_partition(g, lab2_t, 40009)
+        check_score(r, o2.result, f"l10m 40009 ids reorder={reorder}")
         g.close()
