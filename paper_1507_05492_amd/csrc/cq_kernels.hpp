@@ -1375,29 +1375,6 @@ __device__ __forceinline__ u64 block_sum_u64(u64 x, u64* sh) {
   __syncthreads();
   return r;
 }
-__device__ __forceinline__ u32 block_max_u32(u32 x, u64* sh) {
-  x = wave_max_u32(x);
-  int w = threadIdx.x >> 6;
-  if ((threadIdx.x & 63) == 0) sh[w] = x;
-  __syncthreads();
-  u32 r = 0;
-  if (threadIdx.x == 0)
-    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) r = max(r, (u32)sh[i]);
-  __syncthreads();
-  return r;
-}
-__device__ __forceinline__ double block_max_f64(double x, double* sh) {
-  x = wave_max_f64(x);
-  int w = threadIdx.x >> 6;
-  if ((threadIdx.x & 63) == 0) sh[w] = x;
-  __syncthreads();
-  double r = 0.0;
-  if (threadIdx.x == 0)
-    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) r = sh[i] > r ? sh[i] : r;
-  __syncthreads();
-  return r;
-}
-
 // Score visitor: for community g, label j with count x in g's segment:
 //   j == g  ->  x = 2|E_g^in|
 //   j != g  ->  x = |E_{g,j}|; contributes |E_gj|/(2|E|) * |E_gj|/(|g||j|) to g's
@@ -1443,14 +1420,29 @@ struct ScoreVis {
       }
     }
   }
+  // Reduces the threads' sums with one barrier (waves first, then the waves in order);
+  // the caller's next barrier protects the LDS partials.
   __device__ void finish(State& st, u32 g) {
-    __shared__ u64 r_lo[GBLOCK / 64], r_hi[GBLOCK / 64];
-    u128 pen = block_sum_u128(st.pen, r_lo, r_hi);
-    u64 np = block_sum_u64(st.np, r_lo);
+    __shared__ u64 r_lo[GBLOCK / 64], r_hi[GBLOCK / 64], r_np[GBLOCK / 64];
+    const u128 pen = wave_sum_u128(st.pen);
+    const u64 np = wave_sum_u64(st.np);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+      r_lo[w] = (u64)pen;
+      r_hi[w] = (u64)(pen >> 64);
+      r_np[w] = np;
+    }
+    __syncthreads();
     if (threadIdx.x == 0) {
-      PEN[2 * (size_t)g] = (u64)pen;
-      PEN[2 * (size_t)g + 1] = (u64)(pen >> 64);
-      NP[g] = (u32)np;
+      u128 p = 0;
+      u64 q = 0;
+      for (int i = 0; i < (int)(blockDim.x >> 6); ++i) {
+        p += ((u128)r_hi[i] << 64) | r_lo[i];
+        q += r_np[i];
+      }
+      PEN[2 * (size_t)g] = (u64)p;
+      PEN[2 * (size_t)g + 1] = (u64)(p >> 64);
+      NP[g] = (u32)q;
     }
   }
 };
@@ -1509,16 +1501,43 @@ struct CmpVis {
       if ((long long)idx < ecap) { eci[idx] = (int32_t)st.g; ecj[idx] = (int32_t)j; ecnt[idx] = (int64_t)x; }
     }
   }
+  // One barrier for all six reductions (see ScoreVis::finish).
   __device__ void finish(State& st, u32 g) {
-    __shared__ u64 r_lo[GBLOCK / 64], r_hi[GBLOCK / 64];
-    __shared__ double r_d[GBLOCK / 64];
-    u128 mi = block_sum_u128(st.mi, r_lo, r_hi);
-    u128 vi = block_sum_u128(st.vi, r_lo, r_hi);
-    u64 a11 = block_sum_u64(st.a11, r_lo);
-    u32 rmax = block_max_u32(st.rmax, r_lo);
-    double fmax = block_max_f64(st.fmax, r_d);
-    u64 nz = block_sum_u64(st.nz, r_lo);
+    constexpr int NW = GBLOCK / 64;
+    __shared__ u64 r_mlo[NW], r_mhi[NW], r_vlo[NW], r_vhi[NW], r_a11[NW], r_nz[NW];
+    __shared__ u32 r_max[NW];
+    __shared__ double r_f[NW];
+    {
+      const u128 wm = wave_sum_u128(st.mi), wv = wave_sum_u128(st.vi);
+      const u64 wa = wave_sum_u64(st.a11), wn = wave_sum_u64(st.nz);
+      const u32 wx = wave_max_u32(st.rmax);
+      const double wf = wave_max_f64(st.fmax);
+      const int w = threadIdx.x >> 6;
+      if ((threadIdx.x & 63) == 0) {
+        r_mlo[w] = (u64)wm;
+        r_mhi[w] = (u64)(wm >> 64);
+        r_vlo[w] = (u64)wv;
+        r_vhi[w] = (u64)(wv >> 64);
+        r_a11[w] = wa;
+        r_nz[w] = wn;
+        r_max[w] = wx;
+        r_f[w] = wf;
+      }
+    }
+    __syncthreads();
     if (threadIdx.x == 0) {
+      u128 mi = 0, vi = 0;
+      u64 a11 = 0, nz = 0;
+      u32 rmax = 0;
+      double fmax = 0.0;
+      for (int i = 0; i < (int)(blockDim.x >> 6); ++i) {
+        mi += ((u128)r_mhi[i] << 64) | r_mlo[i];
+        vi += ((u128)r_vhi[i] << 64) | r_vlo[i];
+        a11 += r_a11[i];
+        nz += r_nz[i];
+        rmax = max(rmax, r_max[i]);
+        fmax = r_f[i] > fmax ? r_f[i] : fmax;
+      }
       atomicAdd(&ctl->cells, (unsigned long long)nz);
       RA11[g] = a11;
       RMAX[g] = rmax;
