@@ -1,8 +1,9 @@
 """CPU oracle for community-quality metrics -- TEST INFRASTRUCTURE ONLY.
 
 A plain, slow, obviously-correct C implementation (``cq_oracle.c``) of what the
-paper defines: Q (Eq. 8), Qds (Eq. 9), the six measures of Section II-B3, and
-VI, NMI, F-measure, NVD, RI, ARI, JI (Eqs. 1-7).  It is the independent reference
+paper defines: Q (Eq. 8), Qds (Eq. 9), the six measures of Section II-B3 (also on
+edge-weighted graphs, with the densities kept unweighted), and VI, NMI, F-measure,
+NVD, RI, ARI, JI (Eqs. 1-7).  It is the independent reference
 the GPU library is checked against and shares no code with it.  Only ``tests/``,
 ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of ``bench.py`` may import
 this package; the product path never does.
@@ -48,6 +49,16 @@ class _ScoreResult(ctypes.Structure):
     ]
 
 
+class _ScoreWResult(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_int64) for k in ("n", "m", "K", "num_pairs", "sum_ein", "sum_eout")] + [
+        (k, ctypes.c_double)
+        for k in (
+            "W", "sum_w_in", "sum_w_out", "Q", "Qds", "split_penalty", "mean_intra_edges", "mean_intra_density",
+            "mean_contraction", "mean_inter_edges", "mean_expansion", "mean_conductance",
+        )
+    ]
+
+
 class _CompareResult(ctypes.Structure):
     _fields_ = [(k, ctypes.c_int64) for k in ("n", "Ka", "Kb", "nnz", "a11", "a10", "a01", "a00", "A")] + [
         (k, ctypes.c_double) for k in ("VI", "NMI", "F", "NVD", "RI", "ARI", "JI")
@@ -72,6 +83,9 @@ def load(path: str) -> ctypes.CDLL:
     P = ctypes.c_void_p
     L.orc_score.restype = ctypes.c_int
     L.orc_score.argtypes = [ctypes.c_int32, P, P, P, ctypes.c_int32, ctypes.POINTER(_ScoreResult)] + [P] * 13 + [ctypes.c_int64]
+    if hasattr(L, "orc_score_w"):
+        L.orc_score_w.restype = ctypes.c_int
+        L.orc_score_w.argtypes = [ctypes.c_int32, P, P, P, P, ctypes.c_int32, ctypes.POINTER(_ScoreWResult)] + [P] * 13 + [ctypes.c_int64]
     L.orc_compare.restype = ctypes.c_int
     L.orc_compare.argtypes = [ctypes.c_int32, P, ctypes.c_int32, P, ctypes.c_int32, ctypes.POINTER(_CompareResult), P, P, P, ctypes.c_int64]
     return L
@@ -111,6 +125,22 @@ class ScoreOut:
 
 
 @dataclass
+class ScoreWOut:
+    result: dict
+    strength: np.ndarray
+    w_in: np.ndarray
+    w_out: np.ndarray
+    intra_density: np.ndarray
+    contraction: np.ndarray
+    expansion: np.ndarray
+    conductance: np.ndarray
+    q_term: np.ndarray
+    qds_term: np.ndarray
+    pairs: np.ndarray | None  # (num_pairs, 3) int64: ci, cj, |E_ci,cj| with ci < cj, ascending
+    pair_w: np.ndarray | None  # (num_pairs,) float64: w(ci, cj) in the same order
+
+
+@dataclass
 class CompareOut:
     result: dict
     cells: np.ndarray | None  # (nnz, 3) int64: i, j, |c_i ∩ c'_j|, ascending
@@ -144,6 +174,38 @@ def score(row_ptr, col_idx, labels, num_labels: int, *, want_pairs: bool = True,
         npairs = r["num_pairs"]
         pairs = np.stack([pi[:npairs].astype(np.int64), pj[:npairs].astype(np.int64), pc[:npairs]], axis=1)
     return ScoreOut(r, *[a[:L] for a in arrs_i], *[a[:L] for a in arrs_d], pairs)
+
+
+def score_w(row_ptr, col_idx, weights, labels, num_labels: int, *, want_pairs: bool = True, _lib=None) -> ScoreWOut:
+    """Score a partition of an edge-weighted symmetric CSR graph: Eqs. 8-9 and the six
+    measures with weight sums in place of edge counts, densities unweighted."""
+    rp, ci, lab = _i32(row_ptr), _i32(col_idx), _i32(labels)
+    w = np.ascontiguousarray(np.asarray(weights), dtype=np.float32)
+    n = lab.shape[0]
+    if rp.shape[0] != n + 1 or w.shape[0] != ci.shape[0]:
+        raise ValueError("row_ptr must have n+1 entries and weights one per entry")
+    L = int(num_labels)
+    arrs = [np.zeros(max(L, 1), np.float64) for _ in range(9)]
+    m = int(rp[-1]) // 2 if n > 0 else 0
+    cap = min(m, L * (L - 1) // 2) if want_pairs else 0
+    pi = np.zeros(max(cap, 1), np.int32)
+    pj = np.zeros(max(cap, 1), np.int32)
+    pc = np.zeros(max(cap, 1), np.int64)
+    pw = np.zeros(max(cap, 1), np.float64)
+    res = _ScoreWResult()
+    rc = (_lib or lib()).orc_score_w(
+        n, _ptr(rp), _ptr(ci), _ptr(w), _ptr(lab), L, ctypes.byref(res),
+        *[_ptr(a) for a in arrs], _ptr(pi), _ptr(pj), _ptr(pc), _ptr(pw), cap,
+    )
+    if rc != ORC_OK:
+        raise OracleError(rc, "weighted score")
+    r = {k: getattr(res, k) for k, _ in _ScoreWResult._fields_}
+    pairs = pair_w = None
+    if want_pairs:
+        k = r["num_pairs"]
+        pairs = np.stack([pi[:k].astype(np.int64), pj[:k].astype(np.int64), pc[:k]], axis=1)
+        pair_w = pw[:k].copy()
+    return ScoreWOut(r, *[a[:L] for a in arrs], pairs, pair_w)
 
 
 def compare(labels_a, num_labels_a: int, labels_b, num_labels_b: int, *, want_cells: bool = True, _lib=None) -> CompareOut:

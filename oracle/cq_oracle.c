@@ -39,6 +39,20 @@
  *
  * All floating-point sums use Neumaier (compensated) summation in binary64 over
  * terms evaluated in binary64, accumulated in ascending label order.
+ *
+ * Weighted score (orc_score_w).  The paper defines Eqs. 8-9 for unweighted graphs and
+ * notes (for weighted ones) that the two densities keep unweighted edge counts, so
+ * that they never exceed 1.  Reading used here, for a symmetric positive weight w(e)
+ * per CSR entry:
+ *   - every edge count of Eqs. 8-9 that is not inside a density becomes a weight sum:
+ *     |E| -> W (sum of the weights of the undirected edges), |E_c^in| -> w_in(c),
+ *     |E_c^out| -> w_out(c), 2|E_c^in| + |E_c^out| -> s(c) (the strength sum of c),
+ *     |E_{ci,cj}| in front of d_{ci,cj} -> w(ci,cj);
+ *   - d_c and d_{ci,cj} use the unweighted counts, as in the unweighted case;
+ *   - the six measures: intra-edges w_in(c), intra-density d_c, contraction
+ *     2 w_in(c)/|c|, inter-edges w_out(c), expansion w_out(c)/|c|, conductance
+ *     w_out(c)/s(c) (0 when s(c) = 0).
+ * With every weight equal to 1 this is exactly the unweighted score.
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -242,6 +256,186 @@ int orc_score(int32_t n, const int32_t* row_ptr, const int32_t* col_idx,
   out->mean_expansion = ns_get(&s_exp) / (double)K;
   out->mean_conductance = ns_get(&s_cond) / (double)K;
   free(nc); free(in2); free(outc); free(dens); free(pen);
+  return rc;
+}
+
+/* ---- weighted score (Section II-B with edge weights, see the reading above) -- */
+typedef struct {
+  int64_t n, m, K, num_pairs, sum_ein, sum_eout;   /* unweighted counts, as in orc_score */
+  double W;                /* sum of the weights of the undirected edges */
+  double sum_w_in;         /* sum over c of w_in(c) */
+  double sum_w_out;        /* sum over c of w_out(c) */
+  double Q, Qds, split_penalty;
+  double mean_intra_edges, mean_intra_density, mean_contraction;
+  double mean_inter_edges, mean_expansion, mean_conductance;
+} orc_score_w_result;
+
+/*
+ * Same graph and label contract as orc_score plus w[row_ptr[n]]: one weight per CSR
+ * entry, finite and > 0, equal for the two entries of an undirected edge.  Optional
+ * per-label outputs (length L): strength s(c), w_in(c), w_out(c), intra_density (d_c,
+ * unweighted), contraction, expansion, conductance, q_term, qds_term (weighted).
+ * Optional pair table: unordered pairs (ci < cj) with |E_{ci,cj}| and w(ci,cj),
+ * ascending by (ci, cj).
+ */
+typedef struct { uint64_t key; double w; } orc_wkey;
+static int cmp_wkey(const void* x, const void* y) {
+  uint64_t a = ((const orc_wkey*)x)->key, b = ((const orc_wkey*)y)->key;
+  return (a > b) - (a < b);
+}
+
+int orc_score_w(int32_t n, const int32_t* row_ptr, const int32_t* col_idx, const float* w,
+                const int32_t* labels, int32_t L, orc_score_w_result* out,
+                double* strength, double* w_in, double* w_out, double* intra_density,
+                double* contraction, double* expansion, double* conductance, double* q_term,
+                double* qds_term, int32_t* pair_i, int32_t* pair_j, int64_t* pair_cnt,
+                double* pair_w, int64_t pair_cap) {
+  if (!out || n < 1 || L < 1 || !row_ptr || !col_idx || !labels || !w) return ORC_E_ARG;
+  memset(out, 0, sizeof(*out));
+  int64_t nnz = row_ptr[n];
+  if (row_ptr[0] != 0 || nnz < 0) return ORC_E_GRAPH;
+  for (int32_t u = 0; u < n; ++u)
+    if (row_ptr[u + 1] < row_ptr[u]) return ORC_E_GRAPH;
+  for (int64_t e = 0; e < nnz; ++e) {
+    if (col_idx[e] < 0 || col_idx[e] >= n) return ORC_E_GRAPH;
+    if (!(w[e] > 0.0f) || !isfinite(w[e])) return ORC_E_GRAPH;
+  }
+  for (int32_t u = 0; u < n; ++u)
+    if (labels[u] < 0 || labels[u] >= L) return ORC_E_LABEL;
+  if (nnz % 2 != 0) return ORC_E_GRAPH;
+  int64_t m = nnz / 2;
+  if (m == 0) return ORC_E_NOEDGES;
+
+  int64_t* nc = calloc((size_t)L, sizeof(int64_t));   /* |c| */
+  int64_t* in2 = calloc((size_t)L, sizeof(int64_t));  /* 2|E_c^in| (unweighted) */
+  int64_t* outc = calloc((size_t)L, sizeof(int64_t)); /* |E_c^out| (unweighted) */
+  nsum* s_c = calloc((size_t)L, sizeof(nsum));        /* s(c) */
+  nsum* win2 = calloc((size_t)L, sizeof(nsum));       /* 2 w_in(c) */
+  nsum* wout = calloc((size_t)L, sizeof(nsum));       /* w_out(c) */
+  double* dens = calloc((size_t)L, sizeof(double));
+  nsum* pen = calloc((size_t)L, sizeof(nsum));
+  if (!nc || !in2 || !outc || !s_c || !win2 || !wout || !dens || !pen) {
+    free(nc); free(in2); free(outc); free(s_c); free(win2); free(wout); free(dens); free(pen);
+    return ORC_E_NOMEM;
+  }
+  for (int32_t u = 0; u < n; ++u) nc[labels[u]] += 1;
+  nsum Wsum = {0, 0};
+  int64_t nkeys = 0;
+  for (int32_t u = 0; u < n; ++u) {
+    int32_t cu = labels[u];
+    for (int64_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e) {
+      int32_t cv = labels[col_idx[e]];
+      double we = (double)w[e];
+      ns_add(&Wsum, we);
+      ns_add(&s_c[cu], we);
+      if (cv == cu) { in2[cu] += 1; ns_add(&win2[cu], we); }
+      else { outc[cu] += 1; ns_add(&wout[cu], we); if (cu < cv) ++nkeys; }
+    }
+  }
+  double W = ns_get(&Wsum) / 2.0;  /* every undirected edge is stored twice */
+  orc_wkey* keys = malloc((size_t)(nkeys > 0 ? nkeys : 1) * sizeof(orc_wkey));
+  if (!keys) {
+    free(nc); free(in2); free(outc); free(s_c); free(win2); free(wout); free(dens); free(pen);
+    return ORC_E_NOMEM;
+  }
+  int64_t kk = 0;
+  for (int32_t u = 0; u < n; ++u) {
+    int32_t cu = labels[u];
+    for (int64_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e) {
+      int32_t cv = labels[col_idx[e]];
+      if (cu < cv) {
+        keys[kk].key = ((uint64_t)(uint32_t)cu << 32) | (uint32_t)cv;
+        keys[kk].w = (double)w[e];
+        ++kk;
+      }
+    }
+  }
+  qsort(keys, (size_t)nkeys, sizeof(orc_wkey), cmp_wkey);
+  for (int32_t c = 0; c < L; ++c) {
+    int64_t e_in = in2[c] / 2;
+    dens[c] = nc[c] >= 2 ? (2.0 * (double)e_in) / ((double)nc[c] * (double)(nc[c] - 1)) : 0.0;  /* unweighted count */
+  }
+  int64_t npairs = 0;
+  int rc = ORC_OK;
+  for (int64_t a = 0; a < nkeys;) {
+    int64_t b = a;
+    nsum wij = {0, 0};
+    while (b < nkeys && keys[b].key == keys[a].key) { ns_add(&wij, keys[b].w); ++b; }
+    int32_t ci = (int32_t)(keys[a].key >> 32), cj = (int32_t)(keys[a].key & 0xffffffffu);
+    int64_t eij = b - a;
+    double dij = (double)eij / ((double)nc[ci] * (double)nc[cj]);   /* unweighted density */
+    double term = ns_get(&wij) / (2.0 * W) * dij;                  /* weighted fraction */
+    ns_add(&pen[ci], term);
+    ns_add(&pen[cj], term);
+    if (pair_cap > 0) {
+      if (npairs < pair_cap) {
+        pair_i[npairs] = ci; pair_j[npairs] = cj; pair_cnt[npairs] = eij;
+        if (pair_w) pair_w[npairs] = ns_get(&wij);
+      } else {
+        rc = ORC_E_CAPACITY;
+      }
+    }
+    ++npairs;
+    a = b;
+  }
+  free(keys);
+
+  nsum q = {0, 0}, qds = {0, 0}, ptot = {0, 0}, swin = {0, 0}, swout = {0, 0};
+  nsum s_dens = {0, 0}, s_contr = {0, 0}, s_exp = {0, 0}, s_cond = {0, 0};
+  int64_t K = 0, sum_ein = 0, sum_eout = 0;
+  for (int32_t c = 0; c < L; ++c) {
+    double wi = ns_get(&win2[c]) / 2.0, wo = ns_get(&wout[c]), sc = ns_get(&s_c[c]);
+    double qt = 0.0, qdt = 0.0, contr = 0.0, expa = 0.0, cond = 0.0;
+    if (nc[c] > 0) {
+      ++K;
+      sum_ein += in2[c] / 2;
+      sum_eout += outc[c];
+      double tot = sc / (2.0 * W);
+      qt = wi / W - tot * tot;
+      double tdc = tot * dens[c];
+      qdt = wi / W * dens[c] - tdc * tdc - ns_get(&pen[c]);
+      contr = 2.0 * wi / (double)nc[c];
+      expa = wo / (double)nc[c];
+      cond = sc > 0.0 ? wo / sc : 0.0;
+      ns_add(&q, qt);
+      ns_add(&qds, qdt);
+      ns_add(&ptot, ns_get(&pen[c]));
+      ns_add(&swin, wi);
+      ns_add(&swout, wo);
+      ns_add(&s_dens, dens[c]);
+      ns_add(&s_contr, contr);
+      ns_add(&s_exp, expa);
+      ns_add(&s_cond, cond);
+    }
+    if (strength) strength[c] = sc;
+    if (w_in) w_in[c] = wi;
+    if (w_out) w_out[c] = wo;
+    if (intra_density) intra_density[c] = dens[c];
+    if (contraction) contraction[c] = contr;
+    if (expansion) expansion[c] = expa;
+    if (conductance) conductance[c] = cond;
+    if (q_term) q_term[c] = qt;
+    if (qds_term) qds_term[c] = qdt;
+  }
+  out->n = n;
+  out->m = m;
+  out->K = K;
+  out->num_pairs = npairs;
+  out->sum_ein = sum_ein;
+  out->sum_eout = sum_eout;
+  out->W = W;
+  out->sum_w_in = ns_get(&swin);
+  out->sum_w_out = ns_get(&swout);
+  out->Q = ns_get(&q);
+  out->Qds = ns_get(&qds);
+  out->split_penalty = ns_get(&ptot);
+  out->mean_intra_edges = ns_get(&swin) / (double)K;
+  out->mean_intra_density = ns_get(&s_dens) / (double)K;
+  out->mean_contraction = ns_get(&s_contr) / (double)K;
+  out->mean_inter_edges = ns_get(&swout) / (double)K;
+  out->mean_expansion = ns_get(&s_exp) / (double)K;
+  out->mean_conductance = ns_get(&s_cond) / (double)K;
+  free(nc); free(in2); free(outc); free(s_c); free(win2); free(wout); free(dens); free(pen);
   return rc;
 }
 

@@ -14,6 +14,7 @@ import pytest
 import oracle
 from tests import test_oracle_compare_pins as CP
 from tests import test_oracle_score_pins as SP
+from tests import test_oracle_weighted_pins as WP
 
 SRC = os.path.join(os.path.dirname(oracle.__file__), "cq_oracle.c")
 
@@ -21,9 +22,12 @@ MUTANTS = {
     "penalty_factor": ("double term = (double)eij / (2.0 * (double)m) * dij;", "double term = (double)eij / ((double)m) * dij;"),
     "q_square": ("qt = (double)e_in / (double)m - tot * tot;", "qt = (double)e_in / (double)m - tot;"),
     "q_total": ("double tot = (double)(2 * e_in + e_out) / (2.0 * (double)m);", "double tot = (double)(e_in + e_out) / (2.0 * (double)m);"),
-    "qds_sign": ("- tdc * tdc - ns_get(&pen[c]);", "- tdc * tdc + ns_get(&pen[c]);"),
-    "density": ("((double)nc[c] * (double)(nc[c] - 1))", "((double)nc[c] * (double)(nc[c]))"),
-    "pair_density_operand": ("((double)nc[ci] * (double)nc[cj])", "((double)nc[ci] * (double)nc[ci])"),
+    "qds_sign": ("qdt = (double)e_in / (double)m * dens[c] - tdc * tdc - ns_get(&pen[c]);",
+                 "qdt = (double)e_in / (double)m * dens[c] - tdc * tdc + ns_get(&pen[c]);"),
+    "density": ("((double)nc[c] * (double)(nc[c] - 1)) : 0.0;\n  }\n\n  /* split penalty",
+                "((double)nc[c] * (double)(nc[c])) : 0.0;\n  }\n\n  /* split penalty"),
+    "pair_density_operand": ("((double)nc[ci] * (double)nc[cj]);\n    double term = (double)eij",
+                             "((double)nc[ci] * (double)nc[ci]);\n    double term = (double)eij"),
     "pair_key_orient": ("if (cu < cv) keys[kk++]", "if (cu > cv) keys[kk++]"),
     "conductance": ("(double)e_out / (double)(2 * e_in + e_out) : 0.0", "(double)e_out / (double)(e_in + e_out) : 0.0"),
     "expansion": ("expa = (double)e_out / (double)nc[c];", "expa = (double)e_in / (double)nc[c];"),
@@ -37,6 +41,17 @@ MUTANTS = {
     "a11_choose": ("a11 += choose2(nij);", "a11 += nij;"),
     "ari_half": ("double dd = 0.5 * (", "double dd = 1.0 * ("),
     "ji_numerator": ("out->JI = dj != 0 ? (double)a11 / (double)dj : 1.0;", "out->JI = dj != 0 ? (double)(a11 + a00) / (double)dj : 1.0;"),
+    # weighted score
+    "w_total_half": ("double W = ns_get(&Wsum) / 2.0;", "double W = ns_get(&Wsum);"),
+    "w_q_square": ("qt = wi / W - tot * tot;", "qt = wi / W - tot;"),
+    "w_strength": ("double tot = sc / (2.0 * W);", "double tot = (sc - wo) / (2.0 * W);"),
+    "w_in_half": ("double wi = ns_get(&win2[c]) / 2.0,", "double wi = ns_get(&win2[c]),"),
+    "w_density_weighted": ("dens[c] = nc[c] >= 2 ? (2.0 * (double)e_in) / ((double)nc[c] * (double)(nc[c] - 1)) : 0.0;  /* unweighted count */",
+                           "dens[c] = nc[c] >= 2 ? ns_get(&win2[c]) / ((double)nc[c] * (double)(nc[c] - 1)) : 0.0;"),
+    "w_pair_density_weighted": ("double dij = (double)eij / ((double)nc[ci] * (double)nc[cj]);   /* unweighted density */",
+                                "double dij = ns_get(&wij) / ((double)nc[ci] * (double)nc[cj]);"),
+    "w_pair_weight": ("keys[kk].w = (double)w[e];", "keys[kk].w = 1.0;"),
+    "w_conductance": ("cond = sc > 0.0 ? wo / sc : 0.0;", "cond = sc > 0.0 ? wo / (sc - wo) : 0.0;"),
 }
 
 
@@ -53,6 +68,7 @@ def _build_mutant(tmpdir, name):
     ns = types.SimpleNamespace(**{k: getattr(oracle, k) for k in dir(oracle) if k.startswith("ORC_") or k == "OracleError"})
     ns.score = partial(oracle.score, _lib=lib)
     ns.compare = partial(oracle.compare, _lib=lib)
+    ns.score_w = partial(oracle.score_w, _lib=lib)
     return ns
 
 
@@ -70,6 +86,11 @@ def _pins(orc):
         CP.test_against_brute_force_and_sklearn(orc, case)
     CP.test_identical_partitions(orc, 0)
     CP.test_degenerate_conventions(orc)
+    WP.test_two_triangles_weighted(orc)
+    for case in WP._cases()[2:4]:
+        WP.test_unit_weights_equal_unweighted(orc, case)
+    for seed in (1, 2):
+        WP.test_against_dense_weighted_algebra(orc, seed)
 
 
 def test_unmutated_oracle_passes_the_pin_set(orc):
