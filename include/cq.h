@@ -105,6 +105,9 @@ typedef struct {
   uint32_t reordered;  /* CQ_GRAPH_REORDER if the graph is stored in a locality order, plus
                           CQ_GRAPH_NO_BLOCKS if it is stored without column blocks */
   int64_t owned_bytes; /* device memory the graph handle allocated (0 without CQ_GRAPH_REORDER) */
+  uint32_t weighted;   /* 1 for a graph registered with cq_graph_load_weighted */
+  uint32_t pad;
+  double total_weight; /* W: sum of the edge weights (|E| for an unweighted graph) */
 } cq_graph_stats;
 
 /*
@@ -134,13 +137,32 @@ typedef struct {
  */
 cq_status cq_graph_load(cq_context* ctx, int32_t n, int64_t nnz, const int32_t* d_row_ptr,
                         const int32_t* d_col_idx, uint32_t flags, cq_graph** out);
+/*
+ * Register an edge-weighted graph: as cq_graph_load, plus
+ *   d_weights  DEVICE float[nnz], the weight of every stored entry, BORROWED like the
+ *              CSR arrays; finite, in [2^-40, 2^40], and equal for the two entries of
+ *              an undirected edge (checked with CQ_VALIDATE_GRAPH).
+ * Scoring a weighted graph gives Eqs. 8-9 and the measures of Section II-B3 with
+ * weight sums in place of edge counts, while the densities d_c and d_{ci,cj} keep the
+ * unweighted counts (the paper's note for weighted networks): see cq_score_result.
+ * The total weight is summed exactly at load (cq_graph_stats.total_weight).
+ * Returns CQ_E_GRAPH_FORMAT for a weight outside the range or a mismatched pair.
+ */
+cq_status cq_graph_load_weighted(cq_context* ctx, int32_t n, int64_t nnz, const int32_t* d_row_ptr,
+                                 const int32_t* d_col_idx, const float* d_weights, uint32_t flags,
+                                 cq_graph** out);
 cq_status cq_graph_get_stats(const cq_graph* g, cq_graph_stats* out);
 void cq_graph_release(cq_graph* g);
 
 /* ---- scoring one partition (Section II-B) ---------------------------------- */
 
 /* HOST result of cq_score_partition.  "Communities" are the label ids carried by
- * at least one node; K counts them; means are unweighted over those K. */
+ * at least one node; K counts them; means are unweighted over those K.
+ * Weighted graphs (weighted = 1): the integer fields keep the unweighted edge counts;
+ * Q, Qds, split_penalty and the means of intra-edges (w_in), contraction (2 w_in/|c|),
+ * inter-edges (w_out), expansion (w_out/|c|) and conductance (w_out/s(c)) use weight
+ * sums, with W = total_weight in place of |E| and s(c) = 2 w_in(c) + w_out(c); the
+ * intra-density mean and the pair densities inside Qds use the unweighted counts. */
 typedef struct {
   int64_t n, m;              /* |V|, |E| */
   int64_t K;                 /* non-empty communities */
@@ -154,11 +176,17 @@ typedef struct {
   double mean_intra_edges, mean_intra_density, mean_contraction;
   double mean_inter_edges, mean_expansion, mean_conductance;
   uint32_t device_flags;     /* raw device error bits (0 on success) */
-  uint32_t reserved;
+  uint32_t weighted;         /* 1 when the graph is edge-weighted */
+  double total_weight;       /* W (|E| when unweighted) */
+  double sum_w_in;           /* sum_c w_in(c) (sum_ein when unweighted) */
+  double sum_w_out;          /* sum_c w_out(c) (sum_eout when unweighted) */
 } cq_score_result;
 
 /* Optional per-label outputs: DEVICE arrays of length num_labels, each may be NULL.
- * Entries for label ids that no node carries are zero. */
+ * Entries for label ids that no node carries are zero.  On a weighted graph
+ * contraction, expansion, conductance, q_term and qds_term take the weight sums of
+ * cq_score_result (2 w_in(c)/|c|, w_out(c)/|c|, w_out(c)/s(c)); size, degsum, ein,
+ * eout and intra_density stay unweighted counts. */
 typedef struct {
   int64_t* size;           /* |c| */
   int64_t* degsum;         /* 2|E_c^in| + |E_c^out| */
@@ -170,7 +198,11 @@ typedef struct {
   double* conductance;     /* |E_c^out| / (2|E_c^in| + |E_c^out|); 0 when that is 0 */
   double* q_term;          /* bracket of Eq. 8 for c */
   double* qds_term;        /* bracket of Eq. 9 for c (including its split-penalty sum) */
+  double* w_in;            /* weighted graphs: w_in(c) (ignored otherwise) */
+  double* strength;        /* weighted graphs: s(c) = 2 w_in(c) + w_out(c) (ignored otherwise) */
 } cq_per_community;
+/* (On a weighted graph contraction, expansion, conductance, q_term and qds_term are the
+ * weighted forms; size, degsum, ein, eout and intra_density stay unweighted.) */
 
 /* Optional export of the inter-community edge counts |E_{ci,cj}| (Eq. 9): DEVICE
  * arrays of `capacity` entries; one entry per unordered pair ci < cj with a
@@ -194,8 +226,9 @@ size_t cq_score_workspace_size(const cq_graph* g, int32_t num_labels);
  *   h_out          HOST result.
  *   per_comm       optional per-label DEVICE outputs (NULL to skip).
  *   pairs          optional pair-table export (NULL to skip).
- * Synchronous.  Errors: CQ_E_INVALID_ARG, CQ_E_WORKSPACE, CQ_E_NO_EDGES,
- * CQ_E_LABEL_RANGE, CQ_E_CAPACITY, CQ_E_DEVICE.
+ * Synchronous.  Errors: CQ_E_INVALID_ARG (also: a weighted graph with more than
+ * 32768 label ids), CQ_E_WORKSPACE, CQ_E_NO_EDGES, CQ_E_LABEL_RANGE, CQ_E_CAPACITY,
+ * CQ_E_DEVICE.
  */
 cq_status cq_score_partition(cq_context* ctx, const cq_graph* g, const int32_t* d_labels,
                              int32_t num_labels, void* d_ws, size_t ws_bytes, cq_score_result* h_out,
@@ -218,8 +251,8 @@ cq_status cq_score_partition_async(cq_context* ctx, const cq_graph* g, const int
  * the per-community pass is one persistent launch over the communities of all tasks.
  * The stage sequence is captured once in a HIP graph and replayed by cq_batch_run.
  * Results are those of cq_score_partition for each task (bit for bit).
- * Envelope: 1 <= num_labels <= 16384 per task, graphs with at least one edge; larger
- * label spaces go through cq_score_partition. */
+ * Envelope: 1 <= num_labels <= 16384 per task, unweighted graphs with at least one
+ * edge; larger label spaces and weighted graphs go through cq_score_partition. */
 typedef struct {
   const cq_graph* graph;    /* registered graph (may be shared by several tasks) */
   const int32_t* d_labels;  /* DEVICE int32[n], read at every run (contents may change between runs) */

@@ -50,7 +50,8 @@ class ScoreResult(ctypes.Structure):
     ] + [(k, ctypes.c_double) for k in (
         "Q", "Qds", "split_penalty", "mean_intra_edges", "mean_intra_density", "mean_contraction",
         "mean_inter_edges", "mean_expansion", "mean_conductance",
-    )] + [("device_flags", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+    )] + [("device_flags", ctypes.c_uint32), ("weighted", ctypes.c_uint32)] + [
+        (k, ctypes.c_double) for k in ("total_weight", "sum_w_in", "sum_w_out")]
 
 
 class CompareResult(ctypes.Structure):
@@ -60,7 +61,7 @@ class CompareResult(ctypes.Structure):
 
 
 PER_COMMUNITY_FIELDS = ("size", "degsum", "ein", "eout", "intra_density", "contraction", "expansion",
-                        "conductance", "q_term", "qds_term")
+                        "conductance", "q_term", "qds_term", "w_in", "strength")
 
 
 class PerCommunity(ctypes.Structure):
@@ -98,7 +99,8 @@ CQ_BATCH_NO_GRAPH = 2
 
 class GraphStats(ctypes.Structure):
     _fields_ = [("n", _I64), ("nnz", _I64), ("m", _I64), ("max_degree", _I64), ("validated", ctypes.c_uint32),
-                ("reordered", ctypes.c_uint32), ("owned_bytes", _I64)]
+                ("reordered", ctypes.c_uint32), ("owned_bytes", _I64), ("weighted", ctypes.c_uint32),
+                ("pad", ctypes.c_uint32), ("total_weight", ctypes.c_double)]
 
 
 def _load():
@@ -112,6 +114,7 @@ def _load():
         "cq_context_destroy": (None, [_P]),
         "cq_context_last_error": (ctypes.c_char_p, [_P]),
         "cq_graph_load": (_I32, [_P, _I32, _I64, _P, _P, ctypes.c_uint32, ctypes.POINTER(_P)]),
+        "cq_graph_load_weighted": (_I32, [_P, _I32, _I64, _P, _P, _P, ctypes.c_uint32, ctypes.POINTER(_P)]),
         "cq_graph_get_stats": (_I32, [_P, ctypes.POINTER(GraphStats)]),
         "cq_graph_release": (None, [_P]),
         "cq_score_workspace_size": (_SZ, [_P, _I32]),
@@ -221,12 +224,19 @@ def cq_graph_load(ctx: int, n: int, nnz: int, d_row_ptr: int, d_col_idx: int, fl
     return out.value
 
 
+def cq_graph_load_weighted(ctx: int, n: int, nnz: int, d_row_ptr: int, d_col_idx: int, d_weights: int,
+                           flags: int = 0) -> int:
+    out = _P()
+    _check(ctx, _lib.cq_graph_load_weighted(ctx, n, nnz, d_row_ptr, d_col_idx, d_weights, flags, ctypes.byref(out)))
+    return out.value
+
+
 def cq_graph_get_stats(g: int) -> dict:
     s = GraphStats()
     st = _lib.cq_graph_get_stats(g, ctypes.byref(s))
     if st != CQ_OK:
         raise CQError(st)
-    return {k: getattr(s, k) for k, _ in GraphStats._fields_}
+    return {k: getattr(s, k) for k, _ in GraphStats._fields_ if k != "pad"}
 
 
 def cq_graph_release(g: int) -> None:
@@ -368,6 +378,13 @@ def _dev_i32(t, name):
     return t
 
 
+def _dev_f32(t, name):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda" or t.dtype != torch.float32 or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous float32 CUDA tensor")
+    return t
+
+
 def as_dict(res) -> dict:
     return {k: getattr(res, k) for k, _ in res._fields_ if k != "reserved"}
 
@@ -409,19 +426,29 @@ class Graph:
     """A registered graph; keeps its CSR tensors alive while registered."""
 
     def __init__(self, ctx: Context, row_ptr, col_idx, validate: bool = False, reorder: bool = False,
-                 blocks: bool | None = None):
+                 blocks: bool | None = None, weights=None):
         """reorder: store in a locality order; blocks (with reorder): None = column blocks
-        when the library's size rule says so, True = always (n <= 2^24), False = never."""
+        when the library's size rule says so, True = always (n <= 2^24), False = never.
+        weights: float32 per stored entry (an edge-weighted graph), or None."""
         self.ctx = ctx
         self.row_ptr = _dev_i32(row_ptr, "row_ptr")
         self.col_idx = _dev_i32(col_idx, "col_idx")
         self.n = self.row_ptr.numel() - 1
         self.nnz = self.col_idx.numel()
-        self.handle = cq_graph_load(ctx.handle, self.n, self.nnz, self.row_ptr.data_ptr(),
-                                    self.col_idx.data_ptr() if self.nnz else None,
-                                    (CQ_VALIDATE_GRAPH if validate else 0) | (CQ_GRAPH_REORDER if reorder else 0)
-                                    | (CQ_GRAPH_BLOCKS if reorder and blocks is True else 0)
-                                    | (CQ_GRAPH_NO_BLOCKS if reorder and blocks is False else 0))
+        self.handle = 0
+        flags = ((CQ_VALIDATE_GRAPH if validate else 0) | (CQ_GRAPH_REORDER if reorder else 0)
+                 | (CQ_GRAPH_BLOCKS if reorder and blocks is True else 0)
+                 | (CQ_GRAPH_NO_BLOCKS if reorder and blocks is False else 0))
+        col = self.col_idx.data_ptr() if self.nnz else None
+        if weights is None:
+            self.weights = None
+            self.handle = cq_graph_load(ctx.handle, self.n, self.nnz, self.row_ptr.data_ptr(), col, flags)
+        else:
+            self.weights = _dev_f32(weights, "weights")
+            if self.weights.numel() != self.nnz:
+                raise ValueError("weights must have one entry per stored CSR entry")
+            self.handle = cq_graph_load_weighted(ctx.handle, self.n, self.nnz, self.row_ptr.data_ptr(), col,
+                                                 self.weights.data_ptr() if self.nnz else None, flags)
         self.stats = cq_graph_get_stats(self.handle)
 
     def workspace_size(self, num_labels: int) -> int:

@@ -53,6 +53,22 @@ __device__ __forceinline__ double unfix96(u128 v) {
   return neg ? -d : d;
 }
 
+// ---- exact edge-weight sums --------------------------------------------------
+// A float32 weight w in [2^-40, 2^40] times 2^64 is an integer below 2^105: its 24-bit
+// significand shifted by (biased exponent - 86).  Sums of such integers are exact and
+// independent of order (2^31 entries stay below 2^128).
+constexpr float WEIGHT_MIN = 9.094947017729282e-13f;  // 2^-40
+constexpr float WEIGHT_MAX = 1099511627776.0f;        // 2^40
+__device__ __forceinline__ u128 fix64_f32(float w) {
+  const u32 b = __float_as_uint(w);
+  const u32 e = (b >> 23) & 0xFFu;
+  return (u128)((b & 0x7FFFFFu) | 0x800000u) << (e - 86u);
+}
+// value / 2^64 of an exact weight sum
+__device__ __forceinline__ double unfix64(u128 v) {
+  return (double)(u64)(v >> 64) + (double)(u64)v * 5.421010862427522e-20;  // 2^-64
+}
+
 // ---- wave / block reductions (wave64) ---------------------------------------
 __device__ __forceinline__ u64 wave_sum_u64(u64 x) {
   for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);

@@ -45,7 +45,8 @@ __global__ void k_check_csr(int n, long long nnz, const int32_t* __restrict__ rp
   if (bad) atomicOr(flags, F_GRAPH);
 }
 
-__global__ void k_check_symmetric(int n, const int32_t* __restrict__ rp, const int32_t* __restrict__ col, u32* __restrict__ flags) {
+__global__ void k_check_symmetric(int n, const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
+                                  const float* __restrict__ w, u32* __restrict__ flags) {
   // one wave per row; lanes stride over the row's entries
   int lane = threadIdx.x & 63;
   size_t wave = ((size_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
@@ -63,7 +64,37 @@ __global__ void k_check_symmetric(int n, const int32_t* __restrict__ rp, const i
         if (col[mid] < (int)u) lo = mid + 1; else hi = mid;
       }
       if (lo >= rp[v + 1] || col[lo] != (int)u) bad = 1;
+      else if (w && __float_as_uint(w[lo]) != __float_as_uint(w[e])) bad = 1;  // the two entries of an edge
     }
+  }
+  if (bad) atomicOr(flags, F_GRAPH);
+}
+
+// Edge weights: finite and in [WEIGHT_MIN, WEIGHT_MAX]; per-block exact sums of
+// w * 2^64 (two words per block) for the total weight.
+__global__ __launch_bounds__(256) void k_check_weights(long long nnz, const float* __restrict__ w, u32* __restrict__ flags,
+                                                       u64* __restrict__ parts) {
+  __shared__ u64 s_lo[4], s_hi[4];
+  u32 bad = 0;
+  u128 sum = 0;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < (size_t)nnz; e += stride) {
+    const float x = w[e];
+    if (!(x >= WEIGHT_MIN && x <= WEIGHT_MAX)) bad = 1;  // also catches NaN
+    else sum += fix64_f32(x);
+  }
+  sum = wave_sum_u128(sum);
+  const int wv = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    s_lo[wv] = (u64)sum;
+    s_hi[wv] = (u64)(sum >> 64);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    u128 t = 0;
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) t += ((u128)s_hi[i] << 64) | s_lo[i];
+    parts[2 * blockIdx.x] = (u64)t;
+    parts[2 * blockIdx.x + 1] = (u64)(t >> 64);
   }
   if (bad) atomicOr(flags, F_GRAPH);
 }
@@ -225,14 +256,18 @@ __global__ void k_new_degree(int n, const int32_t* __restrict__ rp, const int32_
 // row i of the renumbered graph = row old[i] of the input, with neighbour ids renumbered
 __global__ __launch_bounds__(256) void k_relabel_rows(int n, const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
                                                       const int32_t* __restrict__ old, const int32_t* __restrict__ newid,
-                                                      const int32_t* __restrict__ rp2, int32_t* __restrict__ col2) {
+                                                      const int32_t* __restrict__ rp2, int32_t* __restrict__ col2,
+                                                      const float* __restrict__ w, float* __restrict__ w2) {
   const int lane = threadIdx.x & 63;
   const size_t wave = ((size_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const size_t nwaves = ((size_t)gridDim.x * blockDim.x) >> 6;
   for (size_t i = wave; i < (size_t)n; i += nwaves) {
     const int u = old[i];
     const int a = rp[u], deg = rp[u + 1] - a, b = rp2[i];
-    for (int k = lane; k < deg; k += 64) col2[b + k] = newid[col[a + k]];
+    for (int k = lane; k < deg; k += 64) {
+      col2[b + k] = newid[col[a + k]];
+      if (w) w2[b + k] = w[a + k];
+    }
   }
 }
 
@@ -266,7 +301,8 @@ __global__ __launch_bounds__(256) void k_blk_count(int n, const int32_t* __restr
 
 __global__ __launch_bounds__(256) void k_blk_place(int n, const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
                                                    int span, const u32* __restrict__ RPB, int32_t* __restrict__ colb,
-                                                   int32_t* __restrict__ rowb) {
+                                                   int32_t* __restrict__ rowb, const float* __restrict__ w,
+                                                   float* __restrict__ wb) {
   const int lane = threadIdx.x & 63;
   const u64 below = lane ? (~0ull >> (64 - lane)) : 0ull;
   const size_t wave = ((size_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
@@ -289,6 +325,7 @@ __global__ __launch_bounds__(256) void k_blk_place(int n, const int32_t* __restr
       if (in) {
         colb[slot] = v;
         rowb[slot] = (int32_t)u;
+        if (w) wb[slot] = w[a + k0 + lane];
       }
     }
   }
@@ -759,7 +796,7 @@ template <bool PRIV, class LT>
 __global__ __launch_bounds__(GROWS) void k_gather(int n, const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
                                                   const LT* __restrict__ labx, int L, int chunk, const u32* __restrict__ PM,
                                                   const u32* __restrict__ start, const u32* __restrict__ loc,
-                                                  LT* __restrict__ CB) {
+                                                  LT* __restrict__ CB, const float* __restrict__ w, float* __restrict__ CW) {
   __shared__ int s_rs[GROWS + 1];
   __shared__ u32 s_base[GROWS];
   const int tid = threadIdx.x;
@@ -789,6 +826,7 @@ __global__ __launch_bounds__(GROWS) void k_gather(int n, const int32_t* __restri
     const u32 base = s_base[lo];
     if (base == SENT) continue;
     CB[base + (u32)(e - s_rs[lo])] = labx[col[e]];
+    if (CW) CW[base + (u32)(e - s_rs[lo])] = w[e];
   }
 }
 
@@ -867,7 +905,8 @@ template <class LT>
 __device__ void gather_own_tile(u32 y, u32 t, int n, int span, const u32* __restrict__ RPB,
                                 const int32_t* __restrict__ colb, const LT* __restrict__ labx,
                                 const u32* __restrict__ start, const u32* __restrict__ D, u32* __restrict__ cursor,
-                                Ctl* __restrict__ ctl, LT* __restrict__ CB, u32* lds, u32* s_w) {
+                                Ctl* __restrict__ ctl, LT* __restrict__ CB, const float* __restrict__ wb,
+                                float* __restrict__ CW, u32* lds, u32* s_w) {
   using LL = GatherLds<LT>;
   constexpr int PER = LL::PER;
   constexpr int WIT = (LL::WINV + BT_THREADS - 1) / BT_THREADS;
@@ -970,6 +1009,11 @@ __device__ void gather_own_tile(u32 y, u32 t, int n, int span, const u32* __rest
 #pragma unroll
     for (int u = 0; u < BT_UNROLL; ++u)
       if (pos[u] != SENT) CB[pos[u]] = x[u];
+    if (CW) {
+#pragma unroll
+      for (int u = 0; u < BT_UNROLL; ++u)
+        if (pos[u] != SENT) CW[pos[u]] = wb[e0 + eb + (u32)(u * BT_THREADS)];
+    }
   }
 }
 
@@ -978,7 +1022,8 @@ template <class LT>
 __device__ void gather_far_tile(u32 y, u32 t, const FarTable& ft, const int32_t* __restrict__ colb,
                                 const int32_t* __restrict__ rowb, const LT* __restrict__ labx,
                                 const u32* __restrict__ start, const u32* __restrict__ D, u32* __restrict__ cursor,
-                                Ctl* __restrict__ ctl, LT* __restrict__ CB, u32* lds, u32* s_w) {
+                                Ctl* __restrict__ ctl, LT* __restrict__ CB, const float* __restrict__ wb,
+                                float* __restrict__ CW, u32* lds, u32* s_w) {
   u32* s_rf = lds;               // first entry of run q (tile-relative); s_rf[nruns] = entry count
   u32* s_rb = lds + FT_ENT + 1;  // staged row labels, then label of run q, then its segment place
   const u32 b0 = ft.b[y][0], b1 = ft.b[y][1], b2 = ft.b[y][2], b3 = ft.b[y][3];
@@ -1040,7 +1085,10 @@ __device__ void gather_far_tile(u32 y, u32 t, const FarTable& ft, const int32_t*
     if (i >= ne) continue;
     const u32 run = q - 1u;  // entry i lies in the last run that starts at or before it
     const u32 base = s_rb[run];
-    if (base != SENT) CB[base + (i - s_rf[run])] = x[j];
+    if (base != SENT) {
+      CB[base + (i - s_rf[run])] = x[j];
+      if (CW) CW[base + (i - s_rf[run])] = wb[e0 + i];
+    }
   }
 }
 
@@ -1054,15 +1102,16 @@ __global__ __launch_bounds__(BT_THREADS) void k_gather_blocked(int n, int span, 
                                                                u32 own_groups, u32 far_groups,
                                                                const LT* __restrict__ labx, const u32* __restrict__ start,
                                                                const u32* __restrict__ D, u32* __restrict__ cursor,
-                                                               Ctl* __restrict__ ctl, LT* __restrict__ CB) {
+                                                               Ctl* __restrict__ ctl, LT* __restrict__ CB,
+                                                               const float* __restrict__ wb, float* __restrict__ CW) {
   __shared__ __align__(16) u32 lds[GatherLds<LT>::WORDS];
   __shared__ u32 s_w[BT_THREADS / 64];
   const u32 y = blockIdx.x % 8u, gi = blockIdx.x / 8u;
   if (y >= (u32)COL_BLOCKS || gi >= own_groups + far_groups) return;
   if (gi < own_groups)
-    gather_own_tile<LT>(y, gi, n, span, RPB, colb, labx, start, D, cursor, ctl, CB, lds, s_w);
+    gather_own_tile<LT>(y, gi, n, span, RPB, colb, labx, start, D, cursor, ctl, CB, wb, CW, lds, s_w);
   else
-    gather_far_tile<LT>(y, gi - own_groups, ft, colb, rowb, labx, start, D, cursor, ctl, CB, lds, s_w);
+    gather_far_tile<LT>(y, gi - own_groups, ft, colb, rowb, labx, start, D, cursor, ctl, CB, wb, CW, lds, s_w);
 }
 
 // Comparison: the segment of ground-truth community a_u receives b_u.
@@ -1447,6 +1496,116 @@ struct ScoreVis {
   }
 };
 
+// ---------------------------------------------------------------------------
+// Weighted group pass (edge-weighted graphs; labels fit a direct LDS table).  Per
+// community g, besides everything ScoreVis computes from the counts:
+//   SW[g] = sum of the weights in g's segment = strength sum s(g)       (x 2^64, exact)
+//   IW[g] = sum of the weights of entries labelled g = 2 w_in(g)         (x 2^64, exact)
+//   PENW[g] = sum_{j != g} w(g,j) d_{g,j} / (2W), d_{g,j} = |E_gj| / (|g||j|)   (fix96)
+// The penalty is summed entry by entry in a second pass over the segment, once the
+// table holds every count |E_gj|: entry (j, w) adds w |E_gj| / (2W |g| |j|).
+struct WeightedOut {
+  u64* SW;
+  u64* IW;
+  u64* PENW;
+  double twoW;
+};
+
+template <class LT>
+__device__ void group_one_w(const LT* __restrict__ CB, const float* __restrict__ CW, const u32 base, const u32 len,
+                            const u32 g, const u32 Lv, ScoreVis& vis, const WeightedOut& wo) {
+  extern __shared__ u32 tab[];
+  __shared__ u32 s_hot;
+  __shared__ u64 r_w[6][GBLOCK / 64];
+  const int tid = threadIdx.x;
+  ScoreVis::State st;
+  vis.begin(st, g);
+  const u32 nq = (Lv + 3u) >> 2;
+  uint4* tab4 = reinterpret_cast<uint4*>(tab);
+  for (u32 q = tid; q < nq; q += GBLOCK) tab4[q] = make_uint4(0u, 0u, 0u, 0u);
+  if (tid == 0) s_hot = 0;
+  __syncthreads();
+  u32 mine = 0;
+  u128 sall = 0, shot = 0;
+  for (u32 e = tid; e < len; e += GBLOCK) {
+    const u32 j = (u32)CB[base + e];
+    const u128 wf = fix64_f32(CW[base + e]);
+    sall += wf;
+    if (j == g) {
+      ++mine;
+      shot += wf;
+    } else if (j < Lv) {
+      atomicAdd(&tab[j], 1u);
+    }
+  }
+  if (mine) atomicAdd(&s_hot, mine);
+  __syncthreads();
+  if (tid == 0 && s_hot && g < Lv) vis.visit(st, g, s_hot);
+  for (u32 q = tid; q < nq; q += GBLOCK) {
+    const uint4 x = tab4[q];
+    if (x.x) vis.visit(st, 4u * q, x.x);
+    if (x.y) vis.visit(st, 4u * q + 1u, x.y);
+    if (x.z) vis.visit(st, 4u * q + 2u, x.z);
+    if (x.w) vis.visit(st, 4u * q + 3u, x.w);
+  }
+  // second pass: weighted split penalty, with every count now in the table
+  u128 pw = 0;
+  const double gden = wo.twoW * (double)vis.N[g];
+  for (u32 e = tid; e < len; e += GBLOCK) {
+    const u32 j = (u32)CB[base + e];
+    if (j == g || j >= Lv) continue;
+    const double t = (double)CW[base + e] * (double)tab[j] / (gden * (double)vis.N[j]);
+    pw += fix96(t);
+  }
+  vis.finish(st, g);  // one barrier; the reads of tab above are done before anyone clears it
+  {
+    const u128 a = wave_sum_u128(sall), b = wave_sum_u128(shot), c = wave_sum_u128(pw);
+    const int w = tid >> 6;
+    if ((tid & 63) == 0) {
+      r_w[0][w] = (u64)a;
+      r_w[1][w] = (u64)(a >> 64);
+      r_w[2][w] = (u64)b;
+      r_w[3][w] = (u64)(b >> 64);
+      r_w[4][w] = (u64)c;
+      r_w[5][w] = (u64)(c >> 64);
+    }
+  }
+  __syncthreads();
+  if (tid == 0) {
+    u128 a = 0, b = 0, c = 0;
+    for (int i = 0; i < GBLOCK / 64; ++i) {
+      a += ((u128)r_w[1][i] << 64) | r_w[0][i];
+      b += ((u128)r_w[3][i] << 64) | r_w[2][i];
+      c += ((u128)r_w[5][i] << 64) | r_w[4][i];
+    }
+    wo.SW[2 * (size_t)g] = (u64)a;
+    wo.SW[2 * (size_t)g + 1] = (u64)(a >> 64);
+    wo.IW[2 * (size_t)g] = (u64)b;
+    wo.IW[2 * (size_t)g + 1] = (u64)(b >> 64);
+    wo.PENW[2 * (size_t)g] = (u64)c;
+    wo.PENW[2 * (size_t)g + 1] = (u64)(c >> 64);
+  }
+  __syncthreads();
+}
+
+template <class LT>
+__global__ __launch_bounds__(GBLOCK) void k_groups_w(const LT* __restrict__ CB, const float* __restrict__ CW,
+                                                     const u32* __restrict__ seg_start, const u32* __restrict__ seg_len,
+                                                     const u32* __restrict__ order, Ctl* __restrict__ ctl, u32 Lv,
+                                                     ScoreVis vis, WeightedOut wo) {
+  __shared__ u32 s_item;
+  const u32 K = ctl->K;
+  for (;;) {
+    if (threadIdx.x == 0) s_item = atomicAdd(&ctl->ticket, 1u);
+    __syncthreads();
+    const u32 item = s_item;
+    __syncthreads();
+    if (item >= K) break;
+    const u32 g = order[item];
+    group_one_w<LT>(CB, CW, seg_start[g], seg_len[g], g, Lv, vis, wo);
+  }
+}
+
 // Comparison visitor: row i of the contingency table, column j, cell x = |c_i ∩ c'_j|.
 struct CmpVis {
   static constexpr bool kHotIsGroup = false;
@@ -1574,6 +1733,8 @@ struct PerComm {
   double* conductance;
   double* q_term;
   double* qds_term;
+  double* w_in;      // weighted graphs only
+  double* strength;  // weighted graphs only
 };
 
 __device__ void score_final1_body(int L, const u32* __restrict__ N, const u32* __restrict__ D, const u32* __restrict__ I,
@@ -1654,7 +1815,8 @@ struct ScoreResultDev {
   double Q, Qds, split_penalty;
   double mean_intra_edges, mean_intra_density, mean_contraction;
   double mean_inter_edges, mean_expansion, mean_conductance;
-  uint32_t device_flags, reserved;
+  uint32_t device_flags, weighted;
+  double total_weight, sum_w_in, sum_w_out;
 };
 
 __device__ void score_final2_body(int G, const ScorePart* __restrict__ parts, long long n, long long twom, long long ecap,
@@ -1687,9 +1849,139 @@ __device__ void score_final2_body(int G, const ScorePart* __restrict__ parts, lo
   r.mean_expansion = s_exp / Kd;
   r.mean_conductance = s_cond / Kd;
   r.device_flags = ctl->flags | ((ecap > 0 && (long long)ctl->export_count > ecap) ? F_EXPORT : 0u);
-  r.reserved = 0;
+  r.weighted = 0;
+  r.total_weight = (double)m;
+  r.sum_w_in = (double)sein;
+  r.sum_w_out = (double)seout;
   *out = r;
 }
+
+// Weighted final reduction (see group_one_w): per community the Eq. 8 and Eq. 9
+// brackets and the six measures with weight sums, densities from the counts.
+struct WScorePart {
+  u64 K, sein, seout, sD2, np, penw_lo, penw_hi, wi_lo, wi_hi, wo_lo, wo_hi, pad;
+  double q, qds_a, s_dens, s_contr, s_exp, s_cond, pad2[2];
+};
+
+__global__ __launch_bounds__(FBLOCK) void k_score_final1_w(int L, const u32* __restrict__ N, const u32* __restrict__ D,
+                                                           const u32* __restrict__ I, const u32* __restrict__ NP,
+                                                           const u64* __restrict__ SW, const u64* __restrict__ IW,
+                                                           const u64* __restrict__ PENW, double W, PerComm pc,
+                                                           WScorePart* __restrict__ parts) {
+  __shared__ u64 sh_lo[FBLOCK / 64], sh_hi[FBLOCK / 64];
+  __shared__ double sh_d[FBLOCK / 64];
+  const int G = gridDim.x, blk = blockIdx.x;
+  const int R = (L + G - 1) / G;
+  const int c0 = blk * R, c1 = min(L, c0 + R);
+  u64 K = 0, sein = 0, seout = 0, sD2 = 0, np = 0;
+  u128 penw = 0, swi2 = 0, swo = 0;
+  double q = 0, qds_a = 0, s_dens = 0, s_contr = 0, s_exp = 0, s_cond = 0;
+  for (int c = c0 + threadIdx.x; c < c1; c += FBLOCK) {
+    const u32 nc = N[c];
+    int64_t o_size = 0, o_deg = 0, o_ein = 0, o_eout = 0;
+    double o_d = 0, o_contr = 0, o_exp = 0, o_cond = 0, o_q = 0, o_qds = 0, o_wi = 0, o_s = 0;
+    if (nc > 0) {
+      const u32 Dc = D[c], Ic = I[c];
+      const u32 ein = Ic / 2u, eout = Dc - Ic;
+      const u128 s128 = ((u128)SW[2 * (size_t)c + 1] << 64) | SW[2 * (size_t)c];
+      const u128 i128 = ((u128)IW[2 * (size_t)c + 1] << 64) | IW[2 * (size_t)c];
+      const u128 p128 = ((u128)PENW[2 * (size_t)c + 1] << 64) | PENW[2 * (size_t)c];
+      const double sc = unfix64(s128);        // s(c)
+      const double wi = 0.5 * unfix64(i128);  // w_in(c)
+      const double wout = unfix64(s128 - i128);
+      const double d = nc >= 2 ? (2.0 * (double)ein) / (double)((u64)nc * (u64)(nc - 1u)) : 0.0;
+      const double tot = sc / (2.0 * W);
+      const double tdc = tot * d;
+      const double qa = wi / W * d - tdc * tdc;
+      o_size = nc; o_deg = Dc; o_ein = ein; o_eout = eout;
+      o_d = d;
+      o_contr = 2.0 * wi / (double)nc;
+      o_exp = wout / (double)nc;
+      o_cond = sc > 0.0 ? wout / sc : 0.0;
+      o_q = wi / W - tot * tot;
+      o_qds = qa - unfix96(p128);
+      o_wi = wi;
+      o_s = sc;
+      K += 1; sein += ein; seout += eout; sD2 += (u64)Dc * (u64)Dc; np += NP[c];
+      penw += p128; swi2 += i128; swo += s128 - i128;
+      q += o_q; qds_a += qa; s_dens += o_d; s_contr += o_contr; s_exp += o_exp; s_cond += o_cond;
+    }
+    if (pc.size) pc.size[c] = o_size;
+    if (pc.degsum) pc.degsum[c] = o_deg;
+    if (pc.ein) pc.ein[c] = o_ein;
+    if (pc.eout) pc.eout[c] = o_eout;
+    if (pc.intra_density) pc.intra_density[c] = o_d;
+    if (pc.contraction) pc.contraction[c] = o_contr;
+    if (pc.expansion) pc.expansion[c] = o_exp;
+    if (pc.conductance) pc.conductance[c] = o_cond;
+    if (pc.q_term) pc.q_term[c] = o_q;
+    if (pc.qds_term) pc.qds_term[c] = o_qds;
+    if (pc.w_in) pc.w_in[c] = o_wi;
+    if (pc.strength) pc.strength[c] = o_s;
+  }
+  WScorePart p;
+  p.K = block_sum_u64(K, sh_lo);
+  p.sein = block_sum_u64(sein, sh_lo);
+  p.seout = block_sum_u64(seout, sh_lo);
+  p.sD2 = block_sum_u64(sD2, sh_lo);
+  p.np = block_sum_u64(np, sh_lo);
+  u128 t = block_sum_u128(penw, sh_lo, sh_hi);
+  p.penw_lo = (u64)t;
+  p.penw_hi = (u64)(t >> 64);
+  t = block_sum_u128(swi2, sh_lo, sh_hi);
+  p.wi_lo = (u64)t;
+  p.wi_hi = (u64)(t >> 64);
+  t = block_sum_u128(swo, sh_lo, sh_hi);
+  p.wo_lo = (u64)t;
+  p.wo_hi = (u64)(t >> 64);
+  p.pad = 0;
+  p.q = block_sum_f64<FBLOCK / 64>(q, sh_d);
+  p.qds_a = block_sum_f64<FBLOCK / 64>(qds_a, sh_d);
+  p.s_dens = block_sum_f64<FBLOCK / 64>(s_dens, sh_d);
+  p.s_contr = block_sum_f64<FBLOCK / 64>(s_contr, sh_d);
+  p.s_exp = block_sum_f64<FBLOCK / 64>(s_exp, sh_d);
+  p.s_cond = block_sum_f64<FBLOCK / 64>(s_cond, sh_d);
+  p.pad2[0] = p.pad2[1] = 0;
+  if (threadIdx.x == 0) parts[blk] = p;
+}
+
+__global__ void k_score_final2_w(int G, const WScorePart* __restrict__ parts, long long n, long long twom, double W,
+                                 long long ecap, Ctl* __restrict__ ctl, ScoreResultDev* __restrict__ out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  u64 K = 0, sein = 0, seout = 0, sD2 = 0, np = 0;
+  u128 penw = 0, swi2 = 0, swo = 0;
+  double q = 0, qds_a = 0, s_dens = 0, s_contr = 0, s_exp = 0, s_cond = 0;
+  for (int b = 0; b < G; ++b) {
+    const WScorePart p = parts[b];
+    K += p.K; sein += p.sein; seout += p.seout; sD2 += p.sD2; np += p.np;
+    penw += ((u128)p.penw_hi << 64) | p.penw_lo;
+    swi2 += ((u128)p.wi_hi << 64) | p.wi_lo;
+    swo += ((u128)p.wo_hi << 64) | p.wo_lo;
+    q += p.q; qds_a += p.qds_a; s_dens += p.s_dens; s_contr += p.s_contr; s_exp += p.s_exp; s_cond += p.s_cond;
+  }
+  ScoreResultDev r;
+  r.n = n; r.m = twom / 2; r.K = (int64_t)K; r.num_pairs = (int64_t)np;
+  r.sum_ein = (int64_t)sein; r.sum_eout = (int64_t)seout; r.sum_degsum_sq = sD2;
+  const double pen = unfix96(penw);
+  r.Q = q;
+  r.split_penalty = pen;
+  r.Qds = qds_a - pen;
+  const double Kd = (double)K;
+  const double wi = 0.5 * unfix64(swi2), wout = unfix64(swo);
+  r.mean_intra_edges = wi / Kd;
+  r.mean_intra_density = s_dens / Kd;
+  r.mean_contraction = s_contr / Kd;
+  r.mean_inter_edges = wout / Kd;
+  r.mean_expansion = s_exp / Kd;
+  r.mean_conductance = s_cond / Kd;
+  r.device_flags = ctl->flags | ((ecap > 0 && (long long)ctl->export_count > ecap) ? F_EXPORT : 0u);
+  r.weighted = 1;
+  r.total_weight = W;
+  r.sum_w_in = wi;
+  r.sum_w_out = wout;
+  *out = r;
+}
+
 
 __global__ void k_score_final2(int G, const ScorePart* __restrict__ parts, long long n, long long twom, long long ecap,
                                Ctl* __restrict__ ctl, ScoreResultDev* __restrict__ out) {

@@ -59,6 +59,10 @@ struct cq_graph {
   u32* tgt = nullptr;
   u32* pbstart = nullptr;          // first slot of every bucket (nb + 1)
   int perm_buckets = 0;
+  const float* w = nullptr;        // edge weights in the stored entry order (borrowed or owned_w); null: unweighted
+  float* owned_w = nullptr;
+  float* wb = nullptr;             // weights in column-block order (with colb)
+  double total_w = 0.0;            // W, summed exactly at load
   FarTable far{};                  // per block: entry ranges of the rows outside its span
   unsigned far_tiles = 0;          // most far-entry tiles of any block
   int64_t owned_bytes = 0;
@@ -71,6 +75,8 @@ struct cq_graph {
     if (rowb) (void)hipFree(rowb);
     for (u32* p : {deg_in, pos1, tgt, pbstart})
       if (p) (void)hipFree(p);
+    if (owned_w) (void)hipFree(owned_w);
+    if (wb) (void)hipFree(wb);
   }
 };
 
@@ -194,9 +200,10 @@ struct ScoreLayout {
   bool priv, small;  // small: labels fit 16 bits (num_labels <= 65535)
   int chunk, W, G;
   size_t ctl, N, D, start, order, I, NP, PEN, SZ, cursor, loc, HN, HD, labx, CB, parts, res, total;
+  size_t CW, SW, IW, PENW;  // weighted graphs only (0 otherwise)
 };
 
-ScoreLayout score_layout(int64_t n, int64_t nnz, int64_t L) {
+ScoreLayout score_layout(int64_t n, int64_t nnz, int64_t L, bool weighted = false) {
   ScoreLayout s{};
   Carve c;
   s.priv = L <= PRIV_MAX;
@@ -220,8 +227,14 @@ ScoreLayout score_layout(int64_t n, int64_t nnz, int64_t L) {
   s.HD = s.priv ? c.take(4 * (size_t)s.W * L) : 0;
   s.labx = c.take(lt * n);
   s.CB = c.take(lt * nnz);
-  s.parts = c.take(sizeof(ScorePart) * s.G);
+  s.parts = c.take(std::max(sizeof(ScorePart), sizeof(WScorePart)) * s.G);
   s.res = c.take(sizeof(ScoreResultDev));
+  if (weighted) {
+    s.CW = c.take(4 * (size_t)nnz);
+    s.SW = c.take(16 * (size_t)L);
+    s.IW = c.take(16 * (size_t)L);
+    s.PENW = c.take(16 * (size_t)L);
+  }
   s.total = c.off;
   return s;
 }
@@ -321,6 +334,7 @@ void score_launch(cq_context* ctx, const cq_graph* g, const int32_t* labels, int
   u32* loc = at<u32>(ws, lay.loc);
   LT* labx = at<LT>(ws, lay.labx);
   LT* CB = at<LT>(ws, lay.CB);
+  float* CW = g->w ? at<float>(ws, lay.CW) : nullptr;  // weights staged beside the labels
   ScorePart* parts = at<ScorePart>(ws, lay.parts);
   const u32* PM = nullptr;
   {
@@ -395,11 +409,13 @@ void score_launch(cq_context* ctx, const cq_graph* g, const int32_t* labels, int
       const unsigned own_groups = (unsigned)((span + BT_ROWS - 1) / BT_ROWS);
       k_gather_blocked<LT><<<COL_BLOCKS * (own_groups + g->far_tiles), BT_THREADS, 0, s>>>(
           (int)n, (int)span, g->rpb, g->colb, g->rowb, g->far, own_groups, g->far_tiles, labx, start, D,
-          at<u32>(ws, lay.cursor), ctl, CB);
+          at<u32>(ws, lay.cursor), ctl, CB, g->wb, CW);
     } else if (lay.priv)
-      k_gather<true, LT><<<grid_for(n, GROWS, 1u << 30), GROWS, 0, s>>>((int)n, g->rp, g->col, labx, L, lay.chunk, PM, start, loc, CB);
+      k_gather<true, LT><<<grid_for(n, GROWS, 1u << 30), GROWS, 0, s>>>((int)n, g->rp, g->col, labx, L, lay.chunk, PM, start, loc, CB,
+                                                                      g->w, CW);
     else
-      k_gather<false, LT><<<grid_for(n, GROWS, 1u << 30), GROWS, 0, s>>>((int)n, g->rp, g->col, labx, L, lay.chunk, PM, start, loc, CB);
+      k_gather<false, LT><<<grid_for(n, GROWS, 1u << 30), GROWS, 0, s>>>((int)n, g->rp, g->col, labx, L, lay.chunk, PM, start, loc,
+                                                                       CB, g->w, CW);
   }
   ScoreVis vis;
   vis.N = N;
@@ -414,13 +430,34 @@ void score_launch(cq_context* ctx, const cq_graph* g, const int32_t* labels, int
   vis.ctl = ctl;
   const u32 lds_words = L <= DIRECT_MAX ? std::max<u32>(((u32)L + 3u) & ~3u, 128u) : HASH_WORDS;
   const size_t lds = (size_t)lds_words * 4;
+  PerComm pc;
+  std::memset(&pc, 0, sizeof(pc));
+  if (per_comm) std::memcpy(&pc, per_comm, sizeof(pc));
+  if (CW) {
+    // weighted graph: direct tables only (L <= HASH_WORDS was checked by the caller)
+    WeightedOut wo;
+    wo.SW = at<u64>(ws, lay.SW);
+    wo.IW = at<u64>(ws, lay.IW);
+    wo.PENW = at<u64>(ws, lay.PENW);
+    wo.twoW = 2.0 * g->total_w;
+    {
+      StageMark mk(ctx, ST_GROUPS, timed);
+      int nb = 0;
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_groups_w<LT>, GBLOCK, lds) != hipSuccess || nb < 1) nb = 1;
+      k_groups_w<LT><<<(unsigned)(ctx->num_cus * nb), GBLOCK, lds, s>>>(CB, CW, start, D, order, ctl, (u32)L, vis, wo);
+    }
+    WScorePart* wparts = reinterpret_cast<WScorePart*>(parts);
+    {
+      StageMark mk(ctx, ST_FINAL, timed);
+      k_score_final1_w<<<lay.G, FBLOCK, 0, s>>>(L, N, D, I, NP, wo.SW, wo.IW, wo.PENW, g->total_w, pc, wparts);
+      k_score_final2_w<<<1, 64, 0, s>>>(lay.G, wparts, n, nnz, g->total_w, vis.ecap, ctl, d_out);
+    }
+    return;
+  }
   {
     StageMark mk(ctx, ST_GROUPS, timed);
     k_groups<ScoreVis, LT><<<group_grid<ScoreVis, LT>(ctx, lds), GBLOCK, lds, s>>>(CB, start, D, order, ctl, (u32)L, lds_words, vis);
   }
-  PerComm pc;
-  std::memset(&pc, 0, sizeof(pc));
-  if (per_comm) std::memcpy(&pc, per_comm, sizeof(pc));
   {
     StageMark mk(ctx, ST_FINAL, timed);
     k_score_final1<<<lay.G, FBLOCK, 0, s>>>(L, N, D, I, NP, PEN, (double)nnz, pc, parts);
@@ -435,9 +472,11 @@ cq_status score_enqueue(cq_context* ctx, const cq_graph* g, const int32_t* label
   if (!g || !labels || !d_out) return fail(ctx, CQ_E_INVALID_ARG, "null graph, labels or output");
   if (L < 1) return fail(ctx, CQ_E_INVALID_ARG, "num_labels must be >= 1");
   if (g->nnz == 0) return fail(ctx, CQ_E_NO_EDGES, "graph has no edges");
+  if (g->w && (int64_t)L > (int64_t)HASH_WORDS)
+    return fail(ctx, CQ_E_INVALID_ARG, "weighted scoring supports up to %u label ids", HASH_WORDS);
   if (pairs && pairs->capacity > 0 && (!pairs->ci || !pairs->cj || !pairs->count))
     return fail(ctx, CQ_E_INVALID_ARG, "pair table with null arrays");
-  const ScoreLayout lay = score_layout(g->n, g->nnz, L);
+  const ScoreLayout lay = score_layout(g->n, g->nnz, L, g->w != nullptr);
   if (!ws || ws_bytes < lay.total)
     return fail(ctx, CQ_E_WORKSPACE, "workspace %zu bytes, need %zu", ws_bytes, lay.total);
   if (lay.small)
@@ -603,6 +642,7 @@ cq_status build_column_blocks(cq_context* ctx, cq_graph* g) {
   alloc((void**)&g->rpb, 4 * ((size_t)len + 1));
   alloc((void**)&g->colb, 4 * (size_t)nnz);
   alloc((void**)&g->rowb, 4 * (size_t)nnz);
+  if (g->owned_w) alloc((void**)&g->wb, 4 * (size_t)nnz);
   alloc((void**)&cnt, 4 * (size_t)len);
   alloc((void**)&tiles, 4 * ((size_t)((len + SCAN_TILE - 1) / SCAN_TILE) + 1));
   cq_status st = CQ_OK;
@@ -613,7 +653,7 @@ cq_status build_column_blocks(cq_context* ctx, cq_graph* g) {
     const unsigned gw = grid_for((int64_t)n * 64, 256, 65535);
     k_blk_count<<<gw, 256, 0, s>>>(n, g->owned_rp, g->owned_col, span, cnt);
     scan_u32(cnt, g->rpb, len, tiles, s);
-    k_blk_place<<<gw, 256, 0, s>>>(n, g->owned_rp, g->owned_col, span, g->rpb, g->colb, g->rowb);
+    k_blk_place<<<gw, 256, 0, s>>>(n, g->owned_rp, g->owned_col, span, g->rpb, g->colb, g->rowb, g->owned_w, g->wb);
     e = hipGetLastError();
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     // far-entry ranges of every block: rows [0, s0) and [s1, n), s0..s1 being its span
@@ -634,9 +674,11 @@ cq_status build_column_blocks(cq_context* ctx, cq_graph* g) {
     if (g->rpb) (void)hipFree(g->rpb);
     if (g->colb) (void)hipFree(g->colb);
     if (g->rowb) (void)hipFree(g->rowb);
+    if (g->wb) (void)hipFree(g->wb);
     g->rpb = nullptr;
     g->colb = nullptr;
     g->rowb = nullptr;
+    g->wb = nullptr;
   }
   return st;
 }
@@ -704,6 +746,7 @@ cq_status build_locality_order(cq_context* ctx, cq_graph* g, const int32_t* rp, 
   alloc((void**)&g->owned_rp, 4 * ((size_t)n + 1));
   alloc((void**)&g->owned_col, 4 * (size_t)std::max<int64_t>(nnz, 1));
   alloc((void**)&g->owned_perm, 4 * (size_t)n);
+  if (g->w) alloc((void**)&g->owned_w, 4 * (size_t)std::max<int64_t>(nnz, 1));
   alloc((void**)&lpA, 4 * (size_t)n);
   alloc((void**)&lpB, 4 * (size_t)n);
   alloc((void**)&newid, 4 * (size_t)n);
@@ -728,7 +771,7 @@ cq_status build_locality_order(cq_context* ctx, cq_graph* g, const int32_t* rp, 
     k_place<<<gn, 256, 0, s>>>(n, lpA, start, cnt, newid, g->owned_perm);
     k_new_degree<<<gn, 256, 0, s>>>(n, rp, g->owned_perm, cnt);
     scan_u32(cnt, reinterpret_cast<u32*>(g->owned_rp), n, tiles, s);
-    k_relabel_rows<<<gw, 256, 0, s>>>(n, rp, col, g->owned_perm, newid, g->owned_rp, g->owned_col);
+    k_relabel_rows<<<gw, 256, 0, s>>>(n, rp, col, g->owned_perm, newid, g->owned_rp, g->owned_col, g->w, g->owned_w);
     if (blocks) st = build_column_blocks(ctx, g);
     if (st == CQ_OK && (g->rpb || n >= BLOCK_MIN_N)) st = build_perm_plan(ctx, g, newid, rp);
     e = hipGetLastError();
@@ -741,10 +784,13 @@ cq_status build_locality_order(cq_context* ctx, cq_graph* g, const int32_t* rp, 
     g->rp = g->owned_rp;
     g->col = g->owned_col;
     g->perm = g->owned_perm;
+    if (g->owned_w) g->w = g->owned_w;
     g->reordered = CQ_GRAPH_REORDER | (g->rpb ? 0u : CQ_GRAPH_NO_BLOCKS);
     g->owned_bytes = (int64_t)(4 * ((size_t)n + 1) + 4 * (size_t)nnz + 4 * (size_t)n);
     if (g->rpb) g->owned_bytes += (int64_t)(4 * ((size_t)COL_BLOCKS * ((size_t)n + 1) + 1) + 8 * (size_t)nnz);
     if (g->pos1) g->owned_bytes += (int64_t)(12 * (size_t)n + 4 * ((size_t)g->perm_buckets + 1));
+    if (g->owned_w) g->owned_bytes += (int64_t)(4 * (size_t)nnz);
+    if (g->wb) g->owned_bytes += (int64_t)(4 * (size_t)nnz);
   }
   return st;
 }
@@ -1307,6 +1353,8 @@ cq_status cq_context_create(int device, void* hip_stream, cq_context** out) {
   set_big_lds(reinterpret_cast<const void*>(k_node_priv<false, uint32_t>), PRIV_MAX * 4);
   set_big_lds(reinterpret_cast<const void*>(k_hist_priv), PRIV_MAX * 4);
   set_big_lds(reinterpret_cast<const void*>(k_groups<ScoreVis, uint16_t>), gl);
+  set_big_lds(reinterpret_cast<const void*>(k_groups_w<uint16_t>), gl);
+  set_big_lds(reinterpret_cast<const void*>(k_groups_w<uint32_t>), gl);
   set_big_lds(reinterpret_cast<const void*>(k_groups<ScoreVis, uint32_t>), gl);
   set_big_lds(reinterpret_cast<const void*>(k_groups<CmpVis, uint16_t>), gl);
   set_big_lds(reinterpret_cast<const void*>(k_groups<CmpVis, uint32_t>), gl);
@@ -1355,8 +1403,10 @@ const char* cq_stage_name(int32_t s) { return (s >= 0 && s < ST_COUNT) ? kStageN
 
 const char* cq_context_last_error(const cq_context* ctx) { return ctx ? ctx->err : "null context"; }
 
-cq_status cq_graph_load(cq_context* ctx, int32_t n, int64_t nnz, const int32_t* d_row_ptr, const int32_t* d_col_idx,
-                        uint32_t flags, cq_graph** out) {
+namespace {
+// Shared by the unweighted and weighted loads; d_weights may be null.
+cq_status graph_load(cq_context* ctx, int32_t n, int64_t nnz, const int32_t* d_row_ptr, const int32_t* d_col_idx,
+                     const float* d_weights, uint32_t flags, cq_graph** out) {
   if (!ctx) return CQ_E_INVALID_ARG;
   ctx->err[0] = 0;
   if (!out || !d_row_ptr || (nnz > 0 && !d_col_idx)) return fail(ctx, CQ_E_INVALID_ARG, "null pointer");
@@ -1388,13 +1438,39 @@ cq_status cq_graph_load(cq_context* ctx, int32_t n, int64_t nnz, const int32_t* 
   uint32_t validated = 0;
   if (flags & CQ_VALIDATE_GRAPH) {
     fill(ctx->dscratch, 1, 0, s);
-    k_check_symmetric<<<grid_for(n, 4, 8192), 256, 0, s>>>(n, d_row_ptr, d_col_idx, ctx->dscratch);
+    k_check_symmetric<<<grid_for(n, 4, 8192), 256, 0, s>>>(n, d_row_ptr, d_col_idx, d_weights, ctx->dscratch);
     u32 f = 0;
     e = hipMemcpyAsync(&f, ctx->dscratch, 4, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return fail(ctx, CQ_E_DEVICE, "symmetry check: %s", hipGetErrorString(e));
-    if (f) return fail(ctx, CQ_E_GRAPH_FORMAT, "graph is not a simple symmetric CSR with sorted rows");
+    if (f) return fail(ctx, CQ_E_GRAPH_FORMAT,
+                       d_weights ? "graph is not a simple symmetric CSR with sorted rows and equal weights on both "
+                                   "entries of every edge"
+                                 : "graph is not a simple symmetric CSR with sorted rows");
     validated = CQ_VALIDATE_GRAPH;
+  }
+  double total_w = 0.0;
+  if (d_weights && nnz > 0) {
+    // every weight in range, and W = (sum of all entries) / 2 summed exactly
+    const unsigned gb = grid_for(nnz, 256, 1024);
+    u64* parts = nullptr;
+    e = hipMalloc((void**)&parts, 16 * (size_t)gb);
+    if (e != hipSuccess) return fail(ctx, CQ_E_DEVICE, "allocating the weight sums: %s", hipGetErrorString(e));
+    std::vector<u64> hp(2 * (size_t)gb);
+    fill(ctx->dscratch, 1, 0, s);
+    k_check_weights<<<gb, 256, 0, s>>>(nnz, d_weights, ctx->dscratch, parts);
+    u32 f = 0;
+    e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(&f, ctx->dscratch, 4, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(hp.data(), parts, 16 * (size_t)gb, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFree(parts);
+    if (e != hipSuccess) return fail(ctx, CQ_E_DEVICE, "weight check: %s", hipGetErrorString(e));
+    if (f) return fail(ctx, CQ_E_GRAPH_FORMAT, "edge weights must be finite and in [2^-40, 2^40]");
+    u128 t = 0;
+    for (unsigned b = 0; b < gb; ++b) t += ((u128)hp[2 * b + 1] << 64) | hp[2 * b];
+    t >>= 1;  // every edge is stored twice with the same weight (odd halves only if unvalidated)
+    total_w = (double)(u64)(t >> 64) + std::ldexp((double)(u64)t, -64);
   }
   cq_graph* g = new (std::nothrow) cq_graph();
   if (!g) return fail(ctx, CQ_E_DEVICE, "out of host memory");
@@ -1405,6 +1481,8 @@ cq_status cq_graph_load(cq_context* ctx, int32_t n, int64_t nnz, const int32_t* 
   g->col = d_col_idx;
   g->max_degree = res[1];
   g->validated = validated;
+  g->w = d_weights;
+  g->total_w = total_w;
   if ((flags & CQ_GRAPH_REORDER) && nnz > 0) {
     const bool blocks = (flags & CQ_GRAPH_BLOCKS) ? n <= BLOCK_MAX_N
                         : !(flags & CQ_GRAPH_NO_BLOCKS) && n >= BLOCK_MIN_N && n <= BLOCK_MAX_N;
@@ -1417,6 +1495,21 @@ cq_status cq_graph_load(cq_context* ctx, int32_t n, int64_t nnz, const int32_t* 
   *out = g;
   return CQ_OK;
 }
+}  // namespace
+
+cq_status cq_graph_load(cq_context* ctx, int32_t n, int64_t nnz, const int32_t* d_row_ptr, const int32_t* d_col_idx,
+                        uint32_t flags, cq_graph** out) {
+  return graph_load(ctx, n, nnz, d_row_ptr, d_col_idx, nullptr, flags, out);
+}
+
+cq_status cq_graph_load_weighted(cq_context* ctx, int32_t n, int64_t nnz, const int32_t* d_row_ptr,
+                                 const int32_t* d_col_idx, const float* d_weights, uint32_t flags, cq_graph** out) {
+  if (ctx && nnz > 0 && !d_weights) {
+    ctx->err[0] = 0;
+    return fail(ctx, CQ_E_INVALID_ARG, "null weights");
+  }
+  return graph_load(ctx, n, nnz, d_row_ptr, d_col_idx, nnz > 0 ? d_weights : nullptr, flags, out);
+}
 
 cq_status cq_graph_get_stats(const cq_graph* g, cq_graph_stats* out) {
   if (!g || !out) return CQ_E_INVALID_ARG;
@@ -1426,6 +1519,9 @@ cq_status cq_graph_get_stats(const cq_graph* g, cq_graph_stats* out) {
   out->max_degree = g->max_degree;
   out->validated = g->validated;
   out->reordered = g->reordered;
+  out->weighted = g->w ? 1u : 0u;
+  out->pad = 0;
+  out->total_weight = g->w ? g->total_w : (double)(g->nnz / 2);
   out->owned_bytes = g->owned_bytes;
   return CQ_OK;
 }
@@ -1434,7 +1530,7 @@ void cq_graph_release(cq_graph* g) { delete g; }
 
 size_t cq_score_workspace_size(const cq_graph* g, int32_t num_labels) {
   if (!g || num_labels < 1) return 0;
-  return score_layout(g->n, g->nnz, num_labels).total;
+  return score_layout(g->n, g->nnz, num_labels, g->w != nullptr).total;
 }
 
 size_t cq_compare_workspace_size(int32_t n, int32_t num_labels_a, int32_t num_labels_b) {
@@ -1455,7 +1551,7 @@ cq_status cq_score_partition(cq_context* ctx, const cq_graph* g, const int32_t* 
   if (!ctx) return CQ_E_INVALID_ARG;
   if (!h_out) return fail(ctx, CQ_E_INVALID_ARG, "null result pointer");
   if (!g) return fail(ctx, CQ_E_INVALID_ARG, "null graph");
-  const ScoreLayout lay = score_layout(g->n, g->nnz, std::max(num_labels, 1));
+  const ScoreLayout lay = score_layout(g->n, g->nnz, std::max(num_labels, 1), g->w != nullptr);
   ScoreResultDev* d_res = (d_ws && ws_bytes >= lay.total) ? at<ScoreResultDev>(d_ws, lay.res) : nullptr;
   cq_status st = score_enqueue(ctx, g, d_labels, num_labels, d_ws, ws_bytes, d_res ? d_res : reinterpret_cast<ScoreResultDev*>(1),
                                per_comm, pairs, true);
@@ -1499,6 +1595,7 @@ cq_status cq_batch_plan_create(cq_context* ctx, const cq_batch_task* tasks, int3
   for (int i = 0; i < num_tasks; ++i) {
     const cq_batch_task& t = tasks[i];
     if (!t.graph || !t.d_labels) return fail(ctx, CQ_E_INVALID_ARG, "task %d: null graph or labels", i);
+    if (t.graph->w) return fail(ctx, CQ_E_INVALID_ARG, "task %d: weighted graphs are scored one call at a time", i);
     if (t.num_labels < 1 || t.num_labels > BATCH_MAX_L)
       return fail(ctx, CQ_E_INVALID_ARG, "task %d: num_labels must be in [1, %lld] for batching", i, (long long)BATCH_MAX_L);
     if (t.graph->nnz == 0) return fail(ctx, CQ_E_NO_EDGES, "task %d: graph has no edges", i);
@@ -1713,8 +1810,8 @@ cq_status cq_server_submit_score(cq_server* srv, const cq_graph* g, const int32_
   r->n = g->n;
   r->L = num_labels;
   r->ha = h_labels;
-  r->ws_bytes = score_layout(g->n, g->nnz, num_labels).total;
-  r->small = num_labels <= BATCH_MAX_L && g->nnz <= srv->cfg.small_nnz;
+  r->ws_bytes = score_layout(g->n, g->nnz, num_labels, g->w != nullptr).total;
+  r->small = num_labels <= BATCH_MAX_L && g->nnz <= srv->cfg.small_nnz && !g->w;  // groups run the unweighted batch kernels
   return srv_submit(srv, r, ticket);
 }
 
