@@ -174,6 +174,16 @@ def main() -> int:
     torch.cuda.synchronize()
     cmp_ms = (time.perf_counter() - tc) * 1e3 / csteps
 
+    # the same graph with seeded symmetric edge weights (weighted Q/Qds/measures), for context
+    from cqgen import edge_weights
+    wts = edge_weights(g.row_ptr, g.col_idx, args.seed)
+    wgraph = cq.Graph(ctx, g.row_ptr, g.col_idx, reorder=(args.order == "locality"), weights=wts)
+    wsteps = max(3, args.steps // 4)
+    wres, wms, _ = timed_run(wgraph, wsteps, 2)
+    wgraph.close()
+    del wts
+    log(f"weighted: {wms:.3f} ms/step")
+
     cpu = None
     check = None
     if not args.no_cpu_baseline:
@@ -205,6 +215,8 @@ def main() -> int:
         "aux": {"graph_order": args.order, "graph_load_ms": round(load_ms, 2), "generate_s": round(gen_s, 2),
                 f"ms_per_step_{other}_order": round(ms_ref, 4),
                 "compare_ms": round(cmp_ms, 4), "compare_Gnodes_per_s": round(n / (cmp_ms * 1e-3) / 1e9, 3),
+                "weighted_ms_per_step": round(wms, 4), "weighted_GEdges_per_s": round(nnz / (wms * 1e-3) / 1e9, 2),
+                "weighted_Q": wres["Q"], "weighted_Qds": wres["Qds"],
                 "oracle_check": check,
                 "Q": r["Q"], "Qds": r["Qds"]},
     }
