@@ -145,8 +145,12 @@ def main() -> int:
     stage_avg = {k: v[0] / v[1] for k, v in stages.items()}
     dom = max(stage_avg, key=stage_avg.get)
     blocked = graph.stats["reordered"] == cq.CQ_GRAPH_REORDER  # renumbered and stored in column blocks
-    kernel_of = {"edge_gather": "k_gather_blocked" if blocked else "k_gather", "group_count": "k_groups<ScoreVis>",
-                 "node_pass": "k_node_perm" if blocked else "k_node_priv",
+    # kernel names as the profiler prints them (namespace dropped): the unweighted instantiations
+    lt = "unsigned short" if L <= 65535 else "unsigned int"
+    priv = "true" if L <= 16384 else "false"
+    kernel_of = {"edge_gather": f"k_gather_blocked<{lt}, false>" if blocked else f"k_gather<{priv}, {lt}, false>",
+                 "group_count": f"k_groups<ScoreVis, {lt}>",
+                 "node_pass": f"k_node_perm<{lt}>" if blocked else f"k_node_priv<true, {lt}, false>",
                  "final_reduce": "k_score_final1", "column_scan": "k_colscan", "scan_order": "k_scan_order"}
     abytes = algorithmic_bytes(n, nnz)
     achieved = abytes / (stage_avg[dom] * 1e-3) / 1e9
@@ -179,10 +183,10 @@ def main() -> int:
     wts = edge_weights(g.row_ptr, g.col_idx, args.seed)
     wgraph = cq.Graph(ctx, g.row_ptr, g.col_idx, reorder=(args.order == "locality"), weights=wts)
     wsteps = max(3, args.steps // 4)
-    wres, wms, _ = timed_run(wgraph, wsteps, 2)
+    wres, wms, wstages = timed_run(wgraph, wsteps, 2)
     wgraph.close()
     del wts
-    log(f"weighted: {wms:.3f} ms/step")
+    log(f"weighted: {wms:.3f} ms/step; stages " + ", ".join(f"{k}={v[0] / v[1]:.3f}ms" for k, v in wstages.items()))
 
     cpu = None
     check = None

@@ -140,7 +140,7 @@ cq_status cq_graph_load(cq_context* ctx, int32_t n, int64_t nnz, const int32_t* 
 /*
  * Register an edge-weighted graph: as cq_graph_load, plus
  *   d_weights  DEVICE float[nnz], the weight of every stored entry, BORROWED like the
- *              CSR arrays; finite, in [2^-40, 2^40], and equal for the two entries of
+ *              CSR arrays; finite, in [2^-32, 2^32], and equal for the two entries of
  *              an undirected edge (checked with CQ_VALIDATE_GRAPH).
  * Scoring a weighted graph gives Eqs. 8-9 and the measures of Section II-B3 with
  * weight sums in place of edge counts, while the densities d_c and d_{ci,cj} keep the

@@ -54,19 +54,21 @@ __device__ __forceinline__ double unfix96(u128 v) {
 }
 
 // ---- exact edge-weight sums --------------------------------------------------
-// A float32 weight w in [2^-40, 2^40] times 2^64 is an integer below 2^105: its 24-bit
-// significand shifted by (biased exponent - 86).  Sums of such integers are exact and
-// independent of order (2^31 entries stay below 2^128).
-constexpr float WEIGHT_MIN = 9.094947017729282e-13f;  // 2^-40
-constexpr float WEIGHT_MAX = 1099511627776.0f;        // 2^40
-__device__ __forceinline__ u128 fix64_f32(float w) {
+// A float32 weight w in [2^-32, 2^32] is its 24-bit significand times 2^(e - 150), e the
+// biased exponent (95 <= e <= 159), so w * 2^55 is the integer significand << (e - 95),
+// below 2^88.  Sums of such integers are exact and independent of order, and 2^31 of
+// them stay below 2^119.
+constexpr float WEIGHT_MIN = 2.3283064365386963e-10f;  // 2^-32
+constexpr float WEIGHT_MAX = 4294967296.0f;            // 2^32
+constexpr u32 WEIGHT_EXP0 = 95;                        // biased exponent of 2^-32
+__device__ __forceinline__ u128 fixw_f32(float w) {
   const u32 b = __float_as_uint(w);
   const u32 e = (b >> 23) & 0xFFu;
-  return (u128)((b & 0x7FFFFFu) | 0x800000u) << (e - 86u);
+  return (u128)((b & 0x7FFFFFu) | 0x800000u) << (e - WEIGHT_EXP0);
 }
-// value / 2^64 of an exact weight sum
-__device__ __forceinline__ double unfix64(u128 v) {
-  return (double)(u64)(v >> 64) + (double)(u64)v * 5.421010862427522e-20;  // 2^-64
+// value / 2^55 of an exact weight sum
+__device__ __forceinline__ double unfixw(u128 v) {
+  return (double)(u64)(v >> 64) * 512.0 + (double)(u64)v * 2.7755575615628914e-17;  // 2^9, 2^-55
 }
 
 // ---- wave / block reductions (wave64) ---------------------------------------

@@ -71,7 +71,7 @@ __global__ void k_check_symmetric(int n, const int32_t* __restrict__ rp, const i
 }
 
 // Edge weights: finite and in [WEIGHT_MIN, WEIGHT_MAX]; per-block exact sums of
-// w * 2^64 (two words per block) for the total weight.
+// w * 2^55 (two words per block) for the total weight.
 __global__ __launch_bounds__(256) void k_check_weights(long long nnz, const float* __restrict__ w, u32* __restrict__ flags,
                                                        u64* __restrict__ parts) {
   __shared__ u64 s_lo[4], s_hi[4];
@@ -81,7 +81,7 @@ __global__ __launch_bounds__(256) void k_check_weights(long long nnz, const floa
   for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < (size_t)nnz; e += stride) {
     const float x = w[e];
     if (!(x >= WEIGHT_MIN && x <= WEIGHT_MAX)) bad = 1;  // also catches NaN
-    else sum += fix64_f32(x);
+    else sum += fixw_f32(x);
   }
   sum = wave_sum_u128(sum);
   const int wv = threadIdx.x >> 6;
@@ -792,7 +792,7 @@ __global__ __launch_bounds__(1024) void k_scan_order(int L, const u32* __restric
 // are walked by all threads in order (coalesced); the owning row of an entry is found
 // by binary search over the 256 row starts staged in LDS.
 constexpr int GROWS = 256;
-template <bool PRIV, class LT>
+template <bool PRIV, class LT, bool WT>
 __global__ __launch_bounds__(GROWS) void k_gather(int n, const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
                                                   const LT* __restrict__ labx, int L, int chunk, const u32* __restrict__ PM,
                                                   const u32* __restrict__ start, const u32* __restrict__ loc,
@@ -826,7 +826,7 @@ __global__ __launch_bounds__(GROWS) void k_gather(int n, const int32_t* __restri
     const u32 base = s_base[lo];
     if (base == SENT) continue;
     CB[base + (u32)(e - s_rs[lo])] = labx[col[e]];
-    if (CW) CW[base + (u32)(e - s_rs[lo])] = w[e];
+    if (WT) CW[base + (u32)(e - s_rs[lo])] = w[e];
   }
 }
 
@@ -901,7 +901,8 @@ __device__ __forceinline__ void claim_runs(u32 nruns, const u32* s_first, u32* s
 }
 
 // Own-span tile t of block y: rows [s0 + t*BT_ROWS, ...) of span y, their block-y entries.
-template <class LT>
+// WT: the graph is weighted, and each entry's weight goes to CW beside its label.
+template <class LT, bool WT>
 __device__ void gather_own_tile(u32 y, u32 t, int n, int span, const u32* __restrict__ RPB,
                                 const int32_t* __restrict__ colb, const LT* __restrict__ labx,
                                 const u32* __restrict__ start, const u32* __restrict__ D, u32* __restrict__ cursor,
@@ -933,13 +934,15 @@ __device__ void gather_own_tile(u32 y, u32 t, int n, int span, const u32* __rest
       ra[j] = rpb[r0 + r];
       rl[j] = (u32)labx[r0 + r];
     }
-    const uint4* src = reinterpret_cast<const uint4*>(labx + w0);
+    // a native vector type: an array of HIP's uint4 class is kept in scratch memory
+    typedef u32 v4u __attribute__((ext_vector_type(4)));
+    const v4u* src = reinterpret_cast<const v4u*>(labx + w0);
+    v4u* s_winv = reinterpret_cast<v4u*>(s_win);
     const int nv = (int)((w1 - w0) / PER);
-    uint4 wv[WIT];
+    v4u wv[WIT];
+    if (nv > 0) {  // uniform; every load unconditional (clamped)
 #pragma unroll
-    for (int j = 0; j < WIT; ++j) {
-      const int i = tid + j * BT_THREADS;
-      if (i < nv) wv[j] = src[i];
+      for (int j = 0; j < WIT; ++j) wv[j] = src[min(tid + j * BT_THREADS, nv - 1)];
     }
 #pragma unroll
     for (int j = 0; j < BT_RPT; ++j) {
@@ -952,7 +955,7 @@ __device__ void gather_own_tile(u32 y, u32 t, int n, int span, const u32* __rest
 #pragma unroll
     for (int j = 0; j < WIT; ++j) {
       const int i = tid + j * BT_THREADS;
-      if (i < nv) s_win[i] = wv[j];
+      if (i < nv) s_winv[i] = wv[j];
     }
   }
   __syncthreads();
@@ -986,9 +989,14 @@ __device__ void gather_own_tile(u32 y, u32 t, int n, int span, const u32* __rest
   const u32 ne = e1 - e0;
   for (u32 eb = tid; eb < ne; eb += BT_THREADS * BT_UNROLL) {
     int v[BT_UNROLL];
+    float wt[BT_UNROLL];
     u32 pos[BT_UNROLL];
 #pragma unroll
     for (int u = 0; u < BT_UNROLL; ++u) v[u] = cb[min(eb + (u32)(u * BT_THREADS), ne - 1u)];  // in bounds; masked below
+    if (WT) {  // weights are loaded with the neighbour ids, so their latency overlaps the run search
+#pragma unroll
+      for (int u = 0; u < BT_UNROLL; ++u) wt[u] = wb[e0 + min(eb + (u32)(u * BT_THREADS), ne - 1u)];
+    }
 #pragma unroll
     for (int u = 0; u < BT_UNROLL; ++u) {
       const u32 e = eb + (u32)(u * BT_THREADS);
@@ -1009,16 +1017,16 @@ __device__ void gather_own_tile(u32 y, u32 t, int n, int span, const u32* __rest
 #pragma unroll
     for (int u = 0; u < BT_UNROLL; ++u)
       if (pos[u] != SENT) CB[pos[u]] = x[u];
-    if (CW) {
+    if (WT) {
 #pragma unroll
       for (int u = 0; u < BT_UNROLL; ++u)
-        if (pos[u] != SENT) CW[pos[u]] = wb[e0 + eb + (u32)(u * BT_THREADS)];
+        if (pos[u] != SENT) CW[pos[u]] = wt[u];
     }
   }
 }
 
 // Far tile t of block y: FT_ENT consecutive entries of the block's far ranges.
-template <class LT>
+template <class LT, bool WT>
 __device__ void gather_far_tile(u32 y, u32 t, const FarTable& ft, const int32_t* __restrict__ colb,
                                 const int32_t* __restrict__ rowb, const LT* __restrict__ labx,
                                 const u32* __restrict__ start, const u32* __restrict__ D, u32* __restrict__ cursor,
@@ -1042,11 +1050,13 @@ __device__ void gather_far_tile(u32 y, u32 t, const FarTable& ft, const int32_t*
   const u32 i0 = (u32)tid * FT_EPT;  // this thread's entries i0 .. i0+FT_EPT-1 (tile-relative)
   LT x[FT_EPT];
   u32 lab[FT_EPT];
+  float wt[FT_EPT];
 #pragma unroll
   for (int j = 0; j < FT_EPT; ++j) {
     const u32 e = e0 + min(i0 + (u32)j, ne - 1u);  // in bounds; entries past ne are masked below
     x[j] = labx[colb[e]];  // the neighbour labels are loaded now and used after the runs are placed
     lab[j] = (u32)labx[rowb[e]];
+    if (WT) wt[j] = wb[e];
   }
 #pragma unroll
   for (int j = 0; j < FT_EPT; ++j)
@@ -1087,7 +1097,7 @@ __device__ void gather_far_tile(u32 y, u32 t, const FarTable& ft, const int32_t*
     const u32 base = s_rb[run];
     if (base != SENT) {
       CB[base + (i - s_rf[run])] = x[j];
-      if (CW) CW[base + (i - s_rf[run])] = wb[e0 + i];
+      if (WT) CW[base + (i - s_rf[run])] = wt[j];
     }
   }
 }
@@ -1095,7 +1105,7 @@ __device__ void gather_far_tile(u32 y, u32 t, const FarTable& ft, const int32_t*
 // One launch for both kinds of tile.  Groups of 8 consecutive workgroups (one per XCD,
 // so workgroup i serves block i % 8): the own-span groups first (they carry most
 // entries), then the far groups.
-template <class LT>
+template <class LT, bool WT>
 __global__ __launch_bounds__(BT_THREADS) void k_gather_blocked(int n, int span, const u32* __restrict__ RPB,
                                                                const int32_t* __restrict__ colb,
                                                                const int32_t* __restrict__ rowb, FarTable ft,
@@ -1109,9 +1119,9 @@ __global__ __launch_bounds__(BT_THREADS) void k_gather_blocked(int n, int span, 
   const u32 y = blockIdx.x % 8u, gi = blockIdx.x / 8u;
   if (y >= (u32)COL_BLOCKS || gi >= own_groups + far_groups) return;
   if (gi < own_groups)
-    gather_own_tile<LT>(y, gi, n, span, RPB, colb, labx, start, D, cursor, ctl, CB, wb, CW, lds, s_w);
+    gather_own_tile<LT, WT>(y, gi, n, span, RPB, colb, labx, start, D, cursor, ctl, CB, wb, CW, lds, s_w);
   else
-    gather_far_tile<LT>(y, gi - own_groups, ft, colb, rowb, labx, start, D, cursor, ctl, CB, wb, CW, lds, s_w);
+    gather_far_tile<LT, WT>(y, gi - own_groups, ft, colb, rowb, labx, start, D, cursor, ctl, CB, wb, CW, lds, s_w);
 }
 
 // Comparison: the segment of ground-truth community a_u receives b_u.
@@ -1499,17 +1509,89 @@ struct ScoreVis {
 // ---------------------------------------------------------------------------
 // Weighted group pass (edge-weighted graphs; labels fit a direct LDS table).  Per
 // community g, besides everything ScoreVis computes from the counts:
-//   SW[g] = sum of the weights in g's segment = strength sum s(g)       (x 2^64, exact)
-//   IW[g] = sum of the weights of entries labelled g = 2 w_in(g)         (x 2^64, exact)
-//   PENW[g] = sum_{j != g} w(g,j) d_{g,j} / (2W), d_{g,j} = |E_gj| / (|g||j|)   (fix96)
-// The penalty is summed entry by entry in a second pass over the segment, once the
-// table holds every count |E_gj|: entry (j, w) adds w |E_gj| / (2W |g| |j|).
+//   SW[g] = sum of the weights in g's segment = strength sum s(g)       (x 2^55, exact)
+//   IW[g] = sum of the weights of entries labelled g = 2 w_in(g)         (x 2^55, exact)
+//   PENW[g] = sum_{j != g} w(g,j) d_{g,j} / (2W), d_{g,j} = |E_gj| / (|g||j|)   (x 2^96)
+// The first pass counts labels exactly as the unweighted pass does.  The second pass,
+// once the table holds every count |E_gj|, reads labels and weights together: entry
+// (j, w) adds w to the weight sums and, for j != g, w |E_gj| / (2W |g| |j|) to the
+// penalty, truncated to a multiple of 2^-96 (term by term, so the sum is exact).
 struct WeightedOut {
   u64* SW;
   u64* IW;
   u64* PENW;
+  const double* invN;  // 1/|j| per label (0 for empty labels)
   double twoW;
 };
+
+// Exact sum of float32 weights in [WEIGHT_MIN, WEIGHT_MAX], times 2^55 (the value of
+// fixw_f32), in two 64-bit words.  split() gives a weight's fixed-point value as
+// (hi, lo): its 24-bit significand shifted left by s = biased exponent - WEIGHT_EXP0
+// (0 <= s <= 64).
+struct WeightSum {
+  u64 lo = 0, hi = 0;
+  static __device__ __forceinline__ void split(float w, u64& vlo, u64& vhi) {
+    const u32 b = __float_as_uint(w);
+    const u32 sh = ((b >> 23) & 0xFFu) - WEIGHT_EXP0;
+    const u64 sig = (u64)((b & 0x7FFFFFu) | 0x800000u);
+    vlo = sh < 64u ? sig << sh : 0ull;
+    vhi = sh > 40u ? sig >> (64u - sh) : 0ull;
+  }
+  __device__ __forceinline__ void add(u64 vlo, u64 vhi) {
+    lo += vlo;
+    hi += vhi + (lo < vlo ? 1ull : 0ull);
+  }
+  __device__ __forceinline__ u128 value() const { return ((u128)hi << 64) | lo; }
+};
+
+// Exact sum of terms t in [0, 1), each truncated to a multiple of 2^-96 (the value fix96
+// gives), kept as three 32-bit limbs of the fraction summed in 64-bit words.
+struct Frac96Sum {
+  u64 a = 0, b = 0, c = 0;
+  __device__ __forceinline__ void add(double t) {
+    const double x = t * 4294967296.0;  // 2^32
+    const u32 l0 = (u32)x;               // truncation
+    const double y = (x - (double)l0) * 4294967296.0;
+    const u32 l1 = (u32)y;
+    const double z = (y - (double)l1) * 4294967296.0;
+    const u32 l2 = (u32)z;
+    a += l0;
+    b += l1;
+    c += l2;
+  }
+  __device__ __forceinline__ u128 value() const { return ((u128)a << 64) + ((u128)b << 32) + (u128)c; }
+};
+
+// Calls f(label, weight) for every entry of a segment of labels and weights (both arrays
+// 16-byte aligned at index 0): 4 entries per load once the index is a multiple of 4.
+// One load in flight per thread: the weighted pass is register-bound, and more waves
+// hide the latency better than a second load would.
+template <class LT, class F>
+__device__ __forceinline__ void for_each_weighted(const LT* __restrict__ lab, const float* __restrict__ wt, const u32 base,
+                                                  const u32 len, F&& f) {
+  u32 head = (4u - (base & 3u)) & 3u;
+  if (head > len) head = len;
+  const u32 nvec = (len - head) / 4u;
+  for (u32 e = threadIdx.x; e < head; e += GBLOCK) f((u32)lab[base + e], wt[base + e]);
+  const u32 b4 = base + head;  // a multiple of 4
+  const float4* wv = reinterpret_cast<const float4*>(wt + b4);
+  auto labels4 = [&](u32 i, u32 (&j)[4]) {
+    if (sizeof(LT) == 2) {
+      const uint2 q = reinterpret_cast<const uint2*>(lab + b4)[i];
+      j[0] = q.x & 0xFFFFu; j[1] = q.x >> 16; j[2] = q.y & 0xFFFFu; j[3] = q.y >> 16;
+    } else {
+      const uint4 q = reinterpret_cast<const uint4*>(lab + b4)[i];
+      j[0] = q.x; j[1] = q.y; j[2] = q.z; j[3] = q.w;
+    }
+  };
+  for (u32 i = threadIdx.x; i < nvec; i += GBLOCK) {
+    u32 j0[4];
+    labels4(i, j0);
+    const float4 w0 = wv[i];
+    f(j0[0], w0.x); f(j0[1], w0.y); f(j0[2], w0.z); f(j0[3], w0.w);
+  }
+  for (u32 e = head + nvec * 4u + threadIdx.x; e < len; e += GBLOCK) f((u32)lab[base + e], wt[base + e]);
+}
 
 template <class LT>
 __device__ void group_one_w(const LT* __restrict__ CB, const float* __restrict__ CW, const u32 base, const u32 len,
@@ -1526,18 +1608,10 @@ __device__ void group_one_w(const LT* __restrict__ CB, const float* __restrict__
   if (tid == 0) s_hot = 0;
   __syncthreads();
   u32 mine = 0;
-  u128 sall = 0, shot = 0;
-  for (u32 e = tid; e < len; e += GBLOCK) {
-    const u32 j = (u32)CB[base + e];
-    const u128 wf = fix64_f32(CW[base + e]);
-    sall += wf;
-    if (j == g) {
-      ++mine;
-      shot += wf;
-    } else if (j < Lv) {
-      atomicAdd(&tab[j], 1u);
-    }
-  }
+  for_each_in_segment<LT>(CB + base, len, [&](u32 j) {
+    if (j == g) ++mine;
+    else if (j < Lv) atomicAdd(&tab[j], 1u);
+  });
   if (mine) atomicAdd(&s_hot, mine);
   __syncthreads();
   if (tid == 0 && s_hot && g < Lv) vis.visit(st, g, s_hot);
@@ -1548,18 +1622,25 @@ __device__ void group_one_w(const LT* __restrict__ CB, const float* __restrict__
     if (x.z) vis.visit(st, 4u * q + 2u, x.z);
     if (x.w) vis.visit(st, 4u * q + 3u, x.w);
   }
-  // second pass: weighted split penalty, with every count now in the table
-  u128 pw = 0;
-  const double gden = wo.twoW * (double)vis.N[g];
-  for (u32 e = tid; e < len; e += GBLOCK) {
-    const u32 j = (u32)CB[base + e];
-    if (j == g || j >= Lv) continue;
-    const double t = (double)CW[base + e] * (double)tab[j] / (gden * (double)vis.N[j]);
-    pw += fix96(t);
-  }
+  // second pass: weight sums and the weighted split penalty, every count now in the table.
+  // Branch-free: an entry of label g adds 0 to the penalty, a label outside [0, Lv) (only
+  // with a label error, which voids the result) reads slot g instead.
+  WeightSum sall, shot;
+  Frac96Sum pw;
+  const double kg = 1.0 / (wo.twoW * (double)vis.N[g]);
+  for_each_weighted<LT>(CB, CW, base, len, [&](u32 j, float w) {
+    u64 vlo, vhi;
+    WeightSum::split(w, vlo, vhi);
+    sall.add(vlo, vhi);
+    const bool own = j == g;
+    shot.add(own ? vlo : 0ull, own ? vhi : 0ull);
+    const u32 jj = j < Lv ? j : g;
+    const double f = own ? 0.0 : (double)tab[jj] * wo.invN[jj];
+    pw.add((double)w * f * kg);
+  });
   vis.finish(st, g);  // one barrier; the reads of tab above are done before anyone clears it
   {
-    const u128 a = wave_sum_u128(sall), b = wave_sum_u128(shot), c = wave_sum_u128(pw);
+    const u128 a = wave_sum_u128(sall.value()), b = wave_sum_u128(shot.value()), c = wave_sum_u128(pw.value());
     const int w = tid >> 6;
     if ((tid & 63) == 0) {
       r_w[0][w] = (u64)a;
@@ -1604,6 +1685,12 @@ __global__ __launch_bounds__(GBLOCK) void k_groups_w(const LT* __restrict__ CB, 
     const u32 g = order[item];
     group_one_w<LT>(CB, CW, seg_start[g], seg_len[g], g, Lv, vis, wo);
   }
+}
+
+// 1/|j| for every label id (0 where no node carries it), for the weighted penalty.
+__global__ void k_inv_sizes(int L, const u32* __restrict__ N, double* __restrict__ invN) {
+  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < L; c += gridDim.x * blockDim.x)
+    invN[c] = N[c] ? 1.0 / (double)N[c] : 0.0;
 }
 
 // Comparison visitor: row i of the contingency table, column j, cell x = |c_i ∩ c'_j|.
@@ -1886,9 +1973,9 @@ __global__ __launch_bounds__(FBLOCK) void k_score_final1_w(int L, const u32* __r
       const u128 s128 = ((u128)SW[2 * (size_t)c + 1] << 64) | SW[2 * (size_t)c];
       const u128 i128 = ((u128)IW[2 * (size_t)c + 1] << 64) | IW[2 * (size_t)c];
       const u128 p128 = ((u128)PENW[2 * (size_t)c + 1] << 64) | PENW[2 * (size_t)c];
-      const double sc = unfix64(s128);        // s(c)
-      const double wi = 0.5 * unfix64(i128);  // w_in(c)
-      const double wout = unfix64(s128 - i128);
+      const double sc = unfixw(s128);        // s(c)
+      const double wi = 0.5 * unfixw(i128);  // w_in(c)
+      const double wout = unfixw(s128 - i128);
       const double d = nc >= 2 ? (2.0 * (double)ein) / (double)((u64)nc * (u64)(nc - 1u)) : 0.0;
       const double tot = sc / (2.0 * W);
       const double tdc = tot * d;
@@ -1967,7 +2054,7 @@ __global__ void k_score_final2_w(int G, const WScorePart* __restrict__ parts, lo
   r.split_penalty = pen;
   r.Qds = qds_a - pen;
   const double Kd = (double)K;
-  const double wi = 0.5 * unfix64(swi2), wout = unfix64(swo);
+  const double wi = 0.5 * unfixw(swi2), wout = unfixw(swo);
   r.mean_intra_edges = wi / Kd;
   r.mean_intra_density = s_dens / Kd;
   r.mean_contraction = s_contr / Kd;

@@ -200,7 +200,7 @@ struct ScoreLayout {
   bool priv, small;  // small: labels fit 16 bits (num_labels <= 65535)
   int chunk, W, G;
   size_t ctl, N, D, start, order, I, NP, PEN, SZ, cursor, loc, HN, HD, labx, CB, parts, res, total;
-  size_t CW, SW, IW, PENW;  // weighted graphs only (0 otherwise)
+  size_t CW, SW, IW, PENW, INVN;  // weighted graphs only (0 otherwise)
 };
 
 ScoreLayout score_layout(int64_t n, int64_t nnz, int64_t L, bool weighted = false) {
@@ -234,6 +234,7 @@ ScoreLayout score_layout(int64_t n, int64_t nnz, int64_t L, bool weighted = fals
     s.SW = c.take(16 * (size_t)L);
     s.IW = c.take(16 * (size_t)L);
     s.PENW = c.take(16 * (size_t)L);
+    s.INVN = c.take(8 * (size_t)L);
   }
   s.total = c.off;
   return s;
@@ -407,15 +408,28 @@ void score_launch(cq_context* ctx, const cq_graph* g, const int32_t* labels, int
     if (g->rpb) {
       const int64_t span = (n + COL_BLOCKS - 1) / COL_BLOCKS;
       const unsigned own_groups = (unsigned)((span + BT_ROWS - 1) / BT_ROWS);
-      k_gather_blocked<LT><<<COL_BLOCKS * (own_groups + g->far_tiles), BT_THREADS, 0, s>>>(
-          (int)n, (int)span, g->rpb, g->colb, g->rowb, g->far, own_groups, g->far_tiles, labx, start, D,
-          at<u32>(ws, lay.cursor), ctl, CB, g->wb, CW);
-    } else if (lay.priv)
-      k_gather<true, LT><<<grid_for(n, GROWS, 1u << 30), GROWS, 0, s>>>((int)n, g->rp, g->col, labx, L, lay.chunk, PM, start, loc, CB,
-                                                                      g->w, CW);
-    else
-      k_gather<false, LT><<<grid_for(n, GROWS, 1u << 30), GROWS, 0, s>>>((int)n, g->rp, g->col, labx, L, lay.chunk, PM, start, loc,
-                                                                       CB, g->w, CW);
+      const unsigned grid = COL_BLOCKS * (own_groups + g->far_tiles);
+      if (CW)
+        k_gather_blocked<LT, true><<<grid, BT_THREADS, 0, s>>>((int)n, (int)span, g->rpb, g->colb, g->rowb, g->far, own_groups,
+                                                               g->far_tiles, labx, start, D, at<u32>(ws, lay.cursor), ctl, CB,
+                                                               g->wb, CW);
+      else
+        k_gather_blocked<LT, false><<<grid, BT_THREADS, 0, s>>>((int)n, (int)span, g->rpb, g->colb, g->rowb, g->far, own_groups,
+                                                                g->far_tiles, labx, start, D, at<u32>(ws, lay.cursor), ctl, CB,
+                                                                nullptr, nullptr);
+    } else {
+      const unsigned grid = grid_for(n, GROWS, 1u << 30);
+      if (lay.priv && CW)
+        k_gather<true, LT, true><<<grid, GROWS, 0, s>>>((int)n, g->rp, g->col, labx, L, lay.chunk, PM, start, loc, CB, g->w, CW);
+      else if (lay.priv)
+        k_gather<true, LT, false><<<grid, GROWS, 0, s>>>((int)n, g->rp, g->col, labx, L, lay.chunk, PM, start, loc, CB, nullptr,
+                                                        nullptr);
+      else if (CW)
+        k_gather<false, LT, true><<<grid, GROWS, 0, s>>>((int)n, g->rp, g->col, labx, L, lay.chunk, PM, start, loc, CB, g->w, CW);
+      else
+        k_gather<false, LT, false><<<grid, GROWS, 0, s>>>((int)n, g->rp, g->col, labx, L, lay.chunk, PM, start, loc, CB, nullptr,
+                                                         nullptr);
+    }
   }
   ScoreVis vis;
   vis.N = N;
@@ -439,9 +453,12 @@ void score_launch(cq_context* ctx, const cq_graph* g, const int32_t* labels, int
     wo.SW = at<u64>(ws, lay.SW);
     wo.IW = at<u64>(ws, lay.IW);
     wo.PENW = at<u64>(ws, lay.PENW);
+    double* invN = at<double>(ws, lay.INVN);
+    wo.invN = invN;
     wo.twoW = 2.0 * g->total_w;
     {
       StageMark mk(ctx, ST_GROUPS, timed);
+      k_inv_sizes<<<grid_for(L, 256, 1024), 256, 0, s>>>(L, N, invN);
       int nb = 0;
       if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_groups_w<LT>, GBLOCK, lds) != hipSuccess || nb < 1) nb = 1;
       k_groups_w<LT><<<(unsigned)(ctx->num_cus * nb), GBLOCK, lds, s>>>(CB, CW, start, D, order, ctl, (u32)L, vis, wo);
@@ -1466,11 +1483,11 @@ cq_status graph_load(cq_context* ctx, int32_t n, int64_t nnz, const int32_t* d_r
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     (void)hipFree(parts);
     if (e != hipSuccess) return fail(ctx, CQ_E_DEVICE, "weight check: %s", hipGetErrorString(e));
-    if (f) return fail(ctx, CQ_E_GRAPH_FORMAT, "edge weights must be finite and in [2^-40, 2^40]");
+    if (f) return fail(ctx, CQ_E_GRAPH_FORMAT, "edge weights must be finite and in [2^-32, 2^32]");
     u128 t = 0;
     for (unsigned b = 0; b < gb; ++b) t += ((u128)hp[2 * b + 1] << 64) | hp[2 * b];
     t >>= 1;  // every edge is stored twice with the same weight (odd halves only if unvalidated)
-    total_w = (double)(u64)(t >> 64) + std::ldexp((double)(u64)t, -64);
+    total_w = std::ldexp((double)(u64)(t >> 64), 9) + std::ldexp((double)(u64)t, -55);  // t / 2^55
   }
   cq_graph* g = new (std::nothrow) cq_graph();
   if (!g) return fail(ctx, CQ_E_DEVICE, "out of host memory");
