@@ -715,11 +715,53 @@ __device__ __forceinline__ void colscan_body(int W, int L, u32* __restrict__ HN,
   if (D) D[c] = sd;
 }
 
+// The same over many rows: a workgroup takes 64 labels (one per lane, so every row read
+// is coalesced) and 16 groups of consecutive rows.  Each group sums its rows, the groups'
+// sums are combined in LDS, and with SCAN each group writes its rows' prefixes starting
+// from the sum of the groups before it.
+constexpr int CS_LABELS = 64;
+constexpr int CS_GROUPS = 16;
 template <bool WEIGHTED, bool SCAN>
-__global__ __launch_bounds__(256) void k_colscan(int W, int L, u32* __restrict__ HN, u32* __restrict__ HD, u32* __restrict__ N,
-                                                 u32* __restrict__ D) {
-  int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c < L) colscan_body<WEIGHTED, SCAN>(W, L, HN, HD, N, D, c);
+__global__ __launch_bounds__(CS_LABELS * CS_GROUPS) void k_colscan(int W, int L, u32* __restrict__ HN,
+                                                                   u32* __restrict__ HD, u32* __restrict__ N,
+                                                                   u32* __restrict__ D) {
+  __shared__ u32 s_n[CS_GROUPS][CS_LABELS], s_d[CS_GROUPS][CS_LABELS];
+  const int lane = threadIdx.x % CS_LABELS, grp = threadIdx.x / CS_LABELS;
+  const int c = blockIdx.x * CS_LABELS + lane;
+  const int per = (W + CS_GROUPS - 1) / CS_GROUPS;
+  const int w0 = min(W, grp * per), w1 = min(W, w0 + per);
+  u32* PM = WEIGHTED ? HD : HN;
+  u32 sn = 0, sd = 0;
+  if (c < L) {
+    for (int w = w0; w < w1; ++w) {
+      const u32 xn = HN[(size_t)w * L + c];
+      sn += xn;
+      sd += WEIGHTED ? HD[(size_t)w * L + c] : xn;
+    }
+  }
+  s_n[grp][lane] = sn;
+  s_d[grp][lane] = sd;
+  __syncthreads();
+  if (c >= L) return;
+  if (SCAN) {
+    u32 run = 0;
+    for (int i = 0; i < grp; ++i) run += s_d[i][lane];
+    for (int w = w0; w < w1; ++w) {
+      const size_t at = (size_t)w * L + c;
+      const u32 x = WEIGHTED ? HD[at] : HN[at];
+      PM[at] = run;
+      run += x;
+    }
+  }
+  if (grp == 0) {
+    u32 tn = 0, td = 0;
+    for (int i = 0; i < CS_GROUPS; ++i) {
+      tn += s_n[i][lane];
+      td += s_d[i][lane];
+    }
+    N[c] = tn;
+    if (D) D[c] = td;
+  }
 }
 
 __global__ void k_unpack(int L, const unsigned long long* __restrict__ SZ, u32* __restrict__ N, u32* __restrict__ D) {

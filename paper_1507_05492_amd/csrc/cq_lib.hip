@@ -185,16 +185,24 @@ struct Carve {
   }
 };
 
-int pick_chunk(int64_t n) {
+// Nodes per workgroup of the private-histogram node passes: about 256 workgroups, at
+// most max_chunk nodes each.
+int pick_chunk(int64_t n, int64_t max_chunk = 65536) {
   int64_t c = 1024;
-  while (c < 65536 && c * 256 < n) c <<= 1;
+  while (c < max_chunk && c * 256 < n) c <<= 1;
   return (int)c;
 }
+// The caller-order node pass of column-blocked graphs (k_node_perm) is bound by its
+// scattered label stores and gains from more, smaller workgroups; its column scan only
+// needs totals, so the extra histogram rows cost little.
+constexpr int64_t PERM_CHUNK_MAX = 16384;
 
 unsigned grid_for(int64_t items, int per_block, unsigned cap) {
   int64_t g = (items + per_block - 1) / per_block;
   return (unsigned)std::max<int64_t>(1, std::min<int64_t>(g, cap));
 }
+
+unsigned colscan_grid(int64_t L) { return grid_for(L, CS_LABELS, 1u << 30); }
 
 struct ScoreLayout {
   bool priv, small;  // small: labels fit 16 bits (num_labels <= 65535)
@@ -203,13 +211,13 @@ struct ScoreLayout {
   size_t CW, SW, IW, PENW, INVN;  // weighted graphs only (0 otherwise)
 };
 
-ScoreLayout score_layout(int64_t n, int64_t nnz, int64_t L, bool weighted = false) {
+ScoreLayout score_layout(int64_t n, int64_t nnz, int64_t L, bool weighted = false, int64_t max_chunk = 65536) {
   ScoreLayout s{};
   Carve c;
   s.priv = L <= PRIV_MAX;
   s.small = L <= 65535;
   const size_t lt = s.small ? 2 : 4;
-  s.chunk = pick_chunk(n);
+  s.chunk = pick_chunk(n, max_chunk);
   s.W = (int)((n + s.chunk - 1) / s.chunk);
   s.G = (int)std::min<int64_t>(128, std::max<int64_t>(1, (L + 1023) / 1024));
   s.ctl = c.take(sizeof(Ctl));
@@ -238,6 +246,12 @@ ScoreLayout score_layout(int64_t n, int64_t nnz, int64_t L, bool weighted = fals
   }
   s.total = c.off;
   return s;
+}
+
+// The layout of one scoring call on graph g (the node pass it takes decides the chunk).
+ScoreLayout graph_score_layout(const cq_graph* g, int64_t L) {
+  const bool perm = g->rpb && g->pos1 && L <= PRIV_MAX;
+  return score_layout(g->n, g->nnz, L, g->w != nullptr, perm ? PERM_CHUNK_MAX : 65536);
 }
 
 struct CmpLayout {
@@ -359,7 +373,7 @@ void score_launch(cq_context* ctx, const cq_graph* g, const int32_t* labels, int
     }
     {
       StageMark mk(ctx, ST_COLSCAN, timed);
-      k_colscan<true, false><<<grid_for(L, 256, 1u << 30), 256, 0, s>>>(lay.W, L, HN, HD, N, D);
+      k_colscan<true, false><<<colscan_grid(L), CS_LABELS * CS_GROUPS, 0, s>>>(lay.W, L, HN, HD, N, D);
     }
     PM = HD;
   } else if (lay.priv) {
@@ -379,7 +393,7 @@ void score_launch(cq_context* ctx, const cq_graph* g, const int32_t* labels, int
     }
     {
       StageMark mk(ctx, ST_COLSCAN, timed);
-      k_colscan<true, true><<<grid_for(L, 256, 1u << 30), 256, 0, s>>>(lay.W, L, HN, HD, N, D);
+      k_colscan<true, true><<<colscan_grid(L), CS_LABELS * CS_GROUPS, 0, s>>>(lay.W, L, HN, HD, N, D);
     }
     PM = HD;
   } else {
@@ -493,7 +507,7 @@ cq_status score_enqueue(cq_context* ctx, const cq_graph* g, const int32_t* label
     return fail(ctx, CQ_E_INVALID_ARG, "weighted scoring supports up to %u label ids", HASH_WORDS);
   if (pairs && pairs->capacity > 0 && (!pairs->ci || !pairs->cj || !pairs->count))
     return fail(ctx, CQ_E_INVALID_ARG, "pair table with null arrays");
-  const ScoreLayout lay = score_layout(g->n, g->nnz, L, g->w != nullptr);
+  const ScoreLayout lay = graph_score_layout(g, L);
   if (!ws || ws_bytes < lay.total)
     return fail(ctx, CQ_E_WORKSPACE, "workspace %zu bytes, need %zu", ws_bytes, lay.total);
   if (lay.small)
@@ -532,7 +546,7 @@ void compare_launch(cq_context* ctx, int32_t n, const int32_t* la, int32_t La, c
     }
     {
       StageMark mk(ctx, ST_COLSCAN, timed);
-      k_colscan<false, true><<<grid_for(La, 256, 1u << 30), 256, 0, s>>>(lay.W, La, HN, HN, A, nullptr);
+      k_colscan<false, true><<<colscan_grid(La), CS_LABELS * CS_GROUPS, 0, s>>>(lay.W, La, HN, HN, A, nullptr);
     }
     PM = HN;
   } else {
@@ -551,7 +565,7 @@ void compare_launch(cq_context* ctx, int32_t n, const int32_t* la, int32_t La, c
     if (lay.privB) {
       u32* HB = at<u32>(ws, lay.HB);
       k_hist_priv<<<lay.Wb, 1024, (size_t)Lb * 4, s>>>(n, lb, Lb, HB, ctl);
-      k_colscan<false, false><<<grid_for(Lb, 256, 1u << 30), 256, 0, s>>>(lay.Wb, Lb, HB, HB, B, nullptr);
+      k_colscan<false, false><<<colscan_grid(Lb), CS_LABELS * CS_GROUPS, 0, s>>>(lay.Wb, Lb, HB, HB, B, nullptr);
     } else {
       k_hist_global<<<grid_for(n, 256, 8192), 256, 0, s>>>(n, lb, Lb, B, ctl);
     }
@@ -1547,7 +1561,7 @@ void cq_graph_release(cq_graph* g) { delete g; }
 
 size_t cq_score_workspace_size(const cq_graph* g, int32_t num_labels) {
   if (!g || num_labels < 1) return 0;
-  return score_layout(g->n, g->nnz, num_labels, g->w != nullptr).total;
+  return graph_score_layout(g, num_labels).total;
 }
 
 size_t cq_compare_workspace_size(int32_t n, int32_t num_labels_a, int32_t num_labels_b) {
@@ -1568,7 +1582,7 @@ cq_status cq_score_partition(cq_context* ctx, const cq_graph* g, const int32_t* 
   if (!ctx) return CQ_E_INVALID_ARG;
   if (!h_out) return fail(ctx, CQ_E_INVALID_ARG, "null result pointer");
   if (!g) return fail(ctx, CQ_E_INVALID_ARG, "null graph");
-  const ScoreLayout lay = score_layout(g->n, g->nnz, std::max(num_labels, 1), g->w != nullptr);
+  const ScoreLayout lay = graph_score_layout(g, std::max(num_labels, 1));
   ScoreResultDev* d_res = (d_ws && ws_bytes >= lay.total) ? at<ScoreResultDev>(d_ws, lay.res) : nullptr;
   cq_status st = score_enqueue(ctx, g, d_labels, num_labels, d_ws, ws_bytes, d_res ? d_res : reinterpret_cast<ScoreResultDev*>(1),
                                per_comm, pairs, true);
@@ -1827,7 +1841,7 @@ cq_status cq_server_submit_score(cq_server* srv, const cq_graph* g, const int32_
   r->n = g->n;
   r->L = num_labels;
   r->ha = h_labels;
-  r->ws_bytes = score_layout(g->n, g->nnz, num_labels, g->w != nullptr).total;
+  r->ws_bytes = graph_score_layout(g, num_labels).total;
   r->small = num_labels <= BATCH_MAX_L && g->nnz <= srv->cfg.small_nnz && !g->w;  // groups run the unweighted batch kernels
   return srv_submit(srv, r, ticket);
 }
