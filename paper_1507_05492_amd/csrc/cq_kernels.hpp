@@ -1239,7 +1239,7 @@ __device__ __forceinline__ void for_each_in_segment(const LT* __restrict__ seg, 
 template <class V, class LT>
 __device__ void group_one(const LT* __restrict__ CB, const u32 base, const u32 len, const u32 g, const u32 Lv,
                           const u32 lds_words, V& vis, Ctl* __restrict__ ctl) {
-  extern __shared__ u32 tab[];
+  extern __shared__ __align__(16) u32 tab[];  // read and cleared as uint4
   __shared__ u32 s_over;
   __shared__ u32 s_hot;
   __shared__ u32 s_nfix;
@@ -1638,7 +1638,7 @@ __device__ __forceinline__ void for_each_weighted(const LT* __restrict__ lab, co
 template <class LT>
 __device__ void group_one_w(const LT* __restrict__ CB, const float* __restrict__ CW, const u32 base, const u32 len,
                             const u32 g, const u32 Lv, ScoreVis& vis, const WeightedOut& wo) {
-  extern __shared__ u32 tab[];
+  extern __shared__ __align__(16) u32 tab[];  // read and cleared as uint4
   __shared__ u32 s_hot;
   __shared__ u64 r_w[6][GBLOCK / 64];
   const int tid = threadIdx.x;
