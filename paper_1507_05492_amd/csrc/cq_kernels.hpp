@@ -885,11 +885,12 @@ __global__ __launch_bounds__(GROWS) void k_gather(int n, const int32_t* __restri
 // its index in the run.
 constexpr int BT_THREADS = 256;
 constexpr int BT_UNROLL = 8;     // entries in flight per thread
-constexpr int BT_HALO = 4096;    // OWN tiles keep labels of ids within this distance of their rows in LDS
+constexpr int BT_HALO = 1024;    // OWN tiles keep labels of ids within this distance of their rows in LDS
 constexpr int BT_RPT = 4;                        // rows per thread in own-span tiles
 constexpr int BT_ROWS = BT_THREADS * BT_RPT;     // rows per own-span tile
 constexpr int FT_EPT = 8;                        // far entries per thread
 constexpr int FT_ENT = BT_THREADS * FT_EPT;      // far entries per tile
+constexpr int OWN_BUF = 1024;  // entries of another label an own-span tile keeps in LDS (compact staging)
 
 // Far entries of column block y: colb/rowb ranges [b[y][0], b[y][1]) (rows before span y)
 // and [b[y][2], b[y][3]) (rows after it), row-major.
@@ -901,9 +902,10 @@ template <class LT>
 struct GatherLds {
   static constexpr int PER = 16 / (int)sizeof(LT);             // labels per 16-byte word
   static constexpr int WINV = (BT_ROWS + 2 * BT_HALO) / PER + 1;  // 16-byte words of the label window
-  static constexpr int RUN_WORDS = (2 * BT_ROWS + 1 + 3) & ~3;    // s_re + s_rl, padded to 16 bytes
-  static constexpr int OWN = RUN_WORDS + 4 * WINV;
-  static constexpr int FAR = 2 * FT_ENT + 1;
+  static constexpr int RUN_WORDS = (4 * (BT_ROWS + 1) + 3) & ~3;  // four per-run arrays, padded to 16 bytes
+  static constexpr int BUF = sizeof(LT) == 2 ? OWN_BUF : 0;        // compact staging buffer (16-bit labels)
+  static constexpr int OWN = RUN_WORDS + 4 * WINV + BUF;
+  static constexpr int FAR = 3 * (FT_ENT + 1);
   static constexpr int WORDS = OWN > FAR ? OWN : FAR;
 };
 
@@ -942,8 +944,37 @@ __device__ __forceinline__ void claim_runs(u32 nruns, const u32* s_first, u32* s
   }
 }
 
+// Compact staging (unweighted graphs): an entry whose neighbour carries the row's own label
+// adds only to 2|E_c^in| and is not staged.  Run r of label c (entries s_first[r] ..
+// s_first[r+1], s_cnt[r] of them with another label) adds (intra << 32) | inter to
+// cur64[c] with one atomic: the low word is the segment cursor, the high word the intra
+// count.  s_base[r] gets the place of the run's first staged entry, or SENT; s_cnt[r]
+// is reset so that it can hand out places inside the run.
+template <class LT>
+__device__ __forceinline__ void claim_runs_compact(u32 nruns, const u32* s_first, const u32* s_lab, u32* s_cnt,
+                                                   u32* s_base, const u32* __restrict__ start, const u32* __restrict__ D,
+                                                   unsigned long long* __restrict__ cur64, Ctl* __restrict__ ctl) {
+  for (u32 r = threadIdx.x; r < nruns; r += BT_THREADS) {
+    const u32 c = s_lab[r];
+    const u32 tot = s_first[r + 1] - s_first[r];
+    const u32 inter = s_cnt[r];
+    u32 base = SENT;
+    if (c != (u32)LabelT<LT>::SENTINEL && tot > 0) {
+      const unsigned long long old = atomicAdd(&cur64[c], ((unsigned long long)(tot - inter) << 32) | inter);
+      const u32 lo = (u32)old;
+      if (lo + inter <= D[c]) base = start[c] + lo;  // < 2^31, so never the SENT marker
+      else atomicOr(&ctl->flags, F_SEGMENT);  // never expected: the block counts disagree with the degrees
+    }
+    s_base[r] = base;
+    s_cnt[r] = 0;
+  }
+}
+
 // Own-span tile t of block y: rows [s0 + t*BT_ROWS, ...) of span y, their block-y entries.
-// WT: the graph is weighted, and each entry's weight goes to CW beside its label.
+// WT: the graph is weighted: every entry is staged, with its weight in CW beside its
+// label.  Otherwise staging is compact (claim_runs_compact): a first pass over the
+// tile's entries counts each run's entries of another label, the runs claim their
+// places, and a second pass stages those entries.
 template <class LT, bool WT>
 __device__ void gather_own_tile(u32 y, u32 t, int n, int span, const u32* __restrict__ RPB,
                                 const int32_t* __restrict__ colb, const LT* __restrict__ labx,
@@ -954,7 +985,9 @@ __device__ void gather_own_tile(u32 y, u32 t, int n, int span, const u32* __rest
   constexpr int PER = LL::PER;
   constexpr int WIT = (LL::WINV + BT_THREADS - 1) / BT_THREADS;
   u32* s_re = lds;                   // staged row starts, then first entry of run q (tile-relative)
-  u32* s_rl = lds + BT_ROWS + 1;     // staged row labels, then label of run q, then its segment place
+  u32* s_rl = lds + BT_ROWS + 1;     // staged row labels, then label of run q (then its place, WT)
+  u32* s_cnt = lds + 2 * (BT_ROWS + 1);   // compact: entries of run q with another label
+  u32* s_base = lds + 3 * (BT_ROWS + 1);  // compact: place of run q's first staged entry
   uint4* s_win = reinterpret_cast<uint4*>(lds + LL::RUN_WORDS);  // labels of ids [w0, w1)
   const long long s0 = min((long long)n, (long long)y * span), s1 = min((long long)n, s0 + span);
   const long long r0 = s0 + (long long)t * BT_ROWS, r1 = min(s1, r0 + BT_ROWS);
@@ -1023,46 +1056,112 @@ __device__ void gather_own_tile(u32 y, u32 t, int n, int span, const u32* __rest
       ++q;
     }
   }
-  if (tid == 0) s_re[nruns] = e1 - e0;
-  __syncthreads();
-  claim_runs<LT>(nruns, s_re, s_rl, start, D, cursor, ctl);
+  if (tid == 0) {
+    s_re[nruns] = e1 - e0;
+    s_base[BT_ROWS] = 0;  // compact: count of buffered entries
+  }
+  if (!WT)
+    for (u32 r = tid; r < nruns; r += BT_THREADS) s_cnt[r] = 0;
   __syncthreads();
   const int32_t* cb = colb + e0;
   const u32 ne = e1 - e0;
-  for (u32 eb = tid; eb < ne; eb += BT_THREADS * BT_UNROLL) {
-    int v[BT_UNROLL];
-    float wt[BT_UNROLL];
-    u32 pos[BT_UNROLL];
+  // f(e, run, x, w) for the BT_UNROLL entries e = eb + u*BT_THREADS of each chunk (e < ne);
+  // w is the entry's weight (WT) or 0
+  auto for_entries = [&](auto&& f) {
+    for (u32 eb = tid; eb < ne; eb += BT_THREADS * BT_UNROLL) {
+      int v[BT_UNROLL];
+      float wt[BT_UNROLL];
+      u32 run[BT_UNROLL];
 #pragma unroll
-    for (int u = 0; u < BT_UNROLL; ++u) v[u] = cb[min(eb + (u32)(u * BT_THREADS), ne - 1u)];  // in bounds; masked below
-    if (WT) {  // weights are loaded with the neighbour ids, so their latency overlaps the run search
+      for (int u = 0; u < BT_UNROLL; ++u) v[u] = cb[min(eb + (u32)(u * BT_THREADS), ne - 1u)];  // in bounds; masked below
 #pragma unroll
-      for (int u = 0; u < BT_UNROLL; ++u) wt[u] = wb[e0 + min(eb + (u32)(u * BT_THREADS), ne - 1u)];
-    }
+      for (int u = 0; u < BT_UNROLL; ++u)  // loaded with the ids, so their latency overlaps the run search
+        wt[u] = WT ? wb[e0 + min(eb + (u32)(u * BT_THREADS), ne - 1u)] : 0.0f;
 #pragma unroll
-    for (int u = 0; u < BT_UNROLL; ++u) {
-      const u32 e = eb + (u32)(u * BT_THREADS);
-      u32 lo = 0, hi = nruns - 1;  // last run r with s_re[r] <= e
-      while (lo < hi) {
-        const u32 mid = (lo + hi + 1) >> 1;
-        if (s_re[mid] <= e) lo = mid; else hi = mid - 1;
+      for (int u = 0; u < BT_UNROLL; ++u) {
+        const u32 e = eb + (u32)(u * BT_THREADS);
+        u32 lo = 0, hi = nruns - 1;  // last run r with s_re[r] <= e
+        while (lo < hi) {
+          const u32 mid = (lo + hi + 1) >> 1;
+          if (s_re[mid] <= e) lo = mid; else hi = mid - 1;
+        }
+        run[u] = lo;
       }
-      const u32 base = s_rl[lo];
-      pos[u] = (e < ne && base != SENT) ? base + (e - s_re[lo]) : SENT;
+      LT x[BT_UNROLL];
+#pragma unroll
+      for (int u = 0; u < BT_UNROLL; ++u) {
+        const u32 off = (u32)((long long)v[u] - w0);
+        x[u] = off < (u32)(w1 - w0) ? reinterpret_cast<const LT*>(s_win)[off] : labx[v[u]];
+      }
+#pragma unroll
+      for (int u = 0; u < BT_UNROLL; ++u) {
+        const u32 e = eb + (u32)(u * BT_THREADS);
+        if (e < ne) f(e, run[u], x[u], wt[u]);
+      }
     }
-    LT x[BT_UNROLL];
-#pragma unroll
-    for (int u = 0; u < BT_UNROLL; ++u) {
-      const u32 off = (u32)((long long)v[u] - w0);
-      x[u] = off < (u32)(w1 - w0) ? reinterpret_cast<const LT*>(s_win)[off] : labx[v[u]];
-    }
-#pragma unroll
-    for (int u = 0; u < BT_UNROLL; ++u)
-      if (pos[u] != SENT) CB[pos[u]] = x[u];
-    if (WT) {
-#pragma unroll
-      for (int u = 0; u < BT_UNROLL; ++u)
-        if (pos[u] != SENT) CW[pos[u]] = wt[u];
+  };
+  if (WT) {
+    claim_runs<LT>(nruns, s_re, s_rl, start, D, cursor, ctl);
+    __syncthreads();
+    for_entries([&](u32 e, u32 r, LT x, float w) {
+      const u32 base = s_rl[r];
+      if (base != SENT) {
+        CB[base + (e - s_re[r])] = x;
+        CW[base + (e - s_re[r])] = w;
+      }
+    });
+  } else {
+    // Pass 1: count each run's entries of another label and keep them, (run << 16) | label,
+    // in the LDS buffer; slots and counts are taken once per wave.
+    u32* s_buf = lds + LL::RUN_WORDS + 4 * LL::WINV;
+    u32* s_nbuf = s_base + BT_ROWS;  // unused by runs (nruns <= BT_ROWS)
+    const int lane = tid & 63;
+    const u64 below = lane ? (~0ull >> (64 - lane)) : 0ull;
+    for_entries([&](u32, u32 r, LT x, float) {
+      const bool inter = (u32)x != s_rl[r];
+      const u64 m = __ballot(inter);
+      if (m == 0) return;
+      const int lead = __ffsll((long long)m) - 1;
+      const u32 rl = __shfl(r, lead, 64);
+      const u64 ms = __ballot(inter && r == rl);
+      u32 slot0 = 0;
+      if (lane == lead) {
+        slot0 = atomicAdd(s_nbuf, (u32)__popcll(m));
+        atomicAdd(&s_cnt[rl], (u32)__popcll(ms));
+      }
+      slot0 = __shfl(slot0, lead, 64);
+      if (inter) {
+        const u32 slot = slot0 + (u32)__popcll(m & below);
+        if (slot < (u32)LL::BUF) s_buf[slot] = (r << 16) | (u32)x;
+        if (r != rl) atomicAdd(&s_cnt[r], 1u);
+      }
+    });
+    __syncthreads();
+    claim_runs_compact<LT>(nruns, s_re, s_rl, s_cnt, s_base, start, D, reinterpret_cast<unsigned long long*>(cursor), ctl);
+    __syncthreads();
+    const u32 nb = *s_nbuf;
+    if (nb <= (u32)LL::BUF) {
+      // write the buffer out: each wave takes consecutive places per run (coalesced)
+      for (u32 k = tid; k < nb; k += BT_THREADS) {
+        const u32 ent = s_buf[k];
+        const u32 r = ent >> 16;
+        const u64 act = __ballot(true);
+        const int lead = __ffsll((long long)act) - 1;
+        const u32 rl = __shfl(r, lead, 64);
+        const u64 ms = __ballot(r == rl);
+        u32 p0 = 0;
+        if (lane == lead) p0 = atomicAdd(&s_cnt[rl], (u32)__popcll(ms));
+        p0 = __shfl(p0, lead, 64);
+        const u32 rank = r == rl ? p0 + (u32)__popcll(ms & below) : atomicAdd(&s_cnt[r], 1u);
+        const u32 base = s_base[r];
+        if (base != SENT) CB[base + rank] = (LT)(ent & 0xFFFFu);
+      }
+    } else {
+      // buffer overflow (or 32-bit labels): classify the tile's entries again
+      for_entries([&](u32, u32 r, LT x, float) {
+        const u32 base = s_base[r];
+        if ((u32)x != s_rl[r] && base != SENT) CB[base + atomicAdd(&s_cnt[r], 1u)] = x;
+      });
     }
   }
 }
@@ -1074,8 +1173,9 @@ __device__ void gather_far_tile(u32 y, u32 t, const FarTable& ft, const int32_t*
                                 const u32* __restrict__ start, const u32* __restrict__ D, u32* __restrict__ cursor,
                                 Ctl* __restrict__ ctl, LT* __restrict__ CB, const float* __restrict__ wb,
                                 float* __restrict__ CW, u32* lds, u32* s_w) {
-  u32* s_rf = lds;               // first entry of run q (tile-relative); s_rf[nruns] = entry count
-  u32* s_rb = lds + FT_ENT + 1;  // staged row labels, then label of run q, then its segment place
+  u32* s_rf = lds;                     // first entry of run q (tile-relative); s_rf[nruns] = entry count
+  u32* s_rb = lds + FT_ENT + 1;        // staged row labels, then label of run q, then its segment place
+  u32* s_cnt = lds + 2 * (FT_ENT + 1);  // compact: entries of run q with another label
   const u32 b0 = ft.b[y][0], b1 = ft.b[y][1], b2 = ft.b[y][2], b3 = ft.b[y][3];
   const u32 t1 = (b1 - b0 + FT_ENT - 1) / FT_ENT;
   u32 e0, e1;
@@ -1126,21 +1226,41 @@ __device__ void gather_far_tile(u32 y, u32 t, const FarTable& ft, const int32_t*
     }
   }
   if (tid == 0) s_rf[nruns] = ne;
+  if (!WT)
+    for (u32 r = tid; r < nruns; r += BT_THREADS) s_cnt[r] = 0;
   __syncthreads();
-  claim_runs<LT>(nruns, s_rf, s_rb, start, D, cursor, ctl);
-  __syncthreads();
-  u32 q = q0;  // runs started up to entry i0 + j
+  // f(j, i, run) for this thread's entries i = i0 + j < ne
+  auto for_entries = [&](auto&& f) {
+    u32 q = q0;  // runs started up to entry i0 + j
 #pragma unroll
-  for (int j = 0; j < FT_EPT; ++j) {
-    const u32 i = i0 + (u32)j;
-    if (heads & (1u << j)) ++q;
-    if (i >= ne) continue;
-    const u32 run = q - 1u;  // entry i lies in the last run that starts at or before it
-    const u32 base = s_rb[run];
-    if (base != SENT) {
-      CB[base + (i - s_rf[run])] = x[j];
-      if (WT) CW[base + (i - s_rf[run])] = wt[j];
+    for (int j = 0; j < FT_EPT; ++j) {
+      const u32 i = i0 + (u32)j;
+      if (heads & (1u << j)) ++q;
+      if (i < ne) f(j, i, q - 1u);  // entry i lies in the last run that starts at or before it
     }
+  };
+  if (WT) {
+    claim_runs<LT>(nruns, s_rf, s_rb, start, D, cursor, ctl);
+    __syncthreads();
+    for_entries([&](int j, u32 i, u32 run) {
+      const u32 base = s_rb[run];
+      if (base != SENT) {
+        CB[base + (i - s_rf[run])] = x[j];
+        CW[base + (i - s_rf[run])] = wt[j];
+      }
+    });
+  } else {
+    for_entries([&](int j, u32, u32 run) {
+      if ((u32)x[j] != lab[j]) atomicAdd(&s_cnt[run], 1u);
+    });
+    __syncthreads();
+    // s_rb: the run's label, replaced by the place of its first staged entry
+    claim_runs_compact<LT>(nruns, s_rf, s_rb, s_cnt, s_rb, start, D, reinterpret_cast<unsigned long long*>(cursor), ctl);
+    __syncthreads();
+    for_entries([&](int j, u32, u32 run) {
+      const u32 base = s_rb[run];
+      if ((u32)x[j] != lab[j] && base != SENT) CB[base + atomicAdd(&s_cnt[run], 1u)] = x[j];
+    });
   }
 }
 
@@ -1235,10 +1355,11 @@ __device__ __forceinline__ void for_each_in_segment(const LT* __restrict__ seg, 
 }
 
 // Counts one group's segment CB[base, base+len) (values in [0, Lv) or the sentinel)
-// in LDS and hands every (label, count) with count > 0 to the visitor.
+// in LDS and hands every (label, count) with count > 0 to the visitor.  hot0 entries of
+// the hot label were counted elsewhere (compact staging leaves them out of the segment).
 template <class V, class LT>
 __device__ void group_one(const LT* __restrict__ CB, const u32 base, const u32 len, const u32 g, const u32 Lv,
-                          const u32 lds_words, V& vis, Ctl* __restrict__ ctl) {
+                          const u32 lds_words, V& vis, Ctl* __restrict__ ctl, const u32 hot0 = 0) {
   extern __shared__ __align__(16) u32 tab[];  // read and cleared as uint4
   __shared__ u32 s_over;
   __shared__ u32 s_hot;
@@ -1267,7 +1388,7 @@ __device__ void group_one(const LT* __restrict__ CB, const u32 base, const u32 l
     uint4* tab4 = reinterpret_cast<uint4*>(tab);
     for (u32 q = tid; q < nq; q += GBLOCK) tab4[q] = make_uint4(0u, 0u, 0u, 0u);
     if (tid == 0) {
-      s_hot = 0;
+      s_hot = hot0;
       s_nfix = 0;
     }
     __syncthreads();
@@ -1332,7 +1453,7 @@ __device__ void group_one(const LT* __restrict__ CB, const u32 base, const u32 l
     const u32 nq = (Lv + 3u) >> 2;  // the table is padded to whole 16-byte words
     uint4* tab4 = reinterpret_cast<uint4*>(tab);
     for (u32 q = tid; q < nq; q += GBLOCK) tab4[q] = make_uint4(0u, 0u, 0u, 0u);
-    if (tid == 0) s_hot = 0;
+    if (tid == 0) s_hot = hot0;
     __syncthreads();
     u32 mine = 0;
     for_each_in_segment<LT>(CB + base, len, [&](u32 j) {
@@ -1369,7 +1490,7 @@ __device__ void group_one(const LT* __restrict__ CB, const u32 base, const u32 l
     u32* cnt = tab + hcap;
     if (tid == 0) {
       s_sp = 0;
-      s_hot = 0;
+      s_hot = hot0;
       for (int r = (int)classes - 1; r >= 0; --r) { s_sr[s_sp] = (u32)r; s_sm[s_sp] = classes; ++s_sp; }
     }
     __syncthreads();
@@ -1437,9 +1558,12 @@ __device__ void group_one(const LT* __restrict__ CB, const u32 base, const u32 l
 }
 
 template <class V, class LT>
+// cur64 (compact staging, else null): low word = segment length, high word = entries of
+// the group's own label left out of the segment; otherwise seg_len gives the length.
 __global__ __launch_bounds__(GBLOCK) void k_groups(const LT* __restrict__ CB, const u32* __restrict__ seg_start,
                                                    const u32* __restrict__ seg_len, const u32* __restrict__ order,
-                                                   Ctl* __restrict__ ctl, u32 Lv, u32 lds_words, V vis) {
+                                                   Ctl* __restrict__ ctl, u32 Lv, u32 lds_words, V vis,
+                                                   const unsigned long long* __restrict__ cur64) {
   __shared__ u32 s_item;
   const u32 K = ctl->K;
   for (;;) {
@@ -1449,7 +1573,8 @@ __global__ __launch_bounds__(GBLOCK) void k_groups(const LT* __restrict__ CB, co
     __syncthreads();
     if (item >= K) break;
     const u32 g = order[item];
-    group_one<V, LT>(CB, seg_start[g], seg_len[g], g, Lv, lds_words, vis, ctl);
+    const unsigned long long c = cur64 ? cur64[g] : (unsigned long long)seg_len[g];
+    group_one<V, LT>(CB, seg_start[g], (u32)c, g, Lv, lds_words, vis, ctl, (u32)(c >> 32));
   }
 }
 

@@ -229,7 +229,7 @@ ScoreLayout score_layout(int64_t n, int64_t nnz, int64_t L, bool weighted = fals
   s.NP = c.take(4 * L);
   s.PEN = c.take(16 * L);
   s.SZ = s.priv ? 0 : c.take(8 * L);
-  s.cursor = c.take(4 * L);
+  s.cursor = c.take(8 * L);  // u32 run cursors, or u64 (cursor, own-label count) with compact staging
   s.loc = c.take(4 * n);
   s.HN = s.priv ? c.take(4 * (size_t)s.W * L) : 0;
   s.HD = s.priv ? c.take(4 * (size_t)s.W * L) : 0;
@@ -356,7 +356,7 @@ void score_launch(cq_context* ctx, const cq_graph* g, const int32_t* labels, int
     StageMark mk(ctx, ST_SETUP, timed);
     fill(reinterpret_cast<u32*>(ctl), sizeof(Ctl) / 4, 0, s);
     if (!lay.priv) fill(at<u32>(ws, lay.SZ), 2 * (size_t)L, 0, s);
-    if (g->rpb) fill(at<u32>(ws, lay.cursor), (size_t)L, 0, s);
+    if (g->rpb) fill(at<u32>(ws, lay.cursor), 2 * (size_t)L, 0, s);
   }
   if (lay.priv && g->rpb && g->pos1) {
     // column-blocked graph: count in the caller's order, move labels with the bucket plan
@@ -487,7 +487,10 @@ void score_launch(cq_context* ctx, const cq_graph* g, const int32_t* labels, int
   }
   {
     StageMark mk(ctx, ST_GROUPS, timed);
-    k_groups<ScoreVis, LT><<<group_grid<ScoreVis, LT>(ctx, lds), GBLOCK, lds, s>>>(CB, start, D, order, ctl, (u32)L, lds_words, vis);
+    // column-blocked graphs stage compactly (see k_gather_blocked): lengths and own-label counts in the cursors
+    const unsigned long long* cur64 = g->rpb ? at<unsigned long long>(ws, lay.cursor) : nullptr;
+    k_groups<ScoreVis, LT><<<group_grid<ScoreVis, LT>(ctx, lds), GBLOCK, lds, s>>>(CB, start, D, order, ctl, (u32)L, lds_words, vis,
+                                                                                 cur64);
   }
   {
     StageMark mk(ctx, ST_FINAL, timed);
@@ -601,7 +604,8 @@ void compare_launch(cq_context* ctx, int32_t n, const int32_t* la, int32_t La, c
   const size_t lds = (size_t)lds_words * 4;
   {
     StageMark mk(ctx, ST_GROUPS, timed);
-    k_groups<CmpVis, LT><<<group_grid<CmpVis, LT>(ctx, lds), GBLOCK, lds, s>>>(CB, start, A, order, ctl, (u32)Lb, lds_words, vis);
+    k_groups<CmpVis, LT><<<group_grid<CmpVis, LT>(ctx, lds), GBLOCK, lds, s>>>(CB, start, A, order, ctl, (u32)Lb, lds_words, vis,
+                                                                               nullptr);
   }
   CmpPart* parts = at<CmpPart>(ws, lay.parts);
   {
