@@ -16,8 +16,8 @@
  *              (for example the storage of torch tensors).  The library never
  *              frees caller memory and never allocates device memory inside a
  *              scoring or comparison call; scratch space is the caller-provided
- *              workspace, sized by the *_workspace_size queries.  Structs marked
- *              HOST are host memory.
+ *              workspace, sized by the *_workspace_size queries and 16-byte aligned
+ *              (hipMalloc's alignment is enough).  Structs marked HOST are host memory.
  *   Streams    Work is enqueued on the context's HIP stream (hipStream_t passed
  *              as void*).  Synchronous calls return after the result struct has
  *              reached host memory.
@@ -221,7 +221,8 @@ size_t cq_score_workspace_size(const cq_graph* g, int32_t num_labels);
 /*
  * Score the partition given by d_labels (DEVICE int32[n], values in
  * [0, num_labels); ids no node carries are allowed and ignored).
- *   d_ws/ws_bytes  DEVICE workspace of at least cq_score_workspace_size bytes;
+ *   d_ws/ws_bytes  DEVICE workspace of at least cq_score_workspace_size bytes, 16-byte
+ *                  aligned (as hipMalloc returns; CQ_E_INVALID_ARG otherwise);
  *                  contents on entry are ignored, on exit unspecified.
  *   h_out          HOST result.
  *   per_comm       optional per-label DEVICE outputs (NULL to skip).

@@ -721,10 +721,12 @@ __device__ __forceinline__ void colscan_body(int W, int L, u32* __restrict__ HN,
 // from the sum of the groups before it.
 constexpr int CS_LABELS = 64;
 constexpr int CS_GROUPS = 16;
+// zero64 (optional): one 64-bit word per label cleared on the way (the run cursors).
 template <bool WEIGHTED, bool SCAN>
 __global__ __launch_bounds__(CS_LABELS * CS_GROUPS) void k_colscan(int W, int L, u32* __restrict__ HN,
                                                                    u32* __restrict__ HD, u32* __restrict__ N,
-                                                                   u32* __restrict__ D) {
+                                                                   u32* __restrict__ D,
+                                                                   unsigned long long* __restrict__ zero64 = nullptr) {
   __shared__ u32 s_n[CS_GROUPS][CS_LABELS], s_d[CS_GROUPS][CS_LABELS];
   const int lane = threadIdx.x % CS_LABELS, grp = threadIdx.x / CS_LABELS;
   const int c = blockIdx.x * CS_LABELS + lane;
@@ -761,6 +763,7 @@ __global__ __launch_bounds__(CS_LABELS * CS_GROUPS) void k_colscan(int W, int L,
     }
     N[c] = tn;
     if (D) D[c] = td;
+    if (zero64) zero64[c] = 0ull;
   }
 }
 
@@ -777,6 +780,38 @@ __global__ void k_unpack(int L, const unsigned long long* __restrict__ SZ, u32* 
 // non-empty groups: by decreasing floor(log2 D), so the largest groups start first.
 __device__ __forceinline__ int size_bucket(u32 x) { return x ? 32 - __clz(x) : 0; }
 
+// Values of labels c0 .. c0+15 (0 past L): 16-byte loads when all 16 exist (c0 is a
+// multiple of 16 and the arrays 16-byte aligned), else one guarded load per label.
+__device__ __forceinline__ void load_labels16(int c0, int L, const u32* __restrict__ N, const u32* __restrict__ D,
+                                              u32 (&d)[16], u32 (&nn)[16]) {
+  typedef u32 v4u __attribute__((ext_vector_type(4)));
+  if (c0 + 16 <= L) {
+    const v4u* dv = reinterpret_cast<const v4u*>(D + c0);
+    const v4u* nv = reinterpret_cast<const v4u*>(N + c0);
+    v4u a[4], b[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      a[i] = dv[i];
+      b[i] = nv[i];
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      d[4 * i] = a[i].x; d[4 * i + 1] = a[i].y; d[4 * i + 2] = a[i].z; d[4 * i + 3] = a[i].w;
+      nn[4 * i] = b[i].x; nn[4 * i + 1] = b[i].y; nn[4 * i + 2] = b[i].z; nn[4 * i + 3] = b[i].w;
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      const int c = c0 + k;
+      d[k] = c < L ? D[c] : 0u;
+      nn[k] = c < L ? N[c] : 0u;
+    }
+  }
+}
+
+// One workgroup of 1024 threads; thread t takes SO_PER consecutive labels of each pass
+// of 1024 * SO_PER, with all of their loads issued before the first use.
+constexpr int SO_PER = 16;  // load_labels16
 __device__ void scan_order_body(int L, const u32* __restrict__ N, const u32* __restrict__ D, u32* __restrict__ start,
                                 u32* __restrict__ order, Ctl* __restrict__ ctl) {
   __shared__ u32 s_wtot[16];
@@ -787,19 +822,26 @@ __device__ void scan_order_body(int L, const u32* __restrict__ N, const u32* __r
   if (tid < 33) s_bcnt[tid] = 0;
   if (tid == 0) s_carry = 0;
   __syncthreads();
-  for (int base = 0; base < L; base += 1024) {
-    int c = base + tid;
-    u32 x = 0;
-    if (c < L) {
-      x = D[c];
-      if (N[c] > 0) atomicAdd(&s_bcnt[size_bucket(x)], 1u);
+  for (int base = 0; base < L; base += 1024 * SO_PER) {
+    const int c0 = base + tid * SO_PER;
+    u32 d[SO_PER], nn[SO_PER];
+    load_labels16(c0, L, N, D, d, nn);
+    u32 sum = 0;
+#pragma unroll
+    for (int k = 0; k < SO_PER; ++k) {
+      sum += d[k];
+      if (nn[k] > 0) atomicAdd(&s_bcnt[size_bucket(d[k])], 1u);
     }
-    u32 incl = wave_incl_scan(x);
+    const u32 incl = wave_incl_scan(sum);
     if (lane == 63) s_wtot[wv] = incl;
     __syncthreads();
-    u32 before = s_carry;
-    for (int i = 0; i < wv; ++i) before += s_wtot[i];
-    if (c < L) start[c] = before + incl - x;
+    u32 run = s_carry + incl - sum;
+    for (int i = 0; i < wv; ++i) run += s_wtot[i];
+#pragma unroll
+    for (int k = 0; k < SO_PER; ++k) {
+      if (c0 + k < L) start[c0 + k] = run;
+      run += d[k];
+    }
     __syncthreads();
     if (tid == 0) {
       u32 t = s_carry;
@@ -814,10 +856,13 @@ __device__ void scan_order_body(int L, const u32* __restrict__ N, const u32* __r
     ctl->K = off;
   }
   __syncthreads();
-  for (int c = tid; c < L; c += 1024) {
-    if (N[c] > 0) {
-      u32 pos = atomicAdd(&s_boff[size_bucket(D[c])], 1u);
-      order[pos] = (u32)c;
+  for (int base = 0; base < L; base += 1024 * SO_PER) {
+    const int c0 = base + tid * SO_PER;
+    u32 d[SO_PER], nn[SO_PER];
+    load_labels16(c0, L, N, D, d, nn);
+#pragma unroll
+    for (int k = 0; k < SO_PER; ++k) {
+      if (nn[k] > 0) order[atomicAdd(&s_boff[size_bucket(d[k])], 1u)] = (u32)(c0 + k);
     }
   }
 }

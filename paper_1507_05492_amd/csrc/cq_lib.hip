@@ -131,7 +131,8 @@ namespace {
 constexpr int64_t PRIV_MAX = 16384;    // labels handled by LDS-private node histograms
 constexpr int64_t DIRECT_MAX = 16384;  // labels handled by direct-indexed group tables
 constexpr u32 HASH_WORDS = 32768;      // LDS words of the group hash table (16384 slots)
-constexpr size_t ALIGN = 256;
+constexpr size_t ALIGN = 256;    // offsets of the arrays carved from a workspace
+constexpr size_t WS_ALIGN = 16;  // workspaces: the kernels load 16-byte vectors from the arrays
 
 enum Stage { ST_SETUP = 0, ST_NODE, ST_COLSCAN, ST_ORDER, ST_GATHER, ST_GROUPS, ST_FINAL, ST_HIST_B, ST_SCATTER, ST_COUNT };
 const char* const kStageNames[ST_COUNT] = {"setup", "node_pass", "column_scan", "scan_order", "edge_gather",
@@ -356,7 +357,9 @@ void score_launch(cq_context* ctx, const cq_graph* g, const int32_t* labels, int
     StageMark mk(ctx, ST_SETUP, timed);
     fill(reinterpret_cast<u32*>(ctl), sizeof(Ctl) / 4, 0, s);
     if (!lay.priv) fill(at<u32>(ws, lay.SZ), 2 * (size_t)L, 0, s);
-    if (g->rpb) fill(at<u32>(ws, lay.cursor), 2 * (size_t)L, 0, s);
+    // run cursors of column-blocked graphs: cleared by the column scan on the
+    // private-histogram path, here otherwise
+    if (g->rpb && !(lay.priv && g->pos1)) fill(at<u32>(ws, lay.cursor), 2 * (size_t)L, 0, s);
   }
   if (lay.priv && g->rpb && g->pos1) {
     // column-blocked graph: count in the caller's order, move labels with the bucket plan
@@ -373,7 +376,8 @@ void score_launch(cq_context* ctx, const cq_graph* g, const int32_t* labels, int
     }
     {
       StageMark mk(ctx, ST_COLSCAN, timed);
-      k_colscan<true, false><<<colscan_grid(L), CS_LABELS * CS_GROUPS, 0, s>>>(lay.W, L, HN, HD, N, D);
+      k_colscan<true, false><<<colscan_grid(L), CS_LABELS * CS_GROUPS, 0, s>>>(lay.W, L, HN, HD, N, D,
+                                                                          at<unsigned long long>(ws, lay.cursor));
     }
     PM = HD;
   } else if (lay.priv) {
@@ -513,6 +517,7 @@ cq_status score_enqueue(cq_context* ctx, const cq_graph* g, const int32_t* label
   const ScoreLayout lay = graph_score_layout(g, L);
   if (!ws || ws_bytes < lay.total)
     return fail(ctx, CQ_E_WORKSPACE, "workspace %zu bytes, need %zu", ws_bytes, lay.total);
+  if (reinterpret_cast<uintptr_t>(ws) % WS_ALIGN) return fail(ctx, CQ_E_INVALID_ARG, "workspace not 16-byte aligned");
   if (lay.small)
     score_launch<uint16_t>(ctx, g, labels, L, ws, lay, d_out, per_comm, pairs, timed);
   else
@@ -628,6 +633,7 @@ cq_status compare_enqueue(cq_context* ctx, int32_t n, const int32_t* la, int32_t
   const CmpLayout lay = cmp_layout(n, La, Lb);
   if (!ws || ws_bytes < lay.total)
     return fail(ctx, CQ_E_WORKSPACE, "workspace %zu bytes, need %zu", ws_bytes, lay.total);
+  if (reinterpret_cast<uintptr_t>(ws) % WS_ALIGN) return fail(ctx, CQ_E_INVALID_ARG, "workspace not 16-byte aligned");
   if (lay.small)
     compare_launch<uint16_t>(ctx, n, la, La, lb, Lb, ws, lay, d_out, cells, timed);
   else
@@ -1660,6 +1666,7 @@ cq_status cq_batch_bind(cq_batch_plan* p, void* d_ws, size_t ws_bytes, cq_score_
   ctx->err[0] = 0;
   if (!d_ws || ws_bytes < p->ws_total)
     return fail(ctx, CQ_E_WORKSPACE, "workspace %zu bytes, need %zu", ws_bytes, p->ws_total);
+  if (reinterpret_cast<uintptr_t>(d_ws) % WS_ALIGN) return fail(ctx, CQ_E_INVALID_ARG, "workspace not 16-byte aligned");
   if (!d_results) return fail(ctx, CQ_E_INVALID_ARG, "null result array");
   if (p->exec) { (void)hipGraphExecDestroy(p->exec); p->exec = nullptr; }
   if (p->graph) { (void)hipGraphDestroy(p->graph); p->graph = nullptr; }

@@ -152,6 +152,13 @@ def test_errors(cq, ctx, reorder):
     with pytest.raises(cq.CQError) as e:
         cq.score_partition(g, lab, 5, workspace=ws)
     assert e.value.status == cq.CQ_E_WORKSPACE
+    note("workspace not 16-byte aligned")
+    big = torch.empty(g.workspace_size(5) + 64, dtype=torch.uint8, device="cuda")
+    with pytest.raises(cq.CQError) as e:
+        cq.score_partition(g, lab, 5, workspace=big[8:])
+    assert e.value.status == cq.CQ_E_INVALID_ARG
+    r, _, _ = cq.score_partition(g, lab, 5, workspace=big[16:])  # 16-byte offsets are fine
+    assert r["status"] == cq.CQ_OK
     note("pair export too small")
     lab2 = torch.as_tensor(np.arange(50, dtype=np.int32) % 7).cuda()
     r, _, pt = cq.score_partition(g, lab2, 7, pairs_capacity=2, allow=(cq.CQ_E_CAPACITY,))
