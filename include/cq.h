@@ -80,8 +80,13 @@ const char* cq_context_last_error(const cq_context* ctx);
  * added to a per-stage total.  Stage ids are small integers named by cq_stage_name.
  * Asynchronous calls are not timed. */
 #define CQ_MAX_STAGES 12
-/* enable != 0 turns timing on, 0 off; both reset the totals. */
+/* enable != 0 turns timing on for every stage, 0 off; both reset the totals. */
 cq_status cq_context_enable_timing(cq_context* ctx, int enable);
+/* Time only the stages whose bit (1 << stage id) is set in stage_mask (0: off); resets
+ * the totals.  Each timed stage adds two event records to the stream, which cost a few
+ * microseconds of device time, so a caller that needs one stage's duration times that
+ * stage alone. */
+cq_status cq_context_time_stages(cq_context* ctx, uint32_t stage_mask);
 /* Copy up to max_stages per-stage totals (milliseconds) and counts (timed calls
  * that ran the stage) into the HOST arrays total_ms[] and counts[]. */
 cq_status cq_context_stage_times(const cq_context* ctx, double* total_ms, int64_t* counts, int32_t max_stages);

@@ -1,7 +1,8 @@
 """Build step: compile the HIP sources into ``libcq.so`` (gfx950) next to this file.
 
-``python -m paper_1507_05492_amd.build`` or :func:`build` from Python.  hipcc
-cross-compiles for gfx950 without a GPU present.
+``python paper_1507_05492_amd/build.py`` or :func:`build` (load this file by path:
+importing it through the package runs the package's ``__init__``, which loads the
+library).  hipcc cross-compiles for gfx950 without a GPU present.
 """
 from __future__ import annotations
 

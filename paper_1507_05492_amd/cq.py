@@ -105,7 +105,7 @@ class GraphStats(ctypes.Structure):
 
 def _load():
     if not os.path.exists(LIB_PATH):
-        raise ImportError(f"{LIB_PATH} is missing: run `python -m paper_1507_05492_amd.build` (needs hipcc)")
+        raise ImportError(f"{LIB_PATH} is missing: run `python paper_1507_05492_amd/build.py` (needs hipcc)")
     L = ctypes.CDLL(LIB_PATH)
     sig = {
         "cq_status_string": (ctypes.c_char_p, [_I32]),
@@ -124,6 +124,7 @@ def _load():
         "cq_compare_partitions": (_I32, [_P, _I32, _P, _I32, _P, _I32, _P, _SZ, ctypes.POINTER(CompareResult), _P]),
         "cq_compare_partitions_async": (_I32, [_P, _I32, _P, _I32, _P, _I32, _P, _SZ, _P, _P]),
         "cq_context_enable_timing": (_I32, [_P, ctypes.c_int]),
+        "cq_context_time_stages": (_I32, [_P, ctypes.c_uint32]),
         "cq_context_stage_times": (_I32, [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_I64), _I32]),
         "cq_stage_name": (ctypes.c_char_p, [_I32]),
         "cq_batch_plan_create": (_I32, [_P, ctypes.POINTER(BatchTask), _I32, ctypes.c_uint32, ctypes.POINTER(_P)]),
@@ -196,6 +197,20 @@ def cq_context_enable_timing(ctx: int, enable: bool) -> None:
     st = _lib.cq_context_enable_timing(ctx, 1 if enable else 0)
     if st != CQ_OK:
         raise CQError(st)
+
+
+def cq_context_time_stages(ctx: int, stage_mask: int) -> None:
+    st = _lib.cq_context_time_stages(ctx, stage_mask)
+    if st != CQ_OK:
+        raise CQError(st)
+
+
+def stage_id(name: str) -> int:
+    """Stage id of a stage name (as cq_context_stage_times reports it)."""
+    for i in range(32):
+        if cq_stage_name(i) == name:
+            return i
+    raise KeyError(name)
 
 
 def cq_stage_name(s: int) -> str:

@@ -31,7 +31,7 @@ struct cq_context {
   u32* dscratch = nullptr; // 2 words used by graph checks
   char err[512] = {0};
   // stage timing
-  bool timing = false;
+  uint32_t timing = 0;  // bit s: stage s is bracketed by events
   hipEvent_t ev[2 * CQ_MAX_STAGES] = {};
   bool recorded[CQ_MAX_STAGES] = {};
   double total_ms[CQ_MAX_STAGES] = {};
@@ -144,7 +144,7 @@ struct StageMark {
   cq_context* ctx;
   int st;
   bool on;
-  StageMark(cq_context* c, int s, bool timed) : ctx(c), st(s), on(timed && c->timing) {
+  StageMark(cq_context* c, int s, bool timed) : ctx(c), st(s), on(timed && ((c->timing >> s) & 1u)) {
     if (on) (void)hipEventRecord(ctx->ev[2 * st], ctx->stream);
   }
   ~StageMark() {
@@ -1420,15 +1420,19 @@ void cq_context_destroy(cq_context* ctx) {
   delete ctx;
 }
 
-cq_status cq_context_enable_timing(cq_context* ctx, int enable) {
+cq_status cq_context_time_stages(cq_context* ctx, uint32_t stage_mask) {
   if (!ctx) return CQ_E_INVALID_ARG;
-  ctx->timing = enable != 0;
+  ctx->timing = stage_mask & ((1u << ST_COUNT) - 1u);
   for (int i = 0; i < CQ_MAX_STAGES; ++i) {
     ctx->total_ms[i] = 0.0;
     ctx->counts[i] = 0;
     ctx->recorded[i] = false;
   }
   return CQ_OK;
+}
+
+cq_status cq_context_enable_timing(cq_context* ctx, int enable) {
+  return cq_context_time_stages(ctx, enable ? ~0u : 0u);
 }
 
 cq_status cq_context_stage_times(const cq_context* ctx, double* total_ms, int64_t* counts, int32_t max_stages) {
