@@ -53,6 +53,24 @@ __device__ __forceinline__ double unfix96(u128 v) {
   return neg ? -d : d;
 }
 
+// The same truncation, floor(t * 2^96), for terms known to lie in [0, 1), accumulated as
+// three 32-bit limbs of the fraction in 64-bit words (fewer instructions than fix96).
+struct Frac96Sum {
+  u64 a = 0, b = 0, c = 0;
+  __device__ __forceinline__ void add(double t) {
+    const double x = t * 4294967296.0;  // 2^32
+    const u32 l0 = (u32)x;               // truncation; each remainder below is exact
+    const double y = (x - (double)l0) * 4294967296.0;
+    const u32 l1 = (u32)y;
+    const double z = (y - (double)l1) * 4294967296.0;
+    const u32 l2 = (u32)z;
+    a += l0;
+    b += l1;
+    c += l2;
+  }
+  __device__ __forceinline__ u128 value() const { return ((u128)a << 64) + ((u128)b << 32) + (u128)c; }
+};
+
 // ---- exact edge-weight sums --------------------------------------------------
 // A float32 weight w in [2^-32, 2^32] is its 24-bit significand times 2^(e - 150), e the
 // biased exponent (95 <= e <= 159), so w * 2^55 is the integer significand << (e - 95),

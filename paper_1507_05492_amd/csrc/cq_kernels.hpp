@@ -1663,13 +1663,13 @@ struct ScoreVis {
   long long ecap;
   Ctl* ctl;
   struct State {
-    u128 pen;
+    Frac96Sum pen;
     u32 np;
     u32 g;
     double denom;
   };
   __device__ void begin(State& st, u32 g) {
-    st.pen = 0;
+    st.pen = Frac96Sum();
     st.np = 0;
     st.g = g;
     st.denom = twom * (double)N[g];
@@ -1681,8 +1681,8 @@ struct ScoreVis {
       return;
     }
     double xd = (double)x;
-    double t = xd * xd / (st.denom * (double)N[j]);
-    st.pen += fix96(t);
+    double t = xd * xd / (st.denom * (double)N[j]);  // <= x / 2m <= 1/2
+    st.pen.add(t);
     if (j > st.g) {
       st.np += 1;
       if (ecap > 0) {
@@ -1695,7 +1695,7 @@ struct ScoreVis {
   // the caller's next barrier protects the LDS partials.
   __device__ void finish(State& st, u32 g) {
     __shared__ u64 r_lo[GBLOCK / 64], r_hi[GBLOCK / 64], r_np[GBLOCK / 64];
-    const u128 pen = wave_sum_u128(st.pen);
+    const u128 pen = wave_sum_u128(st.pen.value());
     const u64 np = wave_sum_u64(st.np);
     const int w = threadIdx.x >> 6;
     if ((threadIdx.x & 63) == 0) {
@@ -1756,23 +1756,6 @@ struct WeightSum {
   __device__ __forceinline__ u128 value() const { return ((u128)hi << 64) | lo; }
 };
 
-// Exact sum of terms t in [0, 1), each truncated to a multiple of 2^-96 (the value fix96
-// gives), kept as three 32-bit limbs of the fraction summed in 64-bit words.
-struct Frac96Sum {
-  u64 a = 0, b = 0, c = 0;
-  __device__ __forceinline__ void add(double t) {
-    const double x = t * 4294967296.0;  // 2^32
-    const u32 l0 = (u32)x;               // truncation
-    const double y = (x - (double)l0) * 4294967296.0;
-    const u32 l1 = (u32)y;
-    const double z = (y - (double)l1) * 4294967296.0;
-    const u32 l2 = (u32)z;
-    a += l0;
-    b += l1;
-    c += l2;
-  }
-  __device__ __forceinline__ u128 value() const { return ((u128)a << 64) + ((u128)b << 32) + (u128)c; }
-};
 
 // Calls f(label, weight) for every entry of a segment of labels and weights (both arrays
 // 16-byte aligned at index 0): 4 entries per load once the index is a multiple of 4.
