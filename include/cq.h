@@ -157,6 +157,11 @@ cq_status cq_graph_load_weighted(cq_context* ctx, int32_t n, int64_t nnz, const 
                                  const int32_t* d_col_idx, const float* d_weights, uint32_t flags,
                                  cq_graph** out);
 cq_status cq_graph_get_stats(const cq_graph* g, cq_graph_stats* out);
+/* Copy the stored node order of a graph loaded with CQ_GRAPH_REORDER into the DEVICE
+ * array d_order[n]: d_order[i] is the caller's id of the i-th stored node.  Enqueued on
+ * the context's stream (asynchronous).  CQ_E_INVALID_ARG if the graph was not
+ * renumbered or d_order is null. */
+cq_status cq_graph_copy_order(cq_context* ctx, const cq_graph* g, int32_t* d_order);
 void cq_graph_release(cq_graph* g);
 
 /* ---- scoring one partition (Section II-B) ---------------------------------- */

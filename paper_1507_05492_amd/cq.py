@@ -116,6 +116,7 @@ def _load():
         "cq_graph_load": (_I32, [_P, _I32, _I64, _P, _P, ctypes.c_uint32, ctypes.POINTER(_P)]),
         "cq_graph_load_weighted": (_I32, [_P, _I32, _I64, _P, _P, _P, ctypes.c_uint32, ctypes.POINTER(_P)]),
         "cq_graph_get_stats": (_I32, [_P, ctypes.POINTER(GraphStats)]),
+        "cq_graph_copy_order": (_I32, [_P, _P, _P]),
         "cq_graph_release": (None, [_P]),
         "cq_score_workspace_size": (_SZ, [_P, _I32]),
         "cq_score_partition": (_I32, [_P, _P, _P, _I32, _P, _SZ, ctypes.POINTER(ScoreResult), _P, _P]),
@@ -244,6 +245,10 @@ def cq_graph_load_weighted(ctx: int, n: int, nnz: int, d_row_ptr: int, d_col_idx
     out = _P()
     _check(ctx, _lib.cq_graph_load_weighted(ctx, n, nnz, d_row_ptr, d_col_idx, d_weights, flags, ctypes.byref(out)))
     return out.value
+
+
+def cq_graph_copy_order(ctx: int, g: int, d_order: int) -> None:
+    _check(ctx, _lib.cq_graph_copy_order(ctx, g, d_order))
 
 
 def cq_graph_get_stats(g: int) -> dict:
@@ -468,6 +473,12 @@ class Graph:
 
     def workspace_size(self, num_labels: int) -> int:
         return cq_score_workspace_size(self.handle, num_labels)
+
+    def order(self):
+        """int32 tensor: caller id of every stored node (graphs loaded with reorder=True)."""
+        out = _torch().empty(self.n, dtype=_torch().int32, device=self.row_ptr.device)
+        cq_graph_copy_order(self.ctx.handle, self.handle, out.data_ptr())
+        return out
 
     def close(self):
         if self.handle:

@@ -1556,6 +1556,16 @@ cq_status cq_graph_load_weighted(cq_context* ctx, int32_t n, int64_t nnz, const 
   return graph_load(ctx, n, nnz, d_row_ptr, d_col_idx, nnz > 0 ? d_weights : nullptr, flags, out);
 }
 
+cq_status cq_graph_copy_order(cq_context* ctx, const cq_graph* g, int32_t* d_order) {
+  if (!ctx) return CQ_E_INVALID_ARG;
+  ctx->err[0] = 0;
+  if (!g || !d_order) return fail(ctx, CQ_E_INVALID_ARG, "null graph or order array");
+  if (!g->perm) return fail(ctx, CQ_E_INVALID_ARG, "graph was loaded without CQ_GRAPH_REORDER");
+  const hipError_t e = hipMemcpyAsync(d_order, g->perm, 4 * (size_t)g->n, hipMemcpyDeviceToDevice, ctx->stream);
+  if (e != hipSuccess) return fail(ctx, CQ_E_DEVICE, "copying the order: %s", hipGetErrorString(e));
+  return CQ_OK;
+}
+
 cq_status cq_graph_get_stats(const cq_graph* g, cq_graph_stats* out) {
   if (!g || !out) return CQ_E_INVALID_ARG;
   out->n = g->n;

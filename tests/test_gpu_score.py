@@ -134,6 +134,24 @@ def test_hub_split_classes(cq, ctx):
         run_case(cq, ctx, rp, ci, lab, 8 * n, "star 20000 singletons, labels = 8i", reorder=order)
 
 
+def test_graph_order(cq, ctx):
+    # the stored order of a renumbered graph is a permutation of the caller's ids
+    rp, ci, lab, L = lfr_case("m100k_mu0.3", 11)
+    rp_t = torch.as_tensor(rp).cuda()
+    ci_t = torch.as_tensor(ci).cuda()
+    for order in ("blocked", "unblocked"):
+        note(f"stored order [{order} graph]")
+        g = open_graph(cq, ctx, rp_t, ci_t, order)
+        perm = g.order().cpu().numpy()
+        assert np.array_equal(np.sort(perm), np.arange(len(rp) - 1))
+        g.close()
+    g = open_graph(cq, ctx, rp_t, ci_t, "input")
+    with pytest.raises(cq.CQError) as e:
+        g.order()
+    assert e.value.status == cq.CQ_E_INVALID_ARG
+    g.close()
+
+
 @pytest.mark.parametrize("reorder", ORDERS)
 def test_errors(cq, ctx, reorder):
     rp, ci = erdos_renyi(50, 0.2, 1)
