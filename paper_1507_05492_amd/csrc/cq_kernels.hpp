@@ -1889,18 +1889,22 @@ __global__ void k_inv_sizes(int L, const u32* __restrict__ N, double* __restrict
 }
 
 // Comparison visitor: row i of the contingency table, column j, cell x = |c_i ∩ c'_j|.
+// The information terms need one logarithm per cell: with N = sum of the cells, the
+// rows summing to a_i and the columns to b_j,
+//   sum (x/N) log(x N / (a_i b_j)) = S + log N - S_a - S_b          (Eq. 2 numerator)
+//   sum (x/N) log(x^2 / (a_i b_j)) = 2 S - S_a - S_b                 (Eq. 1, negated)
+// where S = sum over cells of (x/N) log x, S_a = sum_i (a_i/N) log a_i, S_b likewise.
+// RXL[i] receives row i's part of S (fix96); S_a and S_b are summed in the final pass.
 struct CmpVis {
   static constexpr bool kHotIsGroup = false;
   const u32* A;   // |c_i|
   const u32* B;   // |c'_j|
   double Nd;
-  unsigned long long Nu;
   u32* COLMAX;
   u64* RA11;
   u32* RMAX;
   double* RF;
-  u64* RMI;
-  u64* RVI;
+  u64* RXL;
   int32_t* eci;
   int32_t* ecj;
   int64_t* ecnt;
@@ -1910,7 +1914,7 @@ struct CmpVis {
     u64 a11;
     u32 rmax;
     double fmax;
-    u128 mi, vi;
+    u128 xl;
     u32 g;
     u32 ai;
     u32 nz;
@@ -1919,8 +1923,7 @@ struct CmpVis {
     st.a11 = 0;
     st.rmax = 0;
     st.fmax = 0.0;
-    st.mi = 0;
-    st.vi = 0;
+    st.xl = 0;
     st.g = g;
     st.ai = A[g];
     st.nz = 0;
@@ -1931,10 +1934,7 @@ struct CmpVis {
     st.rmax = max(st.rmax, x);
     double f = 2.0 * (double)x / (double)((u64)st.ai + (u64)bj);   // Eq. 3 ratio
     st.fmax = f > st.fmax ? f : st.fmax;
-    double ab = (double)((u64)st.ai * (u64)bj);
-    double w = (double)x / Nd;
-    st.mi += fix96(w * log((double)((u64)x * Nu) / ab));           // Eq. 2 numerator term
-    st.vi += fix96(w * log((double)((u64)x * (u64)x) / ab));       // Eq. 1 term
+    st.xl += fix96((double)x / Nd * log((double)x));  // the cell's part of S
     atomicMax(&COLMAX[j], x);
     st.nz += 1;
     if (ecap > 0) {
@@ -1945,11 +1945,11 @@ struct CmpVis {
   // One barrier for all six reductions (see ScoreVis::finish).
   __device__ void finish(State& st, u32 g) {
     constexpr int NW = GBLOCK / 64;
-    __shared__ u64 r_mlo[NW], r_mhi[NW], r_vlo[NW], r_vhi[NW], r_a11[NW], r_nz[NW];
+    __shared__ u64 r_mlo[NW], r_mhi[NW], r_a11[NW], r_nz[NW];
     __shared__ u32 r_max[NW];
     __shared__ double r_f[NW];
     {
-      const u128 wm = wave_sum_u128(st.mi), wv = wave_sum_u128(st.vi);
+      const u128 wm = wave_sum_u128(st.xl);
       const u64 wa = wave_sum_u64(st.a11), wn = wave_sum_u64(st.nz);
       const u32 wx = wave_max_u32(st.rmax);
       const double wf = wave_max_f64(st.fmax);
@@ -1957,8 +1957,6 @@ struct CmpVis {
       if ((threadIdx.x & 63) == 0) {
         r_mlo[w] = (u64)wm;
         r_mhi[w] = (u64)(wm >> 64);
-        r_vlo[w] = (u64)wv;
-        r_vhi[w] = (u64)(wv >> 64);
         r_a11[w] = wa;
         r_nz[w] = wn;
         r_max[w] = wx;
@@ -1967,13 +1965,12 @@ struct CmpVis {
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-      u128 mi = 0, vi = 0;
+      u128 xl = 0;
       u64 a11 = 0, nz = 0;
       u32 rmax = 0;
       double fmax = 0.0;
       for (int i = 0; i < (int)(blockDim.x >> 6); ++i) {
-        mi += ((u128)r_mhi[i] << 64) | r_mlo[i];
-        vi += ((u128)r_vhi[i] << 64) | r_vlo[i];
+        xl += ((u128)r_mhi[i] << 64) | r_mlo[i];
         a11 += r_a11[i];
         nz += r_nz[i];
         rmax = max(rmax, r_max[i]);
@@ -1983,10 +1980,8 @@ struct CmpVis {
       RA11[g] = a11;
       RMAX[g] = rmax;
       RF[g] = fmax;
-      RMI[2 * (size_t)g] = (u64)mi;
-      RMI[2 * (size_t)g + 1] = (u64)(mi >> 64);
-      RVI[2 * (size_t)g] = (u64)vi;
-      RVI[2 * (size_t)g + 1] = (u64)(vi >> 64);
+      RXL[2 * (size_t)g] = (u64)xl;
+      RXL[2 * (size_t)g + 1] = (u64)(xl >> 64);
     }
   }
 };
@@ -2272,20 +2267,19 @@ __global__ void k_score_final2(int G, const ScorePart* __restrict__ parts, long 
 
 // comparison final reduction ------------------------------------------------
 struct CmpPart {
-  u64 Ka, Kb, a11, X, Y, smax, mi_lo, mi_hi, vi_lo, vi_hi;
-  double fsum, ha, hb, pad;
+  u64 Ka, Kb, a11, X, Y, smax, xl_lo, xl_hi, sa_lo, sa_hi, sb_lo, sb_hi;
+  double fsum, pad[3];
 };
 
 __global__ __launch_bounds__(FBLOCK) void k_cmp_final1(int La, int Lb, int Ga, const u32* __restrict__ A, const u32* __restrict__ B,
                                                        const u32* __restrict__ COLMAX, const u64* __restrict__ RA11,
                                                        const u32* __restrict__ RMAX, const double* __restrict__ RF,
-                                                       const u64* __restrict__ RMI, const u64* __restrict__ RVI, double Nd,
-                                                       CmpPart* __restrict__ parts) {
+                                                       const u64* __restrict__ RXL, double Nd, CmpPart* __restrict__ parts) {
   __shared__ u64 sh_lo[FBLOCK / 64], sh_hi[FBLOCK / 64];
   __shared__ double sh_d[FBLOCK / 64];
   u64 Ka = 0, Kb = 0, a11 = 0, X = 0, Y = 0, smax = 0;
-  u128 mi = 0, vi = 0;
-  double fsum = 0, ha = 0, hb = 0;
+  u128 xl = 0, sa = 0, sb = 0;  // S, S_a, S_b (see CmpVis)
+  double fsum = 0;
   if ((int)blockIdx.x < Ga) {  // rows: ground-truth communities
     const int R = (La + Ga - 1) / Ga;
     const int c0 = blockIdx.x * R, c1 = min(La, c0 + R);
@@ -2296,10 +2290,9 @@ __global__ __launch_bounds__(FBLOCK) void k_cmp_final1(int La, int Lb, int Ga, c
       a11 += RA11[i];
       smax += RMAX[i];
       X += (u64)ai * (u64)(ai - 1u) / 2u;
-      mi += ((u128)RMI[2 * (size_t)i + 1] << 64) | RMI[2 * (size_t)i];
-      vi += ((u128)RVI[2 * (size_t)i + 1] << 64) | RVI[2 * (size_t)i];
+      xl += ((u128)RXL[2 * (size_t)i + 1] << 64) | RXL[2 * (size_t)i];
       fsum += (double)ai * RF[i];
-      ha += (double)ai / Nd * log((double)ai / Nd);
+      sa += fix96((double)ai / Nd * log((double)ai));
     }
   } else {  // columns: detected communities
     const int Gb = gridDim.x - Ga;
@@ -2311,7 +2304,7 @@ __global__ __launch_bounds__(FBLOCK) void k_cmp_final1(int La, int Lb, int Ga, c
       Kb += 1;
       smax += COLMAX[j];
       Y += (u64)bj * (u64)(bj - 1u) / 2u;
-      hb += (double)bj / Nd * log((double)bj / Nd);
+      sb += fix96((double)bj / Nd * log((double)bj));
     }
   }
   CmpPart p;
@@ -2321,14 +2314,14 @@ __global__ __launch_bounds__(FBLOCK) void k_cmp_final1(int La, int Lb, int Ga, c
   p.X = block_sum_u64(X, sh_lo);
   p.Y = block_sum_u64(Y, sh_lo);
   p.smax = block_sum_u64(smax, sh_lo);
-  u128 t = block_sum_u128(mi, sh_lo, sh_hi);
-  p.mi_lo = (u64)t; p.mi_hi = (u64)(t >> 64);
-  t = block_sum_u128(vi, sh_lo, sh_hi);
-  p.vi_lo = (u64)t; p.vi_hi = (u64)(t >> 64);
+  u128 t = block_sum_u128(xl, sh_lo, sh_hi);
+  p.xl_lo = (u64)t; p.xl_hi = (u64)(t >> 64);
+  t = block_sum_u128(sa, sh_lo, sh_hi);
+  p.sa_lo = (u64)t; p.sa_hi = (u64)(t >> 64);
+  t = block_sum_u128(sb, sh_lo, sh_hi);
+  p.sb_lo = (u64)t; p.sb_hi = (u64)(t >> 64);
   p.fsum = block_sum_f64<FBLOCK / 64>(fsum, sh_d);
-  p.ha = block_sum_f64<FBLOCK / 64>(ha, sh_d);
-  p.hb = block_sum_f64<FBLOCK / 64>(hb, sh_d);
-  p.pad = 0;
+  p.pad[0] = p.pad[1] = p.pad[2] = 0;
   if (threadIdx.x == 0) parts[blockIdx.x] = p;
 }
 
@@ -2349,14 +2342,15 @@ __global__ void k_cmp_final2(int G, const CmpPart* __restrict__ parts, long long
                              CmpResultDev* __restrict__ out) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   u64 Ka = 0, Kb = 0, a11 = 0, X = 0, Y = 0, smax = 0;
-  u128 mi = 0, vi = 0;
-  double fsum = 0, ha = 0, hb = 0;
+  u128 xl = 0, sa = 0, sb = 0;
+  double fsum = 0;
   for (int b = 0; b < G; ++b) {
     const CmpPart p = parts[b];
     Ka += p.Ka; Kb += p.Kb; a11 += p.a11; X += p.X; Y += p.Y; smax += p.smax;
-    mi += ((u128)p.mi_hi << 64) | p.mi_lo;
-    vi += ((u128)p.vi_hi << 64) | p.vi_lo;
-    fsum += p.fsum; ha += p.ha; hb += p.hb;
+    xl += ((u128)p.xl_hi << 64) | p.xl_lo;
+    sa += ((u128)p.sa_hi << 64) | p.sa_lo;
+    sb += ((u128)p.sb_hi << 64) | p.sb_lo;
+    fsum += p.fsum;
   }
   const double Nd = (double)n;
   const u64 A = (u64)n * (u64)(n - 1) / 2u;
@@ -2367,9 +2361,15 @@ __global__ void k_cmp_final2(int G, const CmpPart* __restrict__ parts, long long
   r.a01 = (int64_t)(Y - a11);
   r.a00 = (int64_t)(A - X - Y + a11);
   r.A = (int64_t)A;
-  r.VI = -unfix96(vi);
+  // combined in fixed point before the one conversion (see CmpVis).  A side with one
+  // community has entropy 0 and shares no information: exactly, from the counts.
+  const double logN = log(Nd);
+  r.VI = -unfix96(2 * xl - sa - sb);
+  const double ha = Ka == 1 ? 0.0 : logN - unfix96(sa);  // H(C)
+  const double hb = Kb == 1 ? 0.0 : logN - unfix96(sb);  // H(C')
+  const double mi = (Ka == 1 || Kb == 1) ? 0.0 : unfix96(xl - sa - sb) + logN;
   const double den = ha + hb;
-  r.NMI = den != 0.0 ? -2.0 * unfix96(mi) / den : 1.0;
+  r.NMI = den != 0.0 ? 2.0 * mi / den : 1.0;
   r.F = fsum / Nd;
   r.NVD = 1.0 - (double)smax / (2.0 * Nd);
   r.RI = (double)(a11 + (A - X - Y + a11)) / (double)A;

@@ -258,7 +258,7 @@ ScoreLayout graph_score_layout(const cq_graph* g, int64_t L) {
 struct CmpLayout {
   bool privA, privB, small;  // small: detected labels fit 16 bits
   int chunk, W, Wb, Ga, Gb;
-  size_t ctl, A, B, start, order, COLMAX, RA11, RMAX, RF, RMI, RVI, SZ, loc, HN, HB, CB, parts, res, total;
+  size_t ctl, A, B, start, order, COLMAX, RA11, RMAX, RF, RXL, SZ, loc, HN, HB, CB, parts, res, total;
 };
 
 CmpLayout cmp_layout(int64_t n, int64_t La, int64_t Lb) {
@@ -281,8 +281,7 @@ CmpLayout cmp_layout(int64_t n, int64_t La, int64_t Lb) {
   s.RA11 = c.take(8 * La);
   s.RMAX = c.take(4 * La);
   s.RF = c.take(8 * La);
-  s.RMI = c.take(16 * La);
-  s.RVI = c.take(16 * La);
+  s.RXL = c.take(16 * La);
   s.SZ = s.privA ? 0 : c.take(8 * La);
   s.loc = c.take(4 * n);
   s.HN = s.privA ? c.take(4 * (size_t)s.W * La) : 0;
@@ -593,13 +592,11 @@ void compare_launch(cq_context* ctx, int32_t n, const int32_t* la, int32_t La, c
   vis.A = A;
   vis.B = B;
   vis.Nd = (double)n;
-  vis.Nu = (unsigned long long)n;
   vis.COLMAX = COLMAX;
   vis.RA11 = at<u64>(ws, lay.RA11);
   vis.RMAX = at<u32>(ws, lay.RMAX);
   vis.RF = at<double>(ws, lay.RF);
-  vis.RMI = at<u64>(ws, lay.RMI);
-  vis.RVI = at<u64>(ws, lay.RVI);
+  vis.RXL = at<u64>(ws, lay.RXL);
   vis.eci = cells ? cells->ci : nullptr;
   vis.ecj = cells ? cells->cj : nullptr;
   vis.ecnt = cells ? cells->count : nullptr;
@@ -615,8 +612,8 @@ void compare_launch(cq_context* ctx, int32_t n, const int32_t* la, int32_t La, c
   CmpPart* parts = at<CmpPart>(ws, lay.parts);
   {
     StageMark mk(ctx, ST_FINAL, timed);
-    k_cmp_final1<<<lay.Ga + lay.Gb, FBLOCK, 0, s>>>(La, Lb, lay.Ga, A, B, COLMAX, vis.RA11, vis.RMAX, vis.RF, vis.RMI,
-                                                   vis.RVI, (double)n, parts);
+    k_cmp_final1<<<lay.Ga + lay.Gb, FBLOCK, 0, s>>>(La, Lb, lay.Ga, A, B, COLMAX, vis.RA11, vis.RMAX, vis.RF, vis.RXL,
+                                                   (double)n, parts);
     k_cmp_final2<<<1, 64, 0, s>>>(lay.Ga + lay.Gb, parts, n, vis.ecap, ctl, d_out);
   }
 }
