@@ -1418,7 +1418,9 @@ __device__ void group_one(const LT* __restrict__ CB, const u32 base, const u32 l
   vis.begin(st, g);
   const u32 M = min(len, Lv);
   u32 hcap = pow2ceil_u32(max(64u, 2u * M));
-  const bool direct = (Lv <= lds_words) && (2u * hcap > Lv);
+  // direct when the whole table fits; a visitor with costly visits keeps small segments
+  // on the (shorter) hash table
+  const bool direct = (Lv <= lds_words) && (V::kDirectWhenFits || 2u * hcap > Lv);
   // 16-bit counters, two per LDS word, for label spaces up to twice the LDS budget
   const bool wide = !direct && Lv > lds_words && ((Lv + 7u) >> 3) * 4u <= lds_words && (4u * hcap > Lv);
   bool use_hash = !direct && !wide;
@@ -1652,6 +1654,7 @@ __device__ __forceinline__ u64 block_sum_u64(u64 x, u64* sh) {
 //               split-penalty sum (Eq. 9); pairs with j > g are counted (and exported).
 struct ScoreVis {
   static constexpr bool kHotIsGroup = true;
+  static constexpr bool kDirectWhenFits = true;
   const u32* N;
   double twom;
   u32* I;
@@ -1897,6 +1900,7 @@ __global__ void k_inv_sizes(int L, const u32* __restrict__ N, double* __restrict
 // RXL[i] receives row i's part of S (fix96); S_a and S_b are summed in the final pass.
 struct CmpVis {
   static constexpr bool kHotIsGroup = false;
+  static constexpr bool kDirectWhenFits = false;
   const u32* A;   // |c_i|
   const u32* B;   // |c'_j|
   double Nd;
