@@ -113,6 +113,8 @@ typedef struct {
   uint32_t weighted;   /* 1 for a graph registered with cq_graph_load_weighted */
   uint32_t pad;
   double total_weight; /* W: sum of the edge weights (|E| for an unweighted graph) */
+  int64_t clusters;        /* CQ_GRAPH_REORDER: label-propagation clusters the order groups (else 0) */
+  int64_t largest_cluster; /* nodes in the largest of them (else 0) */
 } cq_graph_stats;
 
 /*

@@ -100,7 +100,8 @@ CQ_BATCH_NO_GRAPH = 2
 class GraphStats(ctypes.Structure):
     _fields_ = [("n", _I64), ("nnz", _I64), ("m", _I64), ("max_degree", _I64), ("validated", ctypes.c_uint32),
                 ("reordered", ctypes.c_uint32), ("owned_bytes", _I64), ("weighted", ctypes.c_uint32),
-                ("pad", ctypes.c_uint32), ("total_weight", ctypes.c_double)]
+                ("pad", ctypes.c_uint32), ("total_weight", ctypes.c_double), ("clusters", _I64),
+                ("largest_cluster", _I64)]
 
 
 def _load():

@@ -186,13 +186,16 @@ __global__ void k_iota(int n, int32_t* __restrict__ a) {
 // One sweep: every node takes the label that occurs most often among (up to LP_CAP of)
 // its neighbours; ties go to the label with the smallest hash.  One wave per row.
 __global__ __launch_bounds__(256) void k_lp(int n, const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
-                                            const int32_t* __restrict__ lin, int32_t* __restrict__ lout) {
+                                            const int32_t* __restrict__ lin, int32_t* __restrict__ lout, int sweep) {
   const int lane = threadIdx.x & 63;
   const size_t wave = ((size_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const size_t nwaves = ((size_t)gridDim.x * blockDim.x) >> 6;
   for (size_t u = wave; u < (size_t)n; u += nwaves) {
     const int a = rp[u];
     const int deg = min(rp[u + 1] - a, LP_CAP);
+    // ties between labels: a fixed order of labels (sweep < 0), or one salted per node
+    // and sweep, so that no label wins every tie
+    const u32 salt = sweep < 0 ? 0u : (((u32)u * 0x85EBCA6Bu) ^ ((u32)sweep * 0xC2B2AE35u));
     if (deg == 0) {
       if (lane == 0) lout[u] = lin[u];
       continue;
@@ -221,18 +224,32 @@ __global__ __launch_bounds__(256) void k_lp(int n, const int32_t* __restrict__ r
 #pragma unroll
     for (int q = 0; q < LP_CAP / 64; ++q) {
       if (x[q] >= 0) {
-        const u64 key = ((u64)cnt[q] << 32) | (u64)(~((u32)x[q] * HMUL));
+        const u64 key = ((u64)cnt[q] << 32) | (u64)(~(((u32)x[q] ^ salt) * HMUL));
         best = key > best ? key : best;
       }
     }
     best = wave_max_u64(best);
-    if (lane == 0) lout[u] = (int32_t)((~(u32)best) * HINV);
+    if (lane == 0) lout[u] = (int32_t)(((~(u32)best) * HINV) ^ salt);
   }
 }
 
 __global__ void k_count_labels(int n, const int32_t* __restrict__ lab, u32* __restrict__ cnt) {
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < (size_t)n; i += (size_t)gridDim.x * blockDim.x)
     atomicAdd(&cnt[lab[i]], 1u);
+}
+
+// out[0] += number of non-empty clusters, out[1] = largest cluster (one atomic per wave)
+__global__ void k_cluster_stats(int n, const u32* __restrict__ cnt, u32* __restrict__ out) {
+  for (size_t b = (size_t)blockIdx.x * blockDim.x; b < (size_t)n; b += (size_t)gridDim.x * blockDim.x) {  // uniform
+    const size_t i = b + threadIdx.x;
+    const u32 c = i < (size_t)n ? cnt[i] : 0u;
+    const u64 nz = __ballot(c > 0);
+    const u32 mx = wave_max_u32(c);
+    if ((threadIdx.x & 63) == 0 && nz) {
+      atomicAdd(&out[0], (u32)__popcll(nz));
+      atomicMax(&out[1], mx);
+    }
+  }
 }
 
 // new id of node u = start[cluster] + arrival order inside the cluster

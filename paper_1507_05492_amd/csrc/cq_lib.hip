@@ -64,6 +64,7 @@ struct cq_graph {
   float* wb = nullptr;             // weights in column-block order (with colb)
   double total_w = 0.0;            // W, summed exactly at load
   FarTable far{};                  // per block: entry ranges of the rows outside its span
+  int64_t clusters = 0, largest_cluster = 0;  // of the locality order
   unsigned far_tiles = 0;          // most far-entry tiles of any block
   int64_t owned_bytes = 0;
   ~cq_graph() {
@@ -661,6 +662,7 @@ void scan_u32(const u32* in, u32* out, long long n, u32* tiles, hipStream_t s) {
 }
 
 constexpr int LP_SWEEPS = 10;
+constexpr int LP_SALTED_SWEEPS = 20;
 // Column blocks pay off while one block's labels (2 bytes per node) fit an XCD's L2, and
 // once all labels do not (below that the plain edge pass has more workgroups in flight).
 constexpr int64_t BLOCK_MAX_N = 16 << 20;
@@ -797,13 +799,43 @@ cq_status build_locality_order(cq_context* ctx, cq_graph* g, const int32_t* rp, 
   } else {
     const unsigned gw = grid_for((int64_t)n * 64, 256, 65535);  // one wave per row
     const unsigned gn = grid_for(n, 256, 8192);
+    // Two label propagations: ties broken in one fixed order of labels (LP_SWEEPS sweeps),
+    // and ties broken per node and sweep (LP_SALTED_SWEEPS).  The first settles fast on
+    // sparse graphs; the second gives purer clusters where it converges.  The order uses
+    // the one that ends with fewer clusters.
+    u32 cs[2] = {0, 0};
+    auto count_clusters = [&](const int32_t* lab) {
+      fill(cnt, (size_t)n + 1, 0, s);
+      k_count_labels<<<gn, 256, 0, s>>>(n, lab, cnt);
+      fill(ctx->dscratch, 2, 0, s);
+      k_cluster_stats<<<gn, 256, 0, s>>>(n, cnt, ctx->dscratch);
+      if (e == hipSuccess) e = hipMemcpyAsync(cs, ctx->dscratch, 8, hipMemcpyDeviceToHost, s);
+      if (e == hipSuccess) e = hipStreamSynchronize(s);
+    };
     k_iota<<<gn, 256, 0, s>>>(n, lpA);
     for (int it = 0; it < LP_SWEEPS; ++it) {
-      k_lp<<<gw, 256, 0, s>>>(n, rp, col, lpA, lpB);
+      k_lp<<<gw, 256, 0, s>>>(n, rp, col, lpA, lpB, -1);
       std::swap(lpA, lpB);
     }
-    fill(cnt, (size_t)n + 1, 0, s);
-    k_count_labels<<<gn, 256, 0, s>>>(n, lpA, cnt);
+    count_clusters(lpA);
+    const u32 plain_clusters = cs[0];
+    int32_t* sa = lpB;  // newid is free until the nodes are placed
+    int32_t* sb = newid;
+    k_iota<<<gn, 256, 0, s>>>(n, sa);
+    for (int it = 0; it < LP_SALTED_SWEEPS; ++it) {
+      k_lp<<<gw, 256, 0, s>>>(n, rp, col, sa, sb, it);
+      std::swap(sa, sb);
+    }
+    count_clusters(sa);
+    if (cs[0] < plain_clusters) {
+      // keep the salted labels in lpA; newid takes a free buffer
+      if (sa == newid) std::swap(newid, lpA);
+      else std::swap(lpB, lpA);
+    } else {
+      count_clusters(lpA);
+    }
+    g->clusters = cs[0];
+    g->largest_cluster = cs[1];
     scan_u32(cnt, start, n, tiles, s);
     fill(cnt, (size_t)n + 1, 0, s);
     k_place<<<gn, 256, 0, s>>>(n, lpA, start, cnt, newid, g->owned_perm);
@@ -1574,6 +1606,8 @@ cq_status cq_graph_get_stats(const cq_graph* g, cq_graph_stats* out) {
   out->weighted = g->w ? 1u : 0u;
   out->pad = 0;
   out->total_weight = g->w ? g->total_w : (double)(g->nnz / 2);
+  out->clusters = g->reordered ? g->clusters : 0;
+  out->largest_cluster = g->reordered ? g->largest_cluster : 0;
   out->owned_bytes = g->owned_bytes;
   return CQ_OK;
 }
