@@ -950,8 +950,12 @@ constexpr int BT_UNROLL = 8;     // entries in flight per thread
 constexpr int BT_HALO = 1024;    // OWN tiles keep labels of ids within this distance of their rows in LDS
 constexpr int BT_RPT = 4;                        // rows per thread in own-span tiles
 constexpr int BT_ROWS = BT_THREADS * BT_RPT;     // rows per own-span tile
-constexpr int FT_EPT = 8;                        // far entries per thread
+// Far entries per thread: few, since each is a random label read; weighted entries
+// carry a weight load as well and run best with fewer still.
+constexpr int FT_EPT = 4;
+constexpr int FT_EPT_W = 2;
 constexpr int FT_ENT = BT_THREADS * FT_EPT;      // far entries per tile
+constexpr int FT_ENT_W = BT_THREADS * FT_EPT_W;  // far entries per tile, weighted graphs
 constexpr int OWN_BUF = 1024;  // entries of another label an own-span tile keeps in LDS (compact staging)
 
 // Far entries of column block y: colb/rowb ranges [b[y][0], b[y][1]) (rows before span y)
@@ -1228,48 +1232,51 @@ __device__ void gather_own_tile(u32 y, u32 t, int n, int span, const u32* __rest
   }
 }
 
-// Far tile t of block y: FT_ENT consecutive entries of the block's far ranges.
+// Far tile t of block y: FT_ENT (weighted: FT_ENT_W) consecutive entries of the block's
+// far ranges.
 template <class LT, bool WT>
 __device__ void gather_far_tile(u32 y, u32 t, const FarTable& ft, const int32_t* __restrict__ colb,
                                 const int32_t* __restrict__ rowb, const LT* __restrict__ labx,
                                 const u32* __restrict__ start, const u32* __restrict__ D, u32* __restrict__ cursor,
                                 Ctl* __restrict__ ctl, LT* __restrict__ CB, const float* __restrict__ wb,
                                 float* __restrict__ CW, u32* lds, u32* s_w) {
+  constexpr int EPT = WT ? FT_EPT_W : FT_EPT;
+  constexpr u32 ENT = BT_THREADS * EPT;
   u32* s_rf = lds;                     // first entry of run q (tile-relative); s_rf[nruns] = entry count
-  u32* s_rb = lds + FT_ENT + 1;        // staged row labels, then label of run q, then its segment place
-  u32* s_cnt = lds + 2 * (FT_ENT + 1);  // compact: entries of run q with another label
+  u32* s_rb = lds + ENT + 1;        // staged row labels, then label of run q, then its segment place
+  u32* s_cnt = lds + 2 * (ENT + 1);  // compact: entries of run q with another label
   const u32 b0 = ft.b[y][0], b1 = ft.b[y][1], b2 = ft.b[y][2], b3 = ft.b[y][3];
-  const u32 t1 = (b1 - b0 + FT_ENT - 1) / FT_ENT;
+  const u32 t1 = (b1 - b0 + ENT - 1) / ENT;
   u32 e0, e1;
   if (t < t1) {
-    e0 = b0 + t * FT_ENT;
-    e1 = min(b1, e0 + FT_ENT);
+    e0 = b0 + t * ENT;
+    e1 = min(b1, e0 + ENT);
   } else {
-    e0 = b2 + (t - t1) * FT_ENT;
+    e0 = b2 + (t - t1) * ENT;
     if (e0 >= b3) return;
-    e1 = min(b3, e0 + FT_ENT);
+    e1 = min(b3, e0 + ENT);
   }
   const u32 ne = e1 - e0;
   const int tid = threadIdx.x;
-  const u32 i0 = (u32)tid * FT_EPT;  // this thread's entries i0 .. i0+FT_EPT-1 (tile-relative)
-  LT x[FT_EPT];
-  u32 lab[FT_EPT];
-  float wt[FT_EPT];
+  const u32 i0 = (u32)tid * EPT;  // this thread's entries i0 .. i0+EPT-1 (tile-relative)
+  LT x[EPT];
+  u32 lab[EPT];
+  float wt[EPT];
 #pragma unroll
-  for (int j = 0; j < FT_EPT; ++j) {
+  for (int j = 0; j < EPT; ++j) {
     const u32 e = e0 + min(i0 + (u32)j, ne - 1u);  // in bounds; entries past ne are masked below
     x[j] = labx[colb[e]];  // the neighbour labels are loaded now and used after the runs are placed
     lab[j] = (u32)labx[rowb[e]];
     if (WT) wt[j] = wb[e];
   }
 #pragma unroll
-  for (int j = 0; j < FT_EPT; ++j)
+  for (int j = 0; j < EPT; ++j)
     if (i0 + (u32)j < ne) s_rb[i0 + j] = lab[j];
   __syncthreads();
   u32 prev = (i0 > 0 && i0 - 1 < ne) ? s_rb[i0 - 1] : 0xFFFFFFFFu;
   u32 heads = 0;
 #pragma unroll
-  for (int j = 0; j < FT_EPT; ++j) {
+  for (int j = 0; j < EPT; ++j) {
     const u32 i = i0 + (u32)j;
     if (i < ne && (i == 0 || lab[j] != prev)) heads |= 1u << j;
     prev = lab[j];
@@ -1279,7 +1286,7 @@ __device__ void gather_far_tile(u32 y, u32 t, const FarTable& ft, const int32_t*
   {
     u32 q = q0;
 #pragma unroll
-    for (int j = 0; j < FT_EPT; ++j) {
+    for (int j = 0; j < EPT; ++j) {
       if (heads & (1u << j)) {
         s_rf[q] = i0 + (u32)j;
         s_rb[q] = lab[j];
@@ -1295,7 +1302,7 @@ __device__ void gather_far_tile(u32 y, u32 t, const FarTable& ft, const int32_t*
   auto for_entries = [&](auto&& f) {
     u32 q = q0;  // runs started up to entry i0 + j
 #pragma unroll
-    for (int j = 0; j < FT_EPT; ++j) {
+    for (int j = 0; j < EPT; ++j) {
       const u32 i = i0 + (u32)j;
       if (heads & (1u << j)) ++q;
       if (i < ne) f(j, i, q - 1u);  // entry i lies in the last run that starts at or before it

@@ -698,12 +698,13 @@ cq_status build_column_blocks(cq_context* ctx, cq_graph* g) {
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     // far-entry ranges of every block: rows [0, s0) and [s1, n), s0..s1 being its span
     g->far_tiles = 0;
+    const u32 ent = g->owned_w ? FT_ENT_W : FT_ENT;  // entries per far tile, as the gather kernel takes them
     for (int y = 0; y < COL_BLOCKS && e == hipSuccess; ++y) {
       const int64_t s0 = std::min<int64_t>(n, (int64_t)y * span), s1 = std::min<int64_t>(n, s0 + span);
       const int64_t at_row[4] = {0, s0, s1, n};
       for (int j = 0; j < 4 && e == hipSuccess; ++j)
         e = hipMemcpy(&g->far.b[y][j], g->rpb + (size_t)y * ((size_t)n + 1) + at_row[j], 4, hipMemcpyDeviceToHost);
-      const u32 t = (g->far.b[y][1] - g->far.b[y][0] + FT_ENT - 1) / FT_ENT + (g->far.b[y][3] - g->far.b[y][2] + FT_ENT - 1) / FT_ENT;
+      const u32 t = (g->far.b[y][1] - g->far.b[y][0] + ent - 1) / ent + (g->far.b[y][3] - g->far.b[y][2] + ent - 1) / ent;
       g->far_tiles = std::max(g->far_tiles, (unsigned)t);
     }
     if (e != hipSuccess) st = fail(ctx, CQ_E_DEVICE, "building column blocks: %s", hipGetErrorString(e));
