@@ -68,8 +68,31 @@ struct Frac96Sum {
     b += l1;
     c += l2;
   }
+  // t in [0, 2^20): the integer part joins the first limb as well
+  __device__ __forceinline__ void add_wide(double t) {
+    const double x = t * 4294967296.0;
+    const u64 l0 = (u64)x;
+    const double y = (x - (double)l0) * 4294967296.0;
+    const u32 l1 = (u32)y;
+    const double z = (y - (double)l1) * 4294967296.0;
+    const u32 l2 = (u32)z;
+    a += l0;
+    b += l1;
+    c += l2;
+  }
   __device__ __forceinline__ u128 value() const { return ((u128)a << 64) + ((u128)b << 32) + (u128)c; }
 };
+
+// 1/y for finite y >= 1: the hardware reciprocal estimate refined by two Newton-Raphson
+// steps (r <- r + r(1 - yr), each squaring the relative error), which leaves it within
+// about one unit in the last place; unlike a division it need not be correctly rounded.
+__device__ __forceinline__ double recip_nr(double y) {
+  double r = __builtin_amdgcn_rcp(y);
+  double e = __builtin_fma(-y, r, 1.0);
+  r = __builtin_fma(r, e, r);
+  e = __builtin_fma(-y, r, 1.0);
+  return __builtin_fma(r, e, r);
+}
 
 // ---- exact edge-weight sums --------------------------------------------------
 // A float32 weight w in [2^-32, 2^32] is its 24-bit significand times 2^(e - 150), e the

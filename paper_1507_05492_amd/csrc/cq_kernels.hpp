@@ -948,7 +948,7 @@ __global__ __launch_bounds__(GROWS) void k_gather(int n, const int32_t* __restri
 constexpr int BT_THREADS = 256;
 constexpr int BT_UNROLL = 8;     // entries in flight per thread
 constexpr int BT_HALO = 1024;    // OWN tiles keep labels of ids within this distance of their rows in LDS
-constexpr int BT_RPT = 4;                        // rows per thread in own-span tiles
+constexpr int BT_RPT = 2;                        // rows per thread in own-span tiles
 constexpr int BT_ROWS = BT_THREADS * BT_RPT;     // rows per own-span tile
 // Far entries per thread: few, since each is a random label read; weighted entries
 // carry a weight load as well and run best with fewer still.
@@ -1616,14 +1616,21 @@ __device__ void group_one(const LT* __restrict__ CB, const u32 base, const u32 l
       }
       for (u32 s = tid; s < hcap; s += GBLOCK) {
         u32 k = keys[s];
-        if (k != EMPTY) vis.visit(st, k, cnt[s]);
+        if (k != EMPTY) {
+          vis.visit(st, k, cnt[s]);
+          vis.settle(st);  // slots hold labels in an order the atomics chose
+        }
       }
       __syncthreads();
     }
     if (mine) atomicAdd(&s_hot, mine);
     __syncthreads();
-    if (tid == 0 && s_hot && hot < Lv) vis.visit(st, hot, s_hot);
+    if (tid == 0 && s_hot && hot < Lv) {
+      vis.visit(st, hot, s_hot);
+      vis.settle(st);
+    }
   }
+  vis.settle(st);  // direct and 16-bit tables: each thread met its labels in a fixed order
   vis.finish(st, g);
   __syncthreads();
 }
@@ -1691,12 +1698,14 @@ struct ScoreVis {
   Ctl* ctl;
   struct State {
     Frac96Sum pen;
+    double acc;  // terms not yet in pen
     u32 np;
     u32 g;
     double denom;
   };
   __device__ void begin(State& st, u32 g) {
     st.pen = Frac96Sum();
+    st.acc = 0.0;
     st.np = 0;
     st.g = g;
     st.denom = twom * (double)N[g];
@@ -1707,9 +1716,8 @@ struct ScoreVis {
       I[j] = x;
       return;
     }
-    double xd = (double)x;
-    double t = xd * xd / (st.denom * (double)N[j]);  // <= x / 2m <= 1/2
-    st.pen.add(t);
+    const double xd = (double)x;
+    st.acc += xd * xd * recip_nr(st.denom * (double)N[j]);  // a term <= x / 2m <= 1/2
     if (j > st.g) {
       st.np += 1;
       if (ecap > 0) {
@@ -1717,6 +1725,14 @@ struct ScoreVis {
         if ((long long)idx < ecap) { eci[idx] = (int32_t)st.g; ecj[idx] = (int32_t)j; ecnt[idx] = (int64_t)x; }
       }
     }
+  }
+  // Moves the thread's pending terms into the exact sum.  The group pass settles once per
+  // group where a thread visits its labels in a fixed order (the same binary64 sum on
+  // every run), and after each visit where the order varies, so results never depend on
+  // the order of atomics.
+  __device__ void settle(State& st) {
+    if (st.acc != 0.0) st.pen.add_wide(st.acc);  // at most 1/2 per visit
+    st.acc = 0.0;
   }
   // Reduces the threads' sums with one barrier (waves first, then the waves in order);
   // the caller's next barrier protects the LDS partials.
@@ -1847,6 +1863,7 @@ __device__ void group_one_w(const LT* __restrict__ CB, const float* __restrict__
   // second pass: weight sums and the weighted split penalty, every count now in the table.
   // Branch-free: an entry of label g adds 0 to the penalty, a label outside [0, Lv) (only
   // with a label error, which voids the result) reads slot g instead.
+  vis.settle(st);  // the table gave each thread its labels in a fixed order
   WeightSum sall, shot;
   Frac96Sum pw;
   const double kg = 1.0 / (wo.twoW * (double)vis.N[g]);
@@ -1956,6 +1973,7 @@ struct CmpVis {
     st.ai = A[g];
     st.nz = 0;
   }
+  __device__ void settle(State&) {}  // every visit adds exactly
   __device__ void visit(State& st, u32 j, u32 x) {
     const u32 bj = B[j];
     st.a11 += (u64)x * (u64)(x - 1u) / 2u;
