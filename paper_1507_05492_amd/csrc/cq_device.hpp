@@ -26,7 +26,7 @@ struct Ctl {
   u32 flags;
   u32 K;          // non-empty communities (filled by the scan kernel)
   u32 ticket;     // work-queue cursor of the per-community kernels
-  u32 pad0;
+  u32 dense_rows;  // node pass of column-blocked graphs: buckets that wrote histogram rows
   unsigned long long export_count;
   unsigned long long cells;   // non-zero contingency cells (comparison)
   unsigned long long pad1[4];

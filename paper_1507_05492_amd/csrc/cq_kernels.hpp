@@ -386,23 +386,61 @@ __global__ __launch_bounds__(256) void k_perm_count(int n, const int32_t* __rest
     if (h[i]) atomicAdd(&bcnt[i], h[i]);
 }
 
+// With lrank/spos (column-blocked graphs): the workgroup's slots in bucket order are
+// numbered 0 .. PERM_NODES-1 (its ranges of buckets 0, 1, ... one after the other);
+// lrank[u] is node u's number and spos[u0 + r] the slot numbered r, so a pass that puts
+// the chunk's labels in LDS by number writes them out to consecutive slots.
 __global__ __launch_bounds__(256) void k_perm_plan(int n, const int32_t* __restrict__ newid, int nb,
                                                    const u32* __restrict__ bstart, u32* __restrict__ bcur,
-                                                   u32* __restrict__ pos1, u32* __restrict__ tgt) {
-  __shared__ u32 h[PERM_MAX_BUCKETS];
+                                                   u32* __restrict__ pos1, u32* __restrict__ tgt,
+                                                   uint16_t* __restrict__ lrank, u32* __restrict__ spos) {
+  extern __shared__ u32 plan_sh[];
+  u32* h = plan_sh;        // counts, then the next slot of each range
+  u32* d = plan_sh + nb;   // first slot of range i minus the number of its first slot
+  __shared__ u32 s_part[256];
   for (int i = threadIdx.x; i < nb; i += blockDim.x) h[i] = 0;
   __syncthreads();
   const long long u0 = (long long)blockIdx.x * PERM_NODES, u1 = min((long long)n, u0 + PERM_NODES);
   for (long long u = u0 + threadIdx.x; u < u1; u += blockDim.x) atomicAdd(&h[(u32)newid[u] >> PERM_SHIFT], 1u);
   __syncthreads();
-  for (int i = threadIdx.x; i < nb; i += blockDim.x)
-    if (h[i]) h[i] = bstart[i] + atomicAdd(&bcur[i], h[i]);  // this workgroup's range in bucket i
+  // exclusive scan of the counts: thread t sums buckets [t*per, (t+1)*per)
+  const int per = (nb + (int)blockDim.x - 1) / (int)blockDim.x;
+  const int i0 = min(nb, (int)threadIdx.x * per), i1 = min(nb, i0 + per);
+  u32 part = 0;
+  for (int i = i0; i < i1; ++i) part += h[i];
+  s_part[threadIdx.x] = part;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    u32 run = 0;
+    for (int t = 0; t < (int)blockDim.x; ++t) {
+      const u32 x = s_part[t];
+      s_part[t] = run;
+      run += x;
+    }
+  }
+  __syncthreads();
+  {
+    u32 first = s_part[threadIdx.x];
+    for (int i = i0; i < i1; ++i) {
+      const u32 c = h[i];
+      const u32 base = c ? bstart[i] + atomicAdd(&bcur[i], c) : 0u;  // this workgroup's range in bucket i
+      d[i] = base - first;
+      h[i] = base;
+      first += c;
+    }
+  }
   __syncthreads();
   for (long long u = u0 + threadIdx.x; u < u1; u += blockDim.x) {
     const u32 v = (u32)newid[u];
-    const u32 p = atomicAdd(&h[v >> PERM_SHIFT], 1u);
+    const u32 b = v >> PERM_SHIFT;
+    const u32 p = atomicAdd(&h[b], 1u);
     pos1[u] = p;
     tgt[p] = v;
+    if (lrank) {
+      const u32 r = p - d[b];  // < PERM_NODES
+      lrank[u] = (uint16_t)r;
+      spos[u0 + r] = p;
+    }
   }
 }
 
@@ -459,6 +497,168 @@ __global__ __launch_bounds__(1024) void k_node_perm(int n, const int32_t* __rest
     HD[row + c] = hd[c];
   }
   if (threadIdx.x == 0 && s_bad) atomicOr(&ctl->flags, F_LABEL);
+}
+
+// Node pass of a column-blocked graph, in two kernels.  k_node_scatter moves the labels
+// from the caller's order into the plan's buckets (tmp[pos1[u]]), one workgroup per
+// PERM_NODES nodes, which own one range of every bucket: the labels go to LDS by their
+// number in the plan (lrank) and leave in slot order (spos), so neighbouring lanes write
+// neighbouring slots.  Its first threads also clear N and D.  k_perm_apply_count then
+// moves each bucket to the stored order and counts nodes and degrees per label there,
+// where the labels of a renumbered graph come in long runs.
+template <class LT>
+__global__ __launch_bounds__(1024) void k_node_scatter(int n, const int32_t* __restrict__ labels,
+                                                       const uint16_t* __restrict__ lrank, const u32* __restrict__ spos,
+                                                       int L, LT* __restrict__ tmp, u32* __restrict__ N, u32* __restrict__ D,
+                                                       Ctl* __restrict__ ctl) {
+  __shared__ LT s_lab[PERM_NODES];
+  for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < (size_t)L; c += (size_t)gridDim.x * blockDim.x) {
+    N[c] = 0;
+    D[c] = 0;
+  }
+  constexpr int U = PERM_NODES / 1024;
+  const long long u0 = (long long)blockIdx.x * PERM_NODES;
+  const u32 cnt = (u32)min((long long)PERM_NODES, (long long)n - u0);
+  int c[U];
+  u32 r[U];
+#pragma unroll
+  for (int k = 0; k < U; ++k) {
+    const long long u = min(u0 + k * 1024 + threadIdx.x, (long long)n - 1);  // in bounds; masked below
+    c[k] = labels[u];
+    r[k] = lrank[u];
+  }
+  u32 bad = 0;
+#pragma unroll
+  for (int k = 0; k < U; ++k) {
+    if ((u32)(k * 1024) + threadIdx.x < cnt) {
+      const bool ok = (u32)c[k] < (u32)L;
+      bad |= ok ? 0u : 1u;
+      s_lab[r[k]] = ok ? (LT)c[k] : LabelT<LT>::SENTINEL;
+    }
+  }
+  if (bad) atomicOr(&ctl->flags, F_LABEL);
+  __syncthreads();
+  // numbers 0 .. cnt-1 are the chunk's slots in increasing order within each range
+  for (u32 i = threadIdx.x; i < cnt; i += blockDim.x) tmp[spos[u0 + i]] = s_lab[i];
+}
+
+// Labels up to which k_perm_apply_count counts in LDS: 64 KB of 16-bit labels and two
+// 32-bit counters per label, with its few static words, stay within a CU's 160 KB.
+constexpr int APPLY_COUNT_MAX_L = 12224;
+// A bucket with at most this many distinct labels adds its counts to N and D with
+// global atomics; a denser one writes a histogram row instead (see k_colscan_rows).
+constexpr u32 FLUSH_MAX = 256;
+
+// Bucket b (one workgroup): labx[id] for its stored ids, as k_perm_apply, and per label
+// the number of its nodes and the sum of their degrees (rp: stored-order row_ptr).
+// Each thread takes 8 consecutive ids; a wave whose 512 ids carry one label adds them
+// with one LDS atomic per counter.  Sentinels (out-of-range labels) are not counted.
+__global__ __launch_bounds__(1024) void k_perm_apply_count(const u32* __restrict__ bstart, const u32* __restrict__ tgt,
+                                                           const uint16_t* __restrict__ tmp, uint16_t* __restrict__ labx,
+                                                           const int32_t* __restrict__ rp, int L, u32* __restrict__ N,
+                                                           u32* __restrict__ D, u32* __restrict__ HN, u32* __restrict__ HD,
+                                                           u32* __restrict__ rows, Ctl* __restrict__ ctl) {
+  extern __shared__ uint4 sl4[];
+  uint16_t* sl = reinterpret_cast<uint16_t*>(sl4);
+  u32* hn = reinterpret_cast<u32*>(sl4 + (1u << PERM_SHIFT) / 8u);
+  u32* hd = hn + L;
+  __shared__ u32 s_nz;
+  const int tid = threadIdx.x;
+  const u32 b = blockIdx.x, id0 = b << PERM_SHIFT;
+  const u32 j0 = bstart[b], j1 = bstart[b + 1];
+  for (int i = tid; i < 2 * L; i += blockDim.x) hn[i] = 0;
+  if (tid == 0) s_nz = 0;
+  constexpr int U = 8;
+  for (u32 jb = j0 + tid; jb < j1; jb += U * blockDim.x) {
+    u32 t[U];
+    uint16_t x[U];
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+      const u32 j = min(jb + (u32)k * blockDim.x, j1 - 1u);  // in bounds; masked below
+      t[k] = tgt[j];
+      x[k] = tmp[j];
+    }
+#pragma unroll
+    for (int k = 0; k < U; ++k)
+      if (jb + (u32)k * blockDim.x < j1) sl[t[k] - id0] = x[k];
+  }
+  __syncthreads();
+  // the bucket's ids [id0, id0 + cnt) are all present exactly once: write them in order
+  const u32 cnt = j1 - j0, nv = cnt / 8u;
+  uint4* dst = reinterpret_cast<uint4*>(labx + id0);  // id0 is a multiple of 2^PERM_SHIFT: 16-byte aligned
+  for (u32 v0 = 0; v0 < nv; v0 += blockDim.x) {  // the same trip count for every lane of a wave
+    const u32 i = v0 + (u32)tid;
+    const bool act = i < nv;
+    uint4 q = make_uint4(0u, 0u, 0u, 0u);
+    int r[9];
+    if (act) {
+      q = sl4[i];
+      dst[i] = q;
+      const int32_t* rr = rp + id0 + 8u * i;  // ids id0+8i .. id0+8i+7 and the next row start (<= n)
+#pragma unroll
+      for (int k = 0; k < 9; ++k) r[k] = rr[k];
+    } else {
+#pragma unroll
+      for (int k = 0; k < 9; ++k) r[k] = 0;
+    }
+    const u32 w4[4] = {q.x, q.y, q.z, q.w};
+    const u32 l0 = q.x & 0xFFFFu;
+    bool same = act;
+#pragma unroll
+    for (int k = 1; k < 8; ++k) same = same && ((w4[k >> 1] >> (16 * (k & 1))) & 0xFFFFu) == l0;
+    const u32 key = (same && l0 < (u32)L) ? l0 : 0xFFFFFFFFu;
+    const u32 k0 = __shfl(key, 0, 64);
+    if (__ballot(key == k0) == ~0ull && k0 != 0xFFFFFFFFu) {
+      const u64 ds = wave_sum_u64((u64)(u32)(r[8] - r[0]));
+      if ((tid & 63) == 0) {
+        atomicAdd(&hn[k0], 512u);
+        atomicAdd(&hd[k0], (u32)ds);
+      }
+    } else if (act) {
+      if (key != 0xFFFFFFFFu) {
+        atomicAdd(&hn[key], 8u);
+        atomicAdd(&hd[key], (u32)(r[8] - r[0]));
+      } else {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          const u32 lk = (w4[k >> 1] >> (16 * (k & 1))) & 0xFFFFu;
+          if (lk < (u32)L) {
+            atomicAdd(&hn[lk], 1u);
+            atomicAdd(&hd[lk], (u32)(r[k + 1] - r[k]));
+          }
+        }
+      }
+    }
+  }
+  for (u32 i = nv * 8u + tid; i < cnt; i += blockDim.x) {
+    const u32 lk = sl[i];
+    labx[id0 + i] = (uint16_t)lk;
+    if (lk < (u32)L) {
+      atomicAdd(&hn[lk], 1u);
+      atomicAdd(&hd[lk], (u32)(rp[id0 + i + 1] - rp[id0 + i]));
+    }
+  }
+  __syncthreads();
+  u32 nz = 0;
+  for (int c = tid; c < L; c += blockDim.x) nz += hn[c] ? 1u : 0u;
+  nz = (u32)wave_sum_u64(nz);
+  if ((tid & 63) == 0 && nz) atomicAdd(&s_nz, nz);
+  __syncthreads();
+  if (s_nz <= FLUSH_MAX) {
+    for (int c = tid; c < L; c += blockDim.x) {
+      if (hn[c]) {
+        atomicAdd(&N[c], hn[c]);
+        atomicAdd(&D[c], hd[c]);
+      }
+    }
+  } else {
+    const size_t row = (size_t)b * (size_t)L;
+    for (int c = tid; c < L; c += blockDim.x) {
+      HN[row + c] = hn[c];
+      HD[row + c] = hd[c];
+    }
+    if (tid == 0) rows[atomicAdd(&ctl->dense_rows, 1u)] = b;
+  }
 }
 
 // Caller-order pass without counting (labels beyond LDS, or a graph without column
@@ -782,6 +982,29 @@ __global__ __launch_bounds__(CS_LABELS * CS_GROUPS) void k_colscan(int W, int L,
     if (D) D[c] = td;
     if (zero64) zero64[c] = 0ull;
   }
+}
+
+// Column-blocked node pass: adds the histogram rows of the dense buckets (rows[0,
+// ctl->dense_rows), written by k_perm_apply_count) to N and D, and clears the 64-bit run
+// cursors.  Integer sums, so the order of the row list does not matter.
+__global__ __launch_bounds__(256) void k_colscan_rows(int L, const u32* __restrict__ HN, const u32* __restrict__ HD,
+                                                      const u32* __restrict__ rows, const Ctl* __restrict__ ctl,
+                                                      u32* __restrict__ N, u32* __restrict__ D,
+                                                      unsigned long long* __restrict__ zero64) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= L) return;
+  const u32 nd = ctl->dense_rows;
+  if (nd) {
+    u32 sn = 0, sd = 0;
+    for (u32 i = 0; i < nd; ++i) {
+      const size_t at = (size_t)rows[i] * (size_t)L + (size_t)c;
+      sn += HN[at];
+      sd += HD[at];
+    }
+    N[c] += sn;
+    D[c] += sd;
+  }
+  zero64[c] = 0ull;
 }
 
 __global__ void k_unpack(int L, const unsigned long long* __restrict__ SZ, u32* __restrict__ N, u32* __restrict__ D) {

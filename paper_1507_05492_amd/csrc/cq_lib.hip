@@ -57,6 +57,8 @@ struct cq_graph {
   u32* deg_in = nullptr;           // label permutation plan (caller order -> stored order): degrees,
   u32* pos1 = nullptr;             // bucket slots and their stored ids; null when not built
   u32* tgt = nullptr;
+  uint16_t* lrank = nullptr;       // column-blocked graphs: node numbers and slots of the plan's chunks
+  u32* spos = nullptr;
   u32* pbstart = nullptr;          // first slot of every bucket (nb + 1)
   int perm_buckets = 0;
   const float* w = nullptr;        // edge weights in the stored entry order (borrowed or owned_w); null: unweighted
@@ -76,6 +78,8 @@ struct cq_graph {
     if (rowb) (void)hipFree(rowb);
     for (u32* p : {deg_in, pos1, tgt, pbstart})
       if (p) (void)hipFree(p);
+    if (lrank) (void)hipFree(lrank);
+    if (spos) (void)hipFree(spos);
     if (owned_w) (void)hipFree(owned_w);
     if (wb) (void)hipFree(wb);
   }
@@ -209,7 +213,7 @@ unsigned colscan_grid(int64_t L) { return grid_for(L, CS_LABELS, 1u << 30); }
 struct ScoreLayout {
   bool priv, small;  // small: labels fit 16 bits (num_labels <= 65535)
   int chunk, W, G;
-  size_t ctl, N, D, start, order, I, NP, PEN, SZ, cursor, loc, HN, HD, labx, CB, parts, res, total;
+  size_t ctl, N, D, start, order, I, NP, PEN, SZ, cursor, loc, HN, HD, RL, labx, CB, parts, res, total;
   size_t CW, SW, IW, PENW, INVN;  // weighted graphs only (0 otherwise)
 };
 
@@ -235,6 +239,7 @@ ScoreLayout score_layout(int64_t n, int64_t nnz, int64_t L, bool weighted = fals
   s.loc = c.take(4 * n);
   s.HN = s.priv ? c.take(4 * (size_t)s.W * L) : 0;
   s.HD = s.priv ? c.take(4 * (size_t)s.W * L) : 0;
+  s.RL = c.take(4 * (size_t)(((n + (1 << PERM_SHIFT) - 1) >> PERM_SHIFT) + 1));  // dense-bucket rows of the node pass
   s.labx = c.take(lt * n);
   s.CB = c.take(lt * nnz);
   s.parts = c.take(std::max(sizeof(ScorePart), sizeof(WScorePart)) * s.G);
@@ -362,22 +367,41 @@ void score_launch(cq_context* ctx, const cq_graph* g, const int32_t* labels, int
     if (g->rpb && !(lay.priv && g->pos1)) fill(at<u32>(ws, lay.cursor), 2 * (size_t)L, 0, s);
   }
   if (lay.priv && g->rpb && g->pos1) {
-    // column-blocked graph: count in the caller's order, move labels with the bucket plan
-    // (the blocked edge pass needs no per-node offsets)
+    // column-blocked graph: move the labels with the bucket plan and count per label (the
+    // blocked edge pass needs no per-node offsets)
     u32* HN = at<u32>(ws, lay.HN);
     u32* HD = at<u32>(ws, lay.HD);
     LT* tmp = reinterpret_cast<LT*>(loc);  // per-node offsets are not used on this path
-    {
-      StageMark mk(ctx, ST_NODE, timed);
-      k_node_perm<LT><<<lay.W, 1024, 2 * (size_t)L * 4, s>>>((int)n, labels, g->deg_in, g->pos1, L, lay.chunk, HN, HD, tmp,
-                                                             ctl);
-      k_perm_apply<LT><<<g->perm_buckets, 1024, ((size_t)1 << PERM_SHIFT) * sizeof(LT), s>>>((int)n, g->pbstart, g->tgt, tmp,
-                                                                                          labx);
-    }
-    {
-      StageMark mk(ctx, ST_COLSCAN, timed);
-      k_colscan<true, false><<<colscan_grid(L), CS_LABELS * CS_GROUPS, 0, s>>>(lay.W, L, HN, HD, N, D,
-                                                                          at<unsigned long long>(ws, lay.cursor));
+    if (sizeof(LT) == 2 && L <= APPLY_COUNT_MAX_L && g->lrank) {
+      // count in the stored order while moving the labels there (labels come in runs)
+      u32* rows = at<u32>(ws, lay.RL);
+      {
+        StageMark mk(ctx, ST_NODE, timed);
+        const unsigned gs = (unsigned)(((int64_t)n + PERM_NODES - 1) / PERM_NODES);  // the plan's chunks
+        k_node_scatter<LT><<<gs, 1024, 0, s>>>((int)n, labels, g->lrank, g->spos, L, tmp, N, D, ctl);
+        k_perm_apply_count<<<g->perm_buckets, 1024, ((size_t)1 << PERM_SHIFT) * 2 + 8 * (size_t)L, s>>>(
+            g->pbstart, g->tgt, reinterpret_cast<const uint16_t*>(tmp), reinterpret_cast<uint16_t*>(labx), g->rp, L, N, D, HN, HD,
+            rows, ctl);
+      }
+      {
+        StageMark mk(ctx, ST_COLSCAN, timed);
+        k_colscan_rows<<<grid_for(L, 256, 1u << 30), 256, 0, s>>>(L, HN, HD, rows, ctl, N, D,
+                                                                  at<unsigned long long>(ws, lay.cursor));
+      }
+    } else {
+      // more labels than LDS holds beside a bucket: count in the caller's order
+      {
+        StageMark mk(ctx, ST_NODE, timed);
+        k_node_perm<LT><<<lay.W, 1024, 2 * (size_t)L * 4, s>>>((int)n, labels, g->deg_in, g->pos1, L, lay.chunk, HN, HD, tmp,
+                                                               ctl);
+        k_perm_apply<LT><<<g->perm_buckets, 1024, ((size_t)1 << PERM_SHIFT) * sizeof(LT), s>>>((int)n, g->pbstart, g->tgt, tmp,
+                                                                                            labx);
+      }
+      {
+        StageMark mk(ctx, ST_COLSCAN, timed);
+        k_colscan<true, false><<<colscan_grid(L), CS_LABELS * CS_GROUPS, 0, s>>>(lay.W, L, HN, HD, N, D,
+                                                                            at<unsigned long long>(ws, lay.cursor));
+      }
     }
     PM = HD;
   } else if (lay.priv) {
@@ -740,6 +764,10 @@ cq_status build_perm_plan(cq_context* ctx, cq_graph* g, const int32_t* newid, co
   alloc((void**)&g->pos1, 4 * (size_t)n);
   alloc((void**)&g->tgt, 4 * (size_t)n);
   alloc((void**)&g->pbstart, 4 * ((size_t)nb + 1));
+  if (g->rpb) {
+    alloc((void**)&g->lrank, 2 * (size_t)n);
+    alloc((void**)&g->spos, 4 * (size_t)n);
+  }
   alloc((void**)&bcnt, 4 * ((size_t)nb + 1));
   u32* bstart = g->pbstart;
   alloc((void**)&tiles, 4 * ((size_t)((nb + SCAN_TILE - 1) / SCAN_TILE) + 1));
@@ -754,7 +782,7 @@ cq_status build_perm_plan(cq_context* ctx, cq_graph* g, const int32_t* newid, co
     k_perm_count<<<gp, 256, 0, s>>>(n, newid, nb, bcnt);
     scan_u32(bcnt, bstart, nb, tiles, s);
     fill(bcnt, (size_t)nb + 1, 0, s);
-    k_perm_plan<<<gp, 256, 0, s>>>(n, newid, nb, bstart, bcnt, g->pos1, g->tgt);
+    k_perm_plan<<<gp, 256, 8 * (size_t)nb, s>>>(n, newid, nb, bstart, bcnt, g->pos1, g->tgt, g->lrank, g->spos);
     e = hipGetLastError();
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) st = fail(ctx, CQ_E_DEVICE, "building the label permutation plan: %s", hipGetErrorString(e));
@@ -762,10 +790,12 @@ cq_status build_perm_plan(cq_context* ctx, cq_graph* g, const int32_t* newid, co
   for (void* p : {(void*)bcnt, (void*)tiles})
     if (p) (void)hipFree(p);
   if (st != CQ_OK) {
-    for (u32** p : {&g->deg_in, &g->pos1, &g->tgt, &g->pbstart}) {
+    for (u32** p : {&g->deg_in, &g->pos1, &g->tgt, &g->pbstart, &g->spos}) {
       if (*p) (void)hipFree(*p);
       *p = nullptr;
     }
+    if (g->lrank) (void)hipFree(g->lrank);
+    g->lrank = nullptr;
   } else {
     g->perm_buckets = nb;
   }
@@ -860,6 +890,7 @@ cq_status build_locality_order(cq_context* ctx, cq_graph* g, const int32_t* rp, 
     g->owned_bytes = (int64_t)(4 * ((size_t)n + 1) + 4 * (size_t)nnz + 4 * (size_t)n);
     if (g->rpb) g->owned_bytes += (int64_t)(4 * ((size_t)COL_BLOCKS * ((size_t)n + 1) + 1) + 8 * (size_t)nnz);
     if (g->pos1) g->owned_bytes += (int64_t)(12 * (size_t)n + 4 * ((size_t)g->perm_buckets + 1));
+    if (g->lrank) g->owned_bytes += (int64_t)(6 * (size_t)n);
     if (g->owned_w) g->owned_bytes += (int64_t)(4 * (size_t)nnz);
     if (g->wb) g->owned_bytes += (int64_t)(4 * (size_t)nnz);
   }
@@ -1423,6 +1454,8 @@ cq_status cq_context_create(int device, void* hip_stream, cq_context** out) {
   set_big_lds(reinterpret_cast<const void*>(k_node_priv<true, uint32_t, true>), 2 * PRIV_MAX * 4);
   set_big_lds(reinterpret_cast<const void*>(k_node_priv<false, uint32_t>), PRIV_MAX * 4);
   set_big_lds(reinterpret_cast<const void*>(k_hist_priv), PRIV_MAX * 4);
+  set_big_lds(reinterpret_cast<const void*>(k_perm_plan), 8 * (size_t)PERM_MAX_BUCKETS);
+  set_big_lds(reinterpret_cast<const void*>(k_perm_apply_count), ((size_t)1 << PERM_SHIFT) * 2 + 8 * (size_t)APPLY_COUNT_MAX_L);
   set_big_lds(reinterpret_cast<const void*>(k_groups<ScoreVis, uint16_t>), gl);
   set_big_lds(reinterpret_cast<const void*>(k_groups_w<uint16_t>), gl);
   set_big_lds(reinterpret_cast<const void*>(k_groups_w<uint32_t>), gl);
