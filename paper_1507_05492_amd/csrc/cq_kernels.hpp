@@ -1757,12 +1757,34 @@ __device__ void group_one(const LT* __restrict__ CB, const u32 base, const u32 l
     if (mine) atomicAdd(&s_hot, mine);
     __syncthreads();
     if (tid == 0 && s_hot && hot < Lv) vis.visit(st, hot, s_hot);
-    for (u32 q = tid; q < nq; q += GBLOCK) {
-      const uint4 x = tab4[q];
-      if (x.x) vis.visit(st, 4u * q, x.x);
-      if (x.y) vis.visit(st, 4u * q + 1u, x.y);
-      if (x.z) vis.visit(st, 4u * q + 2u, x.z);
-      if (x.w) vis.visit(st, 4u * q + 3u, x.w);
+    if constexpr (V::kSizesAhead) {
+      // the sizes |j| of two table words' labels are loaded before their visits, so
+      // that the loads overlap; N is read as 16-byte words up to the table's padding
+      // (workspace arrays are 16-byte aligned and padded to 256 bytes)
+      const uint4* N4 = reinterpret_cast<const uint4*>(vis.N);
+      for (u32 q0 = tid; q0 < nq; q0 += 2u * GBLOCK) {
+        const u32 q1 = q0 + GBLOCK;
+        const uint4 n0 = N4[q0];
+        uint4 n1 = make_uint4(0u, 0u, 0u, 0u);
+        if (q1 < nq) n1 = N4[q1];
+        auto visit4 = [&](u32 q, const uint4& nv) {
+          const uint4 x = tab4[q];
+          if (x.x) vis.visit_n(st, 4u * q, x.x, nv.x);
+          if (x.y) vis.visit_n(st, 4u * q + 1u, x.y, nv.y);
+          if (x.z) vis.visit_n(st, 4u * q + 2u, x.z, nv.z);
+          if (x.w) vis.visit_n(st, 4u * q + 3u, x.w, nv.w);
+        };
+        visit4(q0, n0);
+        if (q1 < nq) visit4(q1, n1);
+      }
+    } else {
+      for (u32 q = tid; q < nq; q += GBLOCK) {
+        const uint4 x = tab4[q];
+        if (x.x) vis.visit(st, 4u * q, x.x);
+        if (x.y) vis.visit(st, 4u * q + 1u, x.y);
+        if (x.z) vis.visit(st, 4u * q + 2u, x.z);
+        if (x.w) vis.visit(st, 4u * q + 3u, x.w);
+      }
     }
   }
   if (use_hash) {
@@ -1909,6 +1931,7 @@ __device__ __forceinline__ u64 block_sum_u64(u64 x, u64* sh) {
 struct ScoreVis {
   static constexpr bool kHotIsGroup = true;
   static constexpr bool kDirectWhenFits = true;
+  static constexpr bool kSizesAhead = true;  // visit_n: N (L entries, padded to 16 bytes) read as 16-byte words
   const u32* N;
   double twom;
   u32* I;
@@ -1934,13 +1957,15 @@ struct ScoreVis {
     st.denom = twom * (double)N[g];
     if (threadIdx.x == 0) I[g] = 0;  // overwritten by the thread that meets label g
   }
-  __device__ void visit(State& st, u32 j, u32 x) {
+  __device__ void visit(State& st, u32 j, u32 x) { visit_n(st, j, x, N[j]); }
+  // the same with |j| = nj already loaded
+  __device__ void visit_n(State& st, u32 j, u32 x, u32 nj) {
     if (j == st.g) {
       I[j] = x;
       return;
     }
     const double xd = (double)x;
-    st.acc += xd * xd * recip_nr(st.denom * (double)N[j]);  // a term <= x / 2m <= 1/2
+    st.acc += xd * xd * recip_nr(st.denom * (double)nj);  // a term <= x / 2m <= 1/2
     if (j > st.g) {
       st.np += 1;
       if (ecap > 0) {
@@ -2165,6 +2190,7 @@ __global__ void k_inv_sizes(int L, const u32* __restrict__ N, double* __restrict
 struct CmpVis {
   static constexpr bool kHotIsGroup = false;
   static constexpr bool kDirectWhenFits = false;
+  static constexpr bool kSizesAhead = false;
   const u32* A;   // |c_i|
   const u32* B;   // |c'_j|
   double Nd;
