@@ -137,7 +137,7 @@ typedef struct {
  * When 2^20 <= n <= 2^24 the copy is also kept as 8 column blocks, one per XCD of the
  * device (the edge pass then reads each neighbour label from one XCD's L2; below 2^20
  * nodes one L2 holds all labels anyway), with a plan that moves labels from the
- * caller's order to the stored one: a further 4(8(n+1)+1) + 8 nnz + 18n + 4(n/32768 + 2)
+ * caller's order to the stored one: a further 4(8(n+1)+1) + 8 nnz + 16n + 4(n/32768 + 2)
  * bytes.  CQ_GRAPH_NO_BLOCKS never builds them, CQ_GRAPH_BLOCKS builds them for any
  * n <= 2^24 (both flags at once: CQ_E_INVALID_ARG).  owned_bytes in cq_graph_stats
  * reports the total.

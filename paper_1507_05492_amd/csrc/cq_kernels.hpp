@@ -365,9 +365,10 @@ struct LabelT {
 // whole cache line per label, so the move is done in two streaming passes instead:
 // node u (caller order) first writes its label to tmp[pos1[u]], where tmp is grouped
 // into buckets of 2^PERM_SHIFT stored ids (bucket b = newid >> PERM_SHIFT); then one
-// workgroup per bucket copies every slot j of the bucket to labx[tgt[j]] through LDS
-// (the bucket's labels fit there) and writes the bucket's labels out in order.  The
-// order inside a bucket is whatever the atomics gave.
+// workgroup per bucket copies every slot j of bucket b to labx[b * 2^PERM_SHIFT + tgt[j]]
+// through LDS (the bucket's labels fit there; tgt holds the 16-bit offset of the stored
+// id in its bucket) and writes the bucket's labels out in order.  The order inside a
+// bucket is whatever the atomics gave.
 constexpr int PERM_SHIFT = 15;  // 32768 stored ids per bucket: 64 KB of 16-bit labels
 
 // Each workgroup counts its nodes per bucket in LDS, reserves a range of every bucket
@@ -392,7 +393,7 @@ __global__ __launch_bounds__(256) void k_perm_count(int n, const int32_t* __rest
 // the chunk's labels in LDS by number writes them out to consecutive slots.
 __global__ __launch_bounds__(256) void k_perm_plan(int n, const int32_t* __restrict__ newid, int nb,
                                                    const u32* __restrict__ bstart, u32* __restrict__ bcur,
-                                                   u32* __restrict__ pos1, u32* __restrict__ tgt,
+                                                   u32* __restrict__ pos1, uint16_t* __restrict__ tgt,
                                                    uint16_t* __restrict__ lrank, u32* __restrict__ spos) {
   extern __shared__ u32 plan_sh[];
   u32* h = plan_sh;        // counts, then the next slot of each range
@@ -435,7 +436,7 @@ __global__ __launch_bounds__(256) void k_perm_plan(int n, const int32_t* __restr
     const u32 b = v >> PERM_SHIFT;
     const u32 p = atomicAdd(&h[b], 1u);
     pos1[u] = p;
-    tgt[p] = v;
+    tgt[p] = (uint16_t)(v & ((1u << PERM_SHIFT) - 1u));
     if (lrank) {
       const u32 r = p - d[b];  // < PERM_NODES
       lrank[u] = (uint16_t)r;
@@ -553,7 +554,7 @@ constexpr u32 FLUSH_MAX = 256;
 // the number of its nodes and the sum of their degrees (rp: stored-order row_ptr).
 // Each thread takes 8 consecutive ids; a wave whose 512 ids carry one label adds them
 // with one LDS atomic per counter.  Sentinels (out-of-range labels) are not counted.
-__global__ __launch_bounds__(1024) void k_perm_apply_count(const u32* __restrict__ bstart, const u32* __restrict__ tgt,
+__global__ __launch_bounds__(1024) void k_perm_apply_count(const u32* __restrict__ bstart, const uint16_t* __restrict__ tgt,
                                                            const uint16_t* __restrict__ tmp, uint16_t* __restrict__ labx,
                                                            const int32_t* __restrict__ rp, int L, u32* __restrict__ N,
                                                            u32* __restrict__ D, u32* __restrict__ HN, u32* __restrict__ HD,
@@ -580,7 +581,7 @@ __global__ __launch_bounds__(1024) void k_perm_apply_count(const u32* __restrict
     }
 #pragma unroll
     for (int k = 0; k < U; ++k)
-      if (jb + (u32)k * blockDim.x < j1) sl[t[k] - id0] = x[k];
+      if (jb + (u32)k * blockDim.x < j1) sl[t[k]] = x[k];
   }
   __syncthreads();
   // the bucket's ids [id0, id0 + cnt) are all present exactly once: write them in order
@@ -690,7 +691,7 @@ __global__ __launch_bounds__(256) void k_perm_scatter(int n, const int32_t* __re
 }
 
 template <class LT>
-__global__ __launch_bounds__(1024) void k_perm_apply(int n, const u32* __restrict__ bstart, const u32* __restrict__ tgt,
+__global__ __launch_bounds__(1024) void k_perm_apply(int n, const u32* __restrict__ bstart, const uint16_t* __restrict__ tgt,
                                                      const LT* __restrict__ tmp, LT* __restrict__ labx) {
   extern __shared__ uint4 sl4[];
   LT* sl = reinterpret_cast<LT*>(sl4);
@@ -708,7 +709,7 @@ __global__ __launch_bounds__(1024) void k_perm_apply(int n, const u32* __restric
     }
 #pragma unroll
     for (int k = 0; k < U; ++k)
-      if (jb + (u32)k * blockDim.x < j1) sl[t[k] - id0] = x[k];
+      if (jb + (u32)k * blockDim.x < j1) sl[t[k]] = x[k];
   }
   __syncthreads();
   // the bucket's ids [id0, id0 + cnt) are all present exactly once: write them in order

@@ -56,7 +56,7 @@ struct cq_graph {
   int32_t* rowb = nullptr;
   u32* deg_in = nullptr;           // label permutation plan (caller order -> stored order): degrees,
   u32* pos1 = nullptr;             // bucket slots and their stored ids; null when not built
-  u32* tgt = nullptr;
+  uint16_t* tgt = nullptr;         // offset of the slot's stored id in its bucket
   uint16_t* lrank = nullptr;       // column-blocked graphs: node numbers and slots of the plan's chunks
   u32* spos = nullptr;
   u32* pbstart = nullptr;          // first slot of every bucket (nb + 1)
@@ -76,8 +76,9 @@ struct cq_graph {
     if (rpb) (void)hipFree(rpb);
     if (colb) (void)hipFree(colb);
     if (rowb) (void)hipFree(rowb);
-    for (u32* p : {deg_in, pos1, tgt, pbstart})
+    for (u32* p : {deg_in, pos1, pbstart})
       if (p) (void)hipFree(p);
+    if (tgt) (void)hipFree(tgt);
     if (lrank) (void)hipFree(lrank);
     if (spos) (void)hipFree(spos);
     if (owned_w) (void)hipFree(owned_w);
@@ -762,7 +763,7 @@ cq_status build_perm_plan(cq_context* ctx, cq_graph* g, const int32_t* newid, co
   };
   alloc((void**)&g->deg_in, 4 * (size_t)n);
   alloc((void**)&g->pos1, 4 * (size_t)n);
-  alloc((void**)&g->tgt, 4 * (size_t)n);
+  alloc((void**)&g->tgt, 2 * (size_t)n);
   alloc((void**)&g->pbstart, 4 * ((size_t)nb + 1));
   if (g->rpb) {
     alloc((void**)&g->lrank, 2 * (size_t)n);
@@ -790,12 +791,14 @@ cq_status build_perm_plan(cq_context* ctx, cq_graph* g, const int32_t* newid, co
   for (void* p : {(void*)bcnt, (void*)tiles})
     if (p) (void)hipFree(p);
   if (st != CQ_OK) {
-    for (u32** p : {&g->deg_in, &g->pos1, &g->tgt, &g->pbstart, &g->spos}) {
+    for (u32** p : {&g->deg_in, &g->pos1, &g->pbstart, &g->spos}) {
       if (*p) (void)hipFree(*p);
       *p = nullptr;
     }
-    if (g->lrank) (void)hipFree(g->lrank);
-    g->lrank = nullptr;
+    for (uint16_t** p : {&g->tgt, &g->lrank}) {
+      if (*p) (void)hipFree(*p);
+      *p = nullptr;
+    }
   } else {
     g->perm_buckets = nb;
   }
@@ -889,7 +892,7 @@ cq_status build_locality_order(cq_context* ctx, cq_graph* g, const int32_t* rp, 
     g->reordered = CQ_GRAPH_REORDER | (g->rpb ? 0u : CQ_GRAPH_NO_BLOCKS);
     g->owned_bytes = (int64_t)(4 * ((size_t)n + 1) + 4 * (size_t)nnz + 4 * (size_t)n);
     if (g->rpb) g->owned_bytes += (int64_t)(4 * ((size_t)COL_BLOCKS * ((size_t)n + 1) + 1) + 8 * (size_t)nnz);
-    if (g->pos1) g->owned_bytes += (int64_t)(12 * (size_t)n + 4 * ((size_t)g->perm_buckets + 1));
+    if (g->pos1) g->owned_bytes += (int64_t)(10 * (size_t)n + 4 * ((size_t)g->perm_buckets + 1));
     if (g->lrank) g->owned_bytes += (int64_t)(6 * (size_t)n);
     if (g->owned_w) g->owned_bytes += (int64_t)(4 * (size_t)nnz);
     if (g->wb) g->owned_bytes += (int64_t)(4 * (size_t)nnz);
