@@ -2313,8 +2313,6 @@ struct PerComm {
 __device__ void score_final1_body(int L, const u32* __restrict__ N, const u32* __restrict__ D, const u32* __restrict__ I,
                                   const u32* __restrict__ NP, const u64* __restrict__ PEN, double twom, const PerComm& pc,
                                   ScorePart* __restrict__ parts, int blk, int G) {
-  __shared__ u64 sh_lo[FBLOCK / 64], sh_hi[FBLOCK / 64];
-  __shared__ double sh_d[FBLOCK / 64];
   const int R = (L + G - 1) / G;
   const int c0 = blk * R, c1 = min(L, c0 + R);
   const double m = 0.5 * twom;
@@ -2355,23 +2353,54 @@ __device__ void score_final1_body(int L, const u32* __restrict__ N, const u32* _
     if (pc.q_term) pc.q_term[c] = o_q;
     if (pc.qds_term) pc.qds_term[c] = o_qds;
   }
-  ScorePart p;
-  p.K = block_sum_u64(K, sh_lo);
-  p.sein = block_sum_u64(sein, sh_lo);
-  p.seout = block_sum_u64(seout, sh_lo);
-  p.sD2 = block_sum_u64(sD2, sh_lo);
-  p.np = block_sum_u64(np, sh_lo);
-  u128 pt = block_sum_u128(pen, sh_lo, sh_hi);
-  p.pen_lo = (u64)pt;
-  p.pen_hi = (u64)(pt >> 64);
-  p.pad = 0;
-  p.qds_a = block_sum_f64<FBLOCK / 64>(qds_a, sh_d);
-  p.s_dens = block_sum_f64<FBLOCK / 64>(s_dens, sh_d);
-  p.s_contr = block_sum_f64<FBLOCK / 64>(s_contr, sh_d);
-  p.s_exp = block_sum_f64<FBLOCK / 64>(s_exp, sh_d);
-  p.s_cond = block_sum_f64<FBLOCK / 64>(s_cond, sh_d);
-  p.pad2[0] = p.pad2[1] = p.pad2[2] = 0;
-  if (threadIdx.x == 0) parts[blk] = p;
+  // every field reduced at once: a fixed butterfly in each wave, one barrier, then
+  // thread 0 adds the waves in order (the same order as a block sum of each field)
+  constexpr int NW = FBLOCK / 64;
+  __shared__ u64 sh_u[7][NW];
+  __shared__ double sh_f[5][NW];
+  const u128 pw = wave_sum_u128(pen);
+  const u64 wu[7] = {wave_sum_u64(K), wave_sum_u64(sein), wave_sum_u64(seout), wave_sum_u64(sD2), wave_sum_u64(np),
+                     (u64)pw, (u64)(pw >> 64)};
+  double wf[5] = {qds_a, s_dens, s_contr, s_exp, s_cond};
+#pragma unroll
+  for (int k = 0; k < 5; ++k)
+    for (int o = 32; o > 0; o >>= 1) wf[k] += __shfl_xor(wf[k], o, 64);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+    for (int k = 0; k < 7; ++k) sh_u[k][w] = wu[k];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) sh_f[k][w] = wf[k];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    ScorePart p;
+    u64 t[5] = {0, 0, 0, 0, 0};
+    u128 pt = 0;
+    double f[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int i = 0; i < NW; ++i) {
+#pragma unroll
+      for (int k = 0; k < 5; ++k) t[k] += sh_u[k][i];
+      pt += ((u128)sh_u[6][i] << 64) | sh_u[5][i];
+#pragma unroll
+      for (int k = 0; k < 5; ++k) f[k] += sh_f[k][i];
+    }
+    p.K = t[0];
+    p.sein = t[1];
+    p.seout = t[2];
+    p.sD2 = t[3];
+    p.np = t[4];
+    p.pen_lo = (u64)pt;
+    p.pen_hi = (u64)(pt >> 64);
+    p.pad = 0;
+    p.qds_a = f[0];
+    p.s_dens = f[1];
+    p.s_contr = f[2];
+    p.s_exp = f[3];
+    p.s_cond = f[4];
+    p.pad2[0] = p.pad2[1] = p.pad2[2] = 0;
+    parts[blk] = p;
+  }
 }
 
 __global__ __launch_bounds__(FBLOCK) void k_score_final1(int L, const u32* __restrict__ N, const u32* __restrict__ D,
