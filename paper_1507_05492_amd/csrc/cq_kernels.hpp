@@ -2290,6 +2290,55 @@ struct CmpVis {
 // result is bitwise reproducible.
 constexpr int FBLOCK = 256;
 
+// Block sums of NU u64, NX u128 and NF binary64 fields of an FBLOCK-thread block with one
+// barrier: a fixed butterfly in each wave, then thread 0 adds the waves in order, which
+// gives each field the value a block sum of that field alone would.  The totals replace
+// the inputs in thread 0 only.
+template <int NU, int NX, int NF>
+__device__ __forceinline__ void block_sum_fields(u64 (&u)[NU], u128 (&x)[NX], double (&f)[NF]) {
+  constexpr int NW = FBLOCK / 64;
+  __shared__ u64 s_u[NU][NW];
+  __shared__ u64 s_x[2 * NX][NW];
+  __shared__ double s_f[NF][NW];
+#pragma unroll
+  for (int k = 0; k < NU; ++k) u[k] = wave_sum_u64(u[k]);
+#pragma unroll
+  for (int k = 0; k < NX; ++k) x[k] = wave_sum_u128(x[k]);
+#pragma unroll
+  for (int k = 0; k < NF; ++k)
+    for (int o = 32; o > 0; o >>= 1) f[k] += __shfl_xor(f[k], o, 64);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+    for (int k = 0; k < NU; ++k) s_u[k][w] = u[k];
+#pragma unroll
+    for (int k = 0; k < NX; ++k) {
+      s_x[2 * k][w] = (u64)x[k];
+      s_x[2 * k + 1][w] = (u64)(x[k] >> 64);
+    }
+#pragma unroll
+    for (int k = 0; k < NF; ++k) s_f[k][w] = f[k];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < NU; ++k) {
+      u[k] = 0;
+      for (int i = 0; i < NW; ++i) u[k] += s_u[k][i];
+    }
+#pragma unroll
+    for (int k = 0; k < NX; ++k) {
+      x[k] = 0;
+      for (int i = 0; i < NW; ++i) x[k] += ((u128)s_x[2 * k + 1][i] << 64) | s_x[2 * k][i];
+    }
+#pragma unroll
+    for (int k = 0; k < NF; ++k) {
+      f[k] = 0.0;
+      for (int i = 0; i < NW; ++i) f[k] += s_f[k][i];
+    }
+  }
+}
+
 struct ScorePart {
   u64 K, sein, seout, sD2, np, pen_lo, pen_hi, pad;
   double qds_a, s_dens, s_contr, s_exp, s_cond, pad2[3];
@@ -2353,51 +2402,25 @@ __device__ void score_final1_body(int L, const u32* __restrict__ N, const u32* _
     if (pc.q_term) pc.q_term[c] = o_q;
     if (pc.qds_term) pc.qds_term[c] = o_qds;
   }
-  // every field reduced at once: a fixed butterfly in each wave, one barrier, then
-  // thread 0 adds the waves in order (the same order as a block sum of each field)
-  constexpr int NW = FBLOCK / 64;
-  __shared__ u64 sh_u[7][NW];
-  __shared__ double sh_f[5][NW];
-  const u128 pw = wave_sum_u128(pen);
-  const u64 wu[7] = {wave_sum_u64(K), wave_sum_u64(sein), wave_sum_u64(seout), wave_sum_u64(sD2), wave_sum_u64(np),
-                     (u64)pw, (u64)(pw >> 64)};
-  double wf[5] = {qds_a, s_dens, s_contr, s_exp, s_cond};
-#pragma unroll
-  for (int k = 0; k < 5; ++k)
-    for (int o = 32; o > 0; o >>= 1) wf[k] += __shfl_xor(wf[k], o, 64);
-  const int w = threadIdx.x >> 6;
-  if ((threadIdx.x & 63) == 0) {
-#pragma unroll
-    for (int k = 0; k < 7; ++k) sh_u[k][w] = wu[k];
-#pragma unroll
-    for (int k = 0; k < 5; ++k) sh_f[k][w] = wf[k];
-  }
-  __syncthreads();
+  u64 fu[5] = {K, sein, seout, sD2, np};
+  u128 fx[1] = {pen};
+  double ff[5] = {qds_a, s_dens, s_contr, s_exp, s_cond};
+  block_sum_fields(fu, fx, ff);
   if (threadIdx.x == 0) {
     ScorePart p;
-    u64 t[5] = {0, 0, 0, 0, 0};
-    u128 pt = 0;
-    double f[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    for (int i = 0; i < NW; ++i) {
-#pragma unroll
-      for (int k = 0; k < 5; ++k) t[k] += sh_u[k][i];
-      pt += ((u128)sh_u[6][i] << 64) | sh_u[5][i];
-#pragma unroll
-      for (int k = 0; k < 5; ++k) f[k] += sh_f[k][i];
-    }
-    p.K = t[0];
-    p.sein = t[1];
-    p.seout = t[2];
-    p.sD2 = t[3];
-    p.np = t[4];
-    p.pen_lo = (u64)pt;
-    p.pen_hi = (u64)(pt >> 64);
+    p.K = fu[0];
+    p.sein = fu[1];
+    p.seout = fu[2];
+    p.sD2 = fu[3];
+    p.np = fu[4];
+    p.pen_lo = (u64)fx[0];
+    p.pen_hi = (u64)(fx[0] >> 64);
     p.pad = 0;
-    p.qds_a = f[0];
-    p.s_dens = f[1];
-    p.s_contr = f[2];
-    p.s_exp = f[3];
-    p.s_cond = f[4];
+    p.qds_a = ff[0];
+    p.s_dens = ff[1];
+    p.s_contr = ff[2];
+    p.s_exp = ff[3];
+    p.s_cond = ff[4];
     p.pad2[0] = p.pad2[1] = p.pad2[2] = 0;
     parts[blk] = p;
   }
@@ -2470,8 +2493,6 @@ __global__ __launch_bounds__(FBLOCK) void k_score_final1_w(int L, const u32* __r
                                                            const u64* __restrict__ SW, const u64* __restrict__ IW,
                                                            const u64* __restrict__ PENW, double W, PerComm pc,
                                                            WScorePart* __restrict__ parts) {
-  __shared__ u64 sh_lo[FBLOCK / 64], sh_hi[FBLOCK / 64];
-  __shared__ double sh_d[FBLOCK / 64];
   const int G = gridDim.x, blk = blockIdx.x;
   const int R = (L + G - 1) / G;
   const int c0 = blk * R, c1 = min(L, c0 + R);
@@ -2521,30 +2542,33 @@ __global__ __launch_bounds__(FBLOCK) void k_score_final1_w(int L, const u32* __r
     if (pc.w_in) pc.w_in[c] = o_wi;
     if (pc.strength) pc.strength[c] = o_s;
   }
-  WScorePart p;
-  p.K = block_sum_u64(K, sh_lo);
-  p.sein = block_sum_u64(sein, sh_lo);
-  p.seout = block_sum_u64(seout, sh_lo);
-  p.sD2 = block_sum_u64(sD2, sh_lo);
-  p.np = block_sum_u64(np, sh_lo);
-  u128 t = block_sum_u128(penw, sh_lo, sh_hi);
-  p.penw_lo = (u64)t;
-  p.penw_hi = (u64)(t >> 64);
-  t = block_sum_u128(swi2, sh_lo, sh_hi);
-  p.wi_lo = (u64)t;
-  p.wi_hi = (u64)(t >> 64);
-  t = block_sum_u128(swo, sh_lo, sh_hi);
-  p.wo_lo = (u64)t;
-  p.wo_hi = (u64)(t >> 64);
-  p.pad = 0;
-  p.q = block_sum_f64<FBLOCK / 64>(q, sh_d);
-  p.qds_a = block_sum_f64<FBLOCK / 64>(qds_a, sh_d);
-  p.s_dens = block_sum_f64<FBLOCK / 64>(s_dens, sh_d);
-  p.s_contr = block_sum_f64<FBLOCK / 64>(s_contr, sh_d);
-  p.s_exp = block_sum_f64<FBLOCK / 64>(s_exp, sh_d);
-  p.s_cond = block_sum_f64<FBLOCK / 64>(s_cond, sh_d);
-  p.pad2[0] = p.pad2[1] = 0;
-  if (threadIdx.x == 0) parts[blk] = p;
+  u64 fu[5] = {K, sein, seout, sD2, np};
+  u128 fx[3] = {penw, swi2, swo};
+  double ff[6] = {q, qds_a, s_dens, s_contr, s_exp, s_cond};
+  block_sum_fields(fu, fx, ff);
+  if (threadIdx.x == 0) {
+    WScorePart p;
+    p.K = fu[0];
+    p.sein = fu[1];
+    p.seout = fu[2];
+    p.sD2 = fu[3];
+    p.np = fu[4];
+    p.penw_lo = (u64)fx[0];
+    p.penw_hi = (u64)(fx[0] >> 64);
+    p.wi_lo = (u64)fx[1];
+    p.wi_hi = (u64)(fx[1] >> 64);
+    p.wo_lo = (u64)fx[2];
+    p.wo_hi = (u64)(fx[2] >> 64);
+    p.pad = 0;
+    p.q = ff[0];
+    p.qds_a = ff[1];
+    p.s_dens = ff[2];
+    p.s_contr = ff[3];
+    p.s_exp = ff[4];
+    p.s_cond = ff[5];
+    p.pad2[0] = p.pad2[1] = 0;
+    parts[blk] = p;
+  }
 }
 
 __global__ void k_score_final2_w(int G, const WScorePart* __restrict__ parts, long long n, long long twom, double W,
@@ -2600,8 +2624,6 @@ __global__ __launch_bounds__(FBLOCK) void k_cmp_final1(int La, int Lb, int Ga, c
                                                        const u32* __restrict__ COLMAX, const u64* __restrict__ RA11,
                                                        const u32* __restrict__ RMAX, const double* __restrict__ RF,
                                                        const u64* __restrict__ RXL, double Nd, CmpPart* __restrict__ parts) {
-  __shared__ u64 sh_lo[FBLOCK / 64], sh_hi[FBLOCK / 64];
-  __shared__ double sh_d[FBLOCK / 64];
   u64 Ka = 0, Kb = 0, a11 = 0, X = 0, Y = 0, smax = 0;
   u128 xl = 0, sa = 0, sb = 0;  // S, S_a, S_b (see CmpVis)
   double fsum = 0;
@@ -2632,22 +2654,25 @@ __global__ __launch_bounds__(FBLOCK) void k_cmp_final1(int La, int Lb, int Ga, c
       sb += fix96((double)bj / Nd * log((double)bj));
     }
   }
-  CmpPart p;
-  p.Ka = block_sum_u64(Ka, sh_lo);
-  p.Kb = block_sum_u64(Kb, sh_lo);
-  p.a11 = block_sum_u64(a11, sh_lo);
-  p.X = block_sum_u64(X, sh_lo);
-  p.Y = block_sum_u64(Y, sh_lo);
-  p.smax = block_sum_u64(smax, sh_lo);
-  u128 t = block_sum_u128(xl, sh_lo, sh_hi);
-  p.xl_lo = (u64)t; p.xl_hi = (u64)(t >> 64);
-  t = block_sum_u128(sa, sh_lo, sh_hi);
-  p.sa_lo = (u64)t; p.sa_hi = (u64)(t >> 64);
-  t = block_sum_u128(sb, sh_lo, sh_hi);
-  p.sb_lo = (u64)t; p.sb_hi = (u64)(t >> 64);
-  p.fsum = block_sum_f64<FBLOCK / 64>(fsum, sh_d);
-  p.pad[0] = p.pad[1] = p.pad[2] = 0;
-  if (threadIdx.x == 0) parts[blockIdx.x] = p;
+  u64 fu[6] = {Ka, Kb, a11, X, Y, smax};
+  u128 fx[3] = {xl, sa, sb};
+  double ff[1] = {fsum};
+  block_sum_fields(fu, fx, ff);
+  if (threadIdx.x == 0) {
+    CmpPart p;
+    p.Ka = fu[0];
+    p.Kb = fu[1];
+    p.a11 = fu[2];
+    p.X = fu[3];
+    p.Y = fu[4];
+    p.smax = fu[5];
+    p.xl_lo = (u64)fx[0]; p.xl_hi = (u64)(fx[0] >> 64);
+    p.sa_lo = (u64)fx[1]; p.sa_hi = (u64)(fx[1] >> 64);
+    p.sb_lo = (u64)fx[2]; p.sb_hi = (u64)(fx[2] >> 64);
+    p.fsum = ff[0];
+    p.pad[0] = p.pad[1] = p.pad[2] = 0;
+    parts[blockIdx.x] = p;
+  }
 }
 
 struct CmpResultDev {
