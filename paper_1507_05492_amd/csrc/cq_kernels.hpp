@@ -2209,7 +2209,7 @@ struct CmpVis {
     u64 a11;
     u32 rmax;
     double fmax;
-    u128 xl;
+    Frac96Sum xl;  // S in fixed point; each term lies in [0, log N]
     u32 g;
     u32 ai;
     u32 nz;
@@ -2218,7 +2218,7 @@ struct CmpVis {
     st.a11 = 0;
     st.rmax = 0;
     st.fmax = 0.0;
-    st.xl = 0;
+    st.xl = Frac96Sum();
     st.g = g;
     st.ai = A[g];
     st.nz = 0;
@@ -2230,7 +2230,7 @@ struct CmpVis {
     st.rmax = max(st.rmax, x);
     double f = 2.0 * (double)x / (double)((u64)st.ai + (u64)bj);   // Eq. 3 ratio
     st.fmax = f > st.fmax ? f : st.fmax;
-    st.xl += fix96((double)x / Nd * log((double)x));  // the cell's part of S
+    st.xl.add_wide((double)x / Nd * log((double)x));  // the cell's part of S, truncated to 2^-96 as fix96 does
     atomicMax(&COLMAX[j], x);
     st.nz += 1;
     if (ecap > 0) {
@@ -2245,7 +2245,7 @@ struct CmpVis {
     __shared__ u32 r_max[NW];
     __shared__ double r_f[NW];
     {
-      const u128 wm = wave_sum_u128(st.xl);
+      const u128 wm = wave_sum_u128(st.xl.value());
       const u64 wa = wave_sum_u64(st.a11), wn = wave_sum_u64(st.nz);
       const u32 wx = wave_max_u32(st.rmax);
       const double wf = wave_max_f64(st.fmax);
