@@ -107,6 +107,26 @@ __device__ __forceinline__ u128 fixw_f32(float w) {
   const u32 e = (b >> 23) & 0xFFu;
   return (u128)((b & 0x7FFFFFu) | 0x800000u) << (e - WEIGHT_EXP0);
 }
+// Exact sum of float32 weights in [WEIGHT_MIN, WEIGHT_MAX], times 2^55 (the value of
+// fixw_f32), in two 64-bit words.  split() gives a weight's fixed-point value as
+// (hi, lo): its 24-bit significand shifted left by s = biased exponent - WEIGHT_EXP0
+// (0 <= s <= 64).
+struct WeightSum {
+  u64 lo = 0, hi = 0;
+  static __device__ __forceinline__ void split(float w, u64& vlo, u64& vhi) {
+    const u32 b = __float_as_uint(w);
+    const u32 sh = ((b >> 23) & 0xFFu) - WEIGHT_EXP0;
+    const u64 sig = (u64)((b & 0x7FFFFFu) | 0x800000u);
+    vlo = sh < 64u ? sig << sh : 0ull;
+    vhi = sh > 40u ? sig >> (64u - sh) : 0ull;
+  }
+  __device__ __forceinline__ void add(u64 vlo, u64 vhi) {
+    lo += vlo;
+    hi += vhi + (lo < vlo ? 1ull : 0ull);
+  }
+  __device__ __forceinline__ u128 value() const { return ((u128)hi << 64) | lo; }
+};
+
 // value / 2^55 of an exact weight sum
 __device__ __forceinline__ double unfixw(u128 v) {
   return (double)(u64)(v >> 64) * 512.0 + (double)(u64)v * 2.7755575615628914e-17;  // 2^9, 2^-55

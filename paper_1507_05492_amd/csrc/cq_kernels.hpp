@@ -1188,13 +1188,15 @@ struct FarTable {
   u32 b[COL_BLOCKS][4];
 };
 
-template <class LT>
+template <class LT, bool WT = false>
 struct GatherLds {
   static constexpr int PER = 16 / (int)sizeof(LT);             // labels per 16-byte word
   static constexpr int WINV = (BT_ROWS + 2 * BT_HALO) / PER + 1;  // 16-byte words of the label window
   static constexpr int RUN_WORDS = (4 * (BT_ROWS + 1) + 3) & ~3;  // four per-run arrays, padded to 16 bytes
   static constexpr int BUF = sizeof(LT) == 2 ? OWN_BUF : 0;        // compact staging buffer (16-bit labels)
-  static constexpr int OWN = RUN_WORDS + 4 * WINV + BUF;
+  static constexpr int WBUF = WT ? BUF : 0;                        // the buffered entries' weights
+  static constexpr int ISUM = WT ? 4 * BT_ROWS : 0;                // per run: own-label weight sum, two u64
+  static constexpr int OWN = RUN_WORDS + 4 * WINV + BUF + WBUF + ISUM;
   static constexpr int FAR = 3 * (FT_ENT + 1);
   static constexpr int WORDS = OWN > FAR ? OWN : FAR;
 };
@@ -1261,24 +1263,30 @@ __device__ __forceinline__ void claim_runs_compact(u32 nruns, const u32* s_first
 }
 
 // Own-span tile t of block y: rows [s0 + t*BT_ROWS, ...) of span y, their block-y entries.
-// WT: the graph is weighted: every entry is staged, with its weight in CW beside its
-// label.  Otherwise staging is compact (claim_runs_compact): a first pass over the
-// tile's entries counts each run's entries of another label, the runs claim their
-// places, and a second pass stages those entries.
+// Staging is compact (claim_runs_compact): a first pass over the tile's entries counts
+// each run's entries of another label, the runs claim their places, and those entries
+// are staged (from an LDS buffer, or by a second pass when it overflows).  WT: the graph
+// is weighted: a staged entry's weight goes to CW beside its label, and each run's
+// own-label weights are summed exactly (x 2^55, as WeightSum) and added to IWacc[c] (two
+// u64 words per community, low word first, the carry added to the high word).
 template <class LT, bool WT>
 __device__ void gather_own_tile(u32 y, u32 t, int n, int span, const u32* __restrict__ RPB,
                                 const int32_t* __restrict__ colb, const LT* __restrict__ labx,
                                 const u32* __restrict__ start, const u32* __restrict__ D, u32* __restrict__ cursor,
                                 Ctl* __restrict__ ctl, LT* __restrict__ CB, const float* __restrict__ wb,
-                                float* __restrict__ CW, u32* lds, u32* s_w) {
-  using LL = GatherLds<LT>;
+                                float* __restrict__ CW, unsigned long long* __restrict__ IWacc, u32* lds, u32* s_w) {
+  using LL = GatherLds<LT, WT>;
   constexpr int PER = LL::PER;
   constexpr int WIT = (LL::WINV + BT_THREADS - 1) / BT_THREADS;
   u32* s_re = lds;                   // staged row starts, then first entry of run q (tile-relative)
-  u32* s_rl = lds + BT_ROWS + 1;     // staged row labels, then label of run q (then its place, WT)
-  u32* s_cnt = lds + 2 * (BT_ROWS + 1);   // compact: entries of run q with another label
-  u32* s_base = lds + 3 * (BT_ROWS + 1);  // compact: place of run q's first staged entry
+  u32* s_rl = lds + BT_ROWS + 1;     // staged row labels, then label of run q
+  u32* s_cnt = lds + 2 * (BT_ROWS + 1);   // entries of run q with another label
+  u32* s_base = lds + 3 * (BT_ROWS + 1);  // place of run q's first staged entry
   uint4* s_win = reinterpret_cast<uint4*>(lds + LL::RUN_WORDS);  // labels of ids [w0, w1)
+  // WT: own-label weight sum of run q (low, high words)
+  unsigned long long* s_ilo =
+      reinterpret_cast<unsigned long long*>(lds + LL::RUN_WORDS + 4 * LL::WINV + LL::BUF + LL::WBUF);
+  unsigned long long* s_ihi = s_ilo + BT_ROWS;
   const long long s0 = min((long long)n, (long long)y * span), s1 = min((long long)n, s0 + span);
   const long long r0 = s0 + (long long)t * BT_ROWS, r1 = min(s1, r0 + BT_ROWS);
   if (r0 >= r1) return;
@@ -1350,8 +1358,13 @@ __device__ void gather_own_tile(u32 y, u32 t, int n, int span, const u32* __rest
     s_re[nruns] = e1 - e0;
     s_base[BT_ROWS] = 0;  // compact: count of buffered entries
   }
-  if (!WT)
-    for (u32 r = tid; r < nruns; r += BT_THREADS) s_cnt[r] = 0;
+  for (u32 r = tid; r < nruns; r += BT_THREADS) {
+    s_cnt[r] = 0;
+    if (WT) {
+      s_ilo[r] = 0ull;
+      s_ihi[r] = 0ull;
+    }
+  }
   __syncthreads();
   const int32_t* cb = colb + e0;
   const u32 ne = e1 - e0;
@@ -1390,69 +1403,103 @@ __device__ void gather_own_tile(u32 y, u32 t, int n, int span, const u32* __rest
       }
     }
   };
-  if (WT) {
-    claim_runs<LT>(nruns, s_re, s_rl, start, D, cursor, ctl);
-    __syncthreads();
-    for_entries([&](u32 e, u32 r, LT x, float w) {
-      const u32 base = s_rl[r];
-      if (base != SENT) {
-        CB[base + (e - s_re[r])] = x;
-        CW[base + (e - s_re[r])] = w;
-      }
-    });
-  } else {
-    // Pass 1: count each run's entries of another label and keep them, (run << 16) | label,
-    // in the LDS buffer; slots and counts are taken once per wave.
-    u32* s_buf = lds + LL::RUN_WORDS + 4 * LL::WINV;
-    u32* s_nbuf = s_base + BT_ROWS;  // unused by runs (nruns <= BT_ROWS)
-    const int lane = tid & 63;
-    const u64 below = lane ? (~0ull >> (64 - lane)) : 0ull;
-    for_entries([&](u32, u32 r, LT x, float) {
-      const bool inter = (u32)x != s_rl[r];
-      const u64 m = __ballot(inter);
-      if (m == 0) return;
-      const int lead = __ffsll((long long)m) - 1;
-      const u32 rl = __shfl(r, lead, 64);
-      const u64 ms = __ballot(inter && r == rl);
-      u32 slot0 = 0;
-      if (lane == lead) {
-        slot0 = atomicAdd(s_nbuf, (u32)__popcll(m));
-        atomicAdd(&s_cnt[rl], (u32)__popcll(ms));
-      }
-      slot0 = __shfl(slot0, lead, 64);
-      if (inter) {
-        const u32 slot = slot0 + (u32)__popcll(m & below);
-        if (slot < (u32)LL::BUF) s_buf[slot] = (r << 16) | (u32)x;
-        if (r != rl) atomicAdd(&s_cnt[r], 1u);
-      }
-    });
-    __syncthreads();
-    claim_runs_compact<LT>(nruns, s_re, s_rl, s_cnt, s_base, start, D, reinterpret_cast<unsigned long long*>(cursor), ctl);
-    __syncthreads();
-    const u32 nb = *s_nbuf;
-    if (nb <= (u32)LL::BUF) {
-      // write the buffer out: each wave takes consecutive places per run (coalesced)
-      for (u32 k = tid; k < nb; k += BT_THREADS) {
-        const u32 ent = s_buf[k];
-        const u32 r = ent >> 16;
-        const u64 act = __ballot(true);
-        const int lead = __ffsll((long long)act) - 1;
-        const u32 rl = __shfl(r, lead, 64);
-        const u64 ms = __ballot(r == rl);
-        u32 p0 = 0;
-        if (lane == lead) p0 = atomicAdd(&s_cnt[rl], (u32)__popcll(ms));
-        p0 = __shfl(p0, lead, 64);
-        const u32 rank = r == rl ? p0 + (u32)__popcll(ms & below) : atomicAdd(&s_cnt[r], 1u);
-        const u32 base = s_base[r];
-        if (base != SENT) CB[base + rank] = (LT)(ent & 0xFFFFu);
-      }
-    } else {
-      // buffer overflow (or 32-bit labels): classify the tile's entries again
-      for_entries([&](u32, u32 r, LT x, float) {
-        const u32 base = s_base[r];
-        if ((u32)x != s_rl[r] && base != SENT) CB[base + atomicAdd(&s_cnt[r], 1u)] = x;
-      });
+  // Pass 1: count each run's entries of another label and keep them, (run << 16) | label
+  // (and their weights, WT), in the LDS buffer; slots and counts are taken once per wave.
+  u32* s_buf = lds + LL::RUN_WORDS + 4 * LL::WINV;
+  float* s_wbuf = reinterpret_cast<float*>(s_buf + LL::BUF);
+  u32* s_nbuf = s_base + BT_ROWS;  // unused by runs (nruns <= BT_ROWS)
+  const int lane = tid & 63;
+  const u64 below = lane ? (~0ull >> (64 - lane)) : 0ull;
+  // WT: a thread meets its entries in increasing order, so runs in increasing order: it
+  // sums the own-label weights of its current run and adds them to the run's LDS sum
+  // when the run changes (64-bit atomics, the low word's carry added to the high word)
+  u32 wrun = 0xFFFFFFFFu;
+  WeightSum wacc;
+  auto wflush = [&]() {
+    if (wrun != 0xFFFFFFFFu) {
+      const unsigned long long old = atomicAdd(&s_ilo[wrun], (unsigned long long)wacc.lo);
+      const unsigned long long hi = wacc.hi + (old + wacc.lo < old ? 1ull : 0ull);
+      if (hi) atomicAdd(&s_ihi[wrun], hi);
     }
+  };
+  for_entries([&](u32, u32 r, LT x, float w) {
+    const bool inter = (u32)x != s_rl[r];
+    if (WT && !inter) {
+      if (r != wrun) {
+        wflush();
+        wrun = r;
+        wacc = WeightSum();
+      }
+      u64 vlo, vhi;
+      WeightSum::split(w, vlo, vhi);
+      wacc.add(vlo, vhi);
+    }
+    const u64 m = __ballot(inter);
+    if (m == 0) return;
+    const int lead = __ffsll((long long)m) - 1;
+    const u32 rl = __shfl(r, lead, 64);
+    const u64 ms = __ballot(inter && r == rl);
+    u32 slot0 = 0;
+    if (lane == lead) {
+      slot0 = atomicAdd(s_nbuf, (u32)__popcll(m));
+      atomicAdd(&s_cnt[rl], (u32)__popcll(ms));
+    }
+    slot0 = __shfl(slot0, lead, 64);
+    if (inter) {
+      const u32 slot = slot0 + (u32)__popcll(m & below);
+      if (slot < (u32)LL::BUF) {
+        s_buf[slot] = (r << 16) | (u32)x;
+        if (WT) s_wbuf[slot] = w;
+      }
+      if (r != rl) atomicAdd(&s_cnt[r], 1u);
+    }
+  });
+  if (WT) wflush();
+  __syncthreads();
+  claim_runs_compact<LT>(nruns, s_re, s_rl, s_cnt, s_base, start, D, reinterpret_cast<unsigned long long*>(cursor), ctl);
+  if (WT) {
+    // each run's own-label weights join its community's sum
+    for (u32 r = tid; r < nruns; r += BT_THREADS) {
+      const unsigned long long lo = s_ilo[r], hi = s_ihi[r];
+      const u32 c = s_rl[r];
+      if ((lo | hi) && c != (u32)LabelT<LT>::SENTINEL) {
+        const unsigned long long old = atomicAdd(&IWacc[2 * (size_t)c], lo);
+        const unsigned long long h = hi + (old + lo < old ? 1ull : 0ull);
+        if (h) atomicAdd(&IWacc[2 * (size_t)c + 1], h);
+      }
+    }
+  }
+  __syncthreads();
+  const u32 nb = *s_nbuf;
+  if (nb <= (u32)LL::BUF) {
+    // write the buffer out: each wave takes consecutive places per run (coalesced)
+    for (u32 k = tid; k < nb; k += BT_THREADS) {
+      const u32 ent = s_buf[k];
+      const u32 r = ent >> 16;
+      const u64 act = __ballot(true);
+      const int lead = __ffsll((long long)act) - 1;
+      const u32 rl = __shfl(r, lead, 64);
+      const u64 ms = __ballot(r == rl);
+      u32 p0 = 0;
+      if (lane == lead) p0 = atomicAdd(&s_cnt[rl], (u32)__popcll(ms));
+      p0 = __shfl(p0, lead, 64);
+      const u32 rank = r == rl ? p0 + (u32)__popcll(ms & below) : atomicAdd(&s_cnt[r], 1u);
+      const u32 base = s_base[r];
+      if (base != SENT) {
+        CB[base + rank] = (LT)(ent & 0xFFFFu);
+        if (WT) CW[base + rank] = s_wbuf[k];
+      }
+    }
+  } else {
+    // buffer overflow (or 32-bit labels): classify the tile's entries again
+    for_entries([&](u32, u32 r, LT x, float w) {
+      const u32 base = s_base[r];
+      if ((u32)x != s_rl[r] && base != SENT) {
+        const u32 rank = atomicAdd(&s_cnt[r], 1u);
+        CB[base + rank] = x;
+        if (WT) CW[base + rank] = w;
+      }
+    });
   }
 }
 
@@ -1533,7 +1580,11 @@ __device__ void gather_far_tile(u32 y, u32 t, const FarTable& ft, const int32_t*
     }
   };
   if (WT) {
-    claim_runs<LT>(nruns, s_rf, s_rb, start, D, cursor, ctl);
+    // weighted: every far entry is staged on the compact cursor (its runs add no own-label
+    // count); the few of the row's own label are counted and weighed by the group pass.
+    // Each run's length is set by the thread that claims it.
+    for (u32 r = tid; r < nruns; r += BT_THREADS) s_cnt[r] = s_rf[r + 1] - s_rf[r];
+    claim_runs_compact<LT>(nruns, s_rf, s_rb, s_cnt, s_rb, start, D, reinterpret_cast<unsigned long long*>(cursor), ctl);
     __syncthreads();
     for_entries([&](int j, u32 i, u32 run) {
       const u32 base = s_rb[run];
@@ -1568,13 +1619,14 @@ __global__ __launch_bounds__(BT_THREADS) void k_gather_blocked(int n, int span, 
                                                                const LT* __restrict__ labx, const u32* __restrict__ start,
                                                                const u32* __restrict__ D, u32* __restrict__ cursor,
                                                                Ctl* __restrict__ ctl, LT* __restrict__ CB,
-                                                               const float* __restrict__ wb, float* __restrict__ CW) {
-  __shared__ __align__(16) u32 lds[GatherLds<LT>::WORDS];
+                                                               const float* __restrict__ wb, float* __restrict__ CW,
+                                                               unsigned long long* __restrict__ IWacc) {
+  __shared__ __align__(16) u32 lds[GatherLds<LT, WT>::WORDS];
   __shared__ u32 s_w[BT_THREADS / 64];
   const u32 y = blockIdx.x % 8u, gi = blockIdx.x / 8u;
   if (y >= (u32)COL_BLOCKS || gi >= own_groups + far_groups) return;
   if (gi < own_groups)
-    gather_own_tile<LT, WT>(y, gi, n, span, RPB, colb, labx, start, D, cursor, ctl, CB, wb, CW, lds, s_w);
+    gather_own_tile<LT, WT>(y, gi, n, span, RPB, colb, labx, start, D, cursor, ctl, CB, wb, CW, IWacc, lds, s_w);
   else
     gather_far_tile<LT, WT>(y, gi - own_groups, ft, colb, rowb, labx, start, D, cursor, ctl, CB, wb, CW, lds, s_w);
 }
@@ -2019,7 +2071,10 @@ struct ScoreVis {
 // The first pass counts labels exactly as the unweighted pass does.  The second pass,
 // once the table holds every count |E_gj|, reads labels and weights together: entry
 // (j, w) adds w to the weight sums and, for j != g, w |E_gj| / (2W |g| |j|) to the
-// penalty, truncated to a multiple of 2^-96 (term by term, so the sum is exact).
+// penalty, truncated to a multiple of 2^-96 (term by term, so the sum is exact).  With
+// compact staging (column-blocked graphs) the segment holds only entries of other
+// labels (and far entries): the edge pass has already counted the own-label entries
+// (high word of the cursor) and summed their weights into IW[g], which both sums add.
 struct WeightedOut {
   u64* SW;
   u64* IW;
@@ -2028,25 +2083,6 @@ struct WeightedOut {
   double twoW;
 };
 
-// Exact sum of float32 weights in [WEIGHT_MIN, WEIGHT_MAX], times 2^55 (the value of
-// fixw_f32), in two 64-bit words.  split() gives a weight's fixed-point value as
-// (hi, lo): its 24-bit significand shifted left by s = biased exponent - WEIGHT_EXP0
-// (0 <= s <= 64).
-struct WeightSum {
-  u64 lo = 0, hi = 0;
-  static __device__ __forceinline__ void split(float w, u64& vlo, u64& vhi) {
-    const u32 b = __float_as_uint(w);
-    const u32 sh = ((b >> 23) & 0xFFu) - WEIGHT_EXP0;
-    const u64 sig = (u64)((b & 0x7FFFFFu) | 0x800000u);
-    vlo = sh < 64u ? sig << sh : 0ull;
-    vhi = sh > 40u ? sig >> (64u - sh) : 0ull;
-  }
-  __device__ __forceinline__ void add(u64 vlo, u64 vhi) {
-    lo += vlo;
-    hi += vhi + (lo < vlo ? 1ull : 0ull);
-  }
-  __device__ __forceinline__ u128 value() const { return ((u128)hi << 64) | lo; }
-};
 
 
 // Calls f(label, weight) for every entry of a segment of labels and weights (both arrays
@@ -2082,7 +2118,8 @@ __device__ __forceinline__ void for_each_weighted(const LT* __restrict__ lab, co
 
 template <class LT>
 __device__ void group_one_w(const LT* __restrict__ CB, const float* __restrict__ CW, const u32 base, const u32 len,
-                            const u32 g, const u32 Lv, ScoreVis& vis, const WeightedOut& wo) {
+                            const u32 g, const u32 Lv, ScoreVis& vis, const WeightedOut& wo, const u32 hot0,
+                            const u128 iw0) {
   extern __shared__ __align__(16) u32 tab[];  // read and cleared as uint4
   __shared__ u32 s_hot;
   __shared__ u64 r_w[6][GBLOCK / 64];
@@ -2092,7 +2129,7 @@ __device__ void group_one_w(const LT* __restrict__ CB, const float* __restrict__
   const u32 nq = (Lv + 3u) >> 2;
   uint4* tab4 = reinterpret_cast<uint4*>(tab);
   for (u32 q = tid; q < nq; q += GBLOCK) tab4[q] = make_uint4(0u, 0u, 0u, 0u);
-  if (tid == 0) s_hot = 0;
+  if (tid == 0) s_hot = hot0;
   __syncthreads();
   u32 mine = 0;
   for_each_in_segment<LT>(CB + base, len, [&](u32 j) {
@@ -2141,7 +2178,7 @@ __device__ void group_one_w(const LT* __restrict__ CB, const float* __restrict__
   }
   __syncthreads();
   if (tid == 0) {
-    u128 a = 0, b = 0, c = 0;
+    u128 a = iw0, b = iw0, c = 0;  // own-label weights counted by the edge pass
     for (int i = 0; i < GBLOCK / 64; ++i) {
       a += ((u128)r_w[1][i] << 64) | r_w[0][i];
       b += ((u128)r_w[3][i] << 64) | r_w[2][i];
@@ -2161,7 +2198,8 @@ template <class LT>
 __global__ __launch_bounds__(GBLOCK) void k_groups_w(const LT* __restrict__ CB, const float* __restrict__ CW,
                                                      const u32* __restrict__ seg_start, const u32* __restrict__ seg_len,
                                                      const u32* __restrict__ order, Ctl* __restrict__ ctl, u32 Lv,
-                                                     ScoreVis vis, WeightedOut wo) {
+                                                     ScoreVis vis, WeightedOut wo,
+                                                     const unsigned long long* __restrict__ cur64) {
   __shared__ u32 s_item;
   const u32 K = ctl->K;
   for (;;) {
@@ -2171,7 +2209,15 @@ __global__ __launch_bounds__(GBLOCK) void k_groups_w(const LT* __restrict__ CB, 
     __syncthreads();
     if (item >= K) break;
     const u32 g = order[item];
-    group_one_w<LT>(CB, CW, seg_start[g], seg_len[g], g, Lv, vis, wo);
+    u32 len = seg_len[g], hot0 = 0;
+    u128 iw0 = 0;
+    if (cur64) {  // compact staging: length and own-label count in the cursor, own-label weights in IW
+      const unsigned long long c = cur64[g];
+      len = (u32)c;
+      hot0 = (u32)(c >> 32);
+      iw0 = ((u128)wo.IW[2 * (size_t)g + 1] << 64) | wo.IW[2 * (size_t)g];
+    }
+    group_one_w<LT>(CB, CW, seg_start[g], len, g, Lv, vis, wo, hot0, iw0);
   }
 }
 

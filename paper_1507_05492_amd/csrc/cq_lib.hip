@@ -366,6 +366,8 @@ void score_launch(cq_context* ctx, const cq_graph* g, const int32_t* labels, int
     // run cursors of column-blocked graphs: cleared by the column scan on the
     // private-histogram path, here otherwise
     if (g->rpb && !(lay.priv && g->pos1)) fill(at<u32>(ws, lay.cursor), 2 * (size_t)L, 0, s);
+    // weighted column-blocked graphs: the edge pass adds each community's own-label weights here
+    if (CW && g->rpb) fill(at<u32>(ws, lay.IW), 4 * (size_t)L, 0, s);
   }
   if (lay.priv && g->rpb && g->pos1) {
     // column-blocked graph: move the labels with the bucket plan and count per label (the
@@ -455,11 +457,11 @@ void score_launch(cq_context* ctx, const cq_graph* g, const int32_t* labels, int
       if (CW)
         k_gather_blocked<LT, true><<<grid, BT_THREADS, 0, s>>>((int)n, (int)span, g->rpb, g->colb, g->rowb, g->far, own_groups,
                                                                g->far_tiles, labx, start, D, at<u32>(ws, lay.cursor), ctl, CB,
-                                                               g->wb, CW);
+                                                               g->wb, CW, at<unsigned long long>(ws, lay.IW));
       else
         k_gather_blocked<LT, false><<<grid, BT_THREADS, 0, s>>>((int)n, (int)span, g->rpb, g->colb, g->rowb, g->far, own_groups,
                                                                 g->far_tiles, labx, start, D, at<u32>(ws, lay.cursor), ctl, CB,
-                                                                nullptr, nullptr);
+                                                                nullptr, nullptr, nullptr);
     } else {
       const unsigned grid = grid_for(n, GROWS, 1u << 30);
       if (lay.priv && CW)
@@ -504,7 +506,10 @@ void score_launch(cq_context* ctx, const cq_graph* g, const int32_t* labels, int
       k_inv_sizes<<<grid_for(L, 256, 1024), 256, 0, s>>>(L, N, invN);
       int nb = 0;
       if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_groups_w<LT>, GBLOCK, lds) != hipSuccess || nb < 1) nb = 1;
-      k_groups_w<LT><<<(unsigned)(ctx->num_cus * nb), GBLOCK, lds, s>>>(CB, CW, start, D, order, ctl, (u32)L, vis, wo);
+      // column-blocked graphs stage compactly: lengths and own-label counts in the cursors
+      const unsigned long long* cur64 = g->rpb ? at<unsigned long long>(ws, lay.cursor) : nullptr;
+      k_groups_w<LT><<<(unsigned)(ctx->num_cus * nb), GBLOCK, lds, s>>>(CB, CW, start, D, order, ctl, (u32)L, vis, wo,
+                                                                        cur64);
     }
     WScorePart* wparts = reinterpret_cast<WScorePart*>(parts);
     {
