@@ -2119,7 +2119,7 @@ __device__ __forceinline__ void for_each_weighted(const LT* __restrict__ lab, co
 template <class LT>
 __device__ void group_one_w(const LT* __restrict__ CB, const float* __restrict__ CW, const u32 base, const u32 len,
                             const u32 g, const u32 Lv, ScoreVis& vis, const WeightedOut& wo, const u32 hot0,
-                            const u128 iw0) {
+                            const bool own_in_iw) {
   extern __shared__ __align__(16) u32 tab[];  // read and cleared as uint4
   __shared__ u32 s_hot;
   __shared__ u64 r_w[6][GBLOCK / 64];
@@ -2178,7 +2178,9 @@ __device__ void group_one_w(const LT* __restrict__ CB, const float* __restrict__
   }
   __syncthreads();
   if (tid == 0) {
-    u128 a = iw0, b = iw0, c = 0;  // own-label weights counted by the edge pass
+    // own-label weights the edge pass summed into IW (compact staging)
+    const u128 iw0 = own_in_iw ? ((u128)wo.IW[2 * (size_t)g + 1] << 64) | wo.IW[2 * (size_t)g] : (u128)0;
+    u128 a = iw0, b = iw0, c = 0;
     for (int i = 0; i < GBLOCK / 64; ++i) {
       a += ((u128)r_w[1][i] << 64) | r_w[0][i];
       b += ((u128)r_w[3][i] << 64) | r_w[2][i];
@@ -2195,7 +2197,7 @@ __device__ void group_one_w(const LT* __restrict__ CB, const float* __restrict__
 }
 
 template <class LT>
-__global__ __launch_bounds__(GBLOCK) void k_groups_w(const LT* __restrict__ CB, const float* __restrict__ CW,
+__global__ __launch_bounds__(GBLOCK, 6) void k_groups_w(const LT* __restrict__ CB, const float* __restrict__ CW,
                                                      const u32* __restrict__ seg_start, const u32* __restrict__ seg_len,
                                                      const u32* __restrict__ order, Ctl* __restrict__ ctl, u32 Lv,
                                                      ScoreVis vis, WeightedOut wo,
@@ -2210,14 +2212,12 @@ __global__ __launch_bounds__(GBLOCK) void k_groups_w(const LT* __restrict__ CB, 
     if (item >= K) break;
     const u32 g = order[item];
     u32 len = seg_len[g], hot0 = 0;
-    u128 iw0 = 0;
     if (cur64) {  // compact staging: length and own-label count in the cursor, own-label weights in IW
       const unsigned long long c = cur64[g];
       len = (u32)c;
       hot0 = (u32)(c >> 32);
-      iw0 = ((u128)wo.IW[2 * (size_t)g + 1] << 64) | wo.IW[2 * (size_t)g];
     }
-    group_one_w<LT>(CB, CW, seg_start[g], len, g, Lv, vis, wo, hot0, iw0);
+    group_one_w<LT>(CB, CW, seg_start[g], len, g, Lv, vis, wo, hot0, cur64 != nullptr);
   }
 }
 
