@@ -1181,6 +1181,7 @@ constexpr int FT_EPT_W = 2;
 constexpr int FT_ENT = BT_THREADS * FT_EPT;      // far entries per tile
 constexpr int FT_ENT_W = BT_THREADS * FT_EPT_W;  // far entries per tile, weighted graphs
 constexpr int OWN_BUF = 1024;  // entries of another label an own-span tile keeps in LDS (compact staging)
+constexpr int OWN_BUF_W = 512;  // the same for weighted graphs (with weights and run sums: six workgroups per CU)
 
 // Far entries of column block y: colb/rowb ranges [b[y][0], b[y][1]) (rows before span y)
 // and [b[y][2], b[y][3]) (rows after it), row-major.
@@ -1193,7 +1194,7 @@ struct GatherLds {
   static constexpr int PER = 16 / (int)sizeof(LT);             // labels per 16-byte word
   static constexpr int WINV = (BT_ROWS + 2 * BT_HALO) / PER + 1;  // 16-byte words of the label window
   static constexpr int RUN_WORDS = (4 * (BT_ROWS + 1) + 3) & ~3;  // four per-run arrays, padded to 16 bytes
-  static constexpr int BUF = sizeof(LT) == 2 ? OWN_BUF : 0;        // compact staging buffer (16-bit labels)
+  static constexpr int BUF = sizeof(LT) == 2 ? (WT ? OWN_BUF_W : OWN_BUF) : 0;  // compact staging buffer (16-bit labels)
   static constexpr int WBUF = WT ? BUF : 0;                        // the buffered entries' weights
   static constexpr int ISUM = WT ? 4 * BT_ROWS : 0;                // per run: own-label weight sum, two u64
   static constexpr int OWN = RUN_WORDS + 4 * WINV + BUF + WBUF + ISUM;
