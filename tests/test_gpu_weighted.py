@@ -161,6 +161,20 @@ def test_unit_weights_match_unweighted(cq, ctx):
     gw.close()
 
 
+@pytest.mark.parametrize("order", ORDERS)
+def test_random_labels_compact_staging(cq, ctx, order):
+    """Random labels on a column-blocked weighted graph: nearly every entry has another
+    label, so the own-span tiles' staging buffer overflows and the second pass stages;
+    200 ids leave each bucket of the node pass few enough labels for its atomic totals,
+    3000 ids make every bucket write a histogram row."""
+    rp, ci, lab, L = lfr_case("m100k_mu0.3", 14)
+    w = weights_np(rp, ci, 61)
+    n = len(rp) - 1
+    for nl, seed in ((200, 21), (3000, 22)):
+        labr = random_labels(n, nl, seed).numpy()
+        run_case(cq, ctx, rp, ci, w, labr, nl, f"random labels, {nl} ids", order=order, per_comm=False)
+
+
 def test_label_id_limits(cq, ctx):
     rp, ci, lab, L = lfr_case("m100k_mu0.3", 12)
     w = weights_np(rp, ci, 51)
