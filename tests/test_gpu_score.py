@@ -106,6 +106,19 @@ def test_many_labels_global_paths(cq, ctx):
     run_case(cq, ctx, rp, ci, lab3, 70001, "relabelled into 70001 ids", reorder="unblocked")
 
 
+@pytest.mark.parametrize("reorder", ORDERS)
+def test_random_labels_compact_staging(cq, ctx, reorder):
+    """Random labels: nearly every entry has another label, so on a column-blocked graph
+    the own-span tiles' staging buffer overflows and the second pass stages; 200 ids
+    leave each bucket of the node pass few enough labels for its atomic totals, 3000 ids
+    make every bucket write a histogram row."""
+    rp, ci, lab, L = lfr_case("m100k_mu0.3", 15)
+    n = len(rp) - 1
+    for nl, seed in ((200, 23), (3000, 24)):
+        labr = random_labels(n, nl, seed).numpy()
+        run_case(cq, ctx, rp, ci, labr, nl, f"random labels, {nl} ids", reorder=reorder, per_comm=False)
+
+
 def test_wide_counter_wraps(cq, ctx):
     # 40003 label ids select 16-bit LDS counters for large segments.  Community 0 is
     # joined completely to communities 40000 and 40001 (300 x 300 edges each), so both
