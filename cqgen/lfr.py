@@ -166,38 +166,23 @@ def lfr_graph(params: LFRParams, seed: int, device: str | torch.device = "cpu") 
     kin = torch.minimum(kin_want, real_sizes[labels] - 1).clamp_(min=0)
     kout = k - kin
 
-    # 4a. internal wiring inside each community
+    # 4. wiring: internal stubs inside each community, external stubs across the graph,
+    # then rejected stubs rewired into existing edges (see _rewire)
     stubs = torch.repeat_interleave(torch.arange(n, device=device), kin)
     key = labels[stubs] * (1 << 31) + _randint(gen, 1 << 31, stubs.numel(), device)
     stubs = stubs[torch.argsort(key)]
     del key
-    if stubs.numel() % 2:
-        stubs = stubs[:-1]
-    a, b = stubs[0::2], stubs[1::2]
-    keep = (labels[a] == labels[b]) & (a != b)
-    ia, ib = a[keep], b[keep]
-    del stubs, a, b, keep
-
-    # 4b. external wiring across the graph
+    ia, ib, left_in = _pair_stubs(stubs, labels, n, internal=True)
+    del stubs
     stubs = torch.repeat_interleave(torch.arange(n, device=device), kout)
     stubs = stubs[torch.randperm(stubs.numel(), generator=gen, device=device)]
-    if stubs.numel() % 2:
-        stubs = stubs[:-1]
-    a, b = stubs[0::2], stubs[1::2]
-    keep = (labels[a] != labels[b]) & (a != b)
-    ea, eb = a[keep], b[keep]
-    del stubs, a, b, keep
-
-    src = torch.cat([ia, ea])
-    dst = torch.cat([ib, eb])
+    ea, eb, left_ex = _pair_stubs(stubs, labels, n, internal=False)
+    del stubs
+    ia, ib, left_in, ea, eb, left_ex = _rewire(ia, ib, left_in, ea, eb, left_ex, labels, n, K, gen)
+    dropped = int(left_in.numel() + left_ex.numel())
+    lo = torch.cat([torch.minimum(ia, ib), torch.minimum(ea, eb)])
+    hi = torch.cat([torch.maximum(ia, ib), torch.maximum(ea, eb)])
     del ia, ib, ea, eb
-    lo = torch.minimum(src, dst)
-    hi = torch.maximum(src, dst)
-    und = torch.unique(lo * n + hi)                    # simple graph: no multi-edges
-    del src, dst, lo, hi
-    lo = und // n
-    hi = und % n
-    del und
     row_ptr, col_idx = _csr_sym(n, lo, hi)
     graph = LFRGraph(n, row_ptr, col_idx, labels.to(torch.int32), K, params, int(seed))
     deg = (row_ptr[1:] - row_ptr[:-1])
@@ -211,8 +196,125 @@ def lfr_graph(params: LFRParams, seed: int, device: str | torch.device = "cpu") 
         "min_comm": int(real_sizes.min()),
         "max_comm": int(real_sizes.max()),
         "k_min_solved": kmin,
+        "stubs_drawn": int(k.sum()),
+        "stubs_dropped": dropped,
     }
     return graph
+
+
+def _ukey(a: torch.Tensor, b: torch.Tensor, n: int) -> torch.Tensor:
+    return torch.minimum(a, b) * n + torch.maximum(a, b)
+
+
+def _first_of_equal(keys: torch.Tensor) -> torch.Tensor:
+    """Mask of the first occurrence of every value in keys (by position)."""
+    if keys.numel() == 0:
+        return torch.zeros(0, dtype=torch.bool, device=keys.device)
+    sk, idx = torch.sort(keys, stable=True)
+    head = torch.ones_like(sk, dtype=torch.bool)
+    head[1:] = sk[1:] != sk[:-1]
+    keep = torch.zeros_like(head)
+    keep[idx[head]] = True
+    return keep
+
+
+def _pair_stubs(stubs: torch.Tensor, labels: torch.Tensor, n: int, internal: bool):
+    """Pair consecutive stubs; returns the valid simple edges (a, b) and the stubs of the
+    rejected pairs: self-loops, repeats of an edge already formed, and pairs whose ends
+    are in different communities (internal) or in the same one (external)."""
+    odd = stubs[-1:] if stubs.numel() % 2 else stubs[:0]
+    a, b = stubs[0:stubs.numel() - odd.numel():2], stubs[1:stubs.numel() - odd.numel():2]
+    same = labels[a] == labels[b]
+    ok = (same if internal else ~same) & (a != b)
+    ok &= _first_of_equal(torch.where(ok, _ukey(a, b, n), -1 - torch.arange(a.numel(), device=a.device)))
+    left = torch.cat([a[~ok], b[~ok], odd])
+    return a[ok], b[ok], left
+
+
+def _rewire(ia, ib, left_in, ea, eb, left_ex, labels, n: int, K: int, gen, rounds: int = 40):
+    """Give rejected stubs an edge, as the LFR program does, without changing any degree:
+    the rejected stubs are paired again at random (inside their community for internal
+    stubs), and each such pair (a, b) replaces a random existing edge (x, y) of the same
+    kind (internal edges of the same community, or external edges) by (a, x) and (b, y).
+    A replacement is taken only if both new edges are simple, new and of the right kind;
+    replacements that pick the same existing edge or form the same new edge are
+    resolved in favour of the first.  Stubs still rejected after the last round are
+    dropped."""
+    device = labels.device
+    for _ in range(rounds):
+        if left_in.numel() < 2 and left_ex.numel() < 2:
+            break
+        exist = torch.sort(torch.cat([_ukey(ia, ib, n), _ukey(ea, eb, n)])).values
+        moved = 0
+        # internal: pair leftovers inside their community, swap with an internal edge of it
+        if left_in.numel() >= 2 and ia.numel() > 0:
+            key = labels[left_in] * (1 << 31) + _randint(gen, 1 << 31, left_in.numel(), device)
+            s = left_in[torch.argsort(key)]
+            odd = s[-1:] if s.numel() % 2 else s[:0]
+            a, b = s[0:s.numel() - odd.numel():2], s[1:s.numel() - odd.numel():2]
+            pair_ok = labels[a] == labels[b]
+            rest = torch.cat([a[~pair_ok], b[~pair_ok], odd])
+            a, b = a[pair_ok], b[pair_ok]
+            c = labels[a]
+            el = labels[ia]
+            eo = torch.argsort(el, stable=True)
+            cnt = torch.bincount(el, minlength=K)
+            off = torch.cumsum(cnt, 0) - cnt
+            has = cnt[c] > 0
+            rest = torch.cat([rest, a[~has], b[~has]])
+            a, b, c = a[has], b[has], c[has]
+            r = (torch.rand(c.numel(), generator=gen, device=device, dtype=torch.float64) * cnt[c].to(torch.float64)).long()
+            pick = eo[off[c] + torch.minimum(r, cnt[c] - 1)]
+            ia, ib, a, b, done = _swap(ia, ib, pick, a, b, labels, n, exist, internal=True, gen=gen)
+            left_in = torch.cat([rest, a[~done], b[~done]])
+            moved += int(done.sum())
+        # external: pair leftovers anywhere, swap with a random external edge
+        if left_ex.numel() >= 2 and ea.numel() > 0:
+            s = left_ex[torch.randperm(left_ex.numel(), generator=gen, device=device)]
+            odd = s[-1:] if s.numel() % 2 else s[:0]
+            a, b = s[0:s.numel() - odd.numel():2], s[1:s.numel() - odd.numel():2]
+            pick = _randint(gen, ea.numel(), a.numel(), device)
+            ea, eb, a, b, done = _swap(ea, eb, pick, a, b, labels, n, exist, internal=False, gen=gen)
+            left_ex = torch.cat([odd, a[~done], b[~done]])
+            moved += int(done.sum())
+        if moved == 0:
+            break
+    return ia, ib, left_in, ea, eb, left_ex
+
+
+def _swap(ea, eb, pick, a, b, labels, n: int, exist, internal: bool, gen):
+    """Replace edge pick[p] = (x, y) by (a[p], x) and (b[p], y) where allowed; returns the
+    new edge lists, the proposals (a, b) and the mask of those carried out."""
+    device = a.device
+    x, y = ea[pick], eb[pick]
+    flip = torch.rand(a.numel(), generator=gen, device=device) < 0.5
+    x, y = torch.where(flip, y, x), torch.where(flip, x, y)
+    k1, k2 = _ukey(a, x, n), _ukey(b, y, n)
+    ok = (a != x) & (b != y) & (k1 != k2)
+    if internal:
+        ok &= (labels[a] == labels[x]) & (labels[b] == labels[y])
+    else:
+        ok &= (labels[a] != labels[x]) & (labels[b] != labels[y])
+    for kk in (k1, k2):
+        pos = torch.searchsorted(exist, kk).clamp_(max=max(exist.numel() - 1, 0))
+        ok &= exist[pos] != kk
+    idx = torch.arange(a.numel(), device=device)
+    # one replacement per existing edge
+    ok &= _first_of_equal(torch.where(ok, pick, -1 - idx))
+    # new edges distinct among themselves: a proposal is dropped if either edge repeats
+    both = torch.cat([torch.where(ok, k1, -1 - idx), torch.where(ok, k2, -1 - a.numel() - idx)])
+    sk, order = torch.sort(both)
+    dup = torch.zeros_like(sk, dtype=torch.bool)
+    dup[1:] |= sk[1:] == sk[:-1]
+    dup[:-1] |= sk[1:] == sk[:-1]
+    bad = torch.zeros_like(both, dtype=torch.bool)
+    bad[order] = dup
+    ok &= ~(bad[: a.numel()] | bad[a.numel():])
+    keep = torch.ones(ea.numel(), dtype=torch.bool, device=device)
+    keep[pick[ok]] = False
+    na = torch.cat([ea[keep], a[ok], b[ok]])
+    nb = torch.cat([eb[keep], x[ok], y[ok]])
+    return na, nb, a, b, ok
 
 
 def _csr_sym(n: int, lo: torch.Tensor, hi: torch.Tensor):
