@@ -148,7 +148,8 @@ cq_status cq_graph_load(cq_context* ctx, int32_t n, int64_t nnz, const int32_t* 
  * Register an edge-weighted graph: as cq_graph_load, plus
  *   d_weights  DEVICE float[nnz], the weight of every stored entry, BORROWED like the
  *              CSR arrays; finite, in [2^-32, 2^32], and equal for the two entries of
- *              an undirected edge (checked with CQ_VALIDATE_GRAPH).
+ *              an undirected edge.  A weighted load always runs the CQ_VALIDATE_GRAPH
+ *              checks (rows sorted, symmetric, simple) together with that equality.
  * Scoring a weighted graph gives Eqs. 8-9 and the measures of Section II-B3 with
  * weight sums in place of edge counts, while the densities d_c and d_{ci,cj} keep the
  * unweighted counts (the paper's note for weighted networks): see cq_score_result.
@@ -396,13 +397,16 @@ cq_status cq_server_submit_compare(cq_server* srv, int32_t n, const int32_t* h_l
 /* Wait up to timeout_ms (< 0: no limit) for a request, then release its ticket and
  * return its status and result (score_out or compare_out by kind; either may be NULL)
  * and its latency.  Returns CQ_E_BUSY if the request is not finished in time (the
- * ticket stays valid), CQ_E_INVALID_ARG for an unknown ticket. */
+ * ticket stays valid), CQ_E_INVALID_ARG for an unknown ticket or one another thread is
+ * already waiting for. */
 cq_status cq_server_wait(cq_server* srv, uint64_t ticket, double timeout_ms, cq_status* request_status,
                          cq_score_result* score_out, cq_compare_result* compare_out, double* latency_ms);
 cq_status cq_server_get_stats(cq_server* srv, cq_server_stats* out);
 cq_status cq_server_reset_stats(cq_server* srv);
 /* Stop: waiting requests are cancelled (their status becomes CQ_E_CANCELLED), launches
- * in flight finish, then everything is freed.  Tickets not yet waited for are lost. */
+ * in flight finish, threads blocked in cq_server_wait return (with the request's final
+ * status), then everything is freed.  Tickets not yet waited for are lost.  No call on
+ * srv may start once destroy has begun. */
 void cq_server_destroy(cq_server* srv);
 
 #ifdef __cplusplus

@@ -1148,6 +1148,7 @@ struct SrvReq {
   cq_score_result sres{};
   cq_compare_result cres{};
   bool done = false;
+  bool waited = false;  // a thread is waiting for it (one waiter per ticket)
 };
 
 struct SrvSlot {
@@ -1193,6 +1194,7 @@ struct cq_server {
   std::vector<double> lat_ms;
   int64_t submitted = 0, completed = 0, failed = 0, launches = 0, grouped = 0, rejected = 0;
   int inflight = 0;
+  int waiters = 0;  // threads inside cq_server_wait (destroy waits for them to leave)
   double busy_s = 0;
   SrvClock::time_point busy_since;
 };
@@ -1552,7 +1554,10 @@ cq_status graph_load(cq_context* ctx, int32_t n, int64_t nnz, const int32_t* d_r
   if (e != hipSuccess) return fail(ctx, CQ_E_DEVICE, "graph check: %s", hipGetErrorString(e));
   if (res[0]) return fail(ctx, CQ_E_GRAPH_FORMAT, "row_ptr not monotone or col_idx out of range");
   uint32_t validated = 0;
-  if (flags & CQ_VALIDATE_GRAPH) {
+  // weighted graphs are always checked in full: the two entries of an edge must carry
+  // the same weight (W and every weighted sum count each edge once from its two halves),
+  // and that check needs sorted, symmetric rows
+  if ((flags & CQ_VALIDATE_GRAPH) || d_weights) {
     fill(ctx->dscratch, 1, 0, s);
     k_check_symmetric<<<grid_for(n, 4, 8192), 256, 0, s>>>(n, d_row_ptr, d_col_idx, d_weights, ctx->dscratch);
     u32 f = 0;
@@ -1968,9 +1973,16 @@ cq_status cq_server_wait(cq_server* srv, uint64_t ticket, double timeout_ms, cq_
   auto it = srv->reqs.find(ticket);
   if (it == srv->reqs.end()) return fail(srv->ctx, CQ_E_INVALID_ARG, "unknown ticket");
   SrvReq* r = it->second;
+  if (r->waited) return fail(srv->ctx, CQ_E_INVALID_ARG, "another thread is waiting for this ticket");
+  r->waited = true;
+  ++srv->waiters;
   auto ready = [&] { return r->done; };
+  bool ok = true;
   if (timeout_ms < 0) srv->cv_done.wait(lk, ready);
-  else if (!srv->cv_done.wait_for(lk, std::chrono::duration<double, std::milli>(timeout_ms), ready)) return CQ_E_BUSY;
+  else ok = srv->cv_done.wait_for(lk, std::chrono::duration<double, std::milli>(timeout_ms), ready);
+  r->waited = false;
+  if (--srv->waiters == 0 && srv->stop) srv->cv_done.notify_all();  // destroy waits for the last waiter
+  if (!ok) return CQ_E_BUSY;
   if (request_status) *request_status = r->status;
   if (score_out && r->kind == 0) *score_out = r->sres;
   if (compare_out && r->kind == 1) *compare_out = r->cres;
@@ -2030,7 +2042,13 @@ void cq_server_destroy(cq_server* srv) {
   }
   srv->cv_work.notify_all();
   if (srv->worker.joinable()) srv->worker.join();
-  srv->cv_done.notify_all();
+  {
+    // every request is now finished or cancelled: wake the waiting threads and let them
+    // leave cq_server_wait before the server's memory goes
+    std::unique_lock<std::mutex> lk(srv->mu);
+    srv->cv_done.notify_all();
+    srv->cv_done.wait(lk, [&] { return srv->waiters == 0; });
+  }
   for (SrvSlot* sl : srv->slots) {
     if (sl->stream) (void)hipStreamSynchronize(sl->stream);
     if (sl->ctx) cq_context_destroy(sl->ctx);

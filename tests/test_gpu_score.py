@@ -51,7 +51,7 @@ def run_case(cq, ctx, rp, ci, lab, L, what, *, validate=True, pairs=True, per_co
     torch.cuda.synchronize()
     check_score(r, o.result, what)
     if per_comm:
-        check_per_community(pc, o)
+        check_per_community(pc, o, int(o.result["m"]))
     if pairs:
         assert np.array_equal(sort_rows(pt), o.pairs), f"{what}: pair table differs"
     g.close()
@@ -255,7 +255,7 @@ def test_full_size_l10m(cq, ctx):
         r, pc, pt = cq.score_partition(g, gr.labels, gr.num_labels, per_community=True,
                                        pairs_capacity=int(o.result["num_pairs"]))
         check_score(r, o.result, f"l10m reorder={reorder}")
-        check_per_community(pc, o)
+        check_per_community(pc, o, int(o.result["m"]))
         assert np.array_equal(sort_rows(pt), o.pairs)
     # label ids beyond the LDS histograms: global-atomic node pass after the staged move
     lab2 = (lab.astype(np.int64) * 7919 % 40009).astype(np.int32)

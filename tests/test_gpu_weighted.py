@@ -11,7 +11,7 @@ import torch
 
 import oracle
 from cqgen import CONFIGS, csr_from_edges, edge_weights, erdos_renyi, lfr_graph, perturb_labels, random_labels
-from tests.gpu_util import ABS, REL, check_score, fclose, note, sort_rows
+from tests.gpu_util import SCORE_SCALE, array_mismatch, check_score, fclose, note, per_community_scales, sort_rows
 
 pytestmark = pytest.mark.gpu
 
@@ -52,12 +52,13 @@ def check_weighted(r: dict, o, what: str, per_comm=None, pairs=None):
             bad.append(f"{gk}: gpu {r[gk]!r} oracle {o.result[ok]!r}")
     assert not bad, f"{what}: " + "; ".join(bad)
     if per_comm is not None:
-        for k in ("intra_density", "contraction", "expansion", "conductance", "q_term", "qds_term", "w_in",
-                  "strength"):
-            g = per_comm[k].cpu().numpy()
-            e = getattr(o, k)
-            tol = np.maximum(REL * np.abs(e), ABS)
-            assert (np.abs(g - e) <= tol).all(), (what, k, float(np.max(np.abs(g - e))))
+        # ratios and positive weight sums: 1e-12 relative; the Eq. (8) and (9) brackets with
+        # the near-zero bound scaled by their own terms
+        s_q, s_qds = per_community_scales(o.w_in, o.strength, o.intra_density, o.qds_term, float(o.result["W"]))
+        for k, s in (("intra_density", 0.0), ("contraction", 0.0), ("expansion", 0.0), ("conductance", 0.0),
+                     ("w_in", 0.0), ("strength", 0.0), ("q_term", s_q), ("qds_term", s_qds)):
+            ex = array_mismatch(per_comm[k].cpu().numpy(), getattr(o, k), s)
+            assert ex <= 0, (what, k, ex)
         # integer per-community fields are the unweighted counts
         size = per_comm["size"].cpu().numpy()
         ein = per_comm["ein"].cpu().numpy()
@@ -156,7 +157,7 @@ def test_unit_weights_match_unweighted(cq, ctx):
     assert rw["sum_w_in"] == ru["sum_ein"] and rw["sum_w_out"] == ru["sum_eout"]
     for k in ("Q", "Qds", "split_penalty", "mean_intra_edges", "mean_intra_density", "mean_contraction",
               "mean_inter_edges", "mean_expansion", "mean_conductance"):
-        assert fclose(rw[k], ru[k]), (k, rw[k], ru[k])
+        assert fclose(rw[k], ru[k], SCORE_SCALE.get(k, 0.0)), (k, rw[k], ru[k])
     gu.close()
     gw.close()
 
@@ -212,7 +213,12 @@ def test_load_errors(cq, ctx):
     with pytest.raises(cq.CQError) as e:
         cq.Graph(ctx, rp_t, ci_t, validate=True, weights=torch.as_tensor(wa).cuda())
     assert e.value.status == cq.CQ_E_GRAPH_FORMAT
-    g = cq.Graph(ctx, rp_t, ci_t, validate=False, weights=torch.as_tensor(wa).cuda())  # not checked without validation
+    # a weighted load checks the mirror weights whether or not validation was asked for
+    with pytest.raises(cq.CQError) as e:
+        cq.Graph(ctx, rp_t, ci_t, validate=False, weights=torch.as_tensor(wa).cuda())
+    assert e.value.status == cq.CQ_E_GRAPH_FORMAT
+    g = cq.Graph(ctx, rp_t, ci_t, validate=False, weights=torch.as_tensor(w).cuda())
+    assert g.stats["validated"] == cq.CQ_VALIDATE_GRAPH
     g.close()
     note("null weights")
     with pytest.raises(cq.CQError) as e:
@@ -245,9 +251,11 @@ def test_label_error_and_batch_and_server(cq, ctx):
     srv = cq.Server(ctx, num_slots=2, max_batch=8, memory_budget=1 << 30, small_nnz=1_000_000)
     h = lab_t.cpu().pin_memory()
     tickets = [srv.submit_score(g, h, L) for _ in range(3)]
+    o = oracle.score_w(rp, ci, w, lab, L, want_pairs=False)
     for t in tickets:
         out = srv.wait(t)
         assert out["status"] == cq.CQ_OK and out["score"] == direct
+        check_weighted(out["score"], o, "weighted served request vs oracle")
     assert srv.stats()["grouped_requests"] == 0
     srv.close()
     g.close()
