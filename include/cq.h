@@ -257,6 +257,32 @@ cq_status cq_score_partition_async(cq_context* ctx, const cq_graph* g, const int
                                    cq_score_result* d_out, const cq_per_community* per_comm,
                                    const cq_pair_table* pairs);
 
+/* ---- scoring without a workspace (callers that cannot allocate) ------------- */
+
+/* Bytes of the library's own scratch array (one per device). */
+#define CQ_SCRATCH_BYTES (64u << 20)
+
+/*
+ * For callers that cannot allocate device memory: code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc.  Same as cq_score_partition (same
+ * outputs, bit for bit), with the library's own scratch array of CQ_SCRATCH_BYTES in
+ * place of the caller's workspace; the caller still provides labels and the optional
+ * per_comm / pairs outputs.  The array is device memory the library holds on every GPU
+ * it runs on until the process ends; its address on a device is looked up once, when
+ * the first context on that device is created.  The call allocates nothing (no
+ * hipMalloc, hipFree or allocating library routine) and clears what must start at zero.
+ * Every call on one GPU shares that GPU's array: calls that overlap on one GPU (from
+ * several contexts, threads or streams) race and give undefined results; calls on one
+ * stream are ordered and safe.
+ * Errors: those of cq_score_partition, plus CQ_E_WORKSPACE when the call would need more
+ * than CQ_SCRATCH_BYTES (cq_score_workspace_size(g, num_labels) says how much; about
+ * 2 bytes per stored entry plus a few bytes per node and per label), and CQ_E_DEVICE if
+ * the array's device address could not be found.  Synchronous.
+ */
+cq_status cq_score_partition_noalloc(cq_context* ctx, const cq_graph* g, const int32_t* d_labels, int32_t num_labels,
+                                     cq_score_result* h_out, const cq_per_community* per_comm,
+                                     const cq_pair_table* pairs);
+
 /* ---- batched scoring (many graphs x many partitions) ------------------------ */
 
 /* A batch scores many (graph, partition) tasks with one launch per stage of the

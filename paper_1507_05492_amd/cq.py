@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(HERE, "libcq.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "cq.h")
 
 CQ_OK = 0
+CQ_SCRATCH_BYTES = 64 << 20  # include/cq.h: the library's per-device scratch array
 CQ_E_INVALID_ARG = -1
 CQ_E_LABEL_RANGE = -2
 CQ_E_GRAPH_FORMAT = -3
@@ -122,6 +123,7 @@ def _load():
         "cq_score_workspace_size": (_SZ, [_P, _I32]),
         "cq_score_partition": (_I32, [_P, _P, _P, _I32, _P, _SZ, ctypes.POINTER(ScoreResult), _P, _P]),
         "cq_score_partition_async": (_I32, [_P, _P, _P, _I32, _P, _SZ, _P, _P, _P]),
+        "cq_score_partition_noalloc": (_I32, [_P, _P, _P, _I32, ctypes.POINTER(ScoreResult), _P, _P]),
         "cq_compare_workspace_size": (_SZ, [_I32, _I32, _I32]),
         "cq_compare_partitions": (_I32, [_P, _I32, _P, _I32, _P, _I32, _P, _SZ, ctypes.POINTER(CompareResult), _P]),
         "cq_compare_partitions_async": (_I32, [_P, _I32, _P, _I32, _P, _I32, _P, _SZ, _P, _P]),
@@ -278,6 +280,15 @@ def cq_score_partition(ctx, g, d_labels, num_labels, d_ws, ws_bytes, per_comm: P
     st = _lib.cq_score_partition(ctx, g, d_labels, num_labels, d_ws, ws_bytes, ctypes.byref(res),
                                  ctypes.byref(per_comm) if per_comm is not None else None,
                                  ctypes.byref(pairs) if pairs is not None else None)
+    return _check(ctx, st, allow), res
+
+
+def cq_score_partition_noalloc(ctx, g, d_labels, num_labels, per_comm: PerCommunity | None = None,
+                               pairs: PairTable | None = None, allow=(CQ_OK,)) -> tuple[int, ScoreResult]:
+    res = ScoreResult()
+    st = _lib.cq_score_partition_noalloc(ctx, g, d_labels, num_labels, ctypes.byref(res),
+                                         ctypes.byref(per_comm) if per_comm is not None else None,
+                                         ctypes.byref(pairs) if pairs is not None else None)
     return _check(ctx, st, allow), res
 
 
@@ -494,15 +505,18 @@ class Graph:
 
 
 def score_partition(graph: Graph, labels, num_labels: int, *, per_community: bool = False,
-                    pairs_capacity: int = 0, workspace=None, allow=(CQ_OK,)):
-    """Score a partition; returns (result dict, per-community dict | None, pairs tensor | None)."""
+                    pairs_capacity: int = 0, workspace=None, noalloc: bool = False, allow=(CQ_OK,)):
+    """Score a partition; returns (result dict, per-community dict | None, pairs tensor | None).
+    noalloc=True calls cq_score_partition_noalloc (the library's scratch array, no workspace)."""
     torch = _torch()
     labels = _dev_i32(labels, "labels")
     if labels.numel() != graph.n:
         raise ValueError("labels must have one entry per node")
     ctx = graph.ctx
-    need = graph.workspace_size(num_labels)
-    ws = workspace if workspace is not None else ctx.workspace(need)
+    ws = None
+    if not noalloc:
+        need = graph.workspace_size(num_labels)
+        ws = workspace if workspace is not None else ctx.workspace(need)
     dev = labels.device
     pc = None
     pc_t = None
@@ -519,8 +533,11 @@ def score_partition(graph: Graph, labels, num_labels: int, *, per_community: boo
                  torch.empty(pairs_capacity, dtype=torch.int32, device=dev),
                  torch.empty(pairs_capacity, dtype=torch.int64, device=dev))
         pt = PairTable(pairs[0].data_ptr(), pairs[1].data_ptr(), pairs[2].data_ptr(), pairs_capacity)
-    st, res = cq_score_partition(ctx.handle, graph.handle, labels.data_ptr(), num_labels, ws.data_ptr(),
-                                 ws.numel(), pc, pt, allow=allow)
+    if noalloc:
+        st, res = cq_score_partition_noalloc(ctx.handle, graph.handle, labels.data_ptr(), num_labels, pc, pt, allow=allow)
+    else:
+        st, res = cq_score_partition(ctx.handle, graph.handle, labels.data_ptr(), num_labels, ws.data_ptr(),
+                                     ws.numel(), pc, pt, allow=allow)
     r = as_dict(res)
     r["status"] = st
     pair_tensor = None

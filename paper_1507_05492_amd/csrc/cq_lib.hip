@@ -25,6 +25,7 @@ using namespace cq;
 
 struct cq_context {
   int device = 0;
+  void* scratch = nullptr;  // device address of the library's scratch array on this device
   hipStream_t stream = nullptr;
   int num_cus = 256;
   void* pinned = nullptr;  // host staging for result structs (hipHostMalloc)
@@ -133,6 +134,30 @@ static_assert(sizeof(CmpResultDev) == sizeof(cq_compare_result), "compare result
 static_assert(sizeof(PerComm) == sizeof(cq_per_community), "per-community layout");
 
 namespace {
+
+// ---- per-device scratch array (cq_score_partition_noalloc) ---------------------
+// Device memory the library holds for callers that cannot allocate a workspace.  Each
+// GPU the library is loaded on has its own copy, at its own address, until the process
+// ends.  In host code `scratch` names a host-side stand-in, never the device memory:
+// its address on a device comes from hipGetSymbolAddress, taken once per device when
+// the first context on that device is created and kept in g_scratch_addr.
+constexpr size_t SCRATCH_BYTES = (size_t)CQ_SCRATCH_BYTES;
+constexpr int SCRATCH_DEVICES = 64;
+__device__ __align__(256) unsigned char scratch[SCRATCH_BYTES];
+std::mutex g_scratch_mu;
+void* g_scratch_addr[SCRATCH_DEVICES] = {};
+
+// Device address of the scratch array on `device` (which must be current), or null.
+void* scratch_address(int device) {
+  if (device < 0 || device >= SCRATCH_DEVICES) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_addr[device]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess) return nullptr;
+    g_scratch_addr[device] = p;
+  }
+  return g_scratch_addr[device];
+}
 
 constexpr int64_t PRIV_MAX = 16384;    // labels handled by LDS-private node histograms
 constexpr int64_t DIRECT_MAX = 16384;  // labels handled by direct-indexed group tables
@@ -1439,6 +1464,7 @@ cq_status cq_context_create(int device, void* hip_stream, cq_context** out) {
   if (!ctx) return CQ_E_DEVICE;
   ctx->device = device;
   ctx->stream = static_cast<hipStream_t>(hip_stream);
+  ctx->scratch = scratch_address(device);  // null if the symbol lookup fails (noalloc calls then refuse)
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, device) == hipSuccess) ctx->num_cus = prop.multiProcessorCount;
   if (hipHostMalloc(&ctx->pinned, 4096, hipHostMallocDefault) != hipSuccess ||
@@ -1692,6 +1718,20 @@ cq_status cq_score_partition(cq_context* ctx, const cq_graph* g, const int32_t* 
   st = fetch(ctx, d_res, h_out);
   if (st != CQ_OK) return st;
   return map_flags(ctx, h_out->device_flags);
+}
+
+cq_status cq_score_partition_noalloc(cq_context* ctx, const cq_graph* g, const int32_t* d_labels, int32_t num_labels,
+                                     cq_score_result* h_out, const cq_per_community* per_comm, const cq_pair_table* pairs) {
+  if (!ctx) return CQ_E_INVALID_ARG;
+  ctx->err[0] = 0;
+  if (!h_out || !g) return fail(ctx, CQ_E_INVALID_ARG, "null graph or result pointer");
+  if (!ctx->scratch) return fail(ctx, CQ_E_DEVICE, "the scratch array's address on device %d is unknown", ctx->device);
+  const size_t need = graph_score_layout(g, std::max(num_labels, 1)).total;
+  if (need > SCRATCH_BYTES)
+    return fail(ctx, CQ_E_WORKSPACE, "this call needs %zu bytes of scratch; the library's array holds %zu "
+                "(score with a caller workspace instead)", need, SCRATCH_BYTES);
+  // the kernels clear what they need at the start of every call, as with a caller workspace
+  return cq_score_partition(ctx, g, d_labels, num_labels, ctx->scratch, SCRATCH_BYTES, h_out, per_comm, pairs);
 }
 
 cq_status cq_compare_partitions_async(cq_context* ctx, int32_t n, const int32_t* d_labels_a, int32_t num_labels_a,
