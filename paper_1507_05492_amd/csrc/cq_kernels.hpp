@@ -723,19 +723,25 @@ __global__ __launch_bounds__(1024) void k_perm_apply(int n, const u32* __restric
 
 // STAGED: the labels were already moved to the stored order into labx (sentinel = out of
 // range); otherwise they are read from labels[perm[u]] (or labels[u]) and written to labx.
+// Label range: the LDS histograms hold the LR labels [lbase, lbase + LR); a label space
+// wider than the LDS budget is counted in several launches, one per range, each node in
+// the launch whose range holds its label (which gives its offset loc[u]).  The launch
+// with lbase = 0 also flags invalid labels and writes labx; the others skip nodes with
+// invalid labels.
 template <bool WEIGHTED, class LT, bool STAGED = false>
 __device__ __forceinline__ void node_priv_body(int n, const int32_t* __restrict__ labels, const int32_t* __restrict__ perm,
                                                const int32_t* __restrict__ rp, int L, int chunk, u32* __restrict__ HN,
                                                u32* __restrict__ HD, u32* __restrict__ loc, LT* __restrict__ labx,
-                                               Ctl* __restrict__ ctl, int blk) {
+                                               Ctl* __restrict__ ctl, int blk, int lbase, int LR) {
   extern __shared__ u32 sh[];
   u32* hn = sh;
-  u32* hd = WEIGHTED ? sh + L : sh;
+  u32* hd = WEIGHTED ? sh + LR : sh;
   __shared__ u32 s_bad;
-  const int words = WEIGHTED ? 2 * L : L;
+  const int words = WEIGHTED ? 2 * LR : LR;
   for (int i = threadIdx.x; i < words; i += blockDim.x) sh[i] = 0;
   if (threadIdx.x == 0) s_bad = 0;
   __syncthreads();
+  const bool first = lbase == 0;
   const long long u0 = (long long)blk * chunk;
   const long long u1 = min((long long)n, u0 + chunk);
   const int lane = threadIdx.x & 63;
@@ -751,23 +757,25 @@ __device__ __forceinline__ void node_priv_body(int n, const int32_t* __restrict_
       c = in ? labels[perm ? perm[u] : u] : 0;
     }
     const bool valid = in && (u32)c < (u32)L;
-    if (in && !valid) {
+    if (first && in && !valid) {
       bad = 1;
       loc[u] = SENT;
       if (labx && !STAGED) labx[u] = LabelT<LT>::SENTINEL;
     }
-    const u32 w = valid ? (WEIGHTED ? (u32)(rp[u + 1] - rp[u]) : 1u) : 0u;
+    const int cl = c - lbase;
+    const bool here = valid && (u32)cl < (u32)LR;
+    const u32 w = here ? (WEIGHTED ? (u32)(rp[u + 1] - rp[u]) : 1u) : 0u;
     // Lanes with equal labels (common when the graph is stored in a locality order)
     // add to the LDS histogram through one leader lane; each lane's offset is the
     // leader's old value plus the weights of the group's lower lanes.
-    bool pending = valid;
+    bool pending = here;
     u32 old = 0;
     for (int round = 0; round < 4; ++round) {
       const u64 act = __ballot(pending);
       if (act == 0) break;
       const int leader = __ffsll((long long)act) - 1;
-      const int lc = __shfl(c, leader, 64);
-      const bool mine = pending && c == lc;
+      const int lc = __shfl(cl, leader, 64);
+      const bool mine = pending && cl == lc;
       const u64 grp = __ballot(mine);
       if (__popcll(grp) < 4) break;  // mixed labels: plain atomics below
       const u32 pw = mine ? w : 0u;
@@ -785,18 +793,16 @@ __device__ __forceinline__ void node_priv_body(int n, const int32_t* __restrict_
       }
     }
     if (pending) {
-      if (WEIGHTED) atomicAdd(&hn[c], 1u);
-      old = atomicAdd(&hd[c], w);
+      if (WEIGHTED) atomicAdd(&hn[cl], 1u);
+      old = atomicAdd(&hd[cl], w);
     }
-    if (valid) {
-      loc[u] = old;
-      if (labx && !STAGED) labx[u] = (LT)c;
-    }
+    if (here) loc[u] = old;
+    if (first && valid && labx && !STAGED) labx[u] = (LT)c;
   }
   if (bad) s_bad = 1;
   __syncthreads();
-  size_t row = (size_t)blk * (size_t)L;
-  for (int c = threadIdx.x; c < L; c += blockDim.x) {
+  const size_t row = (size_t)blk * (size_t)L + (size_t)lbase;
+  for (int c = threadIdx.x; c < LR; c += blockDim.x) {
     HN[row + c] = hn[c];
     if (WEIGHTED) HD[row + c] = hd[c];
   }
@@ -807,8 +813,8 @@ template <bool WEIGHTED, class LT, bool STAGED = false>
 __global__ __launch_bounds__(1024) void k_node_priv(int n, const int32_t* __restrict__ labels, const int32_t* __restrict__ perm,
                                                     const int32_t* __restrict__ rp, int L, int chunk, u32* __restrict__ HN,
                                                     u32* __restrict__ HD, u32* __restrict__ loc, LT* __restrict__ labx,
-                                                    Ctl* __restrict__ ctl) {
-  node_priv_body<WEIGHTED, LT, STAGED>(n, labels, perm, rp, L, chunk, HN, HD, loc, labx, ctl, blockIdx.x);
+                                                    Ctl* __restrict__ ctl, int lbase, int LR) {
+  node_priv_body<WEIGHTED, LT, STAGED>(n, labels, perm, rp, L, chunk, HN, HD, loc, labx, ctl, blockIdx.x, lbase, LR);
 }
 
 // Node pass with global atomics (too many labels for LDS).  SZ[c] packs
@@ -868,24 +874,30 @@ __global__ __launch_bounds__(256) void k_node_global(int n, const int32_t* __res
   if (bad) atomicOr(&ctl->flags, F_LABEL);
 }
 
-// Plain label histogram (no slots): detected-partition sizes |c'| for the comparison.
+// Plain label histogram (no slots): detected-partition sizes |c'| for the comparison,
+// for the LR labels [lbase, lbase + LR) (one launch per range, as in the node pass; the
+// launch with lbase = 0 flags invalid labels).
 __global__ __launch_bounds__(1024) void k_hist_priv(int n, const int32_t* __restrict__ labels, int L, u32* __restrict__ HN,
-                                                    Ctl* __restrict__ ctl) {
+                                                    Ctl* __restrict__ ctl, int lbase, int LR) {
   extern __shared__ u32 sh[];
   __shared__ u32 s_bad;
-  for (int i = threadIdx.x; i < L; i += blockDim.x) sh[i] = 0;
+  for (int i = threadIdx.x; i < LR; i += blockDim.x) sh[i] = 0;
   if (threadIdx.x == 0) s_bad = 0;
   __syncthreads();
   u32 bad = 0;
   for (size_t u = (size_t)blockIdx.x * blockDim.x + threadIdx.x; u < (size_t)n; u += (size_t)gridDim.x * blockDim.x) {
-    int c = labels[u];
-    if ((u32)c >= (u32)L) { bad = 1; continue; }
-    atomicAdd(&sh[c], 1u);
+    const int c = labels[u];
+    if ((u32)c >= (u32)L) {
+      bad = 1;
+      continue;
+    }
+    const int cl = c - lbase;
+    if ((u32)cl < (u32)LR) atomicAdd(&sh[cl], 1u);
   }
-  if (bad) s_bad = 1;
+  if (bad && lbase == 0) s_bad = 1;
   __syncthreads();
-  size_t row = (size_t)blockIdx.x * (size_t)L;
-  for (int c = threadIdx.x; c < L; c += blockDim.x) HN[row + c] = sh[c];
+  const size_t row = (size_t)blockIdx.x * (size_t)L + (size_t)lbase;
+  for (int c = threadIdx.x; c < LR; c += blockDim.x) HN[row + c] = sh[c];
   if (threadIdx.x == 0 && s_bad) atomicOr(&ctl->flags, F_LABEL);
 }
 
@@ -2840,7 +2852,7 @@ __global__ __launch_bounds__(1024) void k_b_node(const TaskDev* __restrict__ td,
   const int t = find_seg(Wpre, T, blockIdx.x);
   const TaskDev& d = td[t];
   node_priv_body<true, uint16_t>(d.n, d.labels, d.perm, d.rp, d.L, d.chunk, d.HN, d.HD, d.loc, d.labx, d.ctl,
-                                 (int)(blockIdx.x - Wpre[t]));
+                                 (int)(blockIdx.x - Wpre[t]), 0, d.L);
 }
 
 __global__ __launch_bounds__(256) void k_b_colscan(const TaskDev* __restrict__ td, const u32* __restrict__ Lpre, int T) {

@@ -159,7 +159,8 @@ void* scratch_address(int device) {
   return g_scratch_addr[device];
 }
 
-constexpr int64_t PRIV_MAX = 16384;    // labels handled by LDS-private node histograms
+constexpr int64_t PRIV_MAX = 16384;    // labels one LDS-private node-histogram launch holds
+constexpr int64_t RANGE_MAX = 8 * PRIV_MAX;  // labels counted in LDS-private launches, PRIV_MAX per range
 constexpr int64_t DIRECT_MAX = 16384;  // labels handled by direct-indexed group tables
 constexpr u32 HASH_WORDS = 32768;      // LDS words of the group hash table (16384 slots)
 constexpr size_t ALIGN = 256;    // offsets of the arrays carved from a workspace
@@ -224,6 +225,8 @@ int pick_chunk(int64_t n, int64_t max_chunk = 65536) {
   while (c < max_chunk && c * 256 < n) c <<= 1;
   return (int)c;
 }
+// Node chunk limit when the labels span several LDS ranges (the histogram rows are W x L).
+constexpr int64_t RANGE_CHUNK_MAX = 1 << 18;
 // The caller-order node pass of column-blocked graphs (k_node_perm) is bound by its
 // scattered label stores and gains from more, smaller workgroups; its column scan only
 // needs totals, so the extra histogram rows cost little.
@@ -246,10 +249,11 @@ struct ScoreLayout {
 ScoreLayout score_layout(int64_t n, int64_t nnz, int64_t L, bool weighted = false, int64_t max_chunk = 65536) {
   ScoreLayout s{};
   Carve c;
-  s.priv = L <= PRIV_MAX;
+  s.priv = L <= RANGE_MAX;
   s.small = L <= 65535;
   const size_t lt = s.small ? 2 : 4;
-  s.chunk = pick_chunk(n, max_chunk);
+  // several label ranges: fewer, larger node chunks keep the W x L histogram rows small
+  s.chunk = pick_chunk(n, L > PRIV_MAX ? RANGE_CHUNK_MAX : max_chunk);
   s.W = (int)((n + s.chunk - 1) / s.chunk);
   s.G = (int)std::min<int64_t>(128, std::max<int64_t>(1, (L + 1023) / 1024));
   s.ctl = c.take(sizeof(Ctl));
@@ -296,10 +300,10 @@ struct CmpLayout {
 CmpLayout cmp_layout(int64_t n, int64_t La, int64_t Lb) {
   CmpLayout s{};
   Carve c;
-  s.privA = La <= PRIV_MAX;
-  s.privB = Lb <= PRIV_MAX;
+  s.privA = La <= RANGE_MAX;
+  s.privB = Lb <= RANGE_MAX;
   s.small = Lb <= 65535;
-  s.chunk = pick_chunk(n);
+  s.chunk = pick_chunk(n, La > PRIV_MAX ? RANGE_CHUNK_MAX : 65536);
   s.W = (int)((n + s.chunk - 1) / s.chunk);
   s.Wb = (int)std::min<int64_t>(256, std::max<int64_t>(1, (n + 8191) / 8192));
   s.Ga = (int)std::min<int64_t>(64, std::max<int64_t>(1, (La + 1023) / 1024));
@@ -390,11 +394,11 @@ void score_launch(cq_context* ctx, const cq_graph* g, const int32_t* labels, int
     if (!lay.priv) fill(at<u32>(ws, lay.SZ), 2 * (size_t)L, 0, s);
     // run cursors of column-blocked graphs: cleared by the column scan on the
     // private-histogram path, here otherwise
-    if (g->rpb && !(lay.priv && g->pos1)) fill(at<u32>(ws, lay.cursor), 2 * (size_t)L, 0, s);
+    if (g->rpb && !(L <= PRIV_MAX && g->pos1)) fill(at<u32>(ws, lay.cursor), 2 * (size_t)L, 0, s);
     // weighted column-blocked graphs: the edge pass adds each community's own-label weights here
     if (CW && g->rpb) fill(at<u32>(ws, lay.IW), 4 * (size_t)L, 0, s);
   }
-  if (lay.priv && g->rpb && g->pos1) {
+  if (L <= PRIV_MAX && g->rpb && g->pos1) {
     // column-blocked graph: move the labels with the bucket plan and count per label (the
     // blocked edge pass needs no per-node offsets)
     u32* HN = at<u32>(ws, lay.HN);
@@ -437,14 +441,18 @@ void score_launch(cq_context* ctx, const cq_graph* g, const int32_t* labels, int
     u32* HD = at<u32>(ws, lay.HD);
     {
       StageMark mk(ctx, ST_NODE, timed);
-      if (g->pos1) {
-        // move the labels to the stored order first (streaming), then count in that order
-        stage_labels<LT>(g, labels, L, reinterpret_cast<LT*>(loc), labx, ctl, s);
-        k_node_priv<true, LT, true><<<lay.W, 1024, 2 * (size_t)L * 4, s>>>((int)n, labels, g->perm, g->rp, L, lay.chunk, HN, HD,
-                                                                         loc, labx, ctl);
-      } else {
-        k_node_priv<true, LT><<<lay.W, 1024, 2 * (size_t)L * 4, s>>>((int)n, labels, g->perm, g->rp, L, lay.chunk, HN, HD, loc,
-                                                                     labx, ctl);
+      // move the labels to the stored order first (streaming), then count in that order;
+      // without a plan the first range's launch reads them and writes labx
+      if (g->pos1) stage_labels<LT>(g, labels, L, reinterpret_cast<LT*>(loc), labx, ctl, s);
+      for (int64_t lb = 0; lb < L; lb += PRIV_MAX) {
+        const int lr = (int)std::min<int64_t>(PRIV_MAX, L - lb);
+        const size_t shm = 2 * (size_t)lr * 4;
+        if (g->pos1 || lb > 0)
+          k_node_priv<true, LT, true><<<lay.W, 1024, shm, s>>>((int)n, labels, g->perm, g->rp, L, lay.chunk, HN, HD, loc, labx,
+                                                             ctl, (int)lb, lr);
+        else
+          k_node_priv<true, LT><<<lay.W, 1024, shm, s>>>((int)n, labels, g->perm, g->rp, L, lay.chunk, HN, HD, loc, labx, ctl, 0,
+                                                         lr);
       }
     }
     {
@@ -604,8 +612,11 @@ void compare_launch(cq_context* ctx, int32_t n, const int32_t* la, int32_t La, c
     u32* HN = at<u32>(ws, lay.HN);
     {
       StageMark mk(ctx, ST_NODE, timed);
-      k_node_priv<false, uint32_t><<<lay.W, 1024, (size_t)La * 4, s>>>(n, la, nullptr, nullptr, La, lay.chunk, HN, nullptr, loc,
-                                                                       nullptr, ctl);
+      for (int64_t lb = 0; lb < La; lb += PRIV_MAX) {
+        const int lr = (int)std::min<int64_t>(PRIV_MAX, La - lb);
+        k_node_priv<false, uint32_t><<<lay.W, 1024, (size_t)lr * 4, s>>>(n, la, nullptr, nullptr, La, lay.chunk, HN, nullptr, loc,
+                                                                         nullptr, ctl, (int)lb, lr);
+      }
     }
     {
       StageMark mk(ctx, ST_COLSCAN, timed);
@@ -627,7 +638,10 @@ void compare_launch(cq_context* ctx, int32_t n, const int32_t* la, int32_t La, c
     StageMark mk(ctx, ST_HIST_B, timed);
     if (lay.privB) {
       u32* HB = at<u32>(ws, lay.HB);
-      k_hist_priv<<<lay.Wb, 1024, (size_t)Lb * 4, s>>>(n, lb, Lb, HB, ctl);
+      for (int64_t b0 = 0; b0 < Lb; b0 += PRIV_MAX) {
+        const int br = (int)std::min<int64_t>(PRIV_MAX, Lb - b0);
+        k_hist_priv<<<lay.Wb, 1024, (size_t)br * 4, s>>>(n, lb, Lb, HB, ctl, (int)b0, br);
+      }
       k_colscan<false, false><<<colscan_grid(Lb), CS_LABELS * CS_GROUPS, 0, s>>>(lay.Wb, Lb, HB, HB, B, nullptr);
     } else {
       k_hist_global<<<grid_for(n, 256, 8192), 256, 0, s>>>(n, lb, Lb, B, ctl);
