@@ -44,6 +44,16 @@ def algorithmic_bytes(n: int, nnz: int) -> int:
     return 4 * nnz + 8 * n
 
 
+def kernel_names(L: int, blocked: bool) -> dict:
+    """Profiler names of the unweighted kernels of each stage (namespace dropped)."""
+    lt = "unsigned short" if L <= 65535 else "unsigned int"
+    priv = "true" if L <= 131072 else "false"  # LDS-private node histograms (in label ranges)
+    return {"edge_gather": f"k_gather_blocked<{lt}, false>" if blocked else f"k_gather<{priv}, {lt}, false>",
+            "group_count": f"k_groups<ScoreVis, {lt}>",
+            "node_pass": f"k_node_scatter<{lt}>" if blocked else f"k_node_priv<true, {lt}, true>",
+            "final_reduce": "k_score_final1", "column_scan": "k_colscan", "scan_order": "k_scan_order"}
+
+
 def traffic_for(kernel: str):
     """Measured HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated),
     valid only if the kernels are unchanged since the counters were taken."""
@@ -70,6 +80,9 @@ def main() -> int:
     ap.add_argument("--order", default="locality", choices=["locality", "input"],
                     help="graph storage order: 'locality' loads with CQ_GRAPH_REORDER (default), 'input' keeps node ids")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="l10m: skip the reassigned/random partitions and the 100M-node line")
+    ap.add_argument("--no-s100m", action="store_true", help="l10m: skip the 100M-node line")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one plain 1 GiB device-to-device copy (a known-size reference for HBM counters)")
     args = ap.parse_args()
@@ -112,7 +125,7 @@ def main() -> int:
     ctx = cq.Context(0)
     labels = g.labels
 
-    def timed_run(graph, steps, warmup):
+    def timed_run(graph, steps, warmup, labels=labels, L=L):
         """Warmup, then a few steps with every stage timed (the stage breakdown and the
         dominant stage), then the timed steps with events around the dominant stage only:
         each timed stage costs a few microseconds of device time.  Returns the result,
@@ -155,13 +168,7 @@ def main() -> int:
     log(f"{ms_per_step:.3f} ms/step, {gedges:.1f} GEdges/s; {dom} {dom_ms:.3f} ms; stages (all timed) " +
         ", ".join(f"{k}={v:.3f}ms" for k, v in stage_avg.items()))
     blocked = graph.stats["reordered"] == cq.CQ_GRAPH_REORDER  # renumbered and stored in column blocks
-    # kernel names as the profiler prints them (namespace dropped): the unweighted instantiations
-    lt = "unsigned short" if L <= 65535 else "unsigned int"
-    priv = "true" if L <= 16384 else "false"
-    kernel_of = {"edge_gather": f"k_gather_blocked<{lt}, false>" if blocked else f"k_gather<{priv}, {lt}, false>",
-                 "group_count": f"k_groups<ScoreVis, {lt}>",
-                 "node_pass": f"k_node_perm<{lt}>" if blocked else f"k_node_priv<true, {lt}, false>",
-                 "final_reduce": "k_score_final1", "column_scan": "k_colscan", "scan_order": "k_scan_order"}
+    kernel_of = kernel_names(L, blocked)
     abytes = algorithmic_bytes(n, nnz)
     achieved = abytes / (dom_ms * 1e-3) / 1e9
     roofline = {
@@ -170,6 +177,7 @@ def main() -> int:
         "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4),
         "algorithmic_bytes": abytes,
+        "step_frac": round(abytes / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         "traffic": traffic_for(kernel_of.get(dom, dom)),
         "stage_ms_all_timed": {k: round(v, 4) for k, v in stage_avg.items()},
     }
@@ -201,10 +209,24 @@ def main() -> int:
         del wts
         log(f"weighted: {wms:.3f} ms/step; stages (all timed) " + ", ".join(f"{k}={v:.3f}ms" for k, v in wstages.items()))
 
+    # partitions that do not follow the stored node order, on the same loaded graph
+    parts = {}
+    if args.workload == "l10m" and not args.no_extra:
+        from cqgen import random_labels
+        for name, lab in (("reassigned_30pct", perturb_labels(labels, L, 0.30, 3030)),
+                          ("random", random_labels(n, L, 3131, device="cuda"))):
+            pr, pms, pdom, pdom_ms, pst = timed_run(graph, max(5, args.steps // 4), 2, labels=lab)
+            parts[name] = {"ms_per_step": round(pms, 4), "GEdges_per_s": round(nnz / (pms * 1e-3) / 1e9, 2),
+                           "Q": pr["Q"], "dominant": pdom, "stage_ms_all_timed": {k: round(v, 4) for k, v in pst.items()},
+                           "labels": lab}
+            log(f"partition {name}: {pms:.3f} ms/step; " + ", ".join(f"{k}={v:.3f}ms" for k, v in pst.items()))
+
     cpu = None
     check = None
+    cpu_threaded = None
     if not args.no_cpu_baseline:
         import oracle
+        from oracle.parity import score_mismatches
 
         rp, ci, lab = g.row_ptr.cpu().numpy(), g.col_idx.cpu().numpy(), labels.cpu().numpy()
         oracle.lib()
@@ -212,13 +234,20 @@ def main() -> int:
         t = time.perf_counter()
         o = oracle.score(rp, ci, lab, L, want_pairs=False)
         cpu_s = time.perf_counter() - t
+        host = host_info()
         cpu = {"value": round(nnz / cpu_s / 1e9, 5), "unit": "GEdges/s", "cores": 1, "kind": "oracle",
                "sample": f"whole {args.workload} graph (n={n}, 2|E|={nnz}), one partition, single-threaded C oracle",
-               "seconds": round(cpu_s, 2)}
-        from oracle.parity import score_mismatches
-
+               "seconds": round(cpu_s, 2), **host}
         bad = score_mismatches(r, o.result)
         check = "match" if not bad else "MISMATCH: " + "; ".join(bad)
+        for name, pt in parts.items():
+            op = oracle.score(rp, ci, pt["labels"].cpu().numpy(), L, want_pairs=False)
+            pr, _, _ = cq.score_partition(graph, pt["labels"], L)
+            bad = score_mismatches(pr, op.result)
+            pt["oracle_check"] = "match" if not bad else "MISMATCH: " + "; ".join(bad)
+        cpu_threaded = threaded_cpu(rp, ci, lab, L, nnz, log)
+    for pt in parts.values():
+        pt.pop("labels", None)
 
     out = {
         "metric": METRIC, "value": round(gedges, 2), "unit": "GEdges/s", "n_gpus": 1,
@@ -237,12 +266,130 @@ def main() -> int:
                 "weighted_GEdges_per_s": None if wms is None else round(nnz / (wms * 1e-3) / 1e9, 2),
                 "weighted_Q": None if wres is None else wres["Q"], "weighted_Qds": None if wres is None else wres["Qds"],
                 "oracle_check": check,
-                "Q": r["Q"], "Qds": r["Qds"]},
+                "Q": r["Q"], "Qds": r["Qds"],
+                "partitions": parts or None,
+                "cpu_threaded": cpu_threaded},
     }
-    print(json.dumps(out), flush=True)
     graph.close()
+    del ws, cws
+    if args.workload == "l10m" and not args.no_extra and not args.no_s100m:
+        torch.cuda.empty_cache()
+        out["aux"]["s100m"] = big_graph_leg(args, ctx, cq, timed_run_factory, log)
+    print(json.dumps(out), flush=True)
     ctx.close()
     return 0
+
+
+def host_info() -> dict:
+    import cpubase
+
+    return {"host_cores": os.cpu_count(), "host_threads_usable": cpubase.host_threads(), "cpu_model": cpubase.cpu_model()}
+
+
+def threaded_cpu(rp, ci, lab, L, nnz, log) -> dict:
+    """The multi-threaded CPU scoring (cpubase, the paper's community-per-thread layout) at
+    one thread and at all usable host threads: speedup T1/Tp and efficiency speedup/p as
+    the paper defines them (Eqs. 10-11)."""
+    import cpubase
+
+    T = cpubase.host_threads()
+    cpubase.lib()
+    times = {}
+    for t in sorted({1, T}):
+        log(f"threaded CPU scoring, {t} thread(s)")
+        t0 = time.perf_counter()
+        cpubase.score(rp, ci, lab, L, t)
+        times[t] = time.perf_counter() - t0
+    sp = times[1] / times[T]
+    return {"threads": T, "seconds_1": round(times[1], 3), f"seconds_{T}": round(times[T], 3),
+            "GEdges_per_s": round(nnz / times[T] / 1e9, 4), "speedup": round(sp, 2), "efficiency": round(sp / T, 3),
+            "kind": "pthreads, communities assigned to threads by id (the paper's shared-memory layout)",
+            **host_info()}
+
+
+def timed_run_factory(ctx, cq, graph, labels, L):
+    """Same timing protocol as the main line's timed_run, for another graph."""
+    import torch
+
+    def run(steps, warmup):
+        ws = ctx.workspace(graph.workspace_size(L))
+        for _ in range(warmup):
+            cq.score_partition(graph, labels, L, workspace=ws)
+        cq.cq_context_enable_timing(ctx.handle, True)
+        for _ in range(max(2, steps // 2)):
+            cq.score_partition(graph, labels, L, workspace=ws)
+        breakdown = {k: v[0] / v[1] for k, v in cq.cq_context_stage_times(ctx.handle).items()}
+        dom = max(breakdown, key=breakdown.get)
+        cq.cq_context_time_stages(ctx.handle, 1 << cq.stage_id(dom))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            res, _, _ = cq.score_partition(graph, labels, L, workspace=ws)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        tot, cnt = cq.cq_context_stage_times(ctx.handle)[dom]
+        cq.cq_context_enable_timing(ctx.handle, False)
+        return res, (t1 - t0) * 1e3 / steps, dom, tot / cnt, breakdown
+
+    return run
+
+
+def big_graph_leg(args, ctx, cq, factory, log) -> dict:
+    """The 100M-node graph (average degree 10, maximum 1,000, communities 50-10,000,
+    mixing 0.3): step time, dominant kernel against the HBM roofline, the comparison of
+    two 1e8-node partitions, and the oracle's check of the score."""
+    import torch
+
+    from cqgen import CONFIGS, lfr_graph, perturb_labels
+
+    t = time.perf_counter()
+    g = lfr_graph(CONFIGS["s100m"], args.seed, device="cuda")
+    torch.cuda.synchronize()
+    gen_s = time.perf_counter() - t
+    n, nnz, L = g.n, g.nnz, g.num_labels
+    log(f"graph s100m: n={n} nnz={nnz} K={L} generated in {gen_s:.1f}s")
+    t = time.perf_counter()
+    graph = cq.Graph(ctx, g.row_ptr, g.col_idx, reorder=True)
+    load_ms = (time.perf_counter() - t) * 1e3
+    r, ms, dom, dom_ms, st = factory(ctx, cq, graph, g.labels, L)(5, 1)
+    blocked = graph.stats["reordered"] == cq.CQ_GRAPH_REORDER
+    abytes = algorithmic_bytes(n, nnz)
+    log(f"s100m: {ms:.3f} ms/step; " + ", ".join(f"{k}={v:.3f}ms" for k, v in st.items()))
+    pert = perturb_labels(g.labels, L, 0.10, 1010)
+    cws = ctx.workspace(cq.cq_compare_workspace_size(n, L, L))
+    cq.compare_partitions(ctx, g.labels, L, pert, L, workspace=cws)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(3):
+        cq.compare_partitions(ctx, g.labels, L, pert, L, workspace=cws)
+    torch.cuda.synchronize()
+    cmp_ms = (time.perf_counter() - t) * 1e3 / 3
+    del cws, pert
+    graph.close()
+    out = {"workload": "lfr_s100m", "n": n, "nnz": nnz, "communities": L, "seed": args.seed,
+           "max_degree": g.stats["max_degree"], "graph_order": "locality (no column blocks above 2^24 nodes)",
+           "graph_load_ms": round(load_ms, 1), "ms_per_step": round(ms, 4),
+           "GEdges_per_s": round(nnz / (ms * 1e-3) / 1e9, 2),
+           "roofline": {"bound": "hbm", "kernel": kernel_names(L, blocked).get(dom, dom), "stage": dom,
+                        "avg_ms": round(dom_ms, 4), "achieved": round(abytes / (dom_ms * 1e-3) / 1e9, 1),
+                        "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(abytes / (dom_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                        "algorithmic_bytes": abytes, "step_frac": round(abytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
+           "stage_ms_all_timed": {k: round(v, 4) for k, v in st.items()},
+           "compare_ms": round(cmp_ms, 3), "compare_Gnodes_per_s": round(n / (cmp_ms * 1e-3) / 1e9, 3),
+           "Q": r["Q"], "Qds": r["Qds"], "oracle_check": None}
+    if not args.no_cpu_baseline:
+        import oracle
+        from oracle.parity import score_mismatches
+
+        log("s100m: oracle on the host (whole graph, one thread)")
+        t = time.perf_counter()
+        o = oracle.score(g.row_ptr.cpu().numpy(), g.col_idx.cpu().numpy(), g.labels.cpu().numpy(), L, want_pairs=False)
+        out["oracle_seconds"] = round(time.perf_counter() - t, 1)
+        bad = score_mismatches(r, o.result)
+        out["oracle_check"] = "match" if not bad else "MISMATCH: " + "; ".join(bad)
+    del g
+    torch.cuda.empty_cache()
+    return out
 
 
 def bench_batch(args, log) -> int:
