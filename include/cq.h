@@ -93,6 +93,19 @@ cq_status cq_context_stage_times(const cq_context* ctx, double* total_ms, int64_
 /* Name of stage id s (static storage), or "" if s is not a stage id. */
 const char* cq_stage_name(int32_t s);
 
+/* ---- staging choice on column-blocked graphs -------------------------------- */
+
+/* A column-blocked graph stores nodes so that communities found at load time are runs of
+ * consecutive ids, and stages neighbour labels with one claim per run of equal labels.  A
+ * partition that does not follow that order (say, a perturbed or unrelated one) breaks
+ * the runs, and the claims grow to one per node.  Each unweighted call on such a graph
+ * (with up to 12,224 label ids) therefore counts, on the device, the label changes between
+ * consecutive stored nodes; when they reach change_fraction * n the call stages through
+ * the graph's row-major copy with per-node offsets instead (cq_score_result.staging says
+ * which).  Default 1/16; <= 0 always takes the row-major copy, >= 1 never does.  The
+ * results are the same either way. */
+cq_status cq_context_set_row_staging(cq_context* ctx, double change_fraction);
+
 /* ---- graphs ---------------------------------------------------------------- */
 
 /* Flags for cq_graph_load. */
@@ -193,7 +206,15 @@ typedef struct {
   double total_weight;       /* W (|E| when unweighted) */
   double sum_w_in;           /* sum_c w_in(c) (sum_ein when unweighted) */
   double sum_w_out;          /* sum_c w_out(c) (sum_eout when unweighted) */
+  uint32_t staging;          /* how the neighbour labels were staged: CQ_STAGING_* (informational) */
+  uint32_t reserved;
 } cq_score_result;
+
+/* cq_score_result.staging.  The results do not depend on it. */
+#define CQ_STAGING_ROWS_ONLY 0u  /* the graph's row-major storage (no column blocks; batched calls) */
+#define CQ_STAGING_BLOCKS 1u     /* column blocks, compact staging with one claim per run of equal labels */
+#define CQ_STAGING_ROWS 2u       /* a column-blocked graph staged through its row-major copy: the partition
+                                    does not follow the stored order (see cq_context_set_row_staging) */
 
 /* Optional per-label outputs: DEVICE arrays of length num_labels, each may be NULL.
  * Entries for label ids that no node carries are zero.  On a weighted graph

@@ -18,6 +18,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "cq.h")
 
 CQ_OK = 0
 CQ_SCRATCH_BYTES = 64 << 20  # include/cq.h: the library's per-device scratch array
+CQ_STAGING_ROWS_ONLY, CQ_STAGING_BLOCKS, CQ_STAGING_ROWS = 0, 1, 2
 CQ_E_INVALID_ARG = -1
 CQ_E_LABEL_RANGE = -2
 CQ_E_GRAPH_FORMAT = -3
@@ -52,7 +53,8 @@ class ScoreResult(ctypes.Structure):
         "Q", "Qds", "split_penalty", "mean_intra_edges", "mean_intra_density", "mean_contraction",
         "mean_inter_edges", "mean_expansion", "mean_conductance",
     )] + [("device_flags", ctypes.c_uint32), ("weighted", ctypes.c_uint32)] + [
-        (k, ctypes.c_double) for k in ("total_weight", "sum_w_in", "sum_w_out")]
+        (k, ctypes.c_double) for k in ("total_weight", "sum_w_in", "sum_w_out")] + [
+        ("staging", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
 
 
 class CompareResult(ctypes.Structure):
@@ -128,6 +130,7 @@ def _load():
         "cq_compare_partitions": (_I32, [_P, _I32, _P, _I32, _P, _I32, _P, _SZ, ctypes.POINTER(CompareResult), _P]),
         "cq_compare_partitions_async": (_I32, [_P, _I32, _P, _I32, _P, _I32, _P, _SZ, _P, _P]),
         "cq_context_enable_timing": (_I32, [_P, ctypes.c_int]),
+        "cq_context_set_row_staging": (_I32, [_P, ctypes.c_double]),
         "cq_context_time_stages": (_I32, [_P, ctypes.c_uint32]),
         "cq_context_stage_times": (_I32, [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_I64), _I32]),
         "cq_stage_name": (ctypes.c_char_p, [_I32]),
@@ -283,6 +286,10 @@ def cq_score_partition(ctx, g, d_labels, num_labels, d_ws, ws_bytes, per_comm: P
     return _check(ctx, st, allow), res
 
 
+def cq_context_set_row_staging(ctx, change_fraction: float) -> None:
+    _check(ctx, _lib.cq_context_set_row_staging(ctx, float(change_fraction)))
+
+
 def cq_score_partition_noalloc(ctx, g, d_labels, num_labels, per_comm: PerCommunity | None = None,
                                pairs: PairTable | None = None, allow=(CQ_OK,)) -> tuple[int, ScoreResult]:
     res = ScoreResult()
@@ -417,8 +424,13 @@ def _dev_f32(t, name):
     return t
 
 
+# Fields that describe how a call ran rather than what it computed: left out of result
+# dicts, so that results of the same inputs compare equal whatever path produced them.
+_INFO_FIELDS = ("reserved", "staging")
+
+
 def as_dict(res) -> dict:
-    return {k: getattr(res, k) for k, _ in res._fields_ if k != "reserved"}
+    return {k: getattr(res, k) for k, _ in res._fields_ if k not in _INFO_FIELDS}
 
 
 class Context:
@@ -468,6 +480,7 @@ class Graph:
         self.n = self.row_ptr.numel() - 1
         self.nnz = self.col_idx.numel()
         self.handle = 0
+        self.last_staging = None  # CQ_STAGING_* of the last score_partition call on this graph
         flags = ((CQ_VALIDATE_GRAPH if validate else 0) | (CQ_GRAPH_REORDER if reorder else 0)
                  | (CQ_GRAPH_BLOCKS if reorder and blocks is True else 0)
                  | (CQ_GRAPH_NO_BLOCKS if reorder and blocks is False else 0))
@@ -540,6 +553,7 @@ def score_partition(graph: Graph, labels, num_labels: int, *, per_community: boo
                                      ws.numel(), pc, pt, allow=allow)
     r = as_dict(res)
     r["status"] = st
+    graph.last_staging = res.staging  # CQ_STAGING_*: how this call staged the neighbour labels
     pair_tensor = None
     if pairs is not None:
         k = min(r["num_pairs"], pairs_capacity)

@@ -29,8 +29,18 @@ struct Ctl {
   u32 dense_rows;  // node pass of column-blocked graphs: buckets that wrote histogram rows
   unsigned long long export_count;
   unsigned long long cells;   // non-zero contingency cells (comparison)
-  unsigned long long pad1[4];
+  u32 changes;    // column-blocked node pass: label changes between consecutive stored ids
+  u32 mode;       // column-blocked graphs: STAGE_BLOCKS or STAGE_ROWS, chosen from `changes`
+  unsigned long long pad1[3];
 };
+
+// How a call on a column-blocked graph stages the neighbour labels (Ctl::mode; also
+// reported in the result): through the column blocks with run claims, or through the
+// graph's row-major copy with per-node offsets when the partition does not follow the
+// stored order (short runs of equal labels make run claims as many as the nodes).
+constexpr u32 STAGE_ROWS_ONLY = 0;  // the graph has no column blocks
+constexpr u32 STAGE_BLOCKS = 1;
+constexpr u32 STAGE_ROWS = 2;
 
 // ---- exact fixed-point accumulation --------------------------------------
 // A binary64 value t is turned into the integer round_toward_zero(t * 2^96) held in

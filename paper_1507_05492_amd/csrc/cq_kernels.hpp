@@ -564,11 +564,16 @@ __global__ __launch_bounds__(1024) void k_perm_apply_count(const u32* __restrict
   u32* hn = reinterpret_cast<u32*>(sl4 + (1u << PERM_SHIFT) / 8u);
   u32* hd = hn + L;
   __shared__ u32 s_nz;
+  __shared__ u32 s_chg;
   const int tid = threadIdx.x;
   const u32 b = blockIdx.x, id0 = b << PERM_SHIFT;
   const u32 j0 = bstart[b], j1 = bstart[b + 1];
   for (int i = tid; i < 2 * L; i += blockDim.x) hn[i] = 0;
-  if (tid == 0) s_nz = 0;
+  if (tid == 0) {
+    s_nz = 0;
+    s_chg = 0;
+  }
+  u32 chg = 0;  // label changes between consecutive stored ids of this bucket
   constexpr int U = 8;
   for (u32 jb = j0 + tid; jb < j1; jb += U * blockDim.x) {
     u32 t[U];
@@ -607,6 +612,15 @@ __global__ __launch_bounds__(1024) void k_perm_apply_count(const u32* __restrict
     bool same = act;
 #pragma unroll
     for (int k = 1; k < 8; ++k) same = same && ((w4[k >> 1] >> (16 * (k & 1))) & 0xFFFFu) == l0;
+    if (act) {
+      u32 prev = i ? (u32)sl[8u * i - 1u] : l0;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const u32 lk = (w4[k >> 1] >> (16 * (k & 1))) & 0xFFFFu;
+        chg += lk != prev ? 1u : 0u;
+        prev = lk;
+      }
+    }
     const u32 key = (same && l0 < (u32)L) ? l0 : 0xFFFFFFFFu;
     const u32 k0 = __shfl(key, 0, 64);
     if (__ballot(key == k0) == ~0ull && k0 != 0xFFFFFFFFu) {
@@ -633,18 +647,22 @@ __global__ __launch_bounds__(1024) void k_perm_apply_count(const u32* __restrict
   }
   for (u32 i = nv * 8u + tid; i < cnt; i += blockDim.x) {
     const u32 lk = sl[i];
+    chg += (i && lk != (u32)sl[i - 1u]) ? 1u : 0u;
     labx[id0 + i] = (uint16_t)lk;
     if (lk < (u32)L) {
       atomicAdd(&hn[lk], 1u);
       atomicAdd(&hd[lk], (u32)(rp[id0 + i + 1] - rp[id0 + i]));
     }
   }
+  chg = (u32)wave_sum_u64(chg);
+  if ((tid & 63) == 0 && chg) atomicAdd(&s_chg, chg);
   __syncthreads();
   u32 nz = 0;
   for (int c = tid; c < L; c += blockDim.x) nz += hn[c] ? 1u : 0u;
   nz = (u32)wave_sum_u64(nz);
   if ((tid & 63) == 0 && nz) atomicAdd(&s_nz, nz);
   __syncthreads();
+  if (tid == 0 && s_chg) atomicAdd(&ctl->changes, s_chg);
   if (s_nz <= FLUSH_MAX) {
     for (int c = tid; c < L; c += blockDim.x) {
       if (hn[c]) {
@@ -809,11 +827,14 @@ __device__ __forceinline__ void node_priv_body(int n, const int32_t* __restrict_
   if (threadIdx.x == 0 && s_bad) atomicOr(&ctl->flags, F_LABEL);
 }
 
+// run_if != 0: the launch does nothing unless ctl->mode == run_if (the staging choice is
+// made on the device, so both choices' kernels are enqueued and one of them returns).
 template <bool WEIGHTED, class LT, bool STAGED = false>
 __global__ __launch_bounds__(1024) void k_node_priv(int n, const int32_t* __restrict__ labels, const int32_t* __restrict__ perm,
                                                     const int32_t* __restrict__ rp, int L, int chunk, u32* __restrict__ HN,
                                                     u32* __restrict__ HD, u32* __restrict__ loc, LT* __restrict__ labx,
-                                                    Ctl* __restrict__ ctl, int lbase, int LR) {
+                                                    Ctl* __restrict__ ctl, int lbase, int LR, u32 run_if = 0) {
+  if (run_if && ctl->mode != run_if) return;
   node_priv_body<WEIGHTED, LT, STAGED>(n, labels, perm, rp, L, chunk, HN, HD, loc, labx, ctl, blockIdx.x, lbase, LR);
 }
 
@@ -956,7 +977,9 @@ template <bool WEIGHTED, bool SCAN>
 __global__ __launch_bounds__(CS_LABELS * CS_GROUPS) void k_colscan(int W, int L, u32* __restrict__ HN,
                                                                    u32* __restrict__ HD, u32* __restrict__ N,
                                                                    u32* __restrict__ D,
-                                                                   unsigned long long* __restrict__ zero64 = nullptr) {
+                                                                   unsigned long long* __restrict__ zero64 = nullptr,
+                                                                   const Ctl* __restrict__ gate = nullptr, u32 run_if = 0) {
+  if (gate && gate->mode != run_if) return;  // see k_node_priv
   __shared__ u32 s_n[CS_GROUPS][CS_LABELS], s_d[CS_GROUPS][CS_LABELS];
   const int lane = threadIdx.x % CS_LABELS, grp = threadIdx.x / CS_LABELS;
   const int c = blockIdx.x * CS_LABELS + lane;
@@ -1000,12 +1023,21 @@ __global__ __launch_bounds__(CS_LABELS * CS_GROUPS) void k_colscan(int W, int L,
 // Column-blocked node pass: adds the histogram rows of the dense buckets (rows[0,
 // ctl->dense_rows), written by k_perm_apply_count) to N and D, and clears the 64-bit run
 // cursors.  Integer sums, so the order of the row list does not matter.
+// It also chooses how the call stages neighbour labels (Ctl::mode): through the row-major
+// copy when the stored-order labels change at least `rows_from` times (a partition that
+// does not follow the stored order), else through the column blocks.
 __global__ __launch_bounds__(256) void k_colscan_rows(int L, const u32* __restrict__ HN, const u32* __restrict__ HD,
-                                                      const u32* __restrict__ rows, const Ctl* __restrict__ ctl,
+                                                      const u32* __restrict__ rows, Ctl* __restrict__ ctl,
                                                       u32* __restrict__ N, u32* __restrict__ D,
-                                                      unsigned long long* __restrict__ zero64) {
+                                                      unsigned long long* __restrict__ zero64, u32 rows_from) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  const u32 mode = ctl->changes >= rows_from ? STAGE_ROWS : STAGE_BLOCKS;  // every thread reads the final count
+  if (c == 0) ctl->mode = mode;
   if (c >= L) return;
+  if (mode == STAGE_ROWS) {
+    zero64[c] = 0ull;  // N and D come from the row-major node pass (k_colscan after k_node_priv)
+    return;
+  }
   const u32 nd = ctl->dense_rows;
   if (nd) {
     u32 sn = 0, sd = 0;
@@ -1133,14 +1165,11 @@ __global__ __launch_bounds__(1024) void k_scan_order(int L, const u32* __restric
 // by binary search over the 256 row starts staged in LDS.
 constexpr int GROWS = 256;
 template <bool PRIV, class LT, bool WT>
-__global__ __launch_bounds__(GROWS) void k_gather(int n, const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
-                                                  const LT* __restrict__ labx, int L, int chunk, const u32* __restrict__ PM,
-                                                  const u32* __restrict__ start, const u32* __restrict__ loc,
-                                                  LT* __restrict__ CB, const float* __restrict__ w, float* __restrict__ CW) {
-  __shared__ int s_rs[GROWS + 1];
-  __shared__ u32 s_base[GROWS];
+__device__ __forceinline__ void gather_rows(long long r0, int n, const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
+                                            const LT* __restrict__ labx, int L, int chunk, const u32* __restrict__ PM,
+                                            const u32* __restrict__ start, const u32* __restrict__ loc, LT* __restrict__ CB,
+                                            const float* __restrict__ w, float* __restrict__ CW, int* s_rs, u32* s_base) {
   const int tid = threadIdx.x;
-  const long long r0 = (long long)blockIdx.x * GROWS;
   const int rows = (int)min((long long)GROWS, (long long)n - r0);
   if (tid < rows) {
     long long u = r0 + tid;
@@ -1167,6 +1196,25 @@ __global__ __launch_bounds__(GROWS) void k_gather(int n, const int32_t* __restri
     if (base == SENT) continue;
     CB[base + (u32)(e - s_rs[lo])] = labx[col[e]];
     if (WT) CW[base + (u32)(e - s_rs[lo])] = w[e];
+  }
+}
+
+// Workgroups take tiles of GROWS rows in turn (grid-stride).  gate (optional): the launch
+// does nothing unless gate->mode == STAGE_ROWS (a column-blocked graph scored through its
+// row-major copy; see k_colscan_rows).
+template <bool PRIV, class LT, bool WT>
+__global__ __launch_bounds__(GROWS) void k_gather(int n, const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
+                                                  const LT* __restrict__ labx, int L, int chunk, const u32* __restrict__ PM,
+                                                  const u32* __restrict__ start, const u32* __restrict__ loc,
+                                                  LT* __restrict__ CB, const float* __restrict__ w, float* __restrict__ CW,
+                                                  const Ctl* __restrict__ gate = nullptr) {
+  __shared__ int s_rs[GROWS + 1];
+  __shared__ u32 s_base[GROWS];
+  if (gate && gate->mode != STAGE_ROWS) return;
+  const long long tiles = ((long long)n + GROWS - 1) / GROWS;
+  for (long long t = blockIdx.x; t < tiles; t += gridDim.x) {
+    gather_rows<PRIV, LT, WT>(t * GROWS, n, rp, col, labx, L, chunk, PM, start, loc, CB, w, CW, s_rs, s_base);
+    __syncthreads();  // the next tile's row starts replace this one's
   }
 }
 
@@ -1636,6 +1684,7 @@ __global__ __launch_bounds__(BT_THREADS) void k_gather_blocked(int n, int span, 
                                                                unsigned long long* __restrict__ IWacc) {
   __shared__ __align__(16) u32 lds[GatherLds<LT, WT>::WORDS];
   __shared__ u32 s_w[BT_THREADS / 64];
+  if (ctl->mode == STAGE_ROWS) return;  // this call stages through the row-major copy (k_colscan_rows)
   const u32 y = blockIdx.x % 8u, gi = blockIdx.x / 8u;
   if (y >= (u32)COL_BLOCKS || gi >= own_groups + far_groups) return;
   if (gi < own_groups)
@@ -1955,6 +2004,8 @@ __global__ __launch_bounds__(GBLOCK) void k_groups(const LT* __restrict__ CB, co
                                                    const unsigned long long* __restrict__ cur64) {
   __shared__ u32 s_item;
   const u32 K = ctl->K;
+  // read once: the control block's line also holds the ticket every workgroup adds to
+  const bool compact = cur64 && ctl->mode != STAGE_ROWS;
   for (;;) {
     if (threadIdx.x == 0) s_item = atomicAdd(&ctl->ticket, 1u);
     __syncthreads();
@@ -1962,7 +2013,7 @@ __global__ __launch_bounds__(GBLOCK) void k_groups(const LT* __restrict__ CB, co
     __syncthreads();
     if (item >= K) break;
     const u32 g = order[item];
-    const unsigned long long c = cur64 ? cur64[g] : (unsigned long long)seg_len[g];
+    const unsigned long long c = compact ? cur64[g] : (unsigned long long)seg_len[g];
     group_one<V, LT>(CB, seg_start[g], (u32)c, g, Lv, lds_words, vis, ctl, (u32)(c >> 32));
   }
 }
@@ -2501,10 +2552,17 @@ struct ScoreResultDev {
   double mean_inter_edges, mean_expansion, mean_conductance;
   uint32_t device_flags, weighted;
   double total_weight, sum_w_in, sum_w_out;
+  uint32_t staging, reserved;
 };
 
+// staging reported in the result: the choice made on the device (ctl->mode) when there
+// was one, else STAGE_BLOCKS for a column-blocked graph (blocked != 0), STAGE_ROWS_ONLY otherwise.
+__device__ __forceinline__ u32 staging_of(const Ctl* ctl, u32 blocked) {
+  return ctl->mode ? ctl->mode : (blocked ? STAGE_BLOCKS : STAGE_ROWS_ONLY);
+}
+
 __device__ void score_final2_body(int G, const ScorePart* __restrict__ parts, long long n, long long twom, long long ecap,
-                                  Ctl* __restrict__ ctl, ScoreResultDev* __restrict__ out) {
+                                  Ctl* __restrict__ ctl, ScoreResultDev* __restrict__ out, u32 blocked) {
   u64 K = 0, sein = 0, seout = 0, sD2 = 0, np = 0;
   u128 pen = 0;
   double qds_a = 0, s_dens = 0, s_contr = 0, s_exp = 0, s_cond = 0;
@@ -2537,6 +2595,8 @@ __device__ void score_final2_body(int G, const ScorePart* __restrict__ parts, lo
   r.total_weight = (double)m;
   r.sum_w_in = (double)sein;
   r.sum_w_out = (double)seout;
+  r.staging = staging_of(ctl, blocked);
+  r.reserved = 0;
   *out = r;
 }
 
@@ -2631,7 +2691,7 @@ __global__ __launch_bounds__(FBLOCK) void k_score_final1_w(int L, const u32* __r
 }
 
 __global__ void k_score_final2_w(int G, const WScorePart* __restrict__ parts, long long n, long long twom, double W,
-                                 long long ecap, Ctl* __restrict__ ctl, ScoreResultDev* __restrict__ out) {
+                                 long long ecap, Ctl* __restrict__ ctl, ScoreResultDev* __restrict__ out, u32 blocked) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   u64 K = 0, sein = 0, seout = 0, sD2 = 0, np = 0;
   u128 penw = 0, swi2 = 0, swo = 0;
@@ -2664,13 +2724,15 @@ __global__ void k_score_final2_w(int G, const WScorePart* __restrict__ parts, lo
   r.total_weight = W;
   r.sum_w_in = wi;
   r.sum_w_out = wout;
+  r.staging = staging_of(ctl, blocked);
+  r.reserved = 0;
   *out = r;
 }
 
 
 __global__ void k_score_final2(int G, const ScorePart* __restrict__ parts, long long n, long long twom, long long ecap,
-                               Ctl* __restrict__ ctl, ScoreResultDev* __restrict__ out) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) score_final2_body(G, parts, n, twom, ecap, ctl, out);
+                               Ctl* __restrict__ ctl, ScoreResultDev* __restrict__ out, u32 blocked) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) score_final2_body(G, parts, n, twom, ecap, ctl, out, blocked);
 }
 
 // comparison final reduction ------------------------------------------------
@@ -2983,7 +3045,7 @@ __global__ void k_b_final2(const TaskDev* __restrict__ td, int T) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= T) return;
   const TaskDev& d = td[t];
-  score_final2_body(d.G, d.parts, d.n, d.nnz, 0, d.ctl, d.out);
+  score_final2_body(d.G, d.parts, d.n, d.nnz, 0, d.ctl, d.out, 0u);
 }
 
 }  // namespace cq

@@ -25,6 +25,9 @@ using namespace cq;
 
 struct cq_context {
   int device = 0;
+  // column-blocked graphs: a partition whose labels change between at least this fraction
+  // of consecutive stored nodes is staged through the graph's row-major copy
+  double row_staging_from = 1.0 / 16.0;
   void* scratch = nullptr;  // device address of the library's scratch array on this device
   hipStream_t stream = nullptr;
   int num_cus = 256;
@@ -388,6 +391,7 @@ void score_launch(cq_context* ctx, const cq_graph* g, const int32_t* labels, int
   float* CW = g->w ? at<float>(ws, lay.CW) : nullptr;  // weights staged beside the labels
   ScorePart* parts = at<ScorePart>(ws, lay.parts);
   const u32* PM = nullptr;
+  bool dual_rows = false;  // column-blocked graph whose staging is chosen on the device
   {
     StageMark mk(ctx, ST_SETUP, timed);
     fill(reinterpret_cast<u32*>(ctl), sizeof(Ctl) / 4, 0, s);
@@ -415,10 +419,25 @@ void score_launch(cq_context* ctx, const cq_graph* g, const int32_t* labels, int
             g->pbstart, g->tgt, reinterpret_cast<const uint16_t*>(tmp), reinterpret_cast<uint16_t*>(labx), g->rp, L, N, D, HN, HD,
             rows, ctl);
       }
+      // A partition out of the stored order (many label changes along it) would make the
+      // column blocks' run claims as many as the nodes: k_colscan_rows then picks staging
+      // through the row-major copy, whose per-node offsets come from the gated launches
+      // below (they return at once when the blocks are kept).
+      const bool dual = !CW;
       {
         StageMark mk(ctx, ST_COLSCAN, timed);
+        const double f = ctx->row_staging_from;
+        const u32 rows_from = !dual ? 0xFFFFFFFFu : f <= 0.0 ? 0u : (f >= 1.0 ? 0xFFFFFFFFu : (u32)std::ceil(f * (double)n));
         k_colscan_rows<<<grid_for(L, 256, 1u << 30), 256, 0, s>>>(L, HN, HD, rows, ctl, N, D,
-                                                                  at<unsigned long long>(ws, lay.cursor));
+                                                                  at<unsigned long long>(ws, lay.cursor), rows_from);
+        if (dual) {
+          // after k_colscan_rows: it set the mode and has read the dense buckets' rows of HN/HD
+          k_node_priv<true, LT, true><<<lay.W, 1024, 2 * (size_t)L * 4, s>>>((int)n, labels, g->perm, g->rp, L, lay.chunk, HN,
+                                                                           HD, loc, labx, ctl, 0, L, STAGE_ROWS);
+          k_colscan<true, true><<<colscan_grid(L), CS_LABELS * CS_GROUPS, 0, s>>>(lay.W, L, HN, HD, N, D, nullptr, ctl,
+                                                                             STAGE_ROWS);
+        }
+        dual_rows = dual;
       }
     } else {
       // more labels than LDS holds beside a bucket: count in the caller's order
@@ -495,6 +514,12 @@ void score_launch(cq_context* ctx, const cq_graph* g, const int32_t* labels, int
         k_gather_blocked<LT, false><<<grid, BT_THREADS, 0, s>>>((int)n, (int)span, g->rpb, g->colb, g->rowb, g->far, own_groups,
                                                                 g->far_tiles, labx, start, D, at<u32>(ws, lay.cursor), ctl, CB,
                                                                 nullptr, nullptr, nullptr);
+      if (dual_rows) {
+        // the other choice: every entry staged at its row's offset, through the row-major copy
+        const unsigned gr = std::min(grid_for(n, GROWS, 1u << 30), (unsigned)(ctx->num_cus * 64));
+        k_gather<true, LT, false><<<gr, GROWS, 0, s>>>((int)n, g->rp, g->col, labx, L, lay.chunk, PM, start, loc, CB, nullptr,
+                                                       nullptr, ctl);
+      }
     } else {
       const unsigned grid = grid_for(n, GROWS, 1u << 30);
       if (lay.priv && CW)
@@ -548,7 +573,7 @@ void score_launch(cq_context* ctx, const cq_graph* g, const int32_t* labels, int
     {
       StageMark mk(ctx, ST_FINAL, timed);
       k_score_final1_w<<<lay.G, FBLOCK, 0, s>>>(L, N, D, I, NP, wo.SW, wo.IW, wo.PENW, g->total_w, pc, wparts);
-      k_score_final2_w<<<1, 64, 0, s>>>(lay.G, wparts, n, nnz, g->total_w, vis.ecap, ctl, d_out);
+      k_score_final2_w<<<1, 64, 0, s>>>(lay.G, wparts, n, nnz, g->total_w, vis.ecap, ctl, d_out, g->rpb ? 1u : 0u);
     }
     return;
   }
@@ -562,7 +587,7 @@ void score_launch(cq_context* ctx, const cq_graph* g, const int32_t* labels, int
   {
     StageMark mk(ctx, ST_FINAL, timed);
     k_score_final1<<<lay.G, FBLOCK, 0, s>>>(L, N, D, I, NP, PEN, (double)nnz, pc, parts);
-    k_score_final2<<<1, 64, 0, s>>>(lay.G, parts, n, nnz, vis.ecap, ctl, d_out);
+    k_score_final2<<<1, 64, 0, s>>>(lay.G, parts, n, nnz, vis.ecap, ctl, d_out, g->rpb ? 1u : 0u);
   }
 }
 
@@ -1541,6 +1566,13 @@ cq_status cq_context_time_stages(cq_context* ctx, uint32_t stage_mask) {
     ctx->counts[i] = 0;
     ctx->recorded[i] = false;
   }
+  return CQ_OK;
+}
+
+cq_status cq_context_set_row_staging(cq_context* ctx, double change_fraction) {
+  if (!ctx) return CQ_E_INVALID_ARG;
+  if (!(change_fraction == change_fraction)) return fail(ctx, CQ_E_INVALID_ARG, "change_fraction is NaN");
+  ctx->row_staging_from = change_fraction;
   return CQ_OK;
 }
 

@@ -38,7 +38,8 @@ def open_graph(cq, ctx, rp_t, ci_t, order, validate=False):
     return g
 
 
-def run_case(cq, ctx, rp, ci, lab, L, what, *, validate=True, pairs=True, per_comm=True, reorder="input"):
+def run_case(cq, ctx, rp, ci, lab, L, what, *, validate=True, pairs=True, per_comm=True, reorder="input",
+             expect_staging=None):
     what = f"{what} [{reorder} graph]"
     note(what)
     rp_t = torch.as_tensor(np.asarray(rp, np.int32)).cuda()
@@ -54,6 +55,8 @@ def run_case(cq, ctx, rp, ci, lab, L, what, *, validate=True, pairs=True, per_co
         check_per_community(pc, o, int(o.result["m"]))
     if pairs:
         assert np.array_equal(sort_rows(pt), o.pairs), f"{what}: pair table differs"
+    if expect_staging is not None:
+        assert g.last_staging == expect_staging, (what, g.last_staging)
     g.close()
     return r, o
 
@@ -116,7 +119,56 @@ def test_random_labels_compact_staging(cq, ctx, reorder):
     n = len(rp) - 1
     for nl, seed in ((200, 23), (3000, 24)):
         labr = random_labels(n, nl, seed).numpy()
-        run_case(cq, ctx, rp, ci, labr, nl, f"random labels, {nl} ids", reorder=reorder, per_comm=False)
+        if reorder != "blocked":
+            run_case(cq, ctx, rp, ci, labr, nl, f"random labels, {nl} ids", reorder=reorder, per_comm=False)
+            continue
+        # both stagings of a column-blocked graph: the blocks (forced), and the row-major
+        # copy the call picks for labels out of the stored order
+        for frac, want in ((2.0, cq.CQ_STAGING_BLOCKS), (1 / 16, cq.CQ_STAGING_ROWS)):
+            cq.cq_context_set_row_staging(ctx.handle, frac)
+            try:
+                run_case(cq, ctx, rp, ci, labr, nl, f"random labels, {nl} ids, row staging from {frac}", reorder=reorder,
+                         per_comm=False, expect_staging=want)
+            finally:
+                cq.cq_context_set_row_staging(ctx.handle, 1 / 16)
+
+
+def test_staging_choice_on_blocked_graphs(cq, ctx):
+    """A column-blocked graph counts the label changes along its stored order: the ground
+    truth (runs) keeps the blocks, 30 % reassigned nodes or random labels take the
+    row-major copy, and forcing either choice gives the same result bit for bit."""
+    rp, ci, lab, L = lfr_case("m100k_mu0.3", 16)
+    n = len(rp) - 1
+    cases = [("ground truth", lab, cq.CQ_STAGING_BLOCKS),
+             ("1% reassigned", perturb_labels(torch.as_tensor(lab), L, 0.01, 161).numpy(), None),
+             ("30% reassigned", perturb_labels(torch.as_tensor(lab), L, 0.30, 162).numpy(), cq.CQ_STAGING_ROWS),
+             ("random", random_labels(n, L, 163).numpy(), cq.CQ_STAGING_ROWS)]
+    rp_t = torch.as_tensor(np.asarray(rp, np.int32)).cuda()
+    ci_t = torch.as_tensor(np.asarray(ci, np.int32)).cuda()
+    g = open_graph(cq, ctx, rp_t, ci_t, "blocked")
+    for what, lb, want in cases:
+        note(f"staging choice: {what}")
+        o = oracle.score(rp, ci, lb, L)
+        lab_t = torch.as_tensor(np.asarray(lb, np.int32)).cuda()
+        cap = max(1, int(o.result["num_pairs"]))
+        r, pc, pt = cq.score_partition(g, lab_t, L, per_community=True, pairs_capacity=cap)
+        assert want is None or g.last_staging == want, (what, g.last_staging)
+        check_score(r, o.result, what)
+        check_per_community(pc, o, int(o.result["m"]))
+        assert np.array_equal(sort_rows(pt), o.pairs), what
+        for frac, forced in ((-1.0, cq.CQ_STAGING_ROWS), (2.0, cq.CQ_STAGING_BLOCKS)):
+            cq.cq_context_set_row_staging(ctx.handle, frac)
+            try:
+                r2, pc2, pt2 = cq.score_partition(g, lab_t, L, per_community=True, pairs_capacity=cap)
+            finally:
+                cq.cq_context_set_row_staging(ctx.handle, 1 / 16)
+            assert g.last_staging == forced, (what, frac)
+            assert r2 == r, (what, frac)
+            for k in ("size", "degsum", "ein", "eout", "intra_density", "contraction", "expansion", "conductance",
+                      "q_term", "qds_term"):
+                assert torch.equal(pc2[k], pc[k]), (what, frac, k)
+            assert np.array_equal(sort_rows(pt2), o.pairs), (what, frac)
+    g.close()
 
 
 def test_wide_counter_wraps(cq, ctx):
@@ -257,6 +309,24 @@ def test_full_size_l10m(cq, ctx):
         check_score(r, o.result, f"l10m reorder={reorder}")
         check_per_community(pc, o, int(o.result["m"]))
         assert np.array_equal(sort_rows(pt), o.pairs)
+        if reorder == "blocked":
+            assert g.last_staging == cq.CQ_STAGING_BLOCKS  # the ground truth follows the stored order
+    # 30 % of the nodes reassigned: the column-blocked graph stages through its row-major
+    # copy; forcing the blocks gives the same bits
+    pert = perturb_labels(gr.labels, gr.num_labels, 0.30, 2130)
+    note("l10m 30% reassigned: oracle")
+    op = oracle.score(rp, ci, pert.cpu().numpy(), gr.num_labels)
+    gb = graphs["blocked"]
+    r30, _, pt30 = cq.score_partition(gb, pert, gr.num_labels, pairs_capacity=int(op.result["num_pairs"]))
+    assert gb.last_staging == cq.CQ_STAGING_ROWS
+    check_score(r30, op.result, "l10m 30% reassigned [blocked graph, row-major staging]")
+    assert np.array_equal(sort_rows(pt30), op.pairs)
+    cq.cq_context_set_row_staging(ctx.handle, 2.0)
+    try:
+        r30b, _, _ = cq.score_partition(gb, pert, gr.num_labels)
+    finally:
+        cq.cq_context_set_row_staging(ctx.handle, 1 / 16)
+    assert gb.last_staging == cq.CQ_STAGING_BLOCKS and r30b == r30
     # label ids beyond the LDS histograms: global-atomic node pass after the staged move
     lab2 = (lab.astype(np.int64) * 7919 % 40009).astype(np.int32)
     note("l10m relabelled into 40009 ids: oracle")
