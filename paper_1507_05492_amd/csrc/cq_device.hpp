@@ -25,14 +25,44 @@ constexpr u32 F_SEGMENT = 16u;  // internal: a community's entries exceed its se
 struct Ctl {
   u32 flags;
   u32 K;          // non-empty communities (filled by the scan kernel)
-  u32 ticket;     // work-queue cursor of the per-community kernels
+  u32 reserved0;
   u32 dense_rows;  // node pass of column-blocked graphs: buckets that wrote histogram rows
   unsigned long long export_count;
-  unsigned long long cells;   // non-zero contingency cells (comparison)
+  unsigned long long reserved1;
   u32 changes;    // column-blocked node pass: label changes between consecutive stored ids
   u32 mode;       // column-blocked graphs: STAGE_BLOCKS or STAGE_ROWS, chosen from `changes`
   unsigned long long pad1[3];
 };
+
+// ---- work queues of the persistent per-community kernels ----------------------
+// Atomics on one address are serialised where they are performed (about 12 ns each,
+// measured on MI355X), so a single ticket counter caps a persistent kernel at one item
+// per 12 ns however many workgroups wait.  The K items of an ordered list are therefore
+// split into WQ_QUEUES interleaved queues (queue q hands out items q, q + 8, q + 16, ...,
+// so each keeps the list's order), each with its counter on its own 128-byte line.  A
+// workgroup starts on queue blockIdx.x % 8 (workgroups are dealt to the XCDs in turn)
+// and moves on to the next queue when its own is empty, so none exits while work is left.
+constexpr u32 WQ_QUEUES = 8;
+constexpr u32 WQ_LINE = 32;                    // u32 words per counter line (128 bytes)
+constexpr u32 WQ_WORDS = 2 * WQ_QUEUES * WQ_LINE;  // tickets, then per-queue 64-bit sums (cells)
+constexpr size_t WQ_BYTES = 4 * (size_t)WQ_WORDS;
+
+// Next item for the calling workgroup (thread 0 only), or 0xFFFFFFFF when every queue is
+// empty.  q and left are thread 0's own state: start with q = blockIdx.x % 8, left = 8.
+__device__ __forceinline__ u32 wq_next(u32* __restrict__ wq, u32 K, u32& q, u32& left) {
+  while (left) {
+    const u32 i = atomicAdd(&wq[q * WQ_LINE], 1u);
+    const u64 item = (u64)q + (u64)WQ_QUEUES * i;
+    if (item < K) return (u32)item;
+    q = (q + 1u) % WQ_QUEUES;
+    --left;
+  }
+  return 0xFFFFFFFFu;
+}
+// a 64-bit sum kept per queue on its own line (the second half of the region)
+__device__ __forceinline__ unsigned long long* wq_sum(u32* wq, u32 q) {
+  return reinterpret_cast<unsigned long long*>(wq + (WQ_QUEUES + q) * WQ_LINE);
+}
 
 // How a call on a column-blocked graph stages the neighbour labels (Ctl::mode; also
 // reported in the result): through the column blocks with run claims, or through the

@@ -1711,8 +1711,8 @@ __global__ __launch_bounds__(256) void k_cmp_scatter(int n, const int32_t* __res
 }
 
 // ---------------------------------------------------------------------------
-// Group pass.  Persistent workgroups take groups (communities) from a ticket
-// counter in the order produced by k_scan_order.  Each group's segment
+// Group pass.  Persistent workgroups take groups (communities) from work queues
+// (wq_next) in the order produced by k_scan_order.  Each group's segment
 // CB[start, start+len) holds label values in [0, Lv) (or SENT); the workgroup counts
 // them in LDS and hands every (label, count) with count > 0 to the visitor.
 //   direct table : Lv counters, when Lv fits the LDS budget and the group is not tiny
@@ -2001,13 +2001,13 @@ template <class V, class LT>
 __global__ __launch_bounds__(GBLOCK) void k_groups(const LT* __restrict__ CB, const u32* __restrict__ seg_start,
                                                    const u32* __restrict__ seg_len, const u32* __restrict__ order,
                                                    Ctl* __restrict__ ctl, u32 Lv, u32 lds_words, V vis,
-                                                   const unsigned long long* __restrict__ cur64) {
+                                                   const unsigned long long* __restrict__ cur64, u32* __restrict__ wq) {
   __shared__ u32 s_item;
   const u32 K = ctl->K;
-  // read once: the control block's line also holds the ticket every workgroup adds to
   const bool compact = cur64 && ctl->mode != STAGE_ROWS;
+  u32 q = blockIdx.x % WQ_QUEUES, left = WQ_QUEUES;  // thread 0's queue state
   for (;;) {
-    if (threadIdx.x == 0) s_item = atomicAdd(&ctl->ticket, 1u);
+    if (threadIdx.x == 0) s_item = wq_next(wq, K, q, left);
     __syncthreads();
     const u32 item = s_item;
     __syncthreads();
@@ -2265,11 +2265,12 @@ __global__ __launch_bounds__(GBLOCK, 6) void k_groups_w(const LT* __restrict__ C
                                                      const u32* __restrict__ seg_start, const u32* __restrict__ seg_len,
                                                      const u32* __restrict__ order, Ctl* __restrict__ ctl, u32 Lv,
                                                      ScoreVis vis, WeightedOut wo,
-                                                     const unsigned long long* __restrict__ cur64) {
+                                                     const unsigned long long* __restrict__ cur64, u32* __restrict__ wq) {
   __shared__ u32 s_item;
   const u32 K = ctl->K;
+  u32 q = blockIdx.x % WQ_QUEUES, left = WQ_QUEUES;  // thread 0's queue state (see wq_next)
   for (;;) {
-    if (threadIdx.x == 0) s_item = atomicAdd(&ctl->ticket, 1u);
+    if (threadIdx.x == 0) s_item = wq_next(wq, K, q, left);
     __syncthreads();
     const u32 item = s_item;
     __syncthreads();
@@ -2315,6 +2316,7 @@ struct CmpVis {
   int64_t* ecnt;
   long long ecap;
   Ctl* ctl;
+  u32* wq;  // non-zero cells are counted per work queue (wq_sum): one address would serialise
   struct State {
     u64 a11;
     u32 rmax;
@@ -2382,7 +2384,7 @@ struct CmpVis {
         rmax = max(rmax, r_max[i]);
         fmax = r_f[i] > fmax ? r_f[i] : fmax;
       }
-      atomicAdd(&ctl->cells, (unsigned long long)nz);
+      atomicAdd(wq_sum(wq, blockIdx.x % WQ_QUEUES), (unsigned long long)nz);
       RA11[g] = a11;
       RMAX[g] = rmax;
       RF[g] = fmax;
@@ -2810,8 +2812,10 @@ __device__ __forceinline__ double i128_to_f64(__int128 v) {
 }
 
 __global__ void k_cmp_final2(int G, const CmpPart* __restrict__ parts, long long n, long long ecap, Ctl* __restrict__ ctl,
-                             CmpResultDev* __restrict__ out) {
+                             CmpResultDev* __restrict__ out, u32* __restrict__ wq) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  unsigned long long cells = 0;
+  for (u32 q = 0; q < WQ_QUEUES; ++q) cells += *wq_sum(wq, q);
   u64 Ka = 0, Kb = 0, a11 = 0, X = 0, Y = 0, smax = 0;
   u128 xl = 0, sa = 0, sb = 0;
   double fsum = 0;
@@ -2826,7 +2830,7 @@ __global__ void k_cmp_final2(int G, const CmpPart* __restrict__ parts, long long
   const double Nd = (double)n;
   const u64 A = (u64)n * (u64)(n - 1) / 2u;
   CmpResultDev r;
-  r.n = n; r.Ka = (int64_t)Ka; r.Kb = (int64_t)Kb; r.nnz = (int64_t)ctl->cells;
+  r.n = n; r.Ka = (int64_t)Ka; r.Kb = (int64_t)Kb; r.nnz = (int64_t)cells;
   r.a11 = (int64_t)a11;
   r.a10 = (int64_t)(X - a11);
   r.a01 = (int64_t)(Y - a11);
@@ -2901,13 +2905,14 @@ __device__ __forceinline__ int find_seg(const u32* __restrict__ pre, int cnt, u3
   return lo;
 }
 
-__global__ void k_b_setup(int T, const TaskDev* __restrict__ td, u32* __restrict__ ticket) {
+__global__ void k_b_setup(int T, const TaskDev* __restrict__ td, u32* __restrict__ wq) {
   const int t = blockIdx.x;
   if (t < T) {
     u32* c = reinterpret_cast<u32*>(td[t].ctl);
     for (int i = threadIdx.x; i < (int)(sizeof(Ctl) / 4); i += blockDim.x) c[i] = 0;
   }
-  if (t == 0 && threadIdx.x == 0) *ticket = 0;
+  if (t == 0)
+    for (u32 i = threadIdx.x; i < WQ_WORDS; i += blockDim.x) wq[i] = 0;
 }
 
 __global__ __launch_bounds__(1024) void k_b_node(const TaskDev* __restrict__ td, const u32* __restrict__ Wpre, int T) {
@@ -3005,13 +3010,14 @@ __global__ __launch_bounds__(R) void k_b_gather(const GroupDev* __restrict__ gd,
   }
 }
 
-// Persistent group pass over the communities of every task (one ticket counter).
+// Persistent group pass over the communities of every task (per-XCD work queues, wq_next).
 __global__ __launch_bounds__(GBLOCK) void k_b_groups(const TaskDev* __restrict__ td, const u32* __restrict__ Kpre, int T,
-                                                     u32* __restrict__ ticket, u32 lds_words) {
+                                                     u32* __restrict__ wq, u32 lds_words) {
   __shared__ u32 s_item;
   const u32 total = Kpre[T];
+  u32 q = blockIdx.x % WQ_QUEUES, left = WQ_QUEUES;  // thread 0's queue state (see wq_next)
   for (;;) {
-    if (threadIdx.x == 0) s_item = atomicAdd(ticket, 1u);
+    if (threadIdx.x == 0) s_item = wq_next(wq, total, q, left);
     __syncthreads();
     const u32 item = s_item;
     __syncthreads();

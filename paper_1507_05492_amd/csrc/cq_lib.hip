@@ -104,7 +104,7 @@ struct cq_batch_plan {
   size_t tab_bytes = 0;
   void* td = nullptr;  // cq::TaskDev[T]
   void* gd = nullptr;  // cq::GroupDev[ngroups]
-  uint32_t *Wpre = nullptr, *Lpre = nullptr, *Gpre = nullptr, *Kpre = nullptr, *ticket = nullptr;
+  uint32_t *Wpre = nullptr, *Lpre = nullptr, *Gpre = nullptr, *Kpre = nullptr, *wq = nullptr;
   uint32_t* RBpre[3] = {nullptr, nullptr, nullptr};
   uint32_t Wsum = 0, Lsum = 0, Gsum = 0, RBsum[3] = {0, 0, 0};
   // binding
@@ -245,7 +245,7 @@ unsigned colscan_grid(int64_t L) { return grid_for(L, CS_LABELS, 1u << 30); }
 struct ScoreLayout {
   bool priv, small;  // small: labels fit 16 bits (num_labels <= 65535)
   int chunk, W, G;
-  size_t ctl, N, D, start, order, I, NP, PEN, SZ, cursor, loc, HN, HD, RL, labx, CB, parts, res, total;
+  size_t ctl, wq, N, D, start, order, I, NP, PEN, SZ, cursor, loc, HN, HD, RL, labx, CB, parts, res, total;
   size_t CW, SW, IW, PENW, INVN;  // weighted graphs only (0 otherwise)
 };
 
@@ -260,6 +260,7 @@ ScoreLayout score_layout(int64_t n, int64_t nnz, int64_t L, bool weighted = fals
   s.W = (int)((n + s.chunk - 1) / s.chunk);
   s.G = (int)std::min<int64_t>(128, std::max<int64_t>(1, (L + 1023) / 1024));
   s.ctl = c.take(sizeof(Ctl));
+  s.wq = c.take(WQ_BYTES);
   s.N = c.take(4 * L);
   s.D = c.take(4 * L);
   s.start = c.take(4 * L);
@@ -297,7 +298,7 @@ ScoreLayout graph_score_layout(const cq_graph* g, int64_t L) {
 struct CmpLayout {
   bool privA, privB, small;  // small: detected labels fit 16 bits
   int chunk, W, Wb, Ga, Gb;
-  size_t ctl, A, B, start, order, COLMAX, RA11, RMAX, RF, RXL, SZ, loc, HN, HB, CB, parts, res, total;
+  size_t ctl, wq, A, B, start, order, COLMAX, RA11, RMAX, RF, RXL, SZ, loc, HN, HB, CB, parts, res, total;
 };
 
 CmpLayout cmp_layout(int64_t n, int64_t La, int64_t Lb) {
@@ -312,6 +313,7 @@ CmpLayout cmp_layout(int64_t n, int64_t La, int64_t Lb) {
   s.Ga = (int)std::min<int64_t>(64, std::max<int64_t>(1, (La + 1023) / 1024));
   s.Gb = (int)std::min<int64_t>(64, std::max<int64_t>(1, (Lb + 1023) / 1024));
   s.ctl = c.take(sizeof(Ctl));
+  s.wq = c.take(WQ_BYTES);
   s.A = c.take(4 * La);
   s.B = c.take(4 * Lb);
   s.start = c.take(4 * La);
@@ -395,6 +397,7 @@ void score_launch(cq_context* ctx, const cq_graph* g, const int32_t* labels, int
   {
     StageMark mk(ctx, ST_SETUP, timed);
     fill(reinterpret_cast<u32*>(ctl), sizeof(Ctl) / 4, 0, s);
+    fill(at<u32>(ws, lay.wq), WQ_WORDS, 0, s);
     if (!lay.priv) fill(at<u32>(ws, lay.SZ), 2 * (size_t)L, 0, s);
     // run cursors of column-blocked graphs: cleared by the column scan on the
     // private-histogram path, here otherwise
@@ -567,7 +570,7 @@ void score_launch(cq_context* ctx, const cq_graph* g, const int32_t* labels, int
       // column-blocked graphs stage compactly: lengths and own-label counts in the cursors
       const unsigned long long* cur64 = g->rpb ? at<unsigned long long>(ws, lay.cursor) : nullptr;
       k_groups_w<LT><<<(unsigned)(ctx->num_cus * nb), GBLOCK, lds, s>>>(CB, CW, start, D, order, ctl, (u32)L, vis, wo,
-                                                                        cur64);
+                                                                        cur64, at<u32>(ws, lay.wq));
     }
     WScorePart* wparts = reinterpret_cast<WScorePart*>(parts);
     {
@@ -582,7 +585,7 @@ void score_launch(cq_context* ctx, const cq_graph* g, const int32_t* labels, int
     // column-blocked graphs stage compactly (see k_gather_blocked): lengths and own-label counts in the cursors
     const unsigned long long* cur64 = g->rpb ? at<unsigned long long>(ws, lay.cursor) : nullptr;
     k_groups<ScoreVis, LT><<<group_grid<ScoreVis, LT>(ctx, lds), GBLOCK, lds, s>>>(CB, start, D, order, ctl, (u32)L, lds_words, vis,
-                                                                                 cur64);
+                                                                                 cur64, at<u32>(ws, lay.wq));
   }
   {
     StageMark mk(ctx, ST_FINAL, timed);
@@ -629,6 +632,7 @@ void compare_launch(cq_context* ctx, int32_t n, const int32_t* la, int32_t La, c
   {
     StageMark mk(ctx, ST_SETUP, timed);
     fill(reinterpret_cast<u32*>(ctl), sizeof(Ctl) / 4, 0, s);
+    fill(at<u32>(ws, lay.wq), WQ_WORDS, 0, s);
     fill(COLMAX, (size_t)Lb, 0, s);
     if (!lay.privA) fill(at<u32>(ws, lay.SZ), 2 * (size_t)La, 0, s);
     if (!lay.privB) fill(B, (size_t)Lb, 0, s);
@@ -697,19 +701,20 @@ void compare_launch(cq_context* ctx, int32_t n, const int32_t* la, int32_t La, c
   vis.ecnt = cells ? cells->count : nullptr;
   vis.ecap = cells ? cells->capacity : 0;
   vis.ctl = ctl;
+  vis.wq = at<u32>(ws, lay.wq);
   const u32 lds_words = Lb <= DIRECT_MAX ? std::max<u32>(((u32)Lb + 3u) & ~3u, 128u) : HASH_WORDS;
   const size_t lds = (size_t)lds_words * 4;
   {
     StageMark mk(ctx, ST_GROUPS, timed);
     k_groups<CmpVis, LT><<<group_grid<CmpVis, LT>(ctx, lds), GBLOCK, lds, s>>>(CB, start, A, order, ctl, (u32)Lb, lds_words, vis,
-                                                                               nullptr);
+                                                                               nullptr, vis.wq);
   }
   CmpPart* parts = at<CmpPart>(ws, lay.parts);
   {
     StageMark mk(ctx, ST_FINAL, timed);
     k_cmp_final1<<<lay.Ga + lay.Gb, FBLOCK, 0, s>>>(La, Lb, lay.Ga, A, B, COLMAX, vis.RA11, vis.RMAX, vis.RF, vis.RXL,
                                                    (double)n, parts);
-    k_cmp_final2<<<1, 64, 0, s>>>(lay.Ga + lay.Gb, parts, n, vis.ecap, ctl, d_out);
+    k_cmp_final2<<<1, 64, 0, s>>>(lay.Ga + lay.Gb, parts, n, vis.ecap, ctl, d_out, vis.wq);
   }
 }
 
@@ -979,7 +984,7 @@ void batch_launch(cq_batch_plan* p, hipStream_t s, int rsel, int occ) {
   const TaskDev* td = static_cast<const TaskDev*>(p->td);
   const GroupDev* gd = static_cast<const GroupDev*>(p->gd);
   const int ng = (int)p->groups.size();
-  k_b_setup<<<T, 64, 0, s>>>(T, td, p->ticket);
+  k_b_setup<<<T, 64, 0, s>>>(T, td, p->wq);
   k_b_node<<<p->Wsum, 1024, 2 * (size_t)p->maxL * 4, s>>>(td, p->Wpre, T);
   k_b_colscan<<<grid_for(p->Lsum, 256, 1u << 30), 256, 0, s>>>(td, p->Lpre, T);
   k_b_scan_order<<<T, 1024, 0, s>>>(td);
@@ -990,7 +995,7 @@ void batch_launch(cq_batch_plan* p, hipStream_t s, int rsel, int occ) {
     default: k_b_gather<512><<<p->RBsum[2], 512, 0, s>>>(gd, p->RBpre[2], ng, td); break;
   }
   const u32 lds_words = std::max<u32>(((u32)p->maxL + 3u) & ~3u, 128u);
-  k_b_groups<<<(unsigned)(p->ctx->num_cus * occ), GBLOCK, (size_t)lds_words * 4, s>>>(td, p->Kpre, T, p->ticket, lds_words);
+  k_b_groups<<<(unsigned)(p->ctx->num_cus * occ), GBLOCK, (size_t)lds_words * 4, s>>>(td, p->Kpre, T, p->wq, lds_words);
   k_b_final1<<<p->Gsum, FBLOCK, 0, s>>>(td, p->Gpre, T);
   k_b_final2<<<grid_for(T, 64, 1u << 20), 64, 0, s>>>(td, T);
 }
@@ -1009,7 +1014,7 @@ BatchTabLayout batch_tab_layout(int T, int ng) {
   l.L = c.take(4 * (T + 1));
   l.G = c.take(4 * (T + 1));
   l.K = c.take(4 * (T + 1));
-  l.tk = c.take(4);
+  l.tk = c.take(WQ_BYTES);
   for (int r = 0; r < 3; ++r) l.RB[r] = c.take(4 * (ng + 1));
   l.total = c.off;
   return l;
@@ -1030,7 +1035,7 @@ void batch_fill_tables(cq_batch_plan* p, void* d_ws, cq_score_result* d_results,
   u32* Kpre = reinterpret_cast<u32*>(hb + tl.K);
   Wpre[0] = Lpre[0] = Gpre[0] = 0;
   for (int t = 0; t <= T; ++t) Kpre[t] = 0;
-  *reinterpret_cast<u32*>(hb + tl.tk) = 0;
+  std::memset(hb + tl.tk, 0, WQ_BYTES);
   for (int t = 0; t < T; ++t) {
     const cq_batch_task& bt = p->tasks[t];
     const cq_graph* g = bt.graph;
@@ -1092,7 +1097,7 @@ void batch_fill_tables(cq_batch_plan* p, void* d_ws, cq_score_result* d_results,
   p->Lpre = reinterpret_cast<u32*>(b + tl.L);
   p->Gpre = reinterpret_cast<u32*>(b + tl.G);
   p->Kpre = reinterpret_cast<u32*>(b + tl.K);
-  p->ticket = reinterpret_cast<u32*>(b + tl.tk);
+  p->wq = reinterpret_cast<u32*>(b + tl.tk);
   for (int r = 0; r < 3; ++r) {
     p->RBpre[r] = reinterpret_cast<u32*>(b + tl.RB[r]);
     p->RBsum[r] = RB[r][ng];
