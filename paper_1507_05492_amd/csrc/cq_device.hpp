@@ -25,7 +25,7 @@ constexpr u32 F_SEGMENT = 16u;  // internal: a community's entries exceed its se
 struct Ctl {
   u32 flags;
   u32 K;          // non-empty communities (filled by the scan kernel)
-  u32 reserved0;
+  u32 kbig;       // groups whose segment holds at least GW_SPLIT entries (they come first in the order)
   u32 dense_rows;  // node pass of column-blocked graphs: buckets that wrote histogram rows
   unsigned long long export_count;
   unsigned long long reserved1;
@@ -44,8 +44,11 @@ struct Ctl {
 // and moves on to the next queue when its own is empty, so none exits while work is left.
 constexpr u32 WQ_QUEUES = 8;
 constexpr u32 WQ_LINE = 32;                    // u32 words per counter line (128 bytes)
-constexpr u32 WQ_WORDS = 2 * WQ_QUEUES * WQ_LINE;  // tickets, then per-queue 64-bit sums (cells)
+// tickets of the workgroup-per-group pass, per-queue 64-bit sums (cells), tickets of the
+// wave-per-group pass
+constexpr u32 WQ_WORDS = 3 * WQ_QUEUES * WQ_LINE;
 constexpr size_t WQ_BYTES = 4 * (size_t)WQ_WORDS;
+constexpr u32 WQ_WAVE = 2 * WQ_QUEUES * WQ_LINE;  // word offset of the wave pass's tickets
 
 // Next item for the calling workgroup (thread 0 only), or 0xFFFFFFFF when every queue is
 // empty.  q and left are thread 0's own state: start with q = blockIdx.x % 8, left = 8.

@@ -1064,6 +1064,10 @@ __global__ void k_unpack(int L, const unsigned long long* __restrict__ SZ, u32* 
 // Segment starts (exclusive scan of the weights D) and the work order of the
 // non-empty groups: by decreasing floor(log2 D), so the largest groups start first.
 __device__ __forceinline__ int size_bucket(u32 x) { return x ? 32 - __clz(x) : 0; }
+// Groups whose weight (segment length bound) is below GW_SPLIT = 2^(GW_SPLIT_BUCKET - 1)
+// come last in the order; the comparison counts them one per wave (k_groups_wave).
+constexpr int GW_SPLIT_BUCKET = 12;
+constexpr u32 GW_SPLIT = 1u << (GW_SPLIT_BUCKET - 1);  // 2048
 
 // Values of labels c0 .. c0+15 (0 past L): 16-byte loads when all 16 exist (c0 is a
 // multiple of 16 and the arrays 16-byte aligned), else one guarded load per label.
@@ -1139,6 +1143,7 @@ __device__ void scan_order_body(int L, const u32* __restrict__ N, const u32* __r
     u32 off = 0;
     for (int b = 32; b >= 0; --b) { s_boff[b] = off; off += s_bcnt[b]; }
     ctl->K = off;
+    ctl->kbig = s_boff[GW_SPLIT_BUCKET - 1];  // groups in buckets >= GW_SPLIT_BUCKET
   }
   __syncthreads();
   for (int base = 0; base < L; base += 1024 * SO_PER) {
@@ -2001,9 +2006,10 @@ template <class V, class LT>
 __global__ __launch_bounds__(GBLOCK) void k_groups(const LT* __restrict__ CB, const u32* __restrict__ seg_start,
                                                    const u32* __restrict__ seg_len, const u32* __restrict__ order,
                                                    Ctl* __restrict__ ctl, u32 Lv, u32 lds_words, V vis,
-                                                   const unsigned long long* __restrict__ cur64, u32* __restrict__ wq) {
+                                                   const unsigned long long* __restrict__ cur64, u32* __restrict__ wq,
+                                                   bool big_only = false) {
   __shared__ u32 s_item;
-  const u32 K = ctl->K;
+  const u32 K = big_only ? ctl->kbig : ctl->K;  // big_only: the small groups go to k_groups_wave
   const bool compact = cur64 && ctl->mode != STAGE_ROWS;
   u32 q = blockIdx.x % WQ_QUEUES, left = WQ_QUEUES;  // thread 0's queue state
   for (;;) {
@@ -2015,6 +2021,118 @@ __global__ __launch_bounds__(GBLOCK) void k_groups(const LT* __restrict__ CB, co
     const u32 g = order[item];
     const unsigned long long c = compact ? cur64[g] : (unsigned long long)seg_len[g];
     group_one<V, LT>(CB, seg_start[g], (u32)c, g, Lv, lds_words, vis, ctl, (u32)(c >> 32));
+  }
+}
+
+// Group pass, one wave per group, for the groups after ctl->kbig in the order (segments
+// of fewer than GW_SPLIT entries; 16-bit labels).  A workgroup-wide pass spends most of
+// such a small group waiting on its barriers and its few dependent loads; here every
+// wave of a CU works on a group of its own, with no barrier at all.  Each wave counts its
+// segment in its own LDS hash table of 32-bit words (label << 16 | count): the labels are
+// below 65535 (0xFFFF marks an empty slot, never a label) and a count is at most the
+// segment length, below 2^16.  Fewer distinct labels than slots (GW_SLOTS > GW_SPLIT - 1)
+// means every probe sequence ends.  The dominant label is counted in registers as in
+// group_one.  V provides finish_wave (the visitor's reduction over one wave).
+constexpr int GW_WAVES = 8;
+constexpr u32 GW_SLOTS = 2048;
+constexpr int GW_WORDS_PER_LANE = 5;  // 320 16-byte words cover GW_SPLIT - 1 entries at any alignment
+static_assert(64 * GW_WORDS_PER_LANE * 8 >= (int)GW_SPLIT - 1 + 7 + 8, "wave segment words");
+static_assert(GW_SLOTS % (64 * 8) == 0, "visit batches");
+static_assert(GW_SLOTS > GW_SPLIT - 1, "a wave's table must have an empty slot for every segment it takes");
+template <class V>
+__global__ __launch_bounds__(64 * GW_WAVES) void k_groups_wave(const uint16_t* __restrict__ CB, const u32* __restrict__ seg_start,
+                                                              const u32* __restrict__ seg_len, const u32* __restrict__ order,
+                                                              Ctl* __restrict__ ctl, u32 Lv, V vis, u32* __restrict__ wq) {
+  __shared__ u32 s_tab[GW_WAVES * GW_SLOTS];
+  const u32 lane = threadIdx.x & 63u, w = threadIdx.x >> 6;
+  u32* tab = s_tab + w * GW_SLOTS;
+  const u32 k0 = ctl->kbig, K = ctl->K;
+  const u32 nsmall = K > k0 ? K - k0 : 0u;
+  u32 q = (blockIdx.x * GW_WAVES + w) % WQ_QUEUES, left = WQ_QUEUES;  // lane 0's queue state
+  for (;;) {
+    u32 item = 0;
+    if (lane == 0) item = wq_next(wq + WQ_WAVE, nsmall, q, left);
+    item = __shfl(item, 0, 64);
+    if (item == 0xFFFFFFFFu) break;
+    const u32 g = order[k0 + item];
+    const u32 base = seg_start[g], len = min(seg_len[g], GW_SPLIT - 1u);
+    for (u32 i = lane; i < GW_SLOTS; i += 64) tab[i] = EMPTY;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");  // the wave's clears land before its inserts
+    // The segment's 16-byte words, all loaded before the first is used: word w of the
+    // aligned range holds entries a0 + 8w .. a0 + 8w + 7 (entries outside the segment are
+    // skipped; the word past its end still lies inside the workspace's carved array).
+    const u32 a0 = base & ~7u;
+    const u32 nw = (base + len - a0 + 7u) >> 3;  // at most GW_WORDS_PER_LANE * 64 words
+    const uint4* cb4 = reinterpret_cast<const uint4*>(CB + a0);
+    uint4 wv[GW_WORDS_PER_LANE];
+#pragma unroll
+    for (int i = 0; i < GW_WORDS_PER_LANE; ++i) {
+      const u32 wi = lane + 64u * (u32)i;
+      wv[i] = wi < nw ? cb4[wi] : make_uint4(0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu);
+    }
+    const u32 hot = V::kHotIsGroup ? g : (len ? (u32)CB[base] : 0xFFFFFFFFu);
+    u32 mine = 0, lost = 0;
+#pragma unroll
+    for (int i = 0; i < GW_WORDS_PER_LANE; ++i) {
+      const u32 w4[4] = {wv[i].x, wv[i].y, wv[i].z, wv[i].w};
+      const u32 e0 = a0 + 8u * (lane + 64u * (u32)i);
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const u32 e = e0 + (u32)k;
+        const u32 j = (w4[k >> 1] >> (16 * (k & 1))) & 0xFFFFu;
+        if (e < base || e >= base + len) continue;
+        if (j == hot) {
+          ++mine;
+          continue;
+        }
+        if (j >= Lv) continue;
+        u32 h = hash_slot(j, 11);  // log2(GW_SLOTS)
+        bool done = false;
+        for (u32 p = 0; p < GW_SLOTS && !done; ++p) {
+          const u32 t = tab[h];
+          if ((t >> 16) == j) {
+            atomicAdd(&tab[h], 1u);
+            done = true;
+          } else if (t == EMPTY) {
+            const u32 old = atomicCAS(&tab[h], EMPTY, (j << 16) | 1u);
+            if (old == EMPTY) {
+              done = true;
+            } else if ((old >> 16) == j) {
+              atomicAdd(&tab[h], 1u);
+              done = true;
+            }
+          }
+          if (!done) h = (h + 1u) & (GW_SLOTS - 1u);
+        }
+        lost += done ? 0u : 1u;  // never expected (the table always has an empty slot)
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");  // every insert lands before the reads
+    if (lost) atomicOr(&ctl->flags, F_STACK);
+    typename V::State st;
+    vis.begin(st, g);
+    // the lane's slots in batches of 8: the batch's sizes are loaded before its visits
+    for (u32 i0 = lane; i0 < GW_SLOTS; i0 += 64u * 8u) {
+      u32 k[8], sz[8];
+#pragma unroll
+      for (int b = 0; b < 8; ++b) k[b] = tab[i0 + 64u * (u32)b];
+#pragma unroll
+      for (int b = 0; b < 8; ++b) sz[b] = k[b] != EMPTY ? vis.size_of(k[b] >> 16) : 0u;
+#pragma unroll
+      for (int b = 0; b < 8; ++b) {
+        if (k[b] != EMPTY) {
+          vis.visit_n(st, k[b] >> 16, k[b] & 0xFFFFu, sz[b]);
+          vis.settle(st);
+        }
+      }
+    }
+    const u32 nhot = (u32)wave_sum_u64(mine);
+    if (lane == 0 && nhot && hot < Lv) {
+      vis.visit(st, hot, nhot);
+      vis.settle(st);
+    }
+    vis.finish_wave(st, g);
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");  // the table's reads end before the next clears
   }
 }
 
@@ -2336,8 +2454,10 @@ struct CmpVis {
     st.nz = 0;
   }
   __device__ void settle(State&) {}  // every visit adds exactly
-  __device__ void visit(State& st, u32 j, u32 x) {
-    const u32 bj = B[j];
+  __device__ u32 size_of(u32 j) const { return B[j]; }
+  __device__ void visit(State& st, u32 j, u32 x) { visit_n(st, j, x, B[j]); }
+  // the same with |c'_j| = bj already loaded
+  __device__ void visit_n(State& st, u32 j, u32 x, u32 bj) {
     st.a11 += (u64)x * (u64)(x - 1u) / 2u;
     st.rmax = max(st.rmax, x);
     double f = 2.0 * (double)x / (double)((u64)st.ai + (u64)bj);   // Eq. 3 ratio
@@ -2384,6 +2504,21 @@ struct CmpVis {
         rmax = max(rmax, r_max[i]);
         fmax = r_f[i] > fmax ? r_f[i] : fmax;
       }
+      atomicAdd(wq_sum(wq, blockIdx.x % WQ_QUEUES), (unsigned long long)nz);
+      RA11[g] = a11;
+      RMAX[g] = rmax;
+      RF[g] = fmax;
+      RXL[2 * (size_t)g] = (u64)xl;
+      RXL[2 * (size_t)g + 1] = (u64)(xl >> 64);
+    }
+  }
+  // The same reductions over one wave (k_groups_wave): no barrier, lane 0 writes.
+  __device__ void finish_wave(State& st, u32 g) {
+    const u128 xl = wave_sum_u128(st.xl.value());
+    const u64 a11 = wave_sum_u64(st.a11), nz = wave_sum_u64(st.nz);
+    const u32 rmax = wave_max_u32(st.rmax);
+    const double fmax = wave_max_f64(st.fmax);
+    if ((threadIdx.x & 63) == 0) {
       atomicAdd(wq_sum(wq, blockIdx.x % WQ_QUEUES), (unsigned long long)nz);
       RA11[g] = a11;
       RMAX[g] = rmax;

@@ -706,8 +706,16 @@ void compare_launch(cq_context* ctx, int32_t n, const int32_t* la, int32_t La, c
   const size_t lds = (size_t)lds_words * 4;
   {
     StageMark mk(ctx, ST_GROUPS, timed);
+    // 16-bit labels: groups of fewer than GW_SPLIT entries are counted one per wave after
+    // the workgroup-per-group pass has taken the larger ones
+    constexpr bool waves = sizeof(LT) == 2;
     k_groups<CmpVis, LT><<<group_grid<CmpVis, LT>(ctx, lds), GBLOCK, lds, s>>>(CB, start, A, order, ctl, (u32)Lb, lds_words, vis,
-                                                                               nullptr, vis.wq);
+                                                                               nullptr, vis.wq, waves);
+    if constexpr (waves) {
+      int nb = 0;
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_groups_wave<CmpVis>, 64 * GW_WAVES, 0) != hipSuccess || nb < 1) nb = 1;
+      k_groups_wave<CmpVis><<<(unsigned)(ctx->num_cus * nb), 64 * GW_WAVES, 0, s>>>(CB, start, A, order, ctl, (u32)Lb, vis, vis.wq);
+    }
   }
   CmpPart* parts = at<CmpPart>(ws, lay.parts);
   {

@@ -111,6 +111,32 @@ def test_wide_counter_wraps(cq, ctx):
     run_cmp(cq, ctx, a3, 1, b3, 40003, "log overflow: 8.7e6 entries in two cells")
 
 
+def test_wave_groups(cq, ctx):
+    """Ground-truth groups of fewer than 2,048 nodes are counted one per wave, larger ones
+    by a whole workgroup: groups on both sides of the split, a wave group whose 2,046
+    other nodes all carry distinct detected labels (its table nearly full), singletons,
+    and a group of one repeated label, against the oracle with the whole table."""
+    rng = np.random.default_rng(5)
+    sizes = [2047, 2048, 2049, 1, 1, 300, 1500, 4000, 2046]
+    a = np.repeat(np.arange(len(sizes), dtype=np.int32), sizes)
+    b = np.zeros_like(a)
+    off = np.concatenate([[0], np.cumsum(sizes)])
+    Lb = 9000
+    b[off[0]:off[1]] = np.arange(2047) + 10               # every node its own detected label
+    b[off[1]:off[2]] = rng.integers(0, 7, 2048)           # few labels, large counts
+    b[off[2]:off[3]] = rng.integers(0, Lb, 2049)
+    b[off[5]:off[6]] = 3                                  # one label only
+    b[off[6]:off[7]] = rng.integers(0, 40, 1500)
+    b[off[7]:off[8]] = rng.integers(0, Lb, 4000)
+    b[off[8]:off[9]] = np.concatenate([[5] * 1000, rng.integers(100, 8000, 1046)])
+    perm = rng.permutation(len(a))
+    run_cmp(cq, ctx, a[perm], len(sizes), b[perm], Lb, "groups around the wave split")
+    # m100k ground truth against a random partition: every small group is full of distinct labels
+    g = lfr_graph(CONFIGS["m100k_mu0.3"], 19)
+    rl = random_labels(g.n, 20000, 191).numpy()
+    run_cmp(cq, ctx, g.labels.numpy(), g.num_labels, rl, 20000, "m100k ground truth vs 20000 random labels")
+
+
 def test_full_size_l10m(cq, ctx):
     """The comparison the benchmark times: ground truth of the 10M-node graph against 10 %
     of its nodes reassigned.  Every pair count and the whole contingency table exact."""
