@@ -3145,21 +3145,37 @@ __global__ __launch_bounds__(R) void k_b_gather(const GroupDev* __restrict__ gd,
   }
 }
 
+// The group pass's items as one list: item i (Kpre[t] <= i < Kpre[t+1]) is group
+// order_t[i - Kpre[t]] of task t, packed as (t << 14) | group (groups < 16384 in a batch),
+// so that the persistent pass needs one load per item instead of a search over Kpre.
+__global__ __launch_bounds__(256) void k_b_items(const TaskDev* __restrict__ td, const u32* __restrict__ Kpre, int T,
+                                                 u32* __restrict__ items) {
+  const u32 total = Kpre[T];
+  for (u32 i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) {
+    const int t = find_seg(Kpre, T, i);
+    items[i] = ((u32)t << 14) | td[t].order[i - Kpre[t]];
+  }
+}
+
 // Persistent group pass over the communities of every task (per-XCD work queues, wq_next).
 __global__ __launch_bounds__(GBLOCK) void k_b_groups(const TaskDev* __restrict__ td, const u32* __restrict__ Kpre, int T,
-                                                     u32* __restrict__ wq, u32 lds_words) {
-  __shared__ u32 s_item;
+                                                     u32* __restrict__ wq, u32 lds_words, const u32* __restrict__ items) {
+  __shared__ u32 s_item, s_tg;
   const u32 total = Kpre[T];
   u32 q = blockIdx.x % WQ_QUEUES, left = WQ_QUEUES;  // thread 0's queue state (see wq_next)
   for (;;) {
-    if (threadIdx.x == 0) s_item = wq_next(wq, total, q, left);
+    if (threadIdx.x == 0) {
+      const u32 it = wq_next(wq, total, q, left);
+      s_item = it;
+      s_tg = it < total ? items[it] : 0u;
+    }
     __syncthreads();
-    const u32 item = s_item;
+    const u32 item = s_item, tg = s_tg;
     __syncthreads();
     if (item >= total) break;
-    const int t = find_seg(Kpre, T, item);
+    const int t = (int)(tg >> 14);
     const TaskDev& d = td[t];
-    const u32 g = d.order[item - Kpre[t]];
+    const u32 g = tg & 0x3FFFu;
     ScoreVis vis;
     vis.N = d.N;
     vis.twom = (double)d.nnz;

@@ -96,6 +96,7 @@ struct cq_batch_plan {
   std::vector<cq_batch_task> tasks;
   std::vector<size_t> ws_off;  // per-task workspace offset
   size_t ws_total = 0;
+  size_t items_off = 0;  // workspace offset of the flat (task, group) list of the group pass
   std::vector<std::array<int, 4>> groups;
   std::vector<int> group_np;
   int maxL = 1;
@@ -105,6 +106,7 @@ struct cq_batch_plan {
   void* td = nullptr;  // cq::TaskDev[T]
   void* gd = nullptr;  // cq::GroupDev[ngroups]
   uint32_t *Wpre = nullptr, *Lpre = nullptr, *Gpre = nullptr, *Kpre = nullptr, *wq = nullptr;
+  uint32_t* items = nullptr;  // (task << 14) | group of every item of the group pass (in the workspace)
   uint32_t* RBpre[3] = {nullptr, nullptr, nullptr};
   uint32_t Wsum = 0, Lsum = 0, Gsum = 0, RBsum[3] = {0, 0, 0};
   // binding
@@ -986,6 +988,7 @@ cq_status build_locality_order(cq_context* ctx, cq_graph* g, const int32_t* rp, 
 // ---- batched scoring -------------------------------------------------------
 constexpr int kGatherRows[3] = {128, 256, 512};
 constexpr int64_t BATCH_MAX_L = PRIV_MAX;
+constexpr int BATCH_MAX_TASKS = 1 << 18;  // the group pass's item list packs (task << 14) | group
 
 void batch_launch(cq_batch_plan* p, hipStream_t s, int rsel, int occ) {
   const int T = (int)p->tasks.size();
@@ -997,13 +1000,15 @@ void batch_launch(cq_batch_plan* p, hipStream_t s, int rsel, int occ) {
   k_b_colscan<<<grid_for(p->Lsum, 256, 1u << 30), 256, 0, s>>>(td, p->Lpre, T);
   k_b_scan_order<<<T, 1024, 0, s>>>(td);
   k_b_kprefix<<<1, 1024, 0, s>>>(td, T, p->Kpre);
+  k_b_items<<<(unsigned)(p->ctx->num_cus * 4), 256, 0, s>>>(td, p->Kpre, T, p->items);
   switch (rsel) {
     case 0: k_b_gather<128><<<p->RBsum[0], 128, 0, s>>>(gd, p->RBpre[0], ng, td); break;
     case 1: k_b_gather<256><<<p->RBsum[1], 256, 0, s>>>(gd, p->RBpre[1], ng, td); break;
     default: k_b_gather<512><<<p->RBsum[2], 512, 0, s>>>(gd, p->RBpre[2], ng, td); break;
   }
   const u32 lds_words = std::max<u32>(((u32)p->maxL + 3u) & ~3u, 128u);
-  k_b_groups<<<(unsigned)(p->ctx->num_cus * occ), GBLOCK, (size_t)lds_words * 4, s>>>(td, p->Kpre, T, p->wq, lds_words);
+  k_b_groups<<<(unsigned)(p->ctx->num_cus * occ), GBLOCK, (size_t)lds_words * 4, s>>>(td, p->Kpre, T, p->wq, lds_words,
+                                                                                      p->items);
   k_b_final1<<<p->Gsum, FBLOCK, 0, s>>>(td, p->Gpre, T);
   k_b_final2<<<grid_for(T, 64, 1u << 20), 64, 0, s>>>(td, T);
 }
@@ -1114,6 +1119,7 @@ void batch_fill_tables(cq_batch_plan* p, void* d_ws, cq_score_result* d_results,
   p->Lsum = Lpre[T];
   p->Gsum = Gpre[T];
   p->ws = d_ws;
+  p->items = reinterpret_cast<uint32_t*>(static_cast<char*>(d_ws) + p->items_off);
   p->d_results = d_results;
 }
 
@@ -1124,11 +1130,14 @@ void batch_layout(cq_batch_plan* p) {
   p->group_np.clear();
   p->maxL = 1;
   Carve c;
+  size_t labels_total = 0;
   for (const auto& t : p->tasks) {
     const ScoreLayout lay = score_layout(t.graph->n, t.graph->nnz, t.num_labels);
     p->ws_off.push_back(c.take(lay.total));
     p->maxL = std::max(p->maxL, (int)t.num_labels);
+    labels_total += (size_t)t.num_labels;
   }
+  p->items_off = c.take(4 * labels_total);  // at most one item per label id of every task
   p->ws_total = c.off;
   std::map<const cq_graph*, int> open;
   for (int i = 0; i < (int)p->tasks.size(); ++i) {
@@ -1366,12 +1375,13 @@ void srv_dispatch(cq_server* s, SrvSlot* sl) {
 
 // Footprint of a group of small scoring requests run as one batched launch.
 size_t group_footprint(const std::vector<SrvReq*>& g) {
-  size_t lab = 0, ws = 0;
+  size_t lab = 0, ws = 0, items = 0;
   for (const SrvReq* r : g) {
     lab += aup(4 * (size_t)r->n);
     ws += aup(score_layout(r->g->n, r->g->nnz, r->L).total);
+    items += 4 * (size_t)r->L;  // the group pass's item list (batch_layout)
   }
-  return lab + aup(ws) + aup(sizeof(cq_score_result) * g.size());
+  return lab + aup(ws + aup(items)) + aup(sizeof(cq_score_result) * g.size());
 }
 
 void srv_loop(cq_server* s) {
@@ -1832,6 +1842,7 @@ cq_status cq_batch_plan_create(cq_context* ctx, const cq_batch_task* tasks, int3
       return fail(ctx, CQ_E_INVALID_ARG, "task %d: num_labels must be in [1, %lld] for batching", i, (long long)BATCH_MAX_L);
     if (t.graph->nnz == 0) return fail(ctx, CQ_E_NO_EDGES, "task %d: graph has no edges", i);
   }
+  if (num_tasks > BATCH_MAX_TASKS) return fail(ctx, CQ_E_INVALID_ARG, "at most %d tasks per batch", BATCH_MAX_TASKS);
   cq_batch_plan* p = new (std::nothrow) cq_batch_plan();
   if (!p) return fail(ctx, CQ_E_DEVICE, "out of host memory");
   p->ctx = ctx;
