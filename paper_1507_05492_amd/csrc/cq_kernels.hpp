@@ -2039,15 +2039,105 @@ constexpr int GW_WORDS_PER_LANE = 5;  // 320 16-byte words cover GW_SPLIT - 1 en
 static_assert(64 * GW_WORDS_PER_LANE * 8 >= (int)GW_SPLIT - 1 + 7 + 8, "wave segment words");
 static_assert(GW_SLOTS % (64 * 8) == 0, "visit batches");
 static_assert(GW_SLOTS > GW_SPLIT - 1, "a wave's table must have an empty slot for every segment it takes");
+// One group counted by the calling wave in its table `tab` (GW_SLOTS words): segment
+// CB[base, base + len) with len < GW_SPLIT, hot0 entries of the hot label left out of it
+// (compact staging).  Every term the visitor gets is settled on its own (slot order follows
+// the atomics), so a group's result does not depend on which lanes met which labels.
+template <class V>
+__device__ __forceinline__ void wave_group_one(u32* tab, const uint16_t* __restrict__ CB, u32 base, u32 len, u32 hot0, u32 g,
+                                               u32 Lv, V& vis, Ctl* __restrict__ ctl) {
+  const u32 lane = threadIdx.x & 63u;
+  for (u32 i = lane; i < GW_SLOTS; i += 64) tab[i] = EMPTY;
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");  // the wave's clears land before its inserts
+  // The segment's 16-byte words, all loaded before the first is used: word w of the
+  // aligned range holds entries a0 + 8w .. a0 + 8w + 7 (entries outside the segment are
+  // skipped; the word past its end still lies inside the workspace's carved array).
+  const u32 a0 = base & ~7u;
+  const u32 nw = (base + len - a0 + 7u) >> 3;  // at most GW_WORDS_PER_LANE * 64 words
+  const uint4* cb4 = reinterpret_cast<const uint4*>(CB + a0);
+  uint4 wv[GW_WORDS_PER_LANE];
+#pragma unroll
+  for (int i = 0; i < GW_WORDS_PER_LANE; ++i) {
+    const u32 wi = lane + 64u * (u32)i;
+    wv[i] = wi < nw ? cb4[wi] : make_uint4(0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu);
+  }
+  const u32 hot = V::kHotIsGroup ? g : (len ? (u32)CB[base] : 0xFFFFFFFFu);
+  u32 mine = 0, lost = 0;
+#pragma unroll
+  for (int i = 0; i < GW_WORDS_PER_LANE; ++i) {
+    const u32 w4[4] = {wv[i].x, wv[i].y, wv[i].z, wv[i].w};
+    const u32 e0 = a0 + 8u * (lane + 64u * (u32)i);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const u32 e = e0 + (u32)k;
+      const u32 j = (w4[k >> 1] >> (16 * (k & 1))) & 0xFFFFu;
+      if (e < base || e >= base + len) continue;
+      if (j == hot) {
+        ++mine;
+        continue;
+      }
+      if (j >= Lv) continue;
+      u32 h = hash_slot(j, 11);  // log2(GW_SLOTS)
+      bool done = false;
+      for (u32 p = 0; p < GW_SLOTS && !done; ++p) {
+        const u32 t = tab[h];
+        if ((t >> 16) == j) {
+          atomicAdd(&tab[h], 1u);
+          done = true;
+        } else if (t == EMPTY) {
+          const u32 old = atomicCAS(&tab[h], EMPTY, (j << 16) | 1u);
+          if (old == EMPTY) {
+            done = true;
+          } else if ((old >> 16) == j) {
+            atomicAdd(&tab[h], 1u);
+            done = true;
+          }
+        }
+        if (!done) h = (h + 1u) & (GW_SLOTS - 1u);
+      }
+      lost += done ? 0u : 1u;  // never expected (the table always has an empty slot)
+    }
+  }
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");  // every insert lands before the reads
+  if (lost) atomicOr(&ctl->flags, F_STACK);
+  typename V::State st;
+  vis.begin_wave(st, g);
+  // the lane's slots in batches of 8: the batch's sizes are loaded before its visits
+  for (u32 i0 = lane; i0 < GW_SLOTS; i0 += 64u * 8u) {
+    u32 k[8], sz[8];
+#pragma unroll
+    for (int b = 0; b < 8; ++b) k[b] = tab[i0 + 64u * (u32)b];
+#pragma unroll
+    for (int b = 0; b < 8; ++b) sz[b] = k[b] != EMPTY ? vis.size_of(k[b] >> 16) : 0u;
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      if (k[b] != EMPTY) {
+        vis.visit_n(st, k[b] >> 16, k[b] & 0xFFFFu, sz[b]);
+        vis.settle(st);
+      }
+    }
+  }
+  const u32 nhot = (u32)wave_sum_u64(mine) + hot0;
+  if (lane == 0 && nhot && hot < Lv) {
+    vis.visit(st, hot, nhot);
+    vis.settle(st);
+  }
+  vis.finish_wave(st, g);
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");  // the table's reads end before the next clears
+}
+
+// cur64 (compact staging of a column-blocked graph, else null): as in k_groups.
 template <class V>
 __global__ __launch_bounds__(64 * GW_WAVES) void k_groups_wave(const uint16_t* __restrict__ CB, const u32* __restrict__ seg_start,
                                                               const u32* __restrict__ seg_len, const u32* __restrict__ order,
-                                                              Ctl* __restrict__ ctl, u32 Lv, V vis, u32* __restrict__ wq) {
+                                                              Ctl* __restrict__ ctl, u32 Lv, V vis, u32* __restrict__ wq,
+                                                              const unsigned long long* __restrict__ cur64 = nullptr) {
   __shared__ u32 s_tab[GW_WAVES * GW_SLOTS];
   const u32 lane = threadIdx.x & 63u, w = threadIdx.x >> 6;
   u32* tab = s_tab + w * GW_SLOTS;
   const u32 k0 = ctl->kbig, K = ctl->K;
   const u32 nsmall = K > k0 ? K - k0 : 0u;
+  const bool compact = cur64 && ctl->mode != STAGE_ROWS;
   u32 q = (blockIdx.x * GW_WAVES + w) % WQ_QUEUES, left = WQ_QUEUES;  // lane 0's queue state
   for (;;) {
     u32 item = 0;
@@ -2055,84 +2145,8 @@ __global__ __launch_bounds__(64 * GW_WAVES) void k_groups_wave(const uint16_t* _
     item = __shfl(item, 0, 64);
     if (item == 0xFFFFFFFFu) break;
     const u32 g = order[k0 + item];
-    const u32 base = seg_start[g], len = min(seg_len[g], GW_SPLIT - 1u);
-    for (u32 i = lane; i < GW_SLOTS; i += 64) tab[i] = EMPTY;
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");  // the wave's clears land before its inserts
-    // The segment's 16-byte words, all loaded before the first is used: word w of the
-    // aligned range holds entries a0 + 8w .. a0 + 8w + 7 (entries outside the segment are
-    // skipped; the word past its end still lies inside the workspace's carved array).
-    const u32 a0 = base & ~7u;
-    const u32 nw = (base + len - a0 + 7u) >> 3;  // at most GW_WORDS_PER_LANE * 64 words
-    const uint4* cb4 = reinterpret_cast<const uint4*>(CB + a0);
-    uint4 wv[GW_WORDS_PER_LANE];
-#pragma unroll
-    for (int i = 0; i < GW_WORDS_PER_LANE; ++i) {
-      const u32 wi = lane + 64u * (u32)i;
-      wv[i] = wi < nw ? cb4[wi] : make_uint4(0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu);
-    }
-    const u32 hot = V::kHotIsGroup ? g : (len ? (u32)CB[base] : 0xFFFFFFFFu);
-    u32 mine = 0, lost = 0;
-#pragma unroll
-    for (int i = 0; i < GW_WORDS_PER_LANE; ++i) {
-      const u32 w4[4] = {wv[i].x, wv[i].y, wv[i].z, wv[i].w};
-      const u32 e0 = a0 + 8u * (lane + 64u * (u32)i);
-#pragma unroll
-      for (int k = 0; k < 8; ++k) {
-        const u32 e = e0 + (u32)k;
-        const u32 j = (w4[k >> 1] >> (16 * (k & 1))) & 0xFFFFu;
-        if (e < base || e >= base + len) continue;
-        if (j == hot) {
-          ++mine;
-          continue;
-        }
-        if (j >= Lv) continue;
-        u32 h = hash_slot(j, 11);  // log2(GW_SLOTS)
-        bool done = false;
-        for (u32 p = 0; p < GW_SLOTS && !done; ++p) {
-          const u32 t = tab[h];
-          if ((t >> 16) == j) {
-            atomicAdd(&tab[h], 1u);
-            done = true;
-          } else if (t == EMPTY) {
-            const u32 old = atomicCAS(&tab[h], EMPTY, (j << 16) | 1u);
-            if (old == EMPTY) {
-              done = true;
-            } else if ((old >> 16) == j) {
-              atomicAdd(&tab[h], 1u);
-              done = true;
-            }
-          }
-          if (!done) h = (h + 1u) & (GW_SLOTS - 1u);
-        }
-        lost += done ? 0u : 1u;  // never expected (the table always has an empty slot)
-      }
-    }
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");  // every insert lands before the reads
-    if (lost) atomicOr(&ctl->flags, F_STACK);
-    typename V::State st;
-    vis.begin(st, g);
-    // the lane's slots in batches of 8: the batch's sizes are loaded before its visits
-    for (u32 i0 = lane; i0 < GW_SLOTS; i0 += 64u * 8u) {
-      u32 k[8], sz[8];
-#pragma unroll
-      for (int b = 0; b < 8; ++b) k[b] = tab[i0 + 64u * (u32)b];
-#pragma unroll
-      for (int b = 0; b < 8; ++b) sz[b] = k[b] != EMPTY ? vis.size_of(k[b] >> 16) : 0u;
-#pragma unroll
-      for (int b = 0; b < 8; ++b) {
-        if (k[b] != EMPTY) {
-          vis.visit_n(st, k[b] >> 16, k[b] & 0xFFFFu, sz[b]);
-          vis.settle(st);
-        }
-      }
-    }
-    const u32 nhot = (u32)wave_sum_u64(mine);
-    if (lane == 0 && nhot && hot < Lv) {
-      vis.visit(st, hot, nhot);
-      vis.settle(st);
-    }
-    vis.finish_wave(st, g);
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");  // the table's reads end before the next clears
+    const unsigned long long c = compact ? cur64[g] : (unsigned long long)seg_len[g];
+    wave_group_one<V>(tab, CB, seg_start[g], min((u32)c, GW_SPLIT - 1u), (u32)(c >> 32), g, Lv, vis, ctl);
   }
 }
 
@@ -2192,6 +2206,16 @@ struct ScoreVis {
     st.denom = twom * (double)N[g];
     if (threadIdx.x == 0) I[g] = 0;  // overwritten by the thread that meets label g
   }
+  // k_groups_wave: lane 0 of the group's wave clears I[g]
+  __device__ void begin_wave(State& st, u32 g) {
+    st.pen = Frac96Sum();
+    st.acc = 0.0;
+    st.np = 0;
+    st.g = g;
+    st.denom = twom * (double)N[g];
+    if ((threadIdx.x & 63) == 0) I[g] = 0;
+  }
+  __device__ u32 size_of(u32 j) const { return N[j]; }
   __device__ void visit(State& st, u32 j, u32 x) { visit_n(st, j, x, N[j]); }
   // the same with |j| = nj already loaded
   __device__ void visit_n(State& st, u32 j, u32 x, u32 nj) {
@@ -2240,6 +2264,16 @@ struct ScoreVis {
       PEN[2 * (size_t)g] = (u64)p;
       PEN[2 * (size_t)g + 1] = (u64)(p >> 64);
       NP[g] = (u32)q;
+    }
+  }
+  // The same over one wave (k_groups_wave): no barrier, lane 0 writes.
+  __device__ void finish_wave(State& st, u32 g) {
+    const u128 pen = wave_sum_u128(st.pen.value());
+    const u64 np = wave_sum_u64(st.np);
+    if ((threadIdx.x & 63) == 0) {
+      PEN[2 * (size_t)g] = (u64)pen;
+      PEN[2 * (size_t)g + 1] = (u64)(pen >> 64);
+      NP[g] = (u32)np;
     }
   }
 };
@@ -2454,6 +2488,7 @@ struct CmpVis {
     st.nz = 0;
   }
   __device__ void settle(State&) {}  // every visit adds exactly
+  __device__ void begin_wave(State& st, u32 g) { begin(st, g); }
   __device__ u32 size_of(u32 j) const { return B[j]; }
   __device__ void visit(State& st, u32 j, u32 x) { visit_n(st, j, x, B[j]); }
   // the same with |c'_j| = bj already loaded

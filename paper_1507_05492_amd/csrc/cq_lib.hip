@@ -586,8 +586,22 @@ void score_launch(cq_context* ctx, const cq_graph* g, const int32_t* labels, int
     StageMark mk(ctx, ST_GROUPS, timed);
     // column-blocked graphs stage compactly (see k_gather_blocked): lengths and own-label counts in the cursors
     const unsigned long long* cur64 = g->rpb ? at<unsigned long long>(ws, lay.cursor) : nullptr;
+    // Label spaces beyond the direct LDS table (16-bit labels): groups of degree sum below
+    // GW_SPLIT are counted one per wave after the workgroup-per-group pass has taken the
+    // others.  The choice depends on num_labels and the degree sums only, so a group takes
+    // the same pass in every storage; batches (num_labels <= 16384) never split.  With
+    // direct tables the split costs more than it gains: the large groups' tail no longer
+    // overlaps the small ones.
+    const bool waves = sizeof(LT) == 2 && L > DIRECT_MAX;
     k_groups<ScoreVis, LT><<<group_grid<ScoreVis, LT>(ctx, lds), GBLOCK, lds, s>>>(CB, start, D, order, ctl, (u32)L, lds_words, vis,
-                                                                                 cur64, at<u32>(ws, lay.wq));
+                                                                                 cur64, at<u32>(ws, lay.wq), waves);
+    if (waves) {
+      int nb = 0;
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_groups_wave<ScoreVis>, 64 * GW_WAVES, 0) != hipSuccess || nb < 1)
+        nb = 1;
+      k_groups_wave<ScoreVis><<<(unsigned)(ctx->num_cus * nb), 64 * GW_WAVES, 0, s>>>(
+          reinterpret_cast<const uint16_t*>(CB), start, D, order, ctl, (u32)L, vis, at<u32>(ws, lay.wq), cur64);
+    }
   }
   {
     StageMark mk(ctx, ST_FINAL, timed);
