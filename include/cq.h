@@ -128,6 +128,7 @@ typedef struct {
   double total_weight; /* W: sum of the edge weights (|E| for an unweighted graph) */
   int64_t clusters;        /* CQ_GRAPH_REORDER: label-propagation clusters the order groups (else 0) */
   int64_t largest_cluster; /* nodes in the largest of them (else 0) */
+  int64_t degree_bins[32]; /* nodes per degree bin: [0] degree 0, [b] degrees in [2^(b-1), 2^b) */
 } cq_graph_stats;
 
 /*

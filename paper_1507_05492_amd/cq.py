@@ -104,7 +104,7 @@ class GraphStats(ctypes.Structure):
     _fields_ = [("n", _I64), ("nnz", _I64), ("m", _I64), ("max_degree", _I64), ("validated", ctypes.c_uint32),
                 ("reordered", ctypes.c_uint32), ("owned_bytes", _I64), ("weighted", ctypes.c_uint32),
                 ("pad", ctypes.c_uint32), ("total_weight", ctypes.c_double), ("clusters", _I64),
-                ("largest_cluster", _I64)]
+                ("largest_cluster", _I64), ("degree_bins", _I64 * 32)]
 
 
 def _load():
@@ -262,7 +262,9 @@ def cq_graph_get_stats(g: int) -> dict:
     st = _lib.cq_graph_get_stats(g, ctypes.byref(s))
     if st != CQ_OK:
         raise CQError(st)
-    return {k: getattr(s, k) for k, _ in GraphStats._fields_ if k != "pad"}
+    out = {k: getattr(s, k) for k, _ in GraphStats._fields_ if k != "pad"}
+    out["degree_bins"] = list(out["degree_bins"])
+    return out
 
 
 def cq_graph_release(g: int) -> None:

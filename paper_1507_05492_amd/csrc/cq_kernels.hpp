@@ -23,19 +23,34 @@ __global__ void k_fill_u32(u32* __restrict__ p, size_t count, u32 v) {
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x) p[i] = v;
 }
 
+// floor(log2(x)) + 1 for x > 0, 0 for x = 0
+__device__ __forceinline__ int size_bucket_u32(u32 x) { return x ? 32 - __clz(x) : 0; }
+
 // ---------------------------------------------------------------------------
 // Graph checks (load time).  Structural: offsets monotone and within [0, nnz],
 // indices within [0, n).  Full: no self-loops, rows strictly increasing (sorted, no
 // repeated entry), and every (u, v) has its mirror (v, u).
+// It also counts the degrees in power-of-two bins: bins[b] gets the rows with
+// floor(log2(deg)) = b - 1 (bins[0]: the rows without entries).
+constexpr int DEG_BINS = 32;
 __global__ void k_check_csr(int n, long long nnz, const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
-                            u32* __restrict__ flags, u32* __restrict__ maxdeg) {
+                            u32* __restrict__ flags, u32* __restrict__ maxdeg, u32* __restrict__ bins) {
+  __shared__ u32 s_bins[DEG_BINS];
+  if (threadIdx.x < DEG_BINS) s_bins[threadIdx.x] = 0;
+  __syncthreads();
   u32 bad = 0, md = 0;
   size_t stride = (size_t)gridDim.x * blockDim.x;
   for (size_t u = (size_t)blockIdx.x * blockDim.x + threadIdx.x; u < (size_t)n; u += stride) {
     long long a = rp[u], b = rp[u + 1];
-    if (a < 0 || b < a || b > nnz) bad = 1;
-    else md = max(md, (u32)(b - a));
+    if (a < 0 || b < a || b > nnz) {
+      bad = 1;
+    } else {
+      md = max(md, (u32)(b - a));
+      atomicAdd(&s_bins[size_bucket_u32((u32)(b - a))], 1u);
+    }
   }
+  __syncthreads();
+  if (threadIdx.x < DEG_BINS && s_bins[threadIdx.x]) atomicAdd(&bins[threadIdx.x], s_bins[threadIdx.x]);
   for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < (size_t)nnz; e += stride) {
     int v = col[e];
     if (v < 0 || v >= n) bad = 1;

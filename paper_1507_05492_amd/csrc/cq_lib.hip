@@ -50,6 +50,7 @@ struct cq_graph {
   const int32_t* col = nullptr;
   const int32_t* perm = nullptr;  // graph row -> caller node id (null: identity)
   int64_t max_degree = 0;
+  int64_t degree_bins[DEG_BINS] = {};  // rows per power-of-two degree bin (k_check_csr)
   uint32_t validated = 0;
   uint32_t reordered = 0;
   int32_t* owned_rp = nullptr;    // device memory owned by the handle (CQ_GRAPH_REORDER)
@@ -1654,11 +1655,11 @@ cq_status graph_load(cq_context* ctx, int32_t n, int64_t nnz, const int32_t* d_r
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return fail(ctx, CQ_E_DEVICE, "reading row_ptr: %s", hipGetErrorString(e));
   if (ends[0] != 0 || (int64_t)ends[1] != nnz) return fail(ctx, CQ_E_GRAPH_FORMAT, "row_ptr[0] != 0 or row_ptr[n] != nnz");
-  fill(ctx->dscratch, 2, 0, s);
+  fill(ctx->dscratch, 2 + DEG_BINS, 0, s);
   k_check_csr<<<grid_for(std::max<int64_t>(n, nnz), 256, 4096), 256, 0, s>>>(n, nnz, d_row_ptr, d_col_idx, ctx->dscratch,
-                                                                            ctx->dscratch + 1);
-  u32 res[2] = {0, 0};
-  e = hipMemcpyAsync(res, ctx->dscratch, 8, hipMemcpyDeviceToHost, s);
+                                                                            ctx->dscratch + 1, ctx->dscratch + 2);
+  u32 res[2 + DEG_BINS] = {};
+  e = hipMemcpyAsync(res, ctx->dscratch, sizeof(res), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return fail(ctx, CQ_E_DEVICE, "graph check: %s", hipGetErrorString(e));
   if (res[0]) return fail(ctx, CQ_E_GRAPH_FORMAT, "row_ptr not monotone or col_idx out of range");
@@ -1710,6 +1711,7 @@ cq_status graph_load(cq_context* ctx, int32_t n, int64_t nnz, const int32_t* d_r
   g->rp = d_row_ptr;
   g->col = d_col_idx;
   g->max_degree = res[1];
+  for (int b = 0; b < DEG_BINS; ++b) g->degree_bins[b] = res[2 + b];
   g->validated = validated;
   g->w = d_weights;
   g->total_w = total_w;
@@ -1757,6 +1759,7 @@ cq_status cq_graph_get_stats(const cq_graph* g, cq_graph_stats* out) {
   out->nnz = g->nnz;
   out->m = g->nnz / 2;
   out->max_degree = g->max_degree;
+  for (int b = 0; b < DEG_BINS; ++b) out->degree_bins[b] = g->degree_bins[b];
   out->validated = g->validated;
   out->reordered = g->reordered;
   out->weighted = g->w ? 1u : 0u;

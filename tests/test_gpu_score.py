@@ -337,3 +337,21 @@ def test_full_size_l10m(cq, ctx):
         r, _, _ = cq.score_partition(g, lab2_t, 40009)
         check_score(r, o2.result, f"l10m 40009 ids reorder={reorder}")
         g.close()
+
+
+def test_graph_stats_degree_bins(cq, ctx):
+    """cq_graph_get_stats: n, 2|E|, maximum degree and the power-of-two degree histogram
+    (bin 0: isolated nodes; bin b: degrees in [2^(b-1), 2^b))."""
+    g = lfr_graph(CONFIGS["m100k_mu0.3"], 17)
+    rp = g.row_ptr.numpy().astype(np.int64)
+    deg = np.diff(rp)
+    rp2 = np.concatenate([rp, [rp[-1], rp[-1]]])  # two isolated nodes at the end
+    G = cq.Graph(ctx, torch.as_tensor(rp2.astype(np.int32)).cuda(), g.col_idx.cuda())
+    st = G.stats
+    deg2 = np.concatenate([deg, [0, 0]])
+    want = np.zeros(32, np.int64)
+    for d in deg2:
+        want[0 if d == 0 else int(d).bit_length()] += 1
+    assert st["n"] == len(deg2) and st["nnz"] == int(rp[-1]) and st["max_degree"] == int(deg.max())
+    assert st["degree_bins"] == want.tolist()
+    G.close()
