@@ -20,6 +20,7 @@
 
 #include "cq.h"
 #include "cq_kernels.hpp"
+#include "srv_core.hpp"
 
 using namespace cq;
 
@@ -1232,25 +1233,11 @@ void tune_store(const std::string& key, int rsel, int occ, double ms) {
 
 
 // ---- serving -------------------------------------------------------------------
-
-using SrvClock = std::chrono::steady_clock;
-
-struct SrvReq {
-  uint64_t id = 0;
-  int kind = 0;  // 0 score, 1 compare
-  const cq_graph* g = nullptr;
-  int32_t n = 0, L = 0, La = 0, Lb = 0;
-  const int32_t* ha = nullptr;
-  const int32_t* hb = nullptr;
-  size_t ws_bytes = 0, foot = 0;
-  bool small = false;
-  SrvClock::time_point t_submit, t_done;
-  cq_status status = CQ_OK;
-  cq_score_result sres{};
-  cq_compare_result cres{};
-  bool done = false;
-  bool waited = false;  // a thread is waiting for it (one waiter per ticket)
-};
+// The scheduler (request table, arena admission in arrival order, grouping of small
+// scoring requests, waiting, shutdown) is host code in srv_core.hpp.  This executor runs
+// what it admits on the device: one HIP stream per slot, the labels copied up from the
+// caller's host memory, the scoring, comparison or batched kernels enqueued, the results
+// copied back into pinned memory, and an event that tells when the slot is done.
 
 struct SrvSlot {
   cq_context* ctx = nullptr;  // context bound to this slot's stream
@@ -1260,14 +1247,9 @@ struct SrvSlot {
   size_t res_bytes = 0;
   void* d_tab = nullptr;
   cq_batch_plan plan;         // reused host plan for grouped launches (no HIP graph)
-  bool busy = false;
-  bool grouped = false;
-  std::vector<SrvReq*> reqs;
-  size_t off = 0, len = 0;
 };
 
-constexpr size_t kAlign = 256;
-size_t aup(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
+using cqsrv::aup;
 
 cq_status status_of_flags(u32 f) {
   if (f & F_LABEL) return CQ_E_LABEL_RANGE;
@@ -1276,241 +1258,100 @@ cq_status status_of_flags(u32 f) {
   return CQ_OK;
 }
 
+class HipExecutor final : public cqsrv::Executor {
+ public:
+  int device = 0;
+  char* arena = nullptr;  // device memory of memory_budget bytes
+  std::vector<SrvSlot*> slots;
+
+  void worker_init() override { (void)hipSetDevice(device); }
+
+  // Labels at the start of the region, then the workspace, then the result.  A group of
+  // small scoring requests runs as one batched launch: every request's labels, the
+  // batch workspace, the results.
+  void dispatch(int slot, const std::vector<cqsrv::Req*>& reqs, bool grouped, size_t off, size_t) override {
+    SrvSlot* sl = slots[slot];
+    hipStream_t st = sl->stream;
+    char* region = arena + off;
+    if (!grouped) {
+      cqsrv::Req* r = reqs[0];
+      if (r->kind == 0) {
+        int32_t* d_lab = reinterpret_cast<int32_t*>(region);
+        char* d_ws = region + aup(4 * (size_t)r->n);
+        ScoreResultDev* d_res = reinterpret_cast<ScoreResultDev*>(d_ws + aup(r->ws_bytes));
+        (void)hipMemcpyAsync(d_lab, r->ha, 4 * (size_t)r->n, hipMemcpyHostToDevice, st);
+        r->status = score_enqueue(sl->ctx, static_cast<const cq_graph*>(r->graph), d_lab, r->L, d_ws, r->ws_bytes, d_res,
+                                  nullptr, nullptr, false);
+        (void)hipMemcpyAsync(sl->pinned, d_res, sizeof(cq_score_result), hipMemcpyDeviceToHost, st);
+      } else {
+        int32_t* d_a = reinterpret_cast<int32_t*>(region);
+        int32_t* d_b = reinterpret_cast<int32_t*>(region + aup(4 * (size_t)r->n));
+        char* d_ws = region + 2 * aup(4 * (size_t)r->n);
+        CmpResultDev* d_res = reinterpret_cast<CmpResultDev*>(d_ws + aup(r->ws_bytes));
+        (void)hipMemcpyAsync(d_a, r->ha, 4 * (size_t)r->n, hipMemcpyHostToDevice, st);
+        (void)hipMemcpyAsync(d_b, r->hb, 4 * (size_t)r->n, hipMemcpyHostToDevice, st);
+        r->status = compare_enqueue(sl->ctx, r->n, d_a, r->La, d_b, r->Lb, d_ws, r->ws_bytes, d_res, nullptr, false);
+        (void)hipMemcpyAsync(sl->pinned, d_res, sizeof(cq_compare_result), hipMemcpyDeviceToHost, st);
+      }
+    } else {
+      cq_batch_plan* p = &sl->plan;
+      p->tasks.clear();
+      size_t o = 0;
+      for (cqsrv::Req* r : reqs) {
+        int32_t* d_lab = reinterpret_cast<int32_t*>(region + o);
+        (void)hipMemcpyAsync(d_lab, r->ha, 4 * (size_t)r->n, hipMemcpyHostToDevice, st);
+        p->tasks.push_back({static_cast<const cq_graph*>(r->graph), d_lab, r->L});
+        o += aup(4 * (size_t)r->n);
+      }
+      batch_layout(p);
+      char* d_ws = region + o;
+      cq_score_result* d_res = reinterpret_cast<cq_score_result*>(d_ws + aup(p->ws_total));
+      const BatchTabLayout tl = batch_tab_layout((int)p->tasks.size(), (int)p->groups.size());
+      char* blob = sl->pinned + sl->res_bytes;
+      batch_fill_tables(p, d_ws, d_res, blob, sl->d_tab);
+      (void)hipMemcpyAsync(sl->d_tab, blob, tl.total, hipMemcpyHostToDevice, st);
+      batch_launch(p, st, 1, batch_max_occ(p));
+      (void)hipMemcpyAsync(sl->pinned, d_res, sizeof(cq_score_result) * p->tasks.size(), hipMemcpyDeviceToHost, st);
+    }
+    (void)hipEventRecord(sl->ev, st);
+  }
+
+  bool finished(int slot) override { return hipEventQuery(slots[slot]->ev) == hipSuccess; }
+
+  void collect(int slot, const std::vector<cqsrv::Req*>& reqs, bool) override {
+    const SrvSlot* sl = slots[slot];
+    for (size_t i = 0; i < reqs.size(); ++i) {
+      cqsrv::Req* r = reqs[i];
+      if (r->status != CQ_OK) continue;  // never started
+      if (r->kind == 0) {
+        std::memcpy(&r->sres, sl->pinned + i * sizeof(cq_score_result), sizeof(cq_score_result));
+        r->status = status_of_flags(r->sres.device_flags);
+      } else {
+        std::memcpy(&r->cres, sl->pinned, sizeof(cq_compare_result));
+        r->status = status_of_flags(r->cres.device_flags);
+      }
+    }
+  }
+};
+
 }  // namespace
 
 struct cq_server {
   cq_context* ctx = nullptr;
   cq_server_config cfg{};
-  char* arena = nullptr;
-  std::map<size_t, size_t> free_blocks;  // offset -> length
-  size_t in_use = 0, peak = 0;
-  std::vector<SrvSlot*> slots;
-  std::mutex mu;
-  std::condition_variable cv_work, cv_done;
-  std::deque<SrvReq*> pending;
-  std::map<uint64_t, SrvReq*> reqs;
-  uint64_t next_id = 1;
-  bool stop = false;
-  std::thread worker;
-  std::vector<double> lat_ms;
-  int64_t submitted = 0, completed = 0, failed = 0, launches = 0, grouped = 0, rejected = 0;
-  int inflight = 0;
-  int waiters = 0;  // threads inside cq_server_wait (destroy waits for them to leave)
-  double busy_s = 0;
-  SrvClock::time_point busy_since;
+  HipExecutor exec;
+  cqsrv::Scheduler* sched = nullptr;
 };
 
-namespace {
-
-bool arena_alloc(cq_server* s, size_t len, size_t* off) {
-  len = aup(len);
-  for (auto it = s->free_blocks.begin(); it != s->free_blocks.end(); ++it) {
-    if (it->second >= len) {
-      *off = it->first;
-      const size_t rest = it->second - len, noff = it->first + len;
-      s->free_blocks.erase(it);
-      if (rest) s->free_blocks[noff] = rest;
-      s->in_use += len;
-      s->peak = std::max(s->peak, s->in_use);
-      return true;
-    }
-  }
-  return false;
-}
-
-void arena_free(cq_server* s, size_t off, size_t len) {
-  len = aup(len);
-  s->in_use -= len;
-  auto it = s->free_blocks.emplace(off, len).first;
-  auto nx = std::next(it);
-  if (nx != s->free_blocks.end() && it->first + it->second == nx->first) {
-    it->second += nx->second;
-    s->free_blocks.erase(nx);
-  }
-  if (it != s->free_blocks.begin()) {
-    auto pv = std::prev(it);
-    if (pv->first + pv->second == it->first) {
-      pv->second += it->second;
-      s->free_blocks.erase(it);
-    }
-  }
-}
-
-size_t req_footprint(const SrvReq* r) {
-  if (r->kind == 0) return aup(4 * (size_t)r->n) + aup(r->ws_bytes) + aup(sizeof(cq_score_result));
-  return 2 * aup(4 * (size_t)r->n) + aup(r->ws_bytes) + aup(sizeof(cq_compare_result));
-}
-
-// Enqueue one admitted request (or a group of small scoring requests) on a slot.
-void srv_dispatch(cq_server* s, SrvSlot* sl) {
-  hipStream_t st = sl->stream;
-  char* region = s->arena + sl->off;
-  if (!sl->grouped) {
-    SrvReq* r = sl->reqs[0];
-    if (r->kind == 0) {
-      int32_t* d_lab = reinterpret_cast<int32_t*>(region);
-      char* d_ws = region + aup(4 * (size_t)r->n);
-      ScoreResultDev* d_res = reinterpret_cast<ScoreResultDev*>(d_ws + aup(r->ws_bytes));
-      (void)hipMemcpyAsync(d_lab, r->ha, 4 * (size_t)r->n, hipMemcpyHostToDevice, st);
-      r->status = score_enqueue(sl->ctx, r->g, d_lab, r->L, d_ws, r->ws_bytes, d_res, nullptr, nullptr, false);
-      (void)hipMemcpyAsync(sl->pinned, d_res, sizeof(cq_score_result), hipMemcpyDeviceToHost, st);
-    } else {
-      int32_t* d_a = reinterpret_cast<int32_t*>(region);
-      int32_t* d_b = reinterpret_cast<int32_t*>(region + aup(4 * (size_t)r->n));
-      char* d_ws = region + 2 * aup(4 * (size_t)r->n);
-      CmpResultDev* d_res = reinterpret_cast<CmpResultDev*>(d_ws + aup(r->ws_bytes));
-      (void)hipMemcpyAsync(d_a, r->ha, 4 * (size_t)r->n, hipMemcpyHostToDevice, st);
-      (void)hipMemcpyAsync(d_b, r->hb, 4 * (size_t)r->n, hipMemcpyHostToDevice, st);
-      r->status = compare_enqueue(sl->ctx, r->n, d_a, r->La, d_b, r->Lb, d_ws, r->ws_bytes, d_res, nullptr, false);
-      (void)hipMemcpyAsync(sl->pinned, d_res, sizeof(cq_compare_result), hipMemcpyDeviceToHost, st);
-    }
-  } else {
-    // labels of every request, then the batch workspace, then the results
-    cq_batch_plan* p = &sl->plan;
-    p->tasks.clear();
-    size_t o = 0;
-    for (SrvReq* r : sl->reqs) {
-      int32_t* d_lab = reinterpret_cast<int32_t*>(region + o);
-      (void)hipMemcpyAsync(d_lab, r->ha, 4 * (size_t)r->n, hipMemcpyHostToDevice, st);
-      p->tasks.push_back({r->g, d_lab, r->L});
-      o += aup(4 * (size_t)r->n);
-    }
-    batch_layout(p);
-    char* d_ws = region + o;
-    cq_score_result* d_res = reinterpret_cast<cq_score_result*>(d_ws + aup(p->ws_total));
-    const BatchTabLayout tl = batch_tab_layout((int)p->tasks.size(), (int)p->groups.size());
-    char* blob = sl->pinned + sl->res_bytes;
-    batch_fill_tables(p, d_ws, d_res, blob, sl->d_tab);
-    (void)hipMemcpyAsync(sl->d_tab, blob, tl.total, hipMemcpyHostToDevice, st);
-    batch_launch(p, st, 1, batch_max_occ(p));
-    (void)hipMemcpyAsync(sl->pinned, d_res, sizeof(cq_score_result) * p->tasks.size(), hipMemcpyDeviceToHost, st);
-  }
-  (void)hipEventRecord(sl->ev, st);
-}
-
-// Footprint of a group of small scoring requests run as one batched launch.
-size_t group_footprint(const std::vector<SrvReq*>& g) {
-  size_t lab = 0, ws = 0, items = 0;
-  for (const SrvReq* r : g) {
-    lab += aup(4 * (size_t)r->n);
-    ws += aup(score_layout(r->g->n, r->g->nnz, r->L).total);
-    items += 4 * (size_t)r->L;  // the group pass's item list (batch_layout)
-  }
-  return lab + aup(ws + aup(items)) + aup(sizeof(cq_score_result) * g.size());
-}
-
-void srv_loop(cq_server* s) {
-  (void)hipSetDevice(s->ctx->device);
-  for (;;) {
-    bool progress = false;
-    // completions
-    for (SrvSlot* sl : s->slots) {
-      if (!sl->busy || hipEventQuery(sl->ev) != hipSuccess) continue;
-      const auto now = SrvClock::now();
-      std::lock_guard<std::mutex> lk(s->mu);
-      for (size_t i = 0; i < sl->reqs.size(); ++i) {
-        SrvReq* r = sl->reqs[i];
-        if (r->status == CQ_OK) {
-          if (r->kind == 0) {
-            std::memcpy(&r->sres, sl->pinned + i * sizeof(cq_score_result), sizeof(cq_score_result));
-            r->status = status_of_flags(r->sres.device_flags);
-          } else {
-            std::memcpy(&r->cres, sl->pinned, sizeof(cq_compare_result));
-            r->status = status_of_flags(r->cres.device_flags);
-          }
-        }
-        r->t_done = now;
-        r->done = true;
-        s->lat_ms.push_back(std::chrono::duration<double, std::milli>(now - r->t_submit).count());
-        if (r->status == CQ_OK) ++s->completed; else ++s->failed;
-      }
-      arena_free(s, sl->off, sl->len);
-      sl->busy = false;
-      sl->reqs.clear();
-      if (--s->inflight == 0) s->busy_s += std::chrono::duration<double>(now - s->busy_since).count();
-      progress = true;
-      s->cv_done.notify_all();
-    }
-    // admissions: fill free slots in arrival order
-    std::unique_lock<std::mutex> lk(s->mu);
-    for (;;) {
-      if (s->pending.empty()) break;
-      SrvSlot* sl = nullptr;
-      for (SrvSlot* c : s->slots)
-        if (!c->busy) { sl = c; break; }
-      if (!sl) break;
-      SrvReq* head = s->pending.front();
-      std::vector<SrvReq*> take = {head};
-      size_t off = 0, len = 0;
-      bool grouped = false;
-      if (head->small && s->cfg.max_batch > 1) {
-        for (size_t i = 1; i < s->pending.size() && (int)take.size() < s->cfg.max_batch; ++i)
-          if (s->pending[i]->small) take.push_back(s->pending[i]);
-        while (take.size() > 1) {
-          len = group_footprint(take);
-          if (arena_alloc(s, len, &off)) break;
-          take.pop_back();
-        }
-        grouped = take.size() > 1;
-      }
-      if (!grouped) {
-        len = req_footprint(head);
-        if (!arena_alloc(s, len, &off)) break;  // wait for memory (arrival order is kept)
-      }
-      for (SrvReq* r : take) s->pending.erase(std::find(s->pending.begin(), s->pending.end(), r));
-      sl->reqs = take;
-      sl->grouped = grouped;
-      sl->off = off;
-      sl->len = len;
-      sl->busy = true;
-      if (s->inflight++ == 0) s->busy_since = SrvClock::now();
-      ++s->launches;
-      if (grouped) s->grouped += (int64_t)take.size();
-      lk.unlock();
-      srv_dispatch(s, sl);
-      lk.lock();
-      progress = true;
-    }
-    if (s->stop && s->pending.empty() && s->inflight == 0) break;
-    if (!progress) {
-      if (s->inflight > 0) {
-        lk.unlock();
-        std::this_thread::yield();
-      } else {
-        s->cv_work.wait_for(lk, std::chrono::microseconds(200));
-      }
-    }
-  }
-}
-
-cq_status srv_submit(cq_server* s, SrvReq* r, uint64_t* ticket) {
-  r->foot = req_footprint(r);
-  if (r->foot > (size_t)s->cfg.memory_budget) {
-    const size_t need = r->foot;
-    delete r;
-    std::lock_guard<std::mutex> lk(s->mu);
-    ++s->rejected;
-    return fail(s->ctx, CQ_E_BUSY, "request needs %zu bytes, the server arena has %lld", need,
-                (long long)s->cfg.memory_budget);
-  }
-  r->t_submit = SrvClock::now();
-  {
-    std::lock_guard<std::mutex> lk(s->mu);
-    if (s->stop) {
-      delete r;
-      return CQ_E_CANCELLED;
-    }
-    r->id = s->next_id++;
-    s->reqs[r->id] = r;
-    s->pending.push_back(r);
-    ++s->submitted;
-    *ticket = r->id;
-  }
-  s->cv_work.notify_one();
+static cq_status srv_submit(cq_server* srv, cqsrv::Req* r, uint64_t* ticket) {
+  const char* why = nullptr;
+  const size_t foot = cqsrv::req_footprint(*r);
+  const cq_status st = srv->sched->submit(r, ticket, &why);
+  if (st == CQ_E_BUSY)
+    return fail(srv->ctx, st, "request needs %zu bytes, the server arena has %lld", foot, (long long)srv->cfg.memory_budget);
+  if (st != CQ_OK) return fail(srv->ctx, st, "%s", why ? why : "request not queued");
   return CQ_OK;
 }
-
-}  // namespace
 
 extern "C" {
 
@@ -2031,17 +1872,17 @@ cq_status cq_server_create(cq_context* ctx, const cq_server_config* cfg, cq_serv
   if (!s) return fail(ctx, CQ_E_DEVICE, "out of host memory");
   s->ctx = ctx;
   s->cfg = *cfg;
-  hipError_t e = hipMalloc((void**)&s->arena, (size_t)cfg->memory_budget);
+  s->exec.device = ctx->device;
+  hipError_t e = hipMalloc((void**)&s->exec.arena, (size_t)cfg->memory_budget);
   if (e != hipSuccess) {
     delete s;
     return fail(ctx, CQ_E_DEVICE, "allocating the server arena: %s", hipGetErrorString(e));
   }
-  s->free_blocks[0] = (size_t)cfg->memory_budget & ~(kAlign - 1);
   const BatchTabLayout tl = batch_tab_layout(cfg->max_batch, cfg->max_batch);
   const size_t res_bytes = aup(std::max(sizeof(cq_compare_result), sizeof(cq_score_result) * (size_t)cfg->max_batch));
   for (int i = 0; i < cfg->num_slots && e == hipSuccess; ++i) {
     SrvSlot* sl = new SrvSlot();
-    s->slots.push_back(sl);
+    s->exec.slots.push_back(sl);
     e = hipStreamCreateWithFlags(&sl->stream, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&sl->ev, hipEventDisableTiming);
     if (e == hipSuccess) e = hipHostMalloc((void**)&sl->pinned, res_bytes + tl.total, hipHostMallocDefault);
@@ -2054,7 +1895,16 @@ cq_status cq_server_create(cq_context* ctx, const cq_server_config* cfg, cq_serv
     cq_server_destroy(s);
     return fail(ctx, CQ_E_DEVICE, "creating server slots: %s", hipGetErrorString(e));
   }
-  s->worker = std::thread(srv_loop, s);
+  cqsrv::Config sc;
+  sc.num_slots = cfg->num_slots;
+  sc.max_batch = cfg->max_batch;
+  sc.arena_bytes = (size_t)cfg->memory_budget;
+  s->sched = new (std::nothrow) cqsrv::Scheduler(sc, &s->exec);
+  if (!s->sched) {
+    cq_server_destroy(s);
+    return fail(ctx, CQ_E_DEVICE, "out of host memory");
+  }
+  s->sched->start();
   *out = s;
   return CQ_OK;
 }
@@ -2064,14 +1914,15 @@ cq_status cq_server_submit_score(cq_server* srv, const cq_graph* g, const int32_
   if (!srv) return CQ_E_INVALID_ARG;
   if (!g || !h_labels || !ticket || num_labels < 1) return fail(srv->ctx, CQ_E_INVALID_ARG, "bad scoring request");
   if (g->nnz == 0) return fail(srv->ctx, CQ_E_NO_EDGES, "graph has no edges");
-  SrvReq* r = new (std::nothrow) SrvReq();
+  cqsrv::Req* r = new (std::nothrow) cqsrv::Req();
   if (!r) return CQ_E_DEVICE;
   r->kind = 0;
-  r->g = g;
+  r->graph = g;
   r->n = g->n;
   r->L = num_labels;
   r->ha = h_labels;
   r->ws_bytes = graph_score_layout(g, num_labels).total;
+  r->group_ws = score_layout(g->n, g->nnz, num_labels).total;
   r->small = num_labels <= BATCH_MAX_L && g->nnz <= srv->cfg.small_nnz && !g->w;  // groups run the unweighted batch kernels
   return srv_submit(srv, r, ticket);
 }
@@ -2081,7 +1932,7 @@ cq_status cq_server_submit_compare(cq_server* srv, int32_t n, const int32_t* h_l
   if (!srv) return CQ_E_INVALID_ARG;
   if (n < 2 || !h_labels_a || !h_labels_b || !ticket || num_labels_a < 1 || num_labels_b < 1)
     return fail(srv->ctx, CQ_E_INVALID_ARG, "bad comparison request");
-  SrvReq* r = new (std::nothrow) SrvReq();
+  cqsrv::Req* r = new (std::nothrow) cqsrv::Req();
   if (!r) return CQ_E_DEVICE;
   r->kind = 1;
   r->n = n;
@@ -2096,87 +1947,36 @@ cq_status cq_server_submit_compare(cq_server* srv, int32_t n, const int32_t* h_l
 cq_status cq_server_wait(cq_server* srv, uint64_t ticket, double timeout_ms, cq_status* request_status,
                          cq_score_result* score_out, cq_compare_result* compare_out, double* latency_ms) {
   if (!srv) return CQ_E_INVALID_ARG;
-  std::unique_lock<std::mutex> lk(srv->mu);
-  auto it = srv->reqs.find(ticket);
-  if (it == srv->reqs.end()) return fail(srv->ctx, CQ_E_INVALID_ARG, "unknown ticket");
-  SrvReq* r = it->second;
-  if (r->waited) return fail(srv->ctx, CQ_E_INVALID_ARG, "another thread is waiting for this ticket");
-  r->waited = true;
-  ++srv->waiters;
-  auto ready = [&] { return r->done; };
-  bool ok = true;
-  if (timeout_ms < 0) srv->cv_done.wait(lk, ready);
-  else ok = srv->cv_done.wait_for(lk, std::chrono::duration<double, std::milli>(timeout_ms), ready);
-  r->waited = false;
-  if (--srv->waiters == 0 && srv->stop) srv->cv_done.notify_all();  // destroy waits for the last waiter
-  if (!ok) return CQ_E_BUSY;
-  if (request_status) *request_status = r->status;
-  if (score_out && r->kind == 0) *score_out = r->sres;
-  if (compare_out && r->kind == 1) *compare_out = r->cres;
-  if (latency_ms) *latency_ms = std::chrono::duration<double, std::milli>(r->t_done - r->t_submit).count();
-  srv->reqs.erase(it);
-  delete r;
+  cqsrv::Outcome o;
+  const char* why = nullptr;
+  const cq_status st = srv->sched->wait(ticket, timeout_ms, &o, &why);
+  if (st == CQ_E_INVALID_ARG) return fail(srv->ctx, st, "%s", why ? why : "bad ticket");
+  if (st != CQ_OK) return st;
+  if (request_status) *request_status = o.status;
+  if (score_out && o.kind == 0) *score_out = o.sres;
+  if (compare_out && o.kind == 1) *compare_out = o.cres;
+  if (latency_ms) *latency_ms = o.latency_ms;
   return CQ_OK;
 }
 
 cq_status cq_server_get_stats(cq_server* srv, cq_server_stats* out) {
   if (!srv || !out) return CQ_E_INVALID_ARG;
-  std::lock_guard<std::mutex> lk(srv->mu);
-  std::memset(out, 0, sizeof(*out));
-  out->submitted = srv->submitted;
-  out->completed = srv->completed;
-  out->failed = srv->failed;
-  out->rejected = srv->rejected;
-  out->launches = srv->launches;
-  out->grouped_requests = srv->grouped;
-  out->busy_s = srv->busy_s;
-  out->peak_bytes = (int64_t)srv->peak;
-  std::vector<double> v = srv->lat_ms;
-  if (!v.empty()) {
-    std::sort(v.begin(), v.end());
-    auto q = [&](double f) { return v[std::min(v.size() - 1, (size_t)(f * (double)(v.size() - 1) + 0.5))]; };
-    out->p50_ms = q(0.50);
-    out->p99_ms = q(0.99);
-    out->max_ms = v.back();
-    double sum = 0;
-    for (double x : v) sum += x;
-    out->mean_ms = sum / (double)v.size();
-  }
+  srv->sched->stats(out);
   return CQ_OK;
 }
 
 cq_status cq_server_reset_stats(cq_server* srv) {
   if (!srv) return CQ_E_INVALID_ARG;
-  std::lock_guard<std::mutex> lk(srv->mu);
-  srv->lat_ms.clear();
-  srv->submitted = srv->completed = srv->failed = srv->launches = srv->grouped = srv->rejected = 0;
-  srv->busy_s = 0;
-  srv->peak = srv->in_use;
-  if (srv->inflight > 0) srv->busy_since = SrvClock::now();
+  srv->sched->reset_stats();
   return CQ_OK;
 }
 
 void cq_server_destroy(cq_server* srv) {
   if (!srv) return;
-  {
-    std::lock_guard<std::mutex> lk(srv->mu);
-    srv->stop = true;
-    for (SrvReq* r : srv->pending) {
-      r->status = CQ_E_CANCELLED;
-      r->done = true;
-    }
-    srv->pending.clear();
-  }
-  srv->cv_work.notify_all();
-  if (srv->worker.joinable()) srv->worker.join();
-  {
-    // every request is now finished or cancelled: wake the waiting threads and let them
-    // leave cq_server_wait before the server's memory goes
-    std::unique_lock<std::mutex> lk(srv->mu);
-    srv->cv_done.notify_all();
-    srv->cv_done.wait(lk, [&] { return srv->waiters == 0; });
-  }
-  for (SrvSlot* sl : srv->slots) {
+  // cancels what is queued, lets the admitted work finish, and returns once no thread
+  // is left inside cq_server_wait
+  if (srv->sched) srv->sched->shutdown();
+  for (SrvSlot* sl : srv->exec.slots) {
     if (sl->stream) (void)hipStreamSynchronize(sl->stream);
     if (sl->ctx) cq_context_destroy(sl->ctx);
     if (sl->ev) (void)hipEventDestroy(sl->ev);
@@ -2186,8 +1986,9 @@ void cq_server_destroy(cq_server* srv) {
     sl->plan.stream = nullptr;  // the plan object owns nothing here
     delete sl;
   }
-  for (auto& kv : srv->reqs) delete kv.second;
-  if (srv->arena) (void)hipFree(srv->arena);
+  srv->exec.slots.clear();
+  delete srv->sched;
+  if (srv->exec.arena) (void)hipFree(srv->exec.arena);
   delete srv;
 }
 
