@@ -2957,7 +2957,7 @@ __global__ __launch_bounds__(FBLOCK) void k_cmp_final1(int La, int Lb, int Ga, c
       const u32 bj = B[j];
       if (bj == 0) continue;
       Kb += 1;
-      smax += COLMAX[j];
+      smax += max(COLMAX[j], 1u);  // a non-empty column's largest cell holds at least one node
       Y += (u64)bj * (u64)(bj - 1u) / 2u;
       sb += fix96((double)bj / Nd * log((double)bj));
     }

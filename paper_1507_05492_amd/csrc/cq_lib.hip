@@ -20,6 +20,7 @@
 
 #include "cq.h"
 #include "cq_kernels.hpp"
+#include "cq_compare.hpp"
 #include "srv_core.hpp"
 
 using namespace cq;
@@ -301,9 +302,21 @@ ScoreLayout graph_score_layout(const cq_graph* g, int64_t L) {
 
 struct CmpLayout {
   bool privA, privB, small;  // small: detected labels fit 16 bits
+  bool bands;                // both label spaces fit 16 bits: the band path (cq_compare.hpp)
   int chunk, W, Wb, Ga, Gb;
+  int Wa, rounds, Wc, nbmax;  // band path: histogram grid of A, rounds per chunk, chunks, bands at most
+  u32 T;                      // band path: nodes per band aimed at
   size_t ctl, wq, A, B, start, order, COLMAX, RA11, RMAX, RF, RXL, SZ, loc, HN, HB, CB, parts, res, total;
+  size_t HA, sbk, SBA, SZB, SBS, CUR, BORD, E;
 };
+
+// Band path sizes: bands of about T nodes, at least 8,192 (a band's cells then mostly fit
+// the cell table in one class) and at most about 1,024 bands by size (every chunk claims
+// one run per band it has nodes of); chunks of whole rounds of CP_CHUNK nodes, at most
+// about 512 chunks.
+constexpr int64_t CB_MIN_T = 8192;
+constexpr int64_t CB_MAX_BANDS_BY_SIZE = 1024;
+constexpr int64_t CP_MAX_CHUNKS = 512;
 
 CmpLayout cmp_layout(int64_t n, int64_t La, int64_t Lb) {
   CmpLayout s{};
@@ -311,11 +324,41 @@ CmpLayout cmp_layout(int64_t n, int64_t La, int64_t Lb) {
   s.privA = La <= RANGE_MAX;
   s.privB = Lb <= RANGE_MAX;
   s.small = Lb <= 65535;
-  s.chunk = pick_chunk(n, La > PRIV_MAX ? RANGE_CHUNK_MAX : 65536);
-  s.W = (int)((n + s.chunk - 1) / s.chunk);
+  s.bands = La <= 65535 && Lb <= 65535;
   s.Wb = (int)std::min<int64_t>(256, std::max<int64_t>(1, (n + 8191) / 8192));
   s.Ga = (int)std::min<int64_t>(64, std::max<int64_t>(1, (La + 1023) / 1024));
   s.Gb = (int)std::min<int64_t>(64, std::max<int64_t>(1, (Lb + 1023) / 1024));
+  if (s.bands) {
+    s.Wa = s.Wb;
+    s.T = (u32)std::max<int64_t>(CB_MIN_T, (n + CB_MAX_BANDS_BY_SIZE - 1) / CB_MAX_BANDS_BY_SIZE);
+    s.nbmax = (int)(n / s.T + (La + CB_ROWS - 1) / CB_ROWS + 2);
+    s.rounds = (int)std::max<int64_t>(1, (n + CP_CHUNK * CP_MAX_CHUNKS - 1) / (CP_CHUNK * CP_MAX_CHUNKS));
+    s.Wc = (int)((n + (int64_t)CP_CHUNK * s.rounds - 1) / ((int64_t)CP_CHUNK * s.rounds));
+    s.ctl = c.take(sizeof(Ctl));
+    s.wq = c.take(WQ_BYTES);
+    s.A = c.take(4 * La);
+    s.B = c.take(4 * Lb);
+    s.COLMAX = c.take(4 * Lb);
+    s.RA11 = c.take(8 * La);
+    s.RMAX = c.take(4 * La);
+    s.RF = c.take(8 * La);
+    s.RXL = c.take(16 * La);
+    s.HA = c.take(4 * (size_t)s.Wa * La);
+    s.HB = c.take(4 * (size_t)s.Wb * Lb);
+    s.sbk = c.take(4 * La);
+    s.SBA = c.take(4 * ((size_t)s.nbmax + 1));
+    s.SZB = c.take(4 * (size_t)s.nbmax);
+    s.SBS = c.take(4 * ((size_t)s.nbmax + 1));
+    s.CUR = c.take(4 * (size_t)s.nbmax);
+    s.BORD = c.take(4 * (size_t)s.nbmax);
+    s.E = c.take(4 * (size_t)n);
+    s.parts = c.take(sizeof(CmpPart) * (s.Ga + s.Gb));
+    s.res = c.take(sizeof(CmpResultDev));
+    s.total = c.off;
+    return s;
+  }
+  s.chunk = pick_chunk(n, La > PRIV_MAX ? RANGE_CHUNK_MAX : 65536);
+  s.W = (int)((n + s.chunk - 1) / s.chunk);
   s.ctl = c.take(sizeof(Ctl));
   s.wq = c.take(WQ_BYTES);
   s.A = c.take(4 * La);
@@ -744,6 +787,80 @@ void compare_launch(cq_context* ctx, int32_t n, const int32_t* la, int32_t La, c
   }
 }
 
+// Per-label histogram of labels[0, n) (ranges of PRIV_MAX labels per launch) into totals N.
+void label_totals(int n, const int32_t* labels, int L, int W, u32* H, u32* N, Ctl* ctl, hipStream_t s) {
+  for (int64_t l0 = 0; l0 < L; l0 += PRIV_MAX) {
+    const int lr = (int)std::min<int64_t>(PRIV_MAX, L - l0);
+    k_hist_priv<<<W, 1024, (size_t)lr * 4, s>>>(n, labels, L, H, ctl, (int)l0, lr);
+  }
+  k_colscan<false, false><<<colscan_grid(L), CS_LABELS * CS_GROUPS, 0, s>>>(W, L, H, H, N, nullptr);
+}
+
+unsigned cells_grid(cq_context* ctx) {
+  static int nb = 0;
+  if (nb == 0 && (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_cmp_cells, CC_THREADS, 0) != hipSuccess || nb < 1))
+    nb = 1;
+  return (unsigned)(ctx->num_cus * nb);
+}
+
+// Both label spaces fit 16 bits: contingency cells counted per band of ground-truth labels.
+void compare_launch_bands(cq_context* ctx, int32_t n, const int32_t* la, int32_t La, const int32_t* lb, int32_t Lb, void* ws,
+                          const CmpLayout& lay, CmpResultDev* d_out, const cq_cell_table* cells, bool timed) {
+  hipStream_t s = ctx->stream;
+  Ctl* ctl = at<Ctl>(ws, lay.ctl);
+  u32* A = at<u32>(ws, lay.A);
+  u32* B = at<u32>(ws, lay.B);
+  u32* COLMAX = at<u32>(ws, lay.COLMAX);
+  u32* wq = at<u32>(ws, lay.wq);
+  u32* sbk = at<u32>(ws, lay.sbk);
+  u32* SBA = at<u32>(ws, lay.SBA);
+  u32* SZB = at<u32>(ws, lay.SZB);
+  u32* SBS = at<u32>(ws, lay.SBS);
+  u32* CUR = at<u32>(ws, lay.CUR);
+  u32* BORD = at<u32>(ws, lay.BORD);
+  u32* E = at<u32>(ws, lay.E);
+  u64* RA11 = at<u64>(ws, lay.RA11);
+  u32* RMAX = at<u32>(ws, lay.RMAX);
+  double* RF = at<double>(ws, lay.RF);
+  u64* RXL = at<u64>(ws, lay.RXL);
+  {
+    StageMark mk(ctx, ST_SETUP, timed);
+    fill(reinterpret_cast<u32*>(ctl), sizeof(Ctl) / 4, 0, s);
+    fill(wq, WQ_WORDS, 0, s);
+    fill(COLMAX, (size_t)Lb, 0, s);
+  }
+  {
+    StageMark mk(ctx, ST_NODE, timed);
+    label_totals(n, la, La, lay.Wa, at<u32>(ws, lay.HA), A, ctl, s);
+  }
+  {
+    StageMark mk(ctx, ST_HIST_B, timed);
+    label_totals(n, lb, Lb, lay.Wb, at<u32>(ws, lay.HB), B, ctl, s);
+  }
+  {
+    StageMark mk(ctx, ST_ORDER, timed);
+    k_cmp_bands<<<1, 1024, 0, s>>>(La, A, lay.T, sbk, SBA, SBS, SZB, CUR, BORD, ctl);
+  }
+  {
+    StageMark mk(ctx, ST_SCATTER, timed);
+    (void)hipFuncSetAttribute((const void*)k_cmp_part, hipFuncAttributeMaxDynamicSharedMemorySize, lay.nbmax * 8);
+    k_cmp_part<<<lay.Wc, CP_THREADS, (size_t)lay.nbmax * 8, s>>>(n, la, lb, La, Lb, sbk, lay.nbmax, lay.rounds, CUR, E);
+  }
+  const long long ecap = cells ? cells->capacity : 0;
+  {
+    StageMark mk(ctx, ST_GROUPS, timed);
+    k_cmp_cells<<<cells_grid(ctx), CC_THREADS, 0, s>>>(E, SBS, SZB, SBA, BORD, ctl, A, B, (double)n, COLMAX, RA11, RMAX, RF,
+                                                       RXL, cells ? cells->ci : nullptr, cells ? cells->cj : nullptr,
+                                                       cells ? cells->count : nullptr, ecap, wq);
+  }
+  CmpPart* parts = at<CmpPart>(ws, lay.parts);
+  {
+    StageMark mk(ctx, ST_FINAL, timed);
+    k_cmp_final1<<<lay.Ga + lay.Gb, FBLOCK, 0, s>>>(La, Lb, lay.Ga, A, B, COLMAX, RA11, RMAX, RF, RXL, (double)n, parts);
+    k_cmp_final2<<<1, 64, 0, s>>>(lay.Ga + lay.Gb, parts, n, ecap, ctl, d_out, wq);
+  }
+}
+
 cq_status compare_enqueue(cq_context* ctx, int32_t n, const int32_t* la, int32_t La, const int32_t* lb, int32_t Lb, void* ws,
                           size_t ws_bytes, CmpResultDev* d_out, const cq_cell_table* cells, bool timed) {
   if (!ctx) return CQ_E_INVALID_ARG;
@@ -757,7 +874,9 @@ cq_status compare_enqueue(cq_context* ctx, int32_t n, const int32_t* la, int32_t
   if (!ws || ws_bytes < lay.total)
     return fail(ctx, CQ_E_WORKSPACE, "workspace %zu bytes, need %zu", ws_bytes, lay.total);
   if (reinterpret_cast<uintptr_t>(ws) % WS_ALIGN) return fail(ctx, CQ_E_INVALID_ARG, "workspace not 16-byte aligned");
-  if (lay.small)
+  if (lay.bands)
+    compare_launch_bands(ctx, n, la, La, lb, Lb, ws, lay, d_out, cells, timed);
+  else if (lay.small)
     compare_launch<uint16_t>(ctx, n, la, La, lb, Lb, ws, lay, d_out, cells, timed);
   else
     compare_launch<uint32_t>(ctx, n, la, La, lb, Lb, ws, lay, d_out, cells, timed);

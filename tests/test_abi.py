@@ -48,8 +48,8 @@ def test_compare_workspace_size(cq):
     s3 = cq.cq_compare_workspace_size(100_000, 100_000, 399)   # global-atomic layout
     assert 0 < s1 < s2 and s3 > s1
     assert s1 % 256 == 0
-    # at least the staged label array and per-node offsets
-    assert s1 >= 8 * 100_000
+    # at least one 32-bit word per node (the band words, or the staged labels and per-node offsets)
+    assert s1 >= 4 * 100_000
 
 
 def test_null_handles(cq):
