@@ -42,6 +42,81 @@ __device__ __forceinline__ u32 lds_flag(u32* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
+// Label histograms of both partitions in one pass, when both label spaces fit one LDS
+// table together: row blockIdx.x of HA (La counters) and HB (Lb counters).  Labels out
+// of range are flagged (F_LABEL) and not counted.
+constexpr int H2_NPT = 16;  // labels of each side per thread and round
+__global__ __launch_bounds__(1024) void k_hist2_priv(int n, const int32_t* __restrict__ la, int La,
+                                                     const int32_t* __restrict__ lb, int Lb, u32* __restrict__ HA,
+                                                     u32* __restrict__ HB, Ctl* __restrict__ ctl) {
+  extern __shared__ u32 s_h2[];
+  u32* sa = s_h2;
+  u32* sb = s_h2 + La;
+  __shared__ u32 s_bad;
+  for (int i = threadIdx.x; i < La + Lb; i += 1024) s_h2[i] = 0;
+  if (threadIdx.x == 0) s_bad = 0;
+  __syncthreads();
+  u32 bad = 0;
+  for (long long base = (long long)blockIdx.x * 1024 * H2_NPT; base < n; base += (long long)gridDim.x * 1024 * H2_NPT) {
+    int a[H2_NPT], b[H2_NPT];
+#pragma unroll
+    for (int k = 0; k < H2_NPT; ++k) {
+      const long long u = base + threadIdx.x + (long long)k * 1024;
+      a[k] = u < n ? la[u] : -1;
+      b[k] = u < n ? lb[u] : -1;
+      if (u < n) bad |= ((u32)a[k] >= (u32)La) | ((u32)b[k] >= (u32)Lb);
+    }
+#pragma unroll
+    for (int k = 0; k < H2_NPT; ++k) {
+      if ((u32)a[k] < (u32)La) atomicAdd(&sa[a[k]], 1u);
+      if ((u32)b[k] < (u32)Lb) atomicAdd(&sb[b[k]], 1u);
+    }
+  }
+  if (bad) s_bad = 1;
+  __syncthreads();
+  for (int c = threadIdx.x; c < La; c += 1024) HA[(size_t)blockIdx.x * La + c] = sa[c];
+  for (int c = threadIdx.x; c < Lb; c += 1024) HB[(size_t)blockIdx.x * Lb + c] = sb[c];
+  if (threadIdx.x == 0 && s_bad) atomicOr(&ctl->flags, F_LABEL);
+}
+
+// Clears the control block, the work queues and the column maxima in one launch.
+__global__ __launch_bounds__(256) void k_cmp_clear(u32* __restrict__ ctl_words, int nctl, u32* __restrict__ wq,
+                                                   u32* __restrict__ COLMAX, int Lb) {
+  const int stride = gridDim.x * blockDim.x;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nctl + (int)WQ_WORDS + Lb; i += stride) {
+    if (i < nctl) ctl_words[i] = 0;
+    else if (i < nctl + (int)WQ_WORDS) wq[i - nctl] = 0;
+    else COLMAX[i - nctl - (int)WQ_WORDS] = 0;
+  }
+}
+
+// Label totals of both partitions from the per-workgroup rows of k_hist2_priv in one
+// launch: blocks [0, ga) take the ground-truth labels, the others the detected ones.
+__global__ __launch_bounds__(CS_LABELS * CS_GROUPS) void k_cmp_totals(int W, int La, int Lb, int ga,
+                                                                      const u32* __restrict__ HA,
+                                                                      const u32* __restrict__ HB, u32* __restrict__ A,
+                                                                      u32* __restrict__ B) {
+  __shared__ u32 s_n[CS_GROUPS][CS_LABELS];
+  const bool side_a = (int)blockIdx.x < ga;
+  const int L = side_a ? La : Lb;
+  const u32* H = side_a ? HA : HB;
+  u32* N = side_a ? A : B;
+  const int lane = threadIdx.x % CS_LABELS, grp = threadIdx.x / CS_LABELS;
+  const int c = (side_a ? (int)blockIdx.x : (int)blockIdx.x - ga) * CS_LABELS + lane;
+  const int per = (W + CS_GROUPS - 1) / CS_GROUPS;
+  const int w0 = min(W, grp * per), w1 = min(W, w0 + per);
+  u32 sn = 0;
+  if (c < L)
+    for (int w = w0; w < w1; ++w) sn += H[(size_t)w * L + c];
+  s_n[grp][lane] = sn;
+  __syncthreads();
+  if (c < L && grp == 0) {
+    u32 t = 0;
+    for (int i = 0; i < CS_GROUPS; ++i) t += s_n[i][lane];
+    N[c] = t;
+  }
+}
+
 // Bands of ground-truth labels from their sizes A (one workgroup).  Band k holds the
 // labels SBA[k] .. SBA[k+1]-1 and the nodes SBS[k] .. SBS[k+1]-1 of the band words; a band
 // ends after label a when the running node count passes a multiple of T inside a, after
@@ -199,6 +274,51 @@ __global__ __launch_bounds__(CP_THREADS) void k_cmp_part(int n, const int32_t* _
   u32* s_rc = s_dyn + nb;       // the round's nodes per band, then their first place in s_buf
   const int tid = threadIdx.x;
   for (int i = tid; i < nb; i += CP_THREADS) s_run[i] = 0;
+  if (rounds == 1) {
+    // one round: the round's counts are the chunk's counts, so the labels are read once
+    for (int i = tid; i < nb; i += CP_THREADS) s_rc[i] = 0;
+    __syncthreads();
+    const long long u0 = (long long)blockIdx.x * CP_CHUNK;
+    u32 word[CP_NPT], key[CP_NPT], rank[CP_NPT];
+#pragma unroll
+    for (int k = 0; k < CP_NPT; ++k) {
+      const long long u = u0 + tid + (long long)k * CP_THREADS;
+      int a = -1, b = 0;
+      if (u < n) {
+        a = la[u];
+        b = lb[u];
+      }
+      key[k] = (u32)a < (u32)La ? (u32)a : 0xFFFFFFFFu;
+      word[k] = (u32)b < (u32)Lb ? (u32)b : CMP_BAD_B;
+    }
+#pragma unroll
+    for (int k = 0; k < CP_NPT; ++k)
+      if (key[k] != 0xFFFFFFFFu) key[k] = sbk[key[k]];
+#pragma unroll
+    for (int k = 0; k < CP_NPT; ++k)
+      if (key[k] != 0xFFFFFFFFu) rank[k] = atomicAdd(&s_rc[key[k] >> 8], 1u);
+    __syncthreads();
+    for (int i = tid; i < nb; i += CP_THREADS) {
+      const u32 c = s_rc[i];
+      s_run[i] = c ? atomicAdd(&CUR[i], c) : 0u;  // one claim per band the chunk has nodes of
+    }
+    const u32 total = block_excl_scan4(s_rc, nb, s_w);
+#pragma unroll
+    for (int k = 0; k < CP_NPT; ++k) {
+      if (key[k] != 0xFFFFFFFFu) {
+        const u32 band = key[k] >> 8;
+        const u32 p = s_rc[band] + rank[k];
+        s_buf[p] = ((key[k] & 0xFFu) << 16) | word[k];
+        s_bid[p] = (uint16_t)band;
+      }
+    }
+    __syncthreads();
+    for (u32 p = tid; p < total; p += CP_THREADS) {
+      const u32 band = s_bid[p];
+      E[s_run[band] + (p - s_rc[band])] = s_buf[p];
+    }
+    return;
+  }
   __syncthreads();
   const long long c0 = (long long)blockIdx.x * rounds * CP_CHUNK;
   for (int r = 0; r < rounds; ++r) {

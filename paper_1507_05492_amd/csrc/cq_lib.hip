@@ -313,10 +313,10 @@ struct CmpLayout {
 // Band path sizes: bands of about T nodes, at least 8,192 (a band's cells then mostly fit
 // the cell table in one class) and at most about 1,024 bands by size (every chunk claims
 // one run per band it has nodes of); chunks of whole rounds of CP_CHUNK nodes, at most
-// about 512 chunks.
+// about 1,024 chunks.
 constexpr int64_t CB_MIN_T = 8192;
 constexpr int64_t CB_MAX_BANDS_BY_SIZE = 1024;
-constexpr int64_t CP_MAX_CHUNKS = 512;
+constexpr int64_t CP_MAX_CHUNKS = 1024;
 
 CmpLayout cmp_layout(int64_t n, int64_t La, int64_t Lb) {
   CmpLayout s{};
@@ -825,17 +825,26 @@ void compare_launch_bands(cq_context* ctx, int32_t n, const int32_t* la, int32_t
   u64* RXL = at<u64>(ws, lay.RXL);
   {
     StageMark mk(ctx, ST_SETUP, timed);
-    fill(reinterpret_cast<u32*>(ctl), sizeof(Ctl) / 4, 0, s);
-    fill(wq, WQ_WORDS, 0, s);
-    fill(COLMAX, (size_t)Lb, 0, s);
+    const int words = (int)(sizeof(Ctl) / 4) + (int)WQ_WORDS + Lb;
+    k_cmp_clear<<<grid_for(words, 256, 1024), 256, 0, s>>>(reinterpret_cast<u32*>(ctl), (int)(sizeof(Ctl) / 4), wq, COLMAX, Lb);
   }
-  {
+  if ((int64_t)La + Lb <= 2 * PRIV_MAX) {
     StageMark mk(ctx, ST_NODE, timed);
-    label_totals(n, la, La, lay.Wa, at<u32>(ws, lay.HA), A, ctl, s);
-  }
-  {
-    StageMark mk(ctx, ST_HIST_B, timed);
-    label_totals(n, lb, Lb, lay.Wb, at<u32>(ws, lay.HB), B, ctl, s);
+    u32* HA = at<u32>(ws, lay.HA);
+    u32* HB = at<u32>(ws, lay.HB);
+    (void)hipFuncSetAttribute((const void*)k_hist2_priv, hipFuncAttributeMaxDynamicSharedMemorySize, (La + Lb) * 4);
+    k_hist2_priv<<<lay.Wa, 1024, ((size_t)La + Lb) * 4, s>>>(n, la, La, lb, Lb, HA, HB, ctl);
+    const int ga = (int)colscan_grid(La), gb = (int)colscan_grid(Lb);
+    k_cmp_totals<<<ga + gb, CS_LABELS * CS_GROUPS, 0, s>>>(lay.Wa, La, Lb, ga, HA, HB, A, B);
+  } else {
+    {
+      StageMark mk(ctx, ST_NODE, timed);
+      label_totals(n, la, La, lay.Wa, at<u32>(ws, lay.HA), A, ctl, s);
+    }
+    {
+      StageMark mk(ctx, ST_HIST_B, timed);
+      label_totals(n, lb, Lb, lay.Wb, at<u32>(ws, lay.HB), B, ctl, s);
+    }
   }
   {
     StageMark mk(ctx, ST_ORDER, timed);
