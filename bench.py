@@ -425,6 +425,8 @@ def bench_batch(args, log) -> int:
         for lab in parts:
             tasks.append((G, lab, g.num_labels))
             total_nnz += g.nnz
+        if (i + 1) % 32 == 0:
+            log(f"batch: {i + 1} of 256 graphs generated and loaded")
     torch.cuda.synchronize()
     gen_s = time.perf_counter() - t
     log(f"batch: {len(tasks)} tasks over {len(graphs)} graphs, sum 2|E| = {total_nnz}, built in {gen_s:.1f}s")

@@ -3078,6 +3078,7 @@ struct GroupDev {
   const int32_t* col;
   int n, np;
   int task[BATCH_FUSE];
+  unsigned long long* il;  // per stored node: the group's partitions' labels, 16 bits each (partition p at bits 16p)
 };
 
 // largest i in [0, cnt) with pre[i] <= x (pre non-decreasing, pre[0] == 0)
@@ -3142,15 +3143,27 @@ __global__ __launch_bounds__(1024) void k_b_kprefix(const TaskDev* __restrict__ 
 
 // Edge pass for a group of partitions of one graph: every col_idx entry is read once
 // and the neighbour's label of each partition goes to that partition's segment.
+// Workgroup b runs on XCD b % 8 (workgroups are handed to the XCDs in turn) and takes
+// tile b / 8 of that XCD's list: a graph's tiles run on one XCD, so the neighbour labels
+// they read at random stay in that XCD's L2, except for graphs large enough to unbalance
+// the XCDs, whose tiles are dealt to all eight in turn.  Per XCD, ngroups list entries:
+// XRB the tile prefix (ngroups + 1 values, padded with the total), XG the group, XO its
+// first tile (bit 31: the entry takes every 8th tile of the group, else consecutive ones).
 template <int R>
-__global__ __launch_bounds__(R) void k_b_gather(const GroupDev* __restrict__ gd, const u32* __restrict__ RBpre, int ngroups,
-                                                const TaskDev* __restrict__ td) {
+__global__ __launch_bounds__(R) void k_b_gather(const GroupDev* __restrict__ gd, const u32* __restrict__ XRB,
+                                                const u32* __restrict__ XG, int ngroups, const TaskDev* __restrict__ td) {
   __shared__ int s_rs[R + 1];
   __shared__ u32 s_base[BATCH_FUSE][R];
-  const int k = find_seg(RBpre, ngroups, blockIdx.x);
+  const u32 x = blockIdx.x % 8u, i = blockIdx.x / 8u;
+  const u32* pre = XRB + (size_t)x * (ngroups + 1);
+  if (i >= pre[ngroups]) return;
+  const int j = find_seg(pre, ngroups, i);
+  const int k = (int)XG[(size_t)x * ngroups + j];
+  const u32 xo = XG[(size_t)8 * ngroups + (size_t)x * ngroups + j];
+  const u32 tile = (xo & 0x7FFFFFFFu) + ((xo >> 31) ? 8u : 1u) * (i - pre[j]);
   const GroupDev grp = gd[k];
   const int tid = threadIdx.x;
-  const long long r0 = (long long)(blockIdx.x - RBpre[k]) * R;
+  const long long r0 = (long long)tile * R;
   const int rows = (int)min((long long)R, (long long)grp.n - r0);
   if (tid < rows) {
     const long long u = r0 + tid;
@@ -3169,13 +3182,10 @@ __global__ __launch_bounds__(R) void k_b_gather(const GroupDev* __restrict__ gd,
   }
   if (tid == 0) s_rs[rows] = grp.rp[r0 + rows];
   __syncthreads();
-  const uint16_t* lx[BATCH_FUSE];
   uint16_t* cb[BATCH_FUSE];
 #pragma unroll
-  for (int p = 0; p < BATCH_FUSE; ++p) {
-    lx[p] = p < grp.np ? td[grp.task[p]].labx : nullptr;
-    cb[p] = p < grp.np ? td[grp.task[p]].CB : nullptr;
-  }
+  for (int p = 0; p < BATCH_FUSE; ++p) cb[p] = p < grp.np ? td[grp.task[p]].CB : nullptr;
+  const unsigned long long* __restrict__ il = grp.il;
   const int e0 = s_rs[0], e1 = s_rs[rows];
   for (int e = e0 + tid; e < e1; e += R) {
     int lo = 0, hi = rows - 1;
@@ -3185,13 +3195,37 @@ __global__ __launch_bounds__(R) void k_b_gather(const GroupDev* __restrict__ gd,
     }
     const int v = grp.col[e];
     const u32 off = (u32)(e - s_rs[lo]);
+    const unsigned long long w = il[v];  // the neighbour's label in every partition: one load
 #pragma unroll
     for (int p = 0; p < BATCH_FUSE; ++p) {
       if (p < grp.np) {
         const u32 b = s_base[p][lo];
-        if (b != SENT) cb[p][b + off] = lx[p][v];
+        if (b != SENT) cb[p][b + off] = (uint16_t)(w >> (16 * p));
       }
     }
+  }
+}
+
+// The labels of each group's partitions interleaved per stored node (see GroupDev::il), so
+// that the edge pass reads a neighbour's labels with one load instead of one per
+// partition (random 2-byte reads are L2 requests, and their rate is what the edge pass
+// spends).  Workgroup b takes IL_NODES nodes of group find_seg(NBpre, b).
+constexpr int IL_NODES = 4096;
+__global__ __launch_bounds__(256) void k_b_interleave(const GroupDev* __restrict__ gd, const u32* __restrict__ NBpre,
+                                                      int ngroups, const TaskDev* __restrict__ td) {
+  const int k = find_seg(NBpre, ngroups, blockIdx.x);
+  const GroupDev grp = gd[k];
+  const long long u0 = (long long)(blockIdx.x - NBpre[k]) * IL_NODES;
+  const long long u1 = min((long long)grp.n, u0 + IL_NODES);
+  const uint16_t* lx[BATCH_FUSE];
+#pragma unroll
+  for (int p = 0; p < BATCH_FUSE; ++p) lx[p] = p < grp.np ? td[grp.task[p]].labx : nullptr;
+  for (long long u = u0 + threadIdx.x; u < u1; u += 256) {
+    unsigned long long w = 0;
+#pragma unroll
+    for (int p = 0; p < BATCH_FUSE; ++p)
+      w |= (unsigned long long)(p < grp.np ? lx[p][u] : LabelT<uint16_t>::SENTINEL) << (16 * p);
+    grp.il[u] = w;
   }
 }
 

@@ -110,7 +110,11 @@ struct cq_batch_plan {
   void* gd = nullptr;  // cq::GroupDev[ngroups]
   uint32_t *Wpre = nullptr, *Lpre = nullptr, *Gpre = nullptr, *Kpre = nullptr, *wq = nullptr;
   uint32_t* items = nullptr;  // (task << 14) | group of every item of the group pass (in the workspace)
-  uint32_t* RBpre[3] = {nullptr, nullptr, nullptr};
+  uint32_t* RBpre[3] = {nullptr, nullptr, nullptr};  // per gather tile size: per XCD, tile prefixes over its groups
+  uint32_t* XG[3] = {nullptr, nullptr, nullptr};     // per gather tile size: per XCD, its groups
+  std::vector<size_t> il_off;  // per group: workspace offset of its interleaved labels
+  uint32_t* NBpre = nullptr;   // per group: prefix of k_b_interleave workgroups
+  uint32_t NBsum = 0;
   uint32_t Wsum = 0, Lsum = 0, Gsum = 0, RBsum[3] = {0, 0, 0};
   // binding
   void* ws = nullptr;
@@ -1145,10 +1149,11 @@ void batch_launch(cq_batch_plan* p, hipStream_t s, int rsel, int occ) {
   k_b_scan_order<<<T, 1024, 0, s>>>(td);
   k_b_kprefix<<<1, 1024, 0, s>>>(td, T, p->Kpre);
   k_b_items<<<(unsigned)(p->ctx->num_cus * 4), 256, 0, s>>>(td, p->Kpre, T, p->items);
+  k_b_interleave<<<std::max(1u, p->NBsum), 256, 0, s>>>(gd, p->NBpre, ng, td);
   switch (rsel) {
-    case 0: k_b_gather<128><<<p->RBsum[0], 128, 0, s>>>(gd, p->RBpre[0], ng, td); break;
-    case 1: k_b_gather<256><<<p->RBsum[1], 256, 0, s>>>(gd, p->RBpre[1], ng, td); break;
-    default: k_b_gather<512><<<p->RBsum[2], 512, 0, s>>>(gd, p->RBpre[2], ng, td); break;
+    case 0: k_b_gather<128><<<p->RBsum[0], 128, 0, s>>>(gd, p->RBpre[0], p->XG[0], ng, td); break;
+    case 1: k_b_gather<256><<<p->RBsum[1], 256, 0, s>>>(gd, p->RBpre[1], p->XG[1], ng, td); break;
+    default: k_b_gather<512><<<p->RBsum[2], 512, 0, s>>>(gd, p->RBpre[2], p->XG[2], ng, td); break;
   }
   const u32 lds_words = std::max<u32>(((u32)p->maxL + 3u) & ~3u, 128u);
   k_b_groups<<<(unsigned)(p->ctx->num_cus * occ), GBLOCK, (size_t)lds_words * 4, s>>>(td, p->Kpre, T, p->wq, lds_words,
@@ -1159,7 +1164,7 @@ void batch_launch(cq_batch_plan* p, hipStream_t s, int rsel, int occ) {
 
 
 struct BatchTabLayout {
-  size_t td, gd, W, L, G, K, tk, RB[3], total;
+  size_t td, gd, W, L, G, K, tk, RB[3], XG[3], NB, total;
 };
 
 BatchTabLayout batch_tab_layout(int T, int ng) {
@@ -1172,7 +1177,11 @@ BatchTabLayout batch_tab_layout(int T, int ng) {
   l.G = c.take(4 * (T + 1));
   l.K = c.take(4 * (T + 1));
   l.tk = c.take(WQ_BYTES);
-  for (int r = 0; r < 3; ++r) l.RB[r] = c.take(4 * (ng + 1));
+  for (int r = 0; r < 3; ++r) {
+    l.RB[r] = c.take(4 * 8 * ((size_t)ng + 1));
+    l.XG[r] = c.take(4 * 16 * (size_t)std::max(ng, 1));  // groups, then first tiles
+  }
+  l.NB = c.take(4 * ((size_t)ng + 1));
   l.total = c.off;
   return l;
 }
@@ -1230,11 +1239,7 @@ void batch_fill_tables(cq_batch_plan* p, void* d_ws, cq_score_result* d_results,
     Lpre[t + 1] = Lpre[t] + (u32)bt.num_labels;
     Gpre[t + 1] = Gpre[t] + (u32)lay.G;
   }
-  u32* RB[3];
-  for (int r = 0; r < 3; ++r) {
-    RB[r] = reinterpret_cast<u32*>(hb + tl.RB[r]);
-    RB[r][0] = 0;
-  }
+  std::vector<int64_t> gn(ng);
   for (int k = 0; k < ng; ++k) {
     const cq_graph* g = p->tasks[p->groups[k][0]].graph;
     GroupDev gdv;
@@ -1244,8 +1249,66 @@ void batch_fill_tables(cq_batch_plan* p, void* d_ws, cq_score_result* d_results,
     gdv.n = g->n;
     gdv.np = p->group_np[k];
     for (int i = 0; i < BATCH_FUSE; ++i) gdv.task[i] = p->groups[k][i];
+    gdv.il = reinterpret_cast<unsigned long long*>(static_cast<char*>(d_ws) + p->il_off[k]);
     std::memcpy(&gd[k], &gdv, sizeof(gdv));
-    for (int r = 0; r < 3; ++r) RB[r][k + 1] = RB[r][k] + (u32)((g->n + kGatherRows[r] - 1) / kGatherRows[r]);
+    gn[k] = g->n;
+  }
+  u32* NB = reinterpret_cast<u32*>(hb + tl.NB);
+  NB[0] = 0;
+  for (int k = 0; k < ng; ++k) NB[k + 1] = NB[k] + (u32)((gn[k] + IL_NODES - 1) / IL_NODES);
+  // groups to XCDs, per gather tile size: a group with more than 1/16 of all tiles has
+  // its tiles dealt to the eight XCDs in turn; the others go whole, largest first, each to
+  // the XCD with the fewest tiles so far (the edge pass then reads a graph's labels from
+  // one XCD's L2)
+  u32 xmax[3] = {0, 0, 0};
+  for (int r = 0; r < 3; ++r) {
+    const int R = kGatherRows[r];
+    auto tiles = [&](int k) { return (u32)((gn[k] + R - 1) / R); };
+    uint64_t all = 0;
+    for (int k = 0; k < ng; ++k) all += tiles(k);
+    struct Entry {
+      int k;
+      u32 first, count;
+      bool dealt;
+    };
+    std::vector<std::vector<Entry>> lists(8);
+    u32 load[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    std::vector<int> idx;
+    for (int k = 0; k < ng; ++k) {
+      const u32 nt = tiles(k);
+      if ((uint64_t)nt * 16 > all) {
+        for (u32 xb = 0; xb < 8; ++xb) {
+          const u32 cnt = nt > xb ? (nt - xb + 7) / 8 : 0u;
+          if (cnt) {
+            lists[xb].push_back({k, xb, cnt, true});
+            load[xb] += cnt;
+          }
+        }
+      } else {
+        idx.push_back(k);
+      }
+    }
+    std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return gn[a] > gn[b]; });
+    for (int k : idx) {
+      const int xb = (int)(std::min_element(load, load + 8) - load);
+      lists[xb].push_back({k, 0u, tiles(k), false});
+      load[xb] += tiles(k);
+    }
+    u32* XRB = reinterpret_cast<u32*>(hb + tl.RB[r]);
+    u32* XGr = reinterpret_cast<u32*>(hb + tl.XG[r]);
+    const size_t gs = (size_t)std::max(ng, 1);
+    for (int xb = 0; xb < 8; ++xb) {
+      u32* pre = XRB + (size_t)xb * (ng + 1);
+      pre[0] = 0;
+      for (int j = 0; j < ng; ++j) {
+        const bool in = j < (int)lists[xb].size();
+        const Entry e = in ? lists[xb][j] : Entry{0, 0u, 0u, false};
+        XGr[(size_t)xb * gs + j] = (u32)e.k;
+        XGr[8 * gs + (size_t)xb * gs + j] = e.first | (e.dealt ? 0x80000000u : 0u);
+        pre[j + 1] = pre[j] + e.count;
+      }
+      xmax[r] = std::max(xmax[r], pre[ng]);
+    }
   }
   char* b = static_cast<char*>(d_tab);
   p->td = b + tl.td;
@@ -1257,8 +1320,11 @@ void batch_fill_tables(cq_batch_plan* p, void* d_ws, cq_score_result* d_results,
   p->wq = reinterpret_cast<u32*>(b + tl.tk);
   for (int r = 0; r < 3; ++r) {
     p->RBpre[r] = reinterpret_cast<u32*>(b + tl.RB[r]);
-    p->RBsum[r] = RB[r][ng];
+    p->XG[r] = reinterpret_cast<u32*>(b + tl.XG[r]);
+    p->RBsum[r] = 8u * xmax[r];  // the gather grid: eight XCD lanes of the longest list
   }
+  p->NBpre = reinterpret_cast<u32*>(b + tl.NB);
+  p->NBsum = NB[ng];
   p->Wsum = Wpre[T];
   p->Lsum = Lpre[T];
   p->Gsum = Gpre[T];
@@ -1282,7 +1348,6 @@ void batch_layout(cq_batch_plan* p) {
     labels_total += (size_t)t.num_labels;
   }
   p->items_off = c.take(4 * labels_total);  // at most one item per label id of every task
-  p->ws_total = c.off;
   std::map<const cq_graph*, int> open;
   for (int i = 0; i < (int)p->tasks.size(); ++i) {
     auto it = open.find(p->tasks[i].graph);
@@ -1294,6 +1359,9 @@ void batch_layout(cq_batch_plan* p) {
     }
     p->groups[it->second][p->group_np[it->second]++] = i;
   }
+  p->il_off.clear();
+  for (const auto& g : p->groups) p->il_off.push_back(c.take(8 * (size_t)p->tasks[g[0]].graph->n));
+  p->ws_total = c.off;
 }
 
 int batch_max_occ(cq_batch_plan* p) {
@@ -2050,7 +2118,9 @@ cq_status cq_server_submit_score(cq_server* srv, const cq_graph* g, const int32_
   r->L = num_labels;
   r->ha = h_labels;
   r->ws_bytes = graph_score_layout(g, num_labels).total;
-  r->group_ws = score_layout(g->n, g->nnz, num_labels).total;
+  // inside a grouped launch: the task's workspace and, at most, one group's interleaved
+  // labels (8 bytes per node; batch_layout)
+  r->group_ws = cqsrv::aup(score_layout(g->n, g->nnz, num_labels).total) + cqsrv::aup(8 * (size_t)g->n);
   r->small = num_labels <= BATCH_MAX_L && g->nnz <= srv->cfg.small_nnz && !g->w;  // groups run the unweighted batch kernels
   return srv_submit(srv, r, ticket);
 }
