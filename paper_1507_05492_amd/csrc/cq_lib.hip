@@ -232,8 +232,8 @@ struct Carve {
 
 // Nodes per workgroup of the private-histogram node passes: about 256 workgroups, at
 // most max_chunk nodes each.
-int pick_chunk(int64_t n, int64_t max_chunk = 65536) {
-  int64_t c = 1024;
+int pick_chunk(int64_t n, int64_t max_chunk = 65536, int64_t min_chunk = 1024) {
+  int64_t c = min_chunk;
   while (c < max_chunk && c * 256 < n) c <<= 1;
   return (int)c;
 }
@@ -258,14 +258,15 @@ struct ScoreLayout {
   size_t CW, SW, IW, PENW, INVN;  // weighted graphs only (0 otherwise)
 };
 
-ScoreLayout score_layout(int64_t n, int64_t nnz, int64_t L, bool weighted = false, int64_t max_chunk = 65536) {
+ScoreLayout score_layout(int64_t n, int64_t nnz, int64_t L, bool weighted = false, int64_t max_chunk = 65536,
+                         int64_t min_chunk = 1024) {
   ScoreLayout s{};
   Carve c;
   s.priv = L <= RANGE_MAX;
   s.small = L <= 65535;
   const size_t lt = s.small ? 2 : 4;
   // several label ranges: fewer, larger node chunks keep the W x L histogram rows small
-  s.chunk = pick_chunk(n, L > PRIV_MAX ? RANGE_CHUNK_MAX : max_chunk);
+  s.chunk = pick_chunk(n, L > PRIV_MAX ? RANGE_CHUNK_MAX : std::max(max_chunk, min_chunk), min_chunk);
   s.W = (int)((n + s.chunk - 1) / s.chunk);
   s.G = (int)std::min<int64_t>(128, std::max<int64_t>(1, (L + 1023) / 1024));
   s.ctl = c.take(sizeof(Ctl));
@@ -297,6 +298,11 @@ ScoreLayout score_layout(int64_t n, int64_t nnz, int64_t L, bool weighted = fals
   s.total = c.off;
   return s;
 }
+
+// A batched task's layout: a batch has parallelism across its tasks, so its node pass
+// takes chunks of at least 4,096 nodes (4 per thread), which keeps the per-workgroup
+// histogram rows (W x L per task) few.  Never larger than the single-call layout.
+ScoreLayout batch_task_layout(int64_t n, int64_t nnz, int64_t L) { return score_layout(n, nnz, L, false, 65536, 4096); }
 
 // The layout of one scoring call on graph g (the node pass it takes decides the chunk).
 ScoreLayout graph_score_layout(const cq_graph* g, int64_t L) {
@@ -1205,7 +1211,7 @@ void batch_fill_tables(cq_batch_plan* p, void* d_ws, cq_score_result* d_results,
   for (int t = 0; t < T; ++t) {
     const cq_batch_task& bt = p->tasks[t];
     const cq_graph* g = bt.graph;
-    const ScoreLayout lay = score_layout(g->n, g->nnz, bt.num_labels);
+    const ScoreLayout lay = batch_task_layout(g->n, g->nnz, bt.num_labels);
     char* base = static_cast<char*>(d_ws) + p->ws_off[t];
     TaskDev d;
     std::memset(&d, 0, sizeof(d));
@@ -1342,7 +1348,7 @@ void batch_layout(cq_batch_plan* p) {
   Carve c;
   size_t labels_total = 0;
   for (const auto& t : p->tasks) {
-    const ScoreLayout lay = score_layout(t.graph->n, t.graph->nnz, t.num_labels);
+    const ScoreLayout lay = batch_task_layout(t.graph->n, t.graph->nnz, t.num_labels);
     p->ws_off.push_back(c.take(lay.total));
     p->maxL = std::max(p->maxL, (int)t.num_labels);
     labels_total += (size_t)t.num_labels;
