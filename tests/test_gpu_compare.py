@@ -162,3 +162,39 @@ def test_errors(cq, ctx):
     with pytest.raises(cq.CQError) as e:
         cq.compare_partitions(ctx, a[:1], 1, b[:1], 2)
     assert e.value.status == cq.CQ_E_INVALID_ARG
+
+
+def test_band_path_edges(cq, ctx):
+    """Both label spaces fit 16 bits: contingency cells counted per band of ground-truth
+    labels.  Bands cut at 128 labels with most labels empty, tables that split into
+    residue classes over two levels, a few rows sharing one large band, the largest
+    valid detected label, labels out of range on either side and an export table that
+    is too small."""
+    n = 300_000
+    a = random_labels(n, 65535, 31).numpy()
+    b = random_labels(n, 65535, 32).numpy()
+    run_cmp(cq, ctx, a, 65535, b, 65535, "65535 x 65535 random labels (class splits)")
+    sparse = (random_labels(n, 500, 33).numpy() * 131).astype(np.int32)  # 500 used of 65,500 ids
+    run_cmp(cq, ctx, sparse, 65500, a, 65535, "500 labels spread over 65500 ids")
+    a3 = random_labels(400_000, 3, 34).numpy()
+    b3 = ((a3.astype(np.int64) * 1000 + random_labels(400_000, 1000, 35).numpy()) % 65535).astype(np.int32)
+    run_cmp(cq, ctx, a3, 3, b3, 65535, "three rows in one band, 3000 cells")
+    run_cmp(cq, ctx, random_labels(50_000, 7, 36).numpy(), 7, np.full(50_000, 65534, np.int32), 65535,
+            "largest valid detected label")
+    a4 = torch.as_tensor(random_labels(20_000, 50, 37).numpy()).cuda()
+    b4 = torch.as_tensor(random_labels(20_000, 60, 38).numpy()).cuda()
+    bad_a = a4.clone()
+    bad_a[5] = 50
+    note("band path: ground-truth label out of range")
+    r, _ = cq.compare_partitions(ctx, bad_a, 50, b4, 60, allow=(cq.CQ_E_LABEL_RANGE,))
+    assert r["status"] == cq.CQ_E_LABEL_RANGE
+    bad_b = b4.clone()
+    bad_b[7] = 60
+    note("band path: detected label out of range")
+    r, _ = cq.compare_partitions(ctx, a4, 50, bad_b, 60, allow=(cq.CQ_E_LABEL_RANGE,))
+    assert r["status"] == cq.CQ_E_LABEL_RANGE
+    o = oracle.compare(a4.cpu().numpy(), 50, b4.cpu().numpy(), 60)
+    note("band path: cell table one short")
+    r, _ = cq.compare_partitions(ctx, a4, 50, b4, 60, cells_capacity=int(o.result["nnz"]) - 1,
+                                 allow=(cq.CQ_E_CAPACITY,))
+    assert r["status"] == cq.CQ_E_CAPACITY
