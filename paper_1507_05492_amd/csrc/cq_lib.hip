@@ -453,8 +453,9 @@ void score_launch(cq_context* ctx, const cq_graph* g, const int32_t* labels, int
   bool dual_rows = false;  // column-blocked graph whose staging is chosen on the device
   {
     StageMark mk(ctx, ST_SETUP, timed);
-    fill(reinterpret_cast<u32*>(ctl), sizeof(Ctl) / 4, 0, s);
-    fill(at<u32>(ws, lay.wq), WQ_WORDS, 0, s);
+    // the control block and the work queues in one launch
+    k_cmp_clear<<<grid_for((int64_t)(sizeof(Ctl) / 4) + WQ_WORDS, 256, 64), 256, 0, s>>>(
+        reinterpret_cast<u32*>(ctl), (int)(sizeof(Ctl) / 4), at<u32>(ws, lay.wq), nullptr, 0);
     if (!lay.priv) fill(at<u32>(ws, lay.SZ), 2 * (size_t)L, 0, s);
     // run cursors of column-blocked graphs: cleared by the column scan on the
     // private-histogram path, here otherwise
