@@ -79,7 +79,7 @@ __global__ __launch_bounds__(1024) void k_hist2_priv(int n, const int32_t* __res
   if (threadIdx.x == 0 && s_bad) atomicOr(&ctl->flags, F_LABEL);
 }
 
-// Clears the control block, the work queues and the column maxima in one launch.
+// Clears the control block, the work queues and (Lb > 0) the column maxima in one launch.
 __global__ __launch_bounds__(256) void k_cmp_clear(u32* __restrict__ ctl_words, int nctl, u32* __restrict__ wq,
                                                    u32* __restrict__ COLMAX, int Lb) {
   const int stride = gridDim.x * blockDim.x;

@@ -765,7 +765,7 @@ template <bool WEIGHTED, class LT, bool STAGED = false>
 __device__ __forceinline__ void node_priv_body(int n, const int32_t* __restrict__ labels, const int32_t* __restrict__ perm,
                                                const int32_t* __restrict__ rp, int L, int chunk, u32* __restrict__ HN,
                                                u32* __restrict__ HD, u32* __restrict__ loc, LT* __restrict__ labx,
-                                               Ctl* __restrict__ ctl, int blk, int lbase, int LR) {
+                                               Ctl* __restrict__ ctl, int blk, int lbase, int LR, int lst = 1) {
   extern __shared__ u32 sh[];
   u32* hn = sh;
   u32* hd = WEIGHTED ? sh + LR : sh;
@@ -784,7 +784,7 @@ __device__ __forceinline__ void node_priv_body(int n, const int32_t* __restrict_
     const bool in = u < u1;
     int c;
     if (STAGED) {
-      const u32 x = in ? (u32)labx[u] : 0u;
+      const u32 x = in ? (u32)labx[u * lst] : 0u;
       c = x == (u32)LabelT<LT>::SENTINEL ? -1 : (int)x;
     } else {
       c = in ? labels[perm ? perm[u] : u] : 0;
@@ -793,7 +793,7 @@ __device__ __forceinline__ void node_priv_body(int n, const int32_t* __restrict_
     if (first && in && !valid) {
       bad = 1;
       loc[u] = SENT;
-      if (labx && !STAGED) labx[u] = LabelT<LT>::SENTINEL;
+      if (labx && !STAGED) labx[u * lst] = LabelT<LT>::SENTINEL;
     }
     const int cl = c - lbase;
     const bool here = valid && (u32)cl < (u32)LR;
@@ -830,7 +830,7 @@ __device__ __forceinline__ void node_priv_body(int n, const int32_t* __restrict_
       old = atomicAdd(&hd[cl], w);
     }
     if (here) loc[u] = old;
-    if (first && valid && labx && !STAGED) labx[u] = (LT)c;
+    if (first && valid && labx && !STAGED) labx[u * lst] = (LT)c;
   }
   if (bad) s_bad = 1;
   __syncthreads();
@@ -1742,6 +1742,10 @@ __global__ __launch_bounds__(256) void k_cmp_scatter(int n, const int32_t* __res
 //                  that overflows is split again.  Every label is counted in exactly one
 //                  class, so visitors see each (label, count) once.
 constexpr int GBLOCK = 512;
+// Score group pass over label spaces that fit a direct LDS table (the batch's too): more,
+// smaller workgroups, so that more communities are counted at once (a community's pass
+// is bound by its few dependent round trips, not by its thread count)
+constexpr int GBLOCK_DIRECT = 256;
 constexpr int STACK = 96;
 constexpr u32 WIDE_FIX = 256;  // wrap corrections a 16-bit table can log per group
 
@@ -1750,13 +1754,13 @@ __device__ __forceinline__ u32 log2_u32(u32 x) { return 31 - __clz(x); }
 
 // Calls f(label) for every entry of a segment: 16-byte vector loads (8 labels of 16
 // bits or 4 of 32 bits), two loads in flight per thread, scalar head and tail.
-template <class LT, class F>
+template <class LT, int NT = GBLOCK, class F>
 __device__ __forceinline__ void for_each_in_segment(const LT* __restrict__ seg, const u32 len, F&& f) {
   constexpr u32 PER = 16u / sizeof(LT);
   u32 head = (u32)(((16u - ((uintptr_t)seg & 15u)) & 15u) / sizeof(LT));
   if (head > len) head = len;
   const u32 nvec = (len - head) / PER;
-  for (u32 e = threadIdx.x; e < head; e += GBLOCK) f((u32)seg[e]);
+  for (u32 e = threadIdx.x; e < head; e += NT) f((u32)seg[e]);
   const uint4* vec = reinterpret_cast<const uint4*>(seg + head);
   auto unpack = [&](const uint4 q) {
     const u32 w4[4] = {q.x, q.y, q.z, q.w};
@@ -1771,20 +1775,20 @@ __device__ __forceinline__ void for_each_in_segment(const LT* __restrict__ seg, 
     }
   };
   u32 i = threadIdx.x;
-  for (; i + GBLOCK < nvec; i += 2 * GBLOCK) {
+  for (; i + NT < nvec; i += 2 * NT) {
     const uint4 q0 = vec[i];
-    const uint4 q1 = vec[i + GBLOCK];
+    const uint4 q1 = vec[i + NT];
     unpack(q0);
     unpack(q1);
   }
-  for (; i < nvec; i += GBLOCK) unpack(vec[i]);
-  for (u32 e = head + nvec * PER + threadIdx.x; e < len; e += GBLOCK) f((u32)seg[e]);
+  for (; i < nvec; i += NT) unpack(vec[i]);
+  for (u32 e = head + nvec * PER + threadIdx.x; e < len; e += NT) f((u32)seg[e]);
 }
 
 // Counts one group's segment CB[base, base+len) (values in [0, Lv) or the sentinel)
 // in LDS and hands every (label, count) with count > 0 to the visitor.  hot0 entries of
 // the hot label were counted elsewhere (compact staging leaves them out of the segment).
-template <class V, class LT>
+template <class V, class LT, int NT = GBLOCK>
 __device__ void group_one(const LT* __restrict__ CB, const u32 base, const u32 len, const u32 g, const u32 Lv,
                           const u32 lds_words, V& vis, Ctl* __restrict__ ctl, const u32 hot0 = 0) {
   extern __shared__ __align__(16) u32 tab[];  // read and cleared as uint4
@@ -1815,7 +1819,7 @@ __device__ void group_one(const LT* __restrict__ CB, const u32 base, const u32 l
     const u32 hot = V::kHotIsGroup ? g : (len ? (u32)CB[base] : 0xFFFFFFFFu);
     const u32 nq = (Lv + 7u) >> 3;  // 16-byte words of the 16-bit table
     uint4* tab4 = reinterpret_cast<uint4*>(tab);
-    for (u32 q = tid; q < nq; q += GBLOCK) tab4[q] = make_uint4(0u, 0u, 0u, 0u);
+    for (u32 q = tid; q < nq; q += NT) tab4[q] = make_uint4(0u, 0u, 0u, 0u);
     if (tid == 0) {
       s_hot = hot0;
       s_nfix = 0;
@@ -1829,7 +1833,7 @@ __device__ void group_one(const LT* __restrict__ CB, const u32 base, const u32 l
         s_fix_del[i] = delta;
       }
     };
-    for_each_in_segment<LT>(CB + base, len, [&](u32 j) {
+    for_each_in_segment<LT, NT>(CB + base, len, [&](u32 j) {
       if (j == hot) {
         ++mine;
         return;
@@ -1860,7 +1864,7 @@ __device__ void group_one(const LT* __restrict__ CB, const u32 base, const u32 l
           if (s_fix_lab[i] == j) t += s_fix_del[i] ? 65536u : (u32)-1;
         return t;
       };
-      for (u32 q = tid; q < nq; q += GBLOCK) {
+      for (u32 q = tid; q < nq; q += NT) {
         const uint4 x = tab4[q];
         const u32 w4[4] = {x.x, x.y, x.z, x.w};
 #pragma unroll
@@ -1881,11 +1885,11 @@ __device__ void group_one(const LT* __restrict__ CB, const u32 base, const u32 l
     const u32 hot = V::kHotIsGroup ? g : (len ? (u32)CB[base] : 0xFFFFFFFFu);
     const u32 nq = (Lv + 3u) >> 2;  // the table is padded to whole 16-byte words
     uint4* tab4 = reinterpret_cast<uint4*>(tab);
-    for (u32 q = tid; q < nq; q += GBLOCK) tab4[q] = make_uint4(0u, 0u, 0u, 0u);
+    for (u32 q = tid; q < nq; q += NT) tab4[q] = make_uint4(0u, 0u, 0u, 0u);
     if (tid == 0) s_hot = hot0;
     __syncthreads();
     u32 mine = 0;
-    for_each_in_segment<LT>(CB + base, len, [&](u32 j) {
+    for_each_in_segment<LT, NT>(CB + base, len, [&](u32 j) {
       if (j == hot) ++mine;
       else if (j < Lv) atomicAdd(&tab[j], 1u);
     });
@@ -1897,8 +1901,8 @@ __device__ void group_one(const LT* __restrict__ CB, const u32 base, const u32 l
       // that the loads overlap; N is read as 16-byte words up to the table's padding
       // (workspace arrays are 16-byte aligned and padded to 256 bytes)
       const uint4* N4 = reinterpret_cast<const uint4*>(vis.N);
-      for (u32 q0 = tid; q0 < nq; q0 += 2u * GBLOCK) {
-        const u32 q1 = q0 + GBLOCK;
+      for (u32 q0 = tid; q0 < nq; q0 += 2u * NT) {
+        const u32 q1 = q0 + NT;
         const uint4 n0 = N4[q0];
         uint4 n1 = make_uint4(0u, 0u, 0u, 0u);
         if (q1 < nq) n1 = N4[q1];
@@ -1913,7 +1917,7 @@ __device__ void group_one(const LT* __restrict__ CB, const u32 base, const u32 l
         if (q1 < nq) visit4(q1, n1);
       }
     } else {
-      for (u32 q = tid; q < nq; q += GBLOCK) {
+      for (u32 q = tid; q < nq; q += NT) {
         const uint4 x = tab4[q];
         if (x.x) vis.visit(st, 4u * q, x.x);
         if (x.y) vis.visit(st, 4u * q + 1u, x.y);
@@ -1953,10 +1957,10 @@ __device__ void group_one(const LT* __restrict__ CB, const u32 base, const u32 l
       const u32 r = s_sr[sp - 1], mod = s_sm[sp - 1];
       __syncthreads();
       if (tid == 0) { s_sp = sp - 1; s_over = 0; }
-      for (u32 s = tid; s < hcap; s += GBLOCK) { keys[s] = EMPTY; cnt[s] = 0; }
+      for (u32 s = tid; s < hcap; s += NT) { keys[s] = EMPTY; cnt[s] = 0; }
       __syncthreads();
       bool over = false;
-      for_each_in_segment<LT>(CB + base, len, [&](u32 j) {
+      for_each_in_segment<LT, NT>(CB + base, len, [&](u32 j) {
         if (j == hot) {
           if (first) ++mine;
           return;
@@ -1994,7 +1998,7 @@ __device__ void group_one(const LT* __restrict__ CB, const u32 base, const u32 l
         __syncthreads();
         continue;
       }
-      for (u32 s = tid; s < hcap; s += GBLOCK) {
+      for (u32 s = tid; s < hcap; s += NT) {
         u32 k = keys[s];
         if (k != EMPTY) {
           vis.visit(st, k, cnt[s]);
@@ -2015,10 +2019,11 @@ __device__ void group_one(const LT* __restrict__ CB, const u32 base, const u32 l
   __syncthreads();
 }
 
-template <class V, class LT>
+template <class V, class LT, int NT = GBLOCK>
 // cur64 (compact staging, else null): low word = segment length, high word = entries of
 // the group's own label left out of the segment; otherwise seg_len gives the length.
-__global__ __launch_bounds__(GBLOCK) void k_groups(const LT* __restrict__ CB, const u32* __restrict__ seg_start,
+// NT threads per workgroup.
+__global__ __launch_bounds__(NT) void k_groups(const LT* __restrict__ CB, const u32* __restrict__ seg_start,
                                                    const u32* __restrict__ seg_len, const u32* __restrict__ order,
                                                    Ctl* __restrict__ ctl, u32 Lv, u32 lds_words, V vis,
                                                    const unsigned long long* __restrict__ cur64, u32* __restrict__ wq,
@@ -2035,7 +2040,7 @@ __global__ __launch_bounds__(GBLOCK) void k_groups(const LT* __restrict__ CB, co
     if (item >= K) break;
     const u32 g = order[item];
     const unsigned long long c = compact ? cur64[g] : (unsigned long long)seg_len[g];
-    group_one<V, LT>(CB, seg_start[g], (u32)c, g, Lv, lds_words, vis, ctl, (u32)(c >> 32));
+    group_one<V, LT, NT>(CB, seg_start[g], (u32)c, g, Lv, lds_words, vis, ctl, (u32)(c >> 32));
   }
 }
 
@@ -2165,7 +2170,7 @@ __global__ __launch_bounds__(64 * GW_WAVES) void k_groups_wave(const uint16_t* _
   }
 }
 
-// block reduction helpers for the visitors (GBLOCK threads = 8 waves)
+// block reduction helpers for the visitors (GBLOCK threads)
 __device__ __forceinline__ u128 block_sum_u128(u128 x, u64* sh_lo, u64* sh_hi) {
   x = wave_sum_u128(x);
   int w = threadIdx.x >> 6;
@@ -3061,7 +3066,8 @@ struct TaskDev {
   const int32_t* rp;
   const int32_t* col;
   long long nnz;
-  int n, L, chunk, W, G, pad;
+  int n, L, chunk, W, G;
+  int lst;  // labx stride: the labels go to lane p of the task's group's interleaved words (GroupDev::il)
   Ctl* ctl;
   u32 *N, *D, *start, *order, *I, *NP;
   u64* PEN;
@@ -3078,7 +3084,11 @@ struct GroupDev {
   const int32_t* col;
   int n, np;
   int task[BATCH_FUSE];
-  unsigned long long* il;  // per stored node: the group's partitions' labels, 16 bits each (partition p at bits 16p)
+  // per stored node: the group's partitions' labels, 16 bits each (partition p at bits 16p),
+  // written by the node pass; the edge pass reads a neighbour's labels in every partition
+  // with one load (random 2-byte reads are L2 requests, and their rate is what the edge
+  // pass spends)
+  unsigned long long* il;
 };
 
 // largest i in [0, cnt) with pre[i] <= x (pre non-decreasing, pre[0] == 0)
@@ -3101,11 +3111,24 @@ __global__ void k_b_setup(int T, const TaskDev* __restrict__ td, u32* __restrict
     for (u32 i = threadIdx.x; i < WQ_WORDS; i += blockDim.x) wq[i] = 0;
 }
 
-__global__ __launch_bounds__(1024) void k_b_node(const TaskDev* __restrict__ td, const u32* __restrict__ Wpre, int T) {
-  const int t = find_seg(Wpre, T, blockIdx.x);
+// Node pass over every task's chunks.  Workgroup b runs on XCD b % 8 and takes entry
+// b / 8 of that XCD's list, so that the labels a task reads at random (in the caller's
+// order, through the graph's permutation) are pulled into one XCD's L2.  Per XCD, T list
+// entries: XW the chunk prefix (T + 1 values, padded with the total), XT the task, then
+// its first chunk (bit 31: the entry takes every 8th chunk of the task, else consecutive
+// ones).
+__global__ __launch_bounds__(1024) void k_b_node(const TaskDev* __restrict__ td, const u32* __restrict__ XW,
+                                                 const u32* __restrict__ XT, int T) {
+  const u32 x = blockIdx.x % 8u, i = blockIdx.x / 8u;
+  const u32* pre = XW + (size_t)x * (T + 1);
+  if (i >= pre[T]) return;
+  const int j = find_seg(pre, T, i);
+  const int t = (int)XT[(size_t)x * T + j];
+  const u32 fo = XT[(size_t)8 * T + (size_t)x * T + j];
+  const u32 blk = (fo & 0x7FFFFFFFu) + ((fo >> 31) ? 8u : 1u) * (i - pre[j]);
   const TaskDev& d = td[t];
-  node_priv_body<true, uint16_t>(d.n, d.labels, d.perm, d.rp, d.L, d.chunk, d.HN, d.HD, d.loc, d.labx, d.ctl,
-                                 (int)(blockIdx.x - Wpre[t]), 0, d.L);
+  node_priv_body<true, uint16_t>(d.n, d.labels, d.perm, d.rp, d.L, d.chunk, d.HN, d.HD, d.loc, d.labx, d.ctl, (int)blk,
+                                 0, d.L, d.lst);
 }
 
 __global__ __launch_bounds__(256) void k_b_colscan(const TaskDev* __restrict__ td, const u32* __restrict__ Lpre, int T) {
@@ -3165,14 +3188,16 @@ __global__ __launch_bounds__(R) void k_b_gather(const GroupDev* __restrict__ gd,
   const int tid = threadIdx.x;
   const long long r0 = (long long)tile * R;
   const int rows = (int)min((long long)R, (long long)grp.n - r0);
+  const unsigned long long* __restrict__ il = grp.il;
   if (tid < rows) {
     const long long u = r0 + tid;
     s_rs[tid] = grp.rp[u];
+    const unsigned long long own = il[u];  // the row's label in every partition
 #pragma unroll
     for (int p = 0; p < BATCH_FUSE; ++p) {
       if (p < grp.np) {
         const TaskDev& d = td[grp.task[p]];
-        const uint16_t c = d.labx[u];
+        const uint16_t c = (uint16_t)(own >> (16 * p));
         const u32 lu = d.loc[u];
         u32 base = SENT;
         if (c != LabelT<uint16_t>::SENTINEL && lu != SENT) base = d.start[c] + d.HD[(size_t)(u / d.chunk) * d.L + c] + lu;
@@ -3185,7 +3210,6 @@ __global__ __launch_bounds__(R) void k_b_gather(const GroupDev* __restrict__ gd,
   uint16_t* cb[BATCH_FUSE];
 #pragma unroll
   for (int p = 0; p < BATCH_FUSE; ++p) cb[p] = p < grp.np ? td[grp.task[p]].CB : nullptr;
-  const unsigned long long* __restrict__ il = grp.il;
   const int e0 = s_rs[0], e1 = s_rs[rows];
   for (int e = e0 + tid; e < e1; e += R) {
     int lo = 0, hi = rows - 1;
@@ -3206,29 +3230,6 @@ __global__ __launch_bounds__(R) void k_b_gather(const GroupDev* __restrict__ gd,
   }
 }
 
-// The labels of each group's partitions interleaved per stored node (see GroupDev::il), so
-// that the edge pass reads a neighbour's labels with one load instead of one per
-// partition (random 2-byte reads are L2 requests, and their rate is what the edge pass
-// spends).  Workgroup b takes IL_NODES nodes of group find_seg(NBpre, b).
-constexpr int IL_NODES = 4096;
-__global__ __launch_bounds__(256) void k_b_interleave(const GroupDev* __restrict__ gd, const u32* __restrict__ NBpre,
-                                                      int ngroups, const TaskDev* __restrict__ td) {
-  const int k = find_seg(NBpre, ngroups, blockIdx.x);
-  const GroupDev grp = gd[k];
-  const long long u0 = (long long)(blockIdx.x - NBpre[k]) * IL_NODES;
-  const long long u1 = min((long long)grp.n, u0 + IL_NODES);
-  const uint16_t* lx[BATCH_FUSE];
-#pragma unroll
-  for (int p = 0; p < BATCH_FUSE; ++p) lx[p] = p < grp.np ? td[grp.task[p]].labx : nullptr;
-  for (long long u = u0 + threadIdx.x; u < u1; u += 256) {
-    unsigned long long w = 0;
-#pragma unroll
-    for (int p = 0; p < BATCH_FUSE; ++p)
-      w |= (unsigned long long)(p < grp.np ? lx[p][u] : LabelT<uint16_t>::SENTINEL) << (16 * p);
-    grp.il[u] = w;
-  }
-}
-
 // The group pass's items as one list: item i (Kpre[t] <= i < Kpre[t+1]) is group
 // order_t[i - Kpre[t]] of task t, packed as (t << 14) | group (groups < 16384 in a batch),
 // so that the persistent pass needs one load per item instead of a search over Kpre.
@@ -3241,8 +3242,9 @@ __global__ __launch_bounds__(256) void k_b_items(const TaskDev* __restrict__ td,
   }
 }
 
-// Persistent group pass over the communities of every task (per-XCD work queues, wq_next).
-__global__ __launch_bounds__(GBLOCK) void k_b_groups(const TaskDev* __restrict__ td, const u32* __restrict__ Kpre, int T,
+// Persistent group pass over the communities of every task (per-XCD work queues, wq_next),
+// in workgroups of GBLOCK_DIRECT threads, as a single call with the same label count.
+__global__ __launch_bounds__(GBLOCK_DIRECT, 8) void k_b_groups(const TaskDev* __restrict__ td, const u32* __restrict__ Kpre, int T,
                                                      u32* __restrict__ wq, u32 lds_words, const u32* __restrict__ items) {
   __shared__ u32 s_item, s_tg;
   const u32 total = Kpre[T];
@@ -3271,7 +3273,7 @@ __global__ __launch_bounds__(GBLOCK) void k_b_groups(const TaskDev* __restrict__
     vis.ecnt = nullptr;
     vis.ecap = 0;
     vis.ctl = d.ctl;
-    group_one<ScoreVis, uint16_t>(d.CB, d.start[g], d.D[g], g, (u32)d.L, lds_words, vis, d.ctl);
+    group_one<ScoreVis, uint16_t, GBLOCK_DIRECT>(d.CB, d.start[g], d.D[g], g, (u32)d.L, lds_words, vis, d.ctl);
   }
 }
 

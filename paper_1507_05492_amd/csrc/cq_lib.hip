@@ -113,8 +113,8 @@ struct cq_batch_plan {
   uint32_t* RBpre[3] = {nullptr, nullptr, nullptr};  // per gather tile size: per XCD, tile prefixes over its groups
   uint32_t* XG[3] = {nullptr, nullptr, nullptr};     // per gather tile size: per XCD, its groups
   std::vector<size_t> il_off;  // per group: workspace offset of its interleaved labels
-  uint32_t* NBpre = nullptr;   // per group: prefix of k_b_interleave workgroups
-  uint32_t NBsum = 0;
+  uint32_t *XWpre = nullptr, *XT = nullptr;  // node pass: per XCD, its tasks' chunk prefix and (task, first chunk)
+  uint32_t NXsum = 0;                        // node pass grid
   uint32_t Wsum = 0, Lsum = 0, Gsum = 0, RBsum[3] = {0, 0, 0};
   // binding
   void* ws = nullptr;
@@ -406,10 +406,10 @@ void fill(u32* p, size_t words, u32 v, hipStream_t s) {
   k_fill_u32<<<grid_for((int64_t)words, 256, 1024), 256, 0, s>>>(p, words, v);
 }
 
-template <class V, class LT>
+template <class V, class LT, int NT = GBLOCK>
 unsigned group_grid(cq_context* ctx, size_t lds_bytes) {
   int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_groups<V, LT>, GBLOCK, lds_bytes) != hipSuccess || nb < 1) nb = 1;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_groups<V, LT, NT>, NT, lds_bytes) != hipSuccess || nb < 1) nb = 1;
   return (unsigned)(ctx->num_cus * nb);
 }
 
@@ -648,9 +648,17 @@ void score_launch(cq_context* ctx, const cq_graph* g, const int32_t* labels, int
     // the same pass in every storage; batches (num_labels <= 16384) never split.  With
     // direct tables the split costs more than it gains: the large groups' tail no longer
     // overlaps the small ones.
+    // Direct tables (the batch's label spaces too) take workgroups of GBLOCK_DIRECT
+    // threads, larger label spaces GBLOCK; a label count always takes the same size, so
+    // a task scores the same bits alone and in a batch (each thread sums its own visits).
     const bool waves = sizeof(LT) == 2 && L > DIRECT_MAX;
-    k_groups<ScoreVis, LT><<<group_grid<ScoreVis, LT>(ctx, lds), GBLOCK, lds, s>>>(CB, start, D, order, ctl, (u32)L, lds_words, vis,
-                                                                                 cur64, at<u32>(ws, lay.wq), waves);
+    if (L <= DIRECT_MAX)
+      k_groups<ScoreVis, LT, GBLOCK_DIRECT><<<group_grid<ScoreVis, LT, GBLOCK_DIRECT>(ctx, lds), GBLOCK_DIRECT, lds, s>>>(
+          CB, start, D, order, ctl, (u32)L, lds_words, vis, cur64, at<u32>(ws, lay.wq), false);
+    else
+      k_groups<ScoreVis, LT><<<group_grid<ScoreVis, LT>(ctx, lds), GBLOCK, lds, s>>>(CB, start, D, order, ctl, (u32)L,
+                                                                                   lds_words, vis, cur64,
+                                                                                   at<u32>(ws, lay.wq), waves);
     if (waves) {
       int nb = 0;
       if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_groups_wave<ScoreVis>, 64 * GW_WAVES, 0) != hipSuccess || nb < 1)
@@ -1151,19 +1159,18 @@ void batch_launch(cq_batch_plan* p, hipStream_t s, int rsel, int occ) {
   const GroupDev* gd = static_cast<const GroupDev*>(p->gd);
   const int ng = (int)p->groups.size();
   k_b_setup<<<T, 64, 0, s>>>(T, td, p->wq);
-  k_b_node<<<p->Wsum, 1024, 2 * (size_t)p->maxL * 4, s>>>(td, p->Wpre, T);
+  k_b_node<<<p->NXsum, 1024, 2 * (size_t)p->maxL * 4, s>>>(td, p->XWpre, p->XT, T);
   k_b_colscan<<<grid_for(p->Lsum, 256, 1u << 30), 256, 0, s>>>(td, p->Lpre, T);
   k_b_scan_order<<<T, 1024, 0, s>>>(td);
   k_b_kprefix<<<1, 1024, 0, s>>>(td, T, p->Kpre);
   k_b_items<<<(unsigned)(p->ctx->num_cus * 4), 256, 0, s>>>(td, p->Kpre, T, p->items);
-  k_b_interleave<<<std::max(1u, p->NBsum), 256, 0, s>>>(gd, p->NBpre, ng, td);
   switch (rsel) {
     case 0: k_b_gather<128><<<p->RBsum[0], 128, 0, s>>>(gd, p->RBpre[0], p->XG[0], ng, td); break;
     case 1: k_b_gather<256><<<p->RBsum[1], 256, 0, s>>>(gd, p->RBpre[1], p->XG[1], ng, td); break;
     default: k_b_gather<512><<<p->RBsum[2], 512, 0, s>>>(gd, p->RBpre[2], p->XG[2], ng, td); break;
   }
   const u32 lds_words = std::max<u32>(((u32)p->maxL + 3u) & ~3u, 128u);
-  k_b_groups<<<(unsigned)(p->ctx->num_cus * occ), GBLOCK, (size_t)lds_words * 4, s>>>(td, p->Kpre, T, p->wq, lds_words,
+  k_b_groups<<<(unsigned)(p->ctx->num_cus * occ), GBLOCK_DIRECT, (size_t)lds_words * 4, s>>>(td, p->Kpre, T, p->wq, lds_words,
                                                                                       p->items);
   k_b_final1<<<p->Gsum, FBLOCK, 0, s>>>(td, p->Gpre, T);
   k_b_final2<<<grid_for(T, 64, 1u << 20), 64, 0, s>>>(td, T);
@@ -1171,7 +1178,7 @@ void batch_launch(cq_batch_plan* p, hipStream_t s, int rsel, int occ) {
 
 
 struct BatchTabLayout {
-  size_t td, gd, W, L, G, K, tk, RB[3], XG[3], NB, total;
+  size_t td, gd, W, L, G, K, tk, RB[3], XG[3], XW, XT, total;
 };
 
 BatchTabLayout batch_tab_layout(int T, int ng) {
@@ -1188,9 +1195,67 @@ BatchTabLayout batch_tab_layout(int T, int ng) {
     l.RB[r] = c.take(4 * 8 * ((size_t)ng + 1));
     l.XG[r] = c.take(4 * 16 * (size_t)std::max(ng, 1));  // groups, then first tiles
   }
-  l.NB = c.take(4 * ((size_t)ng + 1));
+  l.XW = c.take(4 * 8 * ((size_t)T + 1));
+  l.XT = c.take(4 * 16 * (size_t)std::max(T, 1));  // tasks, then first chunks
   l.total = c.off;
   return l;
+}
+
+// Work items (graphs' tile lists, tasks' chunk lists) to XCDs: item k has cnt[k] blocks.
+// An item with more than 1/16 of all blocks has them dealt to the eight XCDs in turn; the
+// others go whole, largest first, each to the XCD with the fewest blocks so far, so that
+// an item's random reads stay in one XCD's L2.  Writes, per XCD, the block prefix of its
+// list (m + 1 values, padded with the total) to pre[x * (m + 1) ..] and its items, then
+// their first blocks (bit 31: dealt, every 8th block), to lst[x * m ..] and
+// lst[8 * m + x * m ..] (m = cnt.size(), at least 1 for the layout); returns the longest
+// list's block count.
+u32 xcd_lists(const std::vector<u32>& cnt, u32* pre_all, u32* lst) {
+  const int m = (int)cnt.size();
+  uint64_t all = 0;
+  for (u32 c : cnt) all += c;
+  struct Entry {
+    int k;
+    u32 first, count;
+    bool dealt;
+  };
+  std::vector<std::vector<Entry>> lists(8);
+  u32 load[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  std::vector<int> idx;
+  for (int k = 0; k < m; ++k) {
+    const u32 nt = cnt[k];
+    if ((uint64_t)nt * 16 > all) {
+      for (u32 xb = 0; xb < 8; ++xb) {
+        const u32 c = nt > xb ? (nt - xb + 7) / 8 : 0u;
+        if (c) {
+          lists[xb].push_back({k, xb, c, true});
+          load[xb] += c;
+        }
+      }
+    } else {
+      idx.push_back(k);
+    }
+  }
+  std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return cnt[a] > cnt[b]; });
+  for (int k : idx) {
+    const int xb = (int)(std::min_element(load, load + 8) - load);
+    lists[xb].push_back({k, 0u, cnt[k], false});
+    load[xb] += cnt[k];
+  }
+  const size_t gs = (size_t)std::max(m, 1);
+  u32 xmax = 0;
+  for (int xb = 0; xb < 8; ++xb) {
+    u32* pre = pre_all + (size_t)xb * (m + 1);
+    pre[0] = 0;
+    for (int j = 0; j < m; ++j) {
+      const bool in = j < (int)lists[xb].size();
+      const Entry e = in ? lists[xb][j] : Entry{0, 0u, 0u, false};
+      lst[(size_t)xb * gs + j] = (u32)e.k;
+      lst[8 * gs + (size_t)xb * gs + j] = e.first | (e.dealt ? 0x80000000u : 0u);
+      pre[j + 1] = pre[j] + e.count;
+    }
+    xmax = std::max(xmax, pre[m]);
+  }
+  return xmax;
 }
 
 // Writes the device tables of plan p (task descriptors, group descriptors, block
@@ -1237,7 +1302,8 @@ void batch_fill_tables(cq_batch_plan* p, void* d_ws, cq_score_result* d_results,
     d.loc = reinterpret_cast<u32*>(base + lay.loc);
     d.HN = reinterpret_cast<u32*>(base + lay.HN);
     d.HD = reinterpret_cast<u32*>(base + lay.HD);
-    d.labx = reinterpret_cast<uint16_t*>(base + lay.labx);
+    d.labx = reinterpret_cast<uint16_t*>(base + lay.labx);  // replaced by the task's lane of its group below
+    d.lst = 1;
     d.CB = reinterpret_cast<uint16_t*>(base + lay.CB);
     d.parts = reinterpret_cast<ScorePart*>(base + lay.parts);
     d.out = reinterpret_cast<ScoreResultDev*>(d_results + t);
@@ -1258,11 +1324,13 @@ void batch_fill_tables(cq_batch_plan* p, void* d_ws, cq_score_result* d_results,
     for (int i = 0; i < BATCH_FUSE; ++i) gdv.task[i] = p->groups[k][i];
     gdv.il = reinterpret_cast<unsigned long long*>(static_cast<char*>(d_ws) + p->il_off[k]);
     std::memcpy(&gd[k], &gdv, sizeof(gdv));
+    // the node pass writes task i's labels to lane i of the group's interleaved words
+    for (int i = 0; i < gdv.np; ++i) {
+      td[gdv.task[i]].labx = reinterpret_cast<uint16_t*>(gdv.il) + i;
+      td[gdv.task[i]].lst = BATCH_FUSE;
+    }
     gn[k] = g->n;
   }
-  u32* NB = reinterpret_cast<u32*>(hb + tl.NB);
-  NB[0] = 0;
-  for (int k = 0; k < ng; ++k) NB[k + 1] = NB[k] + (u32)((gn[k] + IL_NODES - 1) / IL_NODES);
   // groups to XCDs, per gather tile size: a group with more than 1/16 of all tiles has
   // its tiles dealt to the eight XCDs in turn; the others go whole, largest first, each to
   // the XCD with the fewest tiles so far (the edge pass then reads a graph's labels from
@@ -1270,53 +1338,14 @@ void batch_fill_tables(cq_batch_plan* p, void* d_ws, cq_score_result* d_results,
   u32 xmax[3] = {0, 0, 0};
   for (int r = 0; r < 3; ++r) {
     const int R = kGatherRows[r];
-    auto tiles = [&](int k) { return (u32)((gn[k] + R - 1) / R); };
-    uint64_t all = 0;
-    for (int k = 0; k < ng; ++k) all += tiles(k);
-    struct Entry {
-      int k;
-      u32 first, count;
-      bool dealt;
-    };
-    std::vector<std::vector<Entry>> lists(8);
-    u32 load[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    std::vector<int> idx;
-    for (int k = 0; k < ng; ++k) {
-      const u32 nt = tiles(k);
-      if ((uint64_t)nt * 16 > all) {
-        for (u32 xb = 0; xb < 8; ++xb) {
-          const u32 cnt = nt > xb ? (nt - xb + 7) / 8 : 0u;
-          if (cnt) {
-            lists[xb].push_back({k, xb, cnt, true});
-            load[xb] += cnt;
-          }
-        }
-      } else {
-        idx.push_back(k);
-      }
-    }
-    std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return gn[a] > gn[b]; });
-    for (int k : idx) {
-      const int xb = (int)(std::min_element(load, load + 8) - load);
-      lists[xb].push_back({k, 0u, tiles(k), false});
-      load[xb] += tiles(k);
-    }
-    u32* XRB = reinterpret_cast<u32*>(hb + tl.RB[r]);
-    u32* XGr = reinterpret_cast<u32*>(hb + tl.XG[r]);
-    const size_t gs = (size_t)std::max(ng, 1);
-    for (int xb = 0; xb < 8; ++xb) {
-      u32* pre = XRB + (size_t)xb * (ng + 1);
-      pre[0] = 0;
-      for (int j = 0; j < ng; ++j) {
-        const bool in = j < (int)lists[xb].size();
-        const Entry e = in ? lists[xb][j] : Entry{0, 0u, 0u, false};
-        XGr[(size_t)xb * gs + j] = (u32)e.k;
-        XGr[8 * gs + (size_t)xb * gs + j] = e.first | (e.dealt ? 0x80000000u : 0u);
-        pre[j + 1] = pre[j] + e.count;
-      }
-      xmax[r] = std::max(xmax[r], pre[ng]);
-    }
+    std::vector<u32> tiles(ng);
+    for (int k = 0; k < ng; ++k) tiles[k] = (u32)((gn[k] + R - 1) / R);
+    xmax[r] = xcd_lists(tiles, reinterpret_cast<u32*>(hb + tl.RB[r]), reinterpret_cast<u32*>(hb + tl.XG[r]));
   }
+  // the node pass's chunks, by task, the same way
+  std::vector<u32> chunks(T);
+  for (int t = 0; t < T; ++t) chunks[t] = Wpre[t + 1] - Wpre[t];
+  const u32 xmaxw = xcd_lists(chunks, reinterpret_cast<u32*>(hb + tl.XW), reinterpret_cast<u32*>(hb + tl.XT));
   char* b = static_cast<char*>(d_tab);
   p->td = b + tl.td;
   p->gd = b + tl.gd;
@@ -1330,8 +1359,9 @@ void batch_fill_tables(cq_batch_plan* p, void* d_ws, cq_score_result* d_results,
     p->XG[r] = reinterpret_cast<u32*>(b + tl.XG[r]);
     p->RBsum[r] = 8u * xmax[r];  // the gather grid: eight XCD lanes of the longest list
   }
-  p->NBpre = reinterpret_cast<u32*>(b + tl.NB);
-  p->NBsum = NB[ng];
+  p->XWpre = reinterpret_cast<u32*>(b + tl.XW);
+  p->XT = reinterpret_cast<u32*>(b + tl.XT);
+  p->NXsum = 8u * xmaxw;
   p->Wsum = Wpre[T];
   p->Lsum = Lpre[T];
   p->Gsum = Gpre[T];
@@ -1374,7 +1404,8 @@ void batch_layout(cq_batch_plan* p) {
 int batch_max_occ(cq_batch_plan* p) {
   const u32 lds_words = std::max<u32>(((u32)p->maxL + 3u) & ~3u, 128u);
   int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_b_groups, GBLOCK, (size_t)lds_words * 4) != hipSuccess || nb < 1)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_b_groups, GBLOCK_DIRECT, (size_t)lds_words * 4) != hipSuccess ||
+      nb < 1)
     nb = 1;
   return nb;
 }
