@@ -99,6 +99,39 @@ def test_graph_replays_track_label_contents(cq, ctx):
     b.close()
 
 
+def test_large_task_spread_over_xcds(cq, ctx):
+    """A graph large enough that its node chunks and edge tiles are dealt to all eight
+    XCDs (more than 1/16 of the batch's work), beside small graphs that go whole to one
+    XCD, and the large graph's partitions alone (every task dealt): each task equals its
+    single call bit for bit."""
+    note("batch: one 300k-node graph x 4 partitions + 3 small graphs")
+    big = lfr_graph(LFRParams(300_000, 16, 80, 2.0, 1.0, 20, 1000, 0.3), 4100, device="cuda")
+    Gb = cq.Graph(ctx, big.row_ptr, big.col_idx, reorder=True)
+    big_tasks = [(Gb, big.labels.contiguous(), big.num_labels)] + [
+        (Gb, perturb_labels(big.labels, big.num_labels, f, 4110 + k).contiguous(), big.num_labels)
+        for k, f in enumerate((0.05, 0.15, 0.30))]
+    small = []
+    for i in range(3):
+        g = lfr_graph(LFRParams(3000 + 500 * i, 12, 60, 2.0, 1.0, 20, 300, 0.2), 4200 + i, device="cuda")
+        small.append((g, cq.Graph(ctx, g.row_ptr, g.col_idx, reorder=(i != 1))))
+    small_tasks = [(G, g.labels.contiguous(), g.num_labels) for g, G in small]
+    for tasks in (big_tasks + small_tasks, big_tasks):
+        b = cq.Batch(ctx, tasks, autotune=False, use_graph=True)
+        res = b.run_sync()
+        for i, (G, lab, L) in enumerate(tasks):
+            single, _, _ = cq.score_partition(G, lab, L)
+            single.pop("status")
+            r = dict(res[i])
+            r.pop("status")
+            assert r == single, f"task {i} of {len(tasks)}"
+        b.close()
+    o = oracle.score(big.row_ptr.cpu().numpy(), big.col_idx.cpu().numpy(), big_tasks[3][1].cpu().numpy(), big.num_labels,
+                     want_pairs=False)
+    b = cq.Batch(ctx, big_tasks, autotune=False)
+    check_score(b.run_sync()[3], o.result, "dealt batch task, 30 % reassigned")
+    b.close()
+
+
 def test_tuning_cache_and_errors(cq, ctx, tmp_path, monkeypatch):
     monkeypatch.setenv("CQ_TUNE_CACHE", str(tmp_path / "tune.jsonl"))
     graphs, tasks, _ = make_tasks(cq, ctx, ngraphs=3, seed=1300)
