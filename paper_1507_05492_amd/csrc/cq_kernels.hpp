@@ -723,6 +723,100 @@ __global__ __launch_bounds__(256) void k_perm_scatter(int n, const int32_t* __re
   if (bad) atomicOr(&ctl->flags, F_LABEL);
 }
 
+// The same move in two streaming passes, for graphs without column blocks: caller-order
+// labels scattered straight to their buckets land on random cache lines (one partial line
+// per 2-byte write over the whole label array).  Stored ids are cut into super-buckets of
+// 2^SB_SHIFT (2 MB of 16-bit labels, one XCD's L2).
+//   k_perm_split: a workgroup takes PS_NODES caller-order nodes, sorts them by super-bucket
+//   in LDS and writes each super-bucket's run, one claim per run, into that super-bucket's
+//   region of a 64-bit staging array: (super-bucket << 52) | (offset << 32) | label.
+//   k_perm_place: the workgroups of a super-bucket, all on one XCD, write its labels to
+//   their stored ids, random 2-byte writes inside one 2 MB range.
+// sid[u] is the stored id of caller node u (a bijection onto [0, n)), so super-bucket b
+// receives exactly min(2^SB_SHIFT, n - b * 2^SB_SHIFT) words.
+constexpr int SB_SHIFT = 20;
+constexpr u32 SB_MASK = (1u << SB_SHIFT) - 1u;
+constexpr int SB_MAX = 1024;  // super-buckets (n <= 2^30): one per thread of k_perm_split's scan
+constexpr int PS_NPT = 8;
+constexpr int PS_NODES = 1024 * PS_NPT;
+constexpr int PP_NPT = 16;
+constexpr u32 PP_PARTS = (1u << SB_SHIFT) / (1024u * PP_NPT);  // k_perm_place workgroups per super-bucket
+
+template <class LT>
+__global__ __launch_bounds__(1024) void k_perm_split(int n, const int32_t* __restrict__ labels, const u32* __restrict__ sid,
+                                                     int L, int nsb, u32* __restrict__ gcur,
+                                                     unsigned long long* __restrict__ stage, Ctl* __restrict__ ctl) {
+  __shared__ unsigned long long s_stage[PS_NODES];
+  __shared__ u32 s_cnt[SB_MAX], s_off[SB_MAX], s_base[SB_MAX];
+  __shared__ u32 s_w[SCAN_THREADS / 64];
+  const int tid = threadIdx.x;
+  const long long u0 = (long long)blockIdx.x * PS_NODES;
+  s_cnt[tid] = 0;
+  __syncthreads();
+  int c[PS_NPT];
+  u32 sv[PS_NPT];
+#pragma unroll
+  for (int k = 0; k < PS_NPT; ++k) {
+    const long long u = min(u0 + tid + (long long)k * 1024, (long long)n - 1);  // in bounds; masked below
+    c[k] = labels[u];
+    sv[k] = sid[u];
+  }
+  unsigned long long wd[PS_NPT];
+  u32 sb[PS_NPT], rank[PS_NPT];
+  u32 bad = 0;
+#pragma unroll
+  for (int k = 0; k < PS_NPT; ++k) {
+    sb[k] = 0xFFFFFFFFu;
+    if (u0 + tid + (long long)k * 1024 < (long long)n) {
+      const bool ok = (u32)c[k] < (u32)L;
+      bad |= ok ? 0u : 1u;
+      const u32 lab = ok ? (u32)(LT)c[k] : (u32)LabelT<LT>::SENTINEL;
+      sb[k] = sv[k] >> SB_SHIFT;
+      wd[k] = ((unsigned long long)sb[k] << 52) | ((unsigned long long)(sv[k] & SB_MASK) << 32) | lab;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < PS_NPT; ++k)
+    if (sb[k] != 0xFFFFFFFFu) rank[k] = atomicAdd(&s_cnt[sb[k]], 1u);
+  __syncthreads();
+  const u32 cnt = s_cnt[tid];
+  u32 total;
+  s_off[tid] = block_excl_scan_1024(cnt, s_w, &total);
+  s_base[tid] = (tid < nsb && cnt) ? atomicAdd(&gcur[tid], cnt) : 0u;  // one claim per run
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < PS_NPT; ++k)
+    if (sb[k] != 0xFFFFFFFFu) s_stage[s_off[sb[k]] + rank[k]] = wd[k];
+  __syncthreads();
+  for (u32 p = tid; p < total; p += 1024) {
+    const unsigned long long w = s_stage[p];
+    const u32 b = (u32)(w >> 52);
+    stage[((size_t)b << SB_SHIFT) + s_base[b] + (p - s_off[b])] = w;
+  }
+  if (bad) atomicOr(&ctl->flags, F_LABEL);
+}
+
+// Workgroup b runs on XCD b % 8 and takes part (b / 8) % PP_PARTS of super-bucket
+// b % 8 + 8 * ((b / 8) / PP_PARTS).
+template <class LT>
+__global__ __launch_bounds__(1024) void k_perm_place(int n, int nsb, const unsigned long long* __restrict__ stage,
+                                                     LT* __restrict__ labx) {
+  const u32 x = blockIdx.x % 8u, i = blockIdx.x / 8u;
+  const u32 b = x + 8u * (i / PP_PARTS), part = i % PP_PARTS;
+  if (b >= (u32)nsb) return;
+  const size_t s0 = (size_t)b << SB_SHIFT;
+  const u32 size = (u32)min((size_t)1 << SB_SHIFT, (size_t)n - s0);
+  const u32 e0 = part * 1024u * PP_NPT;
+  if (e0 >= size) return;
+  constexpr unsigned long long LMASK = sizeof(LT) == 2 ? 0xFFFFull : 0xFFFFFFFFull;
+  unsigned long long w[PP_NPT];
+#pragma unroll
+  for (int k = 0; k < PP_NPT; ++k) w[k] = stage[s0 + min(e0 + threadIdx.x + (u32)k * 1024u, size - 1u)];  // masked below
+#pragma unroll
+  for (int k = 0; k < PP_NPT; ++k)
+    if (e0 + threadIdx.x + (u32)k * 1024u < size) labx[s0 + (u32)((w[k] >> 32) & SB_MASK)] = (LT)(w[k] & LMASK);
+}
+
 template <class LT>
 __global__ __launch_bounds__(1024) void k_perm_apply(int n, const u32* __restrict__ bstart, const uint16_t* __restrict__ tgt,
                                                      const LT* __restrict__ tmp, LT* __restrict__ labx) {

@@ -67,6 +67,7 @@ struct cq_graph {
   uint16_t* lrank = nullptr;       // column-blocked graphs: node numbers and slots of the plan's chunks
   u32* spos = nullptr;
   u32* pbstart = nullptr;          // first slot of every bucket (nb + 1)
+  u32* sid = nullptr;              // graphs without column blocks: stored id of every caller node (k_perm_split)
   int perm_buckets = 0;
   const float* w = nullptr;        // edge weights in the stored entry order (borrowed or owned_w); null: unweighted
   float* owned_w = nullptr;
@@ -83,7 +84,7 @@ struct cq_graph {
     if (rpb) (void)hipFree(rpb);
     if (colb) (void)hipFree(colb);
     if (rowb) (void)hipFree(rowb);
-    for (u32* p : {deg_in, pos1, pbstart})
+    for (u32* p : {deg_in, pos1, pbstart, sid})
       if (p) (void)hipFree(p);
     if (tgt) (void)hipFree(tgt);
     if (lrank) (void)hipFree(lrank);
@@ -421,13 +422,30 @@ cq_status map_flags(cq_context* ctx, u32 flags) {
   return CQ_OK;
 }
 
-// Moves the caller's labels to the stored node order with the graph's bucket plan:
-// labx[stored id] = label, or the sentinel (flagged) when out of range.  tmp holds n
-// labels and may alias the per-node offsets, which are written only afterwards.
+// Moves the caller's labels to the stored node order: labx[stored id] = label, or the
+// sentinel (flagged) when out of range.  tmp holds n labels and may alias the per-node
+// offsets, which are written only afterwards.  scratch (scratch_bytes) is free workspace
+// (the staged-entry array, written only by the edge pass): with the graph's stored ids
+// and room for 8 bytes per node, the move takes the two streaming passes of
+// k_perm_split / k_perm_place; otherwise the bucket plan's scatter and per-bucket pass.
 template <class LT>
-void stage_labels(const cq_graph* g, const int32_t* labels, int32_t L, LT* tmp, LT* labx, Ctl* ctl, hipStream_t s) {
-  k_perm_scatter<LT><<<grid_for(g->n, 256 * 8, 8192), 256, 0, s>>>(g->n, labels, g->pos1, L, tmp, ctl);
-  k_perm_apply<LT><<<g->perm_buckets, 1024, ((size_t)1 << PERM_SHIFT) * sizeof(LT), s>>>(g->n, g->pbstart, g->tgt, tmp, labx);
+void stage_labels(const cq_graph* g, const int32_t* labels, int32_t L, LT* tmp, LT* labx, Ctl* ctl, void* scratch,
+                  size_t scratch_bytes, hipStream_t s) {
+  const int n = g->n;
+  const int nsb = (int)(((int64_t)n + SB_MASK) >> SB_SHIFT);
+  const size_t stage_bytes = 8 * ((size_t)nsb << SB_SHIFT);
+  if (g->sid && nsb <= SB_MAX && stage_bytes + 4 * (size_t)SB_MAX <= scratch_bytes) {
+    auto* stage = static_cast<unsigned long long*>(scratch);
+    u32* gcur = reinterpret_cast<u32*>(static_cast<char*>(scratch) + stage_bytes);
+    fill(gcur, (size_t)nsb, 0, s);
+    k_perm_split<LT><<<(unsigned)(((int64_t)n + PS_NODES - 1) / PS_NODES), 1024, 0, s>>>(n, labels, g->sid, L, nsb, gcur,
+                                                                                        stage, ctl);
+    const unsigned groups = (unsigned)((nsb + 7) / 8);
+    k_perm_place<LT><<<8u * PP_PARTS * groups, 1024, 0, s>>>(n, nsb, stage, labx);
+    return;
+  }
+  k_perm_scatter<LT><<<grid_for(n, 256 * 8, 8192), 256, 0, s>>>(n, labels, g->pos1, L, tmp, ctl);
+  k_perm_apply<LT><<<g->perm_buckets, 1024, ((size_t)1 << PERM_SHIFT) * sizeof(LT), s>>>(n, g->pbstart, g->tgt, tmp, labx);
 }
 
 // The scoring path with staged labels of type LT (u16 when num_labels <= 65535).
@@ -523,7 +541,8 @@ void score_launch(cq_context* ctx, const cq_graph* g, const int32_t* labels, int
       StageMark mk(ctx, ST_NODE, timed);
       // move the labels to the stored order first (streaming), then count in that order;
       // without a plan the first range's launch reads them and writes labx
-      if (g->pos1) stage_labels<LT>(g, labels, L, reinterpret_cast<LT*>(loc), labx, ctl, s);
+      if (g->pos1)
+        stage_labels<LT>(g, labels, L, reinterpret_cast<LT*>(loc), labx, ctl, CB, sizeof(LT) * (size_t)nnz, s);
       for (int64_t lb = 0; lb < L; lb += PRIV_MAX) {
         const int lr = (int)std::min<int64_t>(PRIV_MAX, L - lb);
         const size_t shm = 2 * (size_t)lr * 4;
@@ -545,7 +564,7 @@ void score_launch(cq_context* ctx, const cq_graph* g, const int32_t* labels, int
     {
       StageMark mk(ctx, ST_NODE, timed);
       if (g->pos1) {
-        stage_labels<LT>(g, labels, L, reinterpret_cast<LT*>(loc), labx, ctl, s);
+        stage_labels<LT>(g, labels, L, reinterpret_cast<LT*>(loc), labx, ctl, CB, sizeof(LT) * (size_t)nnz, s);
         k_node_global<true, LT, true><<<grid_for(n, 256, 8192), 256, 0, s>>>((int)n, labels, g->perm, g->rp, L, SZ, loc, labx,
                                                                             ctl);
       } else {
@@ -1015,6 +1034,8 @@ cq_status build_perm_plan(cq_context* ctx, cq_graph* g, const int32_t* newid, co
   if (g->rpb) {
     alloc((void**)&g->lrank, 2 * (size_t)n);
     alloc((void**)&g->spos, 4 * (size_t)n);
+  } else if (((int64_t)n + SB_MASK) >> SB_SHIFT <= SB_MAX) {
+    alloc((void**)&g->sid, 4 * (size_t)n);
   }
   alloc((void**)&bcnt, 4 * ((size_t)nb + 1));
   u32* bstart = g->pbstart;
@@ -1031,14 +1052,15 @@ cq_status build_perm_plan(cq_context* ctx, cq_graph* g, const int32_t* newid, co
     scan_u32(bcnt, bstart, nb, tiles, s);
     fill(bcnt, (size_t)nb + 1, 0, s);
     k_perm_plan<<<gp, 256, 8 * (size_t)nb, s>>>(n, newid, nb, bstart, bcnt, g->pos1, g->tgt, g->lrank, g->spos);
-    e = hipGetLastError();
+    if (g->sid) e = hipMemcpyAsync(g->sid, newid, 4 * (size_t)n, hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess) e = hipGetLastError();
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) st = fail(ctx, CQ_E_DEVICE, "building the label permutation plan: %s", hipGetErrorString(e));
   }
   for (void* p : {(void*)bcnt, (void*)tiles})
     if (p) (void)hipFree(p);
   if (st != CQ_OK) {
-    for (u32** p : {&g->deg_in, &g->pos1, &g->pbstart, &g->spos}) {
+    for (u32** p : {&g->deg_in, &g->pos1, &g->pbstart, &g->spos, &g->sid}) {
       if (*p) (void)hipFree(*p);
       *p = nullptr;
     }
@@ -1141,6 +1163,7 @@ cq_status build_locality_order(cq_context* ctx, cq_graph* g, const int32_t* rp, 
     if (g->rpb) g->owned_bytes += (int64_t)(4 * ((size_t)COL_BLOCKS * ((size_t)n + 1) + 1) + 8 * (size_t)nnz);
     if (g->pos1) g->owned_bytes += (int64_t)(10 * (size_t)n + 4 * ((size_t)g->perm_buckets + 1));
     if (g->lrank) g->owned_bytes += (int64_t)(6 * (size_t)n);
+    if (g->sid) g->owned_bytes += (int64_t)(4 * (size_t)n);
     if (g->owned_w) g->owned_bytes += (int64_t)(4 * (size_t)nnz);
     if (g->wb) g->owned_bytes += (int64_t)(4 * (size_t)nnz);
   }
