@@ -1840,6 +1840,9 @@ constexpr int GBLOCK = 512;
 // smaller workgroups, so that more communities are counted at once (a community's pass
 // is bound by its few dependent round trips, not by its thread count)
 constexpr int GBLOCK_DIRECT = 256;
+// Score group pass over label spaces beyond the direct table: its 128 KB LDS table holds
+// one workgroup per CU, so the workgroup takes every wave the CU can hold
+constexpr int GBLOCK_WIDE = 1024;
 constexpr int STACK = 96;
 constexpr u32 WIDE_FIX = 256;  // wrap corrections a 16-bit table can log per group
 
@@ -2358,7 +2361,7 @@ struct ScoreVis {
   // Reduces the threads' sums with one barrier (waves first, then the waves in order);
   // the caller's next barrier protects the LDS partials.
   __device__ void finish(State& st, u32 g) {
-    __shared__ u64 r_lo[GBLOCK / 64], r_hi[GBLOCK / 64], r_np[GBLOCK / 64];
+    __shared__ u64 r_lo[GBLOCK_WIDE / 64], r_hi[GBLOCK_WIDE / 64], r_np[GBLOCK_WIDE / 64];  // up to 16 waves
     const u128 pen = wave_sum_u128(st.pen.value());
     const u64 np = wave_sum_u64(st.np);
     const int w = threadIdx.x >> 6;

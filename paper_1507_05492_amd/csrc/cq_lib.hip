@@ -668,16 +668,15 @@ void score_launch(cq_context* ctx, const cq_graph* g, const int32_t* labels, int
     // direct tables the split costs more than it gains: the large groups' tail no longer
     // overlaps the small ones.
     // Direct tables (the batch's label spaces too) take workgroups of GBLOCK_DIRECT
-    // threads, larger label spaces GBLOCK; a label count always takes the same size, so
-    // a task scores the same bits alone and in a batch (each thread sums its own visits).
+    // threads, larger label spaces GBLOCK_WIDE; a label count always takes the same size,
+    // so a task scores the same bits alone and in a batch (each thread sums its own visits).
     const bool waves = sizeof(LT) == 2 && L > DIRECT_MAX;
     if (L <= DIRECT_MAX)
       k_groups<ScoreVis, LT, GBLOCK_DIRECT><<<group_grid<ScoreVis, LT, GBLOCK_DIRECT>(ctx, lds), GBLOCK_DIRECT, lds, s>>>(
           CB, start, D, order, ctl, (u32)L, lds_words, vis, cur64, at<u32>(ws, lay.wq), false);
     else
-      k_groups<ScoreVis, LT><<<group_grid<ScoreVis, LT>(ctx, lds), GBLOCK, lds, s>>>(CB, start, D, order, ctl, (u32)L,
-                                                                                   lds_words, vis, cur64,
-                                                                                   at<u32>(ws, lay.wq), waves);
+      k_groups<ScoreVis, LT, GBLOCK_WIDE><<<group_grid<ScoreVis, LT, GBLOCK_WIDE>(ctx, lds), GBLOCK_WIDE, lds, s>>>(
+          CB, start, D, order, ctl, (u32)L, lds_words, vis, cur64, at<u32>(ws, lay.wq), waves);
     if (waves) {
       int nb = 0;
       if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_groups_wave<ScoreVis>, 64 * GW_WAVES, 0) != hipSuccess || nb < 1)
@@ -1667,10 +1666,10 @@ cq_status cq_context_create(int device, void* hip_stream, cq_context** out) {
   set_big_lds(reinterpret_cast<const void*>(k_hist_priv), PRIV_MAX * 4);
   set_big_lds(reinterpret_cast<const void*>(k_perm_plan), 8 * (size_t)PERM_MAX_BUCKETS);
   set_big_lds(reinterpret_cast<const void*>(k_perm_apply_count), ((size_t)1 << PERM_SHIFT) * 2 + 8 * (size_t)APPLY_COUNT_MAX_L);
-  set_big_lds(reinterpret_cast<const void*>(k_groups<ScoreVis, uint16_t>), gl);
+  set_big_lds(reinterpret_cast<const void*>(k_groups<ScoreVis, uint16_t, GBLOCK_WIDE>), gl);
   set_big_lds(reinterpret_cast<const void*>(k_groups_w<uint16_t>), gl);
   set_big_lds(reinterpret_cast<const void*>(k_groups_w<uint32_t>), gl);
-  set_big_lds(reinterpret_cast<const void*>(k_groups<ScoreVis, uint32_t>), gl);
+  set_big_lds(reinterpret_cast<const void*>(k_groups<ScoreVis, uint32_t, GBLOCK_WIDE>), gl);
   set_big_lds(reinterpret_cast<const void*>(k_groups<CmpVis, uint16_t>), gl);
   set_big_lds(reinterpret_cast<const void*>(k_groups<CmpVis, uint32_t>), gl);
   set_big_lds(reinterpret_cast<const void*>(k_b_node), 2 * PRIV_MAX * 4);
