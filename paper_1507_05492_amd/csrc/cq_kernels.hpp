@@ -3156,6 +3156,7 @@ __global__ void k_cmp_final2(int G, const CmpPart* __restrict__ parts, long long
 // the whole group.  Batched tasks use LDS-private histograms and 16-bit labels
 // (num_labels <= 16384).
 constexpr int BATCH_FUSE = 4;
+constexpr int BG_UNROLL = 4;  // entries per thread in flight in the batched edge pass
 
 struct TaskDev {
   const int32_t* labels;
@@ -3308,20 +3309,36 @@ __global__ __launch_bounds__(R) void k_b_gather(const GroupDev* __restrict__ gd,
 #pragma unroll
   for (int p = 0; p < BATCH_FUSE; ++p) cb[p] = p < grp.np ? td[grp.task[p]].CB : nullptr;
   const int e0 = s_rs[0], e1 = s_rs[rows];
-  for (int e = e0 + tid; e < e1; e += R) {
-    int lo = 0, hi = rows - 1;
-    while (lo < hi) {
-      int mid = (lo + hi + 1) >> 1;
-      if (s_rs[mid] <= e) lo = mid; else hi = mid - 1;
-    }
-    const int v = grp.col[e];
-    const u32 off = (u32)(e - s_rs[lo]);
-    const unsigned long long w = il[v];  // the neighbour's label in every partition: one load
+  // BG_UNROLL entries per thread at a time: their row searches (a fixed number of steps)
+  // and their loads are all issued before the first label is used
+  int top = 0;  // largest power of two below rows (0 for one row)
+  if (rows > 1) top = 1 << (31 - __clz(rows - 1));
+  for (int eb = e0 + tid; eb < e1; eb += BG_UNROLL * R) {
+    int lo[BG_UNROLL], v[BG_UNROLL];
 #pragma unroll
-    for (int p = 0; p < BATCH_FUSE; ++p) {
-      if (p < grp.np) {
-        const u32 b = s_base[p][lo];
-        if (b != SENT) cb[p][b + off] = (uint16_t)(w >> (16 * p));
+    for (int k = 0; k < BG_UNROLL; ++k) {
+      const int e = min(eb + k * R, e1 - 1);  // in bounds; masked below
+      int l = 0;  // last row r with s_rs[r] <= e
+      for (int st = top; st > 0; st >>= 1)
+        if (l + st < rows && s_rs[l + st] <= e) l += st;
+      lo[k] = l;
+      v[k] = grp.col[e];
+    }
+    unsigned long long w[BG_UNROLL];
+#pragma unroll
+    for (int k = 0; k < BG_UNROLL; ++k) w[k] = il[v[k]];  // the neighbour's labels in every partition: one load
+#pragma unroll
+    for (int k = 0; k < BG_UNROLL; ++k) {
+      const int e = eb + k * R;
+      if (e < e1) {
+        const u32 off = (u32)(e - s_rs[lo[k]]);
+#pragma unroll
+        for (int p = 0; p < BATCH_FUSE; ++p) {
+          if (p < grp.np) {
+            const u32 b = s_base[p][lo[k]];
+            if (b != SENT) cb[p][b + off] = (uint16_t)(w[k] >> (16 * p));
+          }
+        }
       }
     }
   }
