@@ -3345,37 +3345,42 @@ __global__ __launch_bounds__(R) void k_b_gather(const GroupDev* __restrict__ gd,
 }
 
 // The group pass's items as one list: item i (Kpre[t] <= i < Kpre[t+1]) is group
-// order_t[i - Kpre[t]] of task t, packed as (t << 14) | group (groups < 16384 in a batch),
-// so that the persistent pass needs one load per item instead of a search over Kpre.
+// g = order_t[i - Kpre[t]] of task t, written as ((t << 14) | g, start_t[g], D_t[g], 0)
+// (groups < 16384 in a batch), so that the persistent pass reaches a community's segment
+// with one load after its ticket instead of a search over Kpre and two dependent loads.
 __global__ __launch_bounds__(256) void k_b_items(const TaskDev* __restrict__ td, const u32* __restrict__ Kpre, int T,
-                                                 u32* __restrict__ items) {
+                                                 uint4* __restrict__ items) {
   const u32 total = Kpre[T];
   for (u32 i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) {
     const int t = find_seg(Kpre, T, i);
-    items[i] = ((u32)t << 14) | td[t].order[i - Kpre[t]];
+    const TaskDev& d = td[t];
+    const u32 g = d.order[i - Kpre[t]];
+    items[i] = make_uint4(((u32)t << 14) | g, d.start[g], d.D[g], 0u);
   }
 }
 
 // Persistent group pass over the communities of every task (per-XCD work queues, wq_next),
 // in workgroups of GBLOCK_DIRECT threads, as a single call with the same label count.
 __global__ __launch_bounds__(GBLOCK_DIRECT, 8) void k_b_groups(const TaskDev* __restrict__ td, const u32* __restrict__ Kpre, int T,
-                                                     u32* __restrict__ wq, u32 lds_words, const u32* __restrict__ items) {
-  __shared__ u32 s_item, s_tg;
+                                                     u32* __restrict__ wq, u32 lds_words, const uint4* __restrict__ items) {
+  __shared__ u32 s_item;
+  __shared__ uint4 s_it;
   const u32 total = Kpre[T];
   u32 q = blockIdx.x % WQ_QUEUES, left = WQ_QUEUES;  // thread 0's queue state (see wq_next)
   for (;;) {
     if (threadIdx.x == 0) {
       const u32 it = wq_next(wq, total, q, left);
       s_item = it;
-      s_tg = it < total ? items[it] : 0u;
+      s_it = it < total ? items[it] : make_uint4(0u, 0u, 0u, 0u);
     }
     __syncthreads();
-    const u32 item = s_item, tg = s_tg;
+    const u32 item = s_item;
+    const uint4 x = s_it;
     __syncthreads();
     if (item >= total) break;
-    const int t = (int)(tg >> 14);
+    const int t = (int)(x.x >> 14);
     const TaskDev& d = td[t];
-    const u32 g = tg & 0x3FFFu;
+    const u32 g = x.x & 0x3FFFu;
     ScoreVis vis;
     vis.N = d.N;
     vis.twom = (double)d.nnz;
@@ -3387,7 +3392,7 @@ __global__ __launch_bounds__(GBLOCK_DIRECT, 8) void k_b_groups(const TaskDev* __
     vis.ecnt = nullptr;
     vis.ecap = 0;
     vis.ctl = d.ctl;
-    group_one<ScoreVis, uint16_t, GBLOCK_DIRECT>(d.CB, d.start[g], d.D[g], g, (u32)d.L, lds_words, vis, d.ctl);
+    group_one<ScoreVis, uint16_t, GBLOCK_DIRECT>(d.CB, x.y, x.z, g, (u32)d.L, lds_words, vis, d.ctl);
   }
 }
 

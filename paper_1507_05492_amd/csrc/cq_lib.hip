@@ -110,7 +110,7 @@ struct cq_batch_plan {
   void* td = nullptr;  // cq::TaskDev[T]
   void* gd = nullptr;  // cq::GroupDev[ngroups]
   uint32_t *Wpre = nullptr, *Lpre = nullptr, *Gpre = nullptr, *Kpre = nullptr, *wq = nullptr;
-  uint32_t* items = nullptr;  // (task << 14) | group of every item of the group pass (in the workspace)
+  uint4* items = nullptr;  // ((task << 14) | group, segment start, length, 0) of every item of the group pass (workspace)
   uint32_t* RBpre[3] = {nullptr, nullptr, nullptr};  // per gather tile size: per XCD, tile prefixes over its groups
   uint32_t* XG[3] = {nullptr, nullptr, nullptr};     // per gather tile size: per XCD, its groups
   std::vector<size_t> il_off;  // per group: workspace offset of its interleaved labels
@@ -1388,7 +1388,7 @@ void batch_fill_tables(cq_batch_plan* p, void* d_ws, cq_score_result* d_results,
   p->Lsum = Lpre[T];
   p->Gsum = Gpre[T];
   p->ws = d_ws;
-  p->items = reinterpret_cast<uint32_t*>(static_cast<char*>(d_ws) + p->items_off);
+  p->items = reinterpret_cast<uint4*>(static_cast<char*>(d_ws) + p->items_off);
   p->d_results = d_results;
 }
 
@@ -1406,7 +1406,7 @@ void batch_layout(cq_batch_plan* p) {
     p->maxL = std::max(p->maxL, (int)t.num_labels);
     labels_total += (size_t)t.num_labels;
   }
-  p->items_off = c.take(4 * labels_total);  // at most one item per label id of every task
+  p->items_off = c.take(16 * labels_total);  // at most one item per label id of every task
   std::map<const cq_graph*, int> open;
   for (int i = 0; i < (int)p->tasks.size(); ++i) {
     auto it = open.find(p->tasks[i].graph);

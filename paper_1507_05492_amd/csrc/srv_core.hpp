@@ -54,14 +54,14 @@ inline size_t req_footprint(const Req& r) {
 }
 
 // Device bytes of small scoring requests run as one batched launch: every request's
-// labels, the workspaces and the group pass's item list (4 bytes per label id), the
+// labels, the workspaces and the group pass's item list (16 bytes per label id), the
 // results.
 inline size_t group_footprint(const std::vector<Req*>& g) {
   size_t lab = 0, ws = 0, items = 0;
   for (const Req* r : g) {
     lab += aup(4 * (size_t)r->n);
     ws += aup(r->group_ws);
-    items += 4 * (size_t)r->L;
+    items += 16 * (size_t)r->L;
   }
   return lab + aup(ws + aup(items)) + aup(sizeof(cq_score_result) * g.size());
 }

@@ -54,7 +54,7 @@ using cqsrv::Clock;
 using cqsrv::Req;
 
 // Footprints restated from their definitions (labels, workspace, result; a group adds the
-// item list of 4 bytes per label id), independent of the scheduler's helpers.
+// item list of 16 bytes per label id), independent of the scheduler's helpers.
 static size_t foot_alone(const Req& r) {
   const size_t lab = (r.kind == 0 ? 1 : 2) * aup(4 * (size_t)r.n);
   const size_t res = r.kind == 0 ? sizeof(cq_score_result) : sizeof(cq_compare_result);
@@ -65,7 +65,7 @@ static size_t foot_group(const std::vector<Req*>& g) {
   for (const Req* r : g) {
     lab += aup(4 * (size_t)r->n);
     ws += aup(r->group_ws);
-    items += 4 * (size_t)r->L;
+    items += 16 * (size_t)r->L;
   }
   return lab + aup(ws + aup(items)) + aup(sizeof(cq_score_result) * g.size());
 }
