@@ -1313,9 +1313,13 @@ __device__ __forceinline__ void gather_rows(long long r0, int n, const int32_t* 
   }
 }
 
-// Workgroups take tiles of GROWS rows in turn (grid-stride).  gate (optional): the launch
-// does nothing unless gate->mode == STAGE_ROWS (a column-blocked graph scored through its
-// row-major copy; see k_colscan_rows).
+// Tiles of GROWS rows.  With one workgroup per tile (grid of 8 * ceil(tiles / 8)),
+// workgroup b runs on XCD b % 8 and takes tile (b % 8) * ceil(tiles / 8) + b / 8: each
+// XCD walks its own eighth of the rows in order, so the labels that neighbouring rows
+// share stay in its L2 (the 100M-node graph's edge pass: 7.63 -> 7.40 ms).  A smaller
+// grid takes the tiles in turn (grid-stride).  gate (optional): the launch does nothing
+// unless gate->mode == STAGE_ROWS (a column-blocked graph scored through its row-major
+// copy; see k_colscan_rows).
 template <bool PRIV, class LT, bool WT>
 __global__ __launch_bounds__(GROWS) void k_gather(int n, const int32_t* __restrict__ rp, const int32_t* __restrict__ col,
                                                   const LT* __restrict__ labx, int L, int chunk, const u32* __restrict__ PM,
@@ -1326,6 +1330,12 @@ __global__ __launch_bounds__(GROWS) void k_gather(int n, const int32_t* __restri
   __shared__ u32 s_base[GROWS];
   if (gate && gate->mode != STAGE_ROWS) return;
   const long long tiles = ((long long)n + GROWS - 1) / GROWS;
+  const long long per = (tiles + 7) / 8;
+  if (gridDim.x >= 8 * per) {
+    const long long t = (long long)(blockIdx.x % 8u) * per + blockIdx.x / 8u;
+    if (t < tiles) gather_rows<PRIV, LT, WT>(t * GROWS, n, rp, col, labx, L, chunk, PM, start, loc, CB, w, CW, s_rs, s_base);
+    return;
+  }
   for (long long t = blockIdx.x; t < tiles; t += gridDim.x) {
     gather_rows<PRIV, LT, WT>(t * GROWS, n, rp, col, labx, L, chunk, PM, start, loc, CB, w, CW, s_rs, s_base);
     __syncthreads();  // the next tile's row starts replace this one's

@@ -601,7 +601,7 @@ void score_launch(cq_context* ctx, const cq_graph* g, const int32_t* labels, int
                                                        nullptr, ctl);
       }
     } else {
-      const unsigned grid = grid_for(n, GROWS, 1u << 30);
+      const unsigned grid = 8u * (unsigned)((((int64_t)n + GROWS - 1) / GROWS + 7) / 8);  // one workgroup per tile
       if (lay.priv && CW)
         k_gather<true, LT, true><<<grid, GROWS, 0, s>>>((int)n, g->rp, g->col, labx, L, lay.chunk, PM, start, loc, CB, g->w, CW);
       else if (lay.priv)
