@@ -240,6 +240,8 @@ int pick_chunk(int64_t n, int64_t max_chunk = 65536, int64_t min_chunk = 1024) {
 }
 // Node chunk limit when the labels span several LDS ranges (the histogram rows are W x L).
 constexpr int64_t RANGE_CHUNK_MAX = 1 << 18;
+// Workgroups of a scoring node pass over several label ranges: the CUs of the GPU
+constexpr int64_t RANGE_WGS = 256;
 // The caller-order node pass of column-blocked graphs (k_node_perm) is bound by its
 // scattered label stores and gains from more, smaller workgroups; its column scan only
 // needs totals, so the extra histogram rows cost little.
@@ -267,7 +269,10 @@ ScoreLayout score_layout(int64_t n, int64_t nnz, int64_t L, bool weighted = fals
   s.small = L <= 65535;
   const size_t lt = s.small ? 2 : 4;
   // several label ranges: fewer, larger node chunks keep the W x L histogram rows small
-  s.chunk = pick_chunk(n, L > PRIV_MAX ? RANGE_CHUNK_MAX : std::max(max_chunk, min_chunk), min_chunk);
+  // several label ranges: one workgroup per CU holds a range's LDS histograms, so the
+  // nodes are cut into at most RANGE_WGS chunks (one wave of workgroups, no tail)
+  s.chunk = L > PRIV_MAX ? (int)std::max<int64_t>(1024, ((n + RANGE_WGS - 1) / RANGE_WGS + 1023) / 1024 * 1024)
+                         : pick_chunk(n, std::max(max_chunk, min_chunk), min_chunk);
   s.W = (int)((n + s.chunk - 1) / s.chunk);
   s.G = (int)std::min<int64_t>(128, std::max<int64_t>(1, (L + 1023) / 1024));
   s.ctl = c.take(sizeof(Ctl));
