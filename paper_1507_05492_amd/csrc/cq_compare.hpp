@@ -225,7 +225,7 @@ __global__ __launch_bounds__(1024) void k_cmp_bands(int La, const u32* __restric
 }
 
 constexpr int CP_THREADS = 1024;
-constexpr int CP_NPT = 16;                        // nodes per thread
+constexpr int CP_NPT = 20;                        // nodes per thread (at 10M nodes: 489 workgroups, two waves at one per CU)
 constexpr int CP_CHUNK = CP_THREADS * CP_NPT;     // nodes per workgroup of k_cmp_part
 
 // Exclusive scan of v[0, m) in LDS by one 1024-thread workgroup (m <= 4 * 1024); returns
