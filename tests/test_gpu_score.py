@@ -7,7 +7,7 @@ import pytest
 import torch
 
 import oracle
-from cqgen import CONFIGS, csr_from_edges, erdos_renyi, lfr_graph, perturb_labels, random_labels, star_graph
+from cqgen import CONFIGS, LFRParams, csr_from_edges, erdos_renyi, lfr_graph, perturb_labels, random_labels, star_graph
 from tests.gpu_util import check_per_community, check_score, note, sort_rows
 
 pytestmark = pytest.mark.gpu
@@ -264,6 +264,32 @@ def test_errors(cq, ctx, reorder):
     with pytest.raises(cq.CQError) as e:
         cq.score_partition(g0, torch.zeros(4, dtype=torch.int32, device="cuda"), 1)
     assert e.value.status == cq.CQ_E_NO_EDGES
+
+
+def test_unblocked_label_moves(cq, ctx):
+    """A renumbered graph of more than 2^20 nodes stored without column blocks moves the
+    caller's labels to the stored order in two passes (by super-bucket of 2^20 stored ids,
+    the last one partial): the result equals the input-order graph's bit for bit and the
+    oracle's; a label out of range, on either side of a super-bucket boundary, is
+    reported."""
+    n = (1 << 20) + 300_001
+    g = lfr_graph(LFRParams(n, 6, 30, 2.0, 1.0, 20, 200, 0.3), 4500, device="cuda")
+    Gu = open_graph(cq, ctx, g.row_ptr, g.col_idx, "unblocked")
+    Gi = open_graph(cq, ctx, g.row_ptr, g.col_idx, "input")
+    lab = perturb_labels(g.labels, g.num_labels, 0.15, 4501).contiguous()
+    note("unblocked 1.35M-node graph: 15 % reassigned")
+    ru, _, _ = cq.score_partition(Gu, lab, g.num_labels)
+    ri, _, _ = cq.score_partition(Gi, lab, g.num_labels)
+    assert ru == ri
+    o = oracle.score(g.row_ptr.cpu().numpy(), g.col_idx.cpu().numpy(), lab.cpu().numpy(), g.num_labels, want_pairs=False)
+    check_score(ru, o.result, "unblocked 1.35M-node graph")
+    for u in (0, (1 << 20) - 1, 1 << 20, n - 1):
+        bad = lab.clone()
+        bad[u] = g.num_labels
+        r, _, _ = cq.score_partition(Gu, bad, g.num_labels, allow=(cq.CQ_E_LABEL_RANGE,))
+        assert r["status"] == cq.CQ_E_LABEL_RANGE, u
+    Gu.close()
+    Gi.close()
 
 
 @pytest.mark.parametrize("pct", [0, 30])
