@@ -1850,6 +1850,9 @@ constexpr int GBLOCK = 512;
 // smaller workgroups, so that more communities are counted at once (a community's pass
 // is bound by its few dependent round trips, not by its thread count)
 constexpr int GBLOCK_DIRECT = 256;
+// ... and 128 threads for label spaces of at most SMALL_L_MAX ids, whose tables are short
+constexpr int GBLOCK_SMALL = 128;
+constexpr u32 SMALL_L_MAX = 4096;
 // Score group pass over label spaces beyond the direct table: its 128 KB LDS table holds
 // one workgroup per CU, so the workgroup takes every wave the CU can hold
 constexpr int GBLOCK_WIDE = 1024;
@@ -3216,7 +3219,7 @@ __global__ void k_b_setup(int T, const TaskDev* __restrict__ td, u32* __restrict
     for (int i = threadIdx.x; i < (int)(sizeof(Ctl) / 4); i += blockDim.x) c[i] = 0;
   }
   if (t == 0)
-    for (u32 i = threadIdx.x; i < WQ_WORDS; i += blockDim.x) wq[i] = 0;
+    for (u32 i = threadIdx.x; i < 2 * WQ_WORDS; i += blockDim.x) wq[i] = 0;  // both group passes' queues
 }
 
 // Node pass over every task's chunks.  Workgroup b runs on XCD b % 8 and takes entry
@@ -3370,9 +3373,13 @@ __global__ __launch_bounds__(256) void k_b_items(const TaskDev* __restrict__ td,
 }
 
 // Persistent group pass over the communities of every task (per-XCD work queues, wq_next),
-// in workgroups of GBLOCK_DIRECT threads, as a single call with the same label count.
-__global__ __launch_bounds__(GBLOCK_DIRECT, 8) void k_b_groups(const TaskDev* __restrict__ td, const u32* __restrict__ Kpre, int T,
-                                                     u32* __restrict__ wq, u32 lds_words, const uint4* __restrict__ items) {
+// in workgroups of NT threads, as a single call with the same label count: one launch
+// (NT = GBLOCK_SMALL, small != 0) takes the communities of tasks with at most SMALL_L_MAX
+// label ids and skips the others, a second one (NT = GBLOCK_DIRECT) the rest.
+template <int NT>
+__global__ __launch_bounds__(NT, 8) void k_b_groups(const TaskDev* __restrict__ td, const u32* __restrict__ Kpre, int T,
+                                                    u32* __restrict__ wq, u32 lds_words, const uint4* __restrict__ items,
+                                                    int small) {
   __shared__ u32 s_item;
   __shared__ uint4 s_it;
   const u32 total = Kpre[T];
@@ -3390,6 +3397,7 @@ __global__ __launch_bounds__(GBLOCK_DIRECT, 8) void k_b_groups(const TaskDev* __
     if (item >= total) break;
     const int t = (int)(x.x >> 14);
     const TaskDev& d = td[t];
+    if (((u32)d.L <= SMALL_L_MAX) != (small != 0)) continue;  // the other launch's community
     const u32 g = x.x & 0x3FFFu;
     ScoreVis vis;
     vis.N = d.N;
@@ -3402,7 +3410,7 @@ __global__ __launch_bounds__(GBLOCK_DIRECT, 8) void k_b_groups(const TaskDev* __
     vis.ecnt = nullptr;
     vis.ecap = 0;
     vis.ctl = d.ctl;
-    group_one<ScoreVis, uint16_t, GBLOCK_DIRECT>(d.CB, x.y, x.z, g, (u32)d.L, lds_words, vis, d.ctl);
+    group_one<ScoreVis, uint16_t, NT>(d.CB, x.y, x.z, g, (u32)d.L, lds_words, vis, d.ctl);
   }
 }
 

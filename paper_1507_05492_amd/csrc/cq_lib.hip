@@ -104,6 +104,7 @@ struct cq_batch_plan {
   std::vector<std::array<int, 4>> groups;
   std::vector<int> group_np;
   int maxL = 1;
+  int nsmall = 0;  // tasks with at most SMALL_L_MAX labels (the 128-thread group pass)
   // device tables (owned)
   void* d_tab = nullptr;
   size_t tab_bytes = 0;
@@ -672,11 +673,15 @@ void score_launch(cq_context* ctx, const cq_graph* g, const int32_t* labels, int
     // the same pass in every storage; batches (num_labels <= 16384) never split.  With
     // direct tables the split costs more than it gains: the large groups' tail no longer
     // overlaps the small ones.
-    // Direct tables (the batch's label spaces too) take workgroups of GBLOCK_DIRECT
-    // threads, larger label spaces GBLOCK_WIDE; a label count always takes the same size,
-    // so a task scores the same bits alone and in a batch (each thread sums its own visits).
+    // Direct tables (the batch's label spaces too) take workgroups of GBLOCK_SMALL
+    // threads up to SMALL_L_MAX labels and GBLOCK_DIRECT beyond, larger label spaces
+    // GBLOCK_WIDE; a label count always takes the same size, so a task scores the same
+    // bits alone and in a batch (each thread sums its own visits).
     const bool waves = sizeof(LT) == 2 && L > DIRECT_MAX;
-    if (L <= DIRECT_MAX)
+    if (L <= (int32_t)SMALL_L_MAX)
+      k_groups<ScoreVis, LT, GBLOCK_SMALL><<<group_grid<ScoreVis, LT, GBLOCK_SMALL>(ctx, lds), GBLOCK_SMALL, lds, s>>>(
+          CB, start, D, order, ctl, (u32)L, lds_words, vis, cur64, at<u32>(ws, lay.wq), false);
+    else if (L <= DIRECT_MAX)
       k_groups<ScoreVis, LT, GBLOCK_DIRECT><<<group_grid<ScoreVis, LT, GBLOCK_DIRECT>(ctx, lds), GBLOCK_DIRECT, lds, s>>>(
           CB, start, D, order, ctl, (u32)L, lds_words, vis, cur64, at<u32>(ws, lay.wq), false);
     else
@@ -1197,8 +1202,19 @@ void batch_launch(cq_batch_plan* p, hipStream_t s, int rsel, int occ) {
     default: k_b_gather<512><<<p->RBsum[2], 512, 0, s>>>(gd, p->RBpre[2], p->XG[2], ng, td); break;
   }
   const u32 lds_words = std::max<u32>(((u32)p->maxL + 3u) & ~3u, 128u);
-  k_b_groups<<<(unsigned)(p->ctx->num_cus * occ), GBLOCK_DIRECT, (size_t)lds_words * 4, s>>>(td, p->Kpre, T, p->wq, lds_words,
-                                                                                      p->items);
+  // tasks of at most SMALL_L_MAX labels in 128-thread workgroups (twice the blocks per CU
+  // of the tuned setting, within what fits), the others in 256-thread ones
+  if (p->nsmall > 0) {
+    int nb = 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_b_groups<GBLOCK_SMALL>, GBLOCK_SMALL, (size_t)lds_words * 4) !=
+            hipSuccess || nb < 1)
+      nb = 1;
+    k_b_groups<GBLOCK_SMALL><<<(unsigned)(p->ctx->num_cus * std::min(2 * occ, nb)), GBLOCK_SMALL, (size_t)lds_words * 4, s>>>(
+        td, p->Kpre, T, p->wq, lds_words, p->items, 1);
+  }
+  if (p->nsmall < T)
+    k_b_groups<GBLOCK_DIRECT><<<(unsigned)(p->ctx->num_cus * occ), GBLOCK_DIRECT, (size_t)lds_words * 4, s>>>(
+        td, p->Kpre, T, p->wq + WQ_WORDS, lds_words, p->items, 0);
   k_b_final1<<<p->Gsum, FBLOCK, 0, s>>>(td, p->Gpre, T);
   k_b_final2<<<grid_for(T, 64, 1u << 20), 64, 0, s>>>(td, T);
 }
@@ -1217,7 +1233,7 @@ BatchTabLayout batch_tab_layout(int T, int ng) {
   l.L = c.take(4 * (T + 1));
   l.G = c.take(4 * (T + 1));
   l.K = c.take(4 * (T + 1));
-  l.tk = c.take(WQ_BYTES);
+  l.tk = c.take(2 * WQ_BYTES);  // work queues of the two group passes
   for (int r = 0; r < 3; ++r) {
     l.RB[r] = c.take(4 * 8 * ((size_t)ng + 1));
     l.XG[r] = c.take(4 * 16 * (size_t)std::max(ng, 1));  // groups, then first tiles
@@ -1300,7 +1316,7 @@ void batch_fill_tables(cq_batch_plan* p, void* d_ws, cq_score_result* d_results,
   u32* Kpre = reinterpret_cast<u32*>(hb + tl.K);
   Wpre[0] = Lpre[0] = Gpre[0] = 0;
   for (int t = 0; t <= T; ++t) Kpre[t] = 0;
-  std::memset(hb + tl.tk, 0, WQ_BYTES);
+  std::memset(hb + tl.tk, 0, 2 * WQ_BYTES);
   for (int t = 0; t < T; ++t) {
     const cq_batch_task& bt = p->tasks[t];
     const cq_graph* g = bt.graph;
@@ -1403,12 +1419,14 @@ void batch_layout(cq_batch_plan* p) {
   p->groups.clear();
   p->group_np.clear();
   p->maxL = 1;
+  p->nsmall = 0;
   Carve c;
   size_t labels_total = 0;
   for (const auto& t : p->tasks) {
     const ScoreLayout lay = batch_task_layout(t.graph->n, t.graph->nnz, t.num_labels);
     p->ws_off.push_back(c.take(lay.total));
     p->maxL = std::max(p->maxL, (int)t.num_labels);
+    if ((u32)t.num_labels <= SMALL_L_MAX) ++p->nsmall;
     labels_total += (size_t)t.num_labels;
   }
   p->items_off = c.take(16 * labels_total);  // at most one item per label id of every task
@@ -1431,7 +1449,8 @@ void batch_layout(cq_batch_plan* p) {
 int batch_max_occ(cq_batch_plan* p) {
   const u32 lds_words = std::max<u32>(((u32)p->maxL + 3u) & ~3u, 128u);
   int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_b_groups, GBLOCK_DIRECT, (size_t)lds_words * 4) != hipSuccess ||
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_b_groups<GBLOCK_DIRECT>, GBLOCK_DIRECT, (size_t)lds_words * 4) !=
+          hipSuccess ||
       nb < 1)
     nb = 1;
   return nb;
@@ -1678,7 +1697,8 @@ cq_status cq_context_create(int device, void* hip_stream, cq_context** out) {
   set_big_lds(reinterpret_cast<const void*>(k_groups<CmpVis, uint16_t>), gl);
   set_big_lds(reinterpret_cast<const void*>(k_groups<CmpVis, uint32_t>), gl);
   set_big_lds(reinterpret_cast<const void*>(k_b_node), 2 * PRIV_MAX * 4);
-  set_big_lds(reinterpret_cast<const void*>(k_b_groups), gl);
+  set_big_lds(reinterpret_cast<const void*>(k_b_groups<GBLOCK_DIRECT>), gl);
+  set_big_lds(reinterpret_cast<const void*>(k_b_groups<GBLOCK_SMALL>), gl);
   *out = ctx;
   return CQ_OK;
 }
