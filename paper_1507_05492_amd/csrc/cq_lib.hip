@@ -678,12 +678,17 @@ void score_launch(cq_context* ctx, const cq_graph* g, const int32_t* labels, int
     // GBLOCK_WIDE; a label count always takes the same size, so a task scores the same
     // bits alone and in a batch (each thread sums its own visits).
     const bool waves = sizeof(LT) == 2 && L > DIRECT_MAX;
+    // (no more persistent workgroups than communities can be: a small graph's call would
+    // otherwise launch thousands that find the queues empty)
+    const unsigned lcap = (unsigned)std::max<int64_t>(1, L);
     if (L <= (int32_t)SMALL_L_MAX)
-      k_groups<ScoreVis, LT, GBLOCK_SMALL><<<group_grid<ScoreVis, LT, GBLOCK_SMALL>(ctx, lds), GBLOCK_SMALL, lds, s>>>(
-          CB, start, D, order, ctl, (u32)L, lds_words, vis, cur64, at<u32>(ws, lay.wq), false);
+      k_groups<ScoreVis, LT, GBLOCK_SMALL><<<std::min(group_grid<ScoreVis, LT, GBLOCK_SMALL>(ctx, lds), lcap), GBLOCK_SMALL,
+                                             lds, s>>>(CB, start, D, order, ctl, (u32)L, lds_words, vis, cur64,
+                                                       at<u32>(ws, lay.wq), false);
     else if (L <= DIRECT_MAX)
-      k_groups<ScoreVis, LT, GBLOCK_DIRECT><<<group_grid<ScoreVis, LT, GBLOCK_DIRECT>(ctx, lds), GBLOCK_DIRECT, lds, s>>>(
-          CB, start, D, order, ctl, (u32)L, lds_words, vis, cur64, at<u32>(ws, lay.wq), false);
+      k_groups<ScoreVis, LT, GBLOCK_DIRECT><<<std::min(group_grid<ScoreVis, LT, GBLOCK_DIRECT>(ctx, lds), lcap), GBLOCK_DIRECT,
+                                              lds, s>>>(CB, start, D, order, ctl, (u32)L, lds_words, vis, cur64,
+                                                        at<u32>(ws, lay.wq), false);
     else
       k_groups<ScoreVis, LT, GBLOCK_WIDE><<<group_grid<ScoreVis, LT, GBLOCK_WIDE>(ctx, lds), GBLOCK_WIDE, lds, s>>>(
           CB, start, D, order, ctl, (u32)L, lds_words, vis, cur64, at<u32>(ws, lay.wq), waves);
